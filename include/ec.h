@@ -1,0 +1,201 @@
+/*
+ * ec.h - C ABI of the MI355X (gfx950) FFT eigenstrain / interaction-energy solver.
+ *
+ * Method: Santos-Gueemes, Ortiz, Segurado, "An FFT based approach to account
+ * for elastic interactions in OkMC" (arXiv 2403.09158).
+ *   - Sec. 3.1: defects enter as eigenstrains; a loop carries sym(b x n)/e in a
+ *     slab of thickness e extruded from its area, a point-defect cluster a
+ *     dilatation in a small region (here a sphere, eps* = v I).
+ *   - Sec. 3.2: periodic equilibrium with eigenstrain, solved in Fourier space by
+ *     the Green operator built from the inverse acoustic tensor; then
+ *     sigma = C:(eps - eps*).
+ *   - Sec. 3.4: voxel-centre grid x = h (m + 1/2) and centred frequency labels.
+ *   - Sec. 2: interaction energy in the Betti-reciprocity form.
+ *   - Appendix B (OkMC algorithm): a moved defect changes the total field by
+ *     its own field difference (superposition), which is what the incremental
+ *     update computes.
+ *
+ * Units: lengths nm, stiffness and stress GPa, energies eV.
+ * Fields are structure-of-arrays [6][n][n][n] with x fastest (linear voxel id
+ * (z*n + y)*n + x), component order xx, yy, zz, yz, xz, xy, tensor components
+ * (shear not doubled), so A:B = A_xx B_xx + A_yy B_yy + A_zz B_zz
+ * + 2 (A_yz B_yz + A_xz B_xz + A_xy B_xy).
+ *
+ * Error behaviour: every entry point returns an ec_status; nothing throws across
+ * the boundary.  On error the state is left unchanged (strong guarantee) and a
+ * message is available from ec_last_error().  Ownership: the caller owns every
+ * pointer it passes in (defect records are copied during the call; output
+ * buffers are written, never retained); the library owns every ec_ctx/ec_state
+ * and the device memory behind them until the matching destroy call.
+ * Streams: work is enqueued on the caller's HIP stream (a hipStream_t passed as
+ * void*; NULL = the null stream).  Calls that return host data synchronise that
+ * stream.  One host thread at a time may use a given ec_state; calls on one
+ * state execute in call order.
+ */
+#ifndef EC_H
+#define EC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ec_ctx ec_ctx;     /* one per device: allocator hooks, HBM ledger, cached Green windows */
+typedef struct ec_state ec_state; /* one per replica: resident eps*, sigma (FP64), spectrum, footprints, energies */
+
+typedef enum {
+  EC_OK = 0,
+  EC_ERR_ARG = 1,    /* invalid argument or invalid defect record */
+  EC_ERR_SIZE = 2,   /* grid size not supported (see ec_problem.n) */
+  EC_ERR_ADMIT = 3,  /* would exceed the context's HBM budget */
+  EC_ERR_DEVICE = 4, /* HIP runtime or allocation failure */
+  EC_ERR_STATE = 5   /* call out of order (e.g. energies before any solve) */
+} ec_status;
+
+typedef enum {
+  EC_FP64 = 0, /* FP64 storage and arithmetic throughout */
+  EC_FP32 = 1  /* FP32 storage of the spectra between passes; FP64 arithmetic in
+                  registers, FP64 eigenstrain, resident stress and energies */
+} ec_precision;
+
+typedef enum {
+  EC_MEAN_STRESS_ZERO = 0, /* xi = 0 bin: <eps> = <eps*>, so <sigma> = 0 (default) */
+  EC_MEAN_STRAIN_ZERO = 1  /* xi = 0 bin: <eps> = 0 */
+} ec_mean_bc;
+
+typedef enum {
+  EC_NYQ_PAPER = 0 /* even n: the centred label set of Sec. 3.4 with the real part
+                      of the complex solution, i.e. the Green operator averaged over
+                      the all -n/2 and all +n/2 representatives of a Nyquist bin */
+} ec_nyquist;
+
+/* Periodic cubic cell of n^3 voxels and side L, cubic stiffness C11, C12, C44
+ * with cube axes along x, y, z.  n must be one of
+ * 8 16 24 32 48 64 96 128 160 240 256 512 (even, 2/3/5-smooth);
+ * anything else gives EC_ERR_SIZE. */
+typedef struct {
+  int32_t n;
+  int32_t prec; /* ec_precision */
+  int32_t bc;   /* ec_mean_bc */
+  int32_t nyq;  /* ec_nyquist */
+  double L;
+  double C11, C12, C44;
+} ec_problem;
+
+typedef enum { EC_LOOP = 0, EC_SPHERE = 1 } ec_kind;
+
+/* One defect (104 bytes).  Loops: centre c, in-plane radius, Burgers vector b,
+ * habit normal (must be parallel to an integer lattice direction with
+ * components up to 8), slab thickness (0 = one voxel h).  Eigenstrain
+ * sym(b x n_hat)/e inside {|d.n_hat| in [-e/2, e/2), in-plane |d| <= radius}.
+ * Spheres: eps* = eig_v * I inside {|d| <= radius}.  d is the minimum-image
+ * offset of a voxel centre from c.  Membership is exact integer arithmetic on
+ * coordinates quantised to h/1024.  Rejected (EC_ERR_ARG): radius <= 0,
+ * |b| = 0, a normal that is not a small-integer direction, extent
+ * radius (+ e/2 for loops) >= L/2, non-finite values. */
+typedef struct {
+  int32_t kind; /* ec_kind */
+  int32_t reserved;
+  double c[3];
+  double radius;
+  double b[3];
+  double normal[3];
+  double thickness;
+  double eig_v;
+} ec_defect;
+
+/* Device-memory hooks.  alloc returns device memory usable on `stream` or NULL;
+ * both may be NULL, in which case hipMalloc / hipFree are used. */
+typedef void* (*ec_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*ec_free_fn)(void* p, void* stream, void* user);
+
+/* Create a context on HIP device `device` with an HBM admission budget (bytes;
+ * 0 = the device's free memory at creation).  Caches Green-kernel windows per
+ * (n, C, bc). */
+ec_status ec_ctx_create(int device, size_t hbm_budget_bytes, ec_alloc_fn alloc_fn, ec_free_fn free_fn,
+                        void* user, ec_ctx** out);
+void ec_ctx_destroy(ec_ctx* ctx);
+
+/* Bytes the context has admitted so far, and its budget. */
+ec_status ec_ctx_ledger(const ec_ctx* ctx, size_t* used, size_t* budget);
+
+/* Thread-local text of the last error raised on this thread (never NULL). */
+const char* ec_last_error(void);
+
+/* Create a replica state for one problem; reserves its resident fields in the
+ * ledger (EC_ERR_ADMIT if the budget would be exceeded). */
+ec_status ec_state_create(ec_ctx* ctx, const ec_problem* problem, ec_state** out);
+void ec_state_destroy(ec_state* st);
+
+/* Bytes of device memory the state holds (fields, spectrum, footprints). */
+ec_status ec_state_bytes(const ec_state* st, size_t* bytes);
+
+/* Full solve (Sec. 3.2, 3.4): rasterise defs[0..ndef) (host array, copied),
+ * Fourier-space Green solve, sigma = C:(eps - eps*) kept resident in FP64.
+ * Optional outputs eps_out / sig_out ([6][n^3], float for EC_FP32 states,
+ * double for EC_FP64 states) on the device (out_on_device != 0) or on the host;
+ * NULL skips them.  Replaces any previous defect list of the state. */
+ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, void* hip_stream, void* eps_out,
+                          void* sig_out, int32_t out_on_device);
+
+/* Per-defect interaction energies of the current defect list, in input order
+ * (Sec. 2, Betti form written with the eigenstrain):
+ *   E_i = sum_{j != i} E_ij,   E_ij = -h^3 c sum_x eps*_i(x) : sigma_j(x),
+ * evaluated as -h^3 c E_i:S_i - B_i with S_i the FP64 compensated sum of the
+ * resident stress over the footprint of i and B_i the exact discrete self term
+ * (c = 1 GPa nm^3 in eV).  E_out holds ndef doubles (device or host). */
+ec_status ec_interaction_energies(ec_state* st, void* hip_stream, double* E_out, int32_t out_on_device);
+
+/* Move defect idx to the record *moved (Appendix B: subtract the old field,
+ * add the new one).  By linearity only the eigenstrain difference is solved;
+ * the resident FP64 stress is accumulated and, if E_out != NULL, all ndef
+ * energies are returned as in ec_interaction_energies. */
+ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, void* hip_stream, double* E_out,
+                           int32_t out_on_device);
+
+/* ---- inspection (tests, benchmarks) ---------------------------------------- */
+
+/* Footprints of the current defect list: counts[ndef] and, if ids != NULL, the
+ * concatenated voxel ids in defect order (each defect's ids ascending after a
+ * full solve).  Host buffers; synchronises.  *total receives the id count. */
+ec_status ec_state_footprints(ec_state* st, int32_t* counts, int32_t* ids, int64_t ids_capacity, int64_t* total);
+
+/* Copy a resident field to a host buffer of 6*n^3 doubles: which = 0 sigma,
+ * 1 eps (total strain), 2 eps* (eigenstrain). Synchronises. */
+ec_status ec_state_field(ec_state* st, int32_t which, double* host_out);
+
+/* Self terms B_i (eV) of the current defect list, host buffer of ndef doubles. */
+ec_status ec_state_self_terms(ec_state* st, double* host_out);
+
+/* Kernel timing: when enabled, HIP events bracket every kernel the state
+ * launches; ec_profile_read returns, per kernel family, the launch count,
+ * summed milliseconds and the algorithmic bytes moved per launch.  Families:
+ * 0 raster, 1 x-forward, 2 y-pass, 3 z-pass (fused with the Green operator),
+ * 4 x-inverse + stress, 5 energy reduction, 6 self term, 7 other. */
+#define EC_NPROF 8
+ec_status ec_profile_enable(ec_state* st, int32_t on);
+ec_status ec_profile_read(ec_state* st, int64_t* launches, double* ms, double* bytes_per_launch);
+
+/* ---- kernel-level entry points (parity tests of single passes) -------------- */
+
+/* Forward transform of a real [6][n^3] FP64 host field with this state's
+ * kernels: writes the half spectrum [6][n][n][n/2+1] complex128 (interleaved
+ * re, im; unnormalised forward DFT) to host_out. */
+ec_status ec_debug_forward(ec_state* st, const double* host_field, double* host_out);
+
+/* Green step alone: host half spectrum of eps* ([6][n][n][n/2+1] complex128)
+ * in, half spectrum of sigma = S(xi):eps*_hat out (S = C Gamma C - C, zero at
+ * xi = 0), with the state's Nyquist rule. */
+ec_status ec_debug_green(ec_state* st, const double* host_spec_in, double* host_spec_out);
+
+/* Inverse transform of a host half spectrum to a real [6][n^3] host field
+ * (scaled by 1/n^3, imaginary parts of the kx = 0 and n/2 planes dropped). */
+ec_status ec_debug_inverse(ec_state* st, const double* host_spec, double* host_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EC_H */

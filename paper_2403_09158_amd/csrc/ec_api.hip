@@ -1,0 +1,1194 @@
+// ec_api.hip - host runtime behind the C ABI of include/ec.h.
+//
+// Context: device, allocator hooks, HBM admission ledger, twiddle tables and the
+// cached windows of the discrete Green kernel.  State: one replica's resident
+// eigenstrain (fixed point), FP64 stress, half spectrum, footprint lists and
+// energies.  The defect description is double-buffered so a failed solve leaves
+// the previous one intact.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ec_internal.h"
+
+using namespace ec;
+
+namespace {
+
+thread_local std::string g_err;
+
+ec_status fail(ec_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(EC_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+struct WinCache {
+  int n = 0;
+  double C11 = 0, C12 = 0, C44 = 0;
+  int bc = 0;
+  int D = 0;
+  double* K = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct ec_ctx {
+  int device = 0;
+  size_t budget = 0, used = 0;
+  ec_alloc_fn af = nullptr;
+  ec_free_fn ff = nullptr;
+  void* user = nullptr;
+  std::mutex mu;
+  std::map<int, double2*> tw;
+  std::vector<WinCache> wins;
+};
+
+namespace {
+
+struct DefBuf {
+  DevDefect* tab = nullptr;
+  int32_t* cnt = nullptr;
+  int64_t* off = nullptr;
+  size_t cap = 0;
+  int32_t* ids = nullptr;
+  int64_t ids_cap = 0;
+};
+
+struct ProfRec {
+  int fam;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+}  // namespace
+
+struct ec_state {
+  ec_ctx* ctx = nullptr;
+  ec_problem prob{};
+  int n = 0;
+  int64_t n3 = 0;
+  bool fp64 = true;
+  SpecGeom g{};
+  Cubic C{};
+  double h3c = 0;
+  size_t spec_bytes = 0, held = 0;
+  void* spec = nullptr;
+  int64_t* es = nullptr;
+  double* sig = nullptr;
+  double* add6 = nullptr;  // [0..6) additive stress of the full solve, [6..12) zeros, [12..18) update delta
+  double2* tw = nullptr;
+  // defect list
+  int ndef = 0;
+  bool solved = false;
+  std::vector<DevDefect> hdefs;
+  std::vector<int32_t> hcnt;
+  std::vector<int64_t> hoff;
+  int64_t ids_used = 0;
+  DefBuf db[2];
+  int cur = 0;
+  double* B = nullptr;
+  double* E = nullptr;
+  double* S6 = nullptr;
+  size_t pd_cap = 0;
+  bool B_valid = false;
+  // eigenstrain direction classes and their scalar windows
+  std::vector<std::array<double, 6>> classes;
+  double* dirs = nullptr;
+  double* gcls = nullptr;
+  size_t gcls_bytes = 0;
+  int gcls_D = -1, gcls_ncls = -1;
+  const WinCache* win = nullptr;
+  // update scratch
+  int32_t* upd_ids = nullptr;
+  int64_t upd_cap = 0;
+  double* updE = nullptr;     // 6 doubles
+  int64_t* updfix = nullptr;  // 6 int64
+  // profiling
+  bool prof = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> evpool;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ memory / ledger
+
+void* raw_alloc(ec_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 64;
+  if (c->af) return c->af(bytes, nullptr, c->user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void raw_free(ec_ctx* c, void* p) {
+  if (!p) return;
+  if (c->ff)
+    c->ff(p, nullptr, c->user);
+  else
+    (void)hipFree(p);
+}
+
+bool admit(ec_ctx* c, size_t bytes) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (c->used + bytes > c->budget) return false;
+  c->used += bytes;
+  return true;
+}
+
+void release(ec_ctx* c, size_t bytes) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->used = bytes > c->used ? 0 : c->used - bytes;
+}
+
+// Allocation charged to the ledger; *out is left untouched on failure.
+ec_status ledger_alloc(ec_ctx* c, size_t bytes, void** out) {
+  if (!admit(c, bytes)) return fail(EC_ERR_ADMIT, "HBM budget exceeded (%zu bytes requested)", bytes);
+  void* p = raw_alloc(c, bytes);
+  if (!p) {
+    release(c, bytes);
+    return fail(EC_ERR_DEVICE, "device allocation of %zu bytes failed", bytes);
+  }
+  *out = p;
+  return EC_OK;
+}
+
+void ledger_free(ec_ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  raw_free(c, p);
+  release(c, bytes);
+}
+
+template <class T>
+ec_status st_grow(ec_state* st, T** p, size_t* cap_elems, size_t need, bool keep = false, hipStream_t s = nullptr) {
+  if (need <= *cap_elems && *p) return EC_OK;
+  size_t ncap = std::max<size_t>(need, *cap_elems + *cap_elems / 2);
+  ncap = std::max<size_t>(ncap, 16);
+  void* q = nullptr;
+  ec_status r = ledger_alloc(st->ctx, ncap * sizeof(T), &q);
+  if (r != EC_OK) return r;
+  if (keep && *p && *cap_elems) {
+    if (hipMemcpyAsync(q, *p, *cap_elems * sizeof(T), hipMemcpyDeviceToDevice, s) != hipSuccess) {
+      ledger_free(st->ctx, q, ncap * sizeof(T));
+      return fail(EC_ERR_DEVICE, "device copy failed while growing a buffer");
+    }
+    (void)hipStreamSynchronize(s);
+  }
+  if (*p) ledger_free(st->ctx, *p, *cap_elems * sizeof(T));
+  st->held += ncap * sizeof(T);
+  st->held -= std::min(st->held, *cap_elems * sizeof(T));
+  *p = (T*)q;
+  *cap_elems = ncap;
+  return EC_OK;
+}
+
+// ------------------------------------------------------------------ profiling
+
+hipEvent_t take_event(ec_state* st) {
+  if (!st->evpool.empty()) {
+    hipEvent_t e = st->evpool.back();
+    st->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+template <class F>
+hipError_t run(ec_state* st, hipStream_t s, int fam, double bytes, F&& f) {
+  if (!st->prof) return f();
+  hipEvent_t a = take_event(st), b = take_event(st);
+  (void)hipEventRecord(a, s);
+  hipError_t e = f();
+  (void)hipEventRecord(b, s);
+  st->recs.push_back({fam, a, b, bytes});
+  return e;
+}
+
+#define LAUNCH(st, s, fam, bytes, call)                                                     \
+  do {                                                                                      \
+    hipError_t e_ = run(st, s, fam, (double)(bytes), [&]() { return (call); });             \
+    if (e_ != hipSuccess) return fail(EC_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------------ twiddles
+
+double2* ctx_twiddles(ec_ctx* c, int n) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto it = c->tw.find(n);
+  if (it != c->tw.end()) return it->second;
+  std::vector<double2> h(n);
+  const long double pi = acosl(-1.0L);
+  for (int e = 0; e < n; ++e) {
+    const long double a = 2.0L * pi * (long double)e / (long double)n;
+    h[e] = make_double2((double)cosl(a), (double)(-sinl(a)));
+  }
+  void* p = raw_alloc(c, n * sizeof(double2));
+  if (!p) return nullptr;
+  if (hipMemcpy(p, h.data(), n * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess) {
+    raw_free(c, p);
+    return nullptr;
+  }
+  c->tw[n] = (double2*)p;
+  return (double2*)p;
+}
+
+// ------------------------------------------------------------------ quantisation
+//
+// The same integer description the oracle derives independently: centre
+// c_q = rint(c s) mod 1024 n with s = (1024 n)/L, R2_q = rint((R s)^2),
+// thickness e_q = rint(e s) (1024 for e = 0), habit normal as the smallest
+// integer lattice vector (components up to 8).
+
+#pragma clang fp contract(off)
+
+bool lattice_normal(const double v[3], int m[3]) {
+  double amax = 0.0;
+  for (int k = 0; k < 3; ++k) amax = std::max(amax, std::fabs(v[k]));
+  if (!std::isfinite(amax) || amax == 0.0) return false;
+  double a[3];
+  for (int k = 0; k < 3; ++k) a[k] = v[k] / amax;
+  for (int mult = 1; mult <= 8; ++mult) {
+    bool ok = true;
+    double r[3];
+    for (int k = 0; k < 3; ++k) {
+      const double w = a[k] * (double)mult;
+      r[k] = std::nearbyint(w);
+      if (!(std::fabs(w - r[k]) < 1e-9)) ok = false;
+    }
+    if (ok) {
+      int g = 0;
+      for (int k = 0; k < 3; ++k) {
+        m[k] = (int)r[k];
+        int x = std::abs(m[k]);
+        int y = g;
+        while (y) {
+          int t = x % y;
+          x = y;
+          y = t;
+        }
+        g = x;
+      }
+      for (int k = 0; k < 3; ++k) m[k] /= g;
+      return true;
+    }
+  }
+  return false;
+}
+
+int64_t floordiv(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+int64_t isqrt64(int64_t v) {
+  int64_t r = (int64_t)std::sqrt((double)v);
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+
+bool quantise(const ec_problem& P, const ec_defect& rec, DevDefect& d, std::string& err) {
+  std::memset(&d, 0, sizeof d);
+  const int n = P.n;
+  const double L = P.L;
+  const double s = (1024.0 * n) / L;
+  const int64_t Lq = (int64_t)QSUB * n;
+  const double R = rec.radius;
+  if (!(R > 0.0) || !std::isfinite(R)) return err = "radius must be positive and finite", false;
+  for (int k = 0; k < 3; ++k) {
+    const double v = rec.c[k] * s;
+    if (!std::isfinite(v) || std::fabs(v) > 4.0e18) return err = "centre not finite", false;
+    int64_t q = (int64_t)std::nearbyint(v) % Lq;
+    if (q < 0) q += Lq;
+    d.cq[k] = (int32_t)q;
+  }
+  const double Rs = R * s;
+  const double R2 = Rs * Rs;
+  d.R2q = (int64_t)std::nearbyint(R2);
+  d.kind = rec.kind;
+  d.cls = -1;
+  double E[3][3] = {{0}};
+  int64_t ext = isqrt64(d.R2q) + 1;
+  if (rec.kind == EC_LOOP) {
+    const double bb = rec.b[0] * rec.b[0] + rec.b[1] * rec.b[1] + rec.b[2] * rec.b[2];
+    if (!(bb > 0.0) || !std::isfinite(bb)) return err = "zero or non-finite Burgers vector", false;
+    const double e = rec.thickness;
+    if (e < 0.0 || !std::isfinite(e)) return err = "negative thickness", false;
+    double e_nm;
+    if (e == 0.0) {
+      d.eq = QSUB;
+      e_nm = L / n;
+    } else {
+      d.eq = (int32_t)std::nearbyint(e * s);
+      e_nm = e;
+      if (d.eq <= 0) return err = "thickness below the quantisation step", false;
+    }
+    if (R + 0.5 * e_nm >= 0.5 * L) return err = "loop extent reaches half the cell", false;
+    if (!lattice_normal(rec.normal, d.m)) return err = "habit normal is not a small-integer lattice direction", false;
+    d.mm = d.m[0] * d.m[0] + d.m[1] * d.m[1] + d.m[2] * d.m[2];
+    const double nrm = std::sqrt((double)d.mm);
+    double nh[3];
+    for (int k = 0; k < 3; ++k) nh[k] = (double)d.m[k] / nrm;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) E[a][b] = (rec.b[a] * nh[b] + nh[a] * rec.b[b]) / (2.0 * e_nm);
+    ext += (d.eq + 1) / 2;
+  } else if (rec.kind == EC_SPHERE) {
+    if (R >= 0.5 * L) return err = "sphere extent reaches half the cell", false;
+    if (!std::isfinite(rec.eig_v)) return err = "eigenstrain not finite", false;
+    for (int a = 0; a < 3; ++a) E[a][a] = rec.eig_v;
+  } else {
+    return err = "unknown defect kind", false;
+  }
+  d.E[0] = E[0][0];
+  d.E[1] = E[1][1];
+  d.E[2] = E[2][2];
+  d.E[3] = E[1][2];
+  d.E[4] = E[0][2];
+  d.E[5] = E[0][1];
+  for (int a = 0; a < 6; ++a) {
+    if (!(std::fabs(d.E[a]) < 64.0)) return err = "eigenstrain component too large", false;
+    d.efix[a] = (int64_t)std::llrint(d.E[a] * FIX_SCALE);
+  }
+  for (int k = 0; k < 3; ++k) {
+    const int64_t lo = floordiv((int64_t)d.cq[k] - ext - 512 + (QSUB - 1), QSUB);
+    const int64_t hi = floordiv((int64_t)d.cq[k] + ext - 512, QSUB);
+    const int64_t w = std::min<int64_t>(hi - lo + 1, n);
+    d.w[k] = (int32_t)w;
+    d.lo[k] = (int32_t)(((lo % n) + n) % n);
+  }
+  return true;
+}
+
+#pragma clang fp contract(on)
+
+// Direction class of an eigenstrain: E = s e with e's largest-magnitude entry = 1.
+void direction(const DevDefect& d, std::array<double, 6>& e, double& s) {
+  int am = 0;
+  for (int a = 1; a < 6; ++a)
+    if (std::fabs(d.E[a]) > std::fabs(d.E[am])) am = a;
+  s = d.E[am];
+  for (int a = 0; a < 6; ++a) e[a] = s != 0.0 ? d.E[a] / s : 0.0;
+}
+
+constexpr int MAXCLS = 32;
+
+void assign_class(ec_state* st, DevDefect& d) {
+  std::array<double, 6> e;
+  double s;
+  direction(d, e, s);
+  d.s = s;
+  d.cls = -1;
+  if (s == 0.0) return;
+  for (size_t c = 0; c < st->classes.size(); ++c)
+    if (std::memcmp(st->classes[c].data(), e.data(), sizeof(double) * 6) == 0) {
+      d.cls = (int)c;
+      return;
+    }
+  if ((int)st->classes.size() < MAXCLS) {
+    st->classes.push_back(e);
+    d.cls = (int)st->classes.size() - 1;
+  }
+}
+
+// ------------------------------------------------------------------ solve pipeline
+
+double spec_valid_bytes(const ec_state* st, bool fp64) {
+  return 6.0 * st->n * st->n * (st->n / 2 + 1) * (fp64 ? 16.0 : 8.0);
+}
+
+ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int64_t* es, void* spec, double* sig,
+                   const double* add6) {
+  const Prune full{0, st->n, 0, st->n};
+  const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
+  SpecGeom g{st->n, 0};
+  g.P = fp64 ? ((st->n / 2 + 1 + 7) / 8) * 8 : ((st->n / 2 + 1 + 15) / 16) * 16;
+  LAUNCH(st, s, PF_XF, fb + sb, launch_x_forward(fp64, es, spec, g, st->tw, s));
+  LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, false, 1, spec, g, full, st->tw, s));
+  LAUNCH(st, s, PF_Z, 2 * sb, launch_pencil(fp64, false, 2, spec, g, full, st->tw, s));
+  LAUNCH(st, s, PF_Z, 2 * sb, launch_green(fp64, spec, g, st->C, s));
+  LAUNCH(st, s, PF_Z, 2 * sb, launch_pencil(fp64, true, 2, spec, g, full, st->tw, s));
+  LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, spec, g, full, st->tw, s));
+  LAUNCH(st, s, PF_XI, sb + fb, launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s));
+  return EC_OK;
+}
+
+// Window of the discrete kernel G for this problem: six FP64 impulse solves.
+ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
+  ec_ctx* c = st->ctx;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (auto& w : c->wins)
+      if (w.n == st->n && w.C11 == st->C.C11 && w.C12 == st->C.C12 && w.C44 == st->C.C44 && w.bc == st->prob.bc &&
+          w.D >= Dneed) {
+        st->win = &w;
+        return EC_OK;
+      }
+  }
+  const int D = std::max(1, std::min(Dneed, st->n / 2));
+  const int W = 2 * D + 1;
+  const size_t Kbytes = (size_t)W * W * W * KWIN * sizeof(double);
+  const int n = st->n;
+  const int P64 = ((n / 2 + 1 + 7) / 8) * 8;
+  const size_t sp64 = (size_t)6 * n * n * P64 * sizeof(double2);
+  const size_t fbytes = (size_t)6 * st->n3 * 8;
+  void *K = nullptr, *es = nullptr, *sp = nullptr, *sg = nullptr, *ad = nullptr;
+  ec_status r;
+  if ((r = ledger_alloc(c, Kbytes, &K)) != EC_OK) return r;
+  auto cleanup = [&]() {
+    ledger_free(c, es, fbytes);
+    ledger_free(c, sp, sp64);
+    ledger_free(c, sg, fbytes);
+    ledger_free(c, ad, 64);
+  };
+  if ((r = ledger_alloc(c, fbytes, &es)) != EC_OK || (r = ledger_alloc(c, sp64, &sp)) != EC_OK ||
+      (r = ledger_alloc(c, fbytes, &sg)) != EC_OK || (r = ledger_alloc(c, 64, &ad)) != EC_OK) {
+    cleanup();
+    ledger_free(c, K, Kbytes);
+    return r;
+  }
+  const bool prof = st->prof;
+  st->prof = false;
+  auto body = [&]() -> ec_status {
+    HIPCHK(launch_fill_i64((int64_t*)es, 6 * st->n3, 0, s));
+    HIPCHK(hipMemsetAsync(K, 0, Kbytes, s));
+    for (int b = 0; b < 6; ++b) {
+      if (b > 0) HIPCHK(launch_fill_i64((int64_t*)es + (b - 1) * st->n3, 1, 0, s));
+      HIPCHK(launch_fill_i64((int64_t*)es + b * st->n3, 1, (int64_t)FIX_SCALE, s));
+      double add[6] = {0, 0, 0, 0, 0, 0};
+      if (st->prob.bc == EC_MEAN_STRAIN_ZERO) {
+        // sigma mean = -C : <eps*>, <eps*> = unit component b / n^3
+        double m[6] = {0, 0, 0, 0, 0, 0};
+        m[b] = 1.0 / (double)st->n3;
+        add[0] = -(st->C.C11 * m[0] + st->C.C12 * (m[1] + m[2]));
+        add[1] = -(st->C.C11 * m[1] + st->C.C12 * (m[0] + m[2]));
+        add[2] = -(st->C.C11 * m[2] + st->C.C12 * (m[0] + m[1]));
+        for (int a = 3; a < 6; ++a) add[a] = -2.0 * st->C.C44 * m[a];
+      }
+      HIPCHK(hipMemcpyAsync(ad, add, sizeof add, hipMemcpyHostToDevice, s));
+      ec_status q = pipeline(st, s, true, (const int64_t*)es, sp, (double*)sg, (const double*)ad);
+      if (q != EC_OK) return q;
+      HIPCHK(launch_window_crop((const double*)sg, n, D, b, (double*)K, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return EC_OK;
+  };
+  r = body();
+  st->prof = prof;
+  cleanup();
+  if (r != EC_OK) {
+    ledger_free(c, K, Kbytes);
+    return r;
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (auto it = c->wins.begin(); it != c->wins.end(); ++it)
+    if (it->n == st->n && it->C11 == st->C.C11 && it->C12 == st->C.C12 && it->C44 == st->C.C44 &&
+        it->bc == st->prob.bc) {
+      // states still pointing at the old window refresh through ensure_window
+      raw_free(c, it->K);
+      c->used -= std::min(c->used, it->bytes);
+      c->wins.erase(it);
+      break;
+    }
+  WinCache w;
+  w.n = st->n;
+  w.C11 = st->C.C11;
+  w.C12 = st->C.C12;
+  w.C44 = st->C.C44;
+  w.bc = st->prob.bc;
+  w.D = D;
+  w.K = (double*)K;
+  w.bytes = Kbytes;
+  c->wins.reserve(c->wins.size() + 1);
+  c->wins.push_back(w);
+  st->win = nullptr;
+  for (auto& x : c->wins)
+    if (x.K == (double*)K) st->win = &x;
+  st->gcls_D = -1;
+  return EC_OK;
+}
+
+int window_need(const ec_state* st) {
+  int D = 1;
+  for (const auto& d : st->hdefs)
+    for (int k = 0; k < 3; ++k) D = std::max(D, d.w[k] - 1);
+  return std::min(D, st->n / 2);
+}
+
+ec_status compute_self_terms(ec_state* st, hipStream_t s) {
+  const int need = window_need(st);
+  ec_status r = ensure_window(st, need, s);
+  if (r != EC_OK) return r;
+  const WinCache* w = st->win;
+  const int D = w->D;
+  const int W = 2 * D + 1;
+  const size_t W3 = (size_t)W * W * W;
+  const int ncls = (int)st->classes.size();
+  if (st->gcls_D != D || st->gcls_ncls != ncls) {
+    const size_t need_b = std::max<size_t>(1, (size_t)ncls) * W3 * sizeof(double);
+    if (need_b > st->gcls_bytes) {
+      void* q = nullptr;
+      if ((r = ledger_alloc(st->ctx, need_b, &q)) != EC_OK) return r;
+      ledger_free(st->ctx, st->gcls, st->gcls_bytes);
+      st->held += need_b;
+      st->held -= std::min(st->held, st->gcls_bytes);
+      st->gcls = (double*)q;
+      st->gcls_bytes = need_b;
+    }
+    std::vector<double> dirs(6 * std::max(ncls, 1), 0.0);
+    for (int c = 0; c < ncls; ++c)
+      for (int a = 0; a < 6; ++a) dirs[6 * c + a] = st->classes[c][a];
+    HIPCHK(hipMemcpyAsync(st->dirs, dirs.data(), dirs.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    LAUNCH(st, s, PF_OTHER, W3 * ncls * 8.0 * 22, launch_class_windows(w->K, D, st->dirs, ncls, st->gcls, s));
+    HIPCHK(hipStreamSynchronize(s));  // dirs staging buffer is pageable
+    st->gcls_D = D;
+    st->gcls_ncls = ncls;
+  }
+  const DefBuf& b = st->db[st->cur];
+  double pairs = 0;
+  for (int i = 0; i < st->ndef; ++i) pairs += (double)st->hcnt[i] * st->hcnt[i];
+  LAUNCH(st, s, PF_SELF, pairs * 8.0,
+         launch_self_terms(b.tab, st->ndef, b.off, b.cnt, b.ids, st->n, w->K, st->gcls, D, st->h3c, st->B, s));
+  st->B_valid = true;
+  return EC_OK;
+}
+
+ec_status copy_out(void* dst, const void* src, size_t bytes, bool on_device, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  if (!on_device) HIPCHK(hipStreamSynchronize(s));
+  return EC_OK;
+}
+
+ec_status write_field(ec_state* st, int which, void* out, bool on_device, hipStream_t s) {
+  const bool f32 = !st->fp64;
+  const size_t bytes = (size_t)6 * st->n3 * (f32 ? 4 : 8);
+  if (on_device) {
+    LAUNCH(st, s, PF_OTHER, 96.0 * st->n3, launch_sig_to_out(st->sig, st->es, st->n3, st->C, which, f32, out, s));
+    return EC_OK;
+  }
+  void* tmp = nullptr;
+  ec_status r = ledger_alloc(st->ctx, bytes, &tmp);
+  if (r != EC_OK) return r;
+  hipError_t e = launch_sig_to_out(st->sig, st->es, st->n3, st->C, which, f32, tmp, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  ledger_free(st->ctx, tmp, bytes);
+  if (e != hipSuccess) return fail(EC_ERR_DEVICE, "field output: %s", hipGetErrorString(e));
+  return EC_OK;
+}
+
+ec_status ensure_per_defect(ec_state* st, size_t ndef) {
+  if (ndef <= st->pd_cap && st->B) return EC_OK;
+  size_t cap = std::max<size_t>(ndef, 16);
+  void *b = nullptr, *e = nullptr, *s6 = nullptr;
+  ec_status r;
+  if ((r = ledger_alloc(st->ctx, cap * 8, &b)) != EC_OK) return r;
+  if ((r = ledger_alloc(st->ctx, cap * 8, &e)) != EC_OK) {
+    ledger_free(st->ctx, b, cap * 8);
+    return r;
+  }
+  if ((r = ledger_alloc(st->ctx, cap * 48, &s6)) != EC_OK) {
+    ledger_free(st->ctx, b, cap * 8);
+    ledger_free(st->ctx, e, cap * 8);
+    return r;
+  }
+  ledger_free(st->ctx, st->B, st->pd_cap * 8);
+  ledger_free(st->ctx, st->E, st->pd_cap * 8);
+  ledger_free(st->ctx, st->S6, st->pd_cap * 48);
+  st->held += cap * 64;
+  st->held -= std::min(st->held, st->pd_cap * 64);
+  st->B = (double*)b;
+  st->E = (double*)e;
+  st->S6 = (double*)s6;
+  st->pd_cap = cap;
+  return EC_OK;
+}
+
+ec_status ensure_defbuf(ec_state* st, DefBuf& b, size_t ndef) {
+  if (ndef + 1 <= b.cap && b.tab) return EC_OK;
+  size_t cap = std::max<size_t>(ndef + 1, 16);
+  void *t = nullptr, *c = nullptr, *o = nullptr;
+  ec_status r;
+  if ((r = ledger_alloc(st->ctx, cap * sizeof(DevDefect), &t)) != EC_OK) return r;
+  if ((r = ledger_alloc(st->ctx, cap * 4, &c)) != EC_OK) {
+    ledger_free(st->ctx, t, cap * sizeof(DevDefect));
+    return r;
+  }
+  if ((r = ledger_alloc(st->ctx, cap * 8, &o)) != EC_OK) {
+    ledger_free(st->ctx, t, cap * sizeof(DevDefect));
+    ledger_free(st->ctx, c, cap * 4);
+    return r;
+  }
+  ledger_free(st->ctx, b.tab, b.cap * sizeof(DevDefect));
+  ledger_free(st->ctx, b.cnt, b.cap * 4);
+  ledger_free(st->ctx, b.off, b.cap * 8);
+  st->held += cap * (sizeof(DevDefect) + 12);
+  st->held -= std::min(st->held, b.cap * (sizeof(DevDefect) + 12));
+  b.tab = (DevDefect*)t;
+  b.cnt = (int32_t*)c;
+  b.off = (int64_t*)o;
+  b.cap = cap;
+  return EC_OK;
+}
+
+// Smallest cyclic interval of [0, n) covering [lo1, lo1+w1) and [lo2, lo2+w2).
+void cyclic_cover(int lo1, int w1, int lo2, int w2, int n, int& lo, int& len) {
+  std::vector<char> mark(n, 0);
+  for (int i = 0; i < w1; ++i) mark[(lo1 + i) % n] = 1;
+  for (int i = 0; i < w2; ++i) mark[(lo2 + i) % n] = 1;
+  int best = 0, best_end = 0;
+  for (int start = 0; start < n; ++start) {
+    if (mark[start] || !mark[(start + n - 1) % n]) continue;  // zero run must start after a mark
+    int l = 0;
+    while (l < n && !mark[(start + l) % n]) ++l;
+    if (l > best) {
+      best = l;
+      best_end = (start + l) % n;
+    }
+  }
+  if (best == 0) {
+    lo = 0;
+    len = n;
+    return;
+  }
+  lo = best_end;
+  len = n - best;
+}
+
+}  // namespace
+
+// =============================================================================== ABI
+
+extern "C" {
+
+const char* ec_last_error(void) { return g_err.c_str(); }
+
+ec_status ec_ctx_create(int device, size_t budget, ec_alloc_fn af, ec_free_fn ff, void* user, ec_ctx** out) {
+  if (!out) return fail(EC_ERR_ARG, "out is NULL");
+  if ((af == nullptr) != (ff == nullptr)) return fail(EC_ERR_ARG, "give both allocator hooks or neither");
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(EC_ERR_ARG, "device %d not present (%d devices)", device, ndev);
+  HIPCHK(hipSetDevice(device));
+  size_t fr = 0, tot = 0;
+  HIPCHK(hipMemGetInfo(&fr, &tot));
+  ec_ctx* c = new ec_ctx;
+  c->device = device;
+  c->budget = budget ? budget : fr;
+  c->af = af;
+  c->ff = ff;
+  c->user = user;
+  *out = c;
+  return EC_OK;
+}
+
+void ec_ctx_destroy(ec_ctx* c) {
+  if (!c) return;
+  for (auto& kv : c->tw) raw_free(c, kv.second);
+  for (auto& w : c->wins) raw_free(c, w.K);
+  delete c;
+}
+
+ec_status ec_ctx_ledger(const ec_ctx* c, size_t* used, size_t* budget) {
+  if (!c) return fail(EC_ERR_ARG, "ctx is NULL");
+  ec_ctx* m = const_cast<ec_ctx*>(c);
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (used) *used = c->used;
+  if (budget) *budget = c->budget;
+  return EC_OK;
+}
+
+ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
+  if (!c || !p || !out) return fail(EC_ERR_ARG, "NULL argument");
+  if (!fft_supported(p->n)) return fail(EC_ERR_SIZE, "grid size n = %d is not supported", p->n);
+  if (!(p->L > 0.0) || !std::isfinite(p->L)) return fail(EC_ERR_ARG, "cell side must be positive");
+  if (p->prec != EC_FP64 && p->prec != EC_FP32) return fail(EC_ERR_ARG, "unknown precision");
+  if (p->bc != EC_MEAN_STRESS_ZERO && p->bc != EC_MEAN_STRAIN_ZERO) return fail(EC_ERR_ARG, "unknown mean condition");
+  if (p->nyq != EC_NYQ_PAPER) return fail(EC_ERR_ARG, "unknown Nyquist rule");
+  if (!(p->C11 - p->C12 > 0.0) || !(p->C11 + 2.0 * p->C12 > 0.0) || !(p->C44 > 0.0))
+    return fail(EC_ERR_ARG, "stiffness is not positive definite");
+  ec_state* st = new ec_state;
+  st->ctx = c;
+  st->prob = *p;
+  st->n = p->n;
+  st->n3 = (int64_t)p->n * p->n * p->n;
+  st->fp64 = p->prec == EC_FP64;
+  st->g.n = p->n;
+  st->g.P = st->fp64 ? ((p->n / 2 + 1 + 7) / 8) * 8 : ((p->n / 2 + 1 + 15) / 16) * 16;
+  st->C = Cubic{p->C11, p->C12, p->C44};
+  const double h = p->L / p->n;
+  st->h3c = h * h * h * GPA_NM3_EV;
+  st->spec_bytes = (size_t)6 * p->n * p->n * st->g.P * (st->fp64 ? 16 : 8);
+  const size_t fb = (size_t)6 * st->n3 * 8;
+  st->tw = ctx_twiddles(c, p->n);
+  if (!st->tw) {
+    delete st;
+    return fail(EC_ERR_DEVICE, "twiddle table allocation failed");
+  }
+  void *sp = nullptr, *es = nullptr, *sg = nullptr, *ad = nullptr, *dirs = nullptr, *ue = nullptr, *uf = nullptr;
+  ec_status r;
+  auto undo = [&]() {
+    ledger_free(c, sp, st->spec_bytes);
+    ledger_free(c, es, fb);
+    ledger_free(c, sg, fb);
+    ledger_free(c, ad, 256);
+    ledger_free(c, dirs, MAXCLS * 48);
+    ledger_free(c, ue, 64);
+    ledger_free(c, uf, 64);
+  };
+  if ((r = ledger_alloc(c, st->spec_bytes, &sp)) != EC_OK || (r = ledger_alloc(c, fb, &es)) != EC_OK ||
+      (r = ledger_alloc(c, fb, &sg)) != EC_OK || (r = ledger_alloc(c, 256, &ad)) != EC_OK ||
+      (r = ledger_alloc(c, MAXCLS * 48, &dirs)) != EC_OK || (r = ledger_alloc(c, 64, &ue)) != EC_OK ||
+      (r = ledger_alloc(c, 64, &uf)) != EC_OK) {
+    undo();
+    delete st;
+    return r;
+  }
+  st->spec = sp;
+  st->es = (int64_t*)es;
+  st->sig = (double*)sg;
+  st->add6 = (double*)ad;
+  st->dirs = (double*)dirs;
+  st->updE = (double*)ue;
+  st->updfix = (int64_t*)uf;
+  st->held = st->spec_bytes + 2 * fb + 256 + MAXCLS * 48 + 128;
+  hipError_t e = launch_fill_i64(st->es, 6 * st->n3, 0, nullptr);
+  if (e == hipSuccess) e = hipMemset(st->sig, 0, fb);
+  if (e == hipSuccess) e = hipMemset(st->add6, 0, 256);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    undo();
+    delete st;
+    return fail(EC_ERR_DEVICE, "state initialisation: %s", hipGetErrorString(e));
+  }
+  *out = st;
+  return EC_OK;
+}
+
+void ec_state_destroy(ec_state* st) {
+  if (!st) return;
+  ec_ctx* c = st->ctx;
+  (void)hipDeviceSynchronize();
+  const size_t fb = (size_t)6 * st->n3 * 8;
+  ledger_free(c, st->spec, st->spec_bytes);
+  ledger_free(c, st->es, fb);
+  ledger_free(c, st->sig, fb);
+  ledger_free(c, st->add6, 256);
+  ledger_free(c, st->dirs, MAXCLS * 48);
+  ledger_free(c, st->updE, 64);
+  ledger_free(c, st->updfix, 64);
+  for (auto& b : st->db) {
+    ledger_free(c, b.tab, b.cap * sizeof(DevDefect));
+    ledger_free(c, b.cnt, b.cap * 4);
+    ledger_free(c, b.off, b.cap * 8);
+    ledger_free(c, b.ids, b.ids_cap * 4);
+  }
+  ledger_free(c, st->B, st->pd_cap * 8);
+  ledger_free(c, st->E, st->pd_cap * 8);
+  ledger_free(c, st->S6, st->pd_cap * 48);
+  ledger_free(c, st->gcls, st->gcls_bytes);
+  ledger_free(c, st->upd_ids, st->upd_cap * 4);
+  for (auto& r : st->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : st->evpool) (void)hipEventDestroy(e);
+  delete st;
+}
+
+ec_status ec_state_bytes(const ec_state* st, size_t* bytes) {
+  if (!st || !bytes) return fail(EC_ERR_ARG, "NULL argument");
+  *bytes = st->held;
+  return EC_OK;
+}
+
+ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, void* stream, void* eps_out,
+                          void* sig_out, int32_t on_device) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  if (ndef < 0 || (ndef > 0 && !defs)) return fail(EC_ERR_ARG, "bad defect array");
+  hipStream_t s = (hipStream_t)stream;
+  // 1. validate and quantise everything before touching the state
+  std::vector<DevDefect> h(ndef);
+  std::string err;
+  for (int i = 0; i < ndef; ++i)
+    if (!quantise(st->prob, defs[i], h[i], err)) return fail(EC_ERR_ARG, "defect %d: %s", i, err.c_str());
+  std::vector<std::array<double, 6>> old_classes = st->classes;
+  st->classes.clear();
+  for (auto& d : h) assign_class(st, d);
+  const bool classes_changed = old_classes != st->classes;
+  // 2. footprints of the new list into the spare buffers
+  DefBuf& nb = st->db[1 - st->cur];
+  ec_status r;
+  if ((r = ensure_defbuf(st, nb, ndef)) != EC_OK || (r = ensure_per_defect(st, ndef)) != EC_OK) {
+    st->classes = old_classes;
+    return r;
+  }
+  if (ndef > 0) HIPCHK(hipMemcpyAsync(nb.tab, h.data(), ndef * sizeof(DevDefect), hipMemcpyHostToDevice, s));
+  LAUNCH(st, s, PF_RASTER, 0, launch_raster_count(nb.tab, ndef, st->n, nb.cnt, s));
+  LAUNCH(st, s, PF_RASTER, 0, launch_scan(nb.cnt, ndef, nb.off, s));
+  std::vector<int32_t> hc(ndef);
+  std::vector<int64_t> ho(ndef + 1);
+  if (ndef > 0) HIPCHK(hipMemcpyAsync(hc.data(), nb.cnt, ndef * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(ho.data(), nb.off, (ndef + 1) * 8, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t total = ho[ndef];
+  size_t idcap = (size_t)nb.ids_cap;
+  if ((r = st_grow(st, &nb.ids, &idcap, (size_t)std::max<int64_t>(total, 1))) != EC_OK) {
+    st->classes = old_classes;
+    return r;
+  }
+  nb.ids_cap = (int64_t)idcap;
+  // 3. commit: remove the old eigenstrain, add the new one
+  const DefBuf& ob = st->db[st->cur];
+  if (st->ndef > 0)
+    LAUNCH(st, s, PF_RASTER, 0, launch_unraster(ob.tab, st->ndef, ob.off, ob.cnt, ob.ids, st->n3, st->es, s));
+  LAUNCH(st, s, PF_RASTER, 0, launch_raster_fill(nb.tab, ndef, st->n, nb.off, nb.ids, st->es, s));
+  st->cur = 1 - st->cur;
+  st->hdefs.swap(h);
+  st->hcnt.swap(hc);
+  st->hoff.swap(ho);
+  st->ndef = ndef;
+  st->ids_used = total;
+  st->B_valid = false;
+  if (classes_changed) st->gcls_ncls = -1;
+  LAUNCH(st, s, PF_OTHER, 0,
+         launch_mean_stress(nb.tab, nb.cnt, ndef, st->n3, st->C, st->prob.bc, st->add6, s));
+  // 4. Fourier solve
+  r = pipeline(st, s, st->fp64, st->es, st->spec, st->sig, st->add6);
+  if (r != EC_OK) return r;
+  st->solved = true;
+  if (eps_out && (r = write_field(st, 1, eps_out, on_device != 0, s)) != EC_OK) return r;
+  if (sig_out && (r = write_field(st, 0, sig_out, on_device != 0, s)) != EC_OK) return r;
+  return EC_OK;
+}
+
+ec_status ec_interaction_energies(ec_state* st, void* stream, double* E_out, int32_t on_device) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
+  hipStream_t s = (hipStream_t)stream;
+  ec_status r;
+  if (!st->B_valid && (r = compute_self_terms(st, s)) != EC_OK) return r;
+  const DefBuf& b = st->db[st->cur];
+  LAUNCH(st, s, PF_REDUCE, st->ids_used * 52.0,
+         launch_reduce(b.tab, st->ndef, b.off, b.cnt, b.ids, st->sig, st->n3, st->B, st->h3c, st->S6, st->E, s));
+  if (E_out && st->ndef > 0) return copy_out(E_out, st->E, st->ndef * 8, on_device != 0, s);
+  return EC_OK;
+}
+
+ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, void* stream, double* E_out,
+                           int32_t on_device) {
+  if (!st || !moved) return fail(EC_ERR_ARG, "NULL argument");
+  if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
+  if (idx < 0 || idx >= st->ndef) return fail(EC_ERR_ARG, "defect index %d out of range", idx);
+  hipStream_t s = (hipStream_t)stream;
+  DevDefect nd;
+  std::string err;
+  if (!quantise(st->prob, *moved, nd, err)) return fail(EC_ERR_ARG, "moved defect: %s", err.c_str());
+  const DevDefect od = st->hdefs[idx];
+  const int n = st->n;
+  // whole-voxel move of the same shape: the footprint translates and B_i is unchanged
+  bool hop = od.kind == nd.kind && od.R2q == nd.R2q && od.eq == nd.eq && od.mm == nd.mm;
+  for (int k = 0; k < 3 && hop; ++k) hop = od.m[k] == nd.m[k] && ((nd.cq[k] - od.cq[k]) % QSUB) == 0;
+  for (int a = 0; a < 6 && hop; ++a) hop = od.efix[a] == nd.efix[a];
+  int sh[3] = {0, 0, 0};
+  if (hop)
+    for (int k = 0; k < 3; ++k) {
+      int d = ((nd.cq[k] - od.cq[k]) / QSUB) % n;
+      if (d < 0) d += n;
+      if (d >= n / 2) d -= n;
+      sh[k] = d;
+    }
+  const size_t ncls_before = st->classes.size();
+  nd.cls = -1;
+  if (hop) {
+    nd.cls = od.cls;
+    nd.s = od.s;
+  } else {
+    assign_class(st, nd);
+  }
+  const int cnt_old = st->hcnt[idx];
+  const int64_t off_old = st->hoff[idx];
+  DefBuf& b = st->db[st->cur];
+  std::vector<int32_t> new_ids;
+  int cnt_new = cnt_old;
+  int64_t off_new = off_old;
+  ec_status r;
+  if (!hop) {
+    const long tot = (long)nd.w[0] * nd.w[1] * nd.w[2];
+    for (long e = 0; e < tot; ++e) {
+      const int iz = (int)(e / ((long)nd.w[0] * nd.w[1]));
+      const int iy = (int)((e / nd.w[0]) % nd.w[1]);
+      const int ix = (int)(e % nd.w[0]);
+      const int x = box_axis(nd.lo[0], nd.w[0], n, ix), y = box_axis(nd.lo[1], nd.w[1], n, iy),
+                z = box_axis(nd.lo[2], nd.w[2], n, iz);
+      if (member(nd, n, x, y, z)) new_ids.push_back((z * n + y) * n + x);
+    }
+    cnt_new = (int)new_ids.size();
+    size_t ucap = (size_t)st->upd_cap;
+    if ((r = st_grow(st, &st->upd_ids, &ucap, std::max<size_t>(cnt_new, 1))) != EC_OK) {
+      st->classes.resize(ncls_before);
+      return r;
+    }
+    st->upd_cap = (int64_t)ucap;
+    if (cnt_new > cnt_old) {
+      off_new = st->ids_used;
+      size_t icap = (size_t)b.ids_cap;
+      if ((r = st_grow(st, &b.ids, &icap, (size_t)(st->ids_used + cnt_new), true, s)) != EC_OK) {
+        st->classes.resize(ncls_before);
+        return r;
+      }
+      b.ids_cap = (int64_t)icap;
+    }
+  }
+  // rows of the eigenstrain change
+  int ylo, ylen, zlo, zlen;
+  cyclic_cover(od.lo[1], od.w[1], nd.lo[1], nd.w[1], n, ylo, ylen);
+  cyclic_cover(od.lo[2], od.w[2], nd.lo[2], nd.w[2], n, zlo, zlen);
+  // --- commit
+  if (!hop && cnt_new > 0)
+    HIPCHK(hipMemcpyAsync(st->upd_ids, new_ids.data(), cnt_new * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(st->updE, nd.E, 48, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(st->updfix, nd.efix, 48, hipMemcpyHostToDevice, s));
+  double dadd[6] = {0, 0, 0, 0, 0, 0};
+  if (st->prob.bc == EC_MEAN_STRAIN_ZERO && cnt_new != cnt_old) {
+    double m[6];
+    for (int a = 0; a < 6; ++a) m[a] = (double)(cnt_new - cnt_old) * nd.E[a] / (double)st->n3;
+    dadd[0] = -(st->C.C11 * m[0] + st->C.C12 * (m[1] + m[2]));
+    dadd[1] = -(st->C.C11 * m[1] + st->C.C12 * (m[0] + m[2]));
+    dadd[2] = -(st->C.C11 * m[2] + st->C.C12 * (m[0] + m[1]));
+    for (int a = 3; a < 6; ++a) dadd[a] = -2.0 * st->C.C44 * m[a];
+  }
+  HIPCHK(hipMemcpyAsync(st->add6 + 12, dadd, 48, hipMemcpyHostToDevice, s));
+  const int32_t* oids = b.ids + off_old;
+  const int32_t* nids = hop ? nullptr : st->upd_ids;
+  LAUNCH(st, s, PF_RASTER, 0,
+         launch_update_es(st->updfix, oids, cnt_old, nids, cnt_new, sh[0], sh[1], sh[2], n, st->es, s));
+  {
+    const bool fp64 = st->fp64;
+    const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
+    const double frac_z = (double)zlen / n;
+    LAUNCH(st, s, PF_XF, frac_z * ylen / n * sb,
+           launch_x_forward_sparse(fp64, oids, cnt_old, nids, cnt_new, sh[0], sh[1], sh[2], st->updE, st->spec, st->g,
+                                   ylo, ylen, zlo, zlen, st->tw, s));
+    const Prune py{ylo, ylen, zlo, zlen};
+    LAUNCH(st, s, PF_Y, 2 * frac_z * sb, launch_pencil(fp64, false, 1, st->spec, st->g, py, st->tw, s));
+    const Prune pz{zlo, zlen, 0, n};
+    const Prune full{0, n, 0, n};
+    LAUNCH(st, s, PF_Z, (1 + frac_z) * sb, launch_pencil(fp64, false, 2, st->spec, st->g, pz, st->tw, s));
+    LAUNCH(st, s, PF_Z, 2 * sb, launch_green(fp64, st->spec, st->g, st->C, s));
+    LAUNCH(st, s, PF_Z, 2 * sb, launch_pencil(fp64, true, 2, st->spec, st->g, full, st->tw, s));
+    LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, st->spec, st->g, full, st->tw, s));
+    LAUNCH(st, s, PF_XI, sb + 2 * fb,
+           launch_x_inverse(fp64, true, st->spec, st->sig, st->g, st->add6 + 12, st->tw, s));
+  }
+  // footprint bookkeeping
+  if (hop) {
+    LAUNCH(st, s, PF_OTHER, 0, launch_translate_ids(b.ids + off_old, cnt_old, sh[0], sh[1], sh[2], n, s));
+  } else {
+    if (cnt_new > 0)
+      HIPCHK(hipMemcpyAsync(b.ids + off_new, st->upd_ids, cnt_new * 4, hipMemcpyDeviceToDevice, s));
+    const int32_t c32 = cnt_new;
+    HIPCHK(hipMemcpyAsync(b.cnt + idx, &c32, 4, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(b.off + idx, &off_new, 8, hipMemcpyHostToDevice, s));
+    st->hcnt[idx] = cnt_new;
+    st->hoff[idx] = off_new;
+    if (off_new != off_old) st->ids_used += cnt_new;
+    st->B_valid = false;
+    if (st->classes.size() != ncls_before) st->gcls_ncls = -1;
+  }
+  HIPCHK(hipMemcpyAsync(b.tab + idx, &nd, sizeof nd, hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));  // host staging above is pageable and short-lived
+  st->hdefs[idx] = nd;
+  if (E_out) return ec_interaction_energies(st, stream, E_out, on_device);
+  return EC_OK;
+}
+
+ec_status ec_state_footprints(ec_state* st, int32_t* counts, int32_t* ids, int64_t cap, int64_t* total) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  int64_t tot = 0;
+  for (int i = 0; i < st->ndef; ++i) tot += st->hcnt[i];
+  if (total) *total = tot;
+  if (counts)
+    for (int i = 0; i < st->ndef; ++i) counts[i] = st->hcnt[i];
+  if (!ids) return EC_OK;
+  if (cap < tot) return fail(EC_ERR_ARG, "ids buffer too small (%lld < %lld)", (long long)cap, (long long)tot);
+  const DefBuf& b = st->db[st->cur];
+  std::vector<int32_t> all((size_t)std::max<int64_t>(st->ids_used, 1));
+  HIPCHK(hipDeviceSynchronize());
+  if (st->ids_used > 0) HIPCHK(hipMemcpy(all.data(), b.ids, st->ids_used * 4, hipMemcpyDeviceToHost));
+  int64_t o = 0;
+  for (int i = 0; i < st->ndef; ++i) {
+    std::memcpy(ids + o, all.data() + st->hoff[i], st->hcnt[i] * 4);
+    o += st->hcnt[i];
+  }
+  return EC_OK;
+}
+
+ec_status ec_state_field(ec_state* st, int32_t which, double* out) {
+  if (!st || !out) return fail(EC_ERR_ARG, "NULL argument");
+  HIPCHK(hipDeviceSynchronize());
+  const size_t cnt = (size_t)6 * st->n3;
+  if (which == 0) {
+    HIPCHK(hipMemcpy(out, st->sig, cnt * 8, hipMemcpyDeviceToHost));
+  } else if (which == 1) {
+    void* tmp = nullptr;
+    ec_status r = ledger_alloc(st->ctx, cnt * 8, &tmp);
+    if (r != EC_OK) return r;
+    hipError_t e = launch_sig_to_out(st->sig, st->es, st->n3, st->C, 1, false, tmp, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, tmp, cnt * 8, hipMemcpyDeviceToHost);
+    ledger_free(st->ctx, tmp, cnt * 8);
+    if (e != hipSuccess) return fail(EC_ERR_DEVICE, "strain output: %s", hipGetErrorString(e));
+  } else if (which == 2) {
+    std::vector<int64_t> tmp(cnt);
+    HIPCHK(hipMemcpy(tmp.data(), st->es, cnt * 8, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < cnt; ++i) out[i] = (double)tmp[i] * FIX_INV;
+  } else {
+    return fail(EC_ERR_ARG, "unknown field %d", which);
+  }
+  return EC_OK;
+}
+
+ec_status ec_state_self_terms(ec_state* st, double* out) {
+  if (!st || !out) return fail(EC_ERR_ARG, "NULL argument");
+  if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
+  ec_status r;
+  if (!st->B_valid && (r = compute_self_terms(st, nullptr)) != EC_OK) return r;
+  HIPCHK(hipDeviceSynchronize());
+  if (st->ndef > 0) HIPCHK(hipMemcpy(out, st->B, st->ndef * 8, hipMemcpyDeviceToHost));
+  return EC_OK;
+}
+
+ec_status ec_profile_enable(ec_state* st, int32_t on) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  st->prof = on != 0;
+  return EC_OK;
+}
+
+ec_status ec_profile_read(ec_state* st, int64_t* launches, double* ms, double* bytes) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  HIPCHK(hipDeviceSynchronize());
+  double tms[EC_NPROF] = {0}, tb[EC_NPROF] = {0};
+  int64_t cnt[EC_NPROF] = {0};
+  for (auto& r : st->recs) {
+    float m = 0.f;
+    HIPCHK(hipEventElapsedTime(&m, r.a, r.b));
+    tms[r.fam] += m;
+    tb[r.fam] += r.bytes;
+    cnt[r.fam] += 1;
+    st->evpool.push_back(r.a);
+    st->evpool.push_back(r.b);
+  }
+  st->recs.clear();
+  for (int f = 0; f < EC_NPROF; ++f) {
+    if (launches) launches[f] = cnt[f];
+    if (ms) ms[f] = tms[f];
+    if (bytes) bytes[f] = cnt[f] ? tb[f] / cnt[f] : 0.0;
+  }
+  return EC_OK;
+}
+
+// ---------------------------------------------------------------- debug passes
+
+namespace {
+
+ec_status upload_spec(ec_state* st, const double* host, void* dev) {
+  const int n = st->n, nh = n / 2 + 1;
+  const size_t rows = (size_t)6 * n * n;
+  if (st->fp64) {
+    HIPCHK(hipMemcpy2D(dev, st->g.P * 16, host, nh * 16, nh * 16, rows, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(rows * nh * 2);
+    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)host[i];
+    HIPCHK(hipMemcpy2D(dev, st->g.P * 8, f.data(), nh * 8, nh * 8, rows, hipMemcpyHostToDevice));
+  }
+  return EC_OK;
+}
+
+ec_status download_spec(ec_state* st, const void* dev, double* host) {
+  const int n = st->n, nh = n / 2 + 1;
+  const size_t rows = (size_t)6 * n * n;
+  if (st->fp64) {
+    HIPCHK(hipMemcpy2D(host, nh * 16, dev, st->g.P * 16, nh * 16, rows, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(rows * nh * 2);
+    HIPCHK(hipMemcpy2D(f.data(), nh * 8, dev, st->g.P * 8, nh * 8, rows, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < f.size(); ++i) host[i] = (double)f[i];
+  }
+  return EC_OK;
+}
+
+struct Tmp {
+  ec_ctx* c;
+  void* p = nullptr;
+  size_t b = 0;
+  ~Tmp() { ledger_free(c, p, b); }
+};
+
+}  // namespace
+
+ec_status ec_debug_forward(ec_state* st, const double* field, double* out) {
+  if (!st || !field || !out) return fail(EC_ERR_ARG, "NULL argument");
+  const size_t cnt = (size_t)6 * st->n3;
+  Tmp es{st->ctx}, sp{st->ctx};
+  ec_status r;
+  if ((r = ledger_alloc(st->ctx, es.b = cnt * 8, &es.p)) != EC_OK) return r;
+  if ((r = ledger_alloc(st->ctx, sp.b = st->spec_bytes, &sp.p)) != EC_OK) return r;
+  std::vector<int64_t> fx(cnt);
+  for (size_t i = 0; i < cnt; ++i) fx[i] = (int64_t)std::llrint(field[i] * FIX_SCALE);
+  HIPCHK(hipMemcpy(es.p, fx.data(), cnt * 8, hipMemcpyHostToDevice));
+  const Prune full{0, st->n, 0, st->n};
+  HIPCHK(launch_x_forward(st->fp64, (const int64_t*)es.p, sp.p, st->g, st->tw, nullptr));
+  HIPCHK(launch_pencil(st->fp64, false, 1, sp.p, st->g, full, st->tw, nullptr));
+  HIPCHK(launch_pencil(st->fp64, false, 2, sp.p, st->g, full, st->tw, nullptr));
+  HIPCHK(hipDeviceSynchronize());
+  return download_spec(st, sp.p, out);
+}
+
+ec_status ec_debug_green(ec_state* st, const double* in, double* out) {
+  if (!st || !in || !out) return fail(EC_ERR_ARG, "NULL argument");
+  Tmp sp{st->ctx};
+  ec_status r;
+  if ((r = ledger_alloc(st->ctx, sp.b = st->spec_bytes, &sp.p)) != EC_OK) return r;
+  if ((r = upload_spec(st, in, sp.p)) != EC_OK) return r;
+  HIPCHK(launch_green(st->fp64, sp.p, st->g, st->C, nullptr));
+  HIPCHK(hipDeviceSynchronize());
+  return download_spec(st, sp.p, out);
+}
+
+ec_status ec_debug_inverse(ec_state* st, const double* in, double* out) {
+  if (!st || !in || !out) return fail(EC_ERR_ARG, "NULL argument");
+  const size_t cnt = (size_t)6 * st->n3;
+  Tmp sp{st->ctx}, sg{st->ctx}, ad{st->ctx};
+  ec_status r;
+  if ((r = ledger_alloc(st->ctx, sp.b = st->spec_bytes, &sp.p)) != EC_OK) return r;
+  if ((r = ledger_alloc(st->ctx, sg.b = cnt * 8, &sg.p)) != EC_OK) return r;
+  if ((r = ledger_alloc(st->ctx, ad.b = 64, &ad.p)) != EC_OK) return r;
+  if ((r = upload_spec(st, in, sp.p)) != EC_OK) return r;
+  HIPCHK(hipMemset(ad.p, 0, 64));
+  const Prune full{0, st->n, 0, st->n};
+  HIPCHK(launch_pencil(st->fp64, true, 2, sp.p, st->g, full, st->tw, nullptr));
+  HIPCHK(launch_pencil(st->fp64, true, 1, sp.p, st->g, full, st->tw, nullptr));
+  HIPCHK(launch_x_inverse(st->fp64, false, sp.p, (double*)sg.p, st->g, (const double*)ad.p, st->tw, nullptr));
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(out, sg.p, cnt * 8, hipMemcpyDeviceToHost));
+  return EC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,155 @@
+// ec_internal.h - shared definitions of the HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "ec.h"
+
+namespace ec {
+
+constexpr int QSUB = 1024;  // coordinate quantisation steps per voxel edge (q = h/1024)
+
+// The eigenstrain field is held as int64 fixed point with 56 fractional bits:
+// contributions add and subtract exactly and in any order, so rasterisation is
+// deterministic and an incremental move restores untouched voxels bit for bit.
+// |sum of overlapping components| must stay below 128.
+constexpr double FIX_SCALE = 72057594037927936.0;  // 2^56
+constexpr double FIX_INV = 1.0 / 72057594037927936.0;
+
+// 1 GPa nm^3 in eV (1e-18 J / elementary charge).
+constexpr double GPA_NM3_EV = 1.0e-18 / 1.602176634e-19;
+
+// Tensor-component weights of the double contraction A:B in 6-vector form.
+__host__ __device__ constexpr double ddot_w(int a) { return a < 3 ? 1.0 : 2.0; }
+
+// One quantised defect as the kernels see it (computed on the host).
+struct DevDefect {
+  int32_t kind;   // 0 loop, 1 sphere
+  int32_t cq[3];  // centre in q units, [0, 1024 n)
+  int32_t m[3];   // integer habit normal (loops)
+  int32_t mm;     // m.m
+  int32_t eq;     // slab thickness in q units
+  int32_t lo[3];  // bounding-box first voxel index per axis, in [0, n)
+  int32_t w[3];   // bounding-box widths per axis, <= n
+  int32_t cls;    // eigenstrain direction class (-1: none)
+  int64_t R2q;    // radius^2 in q^2 units
+  int64_t efix[6];
+  double E[6];    // eigenstrain, tensor components xx yy zz yz xz xy
+  double s;       // E = s * class direction (when cls >= 0)
+  double pad_;
+};
+
+// Voxel-centre membership, exact integer arithmetic (loops: half-open slab
+// along the lattice normal m, closed disk; spheres: closed ball).
+__host__ __device__ inline bool member(const DevDefect& d, int n, int x, int y, int z) {
+  const int64_t Lq = (int64_t)QSUB * n, half = Lq / 2;
+  const int v[3] = {x, y, z};
+  int64_t dd[3];
+  for (int k = 0; k < 3; ++k) {
+    int64_t t = (int64_t)QSUB * v[k] + QSUB / 2 - d.cq[k] + half + Lq;
+    dd[k] = t % Lq - half;
+  }
+  const int64_t d2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+  if (d.kind == 1) return d2 <= d.R2q;
+  const int64_t t = d.m[0] * dd[0] + d.m[1] * dd[1] + d.m[2] * dd[2];
+  const int64_t lim = (int64_t)d.eq * d.eq * d.mm;
+  const bool slab = (t >= 0) ? (4 * t * t < lim) : (4 * t * t <= lim);
+  return slab && ((int64_t)d.mm * d2 - t * t <= (int64_t)d.mm * d.R2q);
+}
+
+// Box enumeration order: per axis, the w voxels starting at lo (mod n) listed
+// ascending, so (z, y, x)-lexicographic enumeration yields ascending linear ids.
+__host__ __device__ inline int box_axis(int lo, int w, int n, int i) {
+  const int wl = lo + w - n;  // voxels that wrap to the low end
+  if (wl <= 0) return lo + i;
+  return i < wl ? i : lo + (i - wl);
+}
+
+// Storage helpers
+__device__ __forceinline__ double2 ld2(const float2* p) {
+  float2 v = *p;
+  return make_double2((double)v.x, (double)v.y);
+}
+__device__ __forceinline__ double2 ld2(const double2* p) { return *p; }
+__device__ __forceinline__ void st2(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ void st2(double2* p, double2 v) { *p = v; }
+
+template <typename S>
+struct Cplx;
+template <>
+struct Cplx<float> {
+  using T = float2;
+};
+template <>
+struct Cplx<double> {
+  using T = double2;
+};
+
+// Cubic stiffness passed to kernels.
+struct Cubic {
+  double C11, C12, C44;
+};
+
+// Profiling families (see ec_profile_read).
+enum ProfFam { PF_RASTER = 0, PF_XF = 1, PF_Y = 2, PF_Z = 3, PF_XI = 4, PF_REDUCE = 5, PF_SELF = 6, PF_OTHER = 7 };
+
+// ---- launch interfaces implemented in k_fft.hip ------------------------------
+
+struct SpecGeom {
+  int n;
+  int P;  // row pitch (complex elements) of the half spectrum, >= n/2 + 1
+};
+
+// Pruning of the pencil passes (incremental updates): only positions
+// [lo, lo + len) (cyclic) of the transform axis carry data, and for the y pass
+// only z planes [zlo, zlo + zlen) are transformed.  len = n / zlen = n: no pruning.
+struct Prune {
+  int in_lo, in_len;
+  int z_lo, z_len;
+};
+
+bool fft_supported(int n);
+int pencil_width(int n, bool fp64);
+
+hipError_t launch_x_forward(bool fp64, const int64_t* es, void* spec, SpecGeom g, const double2* tw, hipStream_t s);
+hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, int old_cnt, const int32_t* new_ids, int new_cnt,
+                                   int shift_x, int shift_y, int shift_z, const double* E, void* spec, SpecGeom g,
+                                   int y_lo, int y_len, int z_lo, int z_len, const double2* tw, hipStream_t s);
+hipError_t launch_pencil(bool fp64, bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw,
+                         hipStream_t s);
+hipError_t launch_green(bool fp64, void* spec, SpecGeom g, Cubic C, hipStream_t s);
+hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, hipStream_t s);
+hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
+                            const double2* tw, hipStream_t s);
+
+// ---- k_raster.hip / k_energy.hip -----------------------------------------------
+
+hipError_t launch_raster_count(const DevDefect* d, int ndef, int n, int32_t* counts, hipStream_t s);
+hipError_t launch_scan(const int32_t* counts, int ndef, int64_t* offsets, hipStream_t s);
+hipError_t launch_raster_fill(const DevDefect* d, int ndef, int n, const int64_t* offsets, int32_t* ids,
+                              int64_t* es, hipStream_t s);
+hipError_t launch_unraster(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
+                           const int32_t* ids, int64_t n3, int64_t* es, hipStream_t s);
+hipError_t launch_update_es(const int64_t* efix, const int32_t* old_ids, int cnt_old, const int32_t* new_ids,
+                            int cnt_new, int shift_x, int shift_y, int shift_z, int n, int64_t* es, hipStream_t s);
+hipError_t launch_translate_ids(int32_t* ids, int cnt, int shift_x, int shift_y, int shift_z, int n, hipStream_t s);
+hipError_t launch_mean_stress(const DevDefect* d, const int32_t* counts, int ndef, int64_t n3, Cubic C, int bc,
+                              double* add6, hipStream_t s);
+hipError_t launch_fill_i64(int64_t* p, int64_t count, int64_t v, hipStream_t s);
+hipError_t launch_reduce(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
+                         const int32_t* ids, const double* sig, int64_t n3, const double* B, double h3c, double* S6,
+                         double* E, hipStream_t s);
+hipError_t launch_window_crop(const double* sig, int n, int D, int b, double* K, hipStream_t s);
+hipError_t launch_class_windows(const double* K, int D, const double* dirs, int ncls, double* g, hipStream_t s);
+hipError_t launch_self_terms(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
+                             const int32_t* ids, int n, const double* K, const double* gcls, int D, double h3c,
+                             double* B, hipStream_t s);
+hipError_t launch_sig_to_out(const double* sig, const int64_t* es, int64_t n3, Cubic C, int which, bool fp32,
+                             void* out, hipStream_t s);
+
+constexpr int KWIN = 24;  // doubles per window point (21 used: the symmetric 6x6 kernel)
+
+}  // namespace ec

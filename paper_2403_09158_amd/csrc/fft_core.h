@@ -1,0 +1,266 @@
+// fft_core.h - mixed-radix (2/3/4/5/8/16) Stockham FFT building blocks for gfx950.
+//
+// Every transform here is a 1-D DFT of compile-time length N computed by a
+// workgroup in FP64 registers.  The first stage reads its operands straight from
+// HBM (or from an input rule), intermediate stages exchange through LDS, and the
+// last stage hands its outputs to a store rule, so a two-stage length makes one
+// LDS round trip.  Stockham indexing (self-sorting, no bit reversal):
+//   stage with radix R after a product Ns of earlier radices, butterfly j in [0, N/R):
+//     k = j mod Ns, inputs x[j + r N/R], twiddles W_N^{k r N/(Ns R)},
+//     outputs y[(j/Ns) Ns R + k + r Ns].
+// Twiddles W_N^e = exp(-2 pi i e / N) come from a table computed on the host in
+// extended precision and staged in LDS; the inverse transform uses conjugates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ec {
+
+struct Plan2 {
+  int nstage;
+  int r[3];
+};
+
+// Radix sequence per supported length (first stage first).
+__host__ __device__ constexpr Plan2 plan_of(int N) {
+  return N == 8     ? Plan2{1, {8, 1, 1}}
+         : N == 16  ? Plan2{1, {16, 1, 1}}
+         : N == 24  ? Plan2{2, {8, 3, 1}}
+         : N == 32  ? Plan2{2, {8, 4, 1}}
+         : N == 48  ? Plan2{2, {16, 3, 1}}
+         : N == 64  ? Plan2{2, {8, 8, 1}}
+         : N == 96  ? Plan2{3, {8, 4, 3}}
+         : N == 128 ? Plan2{2, {16, 8, 1}}
+         : N == 160 ? Plan2{3, {8, 4, 5}}
+         : N == 240 ? Plan2{3, {16, 5, 3}}
+         : N == 256 ? Plan2{2, {16, 16, 1}}
+         : N == 512 ? Plan2{3, {8, 8, 8}}
+                    : Plan2{0, {1, 1, 1}};
+}
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 conjd(double2 a) { return make_double2(a.x, -a.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ double2 rot90(double2 a) {
+  return INV ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+// exp(-+ 2 pi i e / R) for the small in-register composites (R = 8, 16).
+template <int R, bool INV>
+__device__ __forceinline__ double2 wsmall(int e) {
+  // cos(2 pi k / 16), k = 0..15
+  constexpr double c16[16] = {1.0,
+                              0.92387953251128675613,
+                              0.70710678118654752440,
+                              0.38268343236508977173,
+                              0.0,
+                              -0.38268343236508977173,
+                              -0.70710678118654752440,
+                              -0.92387953251128675613,
+                              -1.0,
+                              -0.92387953251128675613,
+                              -0.70710678118654752440,
+                              -0.38268343236508977173,
+                              0.0,
+                              0.38268343236508977173,
+                              0.70710678118654752440,
+                              0.92387953251128675613};
+  const int k = (e * (16 / R)) & 15;
+  const double c = c16[k];
+  const double s = c16[(k + 12) & 15];  // sin(2 pi k/16) = cos(2 pi (k - 4)/16)
+  return INV ? make_double2(c, s) : make_double2(c, -s);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ double2 twid_small(double2 a, int e) {
+  const int q = (e * (16 / R)) & 15;
+  if (q == 0) return a;
+  if (q == 8) return make_double2(-a.x, -a.y);
+  if (q == 4) return rot90<INV>(a);
+  if (q == 12) return rot90<!INV>(a);
+  return cmul(a, wsmall<R, INV>(e));
+}
+
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<1, INV> {
+  __device__ __forceinline__ static void run(double2*) {}
+};
+
+template <bool INV>
+struct Dft<2, INV> {
+  __device__ __forceinline__ static void run(double2* v) {
+    double2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <bool INV>
+struct Dft<3, INV> {
+  __device__ __forceinline__ static void run(double2* v) {
+    constexpr double h = 0.86602540378443864676;  // sin(2 pi / 3)
+    double2 a = v[0], s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    double2 t = make_double2(a.x - 0.5 * s.x, a.y - 0.5 * s.y);
+    double2 u = rot90<INV>(cscale(d, h));
+    v[0] = cadd(a, s);
+    v[1] = cadd(t, u);
+    v[2] = csub(t, u);
+  }
+};
+
+template <bool INV>
+struct Dft<4, INV> {
+  __device__ __forceinline__ static void run(double2* v) {
+    double2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    double2 t2 = cadd(v[1], v[3]), t3 = rot90<INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+  }
+};
+
+template <bool INV>
+struct Dft<5, INV> {
+  __device__ __forceinline__ static void run(double2* v) {
+    constexpr double c1 = 0.30901699437494742410;   // cos(2 pi/5)
+    constexpr double c2 = -0.80901699437494742410;  // cos(4 pi/5)
+    constexpr double s1 = 0.95105651629515357212;   // sin(2 pi/5)
+    constexpr double s2 = 0.58778525229247312917;   // sin(4 pi/5)
+    double2 a = v[0];
+    double2 p1 = cadd(v[1], v[4]), m1 = csub(v[1], v[4]);
+    double2 p2 = cadd(v[2], v[3]), m2 = csub(v[2], v[3]);
+    double2 r1 = make_double2(a.x + c1 * p1.x + c2 * p2.x, a.y + c1 * p1.y + c2 * p2.y);
+    double2 r2 = make_double2(a.x + c2 * p1.x + c1 * p2.x, a.y + c2 * p1.y + c1 * p2.y);
+    double2 q1 = rot90<INV>(make_double2(s1 * m1.x + s2 * m2.x, s1 * m1.y + s2 * m2.y));
+    double2 q2 = rot90<INV>(make_double2(s2 * m1.x - s1 * m2.x, s2 * m1.y - s1 * m2.y));
+    v[0] = cadd(a, cadd(p1, p2));
+    v[1] = cadd(r1, q1);
+    v[4] = csub(r1, q1);
+    v[2] = cadd(r2, q2);
+    v[3] = csub(r2, q2);
+  }
+};
+
+// Composite R = R1*R2 in registers: inputs x[n1 + R1 n2], outputs X[k2 + R2 k1].
+template <int R1, int R2, bool INV>
+__device__ __forceinline__ void dft_composite(double2* v) {
+  constexpr int R = R1 * R2;
+  double2 y[R];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) {
+    double2 t[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) t[n2] = v[n1 + R1 * n2];
+    Dft<R2, INV>::run(t);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) y[n1 * R2 + k2] = twid_small<R, INV>(t[k2], n1 * k2);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    double2 t[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) t[n1] = y[n1 * R2 + k2];
+    Dft<R1, INV>::run(t);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) v[k2 + R2 * k1] = t[k1];
+  }
+}
+
+template <bool INV>
+struct Dft<8, INV> {
+  __device__ __forceinline__ static void run(double2* v) { dft_composite<2, 4, INV>(v); }
+};
+
+template <bool INV>
+struct Dft<16, INV> {
+  __device__ __forceinline__ static void run(double2* v) { dft_composite<4, 4, INV>(v); }
+};
+
+// Twiddle from the LDS table (forward W_N^e; conjugated for the inverse).
+template <bool INV>
+__device__ __forceinline__ double2 tw_at(const double2* tw, int e) {
+  double2 t = tw[e];
+  return INV ? make_double2(t.x, -t.y) : t;
+}
+
+// One Stockham stage over `nfft` transforms of length N with radix R after
+// Ns = product of earlier radices.  Butterfly b -> (transform f, index j) by
+// MAP (pencil: f fastest across lanes, so columns stay contiguous; row: j
+// fastest, so positions along a contiguous row stay contiguous).  Operands are
+// all read (LOAD) before the barrier and written (STORE) after it, so the
+// stage may run in place on LDS.  BPT = butterflies per thread.
+enum class Map { Pencil, Row };
+
+template <int N, int R, int NS, bool INV, Map M, int NFFT, int T, class Load, class Store>
+__device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& store, bool sync_between) {
+  constexpr int NB = NFFT * (N / R);
+  constexpr int BPT = (NB + T - 1) / T;
+  double2 v[BPT][R];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * T;
+    if (NB % T == 0 || b < NB) {
+      const int f = (M == Map::Pencil) ? (b % NFFT) : (b / (N / R));
+      const int j = (M == Map::Pencil) ? (b / NFFT) : (b % (N / R));
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = load(f, j + r * (N / R));
+    }
+  }
+  if (sync_between) __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = threadIdx.x + q * T;
+    if (NB % T == 0 || b < NB) {
+      const int f = (M == Map::Pencil) ? (b % NFFT) : (b / (N / R));
+      const int j = (M == Map::Pencil) ? (b / NFFT) : (b % (N / R));
+      const int k = j % NS;
+      if (NS > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw_at<INV>(tw, (k * r * (N / (NS * R))) % N));
+      }
+      Dft<R, INV>::run(v[q]);
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) store(f, base + r * NS, v[q][r]);
+    }
+  }
+}
+
+// Full transform: first stage LOAD0 -> LDS (or -> STORE_LAST for one stage),
+// middle stages in place on LDS, last stage LDS -> STORE_LAST.  `lds(f, i)`
+// returns a reference to element i of transform f in LDS.  LAST_LDS: the last
+// stage's store writes LDS too (then it must not overwrite unread operands),
+// and LOAD0_LDS: the first stage reads LDS in place.
+template <int N, bool INV, Map M, int NFFT, int T, bool LOAD0_LDS = false, bool LAST_LDS = false, class Load0,
+          class Lds, class StoreLast>
+__device__ __forceinline__ void transform(const double2* tw, Load0&& load0, Lds&& lds, StoreLast&& store_last) {
+  constexpr Plan2 P = plan_of(N);
+  static_assert(P.nstage >= 1, "unsupported FFT length");
+  auto to_lds = [&](int f, int i, double2 x) { lds(f, i) = x; };
+  auto from_lds = [&](int f, int i) { return lds(f, i); };
+  if constexpr (P.nstage == 1) {
+    stage<N, P.r[0], 1, INV, M, NFFT, T>(tw, load0, store_last, LOAD0_LDS && LAST_LDS);
+  } else if constexpr (P.nstage == 2) {
+    stage<N, P.r[0], 1, INV, M, NFFT, T>(tw, load0, to_lds, LOAD0_LDS);
+    __syncthreads();
+    stage<N, P.r[1], P.r[0], INV, M, NFFT, T>(tw, from_lds, store_last, LAST_LDS);
+  } else {
+    stage<N, P.r[0], 1, INV, M, NFFT, T>(tw, load0, to_lds, LOAD0_LDS);
+    __syncthreads();
+    stage<N, P.r[1], P.r[0], INV, M, NFFT, T>(tw, from_lds, to_lds, true);
+    __syncthreads();
+    stage<N, P.r[2], P.r[0] * P.r[1], INV, M, NFFT, T>(tw, from_lds, store_last, LAST_LDS);
+  }
+}
+
+}  // namespace ec

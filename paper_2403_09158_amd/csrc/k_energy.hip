@@ -1,0 +1,237 @@
+// k_energy.hip - per-defect interaction energies and the discrete self term.
+//
+// Sec. 2 (Betti form) with the eigenstrain: E_ij = -h^3 c sum_x eps*_i : sigma_j.
+// Summing over j != i with superposition (the total field is the sum of the
+// defects' fields) gives E_i = -h^3 c E_i:S_i - B_i, where S_i is the sum of the
+// resident FP64 stress over the footprint of i and B_i = -h^3 c sum over pairs
+// (x, y) of the footprint of E_i:G(x - y):E_i is the defect's own contribution,
+// G being the discrete periodic kernel sigma = G * eps* (a window of it around
+// r = 0 is enough because footprints are compact).
+#include "ec_internal.h"
+
+namespace ec {
+
+namespace {
+
+// Index of the symmetric pair (a <= b) in the 21-entry window record.
+__host__ __device__ constexpr int tri(int a, int b) { return a * 6 - (a * (a - 1)) / 2 + (b - a); }
+
+__device__ __forceinline__ void neumaier(double& s, double& c, double v) {
+  const double t = s + v;
+  c += (fabs(s) >= fabs(v)) ? ((s - t) + v) : ((v - t) + s);
+  s = t;
+}
+
+constexpr int RDT = 64;  // one wavefront per defect
+
+__global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ defs, const int64_t* __restrict__ off,
+                                                const int32_t* __restrict__ cnt, const int32_t* __restrict__ ids,
+                                                const double* __restrict__ sig, int64_t n3,
+                                                const double* __restrict__ B, double h3c, double* __restrict__ S6,
+                                                double* __restrict__ E) {
+  const int i = blockIdx.x;
+  const int64_t o = off[i];
+  const int m = cnt[i];
+  double s[6], c[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) s[a] = c[a] = 0.0;
+  for (int k = threadIdx.x; k < m; k += RDT) {
+    const int id = ids[o + k];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) neumaier(s[a], c[a], sig[a * n3 + id]);
+  }
+  __shared__ double ps[6][RDT], pc[6][RDT];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    ps[a][threadIdx.x] = s[a];
+    pc[a][threadIdx.x] = c[a];
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int a = threadIdx.x;
+    double ss = 0.0, cc = 0.0;
+    for (int t = 0; t < RDT; ++t) {
+      neumaier(ss, cc, ps[a][t]);
+      cc += pc[a][t];
+    }
+    ps[a][0] = ss + cc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const DevDefect d = defs[i];
+    double dot = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      dot += ddot_w(a) * d.E[a] * ps[a][0];
+      if (S6) S6[6 * i + a] = ps[a][0];
+    }
+    E[i] = -h3c * dot - B[i];
+  }
+}
+
+// Window of the kernel from one impulse solve: sigma_a(r) is the response to a
+// unit eigenstrain component b at voxel 0; store K_ab(r) = w_a sigma_a(r)
+// (w = 1, 1, 1, 2, 2, 2) for a <= b, r in [-D, D]^3.
+__global__ void k_window_crop(const double* __restrict__ sig, int n, int D, int b, double* __restrict__ K) {
+  const int W = 2 * D + 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)W * W * W) return;
+  const int rx = (int)(t % W) - D, ry = (int)((t / W) % W) - D, rz = (int)(t / ((int64_t)W * W)) - D;
+  const int x = (rx % n + n) % n, y = (ry % n + n) % n, z = (rz % n + n) % n;
+  const int64_t n3 = (int64_t)n * n * n;
+  const int64_t id = ((int64_t)z * n + y) * n + x;
+  for (int a = 0; a <= b; ++a) K[t * KWIN + tri(a, b)] = ddot_w(a) * sig[a * n3 + id];
+}
+
+// Scalar window per eigenstrain direction class: g_c(r) = e_c : K(r) : e_c.
+__global__ void k_class_windows(const double* __restrict__ K, int64_t W3, const double* __restrict__ dirs, int ncls,
+                                double* __restrict__ g) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W3 * ncls) return;
+  const int c = (int)(t / W3);
+  const int64_t r = t % W3;
+  const double* e = dirs + 6 * c;
+  const double* k = K + r * KWIN;
+  double s = 0.0;
+  for (int a = 0; a < 6; ++a) {
+    s += e[a] * e[a] * k[tri(a, a)];
+    for (int b = a + 1; b < 6; ++b) s += 2.0 * e[a] * e[b] * k[tri(a, b)];
+  }
+  g[t] = s;
+}
+
+constexpr int ST = 256;
+constexpr int SMAX = 8192;  // footprint voxels staged in LDS
+
+__global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs, const int64_t* __restrict__ off,
+                                             const int32_t* __restrict__ cnt, const int32_t* __restrict__ ids, int n,
+                                             const double* __restrict__ K, const double* __restrict__ gcls, int D,
+                                             double h3c, double* __restrict__ B) {
+  const int i = blockIdx.x;
+  const int m = cnt[i];
+  const int64_t o = off[i];
+  const DevDefect d = defs[i];
+  __shared__ int32_t pk[SMAX];
+  const bool staged = m <= SMAX;
+  if (staged)
+    for (int k = threadIdx.x; k < m; k += ST) {
+      const int id = ids[o + k];
+      pk[k] = (id % n) | (((id / n) % n) << 10) | ((id / (n * n)) << 20);
+    }
+  __syncthreads();
+  auto coord = [&](int k) -> int32_t {
+    if (staged) return pk[k];
+    const int id = ids[o + k];
+    return (id % n) | (((id / n) % n) << 10) | ((id / (n * n)) << 20);
+  };
+  const int W = 2 * D + 1;
+  const int64_t W3 = (int64_t)W * W * W;
+  const int h = n / 2;
+  const double* g = d.cls >= 0 ? gcls + (int64_t)d.cls * W3 : nullptr;
+  double acc = 0.0;
+  for (int p = threadIdx.x; p < m; p += ST) {
+    const int32_t P = coord(p);
+    const int px = P & 1023, py = (P >> 10) & 1023, pz = P >> 20;
+    double rowsum = 0.0;
+    for (int q = 0; q < m; ++q) {
+      const int32_t Q = coord(q);
+      int rx = px - (Q & 1023), ry = py - ((Q >> 10) & 1023), rz = pz - (Q >> 20);
+      rx += rx < -h ? n : (rx >= h ? -n : 0);
+      ry += ry < -h ? n : (ry >= h ? -n : 0);
+      rz += rz < -h ? n : (rz >= h ? -n : 0);
+      const int64_t idx = ((int64_t)(rz + D) * W + (ry + D)) * W + (rx + D);
+      if (g) {
+        rowsum += g[idx];
+      } else {
+        const double* k = K + idx * KWIN;
+        double s = 0.0;
+        for (int a = 0; a < 6; ++a) {
+          s += d.E[a] * d.E[a] * k[tri(a, a)];
+          for (int b = a + 1; b < 6; ++b) s += 2.0 * d.E[a] * d.E[b] * k[tri(a, b)];
+        }
+        rowsum += s;
+      }
+    }
+    acc += rowsum;
+  }
+  __shared__ double red[ST];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0, c = 0.0;
+    for (int t = 0; t < ST; ++t) neumaier(s, c, red[t]);
+    const double scale = g ? d.s * d.s : 1.0;
+    B[i] = -h3c * scale * (s + c);
+  }
+}
+
+// Dense outputs: which 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic compliance).
+template <typename OT>
+__global__ void k_sig_to_out(const double* __restrict__ sig, const int64_t* __restrict__ es, int64_t n3, Cubic C,
+                             int which, OT* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n3) return;
+  double s[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) s[a] = sig[a * n3 + t];
+  if (which == 0) {
+#pragma unroll
+    for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)s[a];
+    return;
+  }
+  const double den = (C.C11 - C.C12) * (C.C11 + 2.0 * C.C12);
+  const double S11 = (C.C11 + C.C12) / den, S12 = -C.C12 / den, S44h = 0.5 / C.C44;
+  double e[6];
+  e[0] = S11 * s[0] + S12 * (s[1] + s[2]);
+  e[1] = S11 * s[1] + S12 * (s[0] + s[2]);
+  e[2] = S11 * s[2] + S12 * (s[0] + s[1]);
+  for (int a = 3; a < 6; ++a) e[a] = S44h * s[a];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)(e[a] + (double)es[a * n3 + t] * FIX_INV);
+}
+
+}  // namespace
+
+hipError_t launch_reduce(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
+                         const int32_t* ids, const double* sig, int64_t n3, const double* B, double h3c, double* S6,
+                         double* E, hipStream_t s) {
+  if (ndef == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(ndef), dim3(RDT), 0, s, d, offsets, counts, ids, sig, n3, B, h3c, S6, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_window_crop(const double* sig, int n, int D, int b, double* K, hipStream_t s) {
+  const int W = 2 * D + 1;
+  const int64_t W3 = (int64_t)W * W * W;
+  hipLaunchKernelGGL(k_window_crop, dim3((unsigned)((W3 + 255) / 256)), dim3(256), 0, s, sig, n, D, b, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_class_windows(const double* K, int D, const double* dirs, int ncls, double* g, hipStream_t s) {
+  if (ncls == 0) return hipSuccess;
+  const int W = 2 * D + 1;
+  const int64_t W3 = (int64_t)W * W * W;
+  hipLaunchKernelGGL(k_class_windows, dim3((unsigned)((W3 * ncls + 255) / 256)), dim3(256), 0, s, K, W3, dirs, ncls,
+                     g);
+  return hipGetLastError();
+}
+
+hipError_t launch_self_terms(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
+                             const int32_t* ids, int n, const double* K, const double* gcls, int D, double h3c,
+                             double* B, hipStream_t s) {
+  if (ndef == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_self, dim3(ndef), dim3(ST), 0, s, d, offsets, counts, ids, n, K, gcls, D, h3c, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_sig_to_out(const double* sig, const int64_t* es, int64_t n3, Cubic C, int which, bool fp32,
+                             void* out, hipStream_t s) {
+  const unsigned grid = (unsigned)((n3 + 255) / 256);
+  if (fp32)
+    hipLaunchKernelGGL(k_sig_to_out<float>, dim3(grid), dim3(256), 0, s, sig, es, n3, C, which, (float*)out);
+  else
+    hipLaunchKernelGGL(k_sig_to_out<double>, dim3(grid), dim3(256), 0, s, sig, es, n3, C, which, (double*)out);
+  return hipGetLastError();
+}
+
+}  // namespace ec

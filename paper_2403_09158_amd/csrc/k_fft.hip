@@ -1,0 +1,544 @@
+// k_fft.hip - FFT passes and the Green operator of the periodic eigenstrain solve.
+//
+// Half-spectrum layout: [6][kz][ky][kx] complex, kx in [0, n/2] with row pitch P
+// (padded so every row starts on a 128-byte boundary).  The solve runs:
+//   x-forward (R2C, two real rows per complex transform), y-forward,
+//   z-forward + Green operator + z-inverse, y-inverse, x-inverse (C2R) + stress.
+// All butterflies, twiddles and the Green operator run in FP64 registers; the
+// storage type S (float or double) only sets what is kept in HBM between passes.
+#include "ec_internal.h"
+#include "fft_core.h"
+
+namespace ec {
+
+namespace {
+
+constexpr int max_nb(int N, int F) {
+  Plan2 p = plan_of(N);
+  int m = 0;
+  for (int s = 0; s < p.nstage; ++s) {
+    int b = F * (N / p.r[s]);
+    if (b > m) m = b;
+  }
+  return m;
+}
+constexpr int pick_T(int nb) { return nb >= 256 ? 256 : ((nb + 63) / 64) * 64; }
+constexpr int pencil_W_of(int N) { return N >= 512 ? 8 : 16; }
+constexpr int x_rows(int N) {
+  int best = 1;
+  for (int r = 1; r <= N; ++r)
+    if (N % r == 0 && 3 * r * N <= 3072) best = r;
+  return best;
+}
+
+// ----------------------------------------------------------------- Green operator
+//
+// Sec. 3.2: eps_hat = Gamma(xi):(C:eps*_hat) with Gamma built from N = K^-1,
+// K_ik = C_ijkl xi_j xi_l; here eps_hat = sym(xi (x) N (tau xi)), tau = C:eps*_hat,
+// and the kernel returns sigma_hat = C:eps_hat - tau (the stress spectrum, so the
+// inverse transform yields sigma directly).  Gamma is homogeneous of degree 0 in
+// xi, so the integer labels stand in for xi = 2 pi k / L.
+
+__device__ __forceinline__ void acc_eps(double ax, double ay, double az, const Cubic& C, const double2* tau,
+                                        double2* eps, double wgt) {
+  const double x2 = ax * ax, y2 = ay * ay, z2 = az * az, r2 = x2 + y2 + z2;
+  const double K00 = C.C11 * x2 + C.C44 * (r2 - x2);
+  const double K11 = C.C11 * y2 + C.C44 * (r2 - y2);
+  const double K22 = C.C11 * z2 + C.C44 * (r2 - z2);
+  const double cc = C.C12 + C.C44;
+  const double K01 = cc * ax * ay, K02 = cc * ax * az, K12 = cc * ay * az;
+  const double A00 = K11 * K22 - K12 * K12;
+  const double A11 = K00 * K22 - K02 * K02;
+  const double A22 = K00 * K11 - K01 * K01;
+  const double A01 = K02 * K12 - K01 * K22;
+  const double A02 = K01 * K12 - K02 * K11;
+  const double A12 = K01 * K02 - K00 * K12;
+  const double inv = wgt / (K00 * A00 + K01 * A01 + K02 * A02);
+  // v = tau . xi (tau symmetric: xx yy zz yz xz xy)
+  double2 v0, v1, v2;
+  v0.x = tau[0].x * ax + tau[5].x * ay + tau[4].x * az;
+  v0.y = tau[0].y * ax + tau[5].y * ay + tau[4].y * az;
+  v1.x = tau[5].x * ax + tau[1].x * ay + tau[3].x * az;
+  v1.y = tau[5].y * ax + tau[1].y * ay + tau[3].y * az;
+  v2.x = tau[4].x * ax + tau[3].x * ay + tau[2].x * az;
+  v2.y = tau[4].y * ax + tau[3].y * ay + tau[2].y * az;
+  double2 w0, w1, w2;  // w = N v (scaled by wgt)
+  w0.x = (A00 * v0.x + A01 * v1.x + A02 * v2.x) * inv;
+  w0.y = (A00 * v0.y + A01 * v1.y + A02 * v2.y) * inv;
+  w1.x = (A01 * v0.x + A11 * v1.x + A12 * v2.x) * inv;
+  w1.y = (A01 * v0.y + A11 * v1.y + A12 * v2.y) * inv;
+  w2.x = (A02 * v0.x + A12 * v1.x + A22 * v2.x) * inv;
+  w2.y = (A02 * v0.y + A12 * v1.y + A22 * v2.y) * inv;
+  eps[0].x += ax * w0.x;
+  eps[0].y += ax * w0.y;
+  eps[1].x += ay * w1.x;
+  eps[1].y += ay * w1.y;
+  eps[2].x += az * w2.x;
+  eps[2].y += az * w2.y;
+  eps[3].x += 0.5 * (ay * w2.x + az * w1.x);
+  eps[3].y += 0.5 * (ay * w2.y + az * w1.y);
+  eps[4].x += 0.5 * (ax * w2.x + az * w0.x);
+  eps[4].y += 0.5 * (ax * w2.y + az * w0.y);
+  eps[5].x += 0.5 * (ax * w1.x + ay * w0.x);
+  eps[5].y += 0.5 * (ax * w1.y + ay * w0.y);
+}
+
+// sigma_hat at bin (kx in [0, n/2], ky, kz in [0, n)) from eps*_hat (in place).
+// Even-n Nyquist rule: a bin with any index at n/2 gets the mean of the
+// operators at the all -n/2 and all +n/2 labels (real part of the centred
+// full-complex solution).  xi = 0: zero (the mean is added in FP64 later).
+__device__ __forceinline__ void green_bin(double2* e, int kx, int ky, int kz, int n, const Cubic& C) {
+  if (kx == 0 && ky == 0 && kz == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = make_double2(0.0, 0.0);
+    return;
+  }
+  double2 tau[6];
+  const double c44x2 = 2.0 * C.C44;
+  tau[0].x = C.C11 * e[0].x + C.C12 * (e[1].x + e[2].x);
+  tau[0].y = C.C11 * e[0].y + C.C12 * (e[1].y + e[2].y);
+  tau[1].x = C.C11 * e[1].x + C.C12 * (e[0].x + e[2].x);
+  tau[1].y = C.C11 * e[1].y + C.C12 * (e[0].y + e[2].y);
+  tau[2].x = C.C11 * e[2].x + C.C12 * (e[0].x + e[1].x);
+  tau[2].y = C.C11 * e[2].y + C.C12 * (e[0].y + e[1].y);
+#pragma unroll
+  for (int c = 3; c < 6; ++c) tau[c] = make_double2(c44x2 * e[c].x, c44x2 * e[c].y);
+  double2 eps[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) eps[c] = make_double2(0.0, 0.0);
+  const int h = n / 2;
+  const bool nx = kx == h, ny = ky == h, nz = kz == h;
+  const double lx = kx, ly = ky < h ? ky : ky - n, lz = kz < h ? kz : kz - n;
+  if (!(nx || ny || nz)) {
+    acc_eps(lx, ly, lz, C, tau, eps, 1.0);
+  } else {
+    acc_eps(nx ? -h : lx, ny ? -h : ly, nz ? -h : lz, C, tau, eps, 0.5);
+    acc_eps(nx ? h : lx, ny ? h : ly, nz ? h : lz, C, tau, eps, 0.5);
+  }
+  e[0].x = C.C11 * eps[0].x + C.C12 * (eps[1].x + eps[2].x) - tau[0].x;
+  e[0].y = C.C11 * eps[0].y + C.C12 * (eps[1].y + eps[2].y) - tau[0].y;
+  e[1].x = C.C11 * eps[1].x + C.C12 * (eps[0].x + eps[2].x) - tau[1].x;
+  e[1].y = C.C11 * eps[1].y + C.C12 * (eps[0].y + eps[2].y) - tau[1].y;
+  e[2].x = C.C11 * eps[2].x + C.C12 * (eps[0].x + eps[1].x) - tau[2].x;
+  e[2].y = C.C11 * eps[2].y + C.C12 * (eps[0].y + eps[1].y) - tau[2].y;
+#pragma unroll
+  for (int c = 3; c < 6; ++c) e[c] = make_double2(c44x2 * eps[c].x - tau[c].x, c44x2 * eps[c].y - tau[c].y);
+}
+
+// ----------------------------------------------------------------- x forward (R2C)
+
+template <int N, typename S>
+__global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
+    const int64_t* __restrict__ es, typename Cplx<S>::T* __restrict__ spec, int P, const double2* __restrict__ twg) {
+  constexpr int ROWS = x_rows(N);
+  constexpr int NF = 3 * ROWS;  // (xx,yy), (zz,yz), (xz,xy) per row
+  constexpr int T = pick_T(max_nb(N, NF));
+  constexpr int LDN = N + N / 16 + 1;
+  constexpr int NH = N / 2 + 1;
+  __shared__ double2 buf[NF * LDN];
+  __shared__ double2 tw[N];
+  for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  const int bpp = N / ROWS;
+  const int z = blockIdx.x / bpp;
+  const int y0 = (blockIdx.x % bpp) * ROWS;
+  const size_t n3 = (size_t)N * N * N;
+  const size_t cs = (size_t)N * N * P;
+  __syncthreads();
+  auto load0 = [&](int f, int x) -> double2 {
+    const int p = f % 3, y = y0 + f / 3;
+    const size_t o = ((size_t)z * N + y) * N + x;
+    return make_double2((double)es[(2 * p) * n3 + o] * FIX_INV, (double)es[(2 * p + 1) * n3 + o] * FIX_INV);
+  };
+  auto lds = [&](int f, int i) -> double2& { return buf[f * LDN + i + (i >> 4)]; };
+  auto to_lds = [&](int f, int i, double2 v) { lds(f, i) = v; };
+  transform<N, false, Map::Row, NF, T, false, true>(tw, load0, lds, to_lds);
+  __syncthreads();
+  for (int e = threadIdx.x; e < NF * NH; e += T) {
+    const int f = e / NH, k = e % NH;
+    const double2 zk = lds(f, k);
+    const double2 zc = conjd(lds(f, k == 0 ? 0 : N - k));
+    const double2 A = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+    const double2 B = make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x));
+    const int p = f % 3, y = y0 + f / 3;
+    const size_t row = ((size_t)z * N + y) * P + k;
+    st2(&spec[(size_t)(2 * p) * cs + row], A);
+    st2(&spec[(size_t)(2 * p + 1) * cs + row], B);
+  }
+}
+
+// Update variant: the rows of the eigenstrain change dE = E (chi_new - chi_old)
+// are built in LDS from the two footprint lists (new ids = old ids shifted by
+// (sx, sy, sz) voxels when new_ids == nullptr), for rows y in [y_lo, y_lo+y_len),
+// z in [z_lo, z_lo+z_len) (cyclic); other rows are zero and never touched.
+template <int N, typename S>
+__global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_sparse(
+    const int32_t* __restrict__ old_ids, int old_cnt, const int32_t* __restrict__ new_ids, int new_cnt, int sx,
+    int sy, int sz, const double* __restrict__ E, typename Cplx<S>::T* __restrict__ spec, int P, int y_lo,
+    int y_len, int z_lo, const double2* __restrict__ twg) {
+  constexpr int ROWS = x_rows(N);
+  constexpr int NF = 3 * ROWS;
+  constexpr int T = pick_T(max_nb(N, NF));
+  constexpr int LDN = N + N / 16 + 1;
+  constexpr int NH = N / 2 + 1;
+  __shared__ double2 buf[NF * LDN];
+  __shared__ double2 tw[N];
+  for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < NF * LDN; i += T) buf[i] = make_double2(0.0, 0.0);
+  const int rb = (y_len + ROWS - 1) / ROWS;
+  const int zi = blockIdx.x / rb;
+  const int y0i = (blockIdx.x % rb) * ROWS;
+  int z = z_lo + zi;
+  if (z >= N) z -= N;
+  const size_t cs = (size_t)N * N * P;
+  __syncthreads();
+  auto lds = [&](int f, int i) -> double2& { return buf[f * LDN + i + (i >> 4)]; };
+  // scatter +-E of the voxels that fall in this block's rows (one row per y)
+  auto scatter = [&](int id, double sgn) {
+    const int x = id % N, y = (id / N) % N, zz = id / (N * N);
+    if (zz != z) return;
+    int yi = y - y_lo;
+    if (yi < 0) yi += N;
+    yi -= y0i;
+    if (yi < 0 || yi >= ROWS || y0i + yi >= y_len) return;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      double2& slot = lds(3 * yi + p, x);
+      slot.x += sgn * E[2 * p];
+      slot.y += sgn * E[2 * p + 1];
+    }
+  };
+  // Each voxel is owned by one thread per list pass; a voxel can sit in both
+  // lists, so the two passes are separated by a barrier.
+  for (int i = threadIdx.x; i < old_cnt; i += T) scatter(old_ids[i], -1.0);
+  __syncthreads();
+  for (int i = threadIdx.x; i < new_cnt; i += T) {
+    int id;
+    if (new_ids) {
+      id = new_ids[i];
+    } else {
+      const int o = old_ids[i];
+      int x = o % N + sx, y = (o / N) % N + sy, zz = o / (N * N) + sz;
+      x = (x % N + N) % N;
+      y = (y % N + N) % N;
+      zz = (zz % N + N) % N;
+      id = (zz * N + y) * N + x;
+    }
+    scatter(id, 1.0);
+  }
+  __syncthreads();
+  auto load0 = [&](int f, int i) -> double2 { return lds(f, i); };
+  auto to_lds = [&](int f, int i, double2 v) { lds(f, i) = v; };
+  transform<N, false, Map::Row, NF, T, true, true>(tw, load0, lds, to_lds);
+  __syncthreads();
+  for (int e = threadIdx.x; e < NF * NH; e += T) {
+    const int f = e / NH, k = e % NH;
+    const int yi = f / 3, p = f % 3;
+    if (y0i + yi >= y_len) continue;
+    int y = y_lo + y0i + yi;
+    if (y >= N) y -= N;
+    const double2 zk = lds(f, k);
+    const double2 zc = conjd(lds(f, k == 0 ? 0 : N - k));
+    const double2 A = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+    const double2 B = make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x));
+    const size_t row = ((size_t)z * N + y) * P + k;
+    st2(&spec[(size_t)(2 * p) * cs + row], A);
+    st2(&spec[(size_t)(2 * p + 1) * cs + row], B);
+  }
+}
+
+// --------------------------------------------------------------- y / z pencils
+//
+// A tile is W consecutive kx columns of one (component, z) plane (y pass) or one
+// (component, y) row (z pass), transformed along y or z; the kx = n/2 column is
+// tiled separately, W planes (y pass) or rows (z pass) at a time.
+
+template <int N>
+struct PencilTile {
+  static constexpr int W = pencil_W_of(N);
+  static constexpr int KXB = (N / 2 + W - 1) / W;
+  int c, outer, kx0, nouter, z_lo;
+  bool nyq;
+  __device__ PencilTile(int bid, int nouter_, int z_lo_) : nouter(nouter_), z_lo(z_lo_) {
+    const int nreg = 6 * nouter * KXB;
+    nyq = bid >= nreg;
+    if (!nyq) {
+      kx0 = (bid % KXB) * W;
+      const int rest = bid / KXB;
+      outer = rest % nouter;
+      c = rest / nouter;
+    } else {
+      bid -= nreg;
+      const int nb = (nouter + W - 1) / W;
+      outer = (bid % nb) * W;
+      c = bid / nb;
+      kx0 = N / 2;
+    }
+  }
+  // column w -> (outer index, kx); false if outside the tile
+  __device__ __forceinline__ bool col(int w, int& o, int& kx) const {
+    if (!nyq) {
+      kx = kx0 + w;
+      o = outer;
+      return kx < N / 2;
+    }
+    kx = N / 2;
+    o = outer + w;
+    return o < nouter;
+  }
+  // element offset for axis 1 (y pass: transform index i = y) or axis 2 (z pass: i = z)
+  __device__ __forceinline__ size_t off(int axis, int o, int kx, int i, int P) const {
+    if (axis == 1) {
+      int z = z_lo + o;
+      if (z >= N) z -= N;
+      return (((size_t)c * N + z) * N + i) * P + kx;
+    }
+    return (((size_t)c * N + i) * N + o) * P + kx;
+  }
+};
+
+template <int N, typename S, bool INV>
+__global__ __launch_bounds__(pick_T(max_nb(N, pencil_W_of(N)))) void k_pencil(typename Cplx<S>::T* __restrict__ spec,
+                                                                              int P, int axis, Prune pr,
+                                                                              const double2* __restrict__ twg) {
+  constexpr int W = pencil_W_of(N);
+  constexpr int T = pick_T(max_nb(N, W));
+  __shared__ double2 buf[N * W];
+  __shared__ double2 tw[N];
+  for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  const PencilTile<N> tile(blockIdx.x, axis == 1 ? pr.z_len : N, pr.z_lo);
+  __syncthreads();
+  auto load0 = [&](int w, int i) -> double2 {
+    int o, kx;
+    if (!tile.col(w, o, kx)) return make_double2(0.0, 0.0);
+    if (pr.in_len < N) {
+      int d = i - pr.in_lo;
+      if (d < 0) d += N;
+      if (d >= pr.in_len) return make_double2(0.0, 0.0);
+    }
+    return ld2(&spec[tile.off(axis, o, kx, i, P)]);
+  };
+  auto lds = [&](int w, int i) -> double2& { return buf[i * W + w]; };
+  auto store_last = [&](int w, int i, double2 v) {
+    int o, kx;
+    if (tile.col(w, o, kx)) st2(&spec[tile.off(axis, o, kx, i, P)], v);
+  };
+  transform<N, INV, Map::Pencil, W, T>(tw, load0, lds, store_last);
+}
+
+// Pointwise Green step over the half spectrum (one thread per bin).
+template <typename S>
+__global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__ spec, int n, int P, Cubic C) {
+  const int NH = n / 2 + 1;
+  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (size_t)n * n * NH) return;
+  const int kx = (int)(t % NH);
+  const size_t r = t / NH;
+  const int ky = (int)(r % n), kz = (int)(r / n);
+  const size_t cs = (size_t)n * n * P;
+  const size_t o = ((size_t)kz * n + ky) * P + kx;
+  double2 e[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) e[c] = ld2(&spec[c * cs + o]);
+  green_bin(e, kx, ky, kz, n, C);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) st2(&spec[c * cs + o], e[c]);
+}
+
+// --------------------------------------------------------- x inverse (C2R) + stress
+
+template <int N, typename S, bool ACC>
+__global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
+    const typename Cplx<S>::T* __restrict__ spec, double* __restrict__ sig, int P, const double* __restrict__ mean6,
+    const double2* __restrict__ twg) {
+  constexpr int ROWS = x_rows(N);
+  constexpr int NF = 3 * ROWS;
+  constexpr int T = pick_T(max_nb(N, NF));
+  constexpr int LDN = N + N / 16 + 1;
+  __shared__ double2 buf[NF * LDN];
+  __shared__ double2 tw[N];
+  __shared__ double mean_s[6];
+  for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  if (threadIdx.x < 6) mean_s[threadIdx.x] = mean6[threadIdx.x];
+  const int bpp = N / ROWS;
+  const int z = blockIdx.x / bpp;
+  const int y0 = (blockIdx.x % bpp) * ROWS;
+  const size_t n3 = (size_t)N * N * N;
+  const size_t cs = (size_t)N * N * P;
+  const double scale = 1.0 / (double)n3;
+  __syncthreads();
+  auto load0 = [&](int f, int k) -> double2 {
+    const int p = f % 3, y = y0 + f / 3;
+    const size_t row = ((size_t)z * N + y) * P;
+    const typename Cplx<S>::T* a = spec + (size_t)(2 * p) * cs + row;
+    const typename Cplx<S>::T* b = spec + (size_t)(2 * p + 1) * cs + row;
+    double2 A, B;
+    if (k <= N / 2) {
+      A = ld2(a + k);
+      B = ld2(b + k);
+      if (k == 0 || k == N / 2) {
+        A.y = 0.0;
+        B.y = 0.0;
+      }
+    } else {
+      A = conjd(ld2(a + (N - k)));
+      B = conjd(ld2(b + (N - k)));
+    }
+    return make_double2(A.x - B.y, A.y + B.x);
+  };
+  auto lds = [&](int f, int i) -> double2& { return buf[f * LDN + i + (i >> 4)]; };
+  auto store_last = [&](int f, int x, double2 v) {
+    const int p = f % 3, y = y0 + f / 3;
+    const size_t o = ((size_t)z * N + y) * N + x;
+    double* s0 = sig + (size_t)(2 * p) * n3 + o;
+    double* s1 = sig + (size_t)(2 * p + 1) * n3 + o;
+    const double a = v.x * scale + mean_s[2 * p], b = v.y * scale + mean_s[2 * p + 1];
+    if (ACC) {
+      *s0 += a;
+      *s1 += b;
+    } else {
+      *s0 = a;
+      *s1 = b;
+    }
+  };
+  transform<N, true, Map::Row, NF, T>(tw, load0, lds, store_last);
+}
+
+// ------------------------------------------------------------------ launchers
+
+template <int N, typename S>
+hipError_t go_xf(const int64_t* es, void* spec, SpecGeom g, const double2* tw, hipStream_t s) {
+  constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
+  const int grid = N * (N / x_rows(N));
+  hipLaunchKernelGGL((k_x_forward<N, S>), dim3(grid), dim3(T), 0, s, es, (typename Cplx<S>::T*)spec, g.P, tw);
+  return hipGetLastError();
+}
+
+template <int N, typename S>
+hipError_t go_xfs(const int32_t* oi, int oc, const int32_t* ni, int nc, int sx, int sy, int sz, const double* E,
+                  void* spec, SpecGeom g, int ylo, int ylen, int zlo, int zlen, const double2* tw, hipStream_t s) {
+  constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
+  const int grid = zlen * ((ylen + x_rows(N) - 1) / x_rows(N));
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_x_forward_sparse<N, S>), dim3(grid), dim3(T), 0, s, oi, oc, ni, nc, sx, sy, sz, E,
+                     (typename Cplx<S>::T*)spec, g.P, ylo, ylen, zlo, tw);
+  return hipGetLastError();
+}
+
+template <int N, typename S>
+hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, hipStream_t s) {
+  constexpr int W = pencil_W_of(N);
+  constexpr int T = pick_T(max_nb(N, W));
+  const int nouter = axis == 1 ? pr.z_len : N;
+  const int grid = 6 * nouter * PencilTile<N>::KXB + 6 * ((nouter + W - 1) / W);
+  if (inv)
+    hipLaunchKernelGGL((k_pencil<N, S, true>), dim3(grid), dim3(T), 0, s, (typename Cplx<S>::T*)spec, g.P, axis,
+                       pr, tw);
+  else
+    hipLaunchKernelGGL((k_pencil<N, S, false>), dim3(grid), dim3(T), 0, s, (typename Cplx<S>::T*)spec, g.P, axis,
+                       pr, tw);
+  return hipGetLastError();
+}
+
+template <int N, typename S>
+hipError_t go_xi(bool acc, const void* spec, double* sig, SpecGeom g, const double* mean6, const double2* tw,
+                 hipStream_t s) {
+  constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
+  const int grid = N * (N / x_rows(N));
+  using C2 = typename Cplx<S>::T;
+  if (acc)
+    hipLaunchKernelGGL((k_x_inverse<N, S, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, g.P, mean6, tw);
+  else
+    hipLaunchKernelGGL((k_x_inverse<N, S, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, g.P, mean6, tw);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define EC_FOR_SIZES(X) X(8) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(160) X(240) X(256) X(512)
+
+bool fft_supported(int n) {
+  switch (n) {
+#define EC_CASE(NN) case NN:
+    EC_FOR_SIZES(EC_CASE)
+#undef EC_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+int pencil_width(int n, bool) { return n >= 512 ? 8 : 16; }
+
+hipError_t launch_x_forward(bool fp64, const int64_t* es, void* spec, SpecGeom g, const double2* tw, hipStream_t s) {
+  switch (g.n) {
+#define EC_CASE(NN) \
+  case NN:          \
+    return fp64 ? go_xf<NN, double>(es, spec, g, tw, s) : go_xf<NN, float>(es, spec, g, tw, s);
+    EC_FOR_SIZES(EC_CASE)
+#undef EC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, int old_cnt, const int32_t* new_ids,
+                                   int new_cnt, int sx, int sy, int sz, const double* E, void* spec, SpecGeom g,
+                                   int y_lo, int y_len, int z_lo, int z_len, const double2* tw, hipStream_t s) {
+  switch (g.n) {
+#define EC_CASE(NN)                                                                                          \
+  case NN:                                                                                                   \
+    return fp64 ? go_xfs<NN, double>(old_ids, old_cnt, new_ids, new_cnt, sx, sy, sz, E, spec, g, y_lo, y_len, \
+                                     z_lo, z_len, tw, s)                                                      \
+                : go_xfs<NN, float>(old_ids, old_cnt, new_ids, new_cnt, sx, sy, sz, E, spec, g, y_lo, y_len,  \
+                                    z_lo, z_len, tw, s);
+    EC_FOR_SIZES(EC_CASE)
+#undef EC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pencil(bool fp64, bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw,
+                         hipStream_t s) {
+  switch (g.n) {
+#define EC_CASE(NN)                                                   \
+  case NN:                                                            \
+    return fp64 ? go_pencil<NN, double>(inv, axis, spec, g, pr, tw, s) \
+                : go_pencil<NN, float>(inv, axis, spec, g, pr, tw, s);
+    EC_FOR_SIZES(EC_CASE)
+#undef EC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_green(bool fp64, void* spec, SpecGeom g, Cubic C, hipStream_t s) {
+  const size_t bins = (size_t)g.n * g.n * (g.n / 2 + 1);
+  const int grid = (int)((bins + 255) / 256);
+  if (fp64)
+    hipLaunchKernelGGL(k_green<double>, dim3(grid), dim3(256), 0, s, (double2*)spec, g.n, g.P, C);
+  else
+    hipLaunchKernelGGL(k_green<float>, dim3(grid), dim3(256), 0, s, (float2*)spec, g.n, g.P, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, hipStream_t s) {
+  hipError_t e = launch_pencil(fp64, false, 2, spec, g, pr, tw, s);
+  if (e != hipSuccess) return e;
+  e = launch_green(fp64, spec, g, C, s);
+  if (e != hipSuccess) return e;
+  Prune full{0, g.n, 0, g.n};
+  return launch_pencil(fp64, true, 2, spec, g, full, tw, s);
+}
+
+hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
+                            const double2* tw, hipStream_t s) {
+  switch (g.n) {
+#define EC_CASE(NN)                                                          \
+  case NN:                                                                   \
+    return fp64 ? go_xi<NN, double>(accum, spec, sig, g, mean6, tw, s) \
+                : go_xi<NN, float>(accum, spec, sig, g, mean6, tw, s);
+    EC_FOR_SIZES(EC_CASE)
+#undef EC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ec
