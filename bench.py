@@ -1,0 +1,244 @@
+#!/usr/bin/env python
+"""Benchmark: grid solves per second + energies at 256^3 (FP32 vs FP64) on one MI355X.
+
+Workload (config 3): periodic 256^3 cell, 80 nm side, cubic iron-like stiffness
+C11/C12/C44 = 243/145/116 GPa, 2000 synthetic defects (70 % 1/2<111> loops,
+10 % <100> loops, 20 % dilatational spheres; seeded).  One step is the whole
+hot path from the defect list: rasterise, forward FFT, Green operator, inverse
+FFT + stress, per-defect self terms and the compensated energy reduction,
+ending with the energies on the host.  ``value`` is FP32-storage steps/s;
+FP64 steps/s and the per-defect FP32 error against the FP64 path are reported
+beside it.  Inputs are resident on the device when timing starts.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2403_09158_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(family, sha):
+    """HBM bytes per launch of `family` from committed rocprofv3 counter runs,
+    or None if absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except OSError:
+        return None
+    if t.get("source_sha") != sha or family not in t.get("families", {}):
+        return None
+    return t["families"][family]
+
+
+def timed_steps(st, defs, steps, warmup, profile):
+    import torch
+
+    for _ in range(warmup):
+        st.solve(defs)
+        st.energies()
+    torch.cuda.synchronize()
+    st.profile(profile)
+    st.profile_read()  # drop warmup records
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.solve(defs)
+        E = st.energies()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = st.profile_read() if profile else None
+    st.profile(False)
+    return dt, E, prof
+
+
+def cpu_baseline(prob, defs, green_planes=16, self_sample=100):
+    """The FP64 oracle on a bounded sample of the same workload, extrapolated to
+    one full solve + energies: full rasterisation and FFTs, the Green step on
+    `green_planes` of n z-planes (scaled by n/green_planes), the stress, the
+    footprint sums for all defects and the self terms of `self_sample` defects
+    (scaled).  The kernel window G (a per-problem setup, six extra solves) is
+    excluded."""
+    import numpy as np
+
+    from oracle import elastic, energy, raster, solve
+
+    n = prob.n
+    C = elastic.stiffness_of(prob)
+    T = {}
+    t = time.perf_counter()
+    fps, Es = raster.rasterise(prob, defs)
+    es = raster.eigenstrain_field(n, fps, Es)
+    T["raster"] = time.perf_counter() - t
+    t = time.perf_counter()
+    tau = np.einsum("ijkl,kl...->ij...", C, es)
+    th = solve.fft3(tau)
+    del tau
+    T["forward"] = time.perf_counter() - t
+    planes = list(range(0, n, n // green_planes))[:green_planes]
+    t = time.perf_counter()
+    eh = solve.apply_green(C, prob.L, th, es.sum(axis=(-3, -2, -1)), prob.bc, planes=planes)
+    T["green"] = (time.perf_counter() - t) * n / len(planes)
+    del th
+    t = time.perf_counter()
+    eps = solve.fft3(eh, inverse=True).real
+    del eh
+    sig = np.einsum("ijkl,kl...->ij...", C, eps - es)
+    T["inverse_stress"] = time.perf_counter() - t
+    del eps
+    t = time.perf_counter()
+    sf = sig.reshape(3, 3, -1)
+    S = [sf[:, :, ids].sum(axis=-1) for ids in fps]
+    T["footprint_sums"] = time.perf_counter() - t
+    # self terms need G; time them on a small synthetic window (values irrelevant)
+    D = energy.window_halfwidth(fps, n)
+    G = np.zeros((3, 3, 3, 3, 2 * D + 1, 2 * D + 1, 2 * D + 1))
+    idx = np.linspace(0, len(fps) - 1, self_sample).astype(int)
+    h3c = prob.h**3 * elastic.GPA_NM3_EV
+    t = time.perf_counter()
+    for i in idx:
+        energy.self_term(fps[i], Es[i], G, D, n, h3c)
+    T["self_terms"] = (time.perf_counter() - t) * len(fps) / len(idx)
+    del sig, S
+    total = sum(T.values())
+    return {
+        "value": 1.0 / total,
+        "unit": "solves/s",
+        "cores": int(os.environ.get("ORACLE_FFT_WORKERS", "0")) or (os.cpu_count() or 1),
+        "kind": "oracle",
+        "sample": (
+            f"config-3 workload at 256^3: full rasterisation, FFTs and footprint sums; Green step on "
+            f"{len(planes)}/{n} z-planes and self terms of {len(idx)}/{len(fps)} defects, scaled; "
+            f"G-window setup excluded; per-stage s: " + ", ".join(f"{k}={v:.2f}" for k, v in T.items())
+        ),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(
+            json.dumps({"error": "this solver runs on one GPU per process; multi-GPU runs are not supported"}),
+            flush=True,
+        )
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2403_09158_amd import ec, inputs
+
+    torch.cuda.set_device(0)
+    prob32, defs = inputs.config3(prec=1)
+    prob64 = prob32.with_(prec=0)
+    ctx = ec.Context(0)
+
+    st64 = ec.State(ctx, prob64)
+    k64 = args.fp64_steps if args.fp64_steps is not None else max(1, args.steps // 2)
+    dt64, E64, prof64 = timed_steps(st64, defs, k64, max(1, args.warmup), profile=False)
+    st64.close()
+
+    st = ec.State(ctx, prob32)
+    dt, E32, prof = timed_steps(st, defs, args.steps, args.warmup, profile=not args.no_profile)
+    sps = args.steps / dt
+
+    err = np.abs(E32 - E64)
+    tol = np.maximum(1e-4 * np.abs(E64), 1e-5)
+    precision = {
+        "fp32_vs_fp64_max_abs_eV": float(err.max()),
+        "fp32_vs_fp64_p50_abs_eV": float(np.median(err)),
+        "fp32_vs_fp64_p99_abs_eV": float(np.quantile(err, 0.99)),
+        "fp32_pass_fraction": float(np.mean(err <= tol)),
+        "fp32_max_err_over_tol": float(np.max(err / tol)),
+    }
+    golden = os.path.join(ROOT, "tests", "golden", "oracle_config3.npz")
+    if os.path.exists(golden):
+        g = np.load(golden)
+        precision["fp64_vs_oracle_max_rel"] = float(np.max(np.abs(E64 - g["E"])) / np.max(np.abs(g["E"])))
+        e32 = np.abs(E32 - g["E"])
+        precision["fp32_vs_oracle_pass_fraction"] = float(np.mean(e32 <= np.maximum(1e-4 * np.abs(g["E"]), 1e-5)))
+
+    roofline = None
+    if prof:
+        n = prob32.n
+        fam = max((k for k in prof if k not in ("raster", "self_term", "energy_reduce", "other")), key=lambda k: prof[k]["ms"])
+        p = prof[fam]
+        avg_ms = p["ms"] / max(p["launches"], 1)
+        achieved = p["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+        sha = kernel_source_sha()
+        roofline = {
+            "bound": "hbm",
+            "kernel": fam,
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(fam, sha),
+            "avg_launch_ms": round(avg_ms, 5),
+            "bytes_per_launch": p["bytes_per_launch"],
+            "source_sha": sha,
+            "per_family": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / max(v["launches"], 1), 5),
+                                "GBps": round(v["bytes_per_launch"] / max(v["ms"] / max(v["launches"], 1), 1e-9) / 1e6, 1)}
+                           for k, v in prof.items() if v["launches"]},
+            # solve-level fraction against the minimal fused schedule: 240 n^3 bytes at FP32 storage
+            "solve_frac_240N": round(240.0 * n**3 / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
+        }
+
+    line = {
+        "metric": "grid-solves/sec + energies at 256^3 (FP32 vs FP64), served p50/p99 latency",
+        "value": round(sps, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-storage/f64-arith",
+        "data": "synthetic",
+        "config": {
+            "workload": "config3: 256^3 periodic cell, 80 nm, cubic C 243/145/116 GPa, 2000 defects "
+            "(70% 1/2<111> loops, 10% <100> loops, 20% dilatational spheres)",
+            "n": prob32.n,
+            "ndef": int(len(defs)),
+            "parallelism": "single GPU",
+        },
+        "fp64": {"value": round(k64 / dt64, 3), "unit": "solves/s", "ms_per_step": round(1e3 * dt64 / k64, 4)},
+        "precision": precision,
+        "roofline": roofline,
+    }
+    st.close()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob64, defs)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

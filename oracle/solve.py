@@ -42,14 +42,15 @@ def fft3(f, inverse=False, workers=None):
     return scipy.fft.fftn(f, axes=(-3, -2, -1), workers=w)
 
 
-def apply_green(C, L, tau_hat, eps_star_dc, bc=0):
-    """eps_hat from tau_hat on the full complex spectrum, plane by plane in z."""
+def apply_green(C, L, tau_hat, eps_star_dc, bc=0, planes=None):
+    """eps_hat from tau_hat on the full complex spectrum, plane by plane in z
+    (``planes``: optional subset of z planes to evaluate, for timing samples)."""
     n = tau_hat.shape[-1]
     lab = centred_labels(n)
     two_pi_L = 2.0 * np.pi / L
     ky, kx = np.meshgrid(lab, lab, indexing="ij")
     eps_hat = np.empty_like(tau_hat)
-    for iz in range(n):
+    for iz in range(n) if planes is None else planes:
         kz = lab[iz]
         xi = two_pi_L * np.stack([kx, ky, np.full_like(kx, kz)], axis=-1).astype(np.float64)
         zero = (kx == 0) & (ky == 0) & (kz == 0)

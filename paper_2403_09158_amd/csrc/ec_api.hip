@@ -117,6 +117,13 @@ struct ec_state {
   size_t gcls_bytes = 0;
   int gcls_D = -1, gcls_ncls = -1;
   const WinCache* win = nullptr;
+  // self-term work list
+  SelfWork* work = nullptr;
+  size_t work_cap = 0;
+  double* partial = nullptr;
+  size_t partial_cap = 0;
+  int32_t* wbeg = nullptr;
+  size_t wbeg_cap = 0;
   // update scratch
   int32_t* upd_ids = nullptr;
   int64_t upd_cap = 0;
@@ -561,11 +568,45 @@ ec_status compute_self_terms(ec_state* st, hipStream_t s) {
     st->gcls_D = D;
     st->gcls_ncls = ncls;
   }
-  const DefBuf& b = st->db[st->cur];
+  // Split every defect's pair triangle (q >= p) into work items of about
+  // TARGET pairs; rows p in [0, m), row p holds m - p pairs.
+  constexpr double TARGET = 32768.0;
+  std::vector<SelfWork> work;
+  std::vector<int32_t> wbeg(st->ndef + 1);
   double pairs = 0;
-  for (int i = 0; i < st->ndef; ++i) pairs += (double)st->hcnt[i] * st->hcnt[i];
+  for (int i = 0; i < st->ndef; ++i) {
+    wbeg[i] = (int32_t)work.size();
+    const double m = st->hcnt[i];
+    const double tot = m * (m + 1) / 2;
+    pairs += tot;
+    const int k = std::max(1, (int)std::ceil(tot / TARGET));
+    int p0 = 0;
+    for (int j = 1; j <= k; ++j) {
+      int p1;
+      if (j == k) {
+        p1 = (int)m;
+      } else {
+        // smallest p with p m - p (p - 1)/2 >= j tot / k
+        const double T = j * tot / k, a = m + 0.5;
+        p1 = (int)std::ceil(a - std::sqrt(std::max(0.0, a * a - 2.0 * T)));
+        p1 = std::min(std::max(p1, p0), (int)m);
+      }
+      if (p1 > p0 || (j == k && work.size() == (size_t)wbeg[i])) work.push_back({i, p0, p1, 0});
+      p0 = p1;
+    }
+  }
+  wbeg[st->ndef] = (int32_t)work.size();
+  const int nwork = (int)work.size();
+  if ((r = st_grow(st, &st->work, &st->work_cap, std::max(nwork, 1))) != EC_OK) return r;
+  if ((r = st_grow(st, &st->partial, &st->partial_cap, std::max(nwork, 1))) != EC_OK) return r;
+  if ((r = st_grow(st, &st->wbeg, &st->wbeg_cap, wbeg.size())) != EC_OK) return r;
+  if (nwork > 0) HIPCHK(hipMemcpyAsync(st->work, work.data(), nwork * sizeof(SelfWork), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(st->wbeg, wbeg.data(), wbeg.size() * 4, hipMemcpyHostToDevice, s));
+  const DefBuf& b = st->db[st->cur];
   LAUNCH(st, s, PF_SELF, pairs * 8.0,
-         launch_self_terms(b.tab, st->ndef, b.off, b.cnt, b.ids, st->n, w->K, st->gcls, D, st->h3c, st->B, s));
+         launch_self_terms(b.tab, b.off, b.cnt, b.ids, st->n, w->K, st->gcls, D, st->work, nwork, st->partial,
+                           st->wbeg, st->ndef, st->h3c, st->B, s));
+  HIPCHK(hipStreamSynchronize(s));  // work list staging is pageable
   st->B_valid = true;
   return EC_OK;
 }
@@ -805,6 +846,9 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->S6, st->pd_cap * 48);
   ledger_free(c, st->gcls, st->gcls_bytes);
   ledger_free(c, st->upd_ids, st->upd_cap * 4);
+  ledger_free(c, st->work, st->work_cap * sizeof(SelfWork));
+  ledger_free(c, st->partial, st->partial_cap * 8);
+  ledger_free(c, st->wbeg, st->wbeg_cap * 4);
   for (auto& r : st->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);

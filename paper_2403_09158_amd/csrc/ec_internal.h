@@ -43,18 +43,21 @@ struct DevDefect {
 };
 
 // Voxel-centre membership, exact integer arithmetic (loops: half-open slab
-// along the lattice normal m, closed disk; spheres: closed ball).
+// along the lattice normal m, closed disk; spheres: closed ball).  d is the
+// minimum-image offset of the voxel centre from the defect centre, q units.
 __host__ __device__ inline bool member(const DevDefect& d, int n, int x, int y, int z) {
-  const int64_t Lq = (int64_t)QSUB * n, half = Lq / 2;
+  const int32_t Lq = QSUB * n, half = Lq / 2;
   const int v[3] = {x, y, z};
-  int64_t dd[3];
+  int32_t dd[3];
   for (int k = 0; k < 3; ++k) {
-    int64_t t = (int64_t)QSUB * v[k] + QSUB / 2 - d.cq[k] + half + Lq;
-    dd[k] = t % Lq - half;
+    int32_t t = QSUB * v[k] + QSUB / 2 - d.cq[k];  // in (-Lq, Lq)
+    t += (t < -half) ? Lq : 0;
+    t -= (t >= half) ? Lq : 0;
+    dd[k] = t;
   }
-  const int64_t d2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+  const int64_t d2 = (int64_t)dd[0] * dd[0] + (int64_t)dd[1] * dd[1] + (int64_t)dd[2] * dd[2];
   if (d.kind == 1) return d2 <= d.R2q;
-  const int64_t t = d.m[0] * dd[0] + d.m[1] * dd[1] + d.m[2] * dd[2];
+  const int64_t t = (int64_t)d.m[0] * dd[0] + (int64_t)d.m[1] * dd[1] + (int64_t)d.m[2] * dd[2];
   const int64_t lim = (int64_t)d.eq * d.eq * d.mm;
   const bool slab = (t >= 0) ? (4 * t * t < lim) : (4 * t * t <= lim);
   return slab && ((int64_t)d.mm * d2 - t * t <= (int64_t)d.mm * d.R2q);
@@ -144,9 +147,14 @@ hipError_t launch_reduce(const DevDefect* d, int ndef, const int64_t* offsets, c
                          double* E, hipStream_t s);
 hipError_t launch_window_crop(const double* sig, int n, int D, int b, double* K, hipStream_t s);
 hipError_t launch_class_windows(const double* K, int D, const double* dirs, int ncls, double* g, hipStream_t s);
-hipError_t launch_self_terms(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
-                             const int32_t* ids, int n, const double* K, const double* gcls, int D, double h3c,
-                             double* B, hipStream_t s);
+// Self-term work item: rows [p0, p1) of defect `def`'s pair triangle.
+struct SelfWork {
+  int32_t def, p0, p1, pad;
+};
+hipError_t launch_self_terms(const DevDefect* d, const int64_t* offsets, const int32_t* counts, const int32_t* ids,
+                             int n, const double* K, const double* gcls, int D, const SelfWork* work, int nwork,
+                             double* partial, const int32_t* work_begin, int ndef, double h3c, double* B,
+                             hipStream_t s);
 hipError_t launch_sig_to_out(const double* sig, const int64_t* es, int64_t n3, Cubic C, int which, bool fp32,
                              void* out, hipStream_t s);
 

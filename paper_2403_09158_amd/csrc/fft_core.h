@@ -226,7 +226,7 @@ __device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& st
       const int k = j % NS;
       if (NS > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw_at<INV>(tw, (k * r * (N / (NS * R))) % N));
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw_at<INV>(tw, k * r * (N / (NS * R))));
       }
       Dft<R, INV>::run(v[q]);
       const int base = (j / NS) * NS * R + k;
@@ -237,17 +237,17 @@ __device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& st
 }
 
 // Full transform: first stage LOAD0 -> LDS (or -> STORE_LAST for one stage),
-// middle stages in place on LDS, last stage LDS -> STORE_LAST.  `lds(f, i)`
-// returns a reference to element i of transform f in LDS.  LAST_LDS: the last
-// stage's store writes LDS too (then it must not overwrite unread operands),
-// and LOAD0_LDS: the first stage reads LDS in place.
+// middle stages in place on LDS, last stage LDS -> STORE_LAST.  LDS is reached
+// through `lds_ld(f, i)` / `lds_st(f, i, v)` (element i of transform f), so the
+// staging precision is the caller's choice.  LAST_LDS: the last stage's store
+// writes LDS too (operands are then all read before the barrier), LOAD0_LDS:
+// the first stage reads LDS in place.
 template <int N, bool INV, Map M, int NFFT, int T, bool LOAD0_LDS = false, bool LAST_LDS = false, class Load0,
-          class Lds, class StoreLast>
-__device__ __forceinline__ void transform(const double2* tw, Load0&& load0, Lds&& lds, StoreLast&& store_last) {
+          class LdsLd, class LdsSt, class StoreLast>
+__device__ __forceinline__ void transform(const double2* tw, Load0&& load0, LdsLd&& from_lds, LdsSt&& to_lds,
+                                          StoreLast&& store_last) {
   constexpr Plan2 P = plan_of(N);
   static_assert(P.nstage >= 1, "unsupported FFT length");
-  auto to_lds = [&](int f, int i, double2 x) { lds(f, i) = x; };
-  auto from_lds = [&](int f, int i) { return lds(f, i); };
   if constexpr (P.nstage == 1) {
     stage<N, P.r[0], 1, INV, M, NFFT, T>(tw, load0, store_last, LOAD0_LDS && LAST_LDS);
   } else if constexpr (P.nstage == 2) {

@@ -103,66 +103,86 @@ __global__ void k_class_windows(const double* __restrict__ K, int64_t W3, const 
 constexpr int ST = 256;
 constexpr int SMAX = 8192;  // footprint voxels staged in LDS
 
+__device__ __forceinline__ int32_t pack_xyz(int id, int n) {
+  return (id % n) | (((id / n) % n) << 10) | ((id / (n * n)) << 20);
+}
+
+// One work item = rows [p0, p1) of a defect's pair triangle q >= p.  Each
+// wavefront takes one row p and its lanes walk q = p + lane, p + lane + 64, ...:
+// consecutive footprint voxels are x-neighbours, so the lanes read nearly
+// consecutive window entries.  Off-diagonal pairs count twice (G(r) = G(-r)).
 __global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs, const int64_t* __restrict__ off,
                                              const int32_t* __restrict__ cnt, const int32_t* __restrict__ ids, int n,
                                              const double* __restrict__ K, const double* __restrict__ gcls, int D,
-                                             double h3c, double* __restrict__ B) {
-  const int i = blockIdx.x;
+                                             const SelfWork* __restrict__ work, double* __restrict__ partial) {
+  const SelfWork wk = work[blockIdx.x];
+  const int i = wk.def;
   const int m = cnt[i];
   const int64_t o = off[i];
-  const DevDefect d = defs[i];
+  const int cls = defs[i].cls;
   __shared__ int32_t pk[SMAX];
+  __shared__ double wsum[ST / 64];
   const bool staged = m <= SMAX;
   if (staged)
-    for (int k = threadIdx.x; k < m; k += ST) {
-      const int id = ids[o + k];
-      pk[k] = (id % n) | (((id / n) % n) << 10) | ((id / (n * n)) << 20);
-    }
+    for (int k = threadIdx.x; k < m; k += ST) pk[k] = pack_xyz(ids[o + k], n);
   __syncthreads();
-  auto coord = [&](int k) -> int32_t {
-    if (staged) return pk[k];
-    const int id = ids[o + k];
-    return (id % n) | (((id / n) % n) << 10) | ((id / (n * n)) << 20);
-  };
+  auto coord = [&](int k) -> int32_t { return staged ? pk[k] : pack_xyz(ids[o + k], n); };
   const int W = 2 * D + 1;
-  const int64_t W3 = (int64_t)W * W * W;
   const int h = n / 2;
-  const double* g = d.cls >= 0 ? gcls + (int64_t)d.cls * W3 : nullptr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto widx = [&](int32_t P, int32_t Q) -> int {
+    int rx = (P & 1023) - (Q & 1023), ry = ((P >> 10) & 1023) - ((Q >> 10) & 1023), rz = (P >> 20) - (Q >> 20);
+    rx += rx < -h ? n : (rx >= h ? -n : 0);
+    ry += ry < -h ? n : (ry >= h ? -n : 0);
+    rz += rz < -h ? n : (rz >= h ? -n : 0);
+    return ((rz + D) * W + (ry + D)) * W + (rx + D);
+  };
   double acc = 0.0;
-  for (int p = threadIdx.x; p < m; p += ST) {
-    const int32_t P = coord(p);
-    const int px = P & 1023, py = (P >> 10) & 1023, pz = P >> 20;
-    double rowsum = 0.0;
-    for (int q = 0; q < m; ++q) {
-      const int32_t Q = coord(q);
-      int rx = px - (Q & 1023), ry = py - ((Q >> 10) & 1023), rz = pz - (Q >> 20);
-      rx += rx < -h ? n : (rx >= h ? -n : 0);
-      ry += ry < -h ? n : (ry >= h ? -n : 0);
-      rz += rz < -h ? n : (rz >= h ? -n : 0);
-      const int64_t idx = ((int64_t)(rz + D) * W + (ry + D)) * W + (rx + D);
-      if (g) {
-        rowsum += g[idx];
-      } else {
-        const double* k = K + idx * KWIN;
-        double s = 0.0;
-        for (int a = 0; a < 6; ++a) {
-          s += d.E[a] * d.E[a] * k[tri(a, a)];
-          for (int b = a + 1; b < 6; ++b) s += 2.0 * d.E[a] * d.E[b] * k[tri(a, b)];
-        }
-        rowsum += s;
+  if (cls >= 0) {
+    const double* g = gcls + (size_t)cls * W * W * W;
+    for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
+      const int32_t P = coord(p);
+      for (int q = p + lane; q < m; q += 64) {
+        const double v = g[widx(P, coord(q))];
+        acc += (q == p) ? v : 2.0 * v;
       }
     }
-    acc += rowsum;
+  } else {
+    double E[6];
+    for (int a = 0; a < 6; ++a) E[a] = defs[i].E[a];
+    for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
+      const int32_t P = coord(p);
+      for (int q = p + lane; q < m; q += 64) {
+        const double* k = K + (size_t)widx(P, coord(q)) * KWIN;
+        double v = 0.0;
+        for (int a = 0; a < 6; ++a) {
+          v += E[a] * E[a] * k[tri(a, a)];
+          for (int b = a + 1; b < 6; ++b) v += 2.0 * E[a] * E[b] * k[tri(a, b)];
+        }
+        acc += (q == p) ? v : 2.0 * v;
+      }
+    }
   }
-  __shared__ double red[ST];
-  red[threadIdx.x] = acc;
+  for (int s = 32; s > 0; s >>= 1) acc += __shfl_down(acc, s);
+  if (lane == 0) wsum[wave] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0, c = 0.0;
-    for (int t = 0; t < ST; ++t) neumaier(s, c, red[t]);
-    const double scale = g ? d.s * d.s : 1.0;
-    B[i] = -h3c * scale * (s + c);
+    double t = 0.0;
+    for (int w = 0; w < ST / 64; ++w) t += wsum[w];
+    partial[blockIdx.x] = t;
   }
+}
+
+// B_i = -h^3 c s_i^2 sum(partials) (class windows hold the unit direction) or
+// -h^3 c sum(partials) (full-tensor path); partials added in a fixed order.
+__global__ void k_self_finish(const int32_t* __restrict__ wbeg, const double* __restrict__ partial,
+                              const DevDefect* __restrict__ defs, int ndef, double h3c, double* __restrict__ B) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndef) return;
+  double s = 0.0, c = 0.0;
+  for (int w = wbeg[i]; w < wbeg[i + 1]; ++w) neumaier(s, c, partial[w]);
+  const double scale = defs[i].cls >= 0 ? defs[i].s * defs[i].s : 1.0;
+  B[i] = -h3c * scale * (s + c);
 }
 
 // Dense outputs: which 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic compliance).
@@ -216,11 +236,15 @@ hipError_t launch_class_windows(const double* K, int D, const double* dirs, int 
   return hipGetLastError();
 }
 
-hipError_t launch_self_terms(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
-                             const int32_t* ids, int n, const double* K, const double* gcls, int D, double h3c,
-                             double* B, hipStream_t s) {
+hipError_t launch_self_terms(const DevDefect* d, const int64_t* offsets, const int32_t* counts, const int32_t* ids,
+                             int n, const double* K, const double* gcls, int D, const SelfWork* work, int nwork,
+                             double* partial, const int32_t* work_begin, int ndef, double h3c, double* B,
+                             hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_self, dim3(ndef), dim3(ST), 0, s, d, offsets, counts, ids, n, K, gcls, D, h3c, B);
+  hipLaunchKernelGGL(k_self, dim3(nwork), dim3(ST), 0, s, d, offsets, counts, ids, n, K, gcls, D, work, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_self_finish, dim3((ndef + 255) / 256), dim3(256), 0, s, work_begin, partial, d, ndef, h3c, B);
   return hipGetLastError();
 }
 

@@ -150,8 +150,9 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
     return make_double2((double)es[(2 * p) * n3 + o] * FIX_INV, (double)es[(2 * p + 1) * n3 + o] * FIX_INV);
   };
   auto lds = [&](int f, int i) -> double2& { return buf[f * LDN + i + (i >> 4)]; };
+  auto from_lds = [&](int f, int i) { return lds(f, i); };
   auto to_lds = [&](int f, int i, double2 v) { lds(f, i) = v; };
-  transform<N, false, Map::Row, NF, T, false, true>(tw, load0, lds, to_lds);
+  transform<N, false, Map::Row, NF, T, false, true>(tw, load0, from_lds, to_lds, to_lds);
   __syncthreads();
   for (int e = threadIdx.x; e < NF * NH; e += T) {
     const int f = e / NH, k = e % NH;
@@ -226,9 +227,9 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
     scatter(id, 1.0);
   }
   __syncthreads();
-  auto load0 = [&](int f, int i) -> double2 { return lds(f, i); };
+  auto from_lds = [&](int f, int i) { return lds(f, i); };
   auto to_lds = [&](int f, int i, double2 v) { lds(f, i) = v; };
-  transform<N, false, Map::Row, NF, T, true, true>(tw, load0, lds, to_lds);
+  transform<N, false, Map::Row, NF, T, true, true>(tw, from_lds, from_lds, to_lds, to_lds);
   __syncthreads();
   for (int e = threadIdx.x; e < NF * NH; e += T) {
     const int f = e / NH, k = e % NH;
@@ -252,9 +253,8 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
 // (component, y) row (z pass), transformed along y or z; the kx = n/2 column is
 // tiled separately, W planes (y pass) or rows (z pass) at a time.
 
-template <int N>
+template <int N, int W>
 struct PencilTile {
-  static constexpr int W = pencil_W_of(N);
   static constexpr int KXB = (N / 2 + W - 1) / W;
   int c, outer, kx0, nouter, z_lo;
   bool nyq;
@@ -296,33 +296,42 @@ struct PencilTile {
   }
 };
 
-template <int N, typename S, bool INV>
-__global__ __launch_bounds__(pick_T(max_nb(N, pencil_W_of(N)))) void k_pencil(typename Cplx<S>::T* __restrict__ spec,
-                                                                              int P, int axis, Prune pr,
-                                                                              const double2* __restrict__ twg) {
-  constexpr int W = pencil_W_of(N);
-  constexpr int T = pick_T(max_nb(N, W));
-  __shared__ double2 buf[N * W];
+// W columns per tile, LT = LDS staging type (double2, or float2 for FP32 storage),
+// TMAX = largest workgroup, PRUNE = input confined to a cyclic range (updates).
+constexpr int pick_T2(int nb, int tmax) { return nb >= tmax ? tmax : ((nb + 63) / 64) * 64; }
+
+template <int N, typename S, bool INV, int W, typename LT, int TMAX, bool PRUNE>
+__global__ __launch_bounds__(pick_T2(max_nb(N, W), TMAX)) void k_pencil(typename Cplx<S>::T* __restrict__ spec, int P,
+                                                                      int axis, Prune pr,
+                                                                      const double2* __restrict__ twg) {
+  constexpr int T = pick_T2(max_nb(N, W), TMAX);
+  static_assert(T % W == 0, "a thread must keep its column across butterflies");
+  __shared__ LT buf[N * W];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
-  const PencilTile<N> tile(blockIdx.x, axis == 1 ? pr.z_len : N, pr.z_lo);
+  const PencilTile<N, W> tile(blockIdx.x, axis == 1 ? pr.z_len : N, pr.z_lo);
+  // every butterfly of this thread sits in column w = threadIdx.x % W
+  int o, kx;
+  const bool valid = tile.col(threadIdx.x % W, o, kx);
+  using C2 = typename Cplx<S>::T;
+  C2* const colp = spec + (valid ? tile.off(axis, o, kx, 0, P) : 0);
+  const int si = axis == 1 ? P : N * P;  // element stride along the transform axis
   __syncthreads();
-  auto load0 = [&](int w, int i) -> double2 {
-    int o, kx;
-    if (!tile.col(w, o, kx)) return make_double2(0.0, 0.0);
-    if (pr.in_len < N) {
+  auto load0 = [&](int, int i) -> double2 {
+    if (!valid) return make_double2(0.0, 0.0);
+    if (PRUNE) {
       int d = i - pr.in_lo;
       if (d < 0) d += N;
       if (d >= pr.in_len) return make_double2(0.0, 0.0);
     }
-    return ld2(&spec[tile.off(axis, o, kx, i, P)]);
+    return ld2(colp + i * si);
   };
-  auto lds = [&](int w, int i) -> double2& { return buf[i * W + w]; };
-  auto store_last = [&](int w, int i, double2 v) {
-    int o, kx;
-    if (tile.col(w, o, kx)) st2(&spec[tile.off(axis, o, kx, i, P)], v);
+  auto from_lds = [&](int w, int i) { return ld2(&buf[i * W + w]); };
+  auto to_lds = [&](int w, int i, double2 v) { st2(&buf[i * W + w], v); };
+  auto store_last = [&](int, int i, double2 v) {
+    if (valid) st2(colp + i * si, v);
   };
-  transform<N, INV, Map::Pencil, W, T>(tw, load0, lds, store_last);
+  transform<N, INV, Map::Pencil, W, T>(tw, load0, from_lds, to_lds, store_last);
 }
 
 // Pointwise Green step over the half spectrum (one thread per bin).
@@ -385,7 +394,8 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
     }
     return make_double2(A.x - B.y, A.y + B.x);
   };
-  auto lds = [&](int f, int i) -> double2& { return buf[f * LDN + i + (i >> 4)]; };
+  auto from_lds = [&](int f, int i) { return buf[f * LDN + i + (i >> 4)]; };
+  auto to_lds = [&](int f, int i, double2 v) { buf[f * LDN + i + (i >> 4)] = v; };
   auto store_last = [&](int f, int x, double2 v) {
     const int p = f % 3, y = y0 + f / 3;
     const size_t o = ((size_t)z * N + y) * N + x;
@@ -400,7 +410,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
       *s1 = b;
     }
   };
-  transform<N, true, Map::Row, NF, T>(tw, load0, lds, store_last);
+  transform<N, true, Map::Row, NF, T>(tw, load0, from_lds, to_lds, store_last);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -424,19 +434,34 @@ hipError_t go_xfs(const int32_t* oi, int oc, const int32_t* ni, int nc, int sx, 
   return hipGetLastError();
 }
 
-template <int N, typename S>
-hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, hipStream_t s) {
-  constexpr int W = pencil_W_of(N);
-  constexpr int T = pick_T(max_nb(N, W));
+template <int N, typename S, int W, typename LT, int TMAX>
+hipError_t go_pencil_v(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, hipStream_t s) {
+  constexpr int T = pick_T2(max_nb(N, W), TMAX);
   const int nouter = axis == 1 ? pr.z_len : N;
-  const int grid = 6 * nouter * PencilTile<N>::KXB + 6 * ((nouter + W - 1) / W);
-  if (inv)
-    hipLaunchKernelGGL((k_pencil<N, S, true>), dim3(grid), dim3(T), 0, s, (typename Cplx<S>::T*)spec, g.P, axis,
+  const int grid = 6 * nouter * PencilTile<N, W>::KXB + 6 * ((nouter + W - 1) / W);
+  using C2 = typename Cplx<S>::T;
+  const bool prune = pr.in_len < N;
+  if (inv && !prune)
+    hipLaunchKernelGGL((k_pencil<N, S, true, W, LT, TMAX, false>), dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis,
+                       pr, tw);
+  else if (inv)
+    hipLaunchKernelGGL((k_pencil<N, S, true, W, LT, TMAX, true>), dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis,
+                       pr, tw);
+  else if (!prune)
+    hipLaunchKernelGGL((k_pencil<N, S, false, W, LT, TMAX, false>), dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis,
                        pr, tw);
   else
-    hipLaunchKernelGGL((k_pencil<N, S, false>), dim3(grid), dim3(T), 0, s, (typename Cplx<S>::T*)spec, g.P, axis,
+    hipLaunchKernelGGL((k_pencil<N, S, false, W, LT, TMAX, true>), dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis,
                        pr, tw);
   return hipGetLastError();
+}
+
+// FP32 storage stages the inter-stage exchange in FP32 too (half the LDS, twice
+// the resident workgroups); FP64 storage keeps FP64 staging.
+template <int N, typename S>
+hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, hipStream_t s) {
+  using LT = typename Cplx<S>::T;
+  return go_pencil_v<N, S, pencil_W_of(N), LT, 256>(inv, axis, spec, g, pr, tw, s);
 }
 
 template <int N, typename S>

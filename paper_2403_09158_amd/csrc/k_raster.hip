@@ -15,12 +15,12 @@ namespace {
 
 constexpr int RT = 256;  // threads per rasteriser workgroup
 
-__device__ __forceinline__ void box_cell(const DevDefect& d, int n, long e, int& x, int& y, int& z) {
-  const long wxy = (long)d.w[0] * d.w[1];
-  const int iz = (int)(e / wxy);
-  const long r = e - (long)iz * wxy;
-  const int iy = (int)(r / d.w[0]);
-  const int ix = (int)(r - (long)iy * d.w[0]);
+__device__ __forceinline__ void box_cell(const DevDefect& d, int n, int e, int& x, int& y, int& z) {
+  const int wxy = d.w[0] * d.w[1];
+  const int iz = e / wxy;
+  const int r = e - iz * wxy;
+  const int iy = r / d.w[0];
+  const int ix = r - iy * d.w[0];
   x = box_axis(d.lo[0], d.w[0], n, ix);
   y = box_axis(d.lo[1], d.w[1], n, iy);
   z = box_axis(d.lo[2], d.w[2], n, iz);
@@ -29,9 +29,9 @@ __device__ __forceinline__ void box_cell(const DevDefect& d, int n, long e, int&
 __global__ __launch_bounds__(RT) void k_raster_count(const DevDefect* __restrict__ defs, int n,
                                                      int32_t* __restrict__ counts) {
   const DevDefect d = defs[blockIdx.x];
-  const long total = (long)d.w[0] * d.w[1] * d.w[2];
+  const int total = d.w[0] * d.w[1] * d.w[2];
   int c = 0;
-  for (long e = threadIdx.x; e < total; e += RT) {
+  for (int e = threadIdx.x; e < total; e += RT) {
     int x, y, z;
     box_cell(d, n, e, x, y, z);
     c += member(d, n, x, y, z) ? 1 : 0;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(RT) void k_raster_fill(const DevDefect* __restrict_
                                                     const int64_t* __restrict__ offsets, int32_t* __restrict__ ids,
                                                     int64_t* __restrict__ es) {
   const DevDefect d = defs[blockIdx.x];
-  const long total = (long)d.w[0] * d.w[1] * d.w[2];
+  const int total = d.w[0] * d.w[1] * d.w[2];
   const int64_t base0 = offsets[blockIdx.x];
   const size_t n3 = (size_t)n * n * n;
   __shared__ int wsum[RT / 64];
@@ -86,8 +86,8 @@ __global__ __launch_bounds__(RT) void k_raster_fill(const DevDefect* __restrict_
   if (threadIdx.x == 0) base_s = base0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
-  for (long r0 = 0; r0 < total; r0 += RT) {
-    const long e = r0 + threadIdx.x;
+  for (int r0 = 0; r0 < total; r0 += RT) {
+    const int e = r0 + threadIdx.x;
     int x = 0, y = 0, z = 0;
     bool in = false;
     if (e < total) {
@@ -169,30 +169,47 @@ __global__ __launch_bounds__(RT) void k_translate_ids(int32_t* __restrict__ ids,
 }
 
 // Additive constant of the stress for the xi = 0 condition.  Mean strain zero:
-// sigma gets -C:<eps*>, <eps*> = (1/n^3) sum_i |Omega_i| E_i (compensated FP64).
-// Mean stress zero: nothing to add.
-__global__ void k_mean_stress(const DevDefect* __restrict__ defs, const int32_t* __restrict__ counts, int ndef,
-                              double inv_n3, Cubic C, int bc, double* __restrict__ add6) {
+// sigma gets -C:<eps*>, <eps*> = (1/n^3) sum_i |Omega_i| E_i, compensated FP64
+// sums over a fixed partition of the defects (deterministic).  Mean stress
+// zero: nothing to add (the host does not launch this kernel).
+constexpr int MT = 256;
+__global__ __launch_bounds__(MT) void k_mean_stress(const DevDefect* __restrict__ defs,
+                                                    const int32_t* __restrict__ counts, int ndef, double inv_n3,
+                                                    Cubic C, double* __restrict__ add6) {
+  __shared__ double ps[6][MT], pc[6][MT];
+  double s[6], c[6];
+  for (int a = 0; a < 6; ++a) s[a] = c[a] = 0.0;
+  for (int i = threadIdx.x; i < ndef; i += MT) {
+    const double k = (double)counts[i];
+    for (int a = 0; a < 6; ++a) {
+      const double v = k * defs[i].E[a];
+      const double t = s[a] + v;
+      c[a] += (fabs(s[a]) >= fabs(v)) ? ((s[a] - t) + v) : ((v - t) + s[a]);
+      s[a] = t;
+    }
+  }
+  for (int a = 0; a < 6; ++a) {
+    ps[a][threadIdx.x] = s[a];
+    pc[a][threadIdx.x] = c[a];
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
   double m[6];
-  for (int c = 0; c < 6; ++c) {
-    double s = 0.0, comp = 0.0;
-    for (int i = 0; i < ndef; ++i) {
-      const double v = (double)counts[i] * defs[i].E[c];
-      const double t = s + v;
-      comp += (fabs(s) >= fabs(v)) ? ((s - t) + v) : ((v - t) + s);
-      s = t;
+  for (int a = 0; a < 6; ++a) {
+    double ss = 0.0, cc = 0.0;
+    for (int t = 0; t < MT; ++t) {
+      const double v = ps[a][t];
+      const double u = ss + v;
+      cc += (fabs(ss) >= fabs(v)) ? ((ss - u) + v) : ((v - u) + ss);
+      ss = u;
+      cc += pc[a][t];
     }
-    m[c] = (s + comp) * inv_n3;
-  }
-  if (bc == 0) {
-    for (int c = 0; c < 6; ++c) add6[c] = 0.0;
-    return;
+    m[a] = (ss + cc) * inv_n3;
   }
   add6[0] = -(C.C11 * m[0] + C.C12 * (m[1] + m[2]));
   add6[1] = -(C.C11 * m[1] + C.C12 * (m[0] + m[2]));
   add6[2] = -(C.C11 * m[2] + C.C12 * (m[0] + m[1]));
-  for (int c = 3; c < 6; ++c) add6[c] = -2.0 * C.C44 * m[c];
+  for (int a = 3; a < 6; ++a) add6[a] = -2.0 * C.C44 * m[a];
 }
 
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
@@ -244,7 +261,8 @@ hipError_t launch_translate_ids(int32_t* ids, int cnt, int sx, int sy, int sz, i
 
 hipError_t launch_mean_stress(const DevDefect* d, const int32_t* counts, int ndef, int64_t n3, Cubic C, int bc,
                               double* add6, hipStream_t s) {
-  hipLaunchKernelGGL(k_mean_stress, dim3(1), dim3(64), 0, s, d, counts, ndef, 1.0 / (double)n3, C, bc, add6);
+  if (bc == 0) return hipSuccess;  // mean stress zero: the additive term stays 0
+  hipLaunchKernelGGL(k_mean_stress, dim3(1), dim3(MT), 0, s, d, counts, ndef, 1.0 / (double)n3, C, add6);
   return hipGetLastError();
 }
 
