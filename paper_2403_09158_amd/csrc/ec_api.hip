@@ -66,10 +66,9 @@ namespace {
 
 struct DefBuf {
   DevDefect* tab = nullptr;
-  int32_t* cnt = nullptr;
-  int64_t* off = nullptr;
+  int32_t* cnt = nullptr;  // footprint counts, written by the rasteriser
   size_t cap = 0;
-  int32_t* ids = nullptr;
+  int32_t* ids = nullptr;  // footprint slots; defect i owns [slot_i, slot_i + box volume)
   int64_t ids_cap = 0;
 };
 
@@ -77,6 +76,15 @@ struct ProfRec {
   int fam;
   hipEvent_t a, b;
   double bytes;
+};
+
+// Pinned host staging for asynchronous uploads: reused across calls, the
+// previous upload from the same buffer is waited for before it is overwritten.
+struct Pinned {
+  char* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
 };
 
 }  // namespace
@@ -100,9 +108,10 @@ struct ec_state {
   int ndef = 0;
   bool solved = false;
   std::vector<DevDefect> hdefs;
-  std::vector<int32_t> hcnt;
-  std::vector<int64_t> hoff;
-  int64_t ids_used = 0;
+  std::vector<int32_t> hcnt;  // host copy of the counts, valid when hcnt_ok
+  bool hcnt_ok = false;
+  std::vector<int64_t> hcap;  // slot capacity per defect
+  int64_t ids_used = 0;       // slot space in use
   DefBuf db[2];
   int cur = 0;
   double* B = nullptr;
@@ -117,18 +126,22 @@ struct ec_state {
   size_t gcls_bytes = 0;
   int gcls_D = -1, gcls_ncls = -1;
   const WinCache* win = nullptr;
-  // self-term work list
+  // self-term work list (built on the device)
   SelfWork* work = nullptr;
   size_t work_cap = 0;
   double* partial = nullptr;
   size_t partial_cap = 0;
-  int32_t* wbeg = nullptr;
+  int32_t* wcnt = nullptr;
+  size_t wcnt_cap = 0;
+  int64_t* wbeg = nullptr;
   size_t wbeg_cap = 0;
   // update scratch
   int32_t* upd_ids = nullptr;
   int64_t upd_cap = 0;
   double* updE = nullptr;     // 6 doubles
   int64_t* updfix = nullptr;  // 6 int64
+  // pinned staging: defect table, per-update records, moved footprint
+  Pinned pin_tab, pin_upd, pin_ids;
   // profiling
   bool prof = false;
   std::vector<ProfRec> recs;
@@ -206,6 +219,39 @@ ec_status st_grow(ec_state* st, T** p, size_t* cap_elems, size_t need, bool keep
   *p = (T*)q;
   *cap_elems = ncap;
   return EC_OK;
+}
+
+// ------------------------------------------------------------------ pinned staging
+
+ec_status pin_begin(Pinned& b, size_t bytes, char** host) {
+  if (b.pending) {
+    HIPCHK(hipEventSynchronize(b.ev));
+    b.pending = false;
+  }
+  if (!b.ev) HIPCHK(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming));
+  if (bytes > b.cap) {
+    if (b.p) HIPCHK(hipHostFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+    const size_t cap = std::max<size_t>(bytes, 4096);
+    HIPCHK(hipHostMalloc((void**)&b.p, cap, hipHostMallocDefault));
+    b.cap = cap;
+  }
+  *host = b.p;
+  return EC_OK;
+}
+
+ec_status pin_end(Pinned& b, hipStream_t s) {
+  HIPCHK(hipEventRecord(b.ev, s));
+  b.pending = true;
+  return EC_OK;
+}
+
+void pin_free(Pinned& b) {
+  if (b.pending) (void)hipEventSynchronize(b.ev);
+  if (b.p) (void)hipHostFree(b.p);
+  if (b.ev) (void)hipEventDestroy(b.ev);
+  b = Pinned{};
 }
 
 // ------------------------------------------------------------------ profiling
@@ -303,6 +349,8 @@ bool lattice_normal(const double v[3], int m[3]) {
   return false;
 }
 
+int64_t box_volume(const DevDefect& d) { return (int64_t)d.w[0] * d.w[1] * d.w[2]; }
+
 int64_t floordiv(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 int64_t isqrt64(int64_t v) {
@@ -380,6 +428,7 @@ bool quantise(const ec_problem& P, const ec_defect& rec, DevDefect& d, std::stri
     const int64_t w = std::min<int64_t>(hi - lo + 1, n);
     d.w[k] = (int32_t)w;
     d.lo[k] = (int32_t)(((lo % n) + n) % n);
+    d.d0[k] = (int32_t)(QSUB * lo + QSUB / 2 - d.cq[k]);
   }
   return true;
 }
@@ -463,10 +512,10 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
     ledger_free(c, es, fbytes);
     ledger_free(c, sp, sp64);
     ledger_free(c, sg, fbytes);
-    ledger_free(c, ad, 64);
+    ledger_free(c, ad, 6 * 64);
   };
   if ((r = ledger_alloc(c, fbytes, &es)) != EC_OK || (r = ledger_alloc(c, sp64, &sp)) != EC_OK ||
-      (r = ledger_alloc(c, fbytes, &sg)) != EC_OK || (r = ledger_alloc(c, 64, &ad)) != EC_OK) {
+      (r = ledger_alloc(c, fbytes, &sg)) != EC_OK || (r = ledger_alloc(c, 6 * 64, &ad)) != EC_OK) {
     cleanup();
     ledger_free(c, K, Kbytes);
     return r;
@@ -474,23 +523,25 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
   const bool prof = st->prof;
   st->prof = false;
   auto body = [&]() -> ec_status {
+    // additive mean stress per impulse: -C:<eps*> for mean strain zero, else 0
+    double add[6][8] = {};
+    if (st->prob.bc == EC_MEAN_STRAIN_ZERO)
+      for (int b = 0; b < 6; ++b) {
+        double m[6] = {0, 0, 0, 0, 0, 0};
+        m[b] = 1.0 / (double)st->n3;
+        add[b][0] = -(st->C.C11 * m[0] + st->C.C12 * (m[1] + m[2]));
+        add[b][1] = -(st->C.C11 * m[1] + st->C.C12 * (m[0] + m[2]));
+        add[b][2] = -(st->C.C11 * m[2] + st->C.C12 * (m[0] + m[1]));
+        for (int a = 3; a < 6; ++a) add[b][a] = -2.0 * st->C.C44 * m[a];
+      }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(ad, add, sizeof add, hipMemcpyHostToDevice));
     HIPCHK(launch_fill_i64((int64_t*)es, 6 * st->n3, 0, s));
     HIPCHK(hipMemsetAsync(K, 0, Kbytes, s));
     for (int b = 0; b < 6; ++b) {
       if (b > 0) HIPCHK(launch_fill_i64((int64_t*)es + (b - 1) * st->n3, 1, 0, s));
       HIPCHK(launch_fill_i64((int64_t*)es + b * st->n3, 1, (int64_t)FIX_SCALE, s));
-      double add[6] = {0, 0, 0, 0, 0, 0};
-      if (st->prob.bc == EC_MEAN_STRAIN_ZERO) {
-        // sigma mean = -C : <eps*>, <eps*> = unit component b / n^3
-        double m[6] = {0, 0, 0, 0, 0, 0};
-        m[b] = 1.0 / (double)st->n3;
-        add[0] = -(st->C.C11 * m[0] + st->C.C12 * (m[1] + m[2]));
-        add[1] = -(st->C.C11 * m[1] + st->C.C12 * (m[0] + m[2]));
-        add[2] = -(st->C.C11 * m[2] + st->C.C12 * (m[0] + m[1]));
-        for (int a = 3; a < 6; ++a) add[a] = -2.0 * st->C.C44 * m[a];
-      }
-      HIPCHK(hipMemcpyAsync(ad, add, sizeof add, hipMemcpyHostToDevice, s));
-      ec_status q = pipeline(st, s, true, (const int64_t*)es, sp, (double*)sg, (const double*)ad);
+      ec_status q = pipeline(st, s, true, (const int64_t*)es, sp, (double*)sg, (const double*)ad + 8 * b);
       if (q != EC_OK) return q;
       HIPCHK(launch_window_crop((const double*)sg, n, D, b, (double*)K, s));
     }
@@ -568,45 +619,24 @@ ec_status compute_self_terms(ec_state* st, hipStream_t s) {
     st->gcls_D = D;
     st->gcls_ncls = ncls;
   }
-  // Split every defect's pair triangle (q >= p) into work items of about
-  // TARGET pairs; rows p in [0, m), row p holds m - p pairs.
-  constexpr double TARGET = 32768.0;
-  std::vector<SelfWork> work;
-  std::vector<int32_t> wbeg(st->ndef + 1);
-  double pairs = 0;
-  for (int i = 0; i < st->ndef; ++i) {
-    wbeg[i] = (int32_t)work.size();
-    const double m = st->hcnt[i];
-    const double tot = m * (m + 1) / 2;
-    pairs += tot;
-    const int k = std::max(1, (int)std::ceil(tot / TARGET));
-    int p0 = 0;
-    for (int j = 1; j <= k; ++j) {
-      int p1;
-      if (j == k) {
-        p1 = (int)m;
-      } else {
-        // smallest p with p m - p (p - 1)/2 >= j tot / k
-        const double T = j * tot / k, a = m + 0.5;
-        p1 = (int)std::ceil(a - std::sqrt(std::max(0.0, a * a - 2.0 * T)));
-        p1 = std::min(std::max(p1, p0), (int)m);
-      }
-      if (p1 > p0 || (j == k && work.size() == (size_t)wbeg[i])) work.push_back({i, p0, p1, 0});
-      p0 = p1;
-    }
+  // Work-list capacity: at most 64 items per defect, fewer for small boxes.
+  int64_t cap = 0;
+  double pairs_bound = 0;
+  for (const auto& d : st->hdefs) {
+    const double m = (double)box_volume(d);
+    const double k = std::ceil(m * (m + 1) / 2 / 32768.0);
+    cap += (int64_t)std::min(64.0, std::max(1.0, k));
+    pairs_bound += m;
   }
-  wbeg[st->ndef] = (int32_t)work.size();
-  const int nwork = (int)work.size();
-  if ((r = st_grow(st, &st->work, &st->work_cap, std::max(nwork, 1))) != EC_OK) return r;
-  if ((r = st_grow(st, &st->partial, &st->partial_cap, std::max(nwork, 1))) != EC_OK) return r;
-  if ((r = st_grow(st, &st->wbeg, &st->wbeg_cap, wbeg.size())) != EC_OK) return r;
-  if (nwork > 0) HIPCHK(hipMemcpyAsync(st->work, work.data(), nwork * sizeof(SelfWork), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(st->wbeg, wbeg.data(), wbeg.size() * 4, hipMemcpyHostToDevice, s));
+  cap = std::max<int64_t>(cap, 1);
+  if ((r = st_grow(st, &st->work, &st->work_cap, (size_t)cap)) != EC_OK) return r;
+  if ((r = st_grow(st, &st->partial, &st->partial_cap, (size_t)cap)) != EC_OK) return r;
+  if ((r = st_grow(st, &st->wcnt, &st->wcnt_cap, (size_t)st->ndef + 1)) != EC_OK) return r;
+  if ((r = st_grow(st, &st->wbeg, &st->wbeg_cap, (size_t)st->ndef + 1)) != EC_OK) return r;
   const DefBuf& b = st->db[st->cur];
-  LAUNCH(st, s, PF_SELF, pairs * 8.0,
-         launch_self_terms(b.tab, b.off, b.cnt, b.ids, st->n, w->K, st->gcls, D, st->work, nwork, st->partial,
-                           st->wbeg, st->ndef, st->h3c, st->B, s));
-  HIPCHK(hipStreamSynchronize(s));  // work list staging is pageable
+  LAUNCH(st, s, PF_SELF, 0,
+         launch_self_terms(b.tab, st->ndef, b.cnt, b.ids, st->n, w->K, st->gcls, D, st->work, (int64_t)st->work_cap,
+                           st->wcnt, st->wbeg, st->partial, st->h3c, st->B, s));
   st->B_valid = true;
   return EC_OK;
 }
@@ -665,27 +695,30 @@ ec_status ensure_per_defect(ec_state* st, size_t ndef) {
 ec_status ensure_defbuf(ec_state* st, DefBuf& b, size_t ndef) {
   if (ndef + 1 <= b.cap && b.tab) return EC_OK;
   size_t cap = std::max<size_t>(ndef + 1, 16);
-  void *t = nullptr, *c = nullptr, *o = nullptr;
+  void *t = nullptr, *c = nullptr;
   ec_status r;
   if ((r = ledger_alloc(st->ctx, cap * sizeof(DevDefect), &t)) != EC_OK) return r;
   if ((r = ledger_alloc(st->ctx, cap * 4, &c)) != EC_OK) {
     ledger_free(st->ctx, t, cap * sizeof(DevDefect));
     return r;
   }
-  if ((r = ledger_alloc(st->ctx, cap * 8, &o)) != EC_OK) {
-    ledger_free(st->ctx, t, cap * sizeof(DevDefect));
-    ledger_free(st->ctx, c, cap * 4);
-    return r;
-  }
   ledger_free(st->ctx, b.tab, b.cap * sizeof(DevDefect));
   ledger_free(st->ctx, b.cnt, b.cap * 4);
-  ledger_free(st->ctx, b.off, b.cap * 8);
-  st->held += cap * (sizeof(DevDefect) + 12);
-  st->held -= std::min(st->held, b.cap * (sizeof(DevDefect) + 12));
+  st->held += cap * (sizeof(DevDefect) + 4);
+  st->held -= std::min(st->held, b.cap * (sizeof(DevDefect) + 4));
   b.tab = (DevDefect*)t;
   b.cnt = (int32_t*)c;
-  b.off = (int64_t*)o;
   b.cap = cap;
+  return EC_OK;
+}
+
+ec_status fetch_counts(ec_state* st) {
+  if (st->hcnt_ok) return EC_OK;
+  st->hcnt.assign(st->ndef, 0);
+  HIPCHK(hipDeviceSynchronize());
+  if (st->ndef > 0)
+    HIPCHK(hipMemcpy(st->hcnt.data(), st->db[st->cur].cnt, st->ndef * 4, hipMemcpyDeviceToHost));
+  st->hcnt_ok = true;
   return EC_OK;
 }
 
@@ -838,7 +871,6 @@ void ec_state_destroy(ec_state* st) {
   for (auto& b : st->db) {
     ledger_free(c, b.tab, b.cap * sizeof(DevDefect));
     ledger_free(c, b.cnt, b.cap * 4);
-    ledger_free(c, b.off, b.cap * 8);
     ledger_free(c, b.ids, b.ids_cap * 4);
   }
   ledger_free(c, st->B, st->pd_cap * 8);
@@ -848,7 +880,11 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->upd_ids, st->upd_cap * 4);
   ledger_free(c, st->work, st->work_cap * sizeof(SelfWork));
   ledger_free(c, st->partial, st->partial_cap * 8);
-  ledger_free(c, st->wbeg, st->wbeg_cap * 4);
+  ledger_free(c, st->wcnt, st->wcnt_cap * 4);
+  ledger_free(c, st->wbeg, st->wbeg_cap * 8);
+  pin_free(st->pin_tab);
+  pin_free(st->pin_upd);
+  pin_free(st->pin_ids);
   for (auto& r : st->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -877,37 +913,39 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   st->classes.clear();
   for (auto& d : h) assign_class(st, d);
   const bool classes_changed = old_classes != st->classes;
-  // 2. footprints of the new list into the spare buffers
+  // 2. footprint slots of the new list (box volumes) in the spare buffers
+  std::vector<int64_t> cap(ndef);
+  int64_t total = 0;
+  for (int i = 0; i < ndef; ++i) {
+    h[i].slot = total;
+    cap[i] = box_volume(h[i]);
+    total += cap[i];
+  }
   DefBuf& nb = st->db[1 - st->cur];
   ec_status r;
-  if ((r = ensure_defbuf(st, nb, ndef)) != EC_OK || (r = ensure_per_defect(st, ndef)) != EC_OK) {
-    st->classes = old_classes;
-    return r;
-  }
-  if (ndef > 0) HIPCHK(hipMemcpyAsync(nb.tab, h.data(), ndef * sizeof(DevDefect), hipMemcpyHostToDevice, s));
-  LAUNCH(st, s, PF_RASTER, 0, launch_raster_count(nb.tab, ndef, st->n, nb.cnt, s));
-  LAUNCH(st, s, PF_RASTER, 0, launch_scan(nb.cnt, ndef, nb.off, s));
-  std::vector<int32_t> hc(ndef);
-  std::vector<int64_t> ho(ndef + 1);
-  if (ndef > 0) HIPCHK(hipMemcpyAsync(hc.data(), nb.cnt, ndef * 4, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(ho.data(), nb.off, (ndef + 1) * 8, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const int64_t total = ho[ndef];
   size_t idcap = (size_t)nb.ids_cap;
-  if ((r = st_grow(st, &nb.ids, &idcap, (size_t)std::max<int64_t>(total, 1))) != EC_OK) {
+  if ((r = ensure_defbuf(st, nb, ndef)) != EC_OK || (r = ensure_per_defect(st, ndef)) != EC_OK ||
+      (r = st_grow(st, &nb.ids, &idcap, (size_t)std::max<int64_t>(total, 1))) != EC_OK) {
     st->classes = old_classes;
     return r;
   }
   nb.ids_cap = (int64_t)idcap;
+  if (ndef > 0) {
+    char* hp = nullptr;
+    if ((r = pin_begin(st->pin_tab, ndef * sizeof(DevDefect), &hp)) != EC_OK) return r;
+    std::memcpy(hp, h.data(), ndef * sizeof(DevDefect));
+    HIPCHK(hipMemcpyAsync(nb.tab, hp, ndef * sizeof(DevDefect), hipMemcpyHostToDevice, s));
+    if ((r = pin_end(st->pin_tab, s)) != EC_OK) return r;
+  }
   // 3. commit: remove the old eigenstrain, add the new one
   const DefBuf& ob = st->db[st->cur];
   if (st->ndef > 0)
-    LAUNCH(st, s, PF_RASTER, 0, launch_unraster(ob.tab, st->ndef, ob.off, ob.cnt, ob.ids, st->n3, st->es, s));
-  LAUNCH(st, s, PF_RASTER, 0, launch_raster_fill(nb.tab, ndef, st->n, nb.off, nb.ids, st->es, s));
+    LAUNCH(st, s, PF_RASTER, 0, launch_unraster(ob.tab, st->ndef, ob.cnt, ob.ids, st->n3, st->es, s));
+  LAUNCH(st, s, PF_RASTER, 0, launch_raster_fill(nb.tab, ndef, st->n, nb.ids, nb.cnt, st->es, s));
   st->cur = 1 - st->cur;
   st->hdefs.swap(h);
-  st->hcnt.swap(hc);
-  st->hoff.swap(ho);
+  st->hcap.swap(cap);
+  st->hcnt_ok = false;
   st->ndef = ndef;
   st->ids_used = total;
   st->B_valid = false;
@@ -930,8 +968,8 @@ ec_status ec_interaction_energies(ec_state* st, void* stream, double* E_out, int
   ec_status r;
   if (!st->B_valid && (r = compute_self_terms(st, s)) != EC_OK) return r;
   const DefBuf& b = st->db[st->cur];
-  LAUNCH(st, s, PF_REDUCE, st->ids_used * 52.0,
-         launch_reduce(b.tab, st->ndef, b.off, b.cnt, b.ids, st->sig, st->n3, st->B, st->h3c, st->S6, st->E, s));
+  LAUNCH(st, s, PF_REDUCE, 0,
+         launch_reduce(b.tab, st->ndef, b.cnt, b.ids, st->sig, st->n3, st->B, st->h3c, st->S6, st->E, s));
   if (E_out && st->ndef > 0) return copy_out(E_out, st->E, st->ndef * 8, on_device != 0, s);
   return EC_OK;
 }
@@ -960,30 +998,28 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
       sh[k] = d;
     }
   const size_t ncls_before = st->classes.size();
-  nd.cls = -1;
   if (hop) {
     nd.cls = od.cls;
     nd.s = od.s;
   } else {
     assign_class(st, nd);
   }
-  const int cnt_old = st->hcnt[idx];
-  const int64_t off_old = st->hoff[idx];
   DefBuf& b = st->db[st->cur];
   std::vector<int32_t> new_ids;
-  int cnt_new = cnt_old;
-  int64_t off_new = off_old;
+  int cnt_new = -1;  // hop: same count as the old footprint (read on the device)
+  int64_t cap_new = st->hcap[idx];
+  nd.slot = od.slot;
   ec_status r;
   if (!hop) {
-    const long tot = (long)nd.w[0] * nd.w[1] * nd.w[2];
-    for (long e = 0; e < tot; ++e) {
-      const int iz = (int)(e / ((long)nd.w[0] * nd.w[1]));
-      const int iy = (int)((e / nd.w[0]) % nd.w[1]);
-      const int ix = (int)(e % nd.w[0]);
-      const int x = box_axis(nd.lo[0], nd.w[0], n, ix), y = box_axis(nd.lo[1], nd.w[1], n, iy),
-                z = box_axis(nd.lo[2], nd.w[2], n, iz);
-      if (member(nd, n, x, y, z)) new_ids.push_back((z * n + y) * n + x);
-    }
+    // new footprint on the host, same enumeration and membership as the rasteriser
+    for (int iz = 0; iz < nd.w[2]; ++iz)
+      for (int iy = 0; iy < nd.w[1]; ++iy) {
+        const int y = box_axis(nd.lo[1], nd.w[1], n, iy), z = box_axis(nd.lo[2], nd.w[2], n, iz);
+        for (int ix = 0; ix < nd.w[0]; ++ix) {
+          const int x = box_axis(nd.lo[0], nd.w[0], n, ix);
+          if (member(nd, n, x, y, z)) new_ids.push_back((z * n + y) * n + x);
+        }
+      }
     cnt_new = (int)new_ids.size();
     size_t ucap = (size_t)st->upd_cap;
     if ((r = st_grow(st, &st->upd_ids, &ucap, std::max<size_t>(cnt_new, 1))) != EC_OK) {
@@ -991,10 +1027,11 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
       return r;
     }
     st->upd_cap = (int64_t)ucap;
-    if (cnt_new > cnt_old) {
-      off_new = st->ids_used;
+    if (cnt_new > st->hcap[idx]) {  // does not fit the old slot: take a new one at the end
+      nd.slot = st->ids_used;
+      cap_new = box_volume(nd);
       size_t icap = (size_t)b.ids_cap;
-      if ((r = st_grow(st, &b.ids, &icap, (size_t)(st->ids_used + cnt_new), true, s)) != EC_OK) {
+      if ((r = st_grow(st, &b.ids, &icap, (size_t)(st->ids_used + cap_new), true, s)) != EC_OK) {
         st->classes.resize(ncls_before);
         return r;
       }
@@ -1005,31 +1042,47 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
   int ylo, ylen, zlo, zlen;
   cyclic_cover(od.lo[1], od.w[1], nd.lo[1], nd.w[1], n, ylo, ylen);
   cyclic_cover(od.lo[2], od.w[2], nd.lo[2], nd.w[2], n, zlo, zlen);
-  // --- commit
-  if (!hop && cnt_new > 0)
-    HIPCHK(hipMemcpyAsync(st->upd_ids, new_ids.data(), cnt_new * 4, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(st->updE, nd.E, 48, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(st->updfix, nd.efix, 48, hipMemcpyHostToDevice, s));
   double dadd[6] = {0, 0, 0, 0, 0, 0};
-  if (st->prob.bc == EC_MEAN_STRAIN_ZERO && cnt_new != cnt_old) {
+  if (!hop && st->prob.bc == EC_MEAN_STRAIN_ZERO) {
+    // mean strain zero: the mean stress moves with the eigenstrain volume
+    if ((r = fetch_counts(st)) != EC_OK) return r;
     double m[6];
-    for (int a = 0; a < 6; ++a) m[a] = (double)(cnt_new - cnt_old) * nd.E[a] / (double)st->n3;
+    for (int a = 0; a < 6; ++a)
+      m[a] = ((double)cnt_new * nd.E[a] - (double)st->hcnt[idx] * od.E[a]) / (double)st->n3;
     dadd[0] = -(st->C.C11 * m[0] + st->C.C12 * (m[1] + m[2]));
     dadd[1] = -(st->C.C11 * m[1] + st->C.C12 * (m[0] + m[2]));
     dadd[2] = -(st->C.C11 * m[2] + st->C.C12 * (m[0] + m[1]));
     for (int a = 3; a < 6; ++a) dadd[a] = -2.0 * st->C.C44 * m[a];
   }
-  HIPCHK(hipMemcpyAsync(st->add6 + 12, dadd, 48, hipMemcpyHostToDevice, s));
-  const int32_t* oids = b.ids + off_old;
+  // --- commit
+  char* up = nullptr;  // [E 48][efix 48][dadd 48][count 8][record]
+  if ((r = pin_begin(st->pin_upd, 152 + sizeof(DevDefect), &up)) != EC_OK) return r;
+  std::memcpy(up, nd.E, 48);
+  std::memcpy(up + 48, nd.efix, 48);
+  std::memcpy(up + 96, dadd, 48);
+  std::memcpy(up + 144, &cnt_new, 4);
+  std::memcpy(up + 152, &nd, sizeof nd);
+  if (!hop && cnt_new > 0) {
+    char* ip = nullptr;
+    if ((r = pin_begin(st->pin_ids, (size_t)cnt_new * 4, &ip)) != EC_OK) return r;
+    std::memcpy(ip, new_ids.data(), (size_t)cnt_new * 4);
+    HIPCHK(hipMemcpyAsync(st->upd_ids, ip, (size_t)cnt_new * 4, hipMemcpyHostToDevice, s));
+    if ((r = pin_end(st->pin_ids, s)) != EC_OK) return r;
+  }
+  HIPCHK(hipMemcpyAsync(st->updE, up, 48, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(st->updfix, up + 48, 48, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(st->add6 + 12, up + 96, 48, hipMemcpyHostToDevice, s));
+  const int32_t* oids = b.ids + od.slot;
+  const int32_t* ocnt = b.cnt + idx;
   const int32_t* nids = hop ? nullptr : st->upd_ids;
   LAUNCH(st, s, PF_RASTER, 0,
-         launch_update_es(st->updfix, oids, cnt_old, nids, cnt_new, sh[0], sh[1], sh[2], n, st->es, s));
+         launch_update_es(st->updfix, oids, ocnt, nids, cnt_new, sh[0], sh[1], sh[2], n, st->es, s));
   {
     const bool fp64 = st->fp64;
     const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
     const double frac_z = (double)zlen / n;
     LAUNCH(st, s, PF_XF, frac_z * ylen / n * sb,
-           launch_x_forward_sparse(fp64, oids, cnt_old, nids, cnt_new, sh[0], sh[1], sh[2], st->updE, st->spec, st->g,
+           launch_x_forward_sparse(fp64, oids, ocnt, nids, cnt_new, sh[0], sh[1], sh[2], st->updE, st->spec, st->g,
                                    ylo, ylen, zlo, zlen, st->tw, s));
     const Prune py{ylo, ylen, zlo, zlen};
     LAUNCH(st, s, PF_Y, 2 * frac_z * sb, launch_pencil(fp64, false, 1, st->spec, st->g, py, st->tw, s));
@@ -1044,21 +1097,21 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
   }
   // footprint bookkeeping
   if (hop) {
-    LAUNCH(st, s, PF_OTHER, 0, launch_translate_ids(b.ids + off_old, cnt_old, sh[0], sh[1], sh[2], n, s));
+    LAUNCH(st, s, PF_OTHER, 0, launch_translate_ids(b.ids + od.slot, ocnt, sh[0], sh[1], sh[2], n, s));
   } else {
     if (cnt_new > 0)
-      HIPCHK(hipMemcpyAsync(b.ids + off_new, st->upd_ids, cnt_new * 4, hipMemcpyDeviceToDevice, s));
-    const int32_t c32 = cnt_new;
-    HIPCHK(hipMemcpyAsync(b.cnt + idx, &c32, 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(b.off + idx, &off_new, 8, hipMemcpyHostToDevice, s));
-    st->hcnt[idx] = cnt_new;
-    st->hoff[idx] = off_new;
-    if (off_new != off_old) st->ids_used += cnt_new;
+      HIPCHK(hipMemcpyAsync(b.ids + nd.slot, st->upd_ids, cnt_new * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(b.cnt + idx, up + 144, 4, hipMemcpyHostToDevice, s));
+    if (nd.slot != od.slot) {
+      st->ids_used += cap_new;
+      st->hcap[idx] = cap_new;
+    }
+    if (st->hcnt_ok) st->hcnt[idx] = cnt_new;
     st->B_valid = false;
     if (st->classes.size() != ncls_before) st->gcls_ncls = -1;
   }
-  HIPCHK(hipMemcpyAsync(b.tab + idx, &nd, sizeof nd, hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));  // host staging above is pageable and short-lived
+  HIPCHK(hipMemcpyAsync(b.tab + idx, up + 152, sizeof nd, hipMemcpyHostToDevice, s));
+  if ((r = pin_end(st->pin_upd, s)) != EC_OK) return r;
   st->hdefs[idx] = nd;
   if (E_out) return ec_interaction_energies(st, stream, E_out, on_device);
   return EC_OK;
@@ -1066,6 +1119,8 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
 
 ec_status ec_state_footprints(ec_state* st, int32_t* counts, int32_t* ids, int64_t cap, int64_t* total) {
   if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  ec_status r = fetch_counts(st);
+  if (r != EC_OK) return r;
   int64_t tot = 0;
   for (int i = 0; i < st->ndef; ++i) tot += st->hcnt[i];
   if (total) *total = tot;
@@ -1075,11 +1130,10 @@ ec_status ec_state_footprints(ec_state* st, int32_t* counts, int32_t* ids, int64
   if (cap < tot) return fail(EC_ERR_ARG, "ids buffer too small (%lld < %lld)", (long long)cap, (long long)tot);
   const DefBuf& b = st->db[st->cur];
   std::vector<int32_t> all((size_t)std::max<int64_t>(st->ids_used, 1));
-  HIPCHK(hipDeviceSynchronize());
   if (st->ids_used > 0) HIPCHK(hipMemcpy(all.data(), b.ids, st->ids_used * 4, hipMemcpyDeviceToHost));
   int64_t o = 0;
   for (int i = 0; i < st->ndef; ++i) {
-    std::memcpy(ids + o, all.data() + st->hoff[i], st->hcnt[i] * 4);
+    std::memcpy(ids + o, all.data() + st->hdefs[i].slot, st->hcnt[i] * 4);
     o += st->hcnt[i];
   }
   return EC_OK;

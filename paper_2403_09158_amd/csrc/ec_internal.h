@@ -35,11 +35,13 @@ struct DevDefect {
   int32_t lo[3];  // bounding-box first voxel index per axis, in [0, n)
   int32_t w[3];   // bounding-box widths per axis, <= n
   int32_t cls;    // eigenstrain direction class (-1: none)
+  int32_t d0[3];  // unwrapped offset (q units) of the box's first voxel centre from the centre
+  int32_t pad_;
   int64_t R2q;    // radius^2 in q^2 units
+  int64_t slot;   // first element of this defect's footprint slot in the id buffer
   int64_t efix[6];
   double E[6];    // eigenstrain, tensor components xx yy zz yz xz xy
   double s;       // E = s * class direction (when cls >= 0)
-  double pad_;
 };
 
 // Voxel-centre membership, exact integer arithmetic (loops: half-open slab
@@ -69,6 +71,60 @@ __host__ __device__ inline int box_axis(int lo, int w, int n, int i) {
   const int wl = lo + w - n;  // voxels that wrap to the low end
   if (wl <= 0) return lo + i;
   return i < wl ? i : lo + (i - wl);
+}
+
+// Conservative range [u0, u1] of box x-indices (0 <= u < w[0]) that can hold
+// members in the box row (iy, iz); the exact test is member().  Returns false if
+// the row cannot hold any.  Bounds come from the geometry in floating point with
+// a two-voxel margin: the slab fixes x within (e/2 |m|)/|m_x| of the plane when
+// m_x != 0, and |d| <= sqrt(R^2 + e^2/4) bounds every member.
+__host__ __device__ inline bool row_range(const DevDefect& d, int n, int y, int z, int& u0, int& u1) {
+  if (d.w[0] >= n) {  // the box spans the whole x axis: no pruning
+    u0 = 0;
+    u1 = n - 1;
+    return true;
+  }
+  const int32_t Lq = QSUB * n, hq = Lq / 2;
+  int32_t ty = QSUB * y + QSUB / 2 - d.cq[1], tz = QSUB * z + QSUB / 2 - d.cq[2];
+  ty += (ty < -hq) ? Lq : 0;
+  ty -= (ty >= hq) ? Lq : 0;
+  tz += (tz < -hq) ? Lq : 0;
+  tz -= (tz >= hq) ? Lq : 0;
+  const double dy = ty, dz = tz;
+  const double dx0 = (double)d.d0[0];
+  const double margin = 8.0;  // q units; covers rounding of the few operations below
+  double lo, hi;
+  if (d.kind == 1) {
+    const double rem = (double)d.R2q - dy * dy - dz * dz;
+    if (rem < -margin * margin) return false;
+    const double r = sqrt(rem > 0.0 ? rem : 0.0) + margin;
+    lo = -r;
+    hi = r;
+  } else {
+    const double half = 0.5 * d.eq * sqrt((double)d.mm);  // slab half-width along m, in q * |m| units
+    const double tyz = (double)d.m[1] * dy + (double)d.m[2] * dz;
+    const double rem = (double)d.R2q + 0.25 * (double)d.eq * d.eq - dy * dy - dz * dz;
+    if (rem < -margin * margin) return false;
+    const double r = sqrt(rem > 0.0 ? rem : 0.0) + margin;
+    lo = -r;
+    hi = r;
+    if (d.m[0] != 0) {
+      double a = (-half - tyz) / d.m[0], b = (half - tyz) / d.m[0];
+      if (a > b) {
+        const double t = a;
+        a = b;
+        b = t;
+      }
+      lo = lo > a - margin ? lo : a - margin;
+      hi = hi < b + margin ? hi : b + margin;
+    } else if (fabs(tyz) > half + margin) {
+      return false;
+    }
+  }
+  const double a = ceil((lo - dx0) / QSUB), b = floor((hi - dx0) / QSUB);
+  u0 = a < 0.0 ? 0 : (int)a;
+  u1 = b > (double)(d.w[0] - 1) ? d.w[0] - 1 : (int)b;
+  return u0 <= u1;
 }
 
 // Storage helpers
@@ -118,7 +174,8 @@ bool fft_supported(int n);
 int pencil_width(int n, bool fp64);
 
 hipError_t launch_x_forward(bool fp64, const int64_t* es, void* spec, SpecGeom g, const double2* tw, hipStream_t s);
-hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, int old_cnt, const int32_t* new_ids, int new_cnt,
+hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, const int32_t* old_cnt, const int32_t* new_ids,
+                                   int new_cnt,
                                    int shift_x, int shift_y, int shift_z, const double* E, void* spec, SpecGeom g,
                                    int y_lo, int y_len, int z_lo, int z_len, const double2* tw, hipStream_t s);
 hipError_t launch_pencil(bool fp64, bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw,
@@ -130,31 +187,34 @@ hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig
 
 // ---- k_raster.hip / k_energy.hip -----------------------------------------------
 
-hipError_t launch_raster_count(const DevDefect* d, int ndef, int n, int32_t* counts, hipStream_t s);
-hipError_t launch_scan(const int32_t* counts, int ndef, int64_t* offsets, hipStream_t s);
-hipError_t launch_raster_fill(const DevDefect* d, int ndef, int n, const int64_t* offsets, int32_t* ids,
-                              int64_t* es, hipStream_t s);
-hipError_t launch_unraster(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
-                           const int32_t* ids, int64_t n3, int64_t* es, hipStream_t s);
-hipError_t launch_update_es(const int64_t* efix, const int32_t* old_ids, int cnt_old, const int32_t* new_ids,
-                            int cnt_new, int shift_x, int shift_y, int shift_z, int n, int64_t* es, hipStream_t s);
-hipError_t launch_translate_ids(int32_t* ids, int cnt, int shift_x, int shift_y, int shift_z, int n, hipStream_t s);
+hipError_t launch_raster_fill(const DevDefect* d, int ndef, int n, int32_t* ids, int32_t* counts, int64_t* es,
+                              hipStream_t s);
+hipError_t launch_unraster(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int64_t n3,
+                           int64_t* es, hipStream_t s);
+// One defect moved: old footprint ids[old_slot .. + *cnt_old) (device count),
+// new footprint = old shifted by whole voxels (new_ids == nullptr) or new_ids[0 .. cnt_new).
+hipError_t launch_update_es(const int64_t* efix, const int32_t* old_ids, const int32_t* cnt_old,
+                            const int32_t* new_ids, int cnt_new, int shift_x, int shift_y, int shift_z, int n,
+                            int64_t* es, hipStream_t s);
+hipError_t launch_translate_ids(int32_t* ids, const int32_t* cnt, int shift_x, int shift_y, int shift_z, int n,
+                                hipStream_t s);
 hipError_t launch_mean_stress(const DevDefect* d, const int32_t* counts, int ndef, int64_t n3, Cubic C, int bc,
                               double* add6, hipStream_t s);
+hipError_t launch_scan(const int32_t* counts, int ndef, int64_t* offsets, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t count, int64_t v, hipStream_t s);
-hipError_t launch_reduce(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
-                         const int32_t* ids, const double* sig, int64_t n3, const double* B, double h3c, double* S6,
-                         double* E, hipStream_t s);
+hipError_t launch_reduce(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, const double* sig,
+                         int64_t n3, const double* B, double h3c, double* S6, double* E, hipStream_t s);
 hipError_t launch_window_crop(const double* sig, int n, int D, int b, double* K, hipStream_t s);
 hipError_t launch_class_windows(const double* K, int D, const double* dirs, int ncls, double* g, hipStream_t s);
 // Self-term work item: rows [p0, p1) of defect `def`'s pair triangle.
 struct SelfWork {
   int32_t def, p0, p1, pad;
 };
-hipError_t launch_self_terms(const DevDefect* d, const int64_t* offsets, const int32_t* counts, const int32_t* ids,
-                             int n, const double* K, const double* gcls, int D, const SelfWork* work, int nwork,
-                             double* partial, const int32_t* work_begin, int ndef, double h3c, double* B,
-                             hipStream_t s);
+// Builds the work list on the device (scratch: wcnt[ndef], wbeg[ndef + 1]) and
+// runs it on a fixed grid; no host synchronisation.
+hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int n,
+                             const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
+                             int32_t* wcnt, int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s);
 hipError_t launch_sig_to_out(const double* sig, const int64_t* es, int64_t n3, Cubic C, int which, bool fp32,
                              void* out, hipStream_t s);
 

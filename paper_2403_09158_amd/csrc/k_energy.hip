@@ -7,6 +7,8 @@
 // (x, y) of the footprint of E_i:G(x - y):E_i is the defect's own contribution,
 // G being the discrete periodic kernel sigma = G * eps* (a window of it around
 // r = 0 is enough because footprints are compact).
+#include <algorithm>
+
 #include "ec_internal.h"
 
 namespace ec {
@@ -24,13 +26,12 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double v) {
 
 constexpr int RDT = 64;  // one wavefront per defect
 
-__global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ defs, const int64_t* __restrict__ off,
-                                                const int32_t* __restrict__ cnt, const int32_t* __restrict__ ids,
-                                                const double* __restrict__ sig, int64_t n3,
-                                                const double* __restrict__ B, double h3c, double* __restrict__ S6,
-                                                double* __restrict__ E) {
+__global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
+                                                const int32_t* __restrict__ ids, const double* __restrict__ sig,
+                                                int64_t n3, const double* __restrict__ B, double h3c,
+                                                double* __restrict__ S6, double* __restrict__ E) {
   const int i = blockIdx.x;
-  const int64_t o = off[i];
+  const int64_t o = defs[i].slot;
   const int m = cnt[i];
   double s[6], c[6];
 #pragma unroll
@@ -107,80 +108,120 @@ __device__ __forceinline__ int32_t pack_xyz(int id, int n) {
   return (id % n) | (((id / n) % n) << 10) | ((id / (n * n)) << 20);
 }
 
-// One work item = rows [p0, p1) of a defect's pair triangle q >= p.  Each
+constexpr double SELF_TARGET = 32768.0;  // pairs per work item
+constexpr int SELF_KMAX = 64;            // work items per defect at most
+
+// Work items per defect: ceil(m (m + 1) / 2 / target), between 1 and SELF_KMAX.
+__global__ void k_self_count(const int32_t* __restrict__ cnt, int ndef, int32_t* __restrict__ wcnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndef) return;
+  const double m = cnt[i];
+  const int k = (int)ceil(m * (m + 1.0) * 0.5 / SELF_TARGET);
+  wcnt[i] = k < 1 ? 1 : (k > SELF_KMAX ? SELF_KMAX : k);
+}
+
+// Rows [p0, p1) with about equal pair counts: rows [0, p) hold p m - p (p - 1)/2 pairs.
+__global__ void k_self_items(const int32_t* __restrict__ cnt, int ndef, const int64_t* __restrict__ wbeg,
+                             SelfWork* __restrict__ work, int64_t cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndef) return;
+  const int m = cnt[i];
+  const double tot = (double)m * (m + 1.0) * 0.5, a = m + 0.5;
+  const int64_t b = wbeg[i];
+  const int k = (int)(wbeg[i + 1] - b);
+  int p0 = 0;
+  for (int j = 1; j <= k; ++j) {
+    int p1 = m;
+    if (j < k) {
+      const double T = j * tot / k;
+      p1 = (int)ceil(a - sqrt(fmax(0.0, a * a - 2.0 * T)));
+      p1 = p1 < p0 ? p0 : (p1 > m ? m : p1);
+    }
+    if (b + j - 1 < cap) work[b + j - 1] = SelfWork{i, p0, p1, 0};
+    p0 = p1;
+  }
+}
+
+// Each work item = rows [p0, p1) of a defect's pair triangle q >= p.  Each
 // wavefront takes one row p and its lanes walk q = p + lane, p + lane + 64, ...:
 // consecutive footprint voxels are x-neighbours, so the lanes read nearly
 // consecutive window entries.  Off-diagonal pairs count twice (G(r) = G(-r)).
-__global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs, const int64_t* __restrict__ off,
-                                             const int32_t* __restrict__ cnt, const int32_t* __restrict__ ids, int n,
-                                             const double* __restrict__ K, const double* __restrict__ gcls, int D,
-                                             const SelfWork* __restrict__ work, double* __restrict__ partial) {
-  const SelfWork wk = work[blockIdx.x];
-  const int i = wk.def;
-  const int m = cnt[i];
-  const int64_t o = off[i];
-  const int cls = defs[i].cls;
+// A fixed grid walks the item list, whose length is read on the device.
+__global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
+                                             const int32_t* __restrict__ ids, int n, const double* __restrict__ K,
+                                             const double* __restrict__ gcls, int D,
+                                             const SelfWork* __restrict__ work, const int64_t* __restrict__ nwork_p,
+                                             int64_t cap, double* __restrict__ partial) {
   __shared__ int32_t pk[SMAX];
   __shared__ double wsum[ST / 64];
-  const bool staged = m <= SMAX;
-  if (staged)
-    for (int k = threadIdx.x; k < m; k += ST) pk[k] = pack_xyz(ids[o + k], n);
-  __syncthreads();
-  auto coord = [&](int k) -> int32_t { return staged ? pk[k] : pack_xyz(ids[o + k], n); };
+  const int64_t nwork = *nwork_p < cap ? *nwork_p : cap;
   const int W = 2 * D + 1;
   const int h = n / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  auto widx = [&](int32_t P, int32_t Q) -> int {
-    int rx = (P & 1023) - (Q & 1023), ry = ((P >> 10) & 1023) - ((Q >> 10) & 1023), rz = (P >> 20) - (Q >> 20);
-    rx += rx < -h ? n : (rx >= h ? -n : 0);
-    ry += ry < -h ? n : (ry >= h ? -n : 0);
-    rz += rz < -h ? n : (rz >= h ? -n : 0);
-    return ((rz + D) * W + (ry + D)) * W + (rx + D);
-  };
-  double acc = 0.0;
-  if (cls >= 0) {
-    const double* g = gcls + (size_t)cls * W * W * W;
-    for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
-      const int32_t P = coord(p);
-      for (int q = p + lane; q < m; q += 64) {
-        const double v = g[widx(P, coord(q))];
-        acc += (q == p) ? v : 2.0 * v;
-      }
-    }
-  } else {
-    double E[6];
-    for (int a = 0; a < 6; ++a) E[a] = defs[i].E[a];
-    for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
-      const int32_t P = coord(p);
-      for (int q = p + lane; q < m; q += 64) {
-        const double* k = K + (size_t)widx(P, coord(q)) * KWIN;
-        double v = 0.0;
-        for (int a = 0; a < 6; ++a) {
-          v += E[a] * E[a] * k[tri(a, a)];
-          for (int b = a + 1; b < 6; ++b) v += 2.0 * E[a] * E[b] * k[tri(a, b)];
+  for (int64_t wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+    const SelfWork wk = work[wi];
+    const int i = wk.def;
+    const int m = cnt[i];
+    const int64_t o = defs[i].slot;
+    const int cls = defs[i].cls;
+    const bool staged = m <= SMAX;
+    if (staged)
+      for (int k = threadIdx.x; k < m; k += ST) pk[k] = pack_xyz(ids[o + k], n);
+    __syncthreads();
+    auto coord = [&](int k) -> int32_t { return staged ? pk[k] : pack_xyz(ids[o + k], n); };
+    auto widx = [&](int32_t P, int32_t Q) -> int {
+      int rx = (P & 1023) - (Q & 1023), ry = ((P >> 10) & 1023) - ((Q >> 10) & 1023), rz = (P >> 20) - (Q >> 20);
+      rx += rx < -h ? n : (rx >= h ? -n : 0);
+      ry += ry < -h ? n : (ry >= h ? -n : 0);
+      rz += rz < -h ? n : (rz >= h ? -n : 0);
+      return ((rz + D) * W + (ry + D)) * W + (rx + D);
+    };
+    double acc = 0.0;
+    if (cls >= 0) {
+      const double* g = gcls + (size_t)cls * W * W * W;
+      for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
+        const int32_t P = coord(p);
+        for (int q = p + lane; q < m; q += 64) {
+          const double v = g[widx(P, coord(q))];
+          acc += (q == p) ? v : 2.0 * v;
         }
-        acc += (q == p) ? v : 2.0 * v;
+      }
+    } else {
+      double E[6];
+      for (int a = 0; a < 6; ++a) E[a] = defs[i].E[a];
+      for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
+        const int32_t P = coord(p);
+        for (int q = p + lane; q < m; q += 64) {
+          const double* k = K + (size_t)widx(P, coord(q)) * KWIN;
+          double v = 0.0;
+          for (int a = 0; a < 6; ++a) {
+            v += E[a] * E[a] * k[tri(a, a)];
+            for (int b = a + 1; b < 6; ++b) v += 2.0 * E[a] * E[b] * k[tri(a, b)];
+          }
+          acc += (q == p) ? v : 2.0 * v;
+        }
       }
     }
-  }
-  for (int s = 32; s > 0; s >>= 1) acc += __shfl_down(acc, s);
-  if (lane == 0) wsum[wave] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < ST / 64; ++w) t += wsum[w];
-    partial[blockIdx.x] = t;
+    for (int s = 32; s > 0; s >>= 1) acc += __shfl_down(acc, s);
+    if (lane == 0) wsum[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < ST / 64; ++w) t += wsum[w];
+      partial[wi] = t;
+    }
+    __syncthreads();  // pk and wsum are rewritten by the next item
   }
 }
 
 // B_i = -h^3 c s_i^2 sum(partials) (class windows hold the unit direction) or
 // -h^3 c sum(partials) (full-tensor path); partials added in a fixed order.
-__global__ void k_self_finish(const int32_t* __restrict__ wbeg, const double* __restrict__ partial,
+__global__ void k_self_finish(const int64_t* __restrict__ wbeg, const double* __restrict__ partial,
                               const DevDefect* __restrict__ defs, int ndef, double h3c, double* __restrict__ B) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ndef) return;
   double s = 0.0, c = 0.0;
-  for (int w = wbeg[i]; w < wbeg[i + 1]; ++w) neumaier(s, c, partial[w]);
+  for (int64_t w = wbeg[i]; w < wbeg[i + 1]; ++w) neumaier(s, c, partial[w]);
   const double scale = defs[i].cls >= 0 ? defs[i].s * defs[i].s : 1.0;
   B[i] = -h3c * scale * (s + c);
 }
@@ -212,11 +253,10 @@ __global__ void k_sig_to_out(const double* __restrict__ sig, const int64_t* __re
 
 }  // namespace
 
-hipError_t launch_reduce(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
-                         const int32_t* ids, const double* sig, int64_t n3, const double* B, double h3c, double* S6,
-                         double* E, hipStream_t s) {
+hipError_t launch_reduce(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, const double* sig,
+                         int64_t n3, const double* B, double h3c, double* S6, double* E, hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(ndef), dim3(RDT), 0, s, d, offsets, counts, ids, sig, n3, B, h3c, S6, E);
+  hipLaunchKernelGGL(k_reduce, dim3(ndef), dim3(RDT), 0, s, d, counts, ids, sig, n3, B, h3c, S6, E);
   return hipGetLastError();
 }
 
@@ -236,15 +276,19 @@ hipError_t launch_class_windows(const double* K, int D, const double* dirs, int 
   return hipGetLastError();
 }
 
-hipError_t launch_self_terms(const DevDefect* d, const int64_t* offsets, const int32_t* counts, const int32_t* ids,
-                             int n, const double* K, const double* gcls, int D, const SelfWork* work, int nwork,
-                             double* partial, const int32_t* work_begin, int ndef, double h3c, double* B,
-                             hipStream_t s) {
+hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int n,
+                             const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
+                             int32_t* wcnt, int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_self, dim3(nwork), dim3(ST), 0, s, d, offsets, counts, ids, n, K, gcls, D, work, partial);
-  hipError_t e = hipGetLastError();
+  const int g1 = (ndef + 255) / 256;
+  hipLaunchKernelGGL(k_self_count, dim3(g1), dim3(256), 0, s, counts, ndef, wcnt);
+  hipError_t e = launch_scan(wcnt, ndef, wbeg, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_self_finish, dim3((ndef + 255) / 256), dim3(256), 0, s, work_begin, partial, d, ndef, h3c, B);
+  hipLaunchKernelGGL(k_self_items, dim3(g1), dim3(256), 0, s, counts, ndef, wbeg, work, work_cap);
+  const int grid = (int)std::min<int64_t>(work_cap, 4096);
+  hipLaunchKernelGGL(k_self, dim3(grid), dim3(ST), 0, s, d, counts, ids, n, K, gcls, D, work, wbeg + ndef, work_cap,
+                     partial);
+  hipLaunchKernelGGL(k_self_finish, dim3(g1), dim3(256), 0, s, wbeg, partial, d, ndef, h3c, B);
   return hipGetLastError();
 }
 

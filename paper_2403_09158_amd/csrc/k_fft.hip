@@ -173,9 +173,11 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
 // z in [z_lo, z_lo+z_len) (cyclic); other rows are zero and never touched.
 template <int N, typename S>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_sparse(
-    const int32_t* __restrict__ old_ids, int old_cnt, const int32_t* __restrict__ new_ids, int new_cnt, int sx,
-    int sy, int sz, const double* __restrict__ E, typename Cplx<S>::T* __restrict__ spec, int P, int y_lo,
-    int y_len, int z_lo, const double2* __restrict__ twg) {
+    const int32_t* __restrict__ old_ids, const int32_t* __restrict__ old_cnt_p, const int32_t* __restrict__ new_ids,
+    int new_cnt, int sx, int sy, int sz, const double* __restrict__ E, typename Cplx<S>::T* __restrict__ spec, int P,
+    int y_lo, int y_len, int z_lo, const double2* __restrict__ twg) {
+  const int old_cnt = *old_cnt_p;
+  if (!new_ids) new_cnt = old_cnt;
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;
   constexpr int T = pick_T(max_nb(N, NF));
@@ -424,7 +426,7 @@ hipError_t go_xf(const int64_t* es, void* spec, SpecGeom g, const double2* tw, h
 }
 
 template <int N, typename S>
-hipError_t go_xfs(const int32_t* oi, int oc, const int32_t* ni, int nc, int sx, int sy, int sz, const double* E,
+hipError_t go_xfs(const int32_t* oi, const int32_t* oc, const int32_t* ni, int nc, int sx, int sy, int sz, const double* E,
                   void* spec, SpecGeom g, int ylo, int ylen, int zlo, int zlen, const double2* tw, hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   const int grid = zlen * ((ylen + x_rows(N) - 1) / x_rows(N));
@@ -505,7 +507,7 @@ hipError_t launch_x_forward(bool fp64, const int64_t* es, void* spec, SpecGeom g
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, int old_cnt, const int32_t* new_ids,
+hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, const int32_t* old_cnt, const int32_t* new_ids,
                                    int new_cnt, int sx, int sy, int sz, const double* E, void* spec, SpecGeom g,
                                    int y_lo, int y_len, int z_lo, int z_len, const double2* tw, hipStream_t s) {
   switch (g.n) {

@@ -15,38 +15,7 @@ namespace {
 
 constexpr int RT = 256;  // threads per rasteriser workgroup
 
-__device__ __forceinline__ void box_cell(const DevDefect& d, int n, int e, int& x, int& y, int& z) {
-  const int wxy = d.w[0] * d.w[1];
-  const int iz = e / wxy;
-  const int r = e - iz * wxy;
-  const int iy = r / d.w[0];
-  const int ix = r - iy * d.w[0];
-  x = box_axis(d.lo[0], d.w[0], n, ix);
-  y = box_axis(d.lo[1], d.w[1], n, iy);
-  z = box_axis(d.lo[2], d.w[2], n, iz);
-}
-
-__global__ __launch_bounds__(RT) void k_raster_count(const DevDefect* __restrict__ defs, int n,
-                                                     int32_t* __restrict__ counts) {
-  const DevDefect d = defs[blockIdx.x];
-  const int total = d.w[0] * d.w[1] * d.w[2];
-  int c = 0;
-  for (int e = threadIdx.x; e < total; e += RT) {
-    int x, y, z;
-    box_cell(d, n, e, x, y, z);
-    c += member(d, n, x, y, z) ? 1 : 0;
-  }
-  __shared__ int red[RT];
-  red[threadIdx.x] = c;
-  __syncthreads();
-  for (int s = RT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
-}
-
-// Exclusive scan of the counts into offsets[0..ndef]; one workgroup.
+// Exclusive scan of counts into offsets[0..ndef] (offsets[ndef] = total); one workgroup.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ counts, int ndef,
                                                int64_t* __restrict__ offsets) {
   __shared__ int64_t part[1024];
@@ -74,63 +43,91 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count
   }
 }
 
+__device__ __forceinline__ void add_fix(int64_t* es, size_t n3, int id, const int64_t* efix, int64_t sgn) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+    if (efix[c] != 0) atomicAdd((unsigned long long*)&es[c * n3 + id], (unsigned long long)(sgn * efix[c]));
+}
+
+// One workgroup per defect, one thread per bounding-box row (y, z) in ascending
+// order: the row's candidate x range comes from the geometry, each candidate is
+// tested exactly, a workgroup scan orders the rows, and every row writes its
+// members in ascending x.  The footprint list of the defect is therefore sorted.
 __global__ __launch_bounds__(RT) void k_raster_fill(const DevDefect* __restrict__ defs, int n,
-                                                    const int64_t* __restrict__ offsets, int32_t* __restrict__ ids,
+                                                    int32_t* __restrict__ ids, int32_t* __restrict__ counts,
                                                     int64_t* __restrict__ es) {
   const DevDefect d = defs[blockIdx.x];
-  const int total = d.w[0] * d.w[1] * d.w[2];
-  const int64_t base0 = offsets[blockIdx.x];
+  const int nrows = d.w[1] * d.w[2];
   const size_t n3 = (size_t)n * n * n;
   __shared__ int wsum[RT / 64];
-  __shared__ int64_t base_s;
-  if (threadIdx.x == 0) base_s = base0;
+  __shared__ int run;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) run = 0;
   __syncthreads();
-  for (int r0 = 0; r0 < total; r0 += RT) {
-    const int e = r0 + threadIdx.x;
-    int x = 0, y = 0, z = 0;
-    bool in = false;
-    if (e < total) {
-      box_cell(d, n, e, x, y, z);
-      in = member(d, n, x, y, z);
+  for (int r0 = 0; r0 < nrows; r0 += RT) {
+    const int r = r0 + threadIdx.x;
+    int y = 0, z = 0, u0 = 0, u1 = -1, cnt = 0;
+    if (r < nrows) {
+      const int iz = r / d.w[1], iy = r - iz * d.w[1];
+      y = box_axis(d.lo[1], d.w[1], n, iy);
+      z = box_axis(d.lo[2], d.w[2], n, iz);
+      if (row_range(d, n, y, z, u0, u1))
+        for (int u = u0; u <= u1; ++u) {
+          int x = d.lo[0] + u;
+          x -= x >= n ? n : 0;
+          cnt += member(d, n, x, y, z) ? 1 : 0;
+        }
     }
-    const unsigned long long mask = __ballot(in);
-    const int before = __popcll(mask & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[wave] = __popcll(mask);
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    int64_t pos = base_s + before;
-    int tot = 0;
+    int before = incl - cnt, tot = 0;
     for (int w = 0; w < RT / 64; ++w) {
-      if (w < wave) pos += wsum[w];
+      if (w < wave) before += wsum[w];
       tot += wsum[w];
     }
-    if (in) {
-      const int id = (z * n + y) * n + x;
-      ids[pos] = id;
-#pragma unroll
-      for (int c = 0; c < 6; ++c)
-        if (d.efix[c] != 0) atomicAdd((unsigned long long*)&es[c * n3 + id], (unsigned long long)d.efix[c]);
+    if (cnt > 0) {
+      int64_t pos = d.slot + run + before;
+      // candidates in ascending x: a range that wraps past n - 1 is emitted low part first
+      const int xa = d.lo[0] + u0, xb = d.lo[0] + u1;
+      const int segs = (xa < n && xb >= n) ? 2 : 1;
+      for (int sgi = 0; sgi < segs; ++sgi) {
+        int lo, hi;
+        if (segs == 2) {
+          lo = sgi == 0 ? 0 : xa;
+          hi = sgi == 0 ? xb - n : n - 1;
+        } else {
+          lo = xa >= n ? xa - n : xa;
+          hi = xb >= n ? xb - n : xb;
+        }
+        for (int x = lo; x <= hi; ++x)
+          if (member(d, n, x, y, z)) {
+            const int id = (z * n + y) * n + x;
+            ids[pos++] = id;
+            add_fix(es, n3, id, d.efix, 1);
+          }
+      }
     }
     __syncthreads();
-    if (threadIdx.x == 0) base_s += tot;
+    if (threadIdx.x == 0) run += tot;
     __syncthreads();
   }
+  if (threadIdx.x == 0) counts[blockIdx.x] = run;
 }
 
 // Remove the defects' contributions (exact inverse of the fill).
 __global__ __launch_bounds__(RT) void k_unraster(const DevDefect* __restrict__ defs,
-                                                 const int64_t* __restrict__ offsets,
                                                  const int32_t* __restrict__ counts, const int32_t* __restrict__ ids,
                                                  int64_t n3, int64_t* __restrict__ es) {
-  const DevDefect d = defs[blockIdx.x];
-  const int64_t o = offsets[blockIdx.x];
+  const int64_t o = defs[blockIdx.x].slot;
   const int cnt = counts[blockIdx.x];
-  for (int i = threadIdx.x; i < cnt; i += RT) {
-    const int id = ids[o + i];
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-      if (d.efix[c] != 0) atomicAdd((unsigned long long*)&es[c * n3 + id], (unsigned long long)(-d.efix[c]));
-  }
+  int64_t efix[6];
+  for (int c = 0; c < 6; ++c) efix[c] = defs[blockIdx.x].efix[c];
+  for (int i = threadIdx.x; i < cnt; i += RT) add_fix(es, n3, ids[o + i], efix, -1);
 }
 
 __device__ __forceinline__ int shift_id(int id, int sx, int sy, int sz, int n) {
@@ -143,29 +140,30 @@ __device__ __forceinline__ int shift_id(int id, int sx, int sy, int sz, int n) {
 
 // Move one defect in the fixed-point field: subtract on the old footprint, add
 // on the new one (new = old shifted by whole voxels when new_ids == nullptr).
+// Grid-stride over 2 * cap threads; the old count is read on the device.
 __global__ __launch_bounds__(RT) void k_update_es(const int64_t* __restrict__ efix, const int32_t* __restrict__ old_ids,
-                                                  int cnt_old, const int32_t* __restrict__ new_ids, int cnt_new,
-                                                  int sx, int sy, int sz, int n, int64_t* __restrict__ es) {
+                                                  const int32_t* __restrict__ cnt_old_p,
+                                                  const int32_t* __restrict__ new_ids, int cnt_new, int sx, int sy,
+                                                  int sz, int n, int64_t* __restrict__ es) {
   const size_t n3 = (size_t)n * n * n;
-  const int t = blockIdx.x * RT + threadIdx.x;
-  if (t < cnt_old) {
-    const int id = old_ids[t];
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-      if (efix[c] != 0) atomicAdd((unsigned long long*)&es[c * n3 + id], (unsigned long long)(-efix[c]));
-  } else if (t < cnt_old + cnt_new) {
-    const int i = t - cnt_old;
-    const int id = new_ids ? new_ids[i] : shift_id(old_ids[i], sx, sy, sz, n);
-#pragma unroll
-    for (int c = 0; c < 6; ++c)
-      if (efix[c] != 0) atomicAdd((unsigned long long*)&es[c * n3 + id], (unsigned long long)efix[c]);
+  const int cnt_old = *cnt_old_p;
+  const int nn = new_ids ? cnt_new : cnt_old;
+  int64_t f[6];
+  for (int c = 0; c < 6; ++c) f[c] = efix[c];
+  for (int t = blockIdx.x * RT + threadIdx.x; t < cnt_old + nn; t += gridDim.x * RT) {
+    if (t < cnt_old) {
+      add_fix(es, n3, old_ids[t], f, -1);
+    } else {
+      const int i = t - cnt_old;
+      add_fix(es, n3, new_ids ? new_ids[i] : shift_id(old_ids[i], sx, sy, sz, n), f, 1);
+    }
   }
 }
 
-__global__ __launch_bounds__(RT) void k_translate_ids(int32_t* __restrict__ ids, int cnt, int sx, int sy, int sz,
-                                                      int n) {
-  const int t = blockIdx.x * RT + threadIdx.x;
-  if (t < cnt) ids[t] = shift_id(ids[t], sx, sy, sz, n);
+__global__ __launch_bounds__(RT) void k_translate_ids(int32_t* __restrict__ ids, const int32_t* __restrict__ cnt_p,
+                                                      int sx, int sy, int sz, int n) {
+  const int cnt = *cnt_p;
+  for (int t = blockIdx.x * RT + threadIdx.x; t < cnt; t += gridDim.x * RT) ids[t] = shift_id(ids[t], sx, sy, sz, n);
 }
 
 // Additive constant of the stress for the xi = 0 condition.  Mean strain zero:
@@ -219,43 +217,35 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
 
 }  // namespace
 
-hipError_t launch_raster_count(const DevDefect* d, int ndef, int n, int32_t* counts, hipStream_t s) {
-  if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_raster_count, dim3(ndef), dim3(RT), 0, s, d, n, counts);
-  return hipGetLastError();
-}
-
 hipError_t launch_scan(const int32_t* counts, int ndef, int64_t* offsets, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, ndef, offsets);
   return hipGetLastError();
 }
 
-hipError_t launch_raster_fill(const DevDefect* d, int ndef, int n, const int64_t* offsets, int32_t* ids,
-                              int64_t* es, hipStream_t s) {
+hipError_t launch_raster_fill(const DevDefect* d, int ndef, int n, int32_t* ids, int32_t* counts, int64_t* es,
+                              hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_raster_fill, dim3(ndef), dim3(RT), 0, s, d, n, offsets, ids, es);
+  hipLaunchKernelGGL(k_raster_fill, dim3(ndef), dim3(RT), 0, s, d, n, ids, counts, es);
   return hipGetLastError();
 }
 
-hipError_t launch_unraster(const DevDefect* d, int ndef, const int64_t* offsets, const int32_t* counts,
-                           const int32_t* ids, int64_t n3, int64_t* es, hipStream_t s) {
+hipError_t launch_unraster(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int64_t n3,
+                           int64_t* es, hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unraster, dim3(ndef), dim3(RT), 0, s, d, offsets, counts, ids, n3, es);
+  hipLaunchKernelGGL(k_unraster, dim3(ndef), dim3(RT), 0, s, d, counts, ids, n3, es);
   return hipGetLastError();
 }
 
-hipError_t launch_update_es(const int64_t* efix, const int32_t* old_ids, int cnt_old, const int32_t* new_ids,
-                            int cnt_new, int sx, int sy, int sz, int n, int64_t* es, hipStream_t s) {
-  const int tot = cnt_old + cnt_new;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_update_es, dim3((tot + RT - 1) / RT), dim3(RT), 0, s, efix, old_ids, cnt_old, new_ids, cnt_new,
-                     sx, sy, sz, n, es);
+hipError_t launch_update_es(const int64_t* efix, const int32_t* old_ids, const int32_t* cnt_old,
+                            const int32_t* new_ids, int cnt_new, int sx, int sy, int sz, int n, int64_t* es,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_update_es, dim3(64), dim3(RT), 0, s, efix, old_ids, cnt_old, new_ids, cnt_new, sx, sy, sz, n,
+                     es);
   return hipGetLastError();
 }
 
-hipError_t launch_translate_ids(int32_t* ids, int cnt, int sx, int sy, int sz, int n, hipStream_t s) {
-  if (cnt == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_translate_ids, dim3((cnt + RT - 1) / RT), dim3(RT), 0, s, ids, cnt, sx, sy, sz, n);
+hipError_t launch_translate_ids(int32_t* ids, const int32_t* cnt, int sx, int sy, int sz, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_translate_ids, dim3(16), dim3(RT), 0, s, ids, cnt, sx, sy, sz, n);
   return hipGetLastError();
 }
 
