@@ -69,6 +69,7 @@ struct DefBuf {
   int32_t* cnt = nullptr;  // footprint counts, written by the rasteriser
   size_t cap = 0;
   int32_t* ids = nullptr;  // footprint slots; defect i owns [slot_i, slot_i + box volume)
+  int2* lnk = nullptr;     // per membership entry: {defect, next entry of the same voxel}
   int64_t ids_cap = 0;
 };
 
@@ -100,7 +101,7 @@ struct ec_state {
   double h3c = 0;
   size_t spec_bytes = 0, held = 0;
   void* spec = nullptr;
-  int64_t* es = nullptr;
+  int32_t* own = nullptr;  // per-voxel head of the membership list
   double* sig = nullptr;
   double* add6 = nullptr;  // [0..6) additive stress of the full solve, [6..12) zeros, [12..18) update delta
   double2* tw = nullptr;
@@ -470,13 +471,14 @@ double spec_valid_bytes(const ec_state* st, bool fp64) {
   return 6.0 * st->n * st->n * (st->n / 2 + 1) * (fp64 ? 16.0 : 8.0);
 }
 
-ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int64_t* es, void* spec, double* sig,
-                   const double* add6) {
+ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs,
+                   void* spec, double* sig, const double* add6) {
   const Prune full{0, st->n, 0, st->n};
   const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
   SpecGeom g{st->n, 0};
   g.P = fp64 ? ((st->n / 2 + 1 + 7) / 8) * 8 : ((st->n / 2 + 1 + 15) / 16) * 16;
-  LAUNCH(st, s, PF_XF, fb + sb, launch_x_forward(fp64, es, spec, g, st->tw, s));
+  LAUNCH(st, s, PF_XF, 4.0 * (double)st->n3 + sb,
+         launch_x_forward(fp64, own, lnk, defs, nullptr, spec, g, st->tw, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, false, 1, spec, g, full, st->tw, s));
   LAUNCH(st, s, PF_Z, 2 * sb, launch_pencil(fp64, false, 2, spec, g, full, st->tw, s));
   LAUNCH(st, s, PF_Z, 2 * sb, launch_green(fp64, spec, g, st->C, s));
@@ -505,17 +507,20 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
   const int P64 = ((n / 2 + 1 + 7) / 8) * 8;
   const size_t sp64 = (size_t)6 * n * n * P64 * sizeof(double2);
   const size_t fbytes = (size_t)6 * st->n3 * 8;
-  void *K = nullptr, *es = nullptr, *sp = nullptr, *sg = nullptr, *ad = nullptr;
+  void *K = nullptr, *own = nullptr, *sp = nullptr, *sg = nullptr, *ad = nullptr, *imp = nullptr;
+  const size_t ownbytes = (size_t)st->n3 * 4;
   ec_status r;
   if ((r = ledger_alloc(c, Kbytes, &K)) != EC_OK) return r;
   auto cleanup = [&]() {
-    ledger_free(c, es, fbytes);
+    ledger_free(c, own, ownbytes);
+    ledger_free(c, imp, 6 * sizeof(DevDefect) + 64);
     ledger_free(c, sp, sp64);
     ledger_free(c, sg, fbytes);
     ledger_free(c, ad, 6 * 64);
   };
-  if ((r = ledger_alloc(c, fbytes, &es)) != EC_OK || (r = ledger_alloc(c, sp64, &sp)) != EC_OK ||
-      (r = ledger_alloc(c, fbytes, &sg)) != EC_OK || (r = ledger_alloc(c, 6 * 64, &ad)) != EC_OK) {
+  if ((r = ledger_alloc(c, ownbytes, &own)) != EC_OK || (r = ledger_alloc(c, sp64, &sp)) != EC_OK ||
+      (r = ledger_alloc(c, fbytes, &sg)) != EC_OK || (r = ledger_alloc(c, 6 * 64, &ad)) != EC_OK ||
+      (r = ledger_alloc(c, 6 * sizeof(DevDefect) + 64, &imp)) != EC_OK) {
     cleanup();
     ledger_free(c, K, Kbytes);
     return r;
@@ -534,14 +539,20 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
         add[b][2] = -(st->C.C11 * m[2] + st->C.C12 * (m[0] + m[1]));
         for (int a = 3; a < 6; ++a) add[b][a] = -2.0 * st->C.C44 * m[a];
       }
+    // six one-voxel "defects" with unit eigenstrain component b at voxel 0
+    DevDefect unit[6];
+    std::memset(unit, 0, sizeof unit);
+    for (int b = 0; b < 6; ++b) unit[b].efix[b] = (int64_t)FIX_SCALE;
+    DevDefect* dunit = (DevDefect*)imp;
+    int2* dlnk = (int2*)((char*)imp + 6 * sizeof(DevDefect));
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(hipMemcpy(ad, add, sizeof add, hipMemcpyHostToDevice));
-    HIPCHK(launch_fill_i64((int64_t*)es, 6 * st->n3, 0, s));
+    HIPCHK(hipMemcpy(dunit, unit, sizeof unit, hipMemcpyHostToDevice));
+    HIPCHK(launch_fill_i32((int32_t*)own, st->n3, -1, s));
     HIPCHK(hipMemsetAsync(K, 0, Kbytes, s));
     for (int b = 0; b < 6; ++b) {
-      if (b > 0) HIPCHK(launch_fill_i64((int64_t*)es + (b - 1) * st->n3, 1, 0, s));
-      HIPCHK(launch_fill_i64((int64_t*)es + b * st->n3, 1, (int64_t)FIX_SCALE, s));
-      ec_status q = pipeline(st, s, true, (const int64_t*)es, sp, (double*)sg, (const double*)ad + 8 * b);
+      HIPCHK(launch_fill_i32((int32_t*)own, 1, b, s));  // voxel 0 owned by unit defect b
+      ec_status q = pipeline(st, s, true, (const int32_t*)own, dlnk, dunit, sp, (double*)sg, (const double*)ad + 8 * b);
       if (q != EC_OK) return q;
       HIPCHK(launch_window_crop((const double*)sg, n, D, b, (double*)K, s));
     }
@@ -651,13 +662,16 @@ ec_status write_field(ec_state* st, int which, void* out, bool on_device, hipStr
   const bool f32 = !st->fp64;
   const size_t bytes = (size_t)6 * st->n3 * (f32 ? 4 : 8);
   if (on_device) {
-    LAUNCH(st, s, PF_OTHER, 96.0 * st->n3, launch_sig_to_out(st->sig, st->es, st->n3, st->C, which, f32, out, s));
+    const DefBuf& b = st->db[st->cur];
+    LAUNCH(st, s, PF_OTHER, 96.0 * st->n3,
+           launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, which, f32, out, s));
     return EC_OK;
   }
   void* tmp = nullptr;
   ec_status r = ledger_alloc(st->ctx, bytes, &tmp);
   if (r != EC_OK) return r;
-  hipError_t e = launch_sig_to_out(st->sig, st->es, st->n3, st->C, which, f32, tmp, s);
+  const DefBuf& b = st->db[st->cur];
+  hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, which, f32, tmp, s);
   if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   ledger_free(st->ctx, tmp, bytes);
@@ -816,18 +830,19 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
     delete st;
     return fail(EC_ERR_DEVICE, "twiddle table allocation failed");
   }
-  void *sp = nullptr, *es = nullptr, *sg = nullptr, *ad = nullptr, *dirs = nullptr, *ue = nullptr, *uf = nullptr;
+  void *sp = nullptr, *own = nullptr, *sg = nullptr, *ad = nullptr, *dirs = nullptr, *ue = nullptr, *uf = nullptr;
+  const size_t ob = (size_t)st->n3 * 4;
   ec_status r;
   auto undo = [&]() {
     ledger_free(c, sp, st->spec_bytes);
-    ledger_free(c, es, fb);
+    ledger_free(c, own, ob);
     ledger_free(c, sg, fb);
     ledger_free(c, ad, 256);
     ledger_free(c, dirs, MAXCLS * 48);
     ledger_free(c, ue, 64);
     ledger_free(c, uf, 64);
   };
-  if ((r = ledger_alloc(c, st->spec_bytes, &sp)) != EC_OK || (r = ledger_alloc(c, fb, &es)) != EC_OK ||
+  if ((r = ledger_alloc(c, st->spec_bytes, &sp)) != EC_OK || (r = ledger_alloc(c, ob, &own)) != EC_OK ||
       (r = ledger_alloc(c, fb, &sg)) != EC_OK || (r = ledger_alloc(c, 256, &ad)) != EC_OK ||
       (r = ledger_alloc(c, MAXCLS * 48, &dirs)) != EC_OK || (r = ledger_alloc(c, 64, &ue)) != EC_OK ||
       (r = ledger_alloc(c, 64, &uf)) != EC_OK) {
@@ -836,14 +851,14 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
     return r;
   }
   st->spec = sp;
-  st->es = (int64_t*)es;
+  st->own = (int32_t*)own;
   st->sig = (double*)sg;
   st->add6 = (double*)ad;
   st->dirs = (double*)dirs;
   st->updE = (double*)ue;
   st->updfix = (int64_t*)uf;
-  st->held = st->spec_bytes + 2 * fb + 256 + MAXCLS * 48 + 128;
-  hipError_t e = launch_fill_i64(st->es, 6 * st->n3, 0, nullptr);
+  st->held = st->spec_bytes + fb + ob + 256 + MAXCLS * 48 + 128;
+  hipError_t e = launch_fill_i32(st->own, st->n3, -1, nullptr);
   if (e == hipSuccess) e = hipMemset(st->sig, 0, fb);
   if (e == hipSuccess) e = hipMemset(st->add6, 0, 256);
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -862,7 +877,7 @@ void ec_state_destroy(ec_state* st) {
   (void)hipDeviceSynchronize();
   const size_t fb = (size_t)6 * st->n3 * 8;
   ledger_free(c, st->spec, st->spec_bytes);
-  ledger_free(c, st->es, fb);
+  ledger_free(c, st->own, (size_t)st->n3 * 4);
   ledger_free(c, st->sig, fb);
   ledger_free(c, st->add6, 256);
   ledger_free(c, st->dirs, MAXCLS * 48);
@@ -872,6 +887,7 @@ void ec_state_destroy(ec_state* st) {
     ledger_free(c, b.tab, b.cap * sizeof(DevDefect));
     ledger_free(c, b.cnt, b.cap * 4);
     ledger_free(c, b.ids, b.ids_cap * 4);
+    ledger_free(c, b.lnk, b.ids_cap * 8);
   }
   ledger_free(c, st->B, st->pd_cap * 8);
   ledger_free(c, st->E, st->pd_cap * 8);
@@ -923,13 +939,14 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   }
   DefBuf& nb = st->db[1 - st->cur];
   ec_status r;
-  size_t idcap = (size_t)nb.ids_cap;
+  size_t idcap = (size_t)nb.ids_cap, lkcap = (size_t)nb.ids_cap;
+  const size_t need = (size_t)std::max<int64_t>(total, 1);
   if ((r = ensure_defbuf(st, nb, ndef)) != EC_OK || (r = ensure_per_defect(st, ndef)) != EC_OK ||
-      (r = st_grow(st, &nb.ids, &idcap, (size_t)std::max<int64_t>(total, 1))) != EC_OK) {
+      (r = st_grow(st, &nb.ids, &idcap, need)) != EC_OK || (r = st_grow(st, &nb.lnk, &lkcap, need)) != EC_OK) {
     st->classes = old_classes;
     return r;
   }
-  nb.ids_cap = (int64_t)idcap;
+  nb.ids_cap = (int64_t)std::min(idcap, lkcap);
   if (ndef > 0) {
     char* hp = nullptr;
     if ((r = pin_begin(st->pin_tab, ndef * sizeof(DevDefect), &hp)) != EC_OK) return r;
@@ -940,8 +957,8 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   // 3. commit: remove the old eigenstrain, add the new one
   const DefBuf& ob = st->db[st->cur];
   if (st->ndef > 0)
-    LAUNCH(st, s, PF_RASTER, 0, launch_unraster(ob.tab, st->ndef, ob.cnt, ob.ids, st->n3, st->es, s));
-  LAUNCH(st, s, PF_RASTER, 0, launch_raster_fill(nb.tab, ndef, st->n, nb.ids, nb.cnt, st->es, s));
+    LAUNCH(st, s, PF_RASTER, 0, launch_unraster(ob.tab, st->ndef, ob.cnt, ob.ids, st->own, s));
+  LAUNCH(st, s, PF_RASTER, 0, launch_raster_fill(nb.tab, ndef, st->n, nb.ids, nb.lnk, nb.cnt, st->own, s));
   st->cur = 1 - st->cur;
   st->hdefs.swap(h);
   st->hcap.swap(cap);
@@ -953,7 +970,7 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   LAUNCH(st, s, PF_OTHER, 0,
          launch_mean_stress(nb.tab, nb.cnt, ndef, st->n3, st->C, st->prob.bc, st->add6, s));
   // 4. Fourier solve
-  r = pipeline(st, s, st->fp64, st->es, st->spec, st->sig, st->add6);
+  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6);
   if (r != EC_OK) return r;
   st->solved = true;
   if (eps_out && (r = write_field(st, 1, eps_out, on_device != 0, s)) != EC_OK) return r;
@@ -1030,12 +1047,14 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
     if (cnt_new > st->hcap[idx]) {  // does not fit the old slot: take a new one at the end
       nd.slot = st->ids_used;
       cap_new = box_volume(nd);
-      size_t icap = (size_t)b.ids_cap;
-      if ((r = st_grow(st, &b.ids, &icap, (size_t)(st->ids_used + cap_new), true, s)) != EC_OK) {
+      size_t icap = (size_t)b.ids_cap, lcap = (size_t)b.ids_cap;
+      const size_t need = (size_t)(st->ids_used + cap_new);
+      if ((r = st_grow(st, &b.ids, &icap, need, true, s)) != EC_OK ||
+          (r = st_grow(st, &b.lnk, &lcap, need, true, s)) != EC_OK) {
         st->classes.resize(ncls_before);
         return r;
       }
-      b.ids_cap = (int64_t)icap;
+      b.ids_cap = (int64_t)std::min(icap, lcap);
     }
   }
   // rows of the eigenstrain change
@@ -1075,8 +1094,6 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
   const int32_t* oids = b.ids + od.slot;
   const int32_t* ocnt = b.cnt + idx;
   const int32_t* nids = hop ? nullptr : st->upd_ids;
-  LAUNCH(st, s, PF_RASTER, 0,
-         launch_update_es(st->updfix, oids, ocnt, nids, cnt_new, sh[0], sh[1], sh[2], n, st->es, s));
   {
     const bool fp64 = st->fp64;
     const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
@@ -1095,12 +1112,12 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
     LAUNCH(st, s, PF_XI, sb + 2 * fb,
            launch_x_inverse(fp64, true, st->spec, st->sig, st->g, st->add6 + 12, st->tw, s));
   }
-  // footprint bookkeeping
-  if (hop) {
-    LAUNCH(st, s, PF_OTHER, 0, launch_translate_ids(b.ids + od.slot, ocnt, sh[0], sh[1], sh[2], n, s));
-  } else {
-    if (cnt_new > 0)
-      HIPCHK(hipMemcpyAsync(b.ids + nd.slot, st->upd_ids, cnt_new * 4, hipMemcpyDeviceToDevice, s));
+  // membership lists and footprint ids of the moved defect (after the sparse
+  // forward pass, which still reads the old footprint)
+  LAUNCH(st, s, PF_RASTER, 0,
+         launch_move_lists(idx, ocnt, od.slot, nids, cnt_new, nd.slot, sh[0], sh[1], sh[2], n, b.ids, b.lnk, st->own,
+                           s));
+  if (!hop) {
     HIPCHK(hipMemcpyAsync(b.cnt + idx, up + 144, 4, hipMemcpyHostToDevice, s));
     if (nd.slot != od.slot) {
       st->ids_used += cap_new;
@@ -1149,14 +1166,20 @@ ec_status ec_state_field(ec_state* st, int32_t which, double* out) {
     void* tmp = nullptr;
     ec_status r = ledger_alloc(st->ctx, cnt * 8, &tmp);
     if (r != EC_OK) return r;
-    hipError_t e = launch_sig_to_out(st->sig, st->es, st->n3, st->C, 1, false, tmp, nullptr);
+    const DefBuf& b = st->db[st->cur];
+    hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, 1, false, tmp, nullptr);
     if (e == hipSuccess) e = hipMemcpy(out, tmp, cnt * 8, hipMemcpyDeviceToHost);
     ledger_free(st->ctx, tmp, cnt * 8);
     if (e != hipSuccess) return fail(EC_ERR_DEVICE, "strain output: %s", hipGetErrorString(e));
   } else if (which == 2) {
-    std::vector<int64_t> tmp(cnt);
-    HIPCHK(hipMemcpy(tmp.data(), st->es, cnt * 8, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < cnt; ++i) out[i] = (double)tmp[i] * FIX_INV;
+    void* tmp = nullptr;
+    ec_status r = ledger_alloc(st->ctx, cnt * 8, &tmp);
+    if (r != EC_OK) return r;
+    const DefBuf& b = st->db[st->cur];
+    hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, 2, false, tmp, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, tmp, cnt * 8, hipMemcpyDeviceToHost);
+    ledger_free(st->ctx, tmp, cnt * 8);
+    if (e != hipSuccess) return fail(EC_ERR_DEVICE, "eigenstrain output: %s", hipGetErrorString(e));
   } else {
     return fail(EC_ERR_ARG, "unknown field %d", which);
   }
@@ -1244,15 +1267,13 @@ struct Tmp {
 ec_status ec_debug_forward(ec_state* st, const double* field, double* out) {
   if (!st || !field || !out) return fail(EC_ERR_ARG, "NULL argument");
   const size_t cnt = (size_t)6 * st->n3;
-  Tmp es{st->ctx}, sp{st->ctx};
+  Tmp fd{st->ctx}, sp{st->ctx};
   ec_status r;
-  if ((r = ledger_alloc(st->ctx, es.b = cnt * 8, &es.p)) != EC_OK) return r;
+  if ((r = ledger_alloc(st->ctx, fd.b = cnt * 8, &fd.p)) != EC_OK) return r;
   if ((r = ledger_alloc(st->ctx, sp.b = st->spec_bytes, &sp.p)) != EC_OK) return r;
-  std::vector<int64_t> fx(cnt);
-  for (size_t i = 0; i < cnt; ++i) fx[i] = (int64_t)std::llrint(field[i] * FIX_SCALE);
-  HIPCHK(hipMemcpy(es.p, fx.data(), cnt * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(fd.p, field, cnt * 8, hipMemcpyHostToDevice));
   const Prune full{0, st->n, 0, st->n};
-  HIPCHK(launch_x_forward(st->fp64, (const int64_t*)es.p, sp.p, st->g, st->tw, nullptr));
+  HIPCHK(launch_x_forward(st->fp64, nullptr, nullptr, nullptr, (const double*)fd.p, sp.p, st->g, st->tw, nullptr));
   HIPCHK(launch_pencil(st->fp64, false, 1, sp.p, st->g, full, st->tw, nullptr));
   HIPCHK(launch_pencil(st->fp64, false, 2, sp.p, st->g, full, st->tw, nullptr));
   HIPCHK(hipDeviceSynchronize());

@@ -12,10 +12,40 @@ namespace ec {
 
 constexpr int QSUB = 1024;  // coordinate quantisation steps per voxel edge (q = h/1024)
 
-// The eigenstrain field is held as int64 fixed point with 56 fractional bits:
-// contributions add and subtract exactly and in any order, so rasterisation is
-// deterministic and an incremental move restores untouched voxels bit for bit.
-// |sum of overlapping components| must stay below 128.
+// Eigenstrain components are int64 fixed point with 56 fractional bits: the
+// contributions of overlapping defects add exactly and in any order, so the
+// field is deterministic and an incremental move restores untouched voxels bit
+// for bit.  |sum of overlapping components| must stay below 128.
+//
+// The field itself is not stored densely.  Every voxel keeps a link own[v]:
+//   -1        no defect covers the voxel;
+//   d >= 0    defect d (and nothing further);
+//   -2 - e    membership entry e (its position in the footprint-id buffer),
+//             whose record lnk[e] = {defect, link} continues with a link of the
+//             same three forms.
+// The first defect to reach a voxel stores itself with one compare-and-swap;
+// later ones push an entry with an exchange.  Decoding sums the owners'
+// fixed-point components, so the order of the chain does not matter.
+__host__ __device__ constexpr int32_t entry_link(int64_t e) { return (int32_t)(-2 - e); }
+
+template <class Defs>
+__device__ __forceinline__ void decode_voxel(int32_t link, const int2* __restrict__ lnk, const Defs& defs,
+                                             int64_t* acc) {
+  for (int guard = 0; guard < 4096 && link != -1; ++guard) {
+    int d;
+    if (link >= 0) {
+      d = link;
+      link = -1;
+    } else {
+      const int2 L = lnk[-2 - link];
+      d = L.x;
+      link = L.y;
+    }
+    const int64_t* f = defs[d].efix;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += f[c];
+  }
+}
 constexpr double FIX_SCALE = 72057594037927936.0;  // 2^56
 constexpr double FIX_INV = 1.0 / 72057594037927936.0;
 
@@ -173,7 +203,10 @@ struct Prune {
 bool fft_supported(int n);
 int pencil_width(int n, bool fp64);
 
-hipError_t launch_x_forward(bool fp64, const int64_t* es, void* spec, SpecGeom g, const double2* tw, hipStream_t s);
+// Owner-list input (own/lnk/defs) or, when dense != nullptr, a dense FP64
+// [6][n^3] field (kernel-level tests).
+hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs, const double* dense,
+                            void* spec, SpecGeom g, const double2* tw, hipStream_t s);
 hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, const int32_t* old_cnt, const int32_t* new_ids,
                                    int new_cnt,
                                    int shift_x, int shift_y, int shift_z, const double* E, void* spec, SpecGeom g,
@@ -187,17 +220,18 @@ hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig
 
 // ---- k_raster.hip / k_energy.hip -----------------------------------------------
 
-hipError_t launch_raster_fill(const DevDefect* d, int ndef, int n, int32_t* ids, int32_t* counts, int64_t* es,
-                              hipStream_t s);
-hipError_t launch_unraster(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int64_t n3,
-                           int64_t* es, hipStream_t s);
-// One defect moved: old footprint ids[old_slot .. + *cnt_old) (device count),
-// new footprint = old shifted by whole voxels (new_ids == nullptr) or new_ids[0 .. cnt_new).
-hipError_t launch_update_es(const int64_t* efix, const int32_t* old_ids, const int32_t* cnt_old,
-                            const int32_t* new_ids, int cnt_new, int shift_x, int shift_y, int shift_z, int n,
-                            int64_t* es, hipStream_t s);
-hipError_t launch_translate_ids(int32_t* ids, const int32_t* cnt, int shift_x, int shift_y, int shift_z, int n,
-                                hipStream_t s);
+hipError_t launch_raster_fill(const DevDefect* d, int ndef, int n, int32_t* ids, int2* lnk, int32_t* counts,
+                              int32_t* own, hipStream_t s);
+// Empty the membership lists of every voxel of every listed footprint.
+hipError_t launch_unraster(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int32_t* own,
+                           hipStream_t s);
+// One defect moved: unlink its old entries [slot, slot + *cnt_old), then link
+// the new ones (new voxel = old shifted by whole voxels when new_ids ==
+// nullptr, else new_ids[0 .. cnt_new) copied into [new_slot, ...)).
+hipError_t launch_move_lists(int def, const int32_t* cnt_old, int64_t old_slot, const int32_t* new_ids, int cnt_new,
+                             int64_t new_slot, int shift_x, int shift_y, int shift_z, int n, int32_t* ids, int2* lnk,
+                             int32_t* own, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 hipError_t launch_mean_stress(const DevDefect* d, const int32_t* counts, int ndef, int64_t n3, Cubic C, int bc,
                               double* add6, hipStream_t s);
 hipError_t launch_scan(const int32_t* counts, int ndef, int64_t* offsets, hipStream_t s);
@@ -215,8 +249,9 @@ struct SelfWork {
 hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int n,
                              const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
                              int32_t* wcnt, int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s);
-hipError_t launch_sig_to_out(const double* sig, const int64_t* es, int64_t n3, Cubic C, int which, bool fp32,
-                             void* out, hipStream_t s);
+// which 0: sigma, 1: eps = C^-1:sigma + eps*, 2: eps* alone; out is float or double.
+hipError_t launch_sig_to_out(const double* sig, const int32_t* own, const int2* lnk, const DevDefect* defs, int64_t n3,
+                             Cubic C, int which, bool fp32, void* out, hipStream_t s);
 
 constexpr int KWIN = 24;  // doubles per window point (21 used: the symmetric 6x6 kernel)
 

@@ -226,12 +226,24 @@ __global__ void k_self_finish(const int64_t* __restrict__ wbeg, const double* __
   B[i] = -h3c * scale * (s + c);
 }
 
-// Dense outputs: which 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic compliance).
+// Dense outputs: which 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic
+// compliance), 2 -> eps* (owner-list gather).
 template <typename OT>
-__global__ void k_sig_to_out(const double* __restrict__ sig, const int64_t* __restrict__ es, int64_t n3, Cubic C,
+__global__ void k_sig_to_out(const double* __restrict__ sig, const int32_t* __restrict__ own,
+                             const int2* __restrict__ lnk, const DevDefect* __restrict__ defs, int64_t n3, Cubic C,
                              int which, OT* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n3) return;
+  double es[6] = {0, 0, 0, 0, 0, 0};
+  if (which > 0) {
+    int64_t acc[6] = {0, 0, 0, 0, 0, 0};
+    decode_voxel(own[t], lnk, defs, acc);
+    for (int c = 0; c < 6; ++c) es[c] = (double)acc[c] * FIX_INV;
+  }
+  if (which == 2) {
+    for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)es[a];
+    return;
+  }
   double s[6];
 #pragma unroll
   for (int a = 0; a < 6; ++a) s[a] = sig[a * n3 + t];
@@ -248,7 +260,7 @@ __global__ void k_sig_to_out(const double* __restrict__ sig, const int64_t* __re
   e[2] = S11 * s[2] + S12 * (s[0] + s[1]);
   for (int a = 3; a < 6; ++a) e[a] = S44h * s[a];
 #pragma unroll
-  for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)(e[a] + (double)es[a * n3 + t] * FIX_INV);
+  for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)(e[a] + es[a]);
 }
 
 }  // namespace
@@ -292,13 +304,15 @@ hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts
   return hipGetLastError();
 }
 
-hipError_t launch_sig_to_out(const double* sig, const int64_t* es, int64_t n3, Cubic C, int which, bool fp32,
-                             void* out, hipStream_t s) {
+hipError_t launch_sig_to_out(const double* sig, const int32_t* own, const int2* lnk, const DevDefect* defs, int64_t n3,
+                             Cubic C, int which, bool fp32, void* out, hipStream_t s) {
   const unsigned grid = (unsigned)((n3 + 255) / 256);
   if (fp32)
-    hipLaunchKernelGGL(k_sig_to_out<float>, dim3(grid), dim3(256), 0, s, sig, es, n3, C, which, (float*)out);
+    hipLaunchKernelGGL(k_sig_to_out<float>, dim3(grid), dim3(256), 0, s, sig, own, lnk, defs, n3, C, which,
+                       (float*)out);
   else
-    hipLaunchKernelGGL(k_sig_to_out<double>, dim3(grid), dim3(256), 0, s, sig, es, n3, C, which, (double*)out);
+    hipLaunchKernelGGL(k_sig_to_out<double>, dim3(grid), dim3(256), 0, s, sig, own, lnk, defs, n3, C, which,
+                       (double*)out);
   return hipGetLastError();
 }
 

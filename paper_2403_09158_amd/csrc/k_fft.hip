@@ -27,7 +27,7 @@ constexpr int pencil_W_of(int N) { return N >= 512 ? 8 : 16; }
 constexpr int x_rows(int N) {
   int best = 1;
   for (int r = 1; r <= N; ++r)
-    if (N % r == 0 && 3 * r * N <= 3072) best = r;
+    if (N % r == 0 && 3 * r * N <= 1536) best = r;
   return best;
 }
 
@@ -127,9 +127,10 @@ __device__ __forceinline__ void green_bin(double2* e, int kx, int ky, int kz, in
 
 // ----------------------------------------------------------------- x forward (R2C)
 
-template <int N, typename S>
+template <int N, typename S, bool DENSE>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
-    const int64_t* __restrict__ es, typename Cplx<S>::T* __restrict__ spec, int P, const double2* __restrict__ twg) {
+    const int32_t* __restrict__ own, const int2* __restrict__ lnk, const DevDefect* __restrict__ defs,
+    const double* __restrict__ dense, typename Cplx<S>::T* __restrict__ spec, int P, const double2* __restrict__ twg) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;  // (xx,yy), (zz,yz), (xz,xy) per row
   constexpr int T = pick_T(max_nb(N, NF));
@@ -143,16 +144,44 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   const int y0 = (blockIdx.x % bpp) * ROWS;
   const size_t n3 = (size_t)N * N * N;
   const size_t cs = (size_t)N * N * P;
-  __syncthreads();
-  auto load0 = [&](int f, int x) -> double2 {
-    const int p = f % 3, y = y0 + f / 3;
-    const size_t o = ((size_t)z * N + y) * N + x;
-    return make_double2((double)es[(2 * p) * n3 + o] * FIX_INV, (double)es[(2 * p + 1) * n3 + o] * FIX_INV);
-  };
   auto lds = [&](int f, int i) -> double2& { return buf[f * LDN + i + (i >> 4)]; };
+  // gather the rows' six components into the transform inputs (xx + i yy, ...);
+  // all of a thread's voxel links are loaded first, then the owners' records
+  constexpr int KV = (ROWS * N + T - 1) / T;
+  int32_t link[KV];
+#pragma unroll
+  for (int k = 0; k < KV; ++k) {
+    const int i = threadIdx.x + k * T;
+    link[k] = -1;
+    if (!DENSE && i < ROWS * N) {
+      const int r = i / N, x = i - r * N;
+      link[k] = own[((size_t)z * N + y0 + r) * N + x];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KV; ++k) {
+    const int i = threadIdx.x + k * T;
+    if (i < ROWS * N) {
+      const int r = i / N, x = i - r * N;
+      double e[6];
+      if (DENSE) {
+        const size_t v = ((size_t)z * N + y0 + r) * N + x;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) e[c] = dense[c * n3 + v];
+      } else {
+        int64_t acc[6] = {0, 0, 0, 0, 0, 0};
+        decode_voxel(link[k], lnk, defs, acc);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) e[c] = (double)acc[c] * FIX_INV;
+      }
+#pragma unroll
+      for (int p = 0; p < 3; ++p) lds(3 * r + p, x) = make_double2(e[2 * p], e[2 * p + 1]);
+    }
+  }
+  __syncthreads();
   auto from_lds = [&](int f, int i) { return lds(f, i); };
   auto to_lds = [&](int f, int i, double2 v) { lds(f, i) = v; };
-  transform<N, false, Map::Row, NF, T, false, true>(tw, load0, from_lds, to_lds, to_lds);
+  transform<N, false, Map::Row, NF, T, true, true>(tw, from_lds, from_lds, to_lds, to_lds);
   __syncthreads();
   for (int e = threadIdx.x; e < NF * NH; e += T) {
     const int f = e / NH, k = e % NH;
@@ -418,10 +447,16 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
 // ------------------------------------------------------------------ launchers
 
 template <int N, typename S>
-hipError_t go_xf(const int64_t* es, void* spec, SpecGeom g, const double2* tw, hipStream_t s) {
+hipError_t go_xf(const int32_t* own, const int2* lnk, const DevDefect* defs, const double* dense, void* spec,
+                 SpecGeom g, const double2* tw, hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   const int grid = N * (N / x_rows(N));
-  hipLaunchKernelGGL((k_x_forward<N, S>), dim3(grid), dim3(T), 0, s, es, (typename Cplx<S>::T*)spec, g.P, tw);
+  using C2 = typename Cplx<S>::T;
+  if (dense)
+    hipLaunchKernelGGL((k_x_forward<N, S, true>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P, tw);
+  else
+    hipLaunchKernelGGL((k_x_forward<N, S, false>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P,
+                       tw);
   return hipGetLastError();
 }
 
@@ -496,11 +531,13 @@ bool fft_supported(int n) {
 
 int pencil_width(int n, bool) { return n >= 512 ? 8 : 16; }
 
-hipError_t launch_x_forward(bool fp64, const int64_t* es, void* spec, SpecGeom g, const double2* tw, hipStream_t s) {
+hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs, const double* dense,
+                            void* spec, SpecGeom g, const double2* tw, hipStream_t s) {
   switch (g.n) {
-#define EC_CASE(NN) \
-  case NN:          \
-    return fp64 ? go_xf<NN, double>(es, spec, g, tw, s) : go_xf<NN, float>(es, spec, g, tw, s);
+#define EC_CASE(NN)                                                           \
+  case NN:                                                                    \
+    return fp64 ? go_xf<NN, double>(own, lnk, defs, dense, spec, g, tw, s) \
+                : go_xf<NN, float>(own, lnk, defs, dense, spec, g, tw, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }

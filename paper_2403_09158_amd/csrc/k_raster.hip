@@ -2,11 +2,11 @@
 //
 // Sec. 3.1: loop eigenstrain sym(b x n)/e over a slab of thickness e around the
 // loop disk; point-defect clusters as dilatational spheres.  Sec. 3.4: fields
-// live at voxel centres h (m + 1/2).  One workgroup per defect enumerates the
-// defect's bounding box in ascending voxel-id order, tests membership in exact
-// integer arithmetic, compacts the members with a workgroup prefix sum (so the
-// footprint list is sorted) and adds the fixed-point eigenstrain with integer
-// atomics (exact and order independent, so overlaps are deterministic).
+// live at voxel centres h (m + 1/2).  One workgroup per defect walks the
+// defect's bounding box row by row in ascending voxel-id order, tests
+// membership in exact integer arithmetic, compacts the members with a
+// workgroup prefix sum (so the footprint list is sorted) and pushes every
+// membership onto its voxel's list with one 32-bit atomic exchange.
 #include "ec_internal.h"
 
 namespace ec {
@@ -43,22 +43,15 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count
   }
 }
 
-__device__ __forceinline__ void add_fix(int64_t* es, size_t n3, int id, const int64_t* efix, int64_t sgn) {
-#pragma unroll
-  for (int c = 0; c < 6; ++c)
-    if (efix[c] != 0) atomicAdd((unsigned long long*)&es[c * n3 + id], (unsigned long long)(sgn * efix[c]));
-}
-
 // One workgroup per defect, one thread per bounding-box row (y, z) in ascending
 // order: the row's candidate x range comes from the geometry, each candidate is
 // tested exactly, a workgroup scan orders the rows, and every row writes its
 // members in ascending x.  The footprint list of the defect is therefore sorted.
 __global__ __launch_bounds__(RT) void k_raster_fill(const DevDefect* __restrict__ defs, int n,
-                                                    int32_t* __restrict__ ids, int32_t* __restrict__ counts,
-                                                    int64_t* __restrict__ es) {
+                                                    int32_t* __restrict__ ids, int2* __restrict__ lnk,
+                                                    int32_t* __restrict__ counts, int32_t* __restrict__ own) {
   const DevDefect d = defs[blockIdx.x];
   const int nrows = d.w[1] * d.w[2];
-  const size_t n3 = (size_t)n * n * n;
   __shared__ int wsum[RT / 64];
   __shared__ int run;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -91,7 +84,7 @@ __global__ __launch_bounds__(RT) void k_raster_fill(const DevDefect* __restrict_
       tot += wsum[w];
     }
     if (cnt > 0) {
-      int64_t pos = d.slot + run + before;
+      int64_t e = d.slot + run + before;
       // candidates in ascending x: a range that wraps past n - 1 is emitted low part first
       const int xa = d.lo[0] + u0, xb = d.lo[0] + u1;
       const int segs = (xa < n && xb >= n) ? 2 : 1;
@@ -107,8 +100,11 @@ __global__ __launch_bounds__(RT) void k_raster_fill(const DevDefect* __restrict_
         for (int x = lo; x <= hi; ++x)
           if (member(d, n, x, y, z)) {
             const int id = (z * n + y) * n + x;
-            ids[pos++] = id;
-            add_fix(es, n3, id, d.efix, 1);
+            ids[e] = id;
+            int32_t next = -1;
+            if (atomicCAS(&own[id], -1, (int32_t)blockIdx.x) != -1) next = atomicExch(&own[id], entry_link(e));
+            lnk[e] = make_int2((int)blockIdx.x, next);
+            ++e;
           }
       }
     }
@@ -119,15 +115,13 @@ __global__ __launch_bounds__(RT) void k_raster_fill(const DevDefect* __restrict_
   if (threadIdx.x == 0) counts[blockIdx.x] = run;
 }
 
-// Remove the defects' contributions (exact inverse of the fill).
+// Empty the lists of all voxels of all listed footprints (plain stores).
 __global__ __launch_bounds__(RT) void k_unraster(const DevDefect* __restrict__ defs,
                                                  const int32_t* __restrict__ counts, const int32_t* __restrict__ ids,
-                                                 int64_t n3, int64_t* __restrict__ es) {
+                                                 int32_t* __restrict__ own) {
   const int64_t o = defs[blockIdx.x].slot;
   const int cnt = counts[blockIdx.x];
-  int64_t efix[6];
-  for (int c = 0; c < 6; ++c) efix[c] = defs[blockIdx.x].efix[c];
-  for (int i = threadIdx.x; i < cnt; i += RT) add_fix(es, n3, ids[o + i], efix, -1);
+  for (int i = threadIdx.x; i < cnt; i += RT) own[ids[o + i]] = -1;
 }
 
 __device__ __forceinline__ int shift_id(int id, int sx, int sy, int sz, int n) {
@@ -138,32 +132,47 @@ __device__ __forceinline__ int shift_id(int id, int sx, int sy, int sz, int n) {
   return (z * n + y) * n + x;
 }
 
-// Move one defect in the fixed-point field: subtract on the old footprint, add
-// on the new one (new = old shifted by whole voxels when new_ids == nullptr).
-// Grid-stride over 2 * cap threads; the old count is read on the device.
-__global__ __launch_bounds__(RT) void k_update_es(const int64_t* __restrict__ efix, const int32_t* __restrict__ old_ids,
-                                                  const int32_t* __restrict__ cnt_old_p,
-                                                  const int32_t* __restrict__ new_ids, int cnt_new, int sx, int sy,
-                                                  int sz, int n, int64_t* __restrict__ es) {
-  const size_t n3 = (size_t)n * n * n;
-  const int cnt_old = *cnt_old_p;
-  const int nn = new_ids ? cnt_new : cnt_old;
-  int64_t f[6];
-  for (int c = 0; c < 6; ++c) f[c] = efix[c];
-  for (int t = blockIdx.x * RT + threadIdx.x; t < cnt_old + nn; t += gridDim.x * RT) {
-    if (t < cnt_old) {
-      add_fix(es, n3, old_ids[t], f, -1);
-    } else {
-      const int i = t - cnt_old;
-      add_fix(es, n3, new_ids ? new_ids[i] : shift_id(old_ids[i], sx, sy, sz, n), f, 1);
+// Remove defect `def` from the chains of its old voxels.  Each voxel of one
+// footprint is visited by exactly one thread, and no other chain changes
+// meanwhile.  The defect sits on the chain either as a terminal id or as an
+// entry; either way the link that points to it is redirected past it.
+__global__ __launch_bounds__(RT) void k_unlink(int def, const int32_t* __restrict__ cnt_p, int64_t slot,
+                                               const int32_t* __restrict__ ids, int2* __restrict__ lnk,
+                                               int32_t* __restrict__ own) {
+  const int cnt = *cnt_p;
+  for (int k = blockIdx.x * RT + threadIdx.x; k < cnt; k += gridDim.x * RT) {
+    int32_t* p = &own[ids[slot + k]];
+    for (int guard = 0; guard < 4096; ++guard) {
+      const int32_t link = *p;
+      if (link == -1) break;  // not found (cannot happen for a consistent chain)
+      if (link >= 0) {
+        if (link == def) *p = -1;
+        break;
+      }
+      int2* L = &lnk[-2 - link];
+      if (L->x == def) {
+        *p = L->y;
+        break;
+      }
+      p = &L->y;
     }
   }
 }
 
-__global__ __launch_bounds__(RT) void k_translate_ids(int32_t* __restrict__ ids, const int32_t* __restrict__ cnt_p,
-                                                      int sx, int sy, int sz, int n) {
-  const int cnt = *cnt_p;
-  for (int t = blockIdx.x * RT + threadIdx.x; t < cnt; t += gridDim.x * RT) ids[t] = shift_id(ids[t], sx, sy, sz, n);
+// Link the moved defect's new entries (ids shifted in place, or copied from new_ids).
+__global__ __launch_bounds__(RT) void k_link(int def, const int32_t* __restrict__ cnt_p, int64_t old_slot,
+                                             const int32_t* __restrict__ new_ids, int cnt_new, int64_t new_slot,
+                                             int sx, int sy, int sz, int n, int32_t* __restrict__ ids,
+                                             int2* __restrict__ lnk, int32_t* __restrict__ own) {
+  const int cnt = new_ids ? cnt_new : *cnt_p;
+  for (int k = blockIdx.x * RT + threadIdx.x; k < cnt; k += gridDim.x * RT) {
+    const int64_t e = new_slot + k;
+    const int id = new_ids ? new_ids[k] : shift_id(ids[old_slot + k], sx, sy, sz, n);
+    ids[e] = id;
+    int32_t next = -1;
+    if (atomicCAS(&own[id], -1, def) != -1) next = atomicExch(&own[id], entry_link(e));
+    lnk[e] = make_int2(def, next);
+  }
 }
 
 // Additive constant of the stress for the xi = 0 condition.  Mean strain zero:
@@ -215,6 +224,11 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
   if (t < n) p[t] = v;
 }
 
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
 }  // namespace
 
 hipError_t launch_scan(const int32_t* counts, int ndef, int64_t* offsets, hipStream_t s) {
@@ -222,30 +236,28 @@ hipError_t launch_scan(const int32_t* counts, int ndef, int64_t* offsets, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_raster_fill(const DevDefect* d, int ndef, int n, int32_t* ids, int32_t* counts, int64_t* es,
-                              hipStream_t s) {
+hipError_t launch_raster_fill(const DevDefect* d, int ndef, int n, int32_t* ids, int2* lnk, int32_t* counts,
+                              int32_t* own, hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_raster_fill, dim3(ndef), dim3(RT), 0, s, d, n, ids, counts, es);
+  hipLaunchKernelGGL(k_raster_fill, dim3(ndef), dim3(RT), 0, s, d, n, ids, lnk, counts, own);
   return hipGetLastError();
 }
 
-hipError_t launch_unraster(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int64_t n3,
-                           int64_t* es, hipStream_t s) {
+hipError_t launch_unraster(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int32_t* own,
+                           hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_unraster, dim3(ndef), dim3(RT), 0, s, d, counts, ids, n3, es);
+  hipLaunchKernelGGL(k_unraster, dim3(ndef), dim3(RT), 0, s, d, counts, ids, own);
   return hipGetLastError();
 }
 
-hipError_t launch_update_es(const int64_t* efix, const int32_t* old_ids, const int32_t* cnt_old,
-                            const int32_t* new_ids, int cnt_new, int sx, int sy, int sz, int n, int64_t* es,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(k_update_es, dim3(64), dim3(RT), 0, s, efix, old_ids, cnt_old, new_ids, cnt_new, sx, sy, sz, n,
-                     es);
-  return hipGetLastError();
-}
-
-hipError_t launch_translate_ids(int32_t* ids, const int32_t* cnt, int sx, int sy, int sz, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_translate_ids, dim3(16), dim3(RT), 0, s, ids, cnt, sx, sy, sz, n);
+hipError_t launch_move_lists(int def, const int32_t* cnt_old, int64_t old_slot, const int32_t* new_ids, int cnt_new,
+                             int64_t new_slot, int sx, int sy, int sz, int n, int32_t* ids, int2* lnk, int32_t* own,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_unlink, dim3(16), dim3(RT), 0, s, def, cnt_old, old_slot, ids, lnk, own);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_link, dim3(16), dim3(RT), 0, s, def, cnt_old, old_slot, new_ids, cnt_new, new_slot, sx, sy, sz,
+                     n, ids, lnk, own);
   return hipGetLastError();
 }
 
@@ -262,4 +274,12 @@ hipError_t launch_fill_i64(int64_t* p, int64_t count, int64_t v, hipStream_t s) 
   return hipGetLastError();
 }
 
+}  // namespace ec
+
+namespace ec {
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
 }  // namespace ec
