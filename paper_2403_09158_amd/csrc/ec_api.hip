@@ -480,9 +480,7 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
   LAUNCH(st, s, PF_XF, 4.0 * (double)st->n3 + sb,
          launch_x_forward(fp64, own, lnk, defs, nullptr, spec, g, st->tw, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, false, 1, spec, g, full, st->tw, s));
-  LAUNCH(st, s, PF_Z, 2 * sb, launch_pencil(fp64, false, 2, spec, g, full, st->tw, s));
-  LAUNCH(st, s, PF_Z, 2 * sb, launch_green(fp64, spec, g, st->C, s));
-  LAUNCH(st, s, PF_Z, 2 * sb, launch_pencil(fp64, true, 2, spec, g, full, st->tw, s));
+  LAUNCH(st, s, PF_Z, 2 * sb, launch_z_green(fp64, spec, g, st->C, full, st->tw, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, spec, g, full, st->tw, s));
   LAUNCH(st, s, PF_XI, sb + fb, launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s));
   return EC_OK;
@@ -1105,9 +1103,7 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
     LAUNCH(st, s, PF_Y, 2 * frac_z * sb, launch_pencil(fp64, false, 1, st->spec, st->g, py, st->tw, s));
     const Prune pz{zlo, zlen, 0, n};
     const Prune full{0, n, 0, n};
-    LAUNCH(st, s, PF_Z, (1 + frac_z) * sb, launch_pencil(fp64, false, 2, st->spec, st->g, pz, st->tw, s));
-    LAUNCH(st, s, PF_Z, 2 * sb, launch_green(fp64, st->spec, st->g, st->C, s));
-    LAUNCH(st, s, PF_Z, 2 * sb, launch_pencil(fp64, true, 2, st->spec, st->g, full, st->tw, s));
+    LAUNCH(st, s, PF_Z, (1 + frac_z) * sb, launch_z_green(fp64, st->spec, st->g, st->C, pz, st->tw, s));
     LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, st->spec, st->g, full, st->tw, s));
     LAUNCH(st, s, PF_XI, sb + 2 * fb,
            launch_x_inverse(fp64, true, st->spec, st->sig, st->g, st->add6 + 12, st->tw, s));

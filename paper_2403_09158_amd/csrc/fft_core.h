@@ -199,9 +199,29 @@ __device__ __forceinline__ double2 tw_at(const double2* tw, int e) {
 // fastest, so positions along a contiguous row stay contiguous).  Operands are
 // all read (LOAD) before the barrier and written (STORE) after it, so the
 // stage may run in place on LDS.  BPT = butterflies per thread.
-enum class Map { Pencil, Row };
+// Butterfly b of a stage -> (transform f, butterfly j within it).  Pencil:
+// transforms interleaved (f = b % NFFT); Row: one transform after another;
+// Group: transforms in groups of GW, one group after another, interleaved
+// inside a group, so a thread keeps its lane of the group in every group.
+enum class Map { Pencil, Row, Group };
 
-template <int N, int R, int NS, bool INV, Map M, int NFFT, int T, class Load, class Store>
+template <Map M, int N, int R, int NFFT, int GW>
+__device__ __forceinline__ void bfly_index(int b, int& f, int& j) {
+  if constexpr (M == Map::Pencil) {
+    f = b % NFFT;
+    j = b / NFFT;
+  } else if constexpr (M == Map::Row) {
+    f = b / (N / R);
+    j = b % (N / R);
+  } else {
+    constexpr int PER = GW * (N / R);
+    const int rem = b % PER;
+    f = (b / PER) * GW + rem % GW;
+    j = rem / GW;
+  }
+}
+
+template <int N, int R, int NS, bool INV, Map M, int NFFT, int T, int GW = NFFT, class Load, class Store>
 __device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& store, bool sync_between) {
   constexpr int NB = NFFT * (N / R);
   constexpr int BPT = (NB + T - 1) / T;
@@ -210,8 +230,8 @@ __device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& st
   for (int q = 0; q < BPT; ++q) {
     const int b = threadIdx.x + q * T;
     if (NB % T == 0 || b < NB) {
-      const int f = (M == Map::Pencil) ? (b % NFFT) : (b / (N / R));
-      const int j = (M == Map::Pencil) ? (b / NFFT) : (b % (N / R));
+      int f, j;
+      bfly_index<M, N, R, NFFT, GW>(b, f, j);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = load(f, j + r * (N / R));
     }
@@ -221,8 +241,8 @@ __device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& st
   for (int q = 0; q < BPT; ++q) {
     const int b = threadIdx.x + q * T;
     if (NB % T == 0 || b < NB) {
-      const int f = (M == Map::Pencil) ? (b % NFFT) : (b / (N / R));
-      const int j = (M == Map::Pencil) ? (b / NFFT) : (b % (N / R));
+      int f, j;
+      bfly_index<M, N, R, NFFT, GW>(b, f, j);
       const int k = j % NS;
       if (NS > 1) {
 #pragma unroll
@@ -261,6 +281,46 @@ __device__ __forceinline__ void transform(const double2* tw, Load0&& load0, LdsL
     __syncthreads();
     stage<N, P.r[2], P.r[0] * P.r[1], INV, M, NFFT, T>(tw, from_lds, store_last, LAST_LDS);
   }
+}
+
+// Transform with an explicit radix sequence (R1 = 1: one stage, R2 = 1: two
+// stages); LOAD0_LDS / LAST_LDS as for transform().
+template <int N, int R0, int R1, int R2, bool INV, Map M, int NFFT, int T, int GW, bool LOAD0_LDS, bool LAST_LDS,
+          class Load0, class LdsLd, class LdsSt, class StoreLast>
+__device__ __forceinline__ void transform_plan(const double2* tw, Load0&& load0, LdsLd&& from_lds, LdsSt&& to_lds,
+                                               StoreLast&& store_last) {
+  static_assert(R0 * R1 * R2 == N, "radices must multiply to N");
+  if constexpr (R1 == 1) {
+    stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, store_last, LOAD0_LDS && LAST_LDS);
+  } else if constexpr (R2 == 1) {
+    stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, to_lds, LOAD0_LDS);
+    __syncthreads();
+    stage<N, R1, R0, INV, M, NFFT, T, GW>(tw, from_lds, store_last, LAST_LDS);
+  } else {
+    stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, to_lds, LOAD0_LDS);
+    __syncthreads();
+    stage<N, R1, R0, INV, M, NFFT, T, GW>(tw, from_lds, to_lds, true);
+    __syncthreads();
+    stage<N, R2, R0 * R1, INV, M, NFFT, T, GW>(tw, from_lds, store_last, LAST_LDS);
+  }
+}
+
+// Factorisation for the fused z pass: radices whose butterfly counts divide
+// evenly over the workgroup when six components are transformed together.
+__host__ __device__ constexpr Plan2 plan_fused(int N) {
+  return N == 8     ? Plan2{2, {4, 2, 1}}
+         : N == 16  ? Plan2{2, {4, 4, 1}}
+         : N == 24  ? Plan2{2, {8, 3, 1}}
+         : N == 32  ? Plan2{2, {8, 4, 1}}
+         : N == 48  ? Plan2{2, {16, 3, 1}}
+         : N == 64  ? Plan2{3, {8, 2, 4}}
+         : N == 96  ? Plan2{3, {8, 4, 3}}
+         : N == 128 ? Plan2{3, {8, 4, 4}}
+         : N == 160 ? Plan2{3, {8, 4, 5}}
+         : N == 240 ? Plan2{3, {16, 5, 3}}
+         : N == 256 ? Plan2{3, {8, 8, 4}}
+         : N == 512 ? Plan2{3, {8, 16, 4}}
+                    : Plan2{0, {1, 1, 1}};
 }
 
 }  // namespace ec

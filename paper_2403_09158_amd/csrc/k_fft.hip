@@ -365,6 +365,106 @@ __global__ __launch_bounds__(pick_T2(max_nb(N, W), TMAX)) void k_pencil(typename
   transform<N, INV, Map::Pencil, W, T>(tw, load0, from_lds, to_lds, store_last);
 }
 
+// ------------------------------------------- z-forward + Green + z-inverse (fused)
+//
+// One workgroup owns W kx columns of one ky row for all six components (6 W
+// transforms of length N along z) in one LDS tile: forward transforms, the
+// Green step per bin in place, inverse transforms.  The spectrum is read and
+// written once per solve instead of three times, and every stage has all six
+// components' butterflies to spread over the workgroup.
+
+template <int N>
+struct FusedPlan {
+  static constexpr Plan2 P = plan_fused(N);
+  static constexpr int NSTG = P.nstage;
+  static constexpr int R0 = P.r[0], R1 = P.r[1], R2 = P.r[2];
+  static constexpr int RL = NSTG == 1 ? R0 : (NSTG == 2 ? R1 : R2);
+  static constexpr int I0 = RL;
+  static constexpr int I1 = NSTG == 1 ? 1 : (NSTG == 2 ? R0 : R1);
+  static constexpr int I2 = NSTG == 3 ? R0 : 1;
+};
+
+// columns per tile: 16-byte storage elements get half the width
+template <int N, typename S>
+constexpr int zg_width() {
+  constexpr int w = sizeof(S) == 4 ? 4 : 2;
+  return N >= 512 ? w / 2 : w;
+}
+
+template <int N, typename S>
+constexpr int zg_threads() {
+  return zg_width<N, S>() * (N / FusedPlan<N>::RL);
+}
+
+// LDS row swizzle: the low three bits of the z index are XORed with the next
+// three, so stride-R stores of the first stages spread over all banks.
+__device__ __forceinline__ int zg_swz(int i) { return (i & ~7) | ((i ^ (i >> 3)) & 7); }
+
+// hardware dispatch places consecutive workgroups on consecutive XCDs; give
+// each XCD a contiguous run of tiles so neighbouring kx tiles share its L2
+__device__ __forceinline__ int xcd_tile(int bid, int nblk) {
+  const int per = nblk / 8;
+  return bid < per * 8 ? (bid % 8) * per + bid / 8 : bid;
+}
+
+template <int N, typename S, bool PRUNE>
+__global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S>::T* __restrict__ spec, int P,
+                                                                Cubic C, Prune pr, const double2* __restrict__ twg) {
+  using FP = FusedPlan<N>;
+  constexpr int W = zg_width<N, S>();
+  constexpr int RL = FP::RL;
+  constexpr int T = zg_threads<N, S>();
+  constexpr int NH = N / 2 + 1;
+  constexpr int KB = (NH + W - 1) / W;
+  static_assert(N % 8 == 0, "row swizzle needs whole groups of eight");
+  using C2 = typename Cplx<S>::T;
+  __shared__ C2 buf[6 * N * W];
+  __shared__ double2 tw[N];
+  for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  const int tile = xcd_tile(blockIdx.x, N * KB);
+  const int ky = tile / KB;
+  const int w = threadIdx.x % W;  // T and every group size are multiples of W
+  const int kx = (tile % KB) * W + w;
+  const bool valid = kx < NH;
+  const int si = N * P;
+  const size_t cs = (size_t)N * N * P;
+  C2* const col0 = spec + (valid ? (size_t)ky * P + kx : 0);
+  auto lds = [&](int f, int i) -> C2* { return &buf[((f / W) * N + zg_swz(i)) * W + f % W]; };
+  auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
+  auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
+  auto load0 = [&](int f, int i) -> double2 {
+    if (!valid) return make_double2(0.0, 0.0);
+    if (PRUNE) {
+      int d = i - pr.in_lo;
+      if (d < 0) d += N;
+      if (d >= pr.in_len) return make_double2(0.0, 0.0);
+    }
+    return ld2(col0 + (f / W) * cs + i * si);
+  };
+  __syncthreads();
+  transform_plan<N, FP::R0, FP::R1, FP::R2, false, Map::Group, 6 * W, T, W, false, true>(tw, load0, from_lds, to_lds,
+                                                                                        to_lds);
+  __syncthreads();
+  // Green step: one bin (all six components) per iteration, in place
+#pragma unroll 1
+  for (int b = threadIdx.x; b < N * W; b += T) {
+    const int bw = b % W, kz = b / W, bkx = kx - w + bw;
+    if (bkx >= NH) continue;
+    double2 e[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = from_lds(c * W + bw, kz);
+    green_bin(e, bkx, ky, kz, N, C);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) to_lds(c * W + bw, kz, e[c]);
+  }
+  __syncthreads();
+  auto store_last = [&](int f, int i, double2 v) {
+    if (valid) st2(col0 + (f / W) * cs + i * si, v);
+  };
+  transform_plan<N, FP::I0, FP::I1, FP::I2, true, Map::Group, 6 * W, T, W, true, false>(tw, from_lds, from_lds, to_lds,
+                                                                                       store_last);
+}
+
 // Pointwise Green step over the half spectrum (one thread per bin).
 template <typename S>
 __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__ spec, int n, int P, Cubic C) {
@@ -583,13 +683,28 @@ hipError_t launch_green(bool fp64, void* spec, SpecGeom g, Cubic C, hipStream_t 
   return hipGetLastError();
 }
 
+template <int N, typename S>
+hipError_t go_zgreen(void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, hipStream_t s) {
+  constexpr int W = zg_width<N, S>();
+  constexpr int T = zg_threads<N, S>();
+  constexpr int KB = (N / 2 + 1 + W - 1) / W;
+  using C2 = typename Cplx<S>::T;
+  if (pr.in_len < N)
+    hipLaunchKernelGGL((k_zgreen<N, S, true>), dim3(N * KB), dim3(T), 0, s, (C2*)spec, g.P, C, pr, tw);
+  else
+    hipLaunchKernelGGL((k_zgreen<N, S, false>), dim3(N * KB), dim3(T), 0, s, (C2*)spec, g.P, C, pr, tw);
+  return hipGetLastError();
+}
+
 hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, hipStream_t s) {
-  hipError_t e = launch_pencil(fp64, false, 2, spec, g, pr, tw, s);
-  if (e != hipSuccess) return e;
-  e = launch_green(fp64, spec, g, C, s);
-  if (e != hipSuccess) return e;
-  Prune full{0, g.n, 0, g.n};
-  return launch_pencil(fp64, true, 2, spec, g, full, tw, s);
+  switch (g.n) {
+#define EC_CASE(NN) \
+  case NN:          \
+    return fp64 ? go_zgreen<NN, double>(spec, g, C, pr, tw, s) : go_zgreen<NN, float>(spec, g, C, pr, tw, s);
+    EC_FOR_SIZES(EC_CASE)
+#undef EC_CASE
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,

@@ -131,6 +131,20 @@ def test_green_step(ctx, n, bc):
 # ------------------------------------------------------------------ full solve
 
 
+@pytest.mark.parametrize("n", [8, 16, 24, 32, 48, 64, 96, 128, 160, 240])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_solve_fields_every_size(ctx, n, prec):
+    """The whole solve (fused z pass included) at every supported length."""
+    prob, d = _mixed(n, max(4, n // 8), 7 * n + prec, prec=prec)
+    _, _, _, _, sig6 = _oracle_fields(prob, d)
+    st = _state(ctx, prob)
+    st.solve(d)
+    tol = 1e-12 if prec == 0 else 1e-5
+    assert rel_l2(st.field("sigma"), sig6) < tol
+    st.close()
+
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("bc", [0, 1])
 def test_config1_fields_and_energies(ctx, prec, bc):
