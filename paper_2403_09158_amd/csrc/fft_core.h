@@ -14,6 +14,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace ec {
 
 struct Plan2 {
@@ -222,24 +224,32 @@ __device__ __forceinline__ void bfly_index(int b, int& f, int& j) {
 }
 
 template <int N, int R, int NS, bool INV, Map M, int NFFT, int T, int GW = NFFT, class Load, class Store>
-__device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& store, bool sync_between) {
+__device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& store, bool sync_between,
+                                      int tid = threadIdx.x) {
   constexpr int NB = NFFT * (N / R);
   constexpr int BPT = (NB + T - 1) / T;
   double2 v[BPT][R];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
-    const int b = threadIdx.x + q * T;
+    const int b = tid + q * T;
     if (NB % T == 0 || b < NB) {
       int f, j;
       bfly_index<M, N, R, NFFT, GW>(b, f, j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = load(f, j + r * (N / R));
+      for (int r = 0; r < R; ++r) {
+        // a 3-argument rule also receives the operand's slot q R + r (see
+        // for_operands), a compile-time index into register-held operands
+        if constexpr (std::is_invocable_v<Load, int, int, int>)
+          v[q][r] = load(f, j + r * (N / R), q * R + r);
+        else
+          v[q][r] = load(f, j + r * (N / R));
+      }
     }
   }
   if (sync_between) __syncthreads();
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
-    const int b = threadIdx.x + q * T;
+    const int b = tid + q * T;
     if (NB % T == 0 || b < NB) {
       int f, j;
       bfly_index<M, N, R, NFFT, GW>(b, f, j);
@@ -252,6 +262,24 @@ __device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& st
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) store(f, base + r * NS, v[q][r]);
+    }
+  }
+}
+
+// Visit the operands a thread reads in a radix-R stage, in the order stage()
+// reads them: fn(f, i, slot) with slot = q R + r for its q-th butterfly.
+template <int N, int R, Map M, int NFFT, int T, int GW = NFFT, class F>
+__device__ __forceinline__ void for_operands(F&& fn, int tid = threadIdx.x) {
+  constexpr int NB = NFFT * (N / R);
+  constexpr int BPT = (NB + T - 1) / T;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = tid + q * T;
+    if (NB % T == 0 || b < NB) {
+      int f, j;
+      bfly_index<M, N, R, NFFT, GW>(b, f, j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) fn(f, j + r * (N / R), q * R + r);
     }
   }
 }
@@ -288,20 +316,20 @@ __device__ __forceinline__ void transform(const double2* tw, Load0&& load0, LdsL
 template <int N, int R0, int R1, int R2, bool INV, Map M, int NFFT, int T, int GW, bool LOAD0_LDS, bool LAST_LDS,
           class Load0, class LdsLd, class LdsSt, class StoreLast>
 __device__ __forceinline__ void transform_plan(const double2* tw, Load0&& load0, LdsLd&& from_lds, LdsSt&& to_lds,
-                                               StoreLast&& store_last) {
+                                               StoreLast&& store_last, int tid = threadIdx.x) {
   static_assert(R0 * R1 * R2 == N, "radices must multiply to N");
   if constexpr (R1 == 1) {
-    stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, store_last, LOAD0_LDS && LAST_LDS);
+    stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, store_last, LOAD0_LDS && LAST_LDS, tid);
   } else if constexpr (R2 == 1) {
-    stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, to_lds, LOAD0_LDS);
+    stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, to_lds, LOAD0_LDS, tid);
     __syncthreads();
-    stage<N, R1, R0, INV, M, NFFT, T, GW>(tw, from_lds, store_last, LAST_LDS);
+    stage<N, R1, R0, INV, M, NFFT, T, GW>(tw, from_lds, store_last, LAST_LDS, tid);
   } else {
-    stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, to_lds, LOAD0_LDS);
+    stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, to_lds, LOAD0_LDS, tid);
     __syncthreads();
-    stage<N, R1, R0, INV, M, NFFT, T, GW>(tw, from_lds, to_lds, true);
+    stage<N, R1, R0, INV, M, NFFT, T, GW>(tw, from_lds, to_lds, true, tid);
     __syncthreads();
-    stage<N, R2, R0 * R1, INV, M, NFFT, T, GW>(tw, from_lds, store_last, LAST_LDS);
+    stage<N, R2, R0 * R1, INV, M, NFFT, T, GW>(tw, from_lds, store_last, LAST_LDS, tid);
   }
 }
 

@@ -6,6 +6,8 @@
 //   z-forward + Green operator + z-inverse, y-inverse, x-inverse (C2R) + stress.
 // All butterflies, twiddles and the Green operator run in FP64 registers; the
 // storage type S (float or double) only sets what is kept in HBM between passes.
+#include <algorithm>
+
 #include "ec_internal.h"
 #include "fft_core.h"
 
@@ -334,35 +336,87 @@ constexpr int pick_T2(int nb, int tmax) { return nb >= tmax ? tmax : ((nb + 63) 
 template <int N, typename S, bool INV, int W, typename LT, int TMAX, bool PRUNE>
 __global__ __launch_bounds__(pick_T2(max_nb(N, W), TMAX)) void k_pencil(typename Cplx<S>::T* __restrict__ spec, int P,
                                                                       int axis, Prune pr,
-                                                                      const double2* __restrict__ twg) {
+                                                                      const double2* __restrict__ twg, int ntiles) {
   constexpr int T = pick_T2(max_nb(N, W), TMAX);
   static_assert(T % W == 0, "a thread must keep its column across butterflies");
+  constexpr Plan2 PL = plan_of(N);
+  constexpr int R0 = PL.r[0];
+  constexpr int NOP = ((W * (N / R0) + T - 1) / T) * R0;  // first-stage operands per thread
+  using C2 = typename Cplx<S>::T;
   __shared__ LT buf[N * W];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
-  const PencilTile<N, W> tile(blockIdx.x, axis == 1 ? pr.z_len : N, pr.z_lo);
-  // every butterfly of this thread sits in column w = threadIdx.x % W
-  int o, kx;
-  const bool valid = tile.col(threadIdx.x % W, o, kx);
-  using C2 = typename Cplx<S>::T;
-  C2* const colp = spec + (valid ? tile.off(axis, o, kx, 0, P) : 0);
+  const int nouter = axis == 1 ? pr.z_len : N;
   const int si = axis == 1 ? P : N * P;  // element stride along the transform axis
-  __syncthreads();
-  auto load0 = [&](int, int i) -> double2 {
-    if (!valid) return make_double2(0.0, 0.0);
-    if (PRUNE) {
-      int d = i - pr.in_lo;
-      if (d < 0) d += N;
-      if (d >= pr.in_len) return make_double2(0.0, 0.0);
-    }
-    return ld2(colp + i * si);
+  auto in_range = [&](int i) {
+    if (!PRUNE) return true;
+    int d = i - pr.in_lo;
+    if (d < 0) d += N;
+    return d < pr.in_len;
+  };
+  // column of thread lane w in tile t (the base of the spectrum if the lane
+  // has no column in this tile)
+  auto column = [&](int t, int w, bool& valid) -> C2* {
+    const PencilTile<N, W> tile(t, nouter, pr.z_lo);
+    int o, kx;
+    valid = tile.col(w, o, kx);
+    return spec + (valid ? tile.off(axis, o, kx, 0, P) : 0);
+  };
+  // FP32 storage: raw first-stage operands of the next tile are loaded while
+  // the current one is transformed (rows outside the input range read row
+  // in_lo, a cache hit, and are zeroed when consumed).  FP64 storage would
+  // need twice the registers for them and loads each tile's operands in turn.
+  constexpr bool PIPE = sizeof(S) == 4;
+  C2 nxt[NOP];
+  auto fetch = [&](int t, int tid) {
+    if constexpr (!PIPE) return;
+    bool v;
+    const C2* colp = column(t, tid % W, v);
+    for_operands<N, R0, Map::Pencil, W, T>(
+        [&](int, int i, int slot) { nxt[slot] = colp[(size_t)(in_range(i) ? i : pr.in_lo) * si]; }, tid);
   };
   auto from_lds = [&](int w, int i) { return ld2(&buf[i * W + w]); };
   auto to_lds = [&](int w, int i, double2 v) { st2(&buf[i * W + w], v); };
-  auto store_last = [&](int, int i, double2 v) {
-    if (valid) st2(colp + i * si, v);
-  };
-  transform<N, INV, Map::Pencil, W, T>(tw, load0, from_lds, to_lds, store_last);
+  // contiguous tile ranges per XCD (workgroup b runs on XCD b % 8)
+  const int g8 = gridDim.x / 8;
+  const int per = (ntiles + 7) / 8;
+  const int lo = (int)(blockIdx.x % 8) * per;
+  const int hi = min(ntiles, lo + per);
+  int t = lo + (int)(blockIdx.x / 8);
+  if (t < hi) fetch(t, threadIdx.x);
+  __syncthreads();
+  for (; t < hi; t += g8) {
+    // laundered thread index: index arithmetic is redone per tile instead of
+    // being held in registers across the loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    bool valid;
+    C2* const colp = column(t, tid % W, valid);
+    auto load0 = [&](int, int i, int slot) -> double2 {
+      if (!(valid && in_range(i))) return make_double2(0.0, 0.0);
+      return PIPE ? ld2(&nxt[slot]) : ld2(colp + (size_t)i * si);
+    };
+    auto store_last = [&](int, int i, double2 v) {
+      if (valid) st2(colp + (size_t)i * si, v);
+    };
+    const bool more = t + g8 < hi;
+    if constexpr (PL.nstage == 1) {
+      stage<N, R0, 1, INV, Map::Pencil, W, T>(tw, load0, store_last, false, tid);
+      if (more) fetch(t + g8, tid);
+    } else {
+      stage<N, R0, 1, INV, Map::Pencil, W, T>(tw, load0, to_lds, false, tid);
+      if (more) fetch(t + g8, tid);
+      __syncthreads();
+      if constexpr (PL.nstage == 2) {
+        stage<N, PL.r[1], R0, INV, Map::Pencil, W, T>(tw, from_lds, store_last, false, tid);
+      } else {
+        stage<N, PL.r[1], R0, INV, Map::Pencil, W, T>(tw, from_lds, to_lds, true, tid);
+        __syncthreads();
+        stage<N, PL.r[2], R0 * PL.r[1], INV, Map::Pencil, W, T>(tw, from_lds, store_last, false, tid);
+      }
+    }
+    __syncthreads();  // the next tile's first stage rewrites LDS
+  }
 }
 
 // ------------------------------------------- z-forward + Green + z-inverse (fused)
@@ -384,16 +438,23 @@ struct FusedPlan {
   static constexpr int I2 = NSTG == 3 ? R0 : 1;
 };
 
-// columns per tile: 16-byte storage elements get half the width
+// columns per tile (two at N = 512, where the tile would not fit twice in LDS)
 template <int N, typename S>
 constexpr int zg_width() {
-  constexpr int w = sizeof(S) == 4 ? 4 : 2;
-  return N >= 512 ? w / 2 : w;
+  return N >= 512 ? 2 : 4;
 }
 
+// one butterfly per thread in the widest-radix stage (at most 1024 threads)
 template <int N, typename S>
 constexpr int zg_threads() {
-  return zg_width<N, S>() * (N / FusedPlan<N>::RL);
+  using FP = FusedPlan<N>;
+  constexpr int rmin = FP::R0 < FP::R1 ? FP::R0 : FP::R1;
+  constexpr int rl = FP::R2 > 1 && FP::R2 < rmin ? FP::R2 : rmin;  // smallest radix
+  constexpr int rmax = FP::R0 > FP::R1 ? (FP::R0 > FP::R2 ? FP::R0 : FP::R2) : (FP::R1 > FP::R2 ? FP::R1 : FP::R2);
+  constexpr int nb = 6 * zg_width<N, S>() * (N / rmax);
+  constexpr int t = ((nb + 63) / 64) * 64;
+  static_assert(rl >= 1, "");
+  return t > 1024 ? 1024 : t;
 }
 
 // LDS row swizzle: the low three bits of the z index are XORed with the next
@@ -412,57 +473,98 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
                                                                 Cubic C, Prune pr, const double2* __restrict__ twg) {
   using FP = FusedPlan<N>;
   constexpr int W = zg_width<N, S>();
-  constexpr int RL = FP::RL;
   constexpr int T = zg_threads<N, S>();
   constexpr int NH = N / 2 + 1;
   constexpr int KB = (NH + W - 1) / W;
+  constexpr int NT = N * KB;  // tiles
+  constexpr int NF = 6 * W;   // transforms per tile
+  constexpr int R0 = FP::R0, R1 = FP::R1, R2 = FP::R2;
+  constexpr int NOP = ((NF * (N / R0) + T - 1) / T) * R0;  // first-stage operands per thread
   static_assert(N % 8 == 0, "row swizzle needs whole groups of eight");
+  static_assert(FP::NSTG >= 2, "the first stage must not be the last");
   using C2 = typename Cplx<S>::T;
   __shared__ C2 buf[6 * N * W];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
-  const int tile = xcd_tile(blockIdx.x, N * KB);
-  const int ky = tile / KB;
-  const int w = threadIdx.x % W;  // T and every group size are multiples of W
-  const int kx = (tile % KB) * W + w;
-  const bool valid = kx < NH;
   const int si = N * P;
   const size_t cs = (size_t)N * N * P;
-  C2* const col0 = spec + (valid ? (size_t)ky * P + kx : 0);
   auto lds = [&](int f, int i) -> C2* { return &buf[((f / W) * N + zg_swz(i)) * W + f % W]; };
   auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
   auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
-  auto load0 = [&](int f, int i) -> double2 {
-    if (!valid) return make_double2(0.0, 0.0);
-    if (PRUNE) {
-      int d = i - pr.in_lo;
-      if (d < 0) d += N;
-      if (d >= pr.in_len) return make_double2(0.0, 0.0);
+  auto in_z = [&](int i) {
+    if (!PRUNE) return true;
+    int d = i - pr.in_lo;
+    if (d < 0) d += N;
+    return d < pr.in_len;
+  };
+  // FP32 storage: raw first-stage operands of the next tile, loaded while the
+  // current one is transformed (rows outside the input range read row in_lo
+  // instead, a cache hit, and are zeroed when consumed).  FP64 storage loads
+  // each tile's operands in turn.
+  constexpr bool PIPE = sizeof(S) == 4;
+  C2 nxt[NOP];
+  auto fetch = [&](int t, int tid) {
+    if constexpr (!PIPE) return;
+    const int kx = (t % KB) * W + tid % W;
+    const C2* col0 = spec + (kx < NH ? (size_t)(t / KB) * P + kx : 0);
+    for_operands<N, R0, Map::Group, NF, T, W>(
+        [&](int f, int i, int slot) { nxt[slot] = col0[(f / W) * cs + (size_t)(in_z(i) ? i : pr.in_lo) * si]; }, tid);
+  };
+  // tiles split into eight contiguous ranges, one per XCD (dispatch order puts
+  // workgroup b on XCD b % 8), so neighbouring kx tiles share an L2
+  const int g8 = gridDim.x / 8;
+  const int per = (NT + 7) / 8;
+  const int lo = (int)(blockIdx.x % 8) * per;
+  const int hi = min(NT, lo + per);
+  int t = lo + (int)(blockIdx.x / 8);
+  if (t < hi) fetch(t, threadIdx.x);
+  __syncthreads();
+  for (; t < hi; t += g8) {
+    // the thread index is laundered per tile so that the many index
+    // expressions derived from it are recomputed, not held in registers
+    // across the loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int ky = t / KB;
+    const int w = tid % W;  // T and every group size are multiples of W
+    const int kx = (t % KB) * W + w;
+    const bool valid = kx < NH;
+    C2* const col0 = spec + (valid ? (size_t)ky * P + kx : 0);
+    auto load0 = [&](int f, int i, int slot) -> double2 {
+      if (!(valid && in_z(i))) return make_double2(0.0, 0.0);
+      return PIPE ? ld2(&nxt[slot]) : ld2(col0 + (f / W) * cs + (size_t)i * si);
+    };
+    stage<N, R0, 1, false, Map::Group, NF, T, W>(tw, load0, to_lds, false, tid);
+    if (t + g8 < hi) fetch(t + g8, tid);
+    __syncthreads();
+    if constexpr (R2 == 1) {
+      stage<N, R1, R0, false, Map::Group, NF, T, W>(tw, from_lds, to_lds, true, tid);
+    } else {
+      stage<N, R1, R0, false, Map::Group, NF, T, W>(tw, from_lds, to_lds, true, tid);
+      __syncthreads();
+      stage<N, R2, R0 * R1, false, Map::Group, NF, T, W>(tw, from_lds, to_lds, true, tid);
     }
-    return ld2(col0 + (f / W) * cs + i * si);
-  };
-  __syncthreads();
-  transform_plan<N, FP::R0, FP::R1, FP::R2, false, Map::Group, 6 * W, T, W, false, true>(tw, load0, from_lds, to_lds,
-                                                                                        to_lds);
-  __syncthreads();
-  // Green step: one bin (all six components) per iteration, in place
+    __syncthreads();
+    // Green step: one bin (all six components) per iteration, in place
 #pragma unroll 1
-  for (int b = threadIdx.x; b < N * W; b += T) {
-    const int bw = b % W, kz = b / W, bkx = kx - w + bw;
-    if (bkx >= NH) continue;
-    double2 e[6];
+    for (int b = tid; b < N * W; b += T) {
+      const int bw = b % W, kz = b / W, bkx = kx - w + bw;
+      if (bkx >= NH) continue;
+      double2 e[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) e[c] = from_lds(c * W + bw, kz);
-    green_bin(e, bkx, ky, kz, N, C);
+      for (int c = 0; c < 6; ++c) e[c] = from_lds(c * W + bw, kz);
+      green_bin(e, bkx, ky, kz, N, C);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) to_lds(c * W + bw, kz, e[c]);
+      for (int c = 0; c < 6; ++c) to_lds(c * W + bw, kz, e[c]);
+    }
+    __syncthreads();
+    auto store_last = [&](int f, int i, double2 v) {
+      if (valid) st2(col0 + (f / W) * cs + (size_t)i * si, v);
+    };
+    transform_plan<N, FP::I0, FP::I1, FP::I2, true, Map::Group, NF, T, W, true, false>(tw, from_lds, from_lds, to_lds,
+                                                                                    store_last, tid);
+    __syncthreads();  // the next tile's first stage rewrites the tile
   }
-  __syncthreads();
-  auto store_last = [&](int f, int i, double2 v) {
-    if (valid) st2(col0 + (f / W) * cs + i * si, v);
-  };
-  transform_plan<N, FP::I0, FP::I1, FP::I2, true, Map::Group, 6 * W, T, W, true, false>(tw, from_lds, from_lds, to_lds,
-                                                                                       store_last);
 }
 
 // Pointwise Green step over the half spectrum (one thread per bin).
@@ -571,25 +673,33 @@ hipError_t go_xfs(const int32_t* oi, const int32_t* oc, const int32_t* ni, int n
   return hipGetLastError();
 }
 
+// Grid of a tile-loop kernel, a multiple of eight.  Kernels that prefetch the
+// next tile (FP32 storage) get as many workgroups as stay resident; the others
+// get one tile per workgroup, so tiles overlap through the hardware scheduler.
+template <class K>
+int tile_grid(K kernel, int threads, int ntiles, bool prefetch) {
+  if (!prefetch) return ((ntiles + 7) / 8) * 8;
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+    return -1;
+  const int g = std::min(ncu * std::max(per_cu, 1), ntiles);
+  return std::max(8, (g / 8) * 8);
+}
+
 template <int N, typename S, int W, typename LT, int TMAX>
 hipError_t go_pencil_v(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, hipStream_t s) {
   constexpr int T = pick_T2(max_nb(N, W), TMAX);
   const int nouter = axis == 1 ? pr.z_len : N;
-  const int grid = 6 * nouter * PencilTile<N, W>::KXB + 6 * ((nouter + W - 1) / W);
+  const int ntiles = 6 * nouter * PencilTile<N, W>::KXB + 6 * ((nouter + W - 1) / W);
   using C2 = typename Cplx<S>::T;
   const bool prune = pr.in_len < N;
-  if (inv && !prune)
-    hipLaunchKernelGGL((k_pencil<N, S, true, W, LT, TMAX, false>), dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis,
-                       pr, tw);
-  else if (inv)
-    hipLaunchKernelGGL((k_pencil<N, S, true, W, LT, TMAX, true>), dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis,
-                       pr, tw);
-  else if (!prune)
-    hipLaunchKernelGGL((k_pencil<N, S, false, W, LT, TMAX, false>), dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis,
-                       pr, tw);
-  else
-    hipLaunchKernelGGL((k_pencil<N, S, false, W, LT, TMAX, true>), dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis,
-                       pr, tw);
+  auto* k = inv ? (prune ? k_pencil<N, S, true, W, LT, TMAX, true> : k_pencil<N, S, true, W, LT, TMAX, false>)
+                : (prune ? k_pencil<N, S, false, W, LT, TMAX, true> : k_pencil<N, S, false, W, LT, TMAX, false>);
+  const int grid = tile_grid(k, T, ntiles, sizeof(S) == 4);
+  if (grid < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis, pr, tw, ntiles);
   return hipGetLastError();
 }
 
@@ -687,12 +797,13 @@ template <int N, typename S>
 hipError_t go_zgreen(void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, hipStream_t s) {
   constexpr int W = zg_width<N, S>();
   constexpr int T = zg_threads<N, S>();
-  constexpr int KB = (N / 2 + 1 + W - 1) / W;
+  constexpr int NT = N * ((N / 2 + 1 + W - 1) / W);
   using C2 = typename Cplx<S>::T;
-  if (pr.in_len < N)
-    hipLaunchKernelGGL((k_zgreen<N, S, true>), dim3(N * KB), dim3(T), 0, s, (C2*)spec, g.P, C, pr, tw);
-  else
-    hipLaunchKernelGGL((k_zgreen<N, S, false>), dim3(N * KB), dim3(T), 0, s, (C2*)spec, g.P, C, pr, tw);
+  const bool prune = pr.in_len < N;
+  auto* k = prune ? k_zgreen<N, S, true> : k_zgreen<N, S, false>;
+  const int grid = tile_grid(k, T, NT, sizeof(S) == 4);
+  if (grid < 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, C, pr, tw);
   return hipGetLastError();
 }
 
