@@ -43,74 +43,112 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ count
   }
 }
 
-// One workgroup per defect, one thread per bounding-box row (y, z) in ascending
-// order: the row's candidate x range comes from the geometry, each candidate is
-// tested exactly, a workgroup scan orders the rows, and every row writes its
-// members in ascending x.  The footprint list of the defect is therefore sorted.
+// One workgroup per defect.  The bounding box is taken in chunks of RCH rows
+// (y, z) in ascending order; each row's candidate x range comes from the
+// geometry, a scan flattens the chunk's candidates in ascending voxel id, and
+// each thread tests one candidate at a time.  A ballot scan gives every member
+// its place, so the footprint list comes out sorted with no per-row serial
+// work, and the atomics of a pass are independent of each other.
+constexpr int RCH = 1024;
+
+__device__ __forceinline__ void row_yz(const DevDefect& d, int n, int r, int& y, int& z) {
+  const int iz = r / d.w[1], iy = r - iz * d.w[1];
+  y = box_axis(d.lo[1], d.w[1], n, iy);
+  z = box_axis(d.lo[2], d.w[2], n, iz);
+}
+
 __global__ __launch_bounds__(RT) void k_raster_fill(const DevDefect* __restrict__ defs, int n,
                                                     int32_t* __restrict__ ids, int2* __restrict__ lnk,
                                                     int32_t* __restrict__ counts, int32_t* __restrict__ own) {
   const DevDefect d = defs[blockIdx.x];
   const int nrows = d.w[1] * d.w[2];
+  __shared__ int roff[RCH + 1];  // candidates before each row of the chunk
+  __shared__ int rxa[RCH];       // first candidate x of each row, unwrapped (may be >= n)
   __shared__ int wsum[RT / 64];
-  __shared__ int run;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) run = 0;
-  __syncthreads();
-  for (int r0 = 0; r0 < nrows; r0 += RT) {
-    const int r = r0 + threadIdx.x;
-    int y = 0, z = 0, u0 = 0, u1 = -1, cnt = 0;
-    if (r < nrows) {
-      const int iz = r / d.w[1], iy = r - iz * d.w[1];
-      y = box_axis(d.lo[1], d.w[1], n, iy);
-      z = box_axis(d.lo[2], d.w[2], n, iz);
-      if (row_range(d, n, y, z, u0, u1))
-        for (int u = u0; u <= u1; ++u) {
-          int x = d.lo[0] + u;
-          x -= x >= n ? n : 0;
-          cnt += member(d, n, x, y, z) ? 1 : 0;
+  constexpr int PER = RCH / RT;
+  int run = 0;  // members placed so far (same value in every thread)
+  for (int r0 = 0; r0 < nrows; r0 += RCH) {
+    const int nr = min(RCH, nrows - r0);
+    // candidate counts of this thread's PER consecutive rows, then a scan
+    int c[PER], s = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int j = threadIdx.x * PER + k;
+      c[k] = 0;
+      if (j < nr) {
+        int y, z, u0, u1;
+        row_yz(d, n, r0 + j, y, z);
+        if (row_range(d, n, y, z, u0, u1)) {
+          c[k] = u1 - u0 + 1;
+          rxa[j] = d.lo[0] + u0;
         }
+      }
+      s += c[k];
     }
-    int incl = cnt;
+    int incl = s;
     for (int o = 1; o < 64; o <<= 1) {
       const int t = __shfl_up(incl, o);
       if (lane >= o) incl += t;
     }
     if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    int before = incl - cnt, tot = 0;
+    int acc = incl - s, ctot = 0;
     for (int w = 0; w < RT / 64; ++w) {
-      if (w < wave) before += wsum[w];
-      tot += wsum[w];
+      if (w < wave) acc += wsum[w];
+      ctot += wsum[w];
     }
-    if (cnt > 0) {
-      int64_t e = d.slot + run + before;
-      // candidates in ascending x: a range that wraps past n - 1 is emitted low part first
-      const int xa = d.lo[0] + u0, xb = d.lo[0] + u1;
-      const int segs = (xa < n && xb >= n) ? 2 : 1;
-      for (int sgi = 0; sgi < segs; ++sgi) {
-        int lo, hi;
-        if (segs == 2) {
-          lo = sgi == 0 ? 0 : xa;
-          hi = sgi == 0 ? xb - n : n - 1;
-        } else {
-          lo = xa >= n ? xa - n : xa;
-          hi = xb >= n ? xb - n : xb;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int j = threadIdx.x * PER + k;
+      if (j < nr) roff[j] = acc;
+      acc += c[k];
+    }
+    if (threadIdx.x == 0) roff[nr] = ctot;
+    __syncthreads();
+    for (int k0 = 0; k0 < ctot; k0 += RT) {
+      const int k = k0 + threadIdx.x;
+      bool is = false;
+      int id = 0;
+      if (k < ctot) {
+        int lo = 0, hi = nr - 1;  // the row holding candidate k
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (roff[mid] <= k) lo = mid;
+          else hi = mid - 1;
         }
-        for (int x = lo; x <= hi; ++x)
-          if (member(d, n, x, y, z)) {
-            const int id = (z * n + y) * n + x;
-            ids[e] = id;
-            int32_t next = -1;
-            if (atomicCAS(&own[id], -1, (int32_t)blockIdx.x) != -1) next = atomicExch(&own[id], entry_link(e));
-            lnk[e] = make_int2((int)blockIdx.x, next);
-            ++e;
-          }
+        const int ci = k - roff[lo];
+        const int xa = rxa[lo], xb = xa + (roff[lo + 1] - roff[lo]) - 1;
+        int x;
+        if (xa < n && xb >= n) {  // wrapped row: [0, xb - n] comes before [xa, n - 1]
+          const int nlow = xb - n + 1;
+          x = ci < nlow ? ci : xa + (ci - nlow);
+        } else {
+          x = (xa >= n ? xa - n : xa) + ci;
+        }
+        int y, z;
+        row_yz(d, n, r0 + lo, y, z);
+        is = member(d, n, x, y, z);
+        id = (z * n + y) * n + x;
       }
+      const uint64_t m = __ballot(is);
+      if (lane == 0) wsum[wave] = __popcll(m);
+      __syncthreads();
+      int before = __popcll(m & ((1ull << lane) - 1)), tot = 0;
+      for (int w = 0; w < RT / 64; ++w) {
+        if (w < wave) before += wsum[w];
+        tot += wsum[w];
+      }
+      if (is) {
+        const int64_t e = d.slot + run + before;
+        ids[e] = id;
+        int32_t next = -1;
+        if (atomicCAS(&own[id], -1, (int32_t)blockIdx.x) != -1) next = atomicExch(&own[id], entry_link(e));
+        lnk[e] = make_int2((int)blockIdx.x, next);
+      }
+      run += tot;
+      __syncthreads();  // wsum is rewritten by the next pass
     }
-    __syncthreads();
-    if (threadIdx.x == 0) run += tot;
-    __syncthreads();
   }
   if (threadIdx.x == 0) counts[blockIdx.x] = run;
 }
