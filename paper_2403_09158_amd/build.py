@@ -33,6 +33,11 @@ CFLAGS = [
     "-Xclang",
     "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # host code: inline rounding and square roots (same IEEE results as libm)
+    "-Xarch_host",
+    "-msse4.2",
+    "-Xarch_host",
+    "-fno-math-errno",
 ]
 
 

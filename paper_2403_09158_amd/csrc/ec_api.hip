@@ -120,8 +120,12 @@ struct ec_state {
   double* S6 = nullptr;
   size_t pd_cap = 0;
   bool B_valid = false;
-  // eigenstrain direction classes and their scalar windows
+  // eigenstrain direction classes and their scalar windows; the classes of a
+  // new defect list are assigned when first needed (classes_ok false until then)
+  bool classes_ok = true;
   std::vector<std::array<double, 6>> classes;
+  ClassTag* tags = nullptr;
+  size_t tags_cap = 0;
   double* dirs = nullptr;
   double* gcls = nullptr;
   size_t gcls_bytes = 0;
@@ -142,7 +146,7 @@ struct ec_state {
   double* updE = nullptr;     // 6 doubles
   int64_t* updfix = nullptr;  // 6 int64
   // pinned staging: defect table, per-update records, moved footprint
-  Pinned pin_tab, pin_upd, pin_ids;
+  Pinned pin_tab, pin_upd, pin_ids, pin_tags;
   // profiling
   bool prof = false;
   std::vector<ProfRec> recs;
@@ -599,9 +603,35 @@ int window_need(const ec_state* st) {
   return std::min(D, st->n / 2);
 }
 
+// Direction classes of the current defect list, assigned on the host (ids in
+// order of first appearance) and written into the device table.
+ec_status ensure_classes(ec_state* st, hipStream_t s) {
+  if (st->classes_ok) return EC_OK;
+  const size_t nd = st->hdefs.size();
+  ec_status r;
+  if (nd > 0 && (r = st_grow(st, &st->tags, &st->tags_cap, nd)) != EC_OK) return r;
+  const std::vector<std::array<double, 6>> old = st->classes;
+  st->classes.clear();
+  for (auto& d : st->hdefs) assign_class(st, d);
+  if (old != st->classes) st->gcls_ncls = -1;
+  if (nd > 0) {
+    char* hp = nullptr;
+    if ((r = pin_begin(st->pin_tags, nd * sizeof(ClassTag), &hp)) != EC_OK) return r;
+    ClassTag* t = (ClassTag*)hp;
+    for (size_t i = 0; i < nd; ++i) t[i] = ClassTag{st->hdefs[i].s, st->hdefs[i].cls, 0};
+    HIPCHK(hipMemcpyAsync(st->tags, hp, nd * sizeof(ClassTag), hipMemcpyHostToDevice, s));
+    if ((r = pin_end(st->pin_tags, s)) != EC_OK) return r;
+    LAUNCH(st, s, PF_OTHER, 0, launch_set_class(st->db[st->cur].tab, (int)nd, st->tags, s));
+  }
+  st->classes_ok = true;
+  return EC_OK;
+}
+
 ec_status compute_self_terms(ec_state* st, hipStream_t s) {
+  ec_status r = ensure_classes(st, s);
+  if (r != EC_OK) return r;
   const int need = window_need(st);
-  ec_status r = ensure_window(st, need, s);
+  r = ensure_window(st, need, s);
   if (r != EC_OK) return r;
   const WinCache* w = st->win;
   const int D = w->D;
@@ -899,6 +929,8 @@ void ec_state_destroy(ec_state* st) {
   pin_free(st->pin_tab);
   pin_free(st->pin_upd);
   pin_free(st->pin_ids);
+  pin_free(st->pin_tags);
+  ledger_free(c, st->tags, st->tags_cap * sizeof(ClassTag));
   for (auto& r : st->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -918,37 +950,29 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   if (!st) return fail(EC_ERR_ARG, "state is NULL");
   if (ndef < 0 || (ndef > 0 && !defs)) return fail(EC_ERR_ARG, "bad defect array");
   hipStream_t s = (hipStream_t)stream;
-  // 1. validate and quantise everything before touching the state
-  std::vector<DevDefect> h(ndef);
+  // 1. validate and quantise everything before touching the state, straight
+  // into the pinned staging buffer of the device table; footprint slots from
+  // the box volumes
+  ec_status r;
+  char* hp = nullptr;
+  if ((r = pin_begin(st->pin_tab, std::max<size_t>(ndef, 1) * sizeof(DevDefect), &hp)) != EC_OK) return r;
+  DevDefect* h = (DevDefect*)hp;
   std::string err;
-  for (int i = 0; i < ndef; ++i)
-    if (!quantise(st->prob, defs[i], h[i], err)) return fail(EC_ERR_ARG, "defect %d: %s", i, err.c_str());
-  std::vector<std::array<double, 6>> old_classes = st->classes;
-  st->classes.clear();
-  for (auto& d : h) assign_class(st, d);
-  const bool classes_changed = old_classes != st->classes;
-  // 2. footprint slots of the new list (box volumes) in the spare buffers
-  std::vector<int64_t> cap(ndef);
   int64_t total = 0;
   for (int i = 0; i < ndef; ++i) {
+    if (!quantise(st->prob, defs[i], h[i], err)) return fail(EC_ERR_ARG, "defect %d: %s", i, err.c_str());
     h[i].slot = total;
-    cap[i] = box_volume(h[i]);
-    total += cap[i];
+    total += box_volume(h[i]);
   }
+  // 2. buffers of the new list (the spare set)
   DefBuf& nb = st->db[1 - st->cur];
-  ec_status r;
   size_t idcap = (size_t)nb.ids_cap, lkcap = (size_t)nb.ids_cap;
   const size_t need = (size_t)std::max<int64_t>(total, 1);
   if ((r = ensure_defbuf(st, nb, ndef)) != EC_OK || (r = ensure_per_defect(st, ndef)) != EC_OK ||
-      (r = st_grow(st, &nb.ids, &idcap, need)) != EC_OK || (r = st_grow(st, &nb.lnk, &lkcap, need)) != EC_OK) {
-    st->classes = old_classes;
+      (r = st_grow(st, &nb.ids, &idcap, need)) != EC_OK || (r = st_grow(st, &nb.lnk, &lkcap, need)) != EC_OK)
     return r;
-  }
   nb.ids_cap = (int64_t)std::min(idcap, lkcap);
   if (ndef > 0) {
-    char* hp = nullptr;
-    if ((r = pin_begin(st->pin_tab, ndef * sizeof(DevDefect), &hp)) != EC_OK) return r;
-    std::memcpy(hp, h.data(), ndef * sizeof(DevDefect));
     HIPCHK(hipMemcpyAsync(nb.tab, hp, ndef * sizeof(DevDefect), hipMemcpyHostToDevice, s));
     if ((r = pin_end(st->pin_tab, s)) != EC_OK) return r;
   }
@@ -958,17 +982,20 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
     LAUNCH(st, s, PF_RASTER, 0, launch_unraster(ob.tab, st->ndef, ob.cnt, ob.ids, st->own, s));
   LAUNCH(st, s, PF_RASTER, 0, launch_raster_fill(nb.tab, ndef, st->n, nb.ids, nb.lnk, nb.cnt, st->own, s));
   st->cur = 1 - st->cur;
-  st->hdefs.swap(h);
-  st->hcap.swap(cap);
   st->hcnt_ok = false;
   st->ndef = ndef;
   st->ids_used = total;
   st->B_valid = false;
-  if (classes_changed) st->gcls_ncls = -1;
+  st->classes_ok = false;
   LAUNCH(st, s, PF_OTHER, 0,
          launch_mean_stress(nb.tab, nb.cnt, ndef, st->n3, st->C, st->prob.bc, st->add6, s));
   // 4. Fourier solve
   r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6);
+  // host copies of the list while the device works (the staging buffer is
+  // only read by the pending upload)
+  st->hdefs.assign(h, h + ndef);
+  st->hcap.resize(ndef);
+  for (int i = 0; i < ndef; ++i) st->hcap[i] = box_volume(h[i]);
   if (r != EC_OK) return r;
   st->solved = true;
   if (eps_out && (r = write_field(st, 1, eps_out, on_device != 0, s)) != EC_OK) return r;
@@ -998,6 +1025,10 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
   DevDefect nd;
   std::string err;
   if (!quantise(st->prob, *moved, nd, err)) return fail(EC_ERR_ARG, "moved defect: %s", err.c_str());
+  {
+    const ec_status rc = ensure_classes(st, s);
+    if (rc != EC_OK) return rc;
+  }
   const DevDefect od = st->hdefs[idx];
   const int n = st->n;
   // whole-voxel move of the same shape: the footprint translates and B_i is unchanged

@@ -249,6 +249,14 @@ struct SelfWork {
 hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int n,
                              const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
                              int32_t* wcnt, int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s);
+// Eigenstrain direction class of a defect (index into the class windows, -1
+// for the generic path) and its scale s (E = s e).
+struct ClassTag {
+  double s;
+  int32_t cls, pad;
+};
+// Writes tags[i] into defs[i].cls / defs[i].s.
+hipError_t launch_set_class(DevDefect* d, int ndef, const ClassTag* tags, hipStream_t s);
 // which 0: sigma, 1: eps = C^-1:sigma + eps*, 2: eps* alone; out is float or double.
 hipError_t launch_sig_to_out(const double* sig, const int32_t* own, const int2* lnk, const DevDefect* defs, int64_t n3,
                              Cubic C, int which, bool fp32, void* out, hipStream_t s);

@@ -263,7 +263,22 @@ __global__ void k_sig_to_out(const double* __restrict__ sig, const int32_t* __re
   for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)(e[a] + es[a]);
 }
 
+__global__ __launch_bounds__(256) void k_set_class(DevDefect* __restrict__ defs, int ndef,
+                                                   const ClassTag* __restrict__ tags) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < ndef) {
+    defs[i].cls = tags[i].cls;
+    defs[i].s = tags[i].s;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_set_class(DevDefect* d, int ndef, const ClassTag* tags, hipStream_t s) {
+  if (ndef <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_class, dim3((ndef + 255) / 256), dim3(256), 0, s, d, ndef, tags);
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, const double* sig,
                          int64_t n3, const double* B, double h3c, double* S6, double* E, hipStream_t s) {
