@@ -254,13 +254,20 @@ class State:
         _check(load().ec_interaction_energies(self.h, _stream_handle(stream), E.ctypes.data, 0))
         return E
 
-    def update(self, idx: int, defect, stream=None, energies: bool = True):
+    def update(self, idx: int, defect, stream=None, energies: bool = True, out=None):
+        """Move defect ``idx`` to ``defect``.  Energies of all defects after the
+        move: a host array (``energies``), written to a device tensor ``out``
+        without synchronising, or not computed."""
         d = as_defects(defect)
-        if energies:
-            E = np.zeros(self.ndef)
-            _check(load().ec_update_defect(self.h, idx, d.ctypes.data, _stream_handle(stream), E.ctypes.data, 0))
+        h = _stream_handle(stream)
+        if out is not None and not isinstance(out, np.ndarray):
+            _check(load().ec_update_defect(self.h, idx, d.ctypes.data, h, out.data_ptr(), 1))
+            return out
+        if energies or out is not None:
+            E = np.zeros(self.ndef) if out is None else out
+            _check(load().ec_update_defect(self.h, idx, d.ctypes.data, h, E.ctypes.data, 0))
             return E
-        _check(load().ec_update_defect(self.h, idx, d.ctypes.data, _stream_handle(stream), None, 0))
+        _check(load().ec_update_defect(self.h, idx, d.ctypes.data, h, None, 0))
         return None
 
     def footprints(self):

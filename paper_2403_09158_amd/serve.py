@@ -1,0 +1,333 @@
+"""Request loop serving many OkMC replicas on one device (continuous batching).
+
+A replica is one defect population on its own periodic grid (its own size and
+defect count) with a resident state on the device: owner map, footprints,
+half spectrum, FP64 stress and energies.  Requests arrive over time and either
+move one defect of a replica by a whole-voxel hop (the incremental update of
+App. A, most requests) or re-solve the replica's current defect list.  Every
+request ends with the replica's interaction energies in host memory.
+
+The loop
+  * keeps one FIFO per replica and runs a replica's requests one after the
+    other (an OkMC replica needs the energies of its last event before it can
+    pick the next one);
+  * admits a replica's state against the context's HBM budget; when the budget
+    is full it evicts the least recently used idle replica, whose state is
+    rebuilt by a solve of its current defect list when it runs again;
+  * runs up to ``slots`` requests of different replicas at the same time, each
+    on a stream of its own, so their kernels overlap on the device, and hands a
+    slot to the next ready request as soon as its request completes (a slot is
+    refilled immediately; requests are not drained in rounds);
+  * times every request from its arrival to the completion of the copy of its
+    energies to host memory, using device events.
+
+All device work goes through the C ABI in ``libec.so``; this module only
+schedules it.  ``run_plain`` is the reference it is compared with: the same
+requests one at a time through the synchronous calls, nothing overlapped.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+
+import numpy as np
+
+from . import ec, inputs
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    replica: int
+    t: float  # arrival time, seconds after the start of the trace
+    op: str  # "update" or "solve"
+    idx: int = -1  # moved defect (updates)
+    hop: tuple = (0, 0, 0)  # whole-voxel displacement (updates)
+
+
+def config4_requests(replicas, nreq: int, rate_per_s: float = 2000.0, update_frac: float = 0.9):
+    """Poisson request trace over ``replicas`` (list of (problem, defects))."""
+    t, rep, is_update, draw, hop = inputs.config4_trace(len(replicas), nreq, rate_per_s, update_frac)
+    out = []
+    for k in range(nreq):
+        r = int(rep[k])
+        ndef = len(replicas[r][1])
+        if is_update[k]:
+            out.append(Request(k, r, float(t[k]), "update", int(draw[k] * ndef), tuple(int(v) for v in inputs.HOPS111[hop[k]])))
+        else:
+            out.append(Request(k, r, float(t[k]), "solve"))
+    return out
+
+
+def moved_defect(defs: np.ndarray, req: Request, h: float) -> np.ndarray:
+    """The defect record of ``req`` after its hop (centre shifted by hop * h)."""
+    d = defs[req.idx].copy()
+    d["c"] = d["c"] + np.asarray(req.hop, dtype=np.float64) * h
+    return d
+
+
+class _Replica:
+    def __init__(self, k: int, problem, defects):
+        self.k = k
+        self.problem = problem
+        self.defs = ec.as_defects(defects).copy()
+        self.state = None
+        self.solved = False
+        self.queue = collections.deque()
+        self.busy = False
+        self.last_used = -1.0
+        self.E_dev = None
+        self.energies_ok = False
+
+
+class _Slot:
+    def __init__(self, torch, max_ndef: int):
+        self.stream = torch.cuda.Stream()
+        self.done = torch.cuda.Event(enable_timing=True)
+        self.E_host = torch.empty(max(1, max_ndef), dtype=torch.float64, pin_memory=True)
+        self.req = None
+
+
+@dataclasses.dataclass
+class ServeStats:
+    completed: int
+    wall_s: float
+    throughput: float  # requests per second
+    p50_ms: float
+    p99_ms: float
+    mean_ms: float
+    admissions: int
+    evictions: int
+    latency_ms: np.ndarray
+    results: dict  # rid -> energies (when kept)
+
+
+class Server:
+    """Continuous-batching request loop over replicas sharing one context."""
+
+    def __init__(self, ctx: ec.Context, replicas, slots: int = 4, keep_results: bool = False):
+        import torch
+
+        self.torch = torch
+        self.ctx = ctx
+        self.reps = [_Replica(k, p, d) for k, (p, d) in enumerate(replicas)]
+        self.keep = keep_results
+        max_ndef = max(len(r.defs) for r in self.reps)
+        self.slots = [_Slot(torch, max_ndef) for _ in range(max(1, slots))]
+        self.admissions = 0
+        self.evictions = 0
+
+    # -------------------------------------------------------------- admission
+    def _evict_one(self, keep: _Replica) -> bool:
+        """Release the least recently used idle replica other than ``keep``."""
+        idle = [r for r in self.reps if r.state is not None and not r.busy and r is not keep]
+        if not idle:
+            return False
+        victim = min(idle, key=lambda r: r.last_used)
+        victim.state.close()
+        victim.state = None
+        victim.solved = False
+        victim.E_dev = None
+        self.evictions += 1
+        return True
+
+    def _admit(self, rep: _Replica, clock: float) -> bool:
+        """Create ``rep``'s state, evicting idle replicas while the budget is
+        short.  False if nothing can be evicted now (retry later)."""
+        while True:
+            try:
+                rep.state = ec.State(self.ctx, rep.problem)
+            except ec.EcError as e:
+                if e.status != ec.EC_ERR_ADMIT or not self._evict_one(rep):
+                    if e.status != ec.EC_ERR_ADMIT:
+                        raise
+                    return False
+                continue
+            rep.E_dev = self.torch.empty(len(rep.defs), dtype=self.torch.float64, device="cuda")
+            rep.solved = False
+            self.admissions += 1
+            return True
+
+    def warm(self):
+        """Admit and solve every replica once (builds the Green windows)."""
+        for rep in self.reps:
+            if rep.state is None and not self._admit(rep, 0.0):
+                continue
+            rep.state.solve(rep.defs)
+            rep.state.energies()
+            rep.solved = rep.energies_ok = True
+        self.torch.cuda.synchronize()
+
+    # --------------------------------------------------------------- dispatch
+    def _enqueue_work(self, rep: _Replica, req: Request, s):
+        st = rep.state
+        if not rep.solved:  # rebuilt after admission: fields, then self terms
+            st.solve(rep.defs, stream=s)
+            rep.solved = True
+            rep.energies_ok = False
+        if not rep.energies_ok:  # before a move, so that a refusal cannot come after it
+            st.energies(stream=s, out=rep.E_dev)
+            rep.energies_ok = True
+        if req.op == "update":
+            d = moved_defect(rep.defs, req, rep.problem.h)
+            st.update(req.idx, d, stream=s, out=rep.E_dev)
+            rep.defs[req.idx] = d
+        else:
+            st.solve(rep.defs, stream=s)
+            st.energies(stream=s, out=rep.E_dev)
+
+    def _dispatch(self, slot: _Slot, rep: _Replica, req: Request) -> bool:
+        """Enqueue ``req`` on ``slot``.  A call refused by the budget leaves the
+        state as it was; idle replicas are then evicted and the request is
+        enqueued again.  False if the budget cannot be met now."""
+        torch = self.torch
+        s = slot.stream
+        while True:
+            try:
+                self._enqueue_work(rep, req, s)
+                break
+            except ec.EcError as e:
+                if e.status != ec.EC_ERR_ADMIT:
+                    raise
+                if not self._evict_one(rep):
+                    return False
+        with torch.cuda.stream(s):
+            slot.E_host[: len(rep.defs)].copy_(rep.E_dev, non_blocking=True)
+        slot.done.record(s)
+        slot.req = req
+        rep.busy = True
+        return True
+
+    @staticmethod
+    def _stalled(busy, rep: _Replica):
+        """A replica that does not fit even with every other one evicted and
+        nothing running would wait forever."""
+        if not busy:
+            raise ec.EcError(ec.EC_ERR_ADMIT, f"replica {rep.k} does not fit in the HBM budget on its own")
+
+    # -------------------------------------------------------------------- run
+    def run(self, requests, realtime: bool = True) -> ServeStats:
+        """Serve ``requests`` (sorted by arrival).  ``realtime``: requests become
+        visible at their arrival times; otherwise all are queued at once."""
+        torch = self.torch
+        reqs = sorted(requests, key=lambda r: r.t)
+        n = len(reqs)
+        ref = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ref.record()
+        ref.synchronize()
+        t0 = time.perf_counter()
+        arrive = np.array([r.t if realtime else 0.0 for r in reqs])
+        done_t = np.zeros(n)
+        results = {}
+        order = {r.rid: i for i, r in enumerate(reqs)}
+        ptr = 0
+        completed = 0
+        free = list(self.slots)
+        busy = []
+        waiting = collections.deque()  # replicas with queued work, in order of their head request
+        while completed < n:
+            now = time.perf_counter() - t0
+            while ptr < n and arrive[ptr] <= now:
+                rq = reqs[ptr]
+                rep = self.reps[rq.replica]
+                if not rep.queue and not rep.busy:
+                    waiting.append(rep)
+                rep.queue.append(rq)
+                ptr += 1
+            # fill free slots with the oldest ready requests
+            if free and waiting:
+                for _ in range(len(waiting)):
+                    if not free:
+                        break
+                    rep = waiting.popleft()
+                    if rep.busy or not rep.queue:
+                        continue
+                    if rep.state is None and not self._admit(rep, now):
+                        self._stalled(busy, rep)
+                        waiting.append(rep)
+                        continue
+                    slot = free.pop()
+                    rep.last_used = now
+                    if self._dispatch(slot, rep, rep.queue[0]):
+                        rep.queue.popleft()
+                        busy.append(slot)
+                    else:  # over budget until running requests finish
+                        self._stalled(busy, rep)
+                        free.append(slot)
+                        waiting.append(rep)
+            # retire finished requests
+            still = []
+            for slot in busy:
+                if slot.done.query():
+                    rq = slot.req
+                    rep = self.reps[rq.replica]
+                    i = order[rq.rid]
+                    done_t[i] = ref.elapsed_time(slot.done) * 1e-3
+                    if self.keep:
+                        results[rq.rid] = slot.E_host[: len(rep.defs)].numpy().copy()
+                    rep.busy = False
+                    rep.last_used = now
+                    if rep.queue:
+                        waiting.append(rep)
+                    slot.req = None
+                    free.append(slot)
+                    completed += 1
+                else:
+                    still.append(slot)
+            busy = still
+        wall = max(done_t.max(), 1e-9) if n else 0.0
+        lat = (done_t - arrive) * 1e3
+        return ServeStats(
+            completed=n,
+            wall_s=wall,
+            throughput=n / wall if n else 0.0,
+            p50_ms=float(np.median(lat)) if n else 0.0,
+            p99_ms=float(np.quantile(lat, 0.99)) if n else 0.0,
+            mean_ms=float(lat.mean()) if n else 0.0,
+            admissions=self.admissions,
+            evictions=self.evictions,
+            latency_ms=lat,
+            results=results,
+        )
+
+    def close(self):
+        for rep in self.reps:
+            if rep.state is not None:
+                rep.state.close()
+                rep.state = None
+
+
+def run_plain(ctx: ec.Context, replicas, requests, keep_results: bool = False):
+    """The same requests one at a time through the synchronous calls (host
+    energies after each), with every replica resident: (requests/s, per-request
+    service times in ms, results)."""
+    reps = [(p, ec.as_defects(d).copy()) for p, d in replicas]
+    states = []
+    for p, d in reps:
+        st = ec.State(ctx, p)
+        st.solve(d)
+        st.energies()
+        states.append(st)
+    svc = []
+    results = {}
+    t_start = time.perf_counter()
+    for rq in requests:
+        t = time.perf_counter()
+        p, defs = reps[rq.replica]
+        st = states[rq.replica]
+        if rq.op == "update":
+            d = moved_defect(defs, rq, p.h)
+            E = st.update(rq.idx, d)
+            defs[rq.idx] = d
+        else:
+            st.solve(defs)
+            E = st.energies()
+        svc.append((time.perf_counter() - t) * 1e3)
+        if keep_results:
+            results[rq.rid] = E.copy()
+    wall = time.perf_counter() - t_start
+    for st in states:
+        st.close()
+    return len(requests) / wall, np.array(svc), results

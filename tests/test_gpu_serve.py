@@ -1,0 +1,135 @@
+"""The request loop: results are the same alone and in the mix, admission by
+HBM budget, and latency bookkeeping.
+
+Small replicas (grids 32-64, tens of defects) keep the cases short; the loop
+is the one the benchmark runs on the full serving workload.
+"""
+import numpy as np
+import pytest
+
+from helpers import energy_ok_fp32
+from paper_2403_09158_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _replicas(nrep, prec=1, seed=0, sizes=(32, 48, 64)):
+    rng = np.random.default_rng(inputs.SEED_BASE + 700 + seed)
+    out = []
+    for _ in range(nrep):
+        n = int(rng.choice(sizes))
+        L = n * inputs.H_VOXEL
+        prob = inputs.Problem(n, L, *inputs.CUBIC_FE, prec=prec)
+        d = inputs.mixed_population(rng, int(rng.integers(10, 40)), L, inputs.H_VOXEL,
+                                    r111=(0.4, 1.6), r100=(0.5, 1.6))
+        out.append((prob, d))
+    return out
+
+
+def _check_same(got, want):
+    assert set(got) == set(want)
+    for rid in want:
+        ok = energy_ok_fp32(got[rid], want[rid])
+        assert np.all(ok), (rid, np.abs(got[rid] - want[rid]).max())
+
+
+def test_same_result_alone_and_in_the_mix():
+    from paper_2403_09158_amd import ec, serve
+
+    reps = _replicas(6)
+    reqs = serve.config4_requests(reps, 60, rate_per_s=1e6)
+    ctx = ec.Context()
+    srv = serve.Server(ctx, reps, slots=4, keep_results=True)
+    srv.warm()
+    stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert stats.completed == len(reqs)
+    _, _, alone = serve.run_plain(ctx, reps, reqs, keep_results=True)
+    _check_same(stats.results, alone)
+    # the mixed run is not merely close: each replica's arithmetic does not
+    # depend on what else runs on the device
+    exact = sum(np.array_equal(stats.results[r], alone[r]) for r in alone)
+    assert exact == len(alone)
+    ctx.close()
+
+
+def test_admission_by_budget_evicts_and_rebuilds():
+    from paper_2403_09158_amd import ec, serve
+
+    reps = _replicas(6, seed=1, sizes=(48,))
+    reqs = serve.config4_requests(reps, 40, rate_per_s=1e6)
+    # memory of the replicas when all are resident; what is not held by the
+    # states (the shared Green windows) stays for the whole run.  The budget
+    # fits the shared part, two states and the transient buffers of a window
+    # build (about 100 n^3 bytes), not all six states.
+    probe = ec.Context()
+    states = []
+    for p, d in reps:
+        st = ec.State(probe, p)
+        st.solve(d)
+        st.energies()
+        states.append(st)
+    total = probe.ledger()[0]
+    held = sorted(st.nbytes() for st in states)
+    shared = total - sum(held)
+    for st in states:
+        st.close()
+    probe.close()
+    budget = int(shared + 1.2 * (held[-1] + held[-2]) + 110 * 48**3)
+    assert budget < total
+    ctx = ec.Context(budget_bytes=budget)
+    srv = serve.Server(ctx, reps, slots=2, keep_results=True)
+    stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert stats.completed == len(reqs)
+    assert stats.evictions > 0
+    assert ctx.ledger()[0] <= budget
+    ref_ctx = ec.Context()
+    _, _, alone = serve.run_plain(ref_ctx, reps, reqs, keep_results=True)
+    _check_same(stats.results, alone)
+    ref_ctx.close()
+    ctx.close()
+
+
+def test_replica_larger_than_budget_is_reported():
+    from paper_2403_09158_amd import ec, serve
+
+    reps = _replicas(2, seed=3)
+    reqs = serve.config4_requests(reps, 4, rate_per_s=1e6)
+    ctx = ec.Context(budget_bytes=1 << 20)
+    srv = serve.Server(ctx, reps, slots=2)
+    with pytest.raises(ec.EcError) as ei:
+        srv.run(reqs, realtime=False)
+    assert ei.value.status == ec.EC_ERR_ADMIT
+    srv.close()
+    ctx.close()
+
+
+def test_state_beyond_budget_is_refused():
+    from paper_2403_09158_amd import ec
+
+    ctx = ec.Context(budget_bytes=1 << 20)
+    prob = inputs.Problem(64, 64 * inputs.H_VOXEL, *inputs.CUBIC_FE, prec=1)
+    with pytest.raises(ec.EcError) as ei:
+        ec.State(ctx, prob)
+    assert ei.value.status == ec.EC_ERR_ADMIT
+    assert ctx.ledger()[0] == 0
+    ctx.close()
+
+
+def test_realtime_latency_bookkeeping():
+    from paper_2403_09158_amd import ec, serve
+
+    reps = _replicas(4, seed=2)
+    reqs = serve.config4_requests(reps, 80, rate_per_s=4000.0)
+    ctx = ec.Context()
+    srv = serve.Server(ctx, reps, slots=4)
+    srv.warm()
+    stats = srv.run(reqs, realtime=True)
+    srv.close()
+    ctx.close()
+    assert stats.completed == len(reqs)
+    assert np.all(stats.latency_ms > 0)
+    assert stats.p50_ms <= stats.p99_ms
+    # the trace spans about 80 / 4000 s; the loop cannot finish before the last arrival
+    assert stats.wall_s >= max(r.t for r in reqs)
