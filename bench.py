@@ -132,6 +132,92 @@ def cpu_baseline(prob, defs, green_planes=16, self_sample=100):
     }
 
 
+def family_table(prof):
+    return {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / max(v["launches"], 1), 5),
+                "GBps": round(v["bytes_per_launch"] / max(v["ms"] / max(v["launches"], 1), 1e-9) / 1e6, 1)}
+            for k, v in prof.items() if v["launches"]}
+
+
+def energy_errors(E32, E64):
+    import numpy as np
+
+    err = np.abs(E32 - E64)
+    tol = np.maximum(1e-4 * np.abs(E64), 1e-5)
+    return {
+        "max_abs_eV": float(err.max()),
+        "p50_abs_eV": float(np.median(err)),
+        "p99_abs_eV": float(np.quantile(err, 0.99)),
+        "pass_fraction": float(np.mean(err <= tol)),
+        "max_err_over_tol": float(np.max(err / tol)),
+    }
+
+
+def serving_block(nreq=4000, rate=2000.0, slots=4, plain_req=1000):
+    """Serving workload: 64 replicas (grids 64-240, 50-1500 defects), Poisson
+    arrivals, 90 % one-defect hops, 10 % re-solves."""
+    import numpy as np
+
+    from paper_2403_09158_amd import ec, inputs, serve
+
+    reps = inputs.config4_replicas(64, prec=1)
+    out = {
+        "workload": "config4: 64 replicas, n ~ U{64,96,128,160,240}, 50-1500 defects each (config-3 mix), "
+        f"Poisson {rate:.0f} req/s, 90% (+-1,+-1,+-1) hops of a random defect, 10% re-solves",
+        "slots": slots,
+    }
+    ctx = ec.Context(0)
+    srv = serve.Server(ctx, reps, slots=slots)
+    srv.warm()
+    st = srv.run(serve.config4_requests(reps, nreq, rate), realtime=True)
+    out["fp32_served"] = {"requests": nreq, "throughput_req_s": round(st.throughput, 1), "p50_ms": round(st.p50_ms, 4),
+                          "p99_ms": round(st.p99_ms, 4), "mean_ms": round(st.mean_ms, 4)}
+    st = srv.run(serve.config4_requests(reps, 3000, 1e9), realtime=False)
+    out["fp32_saturated"] = {"requests": 3000, "throughput_req_s": round(st.throughput, 1),
+                             "p99_ms_queued_at_t0": round(st.p99_ms, 2)}
+    srv.close()
+    ctx.close()
+    ctx = ec.Context(0)
+    reps64 = [(p.with_(prec=0), d) for p, d in reps]
+    thr, svc, _ = serve.run_plain(ctx, reps64, serve.config4_requests(reps, plain_req, rate))
+    ctx.close()
+    out["fp64_plain"] = {"requests": plain_req, "throughput_req_s": round(thr, 1),
+                         "service_p50_ms": round(float(np.median(svc)), 4),
+                         "service_p99_ms": round(float(np.quantile(svc, 0.99)), 4)}
+    out["saturated_fp32_over_plain_fp64"] = round(out["fp32_saturated"]["throughput_req_s"] / thr, 3)
+    return out
+
+
+def config5_block(steps=3):
+    """512^3, 20000 defects: FP32 and FP64 solve + energies, per-pass rates and
+    the FP32 energy error against the FP64 path."""
+    import torch
+
+    from paper_2403_09158_amd import ec, inputs
+
+    prob, defs = inputs.config5(prec=1)
+    ctx = ec.Context(0)
+    out = {"workload": "config5: 512^3 periodic cell, 160 nm, 20000 defects (config-3 mix, loops up to 8 nm)"}
+    E = {}
+    for prec, name in ((1, "fp32"), (0, "fp64")):
+        st = ec.State(ctx, prob.with_(prec=prec))
+        st.solve(defs)
+        st.energies()
+        torch.cuda.synchronize()
+        st.profile(True)
+        st.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st.solve(defs)
+            E[prec] = st.energies()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"ms_per_resolve": round(dt * 1e3, 3), "per_family": family_table(st.profile_read())}
+        st.close()
+    out["fp32_vs_fp64"] = energy_errors(E[1], E[0])
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +227,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true", help="time the FP32 path only (profiling runs)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the many-replica serving workload")
+    ap.add_argument("--no-config5", action="store_true", help="skip the 512^3 / 20000-defect workload")
     ap.add_argument(
         "--calibrate-copy",
         action="store_true",
@@ -221,9 +309,7 @@ def main():
             "avg_launch_ms": round(avg_ms, 5),
             "bytes_per_launch": p["bytes_per_launch"],
             "source_sha": sha,
-            "per_family": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / max(v["launches"], 1), 5),
-                                "GBps": round(v["bytes_per_launch"] / max(v["ms"] / max(v["launches"], 1), 1e-9) / 1e6, 1)}
-                           for k, v in prof.items() if v["launches"]},
+            "per_family": family_table(prof),
             # solve-level fraction against the minimal fused schedule: 240 n^3 bytes at FP32 storage
             "solve_frac_240N": round(240.0 * n**3 / (dt / args.steps) / 1e9 / HBM_PEAK_GBS, 4),
         }
@@ -255,6 +341,10 @@ def main():
     }
     st.close()
     ctx.close()
+    if not args.no_serving:
+        line["serving"] = serving_block()
+    if not args.no_config5:
+        line["config5"] = config5_block()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob64, defs)
     print(json.dumps(line), flush=True)

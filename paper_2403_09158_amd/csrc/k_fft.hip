@@ -438,7 +438,7 @@ struct FusedPlan {
   static constexpr int I2 = NSTG == 3 ? R0 : 1;
 };
 
-// columns per tile (two at N = 512, where the tile would not fit twice in LDS)
+// columns per tile (two at N = 512, where a four-column tile would not fit)
 template <int N, typename S>
 constexpr int zg_width() {
   return N >= 512 ? 2 : 4;
@@ -483,12 +483,15 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   static_assert(N % 8 == 0, "row swizzle needs whole groups of eight");
   static_assert(FP::NSTG >= 2, "the first stage must not be the last");
   using C2 = typename Cplx<S>::T;
-  __shared__ C2 buf[6 * N * W];
+  // FP64 tile in both storage precisions: rounding the whole spectrum to FP32
+  // next to the Green step and between stages roughly doubles the FP32-storage
+  // energy error, while the extra LDS costs little here
+  __shared__ double2 buf[6 * N * W];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
   const int si = N * P;
   const size_t cs = (size_t)N * N * P;
-  auto lds = [&](int f, int i) -> C2* { return &buf[((f / W) * N + zg_swz(i)) * W + f % W]; };
+  auto lds = [&](int f, int i) -> double2* { return &buf[((f / W) * N + zg_swz(i)) * W + f % W]; };
   auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
   auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
   auto in_z = [&](int i) {

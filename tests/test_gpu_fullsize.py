@@ -91,3 +91,33 @@ def test_config3_translation_invariance(ctx):
     E1 = st.energies()
     assert energy_ok_fp64(E1, E0, rtol=1e-11)
     st.close()
+
+
+def test_config5_512_fp32_against_fp64_and_sampled_footprints(ctx):
+    """512^3 / 20000 defects: too large for the oracle's solve, so the FP64
+    path (oracle-matched at smaller sizes) is the reference for the FP32 one,
+    an integer translation must leave the energies unchanged, and a sample of
+    footprints is checked voxel by voxel against the oracle's rasteriser."""
+    from oracle import raster
+    from paper_2403_09158_amd import ec
+
+    prob, defs = inputs.config5(prec=0)
+    st = ec.State(ctx, prob)
+    st.solve(defs)
+    E64 = st.energies().copy()
+    fps = st.footprints()
+    sample = np.linspace(0, len(defs) - 1, 200).astype(int)
+    for i in sample:
+        want = raster.footprint(raster.quantise(prob, defs[i]))
+        assert np.array_equal(fps[i], want), i
+    d2 = defs.copy()
+    d2["c"] = defs["c"] + np.array([-3, 7, 250]) * prob.h
+    st.solve(d2)
+    assert energy_ok_fp64(st.energies(), E64, rtol=1e-11)
+    st.close()
+    st = ec.State(ctx, prob.with_(prec=1))
+    st.solve(defs)
+    E32 = st.energies()
+    st.close()
+    ok = energy_ok_fp32(E32, E64)
+    assert np.all(ok), (np.flatnonzero(~ok)[:10], np.abs(E32 - E64)[~ok][:10])
