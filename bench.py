@@ -27,10 +27,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 
 
+# sources of the FFT-pass kernels (the families the roofline line can name)
+FFT_SOURCES = ("ec_internal.h", "fft_core.h", "k_fft.hip")
+
+
 def kernel_source_sha():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2403_09158_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in FFT_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
