@@ -7,13 +7,19 @@
 // the previous one intact.
 #include <algorithm>
 #include <array>
+#include <atomic>
+#include <climits>
 #include <cmath>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ec_internal.h"
@@ -51,6 +57,73 @@ struct WinCache {
 
 }  // namespace
 
+// Host worker threads for per-defect preparation of large defect lists.
+// run(n, fn) calls fn(c) for every chunk c in [0, n) on the workers and the
+// calling thread and returns when all chunks are done; a worker that wakes
+// after the job has closed does nothing.
+class WorkPool {
+ public:
+  explicit WorkPool(int nworkers) {
+    for (int i = 0; i < nworkers; ++i) th_.emplace_back([this] { loop(); });
+  }
+  ~WorkPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  void run(int nchunks, const std::function<void(int)>& fn) {
+    if (th_.empty() || nchunks <= 1) {
+      for (int c = 0; c < nchunks; ++c) fn(c);
+      return;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      fn_ = &fn;
+      nchunks_ = nchunks;
+      next_.store(0);
+      open_ = true;
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> lk(mu_);
+    open_ = false;
+    done_.wait(lk, [&] { return inside_ == 0; });
+    fn_ = nullptr;
+  }
+
+ private:
+  void work() {
+    for (int c; (c = next_.fetch_add(1)) < nchunks_;) (*fn_)(c);
+  }
+  void loop() {
+    uint64_t seen = 0;
+    std::unique_lock<std::mutex> lk(mu_);
+    for (;;) {
+      cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+      if (stop_) return;
+      seen = gen_;
+      if (!open_) continue;
+      ++inside_;
+      lk.unlock();
+      work();
+      lk.lock();
+      if (--inside_ == 0) done_.notify_all();
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_, done_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int nchunks_ = 0, inside_ = 0;
+  std::atomic<int> next_{0};
+  uint64_t gen_ = 0;
+  bool open_ = false, stop_ = false;
+};
+
 struct ec_ctx {
   int device = 0;
   size_t budget = 0, used = 0;
@@ -60,6 +133,7 @@ struct ec_ctx {
   std::mutex mu;
   std::map<int, double2*> tw;
   std::vector<WinCache> wins;
+  std::unique_ptr<WorkPool> pool;
 };
 
 namespace {
@@ -811,6 +885,8 @@ ec_status ec_ctx_create(int device, size_t budget, ec_alloc_fn af, ec_free_fn ff
   c->af = af;
   c->ff = ff;
   c->user = user;
+  const unsigned hw = std::thread::hardware_concurrency();
+  c->pool.reset(new WorkPool(hw > 2 ? (int)std::min(4u, hw - 1) : 0));
   *out = c;
   return EC_OK;
 }
@@ -957,10 +1033,26 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   char* hp = nullptr;
   if ((r = pin_begin(st->pin_tab, std::max<size_t>(ndef, 1) * sizeof(DevDefect), &hp)) != EC_OK) return r;
   DevDefect* h = (DevDefect*)hp;
-  std::string err;
+  {
+    // chunks of 128 defects on the context's workers; the first invalid
+    // defect in list order is reported
+    const int nch = (ndef + 127) / 128;
+    std::vector<int> bad(nch, INT_MAX);
+    std::vector<std::string> why(nch);
+    st->ctx->pool->run(nch, [&](int c) {
+      std::string e;
+      for (int i = c * 128; i < std::min(ndef, (c + 1) * 128); ++i)
+        if (!quantise(st->prob, defs[i], h[i], e)) {
+          bad[c] = i;
+          why[c] = e;
+          return;
+        }
+    });
+    for (int c = 0; c < nch; ++c)
+      if (bad[c] != INT_MAX) return fail(EC_ERR_ARG, "defect %d: %s", bad[c], why[c].c_str());
+  }
   int64_t total = 0;
   for (int i = 0; i < ndef; ++i) {
-    if (!quantise(st->prob, defs[i], h[i], err)) return fail(EC_ERR_ARG, "defect %d: %s", i, err.c_str());
     h[i].slot = total;
     total += box_volume(h[i]);
   }

@@ -24,8 +24,18 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double v) {
   s = t;
 }
 
-constexpr int RDT = 64;  // one wavefront per defect
+constexpr int RDT = 256;  // threads per defect
 
+// (s, c) += (s2, c2) for Neumaier pairs
+__device__ __forceinline__ void neumaier_merge(double& s, double& c, double s2, double c2) {
+  neumaier(s, c, s2);
+  c += c2;
+}
+
+// One workgroup per defect: S_i = sum of sigma over the footprint (six FP64
+// Neumaier sums; four members in flight per thread), combined in a fixed
+// tree (lane shuffles, then the four wavefronts in order), then
+// E_i = -h^3 c E_i:S_i - B_i.
 __global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
                                                 const int32_t* __restrict__ ids, const double* __restrict__ sig,
                                                 int64_t n3, const double* __restrict__ B, double h3c,
@@ -36,35 +46,51 @@ __global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ de
   double s[6], c[6];
 #pragma unroll
   for (int a = 0; a < 6; ++a) s[a] = c[a] = 0.0;
-  for (int k = threadIdx.x; k < m; k += RDT) {
+  int k = threadIdx.x;
+  for (; k + 3 * RDT < m; k += 4 * RDT) {
+    int id[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) id[j] = ids[o + k + j * RDT];
+    double v[4][6];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int a = 0; a < 6; ++a) v[j][a] = sig[a * n3 + id[j]];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int a = 0; a < 6; ++a) neumaier(s[a], c[a], v[j][a]);
+  }
+  for (; k < m; k += RDT) {
     const int id = ids[o + k];
 #pragma unroll
     for (int a = 0; a < 6; ++a) neumaier(s[a], c[a], sig[a * n3 + id]);
   }
-  __shared__ double ps[6][RDT], pc[6][RDT];
+  for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-  for (int a = 0; a < 6; ++a) {
-    ps[a][threadIdx.x] = s[a];
-    pc[a][threadIdx.x] = c[a];
-  }
-  __syncthreads();
-  if (threadIdx.x < 6) {
-    const int a = threadIdx.x;
-    double ss = 0.0, cc = 0.0;
-    for (int t = 0; t < RDT; ++t) {
-      neumaier(ss, cc, ps[a][t]);
-      cc += pc[a][t];
+    for (int a = 0; a < 6; ++a) {
+      const double s2 = __shfl_down(s[a], off), c2 = __shfl_down(c[a], off);
+      neumaier_merge(s[a], c[a], s2, c2);
     }
-    ps[a][0] = ss + cc;
-  }
+  __shared__ double ws[RDT / 64][6], wc[RDT / 64][6];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      ws[wave][a] = s[a];
+      wc[wave][a] = c[a];
+    }
   __syncthreads();
   if (threadIdx.x == 0) {
     const DevDefect d = defs[i];
     double dot = 0.0;
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-      dot += ddot_w(a) * d.E[a] * ps[a][0];
-      if (S6) S6[6 * i + a] = ps[a][0];
+      double ss = ws[0][a], cc = wc[0][a];
+      for (int w = 1; w < RDT / 64; ++w) neumaier_merge(ss, cc, ws[w][a], wc[w][a]);
+      const double S = ss + cc;
+      dot += ddot_w(a) * d.E[a] * S;
+      if (S6) S6[6 * i + a] = S;
     }
     E[i] = -h3c * dot - B[i];
   }
@@ -165,11 +191,28 @@ __global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs,
     const int64_t o = defs[i].slot;
     const int cls = defs[i].cls;
     const bool staged = m <= SMAX;
+    // Footprints whose bounding box fits the window (every box offset within
+    // +-D, the usual case) use box-relative coordinates: the window index of a
+    // pair is then a difference of per-voxel linear indices, with no minimum
+    // image.  Larger boxes (extent above half the cell) keep the
+    // minimum-image path on packed coordinates.
+    const int lx = defs[i].lo[0], ly = defs[i].lo[1], lz = defs[i].lo[2];
+    const bool lin = defs[i].w[0] <= D + 1 && defs[i].w[1] <= D + 1 && defs[i].w[2] <= D + 1;
+    auto linear = [&](int id) -> int32_t {
+      int x = id % n - lx, y = (id / n) % n - ly, z = id / (n * n) - lz;
+      x += x < 0 ? n : 0;
+      y += y < 0 ? n : 0;
+      z += z < 0 ? n : 0;
+      return (z * W + y) * W + x;
+    };
+    auto enc = [&](int id) -> int32_t { return lin ? linear(id) : pack_xyz(id, n); };
     if (staged)
-      for (int k = threadIdx.x; k < m; k += ST) pk[k] = pack_xyz(ids[o + k], n);
+      for (int k = threadIdx.x; k < m; k += ST) pk[k] = enc(ids[o + k]);
     __syncthreads();
-    auto coord = [&](int k) -> int32_t { return staged ? pk[k] : pack_xyz(ids[o + k], n); };
+    auto coord = [&](int k) -> int32_t { return staged ? pk[k] : enc(ids[o + k]); };
+    const int C0 = (D * W + D) * W + D;  // window index of offset 0
     auto widx = [&](int32_t P, int32_t Q) -> int {
+      if (lin) return P - Q + C0;
       int rx = (P & 1023) - (Q & 1023), ry = ((P >> 10) & 1023) - ((Q >> 10) & 1023), rz = (P >> 20) - (Q >> 20);
       rx += rx < -h ? n : (rx >= h ? -n : 0);
       ry += ry < -h ? n : (ry >= h ? -n : 0);
@@ -181,9 +224,20 @@ __global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs,
       const double* g = gcls + (size_t)cls * W * W * W;
       for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
         const int32_t P = coord(p);
-        for (int q = p + lane; q < m; q += 64) {
-          const double v = g[widx(P, coord(q))];
-          acc += (q == p) ? v : 2.0 * v;
+        // the diagonal term once, every other pair twice (q > p)
+        if (lane == 0) acc += g[C0];
+        int q = p + 1 + lane;
+        if (lin) {
+          const double* gp = g + (P + C0);
+          // four window loads in flight per lane before they are summed
+          for (; q + 192 < m; q += 256) {
+            const double v0 = gp[-coord(q)], v1 = gp[-coord(q + 64)];
+            const double v2 = gp[-coord(q + 128)], v3 = gp[-coord(q + 192)];
+            acc += 2.0 * ((v0 + v1) + (v2 + v3));
+          }
+          for (; q < m; q += 64) acc += 2.0 * gp[-coord(q)];
+        } else {
+          for (; q < m; q += 64) acc += 2.0 * g[widx(P, coord(q))];
         }
       }
     } else {

@@ -129,6 +129,12 @@ __device__ __forceinline__ void green_bin(double2* e, int kx, int ky, int kz, in
 
 // ----------------------------------------------------------------- x forward (R2C)
 
+// LDS staging type of the x-forward transforms
+template <typename S>
+struct XfStage {
+  using T = double2;
+};
+
 template <int N, typename S, bool DENSE>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
     const int32_t* __restrict__ own, const int2* __restrict__ lnk, const DevDefect* __restrict__ defs,
@@ -138,7 +144,8 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   constexpr int T = pick_T(max_nb(N, NF));
   constexpr int LDN = N + N / 16 + 1;
   constexpr int NH = N / 2 + 1;
-  __shared__ double2 buf[NF * LDN];
+  using LT = typename XfStage<S>::T;
+  __shared__ LT buf[NF * LDN];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
   const int bpp = N / ROWS;
@@ -146,7 +153,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   const int y0 = (blockIdx.x % bpp) * ROWS;
   const size_t n3 = (size_t)N * N * N;
   const size_t cs = (size_t)N * N * P;
-  auto lds = [&](int f, int i) -> double2& { return buf[f * LDN + i + (i >> 4)]; };
+  auto lds = [&](int f, int i) -> LT* { return &buf[f * LDN + i + (i >> 4)]; };
   // gather the rows' six components into the transform inputs (xx + i yy, ...);
   // all of a thread's voxel links are loaded first, then the owners' records
   constexpr int KV = (ROWS * N + T - 1) / T;
@@ -177,18 +184,18 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
         for (int c = 0; c < 6; ++c) e[c] = (double)acc[c] * FIX_INV;
       }
 #pragma unroll
-      for (int p = 0; p < 3; ++p) lds(3 * r + p, x) = make_double2(e[2 * p], e[2 * p + 1]);
+      for (int p = 0; p < 3; ++p) st2(lds(3 * r + p, x), make_double2(e[2 * p], e[2 * p + 1]));
     }
   }
   __syncthreads();
-  auto from_lds = [&](int f, int i) { return lds(f, i); };
-  auto to_lds = [&](int f, int i, double2 v) { lds(f, i) = v; };
+  auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
+  auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
   transform<N, false, Map::Row, NF, T, true, true>(tw, from_lds, from_lds, to_lds, to_lds);
   __syncthreads();
   for (int e = threadIdx.x; e < NF * NH; e += T) {
     const int f = e / NH, k = e % NH;
-    const double2 zk = lds(f, k);
-    const double2 zc = conjd(lds(f, k == 0 ? 0 : N - k));
+    const double2 zk = ld2(lds(f, k));
+    const double2 zc = conjd(ld2(lds(f, k == 0 ? 0 : N - k)));
     const double2 A = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
     const double2 B = make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x));
     const int p = f % 3, y = y0 + f / 3;

@@ -84,6 +84,26 @@ def test_invalid_defect_rejected_state_unchanged(ctx):
     assert np.array_equal(st.energies(), E0)
 
 
+def test_first_invalid_defect_of_a_long_list_is_reported(ctx):
+    """Long lists are validated in parallel chunks; the error names the first
+    invalid defect in list order and the state keeps its previous solve."""
+    from paper_2403_09158_amd import ec
+
+    prob, d = _mixed(48, 600, 11)
+    st = _state(ctx, prob)
+    st.solve(d)
+    E0 = st.energies().copy()
+    bad = d.copy()
+    bad[517]["radius"] = -1.0
+    bad[300]["radius"] = prob.L
+    with pytest.raises(ec.EcError) as ei:
+        st.solve(bad)
+    assert ei.value.status == ec.EC_ERR_ARG
+    assert "defect 300" in str(ei.value)
+    assert np.array_equal(st.energies(), E0)
+    st.close()
+
+
 # --------------------------------------------------------------- single passes
 
 
@@ -238,6 +258,40 @@ def test_hops_match_resolve_and_oracle(ctx, prec):
         assert np.all(energy_ok_fp32(E, Er))
     assert [np.array_equal(np.sort(a), b) for a, b in zip(st.footprints(), ref.footprints())] == [True] * len(cur)
     assert np.array_equal(st.field("eps_star"), ref.field("eps_star"))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_update_drift_over_many_moves(ctx, prec):
+    """400 incremental moves (hops and a few general moves) accumulated in the
+    resident FP64 stress stay at the tolerance of a fresh solve of the final
+    list."""
+    prob, d = _mixed(64, 60, 12, prec=prec)
+    rng = np.random.default_rng(13)
+    st = _state(ctx, prob)
+    st.solve(d)
+    st.energies()
+    cur = d.copy()
+    for k in range(400):
+        i = int(rng.integers(0, len(cur)))
+        if k % 50 == 49:  # general move: off-grid shift and a new radius
+            cur[i]["c"] = cur[i]["c"] + rng.uniform(-0.4, 0.4, 3)
+            cur[i]["radius"] = cur[i]["radius"] * rng.uniform(0.8, 1.1)
+        else:
+            cur[i]["c"] = cur[i]["c"] + inputs.HOPS111[rng.integers(0, 8)] * prob.h
+        st.update(i, cur[i], energies=(k % 100 == 99))
+    E = st.energies()
+    ref = _state(ctx, prob)
+    ref.solve(cur)
+    Er = ref.energies()
+    if prec == 0:
+        assert energy_ok_fp64(E, Er)
+        assert rel_l2(st.field("sigma"), ref.field("sigma")) < 1e-12
+    else:
+        assert np.all(energy_ok_fp32(E, Er))
+        assert rel_l2(st.field("sigma"), ref.field("sigma")) < 1e-5
+    assert np.array_equal(st.field("eps_star"), ref.field("eps_star"))
+    st.close()
+    ref.close()
 
 
 def test_general_move_matches_resolve(ctx):
