@@ -1348,29 +1348,51 @@ ec_status ec_profile_read(ec_state* st, int64_t* launches, double* ms, double* b
 
 namespace {
 
+// Host arrays are [6][n][n][n/2+1] complex (re, im); the device spectrum is
+// component-interleaved with row pitch P (spec_at).
 ec_status upload_spec(ec_state* st, const double* host, void* dev) {
-  const int n = st->n, nh = n / 2 + 1;
-  const size_t rows = (size_t)6 * n * n;
+  const int n = st->n, nh = n / 2 + 1, P = st->g.P;
+  const size_t total = (size_t)6 * n * n * P;
+  std::vector<double> d(2 * total, 0.0);
+  for (int c = 0; c < 6; ++c)
+    for (int z = 0; z < n; ++z)
+      for (int y = 0; y < n; ++y)
+        for (int k = 0; k < nh; ++k) {
+          const size_t h = (((size_t)c * n + z) * n + y) * nh + k;
+          const size_t o = spec_at(z, y, k, c, n, P);
+          d[2 * o] = host[2 * h];
+          d[2 * o + 1] = host[2 * h + 1];
+        }
   if (st->fp64) {
-    HIPCHK(hipMemcpy2D(dev, st->g.P * 16, host, nh * 16, nh * 16, rows, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dev, d.data(), total * 16, hipMemcpyHostToDevice));
   } else {
-    std::vector<float> f(rows * nh * 2);
-    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)host[i];
-    HIPCHK(hipMemcpy2D(dev, st->g.P * 8, f.data(), nh * 8, nh * 8, rows, hipMemcpyHostToDevice));
+    std::vector<float> f(2 * total);
+    for (size_t i = 0; i < f.size(); ++i) f[i] = (float)d[i];
+    HIPCHK(hipMemcpy(dev, f.data(), total * 8, hipMemcpyHostToDevice));
   }
   return EC_OK;
 }
 
 ec_status download_spec(ec_state* st, const void* dev, double* host) {
-  const int n = st->n, nh = n / 2 + 1;
-  const size_t rows = (size_t)6 * n * n;
+  const int n = st->n, nh = n / 2 + 1, P = st->g.P;
+  const size_t total = (size_t)6 * n * n * P;
+  std::vector<double> d(2 * total);
   if (st->fp64) {
-    HIPCHK(hipMemcpy2D(host, nh * 16, dev, st->g.P * 16, nh * 16, rows, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(d.data(), dev, total * 16, hipMemcpyDeviceToHost));
   } else {
-    std::vector<float> f(rows * nh * 2);
-    HIPCHK(hipMemcpy2D(f.data(), nh * 8, dev, st->g.P * 8, nh * 8, rows, hipMemcpyDeviceToHost));
-    for (size_t i = 0; i < f.size(); ++i) host[i] = (double)f[i];
+    std::vector<float> f(2 * total);
+    HIPCHK(hipMemcpy(f.data(), dev, total * 8, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < f.size(); ++i) d[i] = (double)f[i];
   }
+  for (int c = 0; c < 6; ++c)
+    for (int z = 0; z < n; ++z)
+      for (int y = 0; y < n; ++y)
+        for (int k = 0; k < nh; ++k) {
+          const size_t h = (((size_t)c * n + z) * n + y) * nh + k;
+          const size_t o = spec_at(z, y, k, c, n, P);
+          host[2 * h] = d[2 * o];
+          host[2 * h + 1] = d[2 * o + 1];
+        }
   return EC_OK;
 }
 

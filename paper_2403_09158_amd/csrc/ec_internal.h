@@ -187,6 +187,14 @@ enum ProfFam { PF_RASTER = 0, PF_XF = 1, PF_Y = 2, PF_Z = 3, PF_XI = 4, PF_REDUC
 
 // ---- launch interfaces implemented in k_fft.hip ------------------------------
 
+// Half spectrum layout: [kz][ky][kx][component], kx < n/2 + 1 padded to a
+// row pitch of P, so element (c, kz, ky, kx) sits at ((kz n + ky) P + kx) 6 + c.
+// The six components of a bin are adjacent: a tile of a few kx columns reads
+// and writes contiguous runs of 6 x (columns) values in every pass.
+__host__ __device__ inline size_t spec_at(int kz, int ky, int kx, int c, int n, int P) {
+  return (((size_t)kz * n + ky) * P + kx) * 6 + c;
+}
+
 struct SpecGeom {
   int n;
   int P;  // row pitch (complex elements) of the half spectrum, >= n/2 + 1

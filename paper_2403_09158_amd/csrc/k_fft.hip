@@ -25,7 +25,6 @@ constexpr int max_nb(int N, int F) {
   return m;
 }
 constexpr int pick_T(int nb) { return nb >= 256 ? 256 : ((nb + 63) / 64) * 64; }
-constexpr int pencil_W_of(int N) { return N >= 512 ? 8 : 16; }
 constexpr int x_rows(int N) {
   int best = 1;
   for (int r = 1; r <= N; ++r)
@@ -129,12 +128,6 @@ __device__ __forceinline__ void green_bin(double2* e, int kx, int ky, int kz, in
 
 // ----------------------------------------------------------------- x forward (R2C)
 
-// LDS staging type of the x-forward transforms
-template <typename S>
-struct XfStage {
-  using T = double2;
-};
-
 template <int N, typename S, bool DENSE>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
     const int32_t* __restrict__ own, const int2* __restrict__ lnk, const DevDefect* __restrict__ defs,
@@ -144,16 +137,14 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   constexpr int T = pick_T(max_nb(N, NF));
   constexpr int LDN = N + N / 16 + 1;
   constexpr int NH = N / 2 + 1;
-  using LT = typename XfStage<S>::T;
-  __shared__ LT buf[NF * LDN];
+  __shared__ double2 buf[NF * LDN];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
   const int bpp = N / ROWS;
   const int z = blockIdx.x / bpp;
   const int y0 = (blockIdx.x % bpp) * ROWS;
   const size_t n3 = (size_t)N * N * N;
-  const size_t cs = (size_t)N * N * P;
-  auto lds = [&](int f, int i) -> LT* { return &buf[f * LDN + i + (i >> 4)]; };
+  auto lds = [&](int f, int i) -> double2* { return &buf[f * LDN + i + (i >> 4)]; };
   // gather the rows' six components into the transform inputs (xx + i yy, ...);
   // all of a thread's voxel links are loaded first, then the owners' records
   constexpr int KV = (ROWS * N + T - 1) / T;
@@ -192,16 +183,18 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
   transform<N, false, Map::Row, NF, T, true, true>(tw, from_lds, from_lds, to_lds, to_lds);
   __syncthreads();
-  for (int e = threadIdx.x; e < NF * NH; e += T) {
-    const int f = e / NH, k = e % NH;
-    const double2 zk = ld2(lds(f, k));
-    const double2 zc = conjd(ld2(lds(f, k == 0 ? 0 : N - k)));
-    const double2 A = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
-    const double2 B = make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x));
-    const int p = f % 3, y = y0 + f / 3;
-    const size_t row = ((size_t)z * N + y) * P + k;
-    st2(&spec[(size_t)(2 * p) * cs + row], A);
-    st2(&spec[(size_t)(2 * p + 1) * cs + row], B);
+  // Hermitian split of the three pair transforms of a row into the six
+  // half-spectrum components of bin k, written side by side
+  for (int e = threadIdx.x; e < ROWS * NH; e += T) {
+    const int r = e / NH, k = e % NH;
+    typename Cplx<S>::T* const out = spec + spec_at(z, y0 + r, k, 0, N, P);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const double2 zk = ld2(lds(3 * r + p, k));
+      const double2 zc = conjd(ld2(lds(3 * r + p, k == 0 ? 0 : N - k)));
+      st2(out + 2 * p, make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y)));
+      st2(out + 2 * p + 1, make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x)));
+    }
   }
 }
 
@@ -230,7 +223,6 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
   const int y0i = (blockIdx.x % rb) * ROWS;
   int z = z_lo + zi;
   if (z >= N) z -= N;
-  const size_t cs = (size_t)N * N * P;
   __syncthreads();
   auto lds = [&](int f, int i) -> double2& { return buf[f * LDN + i + (i >> 4)]; };
   // scatter +-E of the voxels that fall in this block's rows (one row per y)
@@ -271,103 +263,87 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
   auto to_lds = [&](int f, int i, double2 v) { lds(f, i) = v; };
   transform<N, false, Map::Row, NF, T, true, true>(tw, from_lds, from_lds, to_lds, to_lds);
   __syncthreads();
-  for (int e = threadIdx.x; e < NF * NH; e += T) {
-    const int f = e / NH, k = e % NH;
-    const int yi = f / 3, p = f % 3;
+  for (int e = threadIdx.x; e < ROWS * NH; e += T) {
+    const int yi = e / NH, k = e % NH;
     if (y0i + yi >= y_len) continue;
     int y = y_lo + y0i + yi;
     if (y >= N) y -= N;
-    const double2 zk = lds(f, k);
-    const double2 zc = conjd(lds(f, k == 0 ? 0 : N - k));
-    const double2 A = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
-    const double2 B = make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x));
-    const size_t row = ((size_t)z * N + y) * P + k;
-    st2(&spec[(size_t)(2 * p) * cs + row], A);
-    st2(&spec[(size_t)(2 * p + 1) * cs + row], B);
+    typename Cplx<S>::T* const out = spec + spec_at(z, y, k, 0, N, P);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const double2 zk = lds(3 * yi + p, k);
+      const double2 zc = conjd(lds(3 * yi + p, k == 0 ? 0 : N - k));
+      st2(out + 2 * p, make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y)));
+      st2(out + 2 * p + 1, make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x)));
+    }
   }
 }
 
 // --------------------------------------------------------------- y / z pencils
 //
-// A tile is W consecutive kx columns of one (component, z) plane (y pass) or one
-// (component, y) row (z pass), transformed along y or z; the kx = n/2 column is
-// tiled separately, W planes (y pass) or rows (z pass) at a time.
+// A tile is WX consecutive kx columns x all six components (6 WX transforms)
+// of one z plane (y pass) or one y row (z pass), transformed along y or z.  In
+// the component-interleaved layout every row of the tile is one contiguous
+// run of 6 WX values; thread lane f = 6 w + c keeps its (column, component)
+// across butterflies (the workgroup size is a multiple of 6 WX).  The last kx
+// tile holds the n/2 column and idle lanes.
 
-template <int N, int W>
-struct PencilTile {
-  static constexpr int KXB = (N / 2 + W - 1) / W;
-  int c, outer, kx0, nouter, z_lo;
-  bool nyq;
-  __device__ PencilTile(int bid, int nouter_, int z_lo_) : nouter(nouter_), z_lo(z_lo_) {
-    const int nreg = 6 * nouter * KXB;
-    nyq = bid >= nreg;
-    if (!nyq) {
-      kx0 = (bid % KXB) * W;
-      const int rest = bid / KXB;
-      outer = rest % nouter;
-      c = rest / nouter;
-    } else {
-      bid -= nreg;
-      const int nb = (nouter + W - 1) / W;
-      outer = (bid % nb) * W;
-      c = bid / nb;
-      kx0 = N / 2;
-    }
-  }
-  // column w -> (outer index, kx); false if outside the tile
-  __device__ __forceinline__ bool col(int w, int& o, int& kx) const {
-    if (!nyq) {
-      kx = kx0 + w;
-      o = outer;
-      return kx < N / 2;
-    }
-    kx = N / 2;
-    o = outer + w;
-    return o < nouter;
-  }
-  // element offset for axis 1 (y pass: transform index i = y) or axis 2 (z pass: i = z)
-  __device__ __forceinline__ size_t off(int axis, int o, int kx, int i, int P) const {
-    if (axis == 1) {
-      int z = z_lo + o;
-      if (z >= N) z -= N;
-      return (((size_t)c * N + z) * N + i) * P + kx;
-    }
-    return (((size_t)c * N + i) * N + o) * P + kx;
-  }
-};
+// largest radix of the pencil factorisation
+template <int N>
+constexpr int pencil_rmax() {
+  constexpr Plan2 P = plan_of(N);
+  return P.r[0] > P.r[1] ? (P.r[0] > P.r[2] ? P.r[0] : P.r[2]) : (P.r[1] > P.r[2] ? P.r[1] : P.r[2]);
+}
 
-// W columns per tile, LT = LDS staging type (double2, or float2 for FP32 storage),
-// TMAX = largest workgroup, PRUNE = input confined to a cyclic range (updates).
-constexpr int pick_T2(int nb, int tmax) { return nb >= tmax ? tmax : ((nb + 63) / 64) * 64; }
+// kx columns per tile: LDS for 6 WX transforms of N points stays at 48 KB
+template <int N, typename LT>
+constexpr int pencil_wx() {
+  constexpr int w = sizeof(LT) == 8 ? 4 : 2;
+  return N >= 512 ? w / 2 : w;
+}
 
-template <int N, typename S, bool INV, int W, typename LT, int TMAX, bool PRUNE>
-__global__ __launch_bounds__(pick_T2(max_nb(N, W), TMAX)) void k_pencil(typename Cplx<S>::T* __restrict__ spec, int P,
-                                                                      int axis, Prune pr,
-                                                                      const double2* __restrict__ twg, int ntiles) {
-  constexpr int T = pick_T2(max_nb(N, W), TMAX);
-  static_assert(T % W == 0, "a thread must keep its column across butterflies");
+// one butterfly per thread in the widest-radix stage
+template <int N, typename LT>
+constexpr int pencil_threads() {
+  return 6 * pencil_wx<N, LT>() * (N / pencil_rmax<N>());
+}
+
+template <int N, typename S, bool INV, typename LT, bool PRUNE>
+__global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename Cplx<S>::T* __restrict__ spec,
+                                                                     int P, int axis, Prune pr,
+                                                                     const double2* __restrict__ twg, int ntiles) {
+  constexpr int WX = pencil_wx<N, LT>();
+  constexpr int NF = 6 * WX;
+  constexpr int T = pencil_threads<N, LT>();
+  constexpr int NH = N / 2 + 1;
+  constexpr int KB = (NH + WX - 1) / WX;
   constexpr Plan2 PL = plan_of(N);
   constexpr int R0 = PL.r[0];
-  constexpr int NOP = ((W * (N / R0) + T - 1) / T) * R0;  // first-stage operands per thread
+  constexpr int NOP = ((NF * (N / R0) + T - 1) / T) * R0;  // first-stage operands per thread
+  static_assert(T % NF == 0, "a thread must keep its column across butterflies");
   using C2 = typename Cplx<S>::T;
-  __shared__ LT buf[N * W];
+  __shared__ LT buf[N * NF];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
-  const int nouter = axis == 1 ? pr.z_len : N;
-  const int si = axis == 1 ? P : N * P;  // element stride along the transform axis
+  // element stride along the transform axis
+  const size_t si = axis == 1 ? (size_t)6 * P : (size_t)6 * N * P;
   auto in_range = [&](int i) {
     if (!PRUNE) return true;
     int d = i - pr.in_lo;
     if (d < 0) d += N;
     return d < pr.in_len;
   };
-  // column of thread lane w in tile t (the base of the spectrum if the lane
-  // has no column in this tile)
-  auto column = [&](int t, int w, bool& valid) -> C2* {
-    const PencilTile<N, W> tile(t, nouter, pr.z_lo);
-    int o, kx;
-    valid = tile.col(w, o, kx);
-    return spec + (valid ? tile.off(axis, o, kx, 0, P) : 0);
+  // lane f's column in tile t (the base of the spectrum if the lane is idle)
+  auto column = [&](int t, int f, bool& valid) -> C2* {
+    const int o = t / KB, kx = (t % KB) * WX + f / 6;
+    valid = kx < NH;
+    if (!valid) return spec;
+    if (axis == 1) {
+      int z = pr.z_lo + o;
+      if (z >= N) z -= N;
+      return spec + spec_at(z, 0, kx, f % 6, N, P);
+    }
+    return spec + spec_at(0, o, kx, f % 6, N, P);
   };
   // FP32 storage: raw first-stage operands of the next tile are loaded while
   // the current one is transformed (rows outside the input range read row
@@ -378,12 +354,12 @@ __global__ __launch_bounds__(pick_T2(max_nb(N, W), TMAX)) void k_pencil(typename
   auto fetch = [&](int t, int tid) {
     if constexpr (!PIPE) return;
     bool v;
-    const C2* colp = column(t, tid % W, v);
-    for_operands<N, R0, Map::Pencil, W, T>(
+    const C2* colp = column(t, tid % NF, v);
+    for_operands<N, R0, Map::Pencil, NF, T>(
         [&](int, int i, int slot) { nxt[slot] = colp[(size_t)(in_range(i) ? i : pr.in_lo) * si]; }, tid);
   };
-  auto from_lds = [&](int w, int i) { return ld2(&buf[i * W + w]); };
-  auto to_lds = [&](int w, int i, double2 v) { st2(&buf[i * W + w], v); };
+  auto from_lds = [&](int f, int i) { return ld2(&buf[i * NF + f]); };
+  auto to_lds = [&](int f, int i, double2 v) { st2(&buf[i * NF + f], v); };
   // contiguous tile ranges per XCD (workgroup b runs on XCD b % 8)
   const int g8 = gridDim.x / 8;
   const int per = (ntiles + 7) / 8;
@@ -398,7 +374,7 @@ __global__ __launch_bounds__(pick_T2(max_nb(N, W), TMAX)) void k_pencil(typename
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     bool valid;
-    C2* const colp = column(t, tid % W, valid);
+    C2* const colp = column(t, tid % NF, valid);
     auto load0 = [&](int, int i, int slot) -> double2 {
       if (!(valid && in_range(i))) return make_double2(0.0, 0.0);
       return PIPE ? ld2(&nxt[slot]) : ld2(colp + (size_t)i * si);
@@ -408,18 +384,18 @@ __global__ __launch_bounds__(pick_T2(max_nb(N, W), TMAX)) void k_pencil(typename
     };
     const bool more = t + g8 < hi;
     if constexpr (PL.nstage == 1) {
-      stage<N, R0, 1, INV, Map::Pencil, W, T>(tw, load0, store_last, false, tid);
+      stage<N, R0, 1, INV, Map::Pencil, NF, T>(tw, load0, store_last, false, tid);
       if (more) fetch(t + g8, tid);
     } else {
-      stage<N, R0, 1, INV, Map::Pencil, W, T>(tw, load0, to_lds, false, tid);
+      stage<N, R0, 1, INV, Map::Pencil, NF, T>(tw, load0, to_lds, false, tid);
       if (more) fetch(t + g8, tid);
       __syncthreads();
       if constexpr (PL.nstage == 2) {
-        stage<N, PL.r[1], R0, INV, Map::Pencil, W, T>(tw, from_lds, store_last, false, tid);
+        stage<N, PL.r[1], R0, INV, Map::Pencil, NF, T>(tw, from_lds, store_last, false, tid);
       } else {
-        stage<N, PL.r[1], R0, INV, Map::Pencil, W, T>(tw, from_lds, to_lds, true, tid);
+        stage<N, PL.r[1], R0, INV, Map::Pencil, NF, T>(tw, from_lds, to_lds, true, tid);
         __syncthreads();
-        stage<N, PL.r[2], R0 * PL.r[1], INV, Map::Pencil, W, T>(tw, from_lds, store_last, false, tid);
+        stage<N, PL.r[2], R0 * PL.r[1], INV, Map::Pencil, NF, T>(tw, from_lds, store_last, false, tid);
       }
     }
     __syncthreads();  // the next tile's first stage rewrites LDS
@@ -429,9 +405,10 @@ __global__ __launch_bounds__(pick_T2(max_nb(N, W), TMAX)) void k_pencil(typename
 // ------------------------------------------- z-forward + Green + z-inverse (fused)
 //
 // One workgroup owns W kx columns of one ky row for all six components (6 W
-// transforms of length N along z) in one LDS tile: forward transforms, the
-// Green step per bin in place, inverse transforms.  The spectrum is read and
-// written once per solve instead of three times, and every stage has all six
+// transforms of length N along z, each row of the tile one contiguous run of
+// the interleaved spectrum) in one LDS tile: forward transforms, the Green
+// step per bin in place, inverse transforms.  The spectrum is read and written
+// once per solve instead of three times, and every stage has all six
 // components' butterflies to spread over the workgroup.
 
 template <int N>
@@ -451,29 +428,18 @@ constexpr int zg_width() {
   return N >= 512 ? 2 : 4;
 }
 
-// one butterfly per thread in the widest-radix stage (at most 1024 threads)
+// one butterfly per thread in the widest-radix stage; a multiple of the 6 W
+// transforms, so every lane keeps its transform
 template <int N, typename S>
 constexpr int zg_threads() {
   using FP = FusedPlan<N>;
-  constexpr int rmin = FP::R0 < FP::R1 ? FP::R0 : FP::R1;
-  constexpr int rl = FP::R2 > 1 && FP::R2 < rmin ? FP::R2 : rmin;  // smallest radix
   constexpr int rmax = FP::R0 > FP::R1 ? (FP::R0 > FP::R2 ? FP::R0 : FP::R2) : (FP::R1 > FP::R2 ? FP::R1 : FP::R2);
-  constexpr int nb = 6 * zg_width<N, S>() * (N / rmax);
-  constexpr int t = ((nb + 63) / 64) * 64;
-  static_assert(rl >= 1, "");
-  return t > 1024 ? 1024 : t;
+  return 6 * zg_width<N, S>() * (N / rmax);
 }
 
 // LDS row swizzle: the low three bits of the z index are XORed with the next
 // three, so stride-R stores of the first stages spread over all banks.
 __device__ __forceinline__ int zg_swz(int i) { return (i & ~7) | ((i ^ (i >> 3)) & 7); }
-
-// hardware dispatch places consecutive workgroups on consecutive XCDs; give
-// each XCD a contiguous run of tiles so neighbouring kx tiles share its L2
-__device__ __forceinline__ int xcd_tile(int bid, int nblk) {
-  const int per = nblk / 8;
-  return bid < per * 8 ? (bid % 8) * per + bid / 8 : bid;
-}
 
 template <int N, typename S, bool PRUNE>
 __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S>::T* __restrict__ spec, int P,
@@ -496,9 +462,8 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   __shared__ double2 buf[6 * N * W];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
-  const int si = N * P;
-  const size_t cs = (size_t)N * N * P;
-  auto lds = [&](int f, int i) -> double2* { return &buf[((f / W) * N + zg_swz(i)) * W + f % W]; };
+  const size_t si = (size_t)6 * N * P;  // kz stride
+  auto lds = [&](int f, int i) -> double2* { return &buf[zg_swz(i) * NF + f]; };
   auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
   auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
   auto in_z = [&](int i) {
@@ -515,10 +480,10 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   C2 nxt[NOP];
   auto fetch = [&](int t, int tid) {
     if constexpr (!PIPE) return;
-    const int kx = (t % KB) * W + tid % W;
-    const C2* col0 = spec + (kx < NH ? (size_t)(t / KB) * P + kx : 0);
-    for_operands<N, R0, Map::Group, NF, T, W>(
-        [&](int f, int i, int slot) { nxt[slot] = col0[(f / W) * cs + (size_t)(in_z(i) ? i : pr.in_lo) * si]; }, tid);
+    const int f0 = tid % NF, kx = (t % KB) * W + f0 / 6;
+    const C2* col0 = spec + (kx < NH ? spec_at(0, t / KB, kx, f0 % 6, N, P) : 0);
+    for_operands<N, R0, Map::Pencil, NF, T>(
+        [&](int, int i, int slot) { nxt[slot] = col0[(size_t)(in_z(i) ? i : pr.in_lo) * si]; }, tid);
   };
   // tiles split into eight contiguous ranges, one per XCD (dispatch order puts
   // workgroup b on XCD b % 8), so neighbouring kx tiles share an L2
@@ -536,23 +501,23 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int ky = t / KB;
-    const int w = tid % W;  // T and every group size are multiples of W
+    const int f0 = tid % NF, w = f0 / 6;  // lane f = 6 w + c keeps its column
     const int kx = (t % KB) * W + w;
     const bool valid = kx < NH;
-    C2* const col0 = spec + (valid ? (size_t)ky * P + kx : 0);
-    auto load0 = [&](int f, int i, int slot) -> double2 {
+    C2* const col0 = spec + (valid ? spec_at(0, ky, kx, f0 % 6, N, P) : 0);
+    auto load0 = [&](int, int i, int slot) -> double2 {
       if (!(valid && in_z(i))) return make_double2(0.0, 0.0);
-      return PIPE ? ld2(&nxt[slot]) : ld2(col0 + (f / W) * cs + (size_t)i * si);
+      return PIPE ? ld2(&nxt[slot]) : ld2(col0 + (size_t)i * si);
     };
-    stage<N, R0, 1, false, Map::Group, NF, T, W>(tw, load0, to_lds, false, tid);
+    stage<N, R0, 1, false, Map::Pencil, NF, T>(tw, load0, to_lds, false, tid);
     if (t + g8 < hi) fetch(t + g8, tid);
     __syncthreads();
     if constexpr (R2 == 1) {
-      stage<N, R1, R0, false, Map::Group, NF, T, W>(tw, from_lds, to_lds, true, tid);
+      stage<N, R1, R0, false, Map::Pencil, NF, T>(tw, from_lds, to_lds, true, tid);
     } else {
-      stage<N, R1, R0, false, Map::Group, NF, T, W>(tw, from_lds, to_lds, true, tid);
+      stage<N, R1, R0, false, Map::Pencil, NF, T>(tw, from_lds, to_lds, true, tid);
       __syncthreads();
-      stage<N, R2, R0 * R1, false, Map::Group, NF, T, W>(tw, from_lds, to_lds, true, tid);
+      stage<N, R2, R0 * R1, false, Map::Pencil, NF, T>(tw, from_lds, to_lds, true, tid);
     }
     __syncthreads();
     // Green step: one bin (all six components) per iteration, in place
@@ -562,16 +527,16 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
       if (bkx >= NH) continue;
       double2 e[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) e[c] = from_lds(c * W + bw, kz);
+      for (int c = 0; c < 6; ++c) e[c] = from_lds(bw * 6 + c, kz);
       green_bin(e, bkx, ky, kz, N, C);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) to_lds(c * W + bw, kz, e[c]);
+      for (int c = 0; c < 6; ++c) to_lds(bw * 6 + c, kz, e[c]);
     }
     __syncthreads();
-    auto store_last = [&](int f, int i, double2 v) {
-      if (valid) st2(col0 + (f / W) * cs + (size_t)i * si, v);
+    auto store_last = [&](int, int i, double2 v) {
+      if (valid) st2(col0 + (size_t)i * si, v);
     };
-    transform_plan<N, FP::I0, FP::I1, FP::I2, true, Map::Group, NF, T, W, true, false>(tw, from_lds, from_lds, to_lds,
+    transform_plan<N, FP::I0, FP::I1, FP::I2, true, Map::Pencil, NF, T, NF, true, false>(tw, from_lds, from_lds, to_lds,
                                                                                     store_last, tid);
     __syncthreads();  // the next tile's first stage rewrites the tile
   }
@@ -586,14 +551,13 @@ __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__
   const int kx = (int)(t % NH);
   const size_t r = t / NH;
   const int ky = (int)(r % n), kz = (int)(r / n);
-  const size_t cs = (size_t)n * n * P;
-  const size_t o = ((size_t)kz * n + ky) * P + kx;
+  typename Cplx<S>::T* const bin = spec + spec_at(kz, ky, kx, 0, n, P);
   double2 e[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) e[c] = ld2(&spec[c * cs + o]);
+  for (int c = 0; c < 6; ++c) e[c] = ld2(bin + c);
   green_bin(e, kx, ky, kz, n, C);
 #pragma unroll
-  for (int c = 0; c < 6; ++c) st2(&spec[c * cs + o], e[c]);
+  for (int c = 0; c < 6; ++c) st2(bin + c, e[c]);
 }
 
 // --------------------------------------------------------- x inverse (C2R) + stress
@@ -615,25 +579,19 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   const int z = blockIdx.x / bpp;
   const int y0 = (blockIdx.x % bpp) * ROWS;
   const size_t n3 = (size_t)N * N * N;
-  const size_t cs = (size_t)N * N * P;
   const double scale = 1.0 / (double)n3;
   __syncthreads();
   auto load0 = [&](int f, int k) -> double2 {
     const int p = f % 3, y = y0 + f / 3;
-    const size_t row = ((size_t)z * N + y) * P;
-    const typename Cplx<S>::T* a = spec + (size_t)(2 * p) * cs + row;
-    const typename Cplx<S>::T* b = spec + (size_t)(2 * p + 1) * cs + row;
-    double2 A, B;
-    if (k <= N / 2) {
-      A = ld2(a + k);
-      B = ld2(b + k);
-      if (k == 0 || k == N / 2) {
-        A.y = 0.0;
-        B.y = 0.0;
-      }
-    } else {
-      A = conjd(ld2(a + (N - k)));
-      B = conjd(ld2(b + (N - k)));
+    // components 2p and 2p+1 of bin k (or of its mirror n - k) are adjacent
+    const typename Cplx<S>::T* a = spec + spec_at(z, y, k <= N / 2 ? k : N - k, 2 * p, N, P);
+    double2 A = ld2(a), B = ld2(a + 1);
+    if (k > N / 2) {
+      A = conjd(A);
+      B = conjd(B);
+    } else if (k == 0 || k == N / 2) {
+      A.y = 0.0;
+      B.y = 0.0;
     }
     return make_double2(A.x - B.y, A.y + B.x);
   };
@@ -698,27 +656,23 @@ int tile_grid(K kernel, int threads, int ntiles, bool prefetch) {
   return std::max(8, (g / 8) * 8);
 }
 
-template <int N, typename S, int W, typename LT, int TMAX>
-hipError_t go_pencil_v(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, hipStream_t s) {
-  constexpr int T = pick_T2(max_nb(N, W), TMAX);
+// FP32 storage stages the inter-stage exchange in FP32 (half the LDS, so
+// twice the columns per tile); FP64 storage keeps FP64 staging.
+template <int N, typename S>
+hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, hipStream_t s) {
+  using LT = typename Cplx<S>::T;
+  constexpr int T = pencil_threads<N, LT>();
+  constexpr int KB = (N / 2 + 1 + pencil_wx<N, LT>() - 1) / pencil_wx<N, LT>();
   const int nouter = axis == 1 ? pr.z_len : N;
-  const int ntiles = 6 * nouter * PencilTile<N, W>::KXB + 6 * ((nouter + W - 1) / W);
+  const int ntiles = nouter * KB;
   using C2 = typename Cplx<S>::T;
   const bool prune = pr.in_len < N;
-  auto* k = inv ? (prune ? k_pencil<N, S, true, W, LT, TMAX, true> : k_pencil<N, S, true, W, LT, TMAX, false>)
-                : (prune ? k_pencil<N, S, false, W, LT, TMAX, true> : k_pencil<N, S, false, W, LT, TMAX, false>);
+  auto* k = inv ? (prune ? k_pencil<N, S, true, LT, true> : k_pencil<N, S, true, LT, false>)
+                : (prune ? k_pencil<N, S, false, LT, true> : k_pencil<N, S, false, LT, false>);
   const int grid = tile_grid(k, T, ntiles, sizeof(S) == 4);
   if (grid < 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis, pr, tw, ntiles);
   return hipGetLastError();
-}
-
-// FP32 storage stages the inter-stage exchange in FP32 too (half the LDS, twice
-// the resident workgroups); FP64 storage keeps FP64 staging.
-template <int N, typename S>
-hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, hipStream_t s) {
-  using LT = typename Cplx<S>::T;
-  return go_pencil_v<N, S, pencil_W_of(N), LT, 256>(inv, axis, spec, g, pr, tw, s);
 }
 
 template <int N, typename S>
