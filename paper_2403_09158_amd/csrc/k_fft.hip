@@ -184,16 +184,30 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   transform<N, false, Map::Row, NF, T, true, true>(tw, from_lds, from_lds, to_lds, to_lds);
   __syncthreads();
   // Hermitian split of the three pair transforms of a row into the six
-  // half-spectrum components of bin k, written side by side
-  for (int e = threadIdx.x; e < ROWS * NH; e += T) {
-    const int r = e / NH, k = e % NH;
-    typename Cplx<S>::T* const out = spec + spec_at(z, y0 + r, k, 0, N, P);
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
+  // interleaved half-spectrum components.  FP64 storage: one output value per
+  // thread, so consecutive threads write consecutive 16-byte values of the
+  // row; FP32 storage: one bin (six values, 48 bytes) per thread, which
+  // halves the LDS reads and index work where the narrower writes matter less.
+  if constexpr (sizeof(S) == 8) {
+    for (int e = threadIdx.x; e < ROWS * NH * 6; e += T) {
+      const int r = e / (NH * 6), q = e % (NH * 6), k = q / 6, c = q % 6, p = c >> 1;
       const double2 zk = ld2(lds(3 * r + p, k));
       const double2 zc = conjd(ld2(lds(3 * r + p, k == 0 ? 0 : N - k)));
-      st2(out + 2 * p, make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y)));
-      st2(out + 2 * p + 1, make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x)));
+      const double2 v = (c & 1) ? make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x))
+                                : make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+      st2(spec + spec_at(z, y0 + r, k, c, N, P), v);
+    }
+  } else {
+    for (int e = threadIdx.x; e < ROWS * NH; e += T) {
+      const int r = e / NH, k = e % NH;
+      typename Cplx<S>::T* const out = spec + spec_at(z, y0 + r, k, 0, N, P);
+#pragma unroll
+      for (int p = 0; p < 3; ++p) {
+        const double2 zk = ld2(lds(3 * r + p, k));
+        const double2 zc = conjd(ld2(lds(3 * r + p, k == 0 ? 0 : N - k)));
+        st2(out + 2 * p, make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y)));
+        st2(out + 2 * p + 1, make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x)));
+      }
     }
   }
 }
@@ -263,19 +277,16 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
   auto to_lds = [&](int f, int i, double2 v) { lds(f, i) = v; };
   transform<N, false, Map::Row, NF, T, true, true>(tw, from_lds, from_lds, to_lds, to_lds);
   __syncthreads();
-  for (int e = threadIdx.x; e < ROWS * NH; e += T) {
-    const int yi = e / NH, k = e % NH;
+  for (int e = threadIdx.x; e < ROWS * NH * 6; e += T) {
+    const int yi = e / (NH * 6), q = e % (NH * 6), k = q / 6, c = q % 6, p = c >> 1;
     if (y0i + yi >= y_len) continue;
     int y = y_lo + y0i + yi;
     if (y >= N) y -= N;
-    typename Cplx<S>::T* const out = spec + spec_at(z, y, k, 0, N, P);
-#pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      const double2 zk = lds(3 * yi + p, k);
-      const double2 zc = conjd(lds(3 * yi + p, k == 0 ? 0 : N - k));
-      st2(out + 2 * p, make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y)));
-      st2(out + 2 * p + 1, make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x)));
-    }
+    const double2 zk = lds(3 * yi + p, k);
+    const double2 zc = conjd(lds(3 * yi + p, k == 0 ? 0 : N - k));
+    const double2 v = (c & 1) ? make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x))
+                              : make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+    st2(spec + spec_at(z, y, k, c, N, P), v);
   }
 }
 
