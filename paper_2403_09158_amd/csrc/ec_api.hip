@@ -194,6 +194,12 @@ struct ec_state {
   double* S6 = nullptr;
   size_t pd_cap = 0;
   bool B_valid = false;
+  // self terms of a fresh solve run on a side stream beside the Fourier
+  // passes: it starts after the rasterisation (ev_fill) and every later use
+  // of the self terms or of the defect buffers waits for ev_self
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fill = nullptr, ev_self = nullptr;
+  bool self_pending = false;
   // eigenstrain direction classes and their scalar windows; the classes of a
   // new defect list are assigned when first needed (classes_ok false until then)
   bool classes_ok = true;
@@ -1007,6 +1013,9 @@ void ec_state_destroy(ec_state* st) {
   pin_free(st->pin_ids);
   pin_free(st->pin_tags);
   ledger_free(c, st->tags, st->tags_cap * sizeof(ClassTag));
+  if (st->ev_fill) (void)hipEventDestroy(st->ev_fill);
+  if (st->ev_self) (void)hipEventDestroy(st->ev_self);
+  if (st->side) (void)hipStreamDestroy(st->side);
   for (auto& r : st->recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -1018,6 +1027,29 @@ void ec_state_destroy(ec_state* st) {
 ec_status ec_state_bytes(const ec_state* st, size_t* bytes) {
   if (!st || !bytes) return fail(EC_ERR_ARG, "NULL argument");
   *bytes = st->held;
+  return EC_OK;
+}
+
+// Make stream s wait for self terms still running on the side stream.
+ec_status join_self(ec_state* st, hipStream_t s) {
+  if (!st->self_pending) return EC_OK;
+  HIPCHK(hipStreamWaitEvent(s, st->ev_self, 0));
+  st->self_pending = false;
+  return EC_OK;
+}
+
+// Self terms of the list just rasterised on stream s, computed on the side
+// stream after ev_fill while s runs the Fourier passes.
+ec_status self_terms_beside(ec_state* st) {
+  if (!st->side) {
+    HIPCHK(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&st->ev_self, hipEventDisableTiming));
+  }
+  HIPCHK(hipStreamWaitEvent(st->side, st->ev_fill, 0));
+  ec_status r = compute_self_terms(st, st->side);
+  if (r != EC_OK) return r;
+  HIPCHK(hipEventRecord(st->ev_self, st->side));
+  st->self_pending = true;
   return EC_OK;
 }
 
@@ -1069,10 +1101,13 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
     if ((r = pin_end(st->pin_tab, s)) != EC_OK) return r;
   }
   // 3. commit: remove the old eigenstrain, add the new one
+  if ((r = join_self(st, s)) != EC_OK) return r;
   const DefBuf& ob = st->db[st->cur];
   if (st->ndef > 0)
     LAUNCH(st, s, PF_RASTER, 0, launch_unraster(ob.tab, st->ndef, ob.cnt, ob.ids, st->own, s));
   LAUNCH(st, s, PF_RASTER, 0, launch_raster_fill(nb.tab, ndef, st->n, nb.ids, nb.lnk, nb.cnt, st->own, s));
+  if (!st->ev_fill) HIPCHK(hipEventCreateWithFlags(&st->ev_fill, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(st->ev_fill, s));
   st->cur = 1 - st->cur;
   st->hcnt_ok = false;
   st->ndef = ndef;
@@ -1090,6 +1125,7 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   for (int i = 0; i < ndef; ++i) st->hcap[i] = box_volume(h[i]);
   if (r != EC_OK) return r;
   st->solved = true;
+  if (ndef > 0 && (r = self_terms_beside(st)) != EC_OK) return r;
   if (eps_out && (r = write_field(st, 1, eps_out, on_device != 0, s)) != EC_OK) return r;
   if (sig_out && (r = write_field(st, 0, sig_out, on_device != 0, s)) != EC_OK) return r;
   return EC_OK;
@@ -1101,6 +1137,7 @@ ec_status ec_interaction_energies(ec_state* st, void* stream, double* E_out, int
   hipStream_t s = (hipStream_t)stream;
   ec_status r;
   if (!st->B_valid && (r = compute_self_terms(st, s)) != EC_OK) return r;
+  if ((r = join_self(st, s)) != EC_OK) return r;
   const DefBuf& b = st->db[st->cur];
   LAUNCH(st, s, PF_REDUCE, 0,
          launch_reduce(b.tab, st->ndef, b.cnt, b.ids, st->sig, st->n3, st->B, st->h3c, st->S6, st->E, s));
@@ -1118,7 +1155,8 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
   std::string err;
   if (!quantise(st->prob, *moved, nd, err)) return fail(EC_ERR_ARG, "moved defect: %s", err.c_str());
   {
-    const ec_status rc = ensure_classes(st, s);
+    ec_status rc = join_self(st, s);
+    if (rc == EC_OK) rc = ensure_classes(st, s);
     if (rc != EC_OK) return rc;
   }
   const DevDefect od = st->hdefs[idx];
