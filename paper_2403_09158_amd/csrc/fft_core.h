@@ -346,7 +346,7 @@ __host__ __device__ constexpr Plan2 plan_fused(int N) {
          : N == 128 ? Plan2{3, {8, 4, 4}}
          : N == 160 ? Plan2{3, {8, 4, 5}}
          : N == 240 ? Plan2{3, {16, 5, 3}}
-         : N == 256 ? Plan2{3, {8, 8, 4}}
+         : N == 256 ? Plan2{2, {16, 16, 1}}
          : N == 512 ? Plan2{3, {8, 16, 4}}
                     : Plan2{0, {1, 1, 1}};
 }
