@@ -1,7 +1,7 @@
 #!/usr/bin/env python
 """Benchmark: grid solves per second + energies at 256^3 (FP32 vs FP64) on one MI355X.
 
-Workload (config 3): periodic 256^3 cell, 80 nm side, cubic iron-like stiffness
+Workload (mixed_256): periodic 256^3 cell, 80 nm side, cubic iron-like stiffness
 C11/C12/C44 = 243/145/116 GPa, 2000 synthetic defects (70 % 1/2<111> loops,
 10 % <100> loops, 20 % dilatational spheres; seeded).  One step is the whole
 hot path from the defect list: rasterise, forward FFT, Green operator, inverse
@@ -129,7 +129,7 @@ def cpu_baseline(prob, defs, green_planes=16, self_sample=100):
         "cores": int(os.environ.get("ORACLE_FFT_WORKERS", "0")) or (os.cpu_count() or 1),
         "kind": "oracle",
         "sample": (
-            f"config-3 workload at 256^3: full rasterisation, FFTs and footprint sums; Green step on "
+            f"mixed_256 workload at 256^3: full rasterisation, FFTs and footprint sums; Green step on "
             f"{len(planes)}/{n} z-planes and self terms of {len(idx)}/{len(fps)} defects, scaled; "
             f"G-window setup excluded; per-stage s: " + ", ".join(f"{k}={v:.2f}" for k, v in T.items())
         ),
@@ -163,26 +163,26 @@ def serving_block(nreq=4000, rate=2000.0, slots=4, plain_req=1000):
 
     from paper_2403_09158_amd import ec, inputs, serve
 
-    reps = inputs.config4_replicas(64, prec=1)
+    reps = inputs.serving_replicas(64, prec=1)
     out = {
-        "workload": "config4: 64 replicas, n ~ U{64,96,128,160,240}, 50-1500 defects each (config-3 mix), "
+        "workload": "serving: 64 replicas, n ~ U{64,96,128,160,240}, 50-1500 defects each (mixed_256 mix), "
         f"Poisson {rate:.0f} req/s, 90% (+-1,+-1,+-1) hops of a random defect, 10% re-solves",
         "slots": slots,
     }
     ctx = ec.Context(0)
     srv = serve.Server(ctx, reps, slots=slots)
     srv.warm()
-    st = srv.run(serve.config4_requests(reps, nreq, rate), realtime=True)
+    st = srv.run(serve.serving_requests(reps, nreq, rate), realtime=True)
     out["fp32_served"] = {"requests": nreq, "throughput_req_s": round(st.throughput, 1), "p50_ms": round(st.p50_ms, 4),
                           "p99_ms": round(st.p99_ms, 4), "mean_ms": round(st.mean_ms, 4)}
-    st = srv.run(serve.config4_requests(reps, 3000, 1e9), realtime=False)
+    st = srv.run(serve.serving_requests(reps, 3000, 1e9), realtime=False)
     out["fp32_saturated"] = {"requests": 3000, "throughput_req_s": round(st.throughput, 1),
                              "p99_ms_queued_at_t0": round(st.p99_ms, 2)}
     srv.close()
     ctx.close()
     ctx = ec.Context(0)
     reps64 = [(p.with_(prec=0), d) for p, d in reps]
-    thr, svc, _ = serve.run_plain(ctx, reps64, serve.config4_requests(reps, plain_req, rate))
+    thr, svc, _ = serve.run_plain(ctx, reps64, serve.serving_requests(reps, plain_req, rate))
     ctx.close()
     out["fp64_plain"] = {"requests": plain_req, "throughput_req_s": round(thr, 1),
                          "service_p50_ms": round(float(np.median(svc)), 4),
@@ -191,16 +191,16 @@ def serving_block(nreq=4000, rate=2000.0, slots=4, plain_req=1000):
     return out
 
 
-def config5_block(steps=3):
+def mixed_512_block(steps=3):
     """512^3, 20000 defects: FP32 and FP64 solve + energies, per-pass rates and
     the FP32 energy error against the FP64 path."""
     import torch
 
     from paper_2403_09158_amd import ec, inputs
 
-    prob, defs = inputs.config5(prec=1)
+    prob, defs = inputs.mixed_512(prec=1)
     ctx = ec.Context(0)
-    out = {"workload": "config5: 512^3 periodic cell, 160 nm, 20000 defects (config-3 mix, loops up to 8 nm)"}
+    out = {"workload": "mixed_512: 512^3 periodic cell, 160 nm, 20000 defects (mixed_256 mix, loops up to 8 nm)"}
     E = {}
     for prec, name in ((1, "fp32"), (0, "fp64")):
         st = ec.State(ctx, prob.with_(prec=prec))
@@ -232,7 +232,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true", help="time the FP32 path only (profiling runs)")
     ap.add_argument("--no-serving", action="store_true", help="skip the many-replica serving workload")
-    ap.add_argument("--no-config5", action="store_true", help="skip the 512^3 / 20000-defect workload")
+    ap.add_argument("--no-512", action="store_true", help="skip the 512^3 / 20000-defect workload")
     ap.add_argument(
         "--calibrate-copy",
         action="store_true",
@@ -260,7 +260,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 1 << 30}), flush=True)
         return
-    prob32, defs = inputs.config3(prec=1)
+    prob32, defs = inputs.mixed_256(prec=1)
     prob64 = prob32.with_(prec=0)
     ctx = ec.Context(0)
 
@@ -286,7 +286,7 @@ def main():
             "fp32_pass_fraction": float(np.mean(err <= tol)),
             "fp32_max_err_over_tol": float(np.max(err / tol)),
         }
-    golden = os.path.join(ROOT, "tests", "golden", "oracle_config3.npz")
+    golden = os.path.join(ROOT, "tests", "golden", "oracle_mixed_256.npz")
     if os.path.exists(golden):
         g = np.load(golden)
         if E64 is not None:
@@ -334,7 +334,7 @@ def main():
         "dtype": "f32-storage/f64-arith",
         "data": "synthetic",
         "config": {
-            "workload": "config3: 256^3 periodic cell, 80 nm, cubic C 243/145/116 GPa, 2000 defects "
+            "workload": "mixed_256: 256^3 periodic cell, 80 nm, cubic C 243/145/116 GPa, 2000 defects "
             "(70% 1/2<111> loops, 10% <100> loops, 20% dilatational spheres)",
             "n": prob32.n,
             "ndef": int(len(defs)),
@@ -349,8 +349,8 @@ def main():
     ctx.close()
     if not args.no_serving:
         line["serving"] = serving_block()
-    if not args.no_config5:
-        line["config5"] = config5_block()
+    if not args.no_512:
+        line["mixed_512"] = mixed_512_block()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob64, defs)
     print(json.dumps(line), flush=True)

@@ -7,22 +7,24 @@ operator.  Both the FP64 oracle and the HIP path consume its output.
 
 Workload recipes (defect populations in a cubic-iron-like crystal):
 
-* ``config1``: 32^3 voxels, 10 nm box, isotropic E=210 GPa, nu=0.29; one
+* ``pair_32``: 32^3 voxels, 10 nm box, isotropic E=210 GPa, nu=0.29; one
   dilatational sphere (R = 3 voxels, eps* = 0.01 I) at a voxel centre and one
   1/2[111] interstitial loop (a = 0.2866 nm, R = 4 voxels, (111) habit, one voxel
   thick) displaced by a seeded integer voxel offset of norm >= 8.
-* ``config2``: 128^3, 40 nm, cubic C11/C12/C44 = 243/145/116 GPa; 200 1/2<111>
+* ``loops_128``: 128^3, 40 nm, cubic C11/C12/C44 = 243/145/116 GPa; 200 1/2<111>
   loops, centres uniform, R ~ U[1, 4] nm, Burgers vector uniform over the four
   1/2<111> variants, habit normal parallel to b.
-* ``config3``: 256^3, 80 nm, same C; 2000 defects: 70 % 1/2<111> loops
+* ``mixed_256``: 256^3, 80 nm, same C; 2000 defects: 70 % 1/2<111> loops
   (R log-uniform in [0.5, 5] nm), 10 % <100> loops (b = a e_k, R ~ U[1, 6] nm),
   20 % dilatational spheres (R ~ U[1, 3] voxels, eps* = v I, v ~ U[0.005, 0.02]).
-* ``config4``: serving replicas: n ~ U{64, 96, 128, 160, 240}, L = n h with
-  h = 0.3125 nm, 50-1500 defects drawn as in config3.
-* ``config5``: 512^3, 160 nm; 20000 defects as config3 but 1/2<111> R
+* ``serving_replicas``: n ~ U{64, 96, 128, 160, 240}, L = n h with
+  h = 0.3125 nm, 50-1500 defects drawn as in mixed_256.
+* ``mixed_512``: 512^3, 160 nm; 20000 defects as mixed_256 but 1/2<111> R
   log-uniform in [0.5, 8] nm and <100> R ~ U[1, 8] nm.
 
-Seeds: ``numpy.random.default_rng(240309158 + k)`` for config k.
+Seeds: ``numpy.random.default_rng(240309158 + k)`` with k = 1, 2, 3, 5 for the
+four fixed workloads above (pair_32 to mixed_512), 40 + r for serving replica r
+and 400 for the serving arrivals.
 """
 from __future__ import annotations
 
@@ -114,7 +116,7 @@ def _rng(k: int) -> np.random.Generator:
     return np.random.default_rng(SEED_BASE + k)
 
 
-def config1(seed_offset: int = 0):
+def pair_32(seed_offset: int = 0):
     """Two defects in a 32^3 isotropic cell (plain FP64 case)."""
     rng = _rng(1 + seed_offset)
     n, L = 32, 10.0
@@ -186,28 +188,28 @@ def mixed_population(rng, ndef, L, h, r111=(0.5, 5.0), r100=(1.0, 6.0)):
     return d[rng.permutation(ndef)]
 
 
-def config2(prec: int = 0):
+def loops_128(prec: int = 0):
     rng = _rng(2)
     n, L = 128, 40.0
     prob = Problem(n, L, *CUBIC_FE, prec=prec)
     return prob, _loops111(rng, 200, L, 1.0, 4.0, log_uniform=False)
 
 
-def config3(prec: int = 1):
+def mixed_256(prec: int = 1):
     rng = _rng(3)
     n, L = 256, 80.0
     prob = Problem(n, L, *CUBIC_FE, prec=prec)
     return prob, mixed_population(rng, 2000, L, L / n)
 
 
-def config5(prec: int = 1):
+def mixed_512(prec: int = 1):
     rng = _rng(5)
     n, L = 512, 160.0
     prob = Problem(n, L, *CUBIC_FE, prec=prec)
     return prob, mixed_population(rng, 20000, L, L / n, r111=(0.5, 8.0), r100=(1.0, 8.0))
 
 
-def scaled_config3(n: int, prec: int = 1, seed: int = 0):
+def scaled_mixed(n: int, prec: int = 1, seed: int = 0):
     """Config-3 defect density and size mix in an n^3 cell with h = 0.3125 nm."""
     rng = np.random.default_rng(SEED_BASE + 300 + seed)
     L = n * H_VOXEL
@@ -221,7 +223,7 @@ def scaled_config3(n: int, prec: int = 1, seed: int = 0):
 REPLICA_SIZES = (64, 96, 128, 160, 240)
 
 
-def config4_replicas(nrep: int = 64, prec: int = 1):
+def serving_replicas(nrep: int = 64, prec: int = 1):
     """Per-replica (problem, defects) for the serving workload."""
     out = []
     for r in range(nrep):
@@ -239,7 +241,7 @@ HOPS111 = np.array(
 )
 
 
-def config4_trace(nrep: int, nreq: int, rate_per_s: float = 2000.0, update_frac: float = 0.9):
+def serving_trace(nrep: int, nreq: int, rate_per_s: float = 2000.0, update_frac: float = 0.9):
     """Poisson arrival trace: (t_arrival, replica, op, defect_slot_draw, hop_index)."""
     rng = np.random.default_rng(SEED_BASE + 400)
     gaps = rng.exponential(1.0 / rate_per_s, size=nreq)

@@ -46,9 +46,9 @@ class Request:
     hop: tuple = (0, 0, 0)  # whole-voxel displacement (updates)
 
 
-def config4_requests(replicas, nreq: int, rate_per_s: float = 2000.0, update_frac: float = 0.9):
+def serving_requests(replicas, nreq: int, rate_per_s: float = 2000.0, update_frac: float = 0.9):
     """Poisson request trace over ``replicas`` (list of (problem, defects))."""
-    t, rep, is_update, draw, hop = inputs.config4_trace(len(replicas), nreq, rate_per_s, update_frac)
+    t, rep, is_update, draw, hop = inputs.serving_trace(len(replicas), nreq, rate_per_s, update_frac)
     out = []
     for k in range(nreq):
         r = int(rep[k])

@@ -35,12 +35,12 @@ def _fingerprint(fps):
     return cnt, s1, s2
 
 
-@pytest.mark.parametrize("name", ["config2", "config3"])
+@pytest.mark.parametrize("name", ["loops_128", "mixed_256"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_energies_match_stored_oracle(ctx, name, prec):
     from paper_2403_09158_amd import ec
 
-    prob, defs = {"config2": inputs.config2, "config3": inputs.config3}[name](prec=prec)
+    prob, defs = {"loops_128": inputs.loops_128, "mixed_256": inputs.mixed_256}[name](prec=prec)
     g = _golden(name)
     st = ec.State(ctx, prob)
     st.solve(defs)
@@ -59,11 +59,11 @@ def test_energies_match_stored_oracle(ctx, name, prec):
     st.close()
 
 
-def test_config3_field_properties(ctx):
+def test_mixed256_field_properties(ctx):
     """Mean stress zero and the total-energy identity on the full 256^3 fields."""
     from paper_2403_09158_amd import ec
 
-    prob, defs = inputs.config3(prec=0)
+    prob, defs = inputs.mixed_256(prec=0)
     st = ec.State(ctx, prob)
     st.solve(defs)
     E = st.energies()
@@ -78,10 +78,10 @@ def test_config3_field_properties(ctx):
     st.close()
 
 
-def test_config3_translation_invariance(ctx):
+def test_mixed256_translation_invariance(ctx):
     from paper_2403_09158_amd import ec
 
-    prob, defs = inputs.config3(prec=0)
+    prob, defs = inputs.mixed_256(prec=0)
     st = ec.State(ctx, prob)
     st.solve(defs)
     E0 = st.energies().copy()
@@ -93,7 +93,7 @@ def test_config3_translation_invariance(ctx):
     st.close()
 
 
-def test_config5_512_fp32_against_fp64_and_sampled_footprints(ctx):
+def test_mixed512_fp32_against_fp64_and_sampled_footprints(ctx):
     """512^3 / 20000 defects: too large for the oracle's solve, so the FP64
     path (oracle-matched at smaller sizes) is the reference for the FP32 one,
     an integer translation must leave the energies unchanged, and a sample of
@@ -101,7 +101,7 @@ def test_config5_512_fp32_against_fp64_and_sampled_footprints(ctx):
     from oracle import raster
     from paper_2403_09158_amd import ec
 
-    prob, defs = inputs.config5(prec=0)
+    prob, defs = inputs.mixed_512(prec=0)
     st = ec.State(ctx, prob)
     st.solve(defs)
     E64 = st.energies().copy()

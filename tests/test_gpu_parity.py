@@ -46,10 +46,10 @@ def _oracle_fields(prob, defs):
 # ------------------------------------------------------------------ rasteriser
 
 
-@pytest.mark.parametrize("case", ["config1", "mixed24", "mixed32_wrap", "mixed48"])
+@pytest.mark.parametrize("case", ["pair_32", "mixed24", "mixed32_wrap", "mixed48"])
 def test_raster_bit_exact(ctx, case):
-    if case == "config1":
-        prob, d = inputs.config1()
+    if case == "pair_32":
+        prob, d = inputs.pair_32()
     elif case == "mixed24":
         prob, d = _mixed(24, 12, 1)
     elif case == "mixed32_wrap":
@@ -72,7 +72,7 @@ def test_raster_bit_exact(ctx, case):
 def test_invalid_defect_rejected_state_unchanged(ctx):
     from paper_2403_09158_amd import ec
 
-    prob, d = inputs.config1()
+    prob, d = inputs.pair_32()
     st = _state(ctx, prob)
     st.solve(d)
     E0 = st.energies()
@@ -167,8 +167,8 @@ def test_solve_fields_every_size(ctx, n, prec):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("bc", [0, 1])
-def test_config1_fields_and_energies(ctx, prec, bc):
-    prob, d = inputs.config1()
+def test_pair32_fields_and_energies(ctx, prec, bc):
+    prob, d = inputs.pair_32()
     prob = prob.with_(prec=prec, bc=bc)
     _, _, _, eps6, sig6 = _oracle_fields(prob, d)
     Eo, _ = energy.energies_brute(prob, d)

@@ -37,7 +37,7 @@ def test_same_result_alone_and_in_the_mix():
     from paper_2403_09158_amd import ec, serve
 
     reps = _replicas(6)
-    reqs = serve.config4_requests(reps, 60, rate_per_s=1e6)
+    reqs = serve.serving_requests(reps, 60, rate_per_s=1e6)
     ctx = ec.Context()
     srv = serve.Server(ctx, reps, slots=4, keep_results=True)
     srv.warm()
@@ -57,7 +57,7 @@ def test_admission_by_budget_evicts_and_rebuilds():
     from paper_2403_09158_amd import ec, serve
 
     reps = _replicas(6, seed=1, sizes=(48,))
-    reqs = serve.config4_requests(reps, 40, rate_per_s=1e6)
+    reqs = serve.serving_requests(reps, 40, rate_per_s=1e6)
     # memory of the replicas when all are resident; what is not held by the
     # states (the shared Green windows) stays for the whole run.  The budget
     # fits the shared part, two states and the transient buffers of a window
@@ -95,7 +95,7 @@ def test_replica_larger_than_budget_is_reported():
     from paper_2403_09158_amd import ec, serve
 
     reps = _replicas(2, seed=3)
-    reqs = serve.config4_requests(reps, 4, rate_per_s=1e6)
+    reqs = serve.serving_requests(reps, 4, rate_per_s=1e6)
     ctx = ec.Context(budget_bytes=1 << 20)
     srv = serve.Server(ctx, reps, slots=2)
     with pytest.raises(ec.EcError) as ei:
@@ -121,7 +121,7 @@ def test_realtime_latency_bookkeeping():
     from paper_2403_09158_amd import ec, serve
 
     reps = _replicas(4, seed=2)
-    reqs = serve.config4_requests(reps, 80, rate_per_s=4000.0)
+    reqs = serve.serving_requests(reps, 80, rate_per_s=4000.0)
     ctx = ec.Context()
     srv = serve.Server(ctx, reps, slots=4)
     srv.warm()

@@ -15,7 +15,7 @@ def _replicas():
 
 def test_trace_shape():
     reps = _replicas()
-    reqs = serve.config4_requests(reps, 2000, rate_per_s=2000.0)
+    reqs = serve.serving_requests(reps, 2000, rate_per_s=2000.0)
     t = np.array([r.t for r in reqs])
     assert np.all(np.diff(t) > 0)
     # Poisson arrivals at 2000/s: the mean gap is 0.5 ms within sampling error
@@ -32,8 +32,8 @@ def test_trace_shape():
 
 def test_trace_is_reproducible():
     reps = _replicas()
-    a = serve.config4_requests(reps, 100)
-    b = serve.config4_requests(reps, 100)
+    a = serve.serving_requests(reps, 100)
+    b = serve.serving_requests(reps, 100)
     assert a == b
 
 
