@@ -560,7 +560,7 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
   const Prune full{0, st->n, 0, st->n};
   const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
   SpecGeom g{st->n, 0};
-  g.P = fp64 ? ((st->n / 2 + 1 + 7) / 8) * 8 : ((st->n / 2 + 1 + 15) / 16) * 16;
+  g.P = spec_pitch(st->n, fp64);
   LAUNCH(st, s, PF_XF, 4.0 * (double)st->n3 + sb,
          launch_x_forward(fp64, own, lnk, defs, nullptr, spec, g, st->tw, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, false, 1, spec, g, full, st->tw, s));
@@ -929,7 +929,7 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
   st->n3 = (int64_t)p->n * p->n * p->n;
   st->fp64 = p->prec == EC_FP64;
   st->g.n = p->n;
-  st->g.P = st->fp64 ? ((p->n / 2 + 1 + 7) / 8) * 8 : ((p->n / 2 + 1 + 15) / 16) * 16;
+  st->g.P = spec_pitch(p->n, st->fp64);
   st->C = Cubic{p->C11, p->C12, p->C44};
   const double h = p->L / p->n;
   st->h3c = h * h * h * GPA_NM3_EV;

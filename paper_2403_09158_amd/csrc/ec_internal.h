@@ -195,6 +195,12 @@ __host__ __device__ inline size_t spec_at(int kz, int ky, int kx, int c, int n, 
   return (((size_t)kz * n + ky) * P + kx) * 6 + c;
 }
 
+// Row pitch P of the half spectrum: n/2 + 1 bins rounded up to 16 with FP32
+// storage (128-byte rows of float2) or to 8 with FP64 storage.
+__host__ __device__ constexpr int spec_pitch(int n, bool fp64) {
+  return fp64 ? ((n / 2 + 1 + 7) / 8) * 8 : ((n / 2 + 1 + 15) / 16) * 16;
+}
+
 struct SpecGeom {
   int n;
   int P;  // row pitch (complex elements) of the half spectrum, >= n/2 + 1

@@ -195,6 +195,29 @@ __device__ __forceinline__ double2 tw_at(const double2* tw, int e) {
   return INV ? make_double2(t.x, -t.y) : t;
 }
 
+// The R twiddles of one butterfly in registers (forward sign), w[r] for its
+// r-th operand: for kernels whose threads keep the same butterfly of a stage
+// from tile to tile, so the table is read once per kernel instead of once per
+// tile.  A stage given a TwReg uses it in place of the table.
+template <int R>
+struct TwReg {
+  double2 w[R];
+};
+
+template <class TW>
+struct is_twreg : std::false_type {};
+template <int R>
+struct is_twreg<TwReg<R>> : std::true_type {};
+
+template <bool INV>
+__device__ __forceinline__ double2 twiddle(const double2* tw, int, int e) {
+  return tw_at<INV>(tw, e);
+}
+template <bool INV, int R>
+__device__ __forceinline__ double2 twiddle(const TwReg<R>& t, int r, int) {
+  return INV ? conjd(t.w[r]) : t.w[r];
+}
+
 // One Stockham stage over `nfft` transforms of length N with radix R after
 // Ns = product of earlier radices.  Butterfly b -> (transform f, index j) by
 // MAP (pencil: f fastest across lanes, so columns stay contiguous; row: j
@@ -223,11 +246,12 @@ __device__ __forceinline__ void bfly_index(int b, int& f, int& j) {
   }
 }
 
-template <int N, int R, int NS, bool INV, Map M, int NFFT, int T, int GW = NFFT, class Load, class Store>
-__device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& store, bool sync_between,
+template <int N, int R, int NS, bool INV, Map M, int NFFT, int T, int GW = NFFT, class TW, class Load, class Store>
+__device__ __forceinline__ void stage(const TW& tw, Load&& load, Store&& store, bool sync_between,
                                       int tid = threadIdx.x) {
   constexpr int NB = NFFT * (N / R);
   constexpr int BPT = (NB + T - 1) / T;
+  static_assert(!is_twreg<TW>::value || NB == T, "register twiddles need one butterfly per thread");
   double2 v[BPT][R];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
@@ -256,7 +280,7 @@ __device__ __forceinline__ void stage(const double2* tw, Load&& load, Store&& st
       const int k = j % NS;
       if (NS > 1) {
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], tw_at<INV>(tw, k * r * (N / (NS * R))));
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], twiddle<INV>(tw, r, k * r * (N / (NS * R))));
       }
       Dft<R, INV>::run(v[q]);
       const int base = (j / NS) * NS * R + k;
@@ -282,6 +306,20 @@ __device__ __forceinline__ void for_operands(F&& fn, int tid = threadIdx.x) {
       for (int r = 0; r < R; ++r) fn(f, j + r * (N / R), q * R + r);
     }
   }
+}
+
+// Register twiddles of the radix-R stage after NS for the thread whose
+// butterfly in that stage is b = tid (one butterfly per thread).
+template <int N, int R, int NS, Map M, int NFFT, int T, int GW = NFFT>
+__device__ __forceinline__ TwReg<R> make_twreg(const double2* tw, int tid) {
+  static_assert(NFFT * (N / R) == T, "one butterfly per thread");
+  int f, j;
+  bfly_index<M, N, R, NFFT, GW>(tid, f, j);
+  const int k = j % NS;
+  TwReg<R> t;
+#pragma unroll
+  for (int r = 0; r < R; ++r) t.w[r] = tw[k * r * (N / (NS * R))];
+  return t;
 }
 
 // Full transform: first stage LOAD0 -> LDS (or -> STORE_LAST for one stage),
@@ -314,10 +352,12 @@ __device__ __forceinline__ void transform(const double2* tw, Load0&& load0, LdsL
 // Transform with an explicit radix sequence (R1 = 1: one stage, R2 = 1: two
 // stages); LOAD0_LDS / LAST_LDS as for transform().
 template <int N, int R0, int R1, int R2, bool INV, Map M, int NFFT, int T, int GW, bool LOAD0_LDS, bool LAST_LDS,
-          class Load0, class LdsLd, class LdsSt, class StoreLast>
-__device__ __forceinline__ void transform_plan(const double2* tw, Load0&& load0, LdsLd&& from_lds, LdsSt&& to_lds,
+          class TW, class Load0, class LdsLd, class LdsSt, class StoreLast>
+__device__ __forceinline__ void transform_plan(const TW& tw, Load0&& load0, LdsLd&& from_lds, LdsSt&& to_lds,
                                                StoreLast&& store_last, int tid = threadIdx.x) {
   static_assert(R0 * R1 * R2 == N, "radices must multiply to N");
+  // register twiddles serve one twiddled stage only
+  static_assert(!is_twreg<TW>::value || R2 == 1, "register twiddles need a two-stage plan");
   if constexpr (R1 == 1) {
     stage<N, R0, 1, INV, M, NFFT, T, GW>(tw, load0, store_last, LOAD0_LDS && LAST_LDS, tid);
   } else if constexpr (R2 == 1) {

@@ -220,7 +220,28 @@ __global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs,
       return ((rz + D) * W + (ry + D)) * W + (rx + D);
     };
     double acc = 0.0;
-    if (cls >= 0) {
+    if (cls >= 0 && staged && lin) {
+      // the usual case, kept free of the per-pair choices of the general
+      // loop below so that four window loads stay in flight per lane
+      const double* g = gcls + (size_t)cls * W * W * W;
+      for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
+        const double* gp = g + (pk[p] + C0);
+        if (lane == 0) acc += g[C0];
+        // q past the end reads the last voxel's entry (a valid address) and
+        // contributes zero, so the four loads are issued together also in
+        // the row's last iteration
+        for (int q = p + 1 + lane; q < m; q += 256) {
+          double v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int qq = q + 64 * k;
+            const double x = gp[-pk[qq < m ? qq : m - 1]];
+            v[k] = qq < m ? x : 0.0;
+          }
+          acc += 2.0 * ((v[0] + v[1]) + (v[2] + v[3]));
+        }
+      }
+    } else if (cls >= 0) {
       const double* g = gcls + (size_t)cls * W * W * W;
       for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
         const int32_t P = coord(p);

@@ -1,7 +1,7 @@
 // k_fft.hip - FFT passes and the Green operator of the periodic eigenstrain solve.
 //
-// Half-spectrum layout: [6][kz][ky][kx] complex, kx in [0, n/2] with row pitch P
-// (padded so every row starts on a 128-byte boundary).  The solve runs:
+// Half-spectrum layout: [kz][ky][kx][6] complex (the six components of a bin
+// adjacent), kx in [0, n/2] with row pitch P (spec_pitch).  The solve runs:
 //   x-forward (R2C, two real rows per complex transform), y-forward,
 //   z-forward + Green operator + z-inverse, y-inverse, x-inverse (C2R) + stress.
 // All butterflies, twiddles and the Green operator run in FP64 registers; the
@@ -319,10 +319,10 @@ constexpr int pencil_threads() {
   return 6 * pencil_wx<N, LT>() * (N / pencil_rmax<N>());
 }
 
-template <int N, typename S, bool INV, typename LT, bool PRUNE>
+template <int N, typename S, bool INV, typename LT, bool PRUNE, int AXIS>
 __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename Cplx<S>::T* __restrict__ spec,
-                                                                     int P, int axis, Prune pr,
-                                                                     const double2* __restrict__ twg, int ntiles) {
+                                                                     Prune pr, const double2* __restrict__ twg,
+                                                                     int ntiles) {
   constexpr int WX = pencil_wx<N, LT>();
   constexpr int NF = 6 * WX;
   constexpr int T = pencil_threads<N, LT>();
@@ -332,12 +332,14 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
   constexpr int R0 = PL.r[0];
   constexpr int NOP = ((NF * (N / R0) + T - 1) / T) * R0;  // first-stage operands per thread
   static_assert(T % NF == 0, "a thread must keep its column across butterflies");
+  constexpr int P = spec_pitch(N, sizeof(S) == 8);
+  // element stride along the transform axis; all offsets fit 32 bits
+  constexpr int SI = AXIS == 1 ? 6 * P : 6 * N * P;
+  static_assert(6LL * N * N * P < (1LL << 31), "32-bit element offsets");
   using C2 = typename Cplx<S>::T;
   __shared__ LT buf[N * NF];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
-  // element stride along the transform axis
-  const size_t si = axis == 1 ? (size_t)6 * P : (size_t)6 * N * P;
   auto in_range = [&](int i) {
     if (!PRUNE) return true;
     int d = i - pr.in_lo;
@@ -349,12 +351,12 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
     const int o = t / KB, kx = (t % KB) * WX + f / 6;
     valid = kx < NH;
     if (!valid) return spec;
-    if (axis == 1) {
+    if (AXIS == 1) {
       int z = pr.z_lo + o;
       if (z >= N) z -= N;
-      return spec + spec_at(z, 0, kx, f % 6, N, P);
+      return spec + (z * N * P + kx) * 6 + f % 6;
     }
-    return spec + spec_at(0, o, kx, f % 6, N, P);
+    return spec + (o * P + kx) * 6 + f % 6;
   };
   // FP32 storage: raw first-stage operands of the next tile are loaded while
   // the current one is transformed (rows outside the input range read row
@@ -367,7 +369,7 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
     bool v;
     const C2* colp = column(t, tid % NF, v);
     for_operands<N, R0, Map::Pencil, NF, T>(
-        [&](int, int i, int slot) { nxt[slot] = colp[(size_t)(in_range(i) ? i : pr.in_lo) * si]; }, tid);
+        [&](int, int i, int slot) { nxt[slot] = colp[(in_range(i) ? i : pr.in_lo) * SI]; }, tid);
   };
   auto from_lds = [&](int f, int i) { return ld2(&buf[i * NF + f]); };
   auto to_lds = [&](int f, int i, double2 v) { st2(&buf[i * NF + f], v); };
@@ -379,6 +381,16 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
   int t = lo + (int)(blockIdx.x / 8);
   if (t < hi) fetch(t, threadIdx.x);
   __syncthreads();
+  // two equal radices: the second stage gives a thread the same butterfly in
+  // every tile, so its twiddles stay in registers (FP32 storage; with FP64
+  // storage the extra registers would cost occupancy)
+  constexpr bool TWREG = PL.nstage == 2 && PL.r[0] == PL.r[1] && NF * (N / R0) == T && sizeof(S) == 4;
+  const auto twp = [&] {
+    if constexpr (TWREG)
+      return make_twreg<N, R0, R0, Map::Pencil, NF, T>(tw, threadIdx.x);
+    else
+      return (const double2*)tw;
+  }();
   for (; t < hi; t += g8) {
     // laundered thread index: index arithmetic is redone per tile instead of
     // being held in registers across the loop
@@ -386,12 +398,14 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
     asm volatile("" : "+v"(tid));
     bool valid;
     C2* const colp = column(t, tid % NF, valid);
+    // a lane past the last column transforms whatever its loads returned
+    // (finite spectrum values) and stores nothing
     auto load0 = [&](int, int i, int slot) -> double2 {
-      if (!(valid && in_range(i))) return make_double2(0.0, 0.0);
-      return PIPE ? ld2(&nxt[slot]) : ld2(colp + (size_t)i * si);
+      if (PRUNE && !(valid && in_range(i))) return make_double2(0.0, 0.0);
+      return PIPE ? ld2(&nxt[slot]) : ld2(colp + i * SI);
     };
     auto store_last = [&](int, int i, double2 v) {
-      if (valid) st2(colp + (size_t)i * si, v);
+      if (valid) st2(colp + i * SI, v);
     };
     const bool more = t + g8 < hi;
     if constexpr (PL.nstage == 1) {
@@ -402,7 +416,7 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
       if (more) fetch(t + g8, tid);
       __syncthreads();
       if constexpr (PL.nstage == 2) {
-        stage<N, PL.r[1], R0, INV, Map::Pencil, NF, T>(tw, from_lds, store_last, false, tid);
+        stage<N, PL.r[1], R0, INV, Map::Pencil, NF, T>(twp, from_lds, store_last, false, tid);
       } else {
         stage<N, PL.r[1], R0, INV, Map::Pencil, NF, T>(tw, from_lds, to_lds, true, tid);
         __syncthreads();
@@ -433,10 +447,12 @@ struct FusedPlan {
   static constexpr int I2 = NSTG == 3 ? R0 : 1;
 };
 
-// columns per tile (two at N = 512, where a four-column tile would not fit)
+// columns per tile: four, or two at N = 512 (where a four-column tile would
+// not fit) and with FP64 storage from N = 256 on (no prefetch there, so three
+// resident two-column workgroups per CU hide more latency than one wider one)
 template <int N, typename S>
 constexpr int zg_width() {
-  return N >= 512 ? 2 : 4;
+  return (N >= 512 || (sizeof(S) == 8 && N >= 256)) ? 2 : 4;
 }
 
 // one butterfly per thread in the widest-radix stage; a multiple of the 6 W
@@ -453,8 +469,8 @@ constexpr int zg_threads() {
 __device__ __forceinline__ int zg_swz(int i) { return (i & ~7) | ((i ^ (i >> 3)) & 7); }
 
 template <int N, typename S, bool PRUNE>
-__global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S>::T* __restrict__ spec, int P,
-                                                                Cubic C, Prune pr, const double2* __restrict__ twg) {
+__global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S>::T* __restrict__ spec, Cubic C,
+                                                                Prune pr, const double2* __restrict__ twg) {
   using FP = FusedPlan<N>;
   constexpr int W = zg_width<N, S>();
   constexpr int T = zg_threads<N, S>();
@@ -473,8 +489,10 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   __shared__ double2 buf[6 * N * W];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
-  const size_t si = (size_t)6 * N * P;  // kz stride
-  auto lds = [&](int f, int i) -> double2* { return &buf[zg_swz(i) * NF + f]; };
+  constexpr int P = spec_pitch(N, sizeof(S) == 8);
+  constexpr int SI = 6 * N * P;  // kz stride; all offsets fit 32 bits
+  static_assert(6LL * N * N * P < (1LL << 31), "32-bit element offsets");
+  auto lds = [&](int f, int i) -> double2* { return &buf[__umul24(zg_swz(i), NF) + f]; };
   auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
   auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
   auto in_z = [&](int i) {
@@ -492,9 +510,9 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   auto fetch = [&](int t, int tid) {
     if constexpr (!PIPE) return;
     const int f0 = tid % NF, kx = (t % KB) * W + f0 / 6;
-    const C2* col0 = spec + (kx < NH ? spec_at(0, t / KB, kx, f0 % 6, N, P) : 0);
+    const C2* col0 = spec + (kx < NH ? ((t / KB) * P + kx) * 6 + f0 % 6 : 0);
     for_operands<N, R0, Map::Pencil, NF, T>(
-        [&](int, int i, int slot) { nxt[slot] = col0[(size_t)(in_z(i) ? i : pr.in_lo) * si]; }, tid);
+        [&](int, int i, int slot) { nxt[slot] = col0[(in_z(i) ? i : pr.in_lo) * SI]; }, tid);
   };
   // tiles split into eight contiguous ranges, one per XCD (dispatch order puts
   // workgroup b on XCD b % 8), so neighbouring kx tiles share an L2
@@ -505,6 +523,16 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   int t = lo + (int)(blockIdx.x / 8);
   if (t < hi) fetch(t, threadIdx.x);
   __syncthreads();
+  // two equal radices: the twiddled stage of either direction gives a thread
+  // the same butterfly in every tile, so its twiddles stay in registers (FP32
+  // storage; with FP64 storage the extra registers would cost occupancy)
+  constexpr bool TWREG = FP::NSTG == 2 && R0 == R1 && sizeof(S) == 4;
+  const auto twz = [&] {
+    if constexpr (TWREG)
+      return make_twreg<N, R1, R0, Map::Pencil, NF, T>(tw, threadIdx.x);
+    else
+      return (const double2*)tw;
+  }();
   for (; t < hi; t += g8) {
     // the thread index is laundered per tile so that the many index
     // expressions derived from it are recomputed, not held in registers
@@ -515,16 +543,19 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
     const int f0 = tid % NF, w = f0 / 6;  // lane f = 6 w + c keeps its column
     const int kx = (t % KB) * W + w;
     const bool valid = kx < NH;
-    C2* const col0 = spec + (valid ? spec_at(0, ky, kx, f0 % 6, N, P) : 0);
+    C2* const col0 = spec + (valid ? (ky * P + kx) * 6 + f0 % 6 : 0);
+    // a lane past the last column transforms whatever its loads returned
+    // (finite spectrum values), takes no part in the Green step and stores
+    // nothing
     auto load0 = [&](int, int i, int slot) -> double2 {
-      if (!(valid && in_z(i))) return make_double2(0.0, 0.0);
-      return PIPE ? ld2(&nxt[slot]) : ld2(col0 + (size_t)i * si);
+      if (PRUNE && !(valid && in_z(i))) return make_double2(0.0, 0.0);
+      return PIPE ? ld2(&nxt[slot]) : ld2(col0 + i * SI);
     };
     stage<N, R0, 1, false, Map::Pencil, NF, T>(tw, load0, to_lds, false, tid);
     if (t + g8 < hi) fetch(t + g8, tid);
     __syncthreads();
     if constexpr (R2 == 1) {
-      stage<N, R1, R0, false, Map::Pencil, NF, T>(tw, from_lds, to_lds, true, tid);
+      stage<N, R1, R0, false, Map::Pencil, NF, T>(twz, from_lds, to_lds, true, tid);
     } else {
       stage<N, R1, R0, false, Map::Pencil, NF, T>(tw, from_lds, to_lds, true, tid);
       __syncthreads();
@@ -545,10 +576,10 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
     }
     __syncthreads();
     auto store_last = [&](int, int i, double2 v) {
-      if (valid) st2(col0 + (size_t)i * si, v);
+      if (valid) st2(col0 + i * SI, v);
     };
-    transform_plan<N, FP::I0, FP::I1, FP::I2, true, Map::Pencil, NF, T, NF, true, false>(tw, from_lds, from_lds, to_lds,
-                                                                                    store_last, tid);
+    transform_plan<N, FP::I0, FP::I1, FP::I2, true, Map::Pencil, NF, T, NF, true, false>(twz, from_lds, from_lds,
+                                                                                    to_lds, store_last, tid);
     __syncthreads();  // the next tile's first stage rewrites the tile
   }
 }
@@ -575,12 +606,15 @@ __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__
 
 template <int N, typename S, bool ACC>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
-    const typename Cplx<S>::T* __restrict__ spec, double* __restrict__ sig, int P, const double* __restrict__ mean6,
+    const typename Cplx<S>::T* __restrict__ spec, double* __restrict__ sig, const double* __restrict__ mean6,
     const double2* __restrict__ twg) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;
   constexpr int T = pick_T(max_nb(N, NF));
   constexpr int LDN = N + N / 16 + 1;
+  constexpr int P = spec_pitch(N, sizeof(S) == 8);
+  constexpr int N3 = N * N * N;
+  static_assert(6LL * N * N * P < (1LL << 31) && 6LL * N3 < (1LL << 31), "32-bit element offsets");
   __shared__ double2 buf[NF * LDN];
   __shared__ double2 tw[N];
   __shared__ double mean_s[6];
@@ -589,13 +623,12 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   const int bpp = N / ROWS;
   const int z = blockIdx.x / bpp;
   const int y0 = (blockIdx.x % bpp) * ROWS;
-  const size_t n3 = (size_t)N * N * N;
-  const double scale = 1.0 / (double)n3;
+  const double scale = 1.0 / (double)N3;
   __syncthreads();
   auto load0 = [&](int f, int k) -> double2 {
     const int p = f % 3, y = y0 + f / 3;
     // components 2p and 2p+1 of bin k (or of its mirror n - k) are adjacent
-    const typename Cplx<S>::T* a = spec + spec_at(z, y, k <= N / 2 ? k : N - k, 2 * p, N, P);
+    const typename Cplx<S>::T* a = spec + ((z * N + y) * P + (k <= N / 2 ? k : N - k)) * 6 + 2 * p;
     double2 A = ld2(a), B = ld2(a + 1);
     if (k > N / 2) {
       A = conjd(A);
@@ -610,9 +643,8 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   auto to_lds = [&](int f, int i, double2 v) { buf[f * LDN + i + (i >> 4)] = v; };
   auto store_last = [&](int f, int x, double2 v) {
     const int p = f % 3, y = y0 + f / 3;
-    const size_t o = ((size_t)z * N + y) * N + x;
-    double* s0 = sig + (size_t)(2 * p) * n3 + o;
-    double* s1 = sig + (size_t)(2 * p + 1) * n3 + o;
+    double* s0 = sig + (2 * p * N3 + (z * N + y) * N + x);
+    double* s1 = s0 + N3;
     const double a = v.x * scale + mean_s[2 * p], b = v.y * scale + mean_s[2 * p + 1];
     if (ACC) {
       *s0 += a;
@@ -678,11 +710,14 @@ hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const
   const int ntiles = nouter * KB;
   using C2 = typename Cplx<S>::T;
   const bool prune = pr.in_len < N;
-  auto* k = inv ? (prune ? k_pencil<N, S, true, LT, true> : k_pencil<N, S, true, LT, false>)
-                : (prune ? k_pencil<N, S, false, LT, true> : k_pencil<N, S, false, LT, false>);
+  if (g.P != spec_pitch(N, sizeof(S) == 8) || (axis != 1 && axis != 2)) return hipErrorInvalidValue;
+  if (axis == 2 && prune) return hipErrorInvalidValue;  // z pruning runs in the fused z pass
+  auto* k = axis == 1 ? (inv ? (prune ? k_pencil<N, S, true, LT, true, 1> : k_pencil<N, S, true, LT, false, 1>)
+                             : (prune ? k_pencil<N, S, false, LT, true, 1> : k_pencil<N, S, false, LT, false, 1>))
+                      : (inv ? k_pencil<N, S, true, LT, false, 2> : k_pencil<N, S, false, LT, false, 2>);
   const int grid = tile_grid(k, T, ntiles, sizeof(S) == 4);
   if (grid < 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, axis, pr, tw, ntiles);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, pr, tw, ntiles);
   return hipGetLastError();
 }
 
@@ -692,10 +727,11 @@ hipError_t go_xi(bool acc, const void* spec, double* sig, SpecGeom g, const doub
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   const int grid = N * (N / x_rows(N));
   using C2 = typename Cplx<S>::T;
+  if (g.P != spec_pitch(N, sizeof(S) == 8)) return hipErrorInvalidValue;
   if (acc)
-    hipLaunchKernelGGL((k_x_inverse<N, S, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, g.P, mean6, tw);
+    hipLaunchKernelGGL((k_x_inverse<N, S, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw);
   else
-    hipLaunchKernelGGL((k_x_inverse<N, S, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, g.P, mean6, tw);
+    hipLaunchKernelGGL((k_x_inverse<N, S, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw);
   return hipGetLastError();
 }
 
@@ -775,10 +811,11 @@ hipError_t go_zgreen(void* spec, SpecGeom g, Cubic C, Prune pr, const double2* t
   constexpr int NT = N * ((N / 2 + 1 + W - 1) / W);
   using C2 = typename Cplx<S>::T;
   const bool prune = pr.in_len < N;
+  if (g.P != spec_pitch(N, sizeof(S) == 8)) return hipErrorInvalidValue;
   auto* k = prune ? k_zgreen<N, S, true> : k_zgreen<N, S, false>;
   const int grid = tile_grid(k, T, NT, sizeof(S) == 4);
   if (grid < 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, g.P, C, pr, tw);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, C, pr, tw);
   return hipGetLastError();
 }
 
