@@ -224,6 +224,7 @@ struct ec_state {
   int32_t* upd_ids = nullptr;
   int64_t upd_cap = 0;
   double* updE = nullptr;     // 6 doubles
+  uint32_t* tilectr = nullptr;  // NTILECTR tile counters of the persistent passes
   int64_t* updfix = nullptr;  // 6 int64
   // pinned staging: defect table, per-update records, moved footprint
   Pinned pin_tab, pin_upd, pin_ids, pin_tags;
@@ -555,17 +556,19 @@ double spec_valid_bytes(const ec_state* st, bool fp64) {
   return 6.0 * st->n * st->n * (st->n / 2 + 1) * (fp64 ? 16.0 : 8.0);
 }
 
+// ctr: the state's tile counters, or nullptr (fixed tile order; for solves
+// that may run beside the state's own passes)
 ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs,
-                   void* spec, double* sig, const double* add6) {
+                   void* spec, double* sig, const double* add6, uint32_t* ctr) {
   const Prune full{0, st->n, 0, st->n};
   const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
   SpecGeom g{st->n, 0};
   g.P = spec_pitch(st->n, fp64);
   LAUNCH(st, s, PF_XF, 4.0 * (double)st->n3 + sb,
-         launch_x_forward(fp64, own, lnk, defs, nullptr, spec, g, st->tw, s));
-  LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, false, 1, spec, g, full, st->tw, s));
-  LAUNCH(st, s, PF_Z, 2 * sb, launch_z_green(fp64, spec, g, st->C, full, st->tw, s));
-  LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, spec, g, full, st->tw, s));
+         launch_x_forward(fp64, own, lnk, defs, nullptr, spec, g, st->tw, ctr, s));
+  LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, false, 1, spec, g, full, st->tw, ctr ? ctr : nullptr, s));
+  LAUNCH(st, s, PF_Z, 2 * sb, launch_z_green(fp64, spec, g, st->C, full, st->tw, ctr ? ctr + 8 : nullptr, s));
+  LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, spec, g, full, st->tw, ctr ? ctr + 16 : nullptr, s));
   LAUNCH(st, s, PF_XI, sb + fb, launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s));
   return EC_OK;
 }
@@ -634,7 +637,8 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
     HIPCHK(hipMemsetAsync(K, 0, Kbytes, s));
     for (int b = 0; b < 6; ++b) {
       HIPCHK(launch_fill_i32((int32_t*)own, 1, b, s));  // voxel 0 owned by unit defect b
-      ec_status q = pipeline(st, s, true, (const int32_t*)own, dlnk, dunit, sp, (double*)sg, (const double*)ad + 8 * b);
+      ec_status q =
+          pipeline(st, s, true, (const int32_t*)own, dlnk, dunit, sp, (double*)sg, (const double*)ad + 8 * b, nullptr);
       if (q != EC_OK) return q;
       HIPCHK(launch_window_crop((const double*)sg, n, D, b, (double*)K, s));
     }
@@ -941,6 +945,7 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
     return fail(EC_ERR_DEVICE, "twiddle table allocation failed");
   }
   void *sp = nullptr, *own = nullptr, *sg = nullptr, *ad = nullptr, *dirs = nullptr, *ue = nullptr, *uf = nullptr;
+  void* tc = nullptr;
   const size_t ob = (size_t)st->n3 * 4;
   ec_status r;
   auto undo = [&]() {
@@ -951,11 +956,12 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
     ledger_free(c, dirs, MAXCLS * 48);
     ledger_free(c, ue, 64);
     ledger_free(c, uf, 64);
+    ledger_free(c, tc, 128);
   };
   if ((r = ledger_alloc(c, st->spec_bytes, &sp)) != EC_OK || (r = ledger_alloc(c, ob, &own)) != EC_OK ||
       (r = ledger_alloc(c, fb, &sg)) != EC_OK || (r = ledger_alloc(c, 256, &ad)) != EC_OK ||
       (r = ledger_alloc(c, MAXCLS * 48, &dirs)) != EC_OK || (r = ledger_alloc(c, 64, &ue)) != EC_OK ||
-      (r = ledger_alloc(c, 64, &uf)) != EC_OK) {
+      (r = ledger_alloc(c, 64, &uf)) != EC_OK || (r = ledger_alloc(c, 128, &tc)) != EC_OK) {
     undo();
     delete st;
     return r;
@@ -967,7 +973,8 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
   st->dirs = (double*)dirs;
   st->updE = (double*)ue;
   st->updfix = (int64_t*)uf;
-  st->held = st->spec_bytes + fb + ob + 256 + MAXCLS * 48 + 128;
+  st->tilectr = (uint32_t*)tc;
+  st->held = st->spec_bytes + fb + ob + 256 + MAXCLS * 48 + 128 + 128;
   hipError_t e = launch_fill_i32(st->own, st->n3, -1, nullptr);
   if (e == hipSuccess) e = hipMemset(st->sig, 0, fb);
   if (e == hipSuccess) e = hipMemset(st->add6, 0, 256);
@@ -993,6 +1000,7 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->dirs, MAXCLS * 48);
   ledger_free(c, st->updE, 64);
   ledger_free(c, st->updfix, 64);
+  ledger_free(c, st->tilectr, 128);
   for (auto& b : st->db) {
     ledger_free(c, b.tab, b.cap * sizeof(DevDefect));
     ledger_free(c, b.cnt, b.cap * 4);
@@ -1117,7 +1125,7 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   LAUNCH(st, s, PF_OTHER, 0,
          launch_mean_stress(nb.tab, nb.cnt, ndef, st->n3, st->C, st->prob.bc, st->add6, s));
   // 4. Fourier solve
-  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6);
+  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6, st->tilectr);
   // host copies of the list while the device works (the staging buffer is
   // only read by the pending upload)
   st->hdefs.assign(h, h + ndef);
@@ -1259,13 +1267,14 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
     const double frac_z = (double)zlen / n;
     LAUNCH(st, s, PF_XF, frac_z * ylen / n * sb,
            launch_x_forward_sparse(fp64, oids, ocnt, nids, cnt_new, sh[0], sh[1], sh[2], st->updE, st->spec, st->g,
-                                   ylo, ylen, zlo, zlen, st->tw, s));
+                                   ylo, ylen, zlo, zlen, st->tw, st->tilectr, s));
     const Prune py{ylo, ylen, zlo, zlen};
-    LAUNCH(st, s, PF_Y, 2 * frac_z * sb, launch_pencil(fp64, false, 1, st->spec, st->g, py, st->tw, s));
+    LAUNCH(st, s, PF_Y, 2 * frac_z * sb, launch_pencil(fp64, false, 1, st->spec, st->g, py, st->tw, st->tilectr, s));
     const Prune pz{zlo, zlen, 0, n};
     const Prune full{0, n, 0, n};
-    LAUNCH(st, s, PF_Z, (1 + frac_z) * sb, launch_z_green(fp64, st->spec, st->g, st->C, pz, st->tw, s));
-    LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, st->spec, st->g, full, st->tw, s));
+    LAUNCH(st, s, PF_Z, (1 + frac_z) * sb,
+           launch_z_green(fp64, st->spec, st->g, st->C, pz, st->tw, st->tilectr + 8, s));
+    LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, st->spec, st->g, full, st->tw, st->tilectr + 16, s));
     LAUNCH(st, s, PF_XI, sb + 2 * fb,
            launch_x_inverse(fp64, true, st->spec, st->sig, st->g, st->add6 + 12, st->tw, s));
   }
@@ -1452,9 +1461,10 @@ ec_status ec_debug_forward(ec_state* st, const double* field, double* out) {
   if ((r = ledger_alloc(st->ctx, sp.b = st->spec_bytes, &sp.p)) != EC_OK) return r;
   HIPCHK(hipMemcpy(fd.p, field, cnt * 8, hipMemcpyHostToDevice));
   const Prune full{0, st->n, 0, st->n};
-  HIPCHK(launch_x_forward(st->fp64, nullptr, nullptr, nullptr, (const double*)fd.p, sp.p, st->g, st->tw, nullptr));
-  HIPCHK(launch_pencil(st->fp64, false, 1, sp.p, st->g, full, st->tw, nullptr));
-  HIPCHK(launch_pencil(st->fp64, false, 2, sp.p, st->g, full, st->tw, nullptr));
+  HIPCHK(launch_x_forward(st->fp64, nullptr, nullptr, nullptr, (const double*)fd.p, sp.p, st->g, st->tw, nullptr,
+                          nullptr));
+  HIPCHK(launch_pencil(st->fp64, false, 1, sp.p, st->g, full, st->tw, nullptr, nullptr));
+  HIPCHK(launch_pencil(st->fp64, false, 2, sp.p, st->g, full, st->tw, nullptr, nullptr));
   HIPCHK(hipDeviceSynchronize());
   return download_spec(st, sp.p, out);
 }
@@ -1481,8 +1491,8 @@ ec_status ec_debug_inverse(ec_state* st, const double* in, double* out) {
   if ((r = upload_spec(st, in, sp.p)) != EC_OK) return r;
   HIPCHK(hipMemset(ad.p, 0, 64));
   const Prune full{0, st->n, 0, st->n};
-  HIPCHK(launch_pencil(st->fp64, true, 2, sp.p, st->g, full, st->tw, nullptr));
-  HIPCHK(launch_pencil(st->fp64, true, 1, sp.p, st->g, full, st->tw, nullptr));
+  HIPCHK(launch_pencil(st->fp64, true, 2, sp.p, st->g, full, st->tw, nullptr, nullptr));
+  HIPCHK(launch_pencil(st->fp64, true, 1, sp.p, st->g, full, st->tw, nullptr, nullptr));
   HIPCHK(launch_x_inverse(st->fp64, false, sp.p, (double*)sg.p, st->g, (const double*)ad.p, st->tw, nullptr));
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipMemcpy(out, sg.p, cnt * 8, hipMemcpyDeviceToHost));

@@ -217,18 +217,28 @@ struct Prune {
 bool fft_supported(int n);
 int pencil_width(int n, bool fp64);
 
+// Tile counters of the persistent passes (eight per pass, one per XCD; the
+// y, z and y-inverse passes of a solve or update use counters 0-7, 8-15 and
+// 16-23).  The x-forward pass that starts a solve or update zeroes them; a
+// pass given no counters walks its tiles in a fixed order.
+constexpr int NTILECTR = 24;
+
 // Owner-list input (own/lnk/defs) or, when dense != nullptr, a dense FP64
-// [6][n^3] field (kernel-level tests).
+// [6][n^3] field (kernel-level tests).  zero_ctr: NTILECTR counters to zero,
+// or nullptr.
 hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs, const double* dense,
-                            void* spec, SpecGeom g, const double2* tw, hipStream_t s);
+                            void* spec, SpecGeom g, const double2* tw, uint32_t* zero_ctr, hipStream_t s);
 hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, const int32_t* old_cnt, const int32_t* new_ids,
                                    int new_cnt,
                                    int shift_x, int shift_y, int shift_z, const double* E, void* spec, SpecGeom g,
-                                   int y_lo, int y_len, int z_lo, int z_len, const double2* tw, hipStream_t s);
+                                   int y_lo, int y_len, int z_lo, int z_len, const double2* tw, uint32_t* zero_ctr,
+                                   hipStream_t s);
+// ctr: eight zeroed tile counters for this launch, or nullptr
 hipError_t launch_pencil(bool fp64, bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw,
-                         hipStream_t s);
+                         uint32_t* ctr, hipStream_t s);
 hipError_t launch_green(bool fp64, void* spec, SpecGeom g, Cubic C, hipStream_t s);
-hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, hipStream_t s);
+hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, uint32_t* ctr,
+                          hipStream_t s);
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
                             const double2* tw, hipStream_t s);
 

@@ -251,7 +251,7 @@ __device__ __forceinline__ void stage(const TW& tw, Load&& load, Store&& store, 
                                       int tid = threadIdx.x) {
   constexpr int NB = NFFT * (N / R);
   constexpr int BPT = (NB + T - 1) / T;
-  static_assert(!is_twreg<TW>::value || NB == T, "register twiddles need one butterfly per thread");
+  static_assert(!is_twreg<TW>::value || NB <= T, "register twiddles need at most one butterfly per thread");
   double2 v[BPT][R];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
@@ -312,7 +312,9 @@ __device__ __forceinline__ void for_operands(F&& fn, int tid = threadIdx.x) {
 // butterfly in that stage is b = tid (one butterfly per thread).
 template <int N, int R, int NS, Map M, int NFFT, int T, int GW = NFFT>
 __device__ __forceinline__ TwReg<R> make_twreg(const double2* tw, int tid) {
-  static_assert(NFFT * (N / R) == T, "one butterfly per thread");
+  // a thread without a butterfly (b >= NFFT N / R) reads in-range entries it
+  // never uses
+  static_assert(NFFT * (N / R) <= T, "at most one butterfly per thread");
   int f, j;
   bfly_index<M, N, R, NFFT, GW>(tid, f, j);
   const int k = j % NS;
@@ -328,12 +330,13 @@ __device__ __forceinline__ TwReg<R> make_twreg(const double2* tw, int tid) {
 // staging precision is the caller's choice.  LAST_LDS: the last stage's store
 // writes LDS too (operands are then all read before the barrier), LOAD0_LDS:
 // the first stage reads LDS in place.
-template <int N, bool INV, Map M, int NFFT, int T, bool LOAD0_LDS = false, bool LAST_LDS = false, class Load0,
-          class LdsLd, class LdsSt, class StoreLast>
-__device__ __forceinline__ void transform(const double2* tw, Load0&& load0, LdsLd&& from_lds, LdsSt&& to_lds,
+template <int N, bool INV, Map M, int NFFT, int T, bool LOAD0_LDS = false, bool LAST_LDS = false, class TW,
+          class Load0, class LdsLd, class LdsSt, class StoreLast>
+__device__ __forceinline__ void transform(const TW& tw, Load0&& load0, LdsLd&& from_lds, LdsSt&& to_lds,
                                           StoreLast&& store_last) {
   constexpr Plan2 P = plan_of(N);
   static_assert(P.nstage >= 1, "unsupported FFT length");
+  static_assert(!is_twreg<TW>::value || P.nstage == 2, "register twiddles need a two-stage plan");
   if constexpr (P.nstage == 1) {
     stage<N, P.r[0], 1, INV, M, NFFT, T>(tw, load0, store_last, LOAD0_LDS && LAST_LDS);
   } else if constexpr (P.nstage == 2) {

@@ -224,19 +224,26 @@ __global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs,
       // the usual case, kept free of the per-pair choices of the general
       // loop below so that four window loads stay in flight per lane
       const double* g = gcls + (size_t)cls * W * W * W;
-      for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
-        const double* gp = g + (pk[p] + C0);
+      for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64)
         if (lane == 0) acc += g[C0];
-        // q past the end reads the last voxel's entry (a valid address) and
-        // contributes zero, so the four loads are issued together also in
-        // the row's last iteration
-        for (int q = p + 1 + lane; q < m; q += 256) {
+      // the item's rows walk the columns q > p in chunks of 256 footprint
+      // voxels, all rows of a chunk before the next: the window entries a
+      // chunk reaches from neighbouring rows overlap, so they are served
+      // from the L1 cache (rows walked whole would cycle through the entire
+      // footprint image per row)
+      for (int qc = wk.p0 + 1; qc < m; qc += 256) {
+        const int qe = qc + 256 < m ? qc + 256 : m;
+        for (int p = wk.p0 + wave; p < wk.p1 && p + 1 < qe; p += ST / 64) {
+          const double* gp = g + (pk[p] + C0);
+          const int q = (p + 1 > qc ? p + 1 : qc) + lane;
+          // q past the chunk reads the chunk's last voxel entry (a valid
+          // address) and contributes zero, so the four loads go together
           double v[4];
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const int qq = q + 64 * k;
-            const double x = gp[-pk[qq < m ? qq : m - 1]];
-            v[k] = qq < m ? x : 0.0;
+            const double x = gp[-pk[qq < qe ? qq : qe - 1]];
+            v[k] = qq < qe ? x : 0.0;
           }
           acc += 2.0 * ((v[0] + v[1]) + (v[2] + v[3]));
         }

@@ -128,18 +128,42 @@ __device__ __forceinline__ void green_bin(double2* e, int kx, int ky, int kz, in
 
 // ----------------------------------------------------------------- x forward (R2C)
 
+// x forward pass with a two-stage plan of equal radices: each thread reads
+// the twiddles of its second-stage butterfly from the global table into
+// registers, and the block keeps no LDS copy of the table (more resident
+// blocks for these short-lived ones; the inverse pass, which holds more
+// registers, keeps the table).
+template <int N>
+constexpr bool x_twreg() {
+  constexpr Plan2 P = plan_of(N);
+  return P.nstage == 2 && P.r[0] == P.r[1];
+}
+
+template <int N, int NF, int T>
+__device__ __forceinline__ auto x_twiddles(const double2* tw_lds, const double2* twg) {
+  if constexpr (x_twreg<N>()) {
+    constexpr int R = plan_of(N).r[1];
+    return make_twreg<N, R, R, Map::Row, NF, T>(twg, threadIdx.x);
+  } else {
+    return tw_lds;
+  }
+}
+
 template <int N, typename S, bool DENSE>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
     const int32_t* __restrict__ own, const int2* __restrict__ lnk, const DevDefect* __restrict__ defs,
-    const double* __restrict__ dense, typename Cplx<S>::T* __restrict__ spec, int P, const double2* __restrict__ twg) {
+    const double* __restrict__ dense, typename Cplx<S>::T* __restrict__ spec, int P, const double2* __restrict__ twg,
+    uint32_t* __restrict__ zero_ctr) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;  // (xx,yy), (zz,yz), (xz,xy) per row
   constexpr int T = pick_T(max_nb(N, NF));
   constexpr int LDN = N + N / 16 + 1;
   constexpr int NH = N / 2 + 1;
   __shared__ double2 buf[NF * LDN];
-  __shared__ double2 tw[N];
-  for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  __shared__ double2 tw[x_twreg<N>() ? 1 : N];
+  if constexpr (!x_twreg<N>())
+    for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  if (zero_ctr && blockIdx.x == 0 && threadIdx.x < NTILECTR) zero_ctr[threadIdx.x] = 0u;
   const int bpp = N / ROWS;
   const int z = blockIdx.x / bpp;
   const int y0 = (blockIdx.x % bpp) * ROWS;
@@ -181,7 +205,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   __syncthreads();
   auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
   auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
-  transform<N, false, Map::Row, NF, T, true, true>(tw, from_lds, from_lds, to_lds, to_lds);
+  transform<N, false, Map::Row, NF, T, true, true>(x_twiddles<N, NF, T>(tw, twg), from_lds, from_lds, to_lds, to_lds);
   __syncthreads();
   // Hermitian split of the three pair transforms of a row into the six
   // interleaved half-spectrum components.  FP64 storage: one output value per
@@ -220,7 +244,8 @@ template <int N, typename S>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_sparse(
     const int32_t* __restrict__ old_ids, const int32_t* __restrict__ old_cnt_p, const int32_t* __restrict__ new_ids,
     int new_cnt, int sx, int sy, int sz, const double* __restrict__ E, typename Cplx<S>::T* __restrict__ spec, int P,
-    int y_lo, int y_len, int z_lo, const double2* __restrict__ twg) {
+    int y_lo, int y_len, int z_lo, const double2* __restrict__ twg, uint32_t* __restrict__ zero_ctr) {
+  if (zero_ctr && blockIdx.x == 0 && threadIdx.x < NTILECTR) zero_ctr[threadIdx.x] = 0u;
   const int old_cnt = *old_cnt_p;
   if (!new_ids) new_cnt = old_cnt;
   constexpr int ROWS = x_rows(N);
@@ -299,6 +324,42 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
 // across butterflies (the workgroup size is a multiple of 6 WX).  The last kx
 // tile holds the n/2 column and idle lanes.
 
+// Tile order of a persistent pass.  The tiles are split into eight
+// contiguous ranges, one per XCD (dispatch puts workgroup b on XCD b % 8), so
+// that neighbouring tiles share an L2.  With a counter per XCD (zero at
+// launch) the workgroups of an XCD claim its tiles one at a time, so that one
+// starting late behind other work on its CU takes fewer tiles instead of
+// holding up the pass; without counters each takes every (grid / 8)-th tile
+// of the range.  The tile after the current one is known an iteration ahead
+// (for the prefetch): next() at the top of an iteration gives it, the claim
+// for the one after it is issued then and stored before the iteration's last
+// barrier.
+struct TileWalk {
+  int lo, hi, g8, xcd;
+  uint32_t* ctr;  // nullptr: static order
+  int* slot;      // two LDS entries
+  __device__ TileWalk(int ntiles, uint32_t* c, int* sl) : ctr(c), slot(sl) {
+    g8 = (int)gridDim.x / 8;
+    const int per = (ntiles + 7) / 8;
+    xcd = (int)(blockIdx.x % 8);
+    lo = xcd * per;
+    hi = min(ntiles, lo + per);
+  }
+  // the first two tiles (a barrier must follow before first())
+  __device__ void claim_first() {
+    if (ctr && threadIdx.x == 0) {
+      slot[0] = lo + (int)atomicAdd(&ctr[xcd], 1u);
+      slot[1] = lo + (int)atomicAdd(&ctr[xcd], 1u);
+    }
+  }
+  __device__ int first() const { return ctr ? slot[0] : lo + (int)(blockIdx.x / 8); }
+  __device__ int next(int t, int it) const { return ctr ? slot[(it + 1) & 1] : t + g8; }
+  __device__ uint32_t claim_issue() { return (ctr && threadIdx.x == 0) ? atomicAdd(&ctr[xcd], 1u) : 0u; }
+  __device__ void claim_store(int it, uint32_t v) {
+    if (ctr && threadIdx.x == 0) slot[it & 1] = lo + (int)v;
+  }
+};
+
 // largest radix of the pencil factorisation
 template <int N>
 constexpr int pencil_rmax() {
@@ -322,7 +383,7 @@ constexpr int pencil_threads() {
 template <int N, typename S, bool INV, typename LT, bool PRUNE, int AXIS>
 __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename Cplx<S>::T* __restrict__ spec,
                                                                      Prune pr, const double2* __restrict__ twg,
-                                                                     int ntiles) {
+                                                                     int ntiles, uint32_t* __restrict__ ctr) {
   constexpr int WX = pencil_wx<N, LT>();
   constexpr int NF = 6 * WX;
   constexpr int T = pencil_threads<N, LT>();
@@ -373,12 +434,12 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
   };
   auto from_lds = [&](int f, int i) { return ld2(&buf[i * NF + f]); };
   auto to_lds = [&](int f, int i, double2 v) { st2(&buf[i * NF + f], v); };
-  // contiguous tile ranges per XCD (workgroup b runs on XCD b % 8)
-  const int g8 = gridDim.x / 8;
-  const int per = (ntiles + 7) / 8;
-  const int lo = (int)(blockIdx.x % 8) * per;
-  const int hi = min(ntiles, lo + per);
-  int t = lo + (int)(blockIdx.x / 8);
+  __shared__ int tslot[2];
+  TileWalk walk(ntiles, PIPE ? ctr : nullptr, tslot);
+  walk.claim_first();
+  __syncthreads();
+  int t = walk.first();
+  const int hi = walk.hi;
   if (t < hi) fetch(t, threadIdx.x);
   __syncthreads();
   // two equal radices: the second stage gives a thread the same butterfly in
@@ -391,7 +452,9 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
     else
       return (const double2*)tw;
   }();
-  for (; t < hi; t += g8) {
+  for (int it = 0; t < hi; ++it) {
+    const int tn = walk.next(t, it);
+    const uint32_t claim = walk.claim_issue();
     // laundered thread index: index arithmetic is redone per tile instead of
     // being held in registers across the loop
     int tid = threadIdx.x;
@@ -407,13 +470,13 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
     auto store_last = [&](int, int i, double2 v) {
       if (valid) st2(colp + i * SI, v);
     };
-    const bool more = t + g8 < hi;
+    const bool more = tn < hi;
     if constexpr (PL.nstage == 1) {
       stage<N, R0, 1, INV, Map::Pencil, NF, T>(tw, load0, store_last, false, tid);
-      if (more) fetch(t + g8, tid);
+      if (more) fetch(tn, tid);
     } else {
       stage<N, R0, 1, INV, Map::Pencil, NF, T>(tw, load0, to_lds, false, tid);
-      if (more) fetch(t + g8, tid);
+      if (more) fetch(tn, tid);
       __syncthreads();
       if constexpr (PL.nstage == 2) {
         stage<N, PL.r[1], R0, INV, Map::Pencil, NF, T>(twp, from_lds, store_last, false, tid);
@@ -423,7 +486,9 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
         stage<N, PL.r[2], R0 * PL.r[1], INV, Map::Pencil, NF, T>(tw, from_lds, store_last, false, tid);
       }
     }
+    walk.claim_store(it, claim);
     __syncthreads();  // the next tile's first stage rewrites LDS
+    t = tn;
   }
 }
 
@@ -470,7 +535,8 @@ __device__ __forceinline__ int zg_swz(int i) { return (i & ~7) | ((i ^ (i >> 3))
 
 template <int N, typename S, bool PRUNE>
 __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S>::T* __restrict__ spec, Cubic C,
-                                                                Prune pr, const double2* __restrict__ twg) {
+                                                                Prune pr, const double2* __restrict__ twg,
+                                                                uint32_t* __restrict__ ctr) {
   using FP = FusedPlan<N>;
   constexpr int W = zg_width<N, S>();
   constexpr int T = zg_threads<N, S>();
@@ -514,13 +580,12 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
     for_operands<N, R0, Map::Pencil, NF, T>(
         [&](int, int i, int slot) { nxt[slot] = col0[(in_z(i) ? i : pr.in_lo) * SI]; }, tid);
   };
-  // tiles split into eight contiguous ranges, one per XCD (dispatch order puts
-  // workgroup b on XCD b % 8), so neighbouring kx tiles share an L2
-  const int g8 = gridDim.x / 8;
-  const int per = (NT + 7) / 8;
-  const int lo = (int)(blockIdx.x % 8) * per;
-  const int hi = min(NT, lo + per);
-  int t = lo + (int)(blockIdx.x / 8);
+  __shared__ int tslot[2];
+  TileWalk walk(NT, PIPE ? ctr : nullptr, tslot);
+  walk.claim_first();
+  __syncthreads();
+  int t = walk.first();
+  const int hi = walk.hi;
   if (t < hi) fetch(t, threadIdx.x);
   __syncthreads();
   // two equal radices: the twiddled stage of either direction gives a thread
@@ -533,7 +598,9 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
     else
       return (const double2*)tw;
   }();
-  for (; t < hi; t += g8) {
+  for (int it = 0; t < hi; ++it) {
+    const int tn = walk.next(t, it);
+    const uint32_t claim = walk.claim_issue();
     // the thread index is laundered per tile so that the many index
     // expressions derived from it are recomputed, not held in registers
     // across the loop
@@ -552,7 +619,7 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
       return PIPE ? ld2(&nxt[slot]) : ld2(col0 + i * SI);
     };
     stage<N, R0, 1, false, Map::Pencil, NF, T>(tw, load0, to_lds, false, tid);
-    if (t + g8 < hi) fetch(t + g8, tid);
+    if (tn < hi) fetch(tn, tid);
     __syncthreads();
     if constexpr (R2 == 1) {
       stage<N, R1, R0, false, Map::Pencil, NF, T>(twz, from_lds, to_lds, true, tid);
@@ -580,7 +647,9 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
     };
     transform_plan<N, FP::I0, FP::I1, FP::I2, true, Map::Pencil, NF, T, NF, true, false>(twz, from_lds, from_lds,
                                                                                     to_lds, store_last, tid);
+    walk.claim_store(it, claim);
     __syncthreads();  // the next tile's first stage rewrites the tile
+    t = tn;
   }
 }
 
@@ -661,26 +730,30 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
 
 template <int N, typename S>
 hipError_t go_xf(const int32_t* own, const int2* lnk, const DevDefect* defs, const double* dense, void* spec,
-                 SpecGeom g, const double2* tw, hipStream_t s) {
+                 SpecGeom g, const double2* tw, uint32_t* zero_ctr, hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
+  static_assert(T >= NTILECTR, "the first block zeroes the tile counters");
   const int grid = N * (N / x_rows(N));
   using C2 = typename Cplx<S>::T;
   if (dense)
-    hipLaunchKernelGGL((k_x_forward<N, S, true>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P, tw);
+    hipLaunchKernelGGL((k_x_forward<N, S, true>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P, tw,
+                       zero_ctr);
   else
     hipLaunchKernelGGL((k_x_forward<N, S, false>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P,
-                       tw);
+                       tw, zero_ctr);
   return hipGetLastError();
 }
 
 template <int N, typename S>
 hipError_t go_xfs(const int32_t* oi, const int32_t* oc, const int32_t* ni, int nc, int sx, int sy, int sz, const double* E,
-                  void* spec, SpecGeom g, int ylo, int ylen, int zlo, int zlen, const double2* tw, hipStream_t s) {
+                  void* spec, SpecGeom g, int ylo, int ylen, int zlo, int zlen, const double2* tw, uint32_t* zero_ctr,
+                  hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
+  static_assert(T >= NTILECTR, "the first block zeroes the tile counters");
   const int grid = zlen * ((ylen + x_rows(N) - 1) / x_rows(N));
-  if (grid == 0) return hipSuccess;
+  if (grid == 0) return zero_ctr ? launch_fill_i32((int32_t*)zero_ctr, NTILECTR, 0, s) : hipSuccess;
   hipLaunchKernelGGL((k_x_forward_sparse<N, S>), dim3(grid), dim3(T), 0, s, oi, oc, ni, nc, sx, sy, sz, E,
-                     (typename Cplx<S>::T*)spec, g.P, ylo, ylen, zlo, tw);
+                     (typename Cplx<S>::T*)spec, g.P, ylo, ylen, zlo, tw, zero_ctr);
   return hipGetLastError();
 }
 
@@ -702,7 +775,8 @@ int tile_grid(K kernel, int threads, int ntiles, bool prefetch) {
 // FP32 storage stages the inter-stage exchange in FP32 (half the LDS, so
 // twice the columns per tile); FP64 storage keeps FP64 staging.
 template <int N, typename S>
-hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, hipStream_t s) {
+hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw, uint32_t* ctr,
+                     hipStream_t s) {
   using LT = typename Cplx<S>::T;
   constexpr int T = pencil_threads<N, LT>();
   constexpr int KB = (N / 2 + 1 + pencil_wx<N, LT>() - 1) / pencil_wx<N, LT>();
@@ -717,7 +791,7 @@ hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const
                       : (inv ? k_pencil<N, S, true, LT, false, 2> : k_pencil<N, S, false, LT, false, 2>);
   const int grid = tile_grid(k, T, ntiles, sizeof(S) == 4);
   if (grid < 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, pr, tw, ntiles);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, pr, tw, ntiles, ctr);
   return hipGetLastError();
 }
 
@@ -753,12 +827,12 @@ bool fft_supported(int n) {
 int pencil_width(int n, bool) { return n >= 512 ? 8 : 16; }
 
 hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs, const double* dense,
-                            void* spec, SpecGeom g, const double2* tw, hipStream_t s) {
+                            void* spec, SpecGeom g, const double2* tw, uint32_t* zero_ctr, hipStream_t s) {
   switch (g.n) {
-#define EC_CASE(NN)                                                           \
-  case NN:                                                                    \
-    return fp64 ? go_xf<NN, double>(own, lnk, defs, dense, spec, g, tw, s) \
-                : go_xf<NN, float>(own, lnk, defs, dense, spec, g, tw, s);
+#define EC_CASE(NN)                                                                     \
+  case NN:                                                                              \
+    return fp64 ? go_xf<NN, double>(own, lnk, defs, dense, spec, g, tw, zero_ctr, s) \
+                : go_xf<NN, float>(own, lnk, defs, dense, spec, g, tw, zero_ctr, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }
@@ -767,14 +841,15 @@ hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, cons
 
 hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, const int32_t* old_cnt, const int32_t* new_ids,
                                    int new_cnt, int sx, int sy, int sz, const double* E, void* spec, SpecGeom g,
-                                   int y_lo, int y_len, int z_lo, int z_len, const double2* tw, hipStream_t s) {
+                                   int y_lo, int y_len, int z_lo, int z_len, const double2* tw, uint32_t* zero_ctr,
+                                   hipStream_t s) {
   switch (g.n) {
 #define EC_CASE(NN)                                                                                          \
   case NN:                                                                                                   \
     return fp64 ? go_xfs<NN, double>(old_ids, old_cnt, new_ids, new_cnt, sx, sy, sz, E, spec, g, y_lo, y_len, \
-                                     z_lo, z_len, tw, s)                                                      \
+                                     z_lo, z_len, tw, zero_ctr, s)                                            \
                 : go_xfs<NN, float>(old_ids, old_cnt, new_ids, new_cnt, sx, sy, sz, E, spec, g, y_lo, y_len,  \
-                                    z_lo, z_len, tw, s);
+                                    z_lo, z_len, tw, zero_ctr, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }
@@ -782,12 +857,12 @@ hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, const int3
 }
 
 hipError_t launch_pencil(bool fp64, bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw,
-                         hipStream_t s) {
+                         uint32_t* ctr, hipStream_t s) {
   switch (g.n) {
-#define EC_CASE(NN)                                                   \
-  case NN:                                                            \
-    return fp64 ? go_pencil<NN, double>(inv, axis, spec, g, pr, tw, s) \
-                : go_pencil<NN, float>(inv, axis, spec, g, pr, tw, s);
+#define EC_CASE(NN)                                                        \
+  case NN:                                                                 \
+    return fp64 ? go_pencil<NN, double>(inv, axis, spec, g, pr, tw, ctr, s) \
+                : go_pencil<NN, float>(inv, axis, spec, g, pr, tw, ctr, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }
@@ -805,7 +880,7 @@ hipError_t launch_green(bool fp64, void* spec, SpecGeom g, Cubic C, hipStream_t 
 }
 
 template <int N, typename S>
-hipError_t go_zgreen(void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, hipStream_t s) {
+hipError_t go_zgreen(void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, uint32_t* ctr, hipStream_t s) {
   constexpr int W = zg_width<N, S>();
   constexpr int T = zg_threads<N, S>();
   constexpr int NT = N * ((N / 2 + 1 + W - 1) / W);
@@ -815,15 +890,17 @@ hipError_t go_zgreen(void* spec, SpecGeom g, Cubic C, Prune pr, const double2* t
   auto* k = prune ? k_zgreen<N, S, true> : k_zgreen<N, S, false>;
   const int grid = tile_grid(k, T, NT, sizeof(S) == 4);
   if (grid < 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, C, pr, tw);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, C, pr, tw, ctr);
   return hipGetLastError();
 }
 
-hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, hipStream_t s) {
+hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, uint32_t* ctr,
+                          hipStream_t s) {
   switch (g.n) {
-#define EC_CASE(NN) \
-  case NN:          \
-    return fp64 ? go_zgreen<NN, double>(spec, g, C, pr, tw, s) : go_zgreen<NN, float>(spec, g, C, pr, tw, s);
+#define EC_CASE(NN)                                                      \
+  case NN:                                                               \
+    return fp64 ? go_zgreen<NN, double>(spec, g, C, pr, tw, ctr, s)      \
+                : go_zgreen<NN, float>(spec, g, C, pr, tw, ctr, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }
