@@ -162,8 +162,10 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
  * full solve).  Host buffers; synchronises.  *total receives the id count. */
 ec_status ec_state_footprints(ec_state* st, int32_t* counts, int32_t* ids, int64_t ids_capacity, int64_t* total);
 
-/* Copy a resident field to a host buffer of 6*n^3 doubles: which = 0 sigma,
- * 1 eps (total strain), 2 eps* (eigenstrain). Synchronises. */
+/* Copy a resident field to a host buffer of 6*n^3 doubles, component-major
+ * [6][n^3] like every field this interface hands out (the resident stress is
+ * kept voxel-major and converted): which = 0 sigma, 1 eps (total strain),
+ * 2 eps* (eigenstrain). Synchronises. */
 ec_status ec_state_field(ec_state* st, int32_t which, double* host_out);
 
 /* Self terms B_i (eV) of the current defect list, host buffer of ndef doubles. */

@@ -176,7 +176,7 @@ struct ec_state {
   size_t spec_bytes = 0, held = 0;
   void* spec = nullptr;
   int32_t* own = nullptr;  // per-voxel head of the membership list
-  double* sig = nullptr;
+  double* sig = nullptr;   // resident FP64 stress, voxel-major [n^3][6]
   double* add6 = nullptr;  // [0..6) additive stress of the full solve, [6..12) zeros, [12..18) update delta
   double2* tw = nullptr;
   // defect list
@@ -1148,7 +1148,7 @@ ec_status ec_interaction_energies(ec_state* st, void* stream, double* E_out, int
   if ((r = join_self(st, s)) != EC_OK) return r;
   const DefBuf& b = st->db[st->cur];
   LAUNCH(st, s, PF_REDUCE, 0,
-         launch_reduce(b.tab, st->ndef, b.cnt, b.ids, st->sig, st->n3, st->B, st->h3c, st->S6, st->E, s));
+         launch_reduce(b.tab, st->ndef, b.cnt, b.ids, st->sig, st->B, st->h3c, st->S6, st->E, s));
   if (E_out && st->ndef > 0) return copy_out(E_out, st->E, st->ndef * 8, on_device != 0, s);
   return EC_OK;
 }
@@ -1326,26 +1326,17 @@ ec_status ec_state_field(ec_state* st, int32_t which, double* out) {
   if (!st || !out) return fail(EC_ERR_ARG, "NULL argument");
   HIPCHK(hipDeviceSynchronize());
   const size_t cnt = (size_t)6 * st->n3;
-  if (which == 0) {
-    HIPCHK(hipMemcpy(out, st->sig, cnt * 8, hipMemcpyDeviceToHost));
-  } else if (which == 1) {
+  if (which >= 0 && which <= 2) {
+    // component-major copy of the voxel-major stress, or the strain or
+    // eigenstrain derived from it, through a device temporary
     void* tmp = nullptr;
     ec_status r = ledger_alloc(st->ctx, cnt * 8, &tmp);
     if (r != EC_OK) return r;
     const DefBuf& b = st->db[st->cur];
-    hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, 1, false, tmp, nullptr);
+    hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, which, false, tmp, nullptr);
     if (e == hipSuccess) e = hipMemcpy(out, tmp, cnt * 8, hipMemcpyDeviceToHost);
     ledger_free(st->ctx, tmp, cnt * 8);
-    if (e != hipSuccess) return fail(EC_ERR_DEVICE, "strain output: %s", hipGetErrorString(e));
-  } else if (which == 2) {
-    void* tmp = nullptr;
-    ec_status r = ledger_alloc(st->ctx, cnt * 8, &tmp);
-    if (r != EC_OK) return r;
-    const DefBuf& b = st->db[st->cur];
-    hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, 2, false, tmp, nullptr);
-    if (e == hipSuccess) e = hipMemcpy(out, tmp, cnt * 8, hipMemcpyDeviceToHost);
-    ledger_free(st->ctx, tmp, cnt * 8);
-    if (e != hipSuccess) return fail(EC_ERR_DEVICE, "eigenstrain output: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(EC_ERR_DEVICE, "field output %d: %s", which, hipGetErrorString(e));
   } else {
     return fail(EC_ERR_ARG, "unknown field %d", which);
   }
@@ -1483,10 +1474,11 @@ ec_status ec_debug_green(ec_state* st, const double* in, double* out) {
 ec_status ec_debug_inverse(ec_state* st, const double* in, double* out) {
   if (!st || !in || !out) return fail(EC_ERR_ARG, "NULL argument");
   const size_t cnt = (size_t)6 * st->n3;
-  Tmp sp{st->ctx}, sg{st->ctx}, ad{st->ctx};
+  Tmp sp{st->ctx}, sg{st->ctx}, ad{st->ctx}, cm{st->ctx};
   ec_status r;
   if ((r = ledger_alloc(st->ctx, sp.b = st->spec_bytes, &sp.p)) != EC_OK) return r;
   if ((r = ledger_alloc(st->ctx, sg.b = cnt * 8, &sg.p)) != EC_OK) return r;
+  if ((r = ledger_alloc(st->ctx, cm.b = cnt * 8, &cm.p)) != EC_OK) return r;
   if ((r = ledger_alloc(st->ctx, ad.b = 64, &ad.p)) != EC_OK) return r;
   if ((r = upload_spec(st, in, sp.p)) != EC_OK) return r;
   HIPCHK(hipMemset(ad.p, 0, 64));
@@ -1494,8 +1486,10 @@ ec_status ec_debug_inverse(ec_state* st, const double* in, double* out) {
   HIPCHK(launch_pencil(st->fp64, true, 2, sp.p, st->g, full, st->tw, nullptr, nullptr));
   HIPCHK(launch_pencil(st->fp64, true, 1, sp.p, st->g, full, st->tw, nullptr, nullptr));
   HIPCHK(launch_x_inverse(st->fp64, false, sp.p, (double*)sg.p, st->g, (const double*)ad.p, st->tw, nullptr));
+  // voxel-major result -> the component-major [6][n^3] of the entry point
+  HIPCHK(launch_sig_to_out((const double*)sg.p, nullptr, nullptr, nullptr, st->n3, st->C, 0, false, cm.p, nullptr));
   HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMemcpy(out, sg.p, cnt * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(out, cm.p, cnt * 8, hipMemcpyDeviceToHost));
   return EC_OK;
 }
 

@@ -260,8 +260,9 @@ hipError_t launch_mean_stress(const DevDefect* d, const int32_t* counts, int nde
                               double* add6, hipStream_t s);
 hipError_t launch_scan(const int32_t* counts, int ndef, int64_t* offsets, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t count, int64_t v, hipStream_t s);
+// sig: the resident stress, voxel-major [n^3][6]
 hipError_t launch_reduce(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, const double* sig,
-                         int64_t n3, const double* B, double h3c, double* S6, double* E, hipStream_t s);
+                         const double* B, double h3c, double* S6, double* E, hipStream_t s);
 hipError_t launch_window_crop(const double* sig, int n, int D, int b, double* K, hipStream_t s);
 hipError_t launch_class_windows(const double* K, int D, const double* dirs, int ncls, double* g, hipStream_t s);
 // Self-term work item: rows [p0, p1) of defect `def`'s pair triangle.

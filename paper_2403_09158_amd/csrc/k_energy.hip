@@ -26,6 +26,18 @@ __device__ __forceinline__ void neumaier(double& s, double& c, double v) {
 
 constexpr int RDT = 256;  // threads per defect
 
+// The six stress components of voxel id (sigma is voxel-major, [n^3][6]):
+// three aligned 16-byte loads.
+__device__ __forceinline__ void ld_voxel(const double* __restrict__ sig, int64_t id, double* v) {
+  const double2* q = reinterpret_cast<const double2*>(sig + 6 * id);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const double2 w = q[j];
+    v[2 * j] = w.x;
+    v[2 * j + 1] = w.y;
+  }
+}
+
 // (s, c) += (s2, c2) for Neumaier pairs
 __device__ __forceinline__ void neumaier_merge(double& s, double& c, double s2, double c2) {
   neumaier(s, c, s2);
@@ -38,7 +50,7 @@ __device__ __forceinline__ void neumaier_merge(double& s, double& c, double s2, 
 // E_i = -h^3 c E_i:S_i - B_i.
 __global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
                                                 const int32_t* __restrict__ ids, const double* __restrict__ sig,
-                                                int64_t n3, const double* __restrict__ B, double h3c,
+                                                const double* __restrict__ B, double h3c,
                                                 double* __restrict__ S6, double* __restrict__ E) {
   const int i = blockIdx.x;
   const int64_t o = defs[i].slot;
@@ -53,18 +65,17 @@ __global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ de
     for (int j = 0; j < 4; ++j) id[j] = ids[o + k + j * RDT];
     double v[4][6];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int a = 0; a < 6; ++a) v[j][a] = sig[a * n3 + id[j]];
+    for (int j = 0; j < 4; ++j) ld_voxel(sig, id[j], v[j]);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int a = 0; a < 6; ++a) neumaier(s[a], c[a], v[j][a]);
   }
   for (; k < m; k += RDT) {
-    const int id = ids[o + k];
+    double v[6];
+    ld_voxel(sig, ids[o + k], v);
 #pragma unroll
-    for (int a = 0; a < 6; ++a) neumaier(s[a], c[a], sig[a * n3 + id]);
+    for (int a = 0; a < 6; ++a) neumaier(s[a], c[a], v[a]);
   }
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
@@ -105,9 +116,8 @@ __global__ void k_window_crop(const double* __restrict__ sig, int n, int D, int 
   if (t >= (int64_t)W * W * W) return;
   const int rx = (int)(t % W) - D, ry = (int)((t / W) % W) - D, rz = (int)(t / ((int64_t)W * W)) - D;
   const int x = (rx % n + n) % n, y = (ry % n + n) % n, z = (rz % n + n) % n;
-  const int64_t n3 = (int64_t)n * n * n;
   const int64_t id = ((int64_t)z * n + y) * n + x;
-  for (int a = 0; a <= b; ++a) K[t * KWIN + tri(a, b)] = ddot_w(a) * sig[a * n3 + id];
+  for (int a = 0; a <= b; ++a) K[t * KWIN + tri(a, b)] = ddot_w(a) * sig[6 * id + a];
 }
 
 // Scalar window per eigenstrain direction class: g_c(r) = e_c : K(r) : e_c.
@@ -308,8 +318,9 @@ __global__ void k_self_finish(const int64_t* __restrict__ wbeg, const double* __
   B[i] = -h3c * scale * (s + c);
 }
 
-// Dense outputs: which 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic
-// compliance), 2 -> eps* (owner-list gather).
+// Dense component-major outputs [6][n^3] from the voxel-major sigma: which
+// 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic compliance), 2 -> eps*
+// (owner-list gather).
 template <typename OT>
 __global__ void k_sig_to_out(const double* __restrict__ sig, const int32_t* __restrict__ own,
                              const int2* __restrict__ lnk, const DevDefect* __restrict__ defs, int64_t n3, Cubic C,
@@ -327,8 +338,7 @@ __global__ void k_sig_to_out(const double* __restrict__ sig, const int32_t* __re
     return;
   }
   double s[6];
-#pragma unroll
-  for (int a = 0; a < 6; ++a) s[a] = sig[a * n3 + t];
+  ld_voxel(sig, t, s);
   if (which == 0) {
 #pragma unroll
     for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)s[a];
@@ -363,9 +373,9 @@ hipError_t launch_set_class(DevDefect* d, int ndef, const ClassTag* tags, hipStr
 }
 
 hipError_t launch_reduce(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, const double* sig,
-                         int64_t n3, const double* B, double h3c, double* S6, double* E, hipStream_t s) {
+                         const double* B, double h3c, double* S6, double* E, hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(ndef), dim3(RDT), 0, s, d, counts, ids, sig, n3, B, h3c, S6, E);
+  hipLaunchKernelGGL(k_reduce, dim3(ndef), dim3(RDT), 0, s, d, counts, ids, sig, B, h3c, S6, E);
   return hipGetLastError();
 }
 

@@ -710,18 +710,18 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   };
   auto from_lds = [&](int f, int i) { return buf[f * LDN + i + (i >> 4)]; };
   auto to_lds = [&](int f, int i, double2 v) { buf[f * LDN + i + (i >> 4)] = v; };
+  // sigma is voxel-major, [n^3][6]: components 2p and 2p+1 of a voxel are one
+  // aligned 16-byte pair, and the lanes of a store cover whole voxel records
   auto store_last = [&](int f, int x, double2 v) {
     const int p = f % 3, y = y0 + f / 3;
-    double* s0 = sig + (2 * p * N3 + (z * N + y) * N + x);
-    double* s1 = s0 + N3;
-    const double a = v.x * scale + mean_s[2 * p], b = v.y * scale + mean_s[2 * p + 1];
+    double2* s01 = reinterpret_cast<double2*>(sig + (6 * ((z * N + y) * N + x) + 2 * p));
+    double2 r = make_double2(v.x * scale + mean_s[2 * p], v.y * scale + mean_s[2 * p + 1]);
     if (ACC) {
-      *s0 += a;
-      *s1 += b;
-    } else {
-      *s0 = a;
-      *s1 = b;
+      const double2 o = *s01;
+      r.x += o.x;
+      r.y += o.y;
     }
+    *s01 = r;
   };
   transform<N, true, Map::Row, NF, T>(tw, load0, from_lds, to_lds, store_last);
 }
