@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <condition_variable>
@@ -60,8 +61,14 @@ struct WinCache {
 // Host worker threads for per-defect preparation of large defect lists.
 // run(n, fn) calls fn(c) for every chunk c in [0, n) on the workers and the
 // calling thread and returns when all chunks are done; a worker that wakes
-// after the job has closed does nothing.
+// after the job has closed does nothing.  Solves of a running simulation come
+// a millisecond or two apart, so after a job the workers poll for the next
+// one for SPIN_MS (yielding the core between polls) before they sleep: a
+// sleeping worker takes tens of microseconds to wake, longer than its share
+// of a 2000-defect list.
 class WorkPool {
+  static constexpr int SPIN_MS = 5;
+
  public:
   explicit WorkPool(int nworkers) {
     for (int i = 0; i < nworkers; ++i) th_.emplace_back([this] { loop(); });
@@ -70,6 +77,7 @@ class WorkPool {
     {
       std::lock_guard<std::mutex> lk(mu_);
       stop_ = true;
+      astop_.store(true, std::memory_order_release);
     }
     cv_.notify_all();
     for (auto& t : th_) t.join();
@@ -79,6 +87,9 @@ class WorkPool {
       for (int c = 0; c < nchunks; ++c) fn(c);
       return;
     }
+    // states of one context may be driven from several host threads: one job
+    // at a time
+    std::lock_guard<std::mutex> one(run_mu_);
     {
       std::lock_guard<std::mutex> lk(mu_);
       fn_ = &fn;
@@ -86,6 +97,7 @@ class WorkPool {
       next_.store(0);
       open_ = true;
       ++gen_;
+      agen_.store(gen_, std::memory_order_release);
     }
     cv_.notify_all();
     work();
@@ -101,27 +113,36 @@ class WorkPool {
   }
   void loop() {
     uint64_t seen = 0;
-    std::unique_lock<std::mutex> lk(mu_);
+    std::unique_lock<std::mutex> lk(mu_, std::defer_lock);
     for (;;) {
+      const auto until = std::chrono::steady_clock::now() + std::chrono::milliseconds(SPIN_MS);
+      while (agen_.load(std::memory_order_acquire) == seen && !astop_.load(std::memory_order_acquire) &&
+             std::chrono::steady_clock::now() < until)
+        std::this_thread::yield();
+      lk.lock();
       cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
       if (stop_) return;
       seen = gen_;
-      if (!open_) continue;
-      ++inside_;
+      if (open_) {
+        ++inside_;
+        lk.unlock();
+        work();
+        lk.lock();
+        if (--inside_ == 0) done_.notify_all();
+      }
       lk.unlock();
-      work();
-      lk.lock();
-      if (--inside_ == 0) done_.notify_all();
     }
   }
   std::vector<std::thread> th_;
-  std::mutex mu_;
+  std::mutex run_mu_, mu_;
   std::condition_variable cv_, done_;
   const std::function<void(int)>* fn_ = nullptr;
   int nchunks_ = 0, inside_ = 0;
   std::atomic<int> next_{0};
   uint64_t gen_ = 0;
   bool open_ = false, stop_ = false;
+  std::atomic<uint64_t> agen_{0};  // gen_, readable without the lock
+  std::atomic<bool> astop_{false};
 };
 
 struct ec_ctx {
@@ -550,6 +571,53 @@ void assign_class(ec_state* st, DevDefect& d) {
   }
 }
 
+// Classes of a whole list, the same as assign_class on each defect in list
+// order: the directions are computed on the workers, then looked up in list
+// order (so indices follow first appearance) through a small open-addressing
+// table keyed by the direction's bit pattern.
+void assign_classes(ec_state* st, std::vector<DevDefect>& defs) {
+  const size_t nd = defs.size();
+  std::vector<std::array<double, 6>> dir(nd);
+  std::vector<double> sc(nd);
+  constexpr size_t CH = 256;
+  st->ctx->pool->run((int)((nd + CH - 1) / CH), [&](int c) {
+    for (size_t i = c * CH; i < std::min(nd, (c + 1) * CH); ++i) direction(defs[i], dir[i], sc[i]);
+  });
+  constexpr int HS = 2 * MAXCLS;  // at most MAXCLS keys
+  static_assert((HS & (HS - 1)) == 0, "power-of-two table");
+  int slot[HS];
+  std::fill(slot, slot + HS, -1);
+  auto home = [](const std::array<double, 6>& e) {
+    uint64_t h = 1469598103934665603ull;
+    for (double v : e) {
+      uint64_t b;
+      std::memcpy(&b, &v, 8);
+      h = (h ^ b) * 1099511628211ull;
+    }
+    return (int)(h >> 58) & (HS - 1);
+  };
+  for (size_t i = 0; i < nd; ++i) {
+    DevDefect& d = defs[i];
+    d.s = sc[i];
+    d.cls = -1;
+    if (sc[i] == 0.0) continue;
+    for (int k = home(dir[i]);; k = (k + 1) & (HS - 1)) {
+      const int c = slot[k];
+      if (c < 0) {
+        if ((int)st->classes.size() < MAXCLS) {
+          st->classes.push_back(dir[i]);
+          d.cls = slot[k] = (int)st->classes.size() - 1;
+        }
+        break;
+      }
+      if (std::memcmp(st->classes[c].data(), dir[i].data(), sizeof(double) * 6) == 0) {
+        d.cls = c;
+        break;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ solve pipeline
 
 double spec_valid_bytes(const ec_state* st, bool fp64) {
@@ -696,7 +764,7 @@ ec_status ensure_classes(ec_state* st, hipStream_t s) {
   if (nd > 0 && (r = st_grow(st, &st->tags, &st->tags_cap, nd)) != EC_OK) return r;
   const std::vector<std::array<double, 6>> old = st->classes;
   st->classes.clear();
-  for (auto& d : st->hdefs) assign_class(st, d);
+  assign_classes(st, st->hdefs);
   if (old != st->classes) st->gcls_ncls = -1;
   if (nd > 0) {
     char* hp = nullptr;
