@@ -212,18 +212,25 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   // thread, so consecutive threads write consecutive 16-byte values of the
   // row; FP32 storage: one bin (six values, 48 bytes) per thread, which
   // halves the LDS reads and index work where the narrower writes matter less.
+  // The loops run over bins k < n/2; the thread of bin 0 of a row also does
+  // its bin n/2 (k = n/2 is its own mirror), so no loop pass is left with two
+  // busy threads.
   if constexpr (sizeof(S) == 8) {
-    for (int e = threadIdx.x; e < ROWS * NH * 6; e += T) {
-      const int r = e / (NH * 6), q = e % (NH * 6), k = q / 6, c = q % 6, p = c >> 1;
+    auto value = [&](int r, int k, int c) {
+      const int p = c >> 1;
       const double2 zk = ld2(lds(3 * r + p, k));
       const double2 zc = conjd(ld2(lds(3 * r + p, k == 0 ? 0 : N - k)));
       const double2 v = (c & 1) ? make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x))
                                 : make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
       st2(spec + spec_at(z, y0 + r, k, c, N, P), v);
+    };
+    for (int e = threadIdx.x; e < ROWS * (N / 2) * 6; e += T) {
+      const int r = e / ((N / 2) * 6), q = e % ((N / 2) * 6), k = q / 6, c = q % 6;
+      value(r, k, c);
+      if (k == 0) value(r, N / 2, c);
     }
   } else {
-    for (int e = threadIdx.x; e < ROWS * NH; e += T) {
-      const int r = e / NH, k = e % NH;
+    auto bin = [&](int r, int k) {
       typename Cplx<S>::T* const out = spec + spec_at(z, y0 + r, k, 0, N, P);
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
@@ -232,6 +239,11 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
         st2(out + 2 * p, make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y)));
         st2(out + 2 * p + 1, make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x)));
       }
+    };
+    for (int e = threadIdx.x; e < ROWS * (N / 2); e += T) {
+      const int r = e / (N / 2), k = e % (N / 2);
+      bin(r, k);
+      if (k == 0) bin(r, N / 2);
     }
   }
 }

@@ -133,3 +133,55 @@ def test_realtime_latency_bookkeeping():
     assert stats.p50_ms <= stats.p99_ms
     # the trace spans about 80 / 4000 s; the loop cannot finish before the last arrival
     assert stats.wall_s >= max(r.t for r in reqs)
+
+
+def test_states_driven_from_two_host_threads():
+    """Two states of one context, each solved by its own host thread on its own
+    stream at the same time (the context's host workers and each state's tile
+    counters shared or contended), give the energies of one-at-a-time runs,
+    bit for bit."""
+    import threading
+
+    import torch
+
+    from paper_2403_09158_amd import ec
+
+    rng = np.random.default_rng(inputs.SEED_BASE + 720)
+    cases = []
+    for n in (128, 96):
+        L = n * inputs.H_VOXEL
+        prob = inputs.Problem(n, L, *inputs.CUBIC_FE, prec=1)
+        d = inputs.mixed_population(rng, 400, L, inputs.H_VOXEL, r111=(0.4, 1.6), r100=(0.5, 1.6))
+        cases.append((prob, d))
+    ctx = ec.Context()
+    states = [ec.State(ctx, p) for p, _ in cases]
+    want = []
+    for st, (_, d) in zip(states, cases):
+        st.solve(d)
+        want.append(st.energies().copy())
+    got = [[] for _ in cases]
+    errors = []
+
+    def drive(k):
+        try:
+            s = torch.cuda.Stream()
+            for _ in range(6):
+                states[k].solve(cases[k][1], stream=s)
+                got[k].append(states[k].energies(stream=s).copy())
+        except Exception as e:  # reported below, in the test's thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=drive, args=(k,)) for k in range(len(cases))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
+    for k in range(len(cases)):
+        assert len(got[k]) == 6
+        for E in got[k]:
+            assert np.array_equal(E, want[k])
+    for st in states:
+        st.close()
+    ctx.close()
