@@ -35,6 +35,10 @@
 #ifndef EC_H
 #define EC_H
 
+/* The library is built with hidden symbols; these entry points are its only
+ * exports. */
+#define EC_API __attribute__((visibility("default")))
+
 #include <stddef.h>
 #include <stdint.h>
 
@@ -114,30 +118,30 @@ typedef void (*ec_free_fn)(void* p, void* stream, void* user);
 /* Create a context on HIP device `device` with an HBM admission budget (bytes;
  * 0 = the device's free memory at creation).  Caches Green-kernel windows per
  * (n, C, bc). */
-ec_status ec_ctx_create(int device, size_t hbm_budget_bytes, ec_alloc_fn alloc_fn, ec_free_fn free_fn,
+EC_API ec_status ec_ctx_create(int device, size_t hbm_budget_bytes, ec_alloc_fn alloc_fn, ec_free_fn free_fn,
                         void* user, ec_ctx** out);
-void ec_ctx_destroy(ec_ctx* ctx);
+EC_API void ec_ctx_destroy(ec_ctx* ctx);
 
 /* Bytes the context has admitted so far, and its budget. */
-ec_status ec_ctx_ledger(const ec_ctx* ctx, size_t* used, size_t* budget);
+EC_API ec_status ec_ctx_ledger(const ec_ctx* ctx, size_t* used, size_t* budget);
 
 /* Thread-local text of the last error raised on this thread (never NULL). */
-const char* ec_last_error(void);
+EC_API const char* ec_last_error(void);
 
 /* Create a replica state for one problem; reserves its resident fields in the
  * ledger (EC_ERR_ADMIT if the budget would be exceeded). */
-ec_status ec_state_create(ec_ctx* ctx, const ec_problem* problem, ec_state** out);
-void ec_state_destroy(ec_state* st);
+EC_API ec_status ec_state_create(ec_ctx* ctx, const ec_problem* problem, ec_state** out);
+EC_API void ec_state_destroy(ec_state* st);
 
 /* Bytes of device memory the state holds (fields, spectrum, footprints). */
-ec_status ec_state_bytes(const ec_state* st, size_t* bytes);
+EC_API ec_status ec_state_bytes(const ec_state* st, size_t* bytes);
 
 /* Full solve (Sec. 3.2, 3.4): rasterise defs[0..ndef) (host array, copied),
  * Fourier-space Green solve, sigma = C:(eps - eps*) kept resident in FP64.
  * Optional outputs eps_out / sig_out ([6][n^3], float for EC_FP32 states,
  * double for EC_FP64 states) on the device (out_on_device != 0) or on the host;
  * NULL skips them.  Replaces any previous defect list of the state. */
-ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, void* hip_stream, void* eps_out,
+EC_API ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, void* hip_stream, void* eps_out,
                           void* sig_out, int32_t out_on_device);
 
 /* Per-defect interaction energies of the current defect list, in input order
@@ -146,13 +150,13 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
  * evaluated as -h^3 c E_i:S_i - B_i with S_i the FP64 compensated sum of the
  * resident stress over the footprint of i and B_i the exact discrete self term
  * (c = 1 GPa nm^3 in eV).  E_out holds ndef doubles (device or host). */
-ec_status ec_interaction_energies(ec_state* st, void* hip_stream, double* E_out, int32_t out_on_device);
+EC_API ec_status ec_interaction_energies(ec_state* st, void* hip_stream, double* E_out, int32_t out_on_device);
 
 /* Move defect idx to the record *moved (Appendix B: subtract the old field,
  * add the new one).  By linearity only the eigenstrain difference is solved;
  * the resident FP64 stress is accumulated and, if E_out != NULL, all ndef
  * energies are returned as in ec_interaction_energies. */
-ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, void* hip_stream, double* E_out,
+EC_API ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, void* hip_stream, double* E_out,
                            int32_t out_on_device);
 
 /* ---- inspection (tests, benchmarks) ---------------------------------------- */
@@ -160,16 +164,16 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
 /* Footprints of the current defect list: counts[ndef] and, if ids != NULL, the
  * concatenated voxel ids in defect order (each defect's ids ascending after a
  * full solve).  Host buffers; synchronises.  *total receives the id count. */
-ec_status ec_state_footprints(ec_state* st, int32_t* counts, int32_t* ids, int64_t ids_capacity, int64_t* total);
+EC_API ec_status ec_state_footprints(ec_state* st, int32_t* counts, int32_t* ids, int64_t ids_capacity, int64_t* total);
 
 /* Copy a resident field to a host buffer of 6*n^3 doubles, component-major
  * [6][n^3] like every field this interface hands out (the resident stress is
  * kept voxel-major and converted): which = 0 sigma, 1 eps (total strain),
  * 2 eps* (eigenstrain). Synchronises. */
-ec_status ec_state_field(ec_state* st, int32_t which, double* host_out);
+EC_API ec_status ec_state_field(ec_state* st, int32_t which, double* host_out);
 
 /* Self terms B_i (eV) of the current defect list, host buffer of ndef doubles. */
-ec_status ec_state_self_terms(ec_state* st, double* host_out);
+EC_API ec_status ec_state_self_terms(ec_state* st, double* host_out);
 
 /* Kernel timing: when enabled, HIP events bracket every kernel the state
  * launches; ec_profile_read returns, per kernel family, the launch count,
@@ -177,24 +181,24 @@ ec_status ec_state_self_terms(ec_state* st, double* host_out);
  * 0 raster, 1 x-forward, 2 y-pass, 3 z-pass (fused with the Green operator),
  * 4 x-inverse + stress, 5 energy reduction, 6 self term, 7 other. */
 #define EC_NPROF 8
-ec_status ec_profile_enable(ec_state* st, int32_t on);
-ec_status ec_profile_read(ec_state* st, int64_t* launches, double* ms, double* bytes_per_launch);
+EC_API ec_status ec_profile_enable(ec_state* st, int32_t on);
+EC_API ec_status ec_profile_read(ec_state* st, int64_t* launches, double* ms, double* bytes_per_launch);
 
 /* ---- kernel-level entry points (parity tests of single passes) -------------- */
 
 /* Forward transform of a real [6][n^3] FP64 host field with this state's
  * kernels: writes the half spectrum [6][n][n][n/2+1] complex128 (interleaved
  * re, im; unnormalised forward DFT) to host_out. */
-ec_status ec_debug_forward(ec_state* st, const double* host_field, double* host_out);
+EC_API ec_status ec_debug_forward(ec_state* st, const double* host_field, double* host_out);
 
 /* Green step alone: host half spectrum of eps* ([6][n][n][n/2+1] complex128)
  * in, half spectrum of sigma = S(xi):eps*_hat out (S = C Gamma C - C, zero at
  * xi = 0), with the state's Nyquist rule. */
-ec_status ec_debug_green(ec_state* st, const double* host_spec_in, double* host_spec_out);
+EC_API ec_status ec_debug_green(ec_state* st, const double* host_spec_in, double* host_spec_out);
 
 /* Inverse transform of a host half spectrum to a real [6][n^3] host field
  * (scaled by 1/n^3, imaginary parts of the kx = 0 and n/2 planes dropped). */
-ec_status ec_debug_inverse(ec_state* st, const double* host_spec, double* host_out);
+EC_API ec_status ec_debug_inverse(ec_state* st, const double* host_spec, double* host_out);
 
 #ifdef __cplusplus
 }

@@ -38,6 +38,9 @@ CFLAGS = [
     "-msse4.2",
     "-Xarch_host",
     "-fno-math-errno",
+    # host symbols hidden: the C entry points of include/ec.h are the exports
+    "-Xarch_host",
+    "-fvisibility=hidden",
 ]
 
 

@@ -626,8 +626,14 @@ double spec_valid_bytes(const ec_state* st, bool fp64) {
 
 // ctr: the state's tile counters, or nullptr (fixed tile order; for solves
 // that may run beside the state's own passes)
+ec_status self_terms_beside(ec_state* st);
+ec_status join_self(ec_state* st, hipStream_t s);
+
+// `between` (may be empty) runs on the host after the forward x and y passes
+// are enqueued and before the z pass is.
 ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs,
-                   void* spec, double* sig, const double* add6, uint32_t* ctr) {
+                   void* spec, double* sig, const double* add6, uint32_t* ctr,
+                   const std::function<ec_status()>& between = {}) {
   const Prune full{0, st->n, 0, st->n};
   const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
   SpecGeom g{st->n, 0};
@@ -635,6 +641,10 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
   LAUNCH(st, s, PF_XF, 4.0 * (double)st->n3 + sb,
          launch_x_forward(fp64, own, lnk, defs, nullptr, spec, g, st->tw, ctr, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, false, 1, spec, g, full, st->tw, ctr ? ctr : nullptr, s));
+  if (between) {
+    const ec_status r = between();
+    if (r != EC_OK) return r;
+  }
   LAUNCH(st, s, PF_Z, 2 * sb, launch_z_green(fp64, spec, g, st->C, full, st->tw, ctr ? ctr + 8 : nullptr, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, spec, g, full, st->tw, ctr ? ctr + 16 : nullptr, s));
   LAUNCH(st, s, PF_XI, sb + fb, launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s));
@@ -829,6 +839,29 @@ ec_status compute_self_terms(ec_state* st, hipStream_t s) {
          launch_self_terms(b.tab, st->ndef, b.cnt, b.ids, st->n, w->K, st->gcls, D, st->work, (int64_t)st->work_cap,
                            st->wcnt, st->wbeg, st->partial, st->h3c, st->B, s));
   st->B_valid = true;
+  return EC_OK;
+}
+
+// Make stream s wait for self terms still running on the side stream.
+ec_status join_self(ec_state* st, hipStream_t s) {
+  if (!st->self_pending) return EC_OK;
+  HIPCHK(hipStreamWaitEvent(s, st->ev_self, 0));
+  st->self_pending = false;
+  return EC_OK;
+}
+
+// Self terms of the list just rasterised on stream s, computed on the side
+// stream after ev_fill while s runs the Fourier passes.
+ec_status self_terms_beside(ec_state* st) {
+  if (!st->side) {
+    HIPCHK(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&st->ev_self, hipEventDisableTiming));
+  }
+  HIPCHK(hipStreamWaitEvent(st->side, st->ev_fill, 0));
+  ec_status r = compute_self_terms(st, st->side);
+  if (r != EC_OK) return r;
+  HIPCHK(hipEventRecord(st->ev_self, st->side));
+  st->self_pending = true;
   return EC_OK;
 }
 
@@ -1106,29 +1139,6 @@ ec_status ec_state_bytes(const ec_state* st, size_t* bytes) {
   return EC_OK;
 }
 
-// Make stream s wait for self terms still running on the side stream.
-ec_status join_self(ec_state* st, hipStream_t s) {
-  if (!st->self_pending) return EC_OK;
-  HIPCHK(hipStreamWaitEvent(s, st->ev_self, 0));
-  st->self_pending = false;
-  return EC_OK;
-}
-
-// Self terms of the list just rasterised on stream s, computed on the side
-// stream after ev_fill while s runs the Fourier passes.
-ec_status self_terms_beside(ec_state* st) {
-  if (!st->side) {
-    HIPCHK(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&st->ev_self, hipEventDisableTiming));
-  }
-  HIPCHK(hipStreamWaitEvent(st->side, st->ev_fill, 0));
-  ec_status r = compute_self_terms(st, st->side);
-  if (r != EC_OK) return r;
-  HIPCHK(hipEventRecord(st->ev_self, st->side));
-  st->self_pending = true;
-  return EC_OK;
-}
-
 ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, void* stream, void* eps_out,
                           void* sig_out, int32_t on_device) {
   if (!st) return fail(EC_ERR_ARG, "state is NULL");
@@ -1193,15 +1203,23 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   LAUNCH(st, s, PF_OTHER, 0,
          launch_mean_stress(nb.tab, nb.cnt, ndef, st->n3, st->C, st->prob.bc, st->add6, s));
   // 4. Fourier solve
-  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6, st->tilectr);
-  // host copies of the list while the device works (the staging buffer is
-  // only read by the pending upload)
-  st->hdefs.assign(h, h + ndef);
-  st->hcap.resize(ndef);
-  for (int i = 0; i < ndef; ++i) st->hcap[i] = box_volume(h[i]);
+  // The self terms run on the side stream beside the forward x and y passes
+  // (after the rasterisation), and the z pass waits for them: its workgroups
+  // each take most of a CU's LDS, so self-term blocks still resident would
+  // hold some of them back and stretch the pass.
+  auto beside = [&]() -> ec_status {
+    // host copies of the list while the device works (the staging buffer is
+    // only read by the pending upload); the self-term set-up reads them
+    st->hdefs.assign(h, h + ndef);
+    st->hcap.resize(ndef);
+    for (int i = 0; i < ndef; ++i) st->hcap[i] = box_volume(h[i]);
+    if (ndef == 0) return EC_OK;
+    ec_status q = self_terms_beside(st);
+    return q == EC_OK ? join_self(st, s) : q;
+  };
+  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6, st->tilectr, beside);
   if (r != EC_OK) return r;
   st->solved = true;
-  if (ndef > 0 && (r = self_terms_beside(st)) != EC_OK) return r;
   if (eps_out && (r = write_field(st, 1, eps_out, on_device != 0, s)) != EC_OK) return r;
   if (sig_out && (r = write_field(st, 0, sig_out, on_device != 0, s)) != EC_OK) return r;
   return EC_OK;
@@ -1452,6 +1470,8 @@ ec_status ec_profile_read(ec_state* st, int64_t* launches, double* ms, double* b
 
 // ---------------------------------------------------------------- debug passes
 
+}  // extern "C"
+
 namespace {
 
 // Host arrays are [6][n][n][n/2+1] complex (re, im); the device spectrum is
@@ -1510,6 +1530,8 @@ struct Tmp {
 };
 
 }  // namespace
+
+extern "C" {
 
 ec_status ec_debug_forward(ec_state* st, const double* field, double* out) {
   if (!st || !field || !out) return fail(EC_ERR_ARG, "NULL argument");

@@ -18,25 +18,33 @@ constexpr int RT = 256;  // threads per rasteriser workgroup
 // Exclusive scan of counts into offsets[0..ndef] (offsets[ndef] = total); one workgroup.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t* __restrict__ counts, int ndef,
                                                int64_t* __restrict__ offsets) {
-  __shared__ int64_t part[1024];
-  const int T = 1024;
+  constexpr int T = 1024;
+  __shared__ int64_t part[2 * (T / 64)];
   const int per = (ndef + T - 1) / T;
   const int b = threadIdx.x * per, e = min(ndef, b + per);
   int64_t s = 0;
   for (int i = b; i < e; ++i) s += counts[i];
-  part[threadIdx.x] = s;
+  // exclusive scan of the per-thread sums: within each wavefront by lane
+  // shuffles, then over the sixteen wavefront totals
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) part[wv] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t acc = 0;
-    for (int t = 0; t < T; ++t) {
-      const int64_t v = part[t];
-      part[t] = acc;
-      acc += v;
+  if (wv == 0) {
+    int64_t w = lane < T / 64 ? part[lane] : 0;
+    for (int o = 1; o < T / 64; o <<= 1) {
+      const int64_t y = __shfl_up(w, o);
+      if (lane >= o) w += y;
     }
-    offsets[ndef] = acc;
+    if (lane < T / 64) part[T / 64 + lane] = w;  // inclusive wavefront totals
   }
   __syncthreads();
-  int64_t acc = part[threadIdx.x];
+  int64_t acc = x - s + (wv > 0 ? part[T / 64 + wv - 1] : 0);
+  if (threadIdx.x == T - 1) offsets[ndef] = part[T / 64 + T / 64 - 1];
   for (int i = b; i < e; ++i) {
     offsets[i] = acc;
     acc += counts[i];
