@@ -237,8 +237,6 @@ struct ec_state {
   size_t work_cap = 0;
   double* partial = nullptr;
   size_t partial_cap = 0;
-  int32_t* wcnt = nullptr;
-  size_t wcnt_cap = 0;
   int64_t* wbeg = nullptr;
   size_t wbeg_cap = 0;
   // update scratch
@@ -832,12 +830,11 @@ ec_status compute_self_terms(ec_state* st, hipStream_t s) {
   cap = std::max<int64_t>(cap, 1);
   if ((r = st_grow(st, &st->work, &st->work_cap, (size_t)cap)) != EC_OK) return r;
   if ((r = st_grow(st, &st->partial, &st->partial_cap, (size_t)cap)) != EC_OK) return r;
-  if ((r = st_grow(st, &st->wcnt, &st->wcnt_cap, (size_t)st->ndef + 1)) != EC_OK) return r;
   if ((r = st_grow(st, &st->wbeg, &st->wbeg_cap, (size_t)st->ndef + 1)) != EC_OK) return r;
   const DefBuf& b = st->db[st->cur];
   LAUNCH(st, s, PF_SELF, 0,
          launch_self_terms(b.tab, st->ndef, b.cnt, b.ids, st->n, w->K, st->gcls, D, st->work, (int64_t)st->work_cap,
-                           st->wcnt, st->wbeg, st->partial, st->h3c, st->B, s));
+                           st->wbeg, st->partial, st->h3c, st->B, s));
   st->B_valid = true;
   return EC_OK;
 }
@@ -1115,7 +1112,6 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->upd_ids, st->upd_cap * 4);
   ledger_free(c, st->work, st->work_cap * sizeof(SelfWork));
   ledger_free(c, st->partial, st->partial_cap * 8);
-  ledger_free(c, st->wcnt, st->wcnt_cap * 4);
   ledger_free(c, st->wbeg, st->wbeg_cap * 8);
   pin_free(st->pin_tab);
   pin_free(st->pin_upd);

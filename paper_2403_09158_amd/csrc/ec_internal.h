@@ -269,11 +269,11 @@ hipError_t launch_class_windows(const double* K, int D, const double* dirs, int 
 struct SelfWork {
   int32_t def, p0, p1, pad;
 };
-// Builds the work list on the device (scratch: wcnt[ndef], wbeg[ndef + 1]) and
-// runs it on a fixed grid; no host synchronisation.
+// Builds the work list on the device in one workgroup (scratch: wbeg[ndef + 1])
+// and runs it on a fixed grid; no host synchronisation.
 hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int n,
                              const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
-                             int32_t* wcnt, int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s);
+                             int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s);
 // Eigenstrain direction class of a defect (index into the class windows, -1
 // for the generic path) and its scale s (E = s e).
 struct ClassTag {

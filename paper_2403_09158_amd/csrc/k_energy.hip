@@ -148,33 +148,63 @@ constexpr double SELF_TARGET = 32768.0;  // pairs per work item
 constexpr int SELF_KMAX = 64;            // work items per defect at most
 
 // Work items per defect: ceil(m (m + 1) / 2 / target), between 1 and SELF_KMAX.
-__global__ void k_self_count(const int32_t* __restrict__ cnt, int ndef, int32_t* __restrict__ wcnt) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ndef) return;
-  const double m = cnt[i];
-  const int k = (int)ceil(m * (m + 1.0) * 0.5 / SELF_TARGET);
-  wcnt[i] = k < 1 ? 1 : (k > SELF_KMAX ? SELF_KMAX : k);
+__device__ __forceinline__ int self_items_of(int m) {
+  const double md = m;
+  const int k = (int)ceil(md * (md + 1.0) * 0.5 / SELF_TARGET);
+  return k < 1 ? 1 : (k > SELF_KMAX ? SELF_KMAX : k);
 }
 
-// Rows [p0, p1) with about equal pair counts: rows [0, p) hold p m - p (p - 1)/2 pairs.
-__global__ void k_self_items(const int32_t* __restrict__ cnt, int ndef, const int64_t* __restrict__ wbeg,
-                             SelfWork* __restrict__ work, int64_t cap) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ndef) return;
-  const int m = cnt[i];
-  const double tot = (double)m * (m + 1.0) * 0.5, a = m + 0.5;
-  const int64_t b = wbeg[i];
-  const int k = (int)(wbeg[i + 1] - b);
-  int p0 = 0;
-  for (int j = 1; j <= k; ++j) {
-    int p1 = m;
-    if (j < k) {
-      const double T = j * tot / k;
-      p1 = (int)ceil(a - sqrt(fmax(0.0, a * a - 2.0 * T)));
-      p1 = p1 < p0 ? p0 : (p1 > m ? m : p1);
+constexpr int PT = 1024;  // threads of the planning workgroup
+
+// The work list in one workgroup: item counts per defect, their exclusive
+// scan into wbeg[0..ndef] (wbeg[ndef] = list length), and the items, rows
+// [p0, p1) of a defect's pair triangle with about equal pair counts (rows
+// [0, p) hold p m - p (p - 1) / 2 pairs).  Each thread takes a contiguous run
+// of defects.
+__global__ __launch_bounds__(PT) void k_self_plan(const int32_t* __restrict__ cnt, int ndef,
+                                                  int64_t* __restrict__ wbeg, SelfWork* __restrict__ work,
+                                                  int64_t cap) {
+  __shared__ int64_t part[2 * (PT / 64)];
+  const int per = (ndef + PT - 1) / PT;
+  const int b = threadIdx.x * per, e = min(ndef, b + per);
+  int64_t s = 0;
+  for (int i = b; i < e; ++i) s += self_items_of(cnt[i]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) part[wv] = x;
+  __syncthreads();
+  if (wv == 0) {
+    int64_t w = lane < PT / 64 ? part[lane] : 0;
+    for (int o = 1; o < PT / 64; o <<= 1) {
+      const int64_t y = __shfl_up(w, o);
+      if (lane >= o) w += y;
     }
-    if (b + j - 1 < cap) work[b + j - 1] = SelfWork{i, p0, p1, 0};
-    p0 = p1;
+    if (lane < PT / 64) part[PT / 64 + lane] = w;
+  }
+  __syncthreads();
+  int64_t at = x - s + (wv > 0 ? part[PT / 64 + wv - 1] : 0);
+  if (threadIdx.x == PT - 1) wbeg[ndef] = part[2 * (PT / 64) - 1];
+  for (int i = b; i < e; ++i) {
+    const int m = cnt[i];
+    const int k = self_items_of(m);
+    const double tot = (double)m * (m + 1.0) * 0.5, a = m + 0.5;
+    wbeg[i] = at;
+    int p0 = 0;
+    for (int j = 1; j <= k; ++j) {
+      int p1 = m;
+      if (j < k) {
+        const double T = j * tot / k;
+        p1 = (int)ceil(a - sqrt(fmax(0.0, a * a - 2.0 * T)));
+        p1 = p1 < p0 ? p0 : (p1 > m ? m : p1);
+      }
+      if (at + j - 1 < cap) work[at + j - 1] = SelfWork{i, p0, p1, 0};
+      p0 = p1;
+    }
+    at += k;
   }
 }
 
@@ -397,13 +427,10 @@ hipError_t launch_class_windows(const double* K, int D, const double* dirs, int 
 
 hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int n,
                              const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
-                             int32_t* wcnt, int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s) {
+                             int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s) {
   if (ndef == 0) return hipSuccess;
   const int g1 = (ndef + 255) / 256;
-  hipLaunchKernelGGL(k_self_count, dim3(g1), dim3(256), 0, s, counts, ndef, wcnt);
-  hipError_t e = launch_scan(wcnt, ndef, wbeg, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_self_items, dim3(g1), dim3(256), 0, s, counts, ndef, wbeg, work, work_cap);
+  hipLaunchKernelGGL(k_self_plan, dim3(1), dim3(PT), 0, s, counts, ndef, wbeg, work, work_cap);
   const int grid = (int)std::min<int64_t>(work_cap, 4096);
   hipLaunchKernelGGL(k_self, dim3(grid), dim3(ST), 0, s, d, counts, ids, n, K, gcls, D, work, wbeg + ndef, work_cap,
                      partial);
