@@ -271,21 +271,43 @@ __global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs,
       // chunk reaches from neighbouring rows overlap, so they are served
       // from the L1 cache (rows walked whole would cycle through the entire
       // footprint image per row)
+      // one row against the chunk [qc, qe), columns q >= q0; q past the
+      // chunk reads the chunk's last voxel entry (a valid address) and
+      // contributes zero, so the four loads go together
+      auto row = [&](int pr, int q0, int qe) {
+        const double* gp = g + (pk[pr] + C0);
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int qq = q0 + lane + 64 * k;
+          const double x = gp[-pk[qq < qe ? qq : qe - 1]];
+          v[k] = qq < qe ? x : 0.0;
+        }
+        acc += 2.0 * ((v[0] + v[1]) + (v[2] + v[3]));
+      };
       for (int qc = wk.p0 + 1; qc < m; qc += 256) {
         const int qe = qc + 256 < m ? qc + 256 : m;
-        for (int p = wk.p0 + wave; p < wk.p1 && p + 1 < qe; p += ST / 64) {
-          const double* gp = g + (pk[p] + C0);
-          const int q = (p + 1 > qc ? p + 1 : qc) + lane;
-          // q past the chunk reads the chunk's last voxel entry (a valid
-          // address) and contributes zero, so the four loads go together
-          double v[4];
+        // rows in pairs (p, p + 1); when p + 1 is p's x-neighbour its window
+        // entry for any q is the next one in memory, so one 16-byte load
+        // serves both rows (the pair q = p + 1 counts for row p only)
+        for (int p = wk.p0 + 2 * wave; p < wk.p1 && p + 1 < qe; p += 2 * (ST / 64)) {
+          const int P = pk[p];
+          const int q0 = p + 1 > qc ? p + 1 : qc;
+          if (p + 1 < wk.p1 && pk[p + 1] == P + 1) {
+            const double* gp = g + (P + C0);
+            double v[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            const int qq = q + 64 * k;
-            const double x = gp[-pk[qq < qe ? qq : qe - 1]];
-            v[k] = qq < qe ? x : 0.0;
+            for (int k = 0; k < 4; ++k) {
+              const int qq = q0 + lane + 64 * k;
+              double2 w;
+              __builtin_memcpy(&w, gp - pk[qq < qe ? qq : qe - 1], sizeof w);
+              v[k] = qq < qe ? w.x + (qq > p + 1 ? w.y : 0.0) : 0.0;
+            }
+            acc += 2.0 * ((v[0] + v[1]) + (v[2] + v[3]));
+          } else {
+            row(p, q0, qe);
+            if (p + 1 < wk.p1 && p + 2 < qe) row(p + 1, p + 2 > qc ? p + 2 : qc, qe);
           }
-          acc += 2.0 * ((v[0] + v[1]) + (v[2] + v[3]));
         }
       }
     } else if (cls >= 0) {
