@@ -18,10 +18,13 @@ elastic interactions in OkMC" (arXiv 2403.09158):
                  Sec. 3.4, then sigma = C:(eps - eps*) (Sec. 3.2).
 * ``energy``   - interaction energies from the Betti-reciprocity form (Sec. 2),
                  both brute-force pairwise and the fast exact form.
+* ``jumps``    - energy changes of candidate whole-voxel jumps, the biased jump
+                 frequencies and the frequency-line selection (Sec. 4 and the
+                 OkMC loop of App. A).
 
 Everything is float64 / complex128 and uses full 3x3 and 3x3x3x3 tensors (no
-Voigt shortcuts).  Readings of garbled or silent passages follow the design doc's
-list of readings and are repeated in each function's docstring.
+Voigt shortcuts).  Readings of garbled or silent passages are stated in each
+function's docstring.
 
 Parity status: every function here is pinned by a ``-m "not gpu"`` test
 against a closed form, an invariant, a brute-force evaluation or a textbook
