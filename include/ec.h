@@ -159,6 +159,34 @@ EC_API ec_status ec_interaction_energies(ec_state* st, void* hip_stream, double*
 EC_API ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, void* hip_stream, double* E_out,
                            int32_t out_on_device);
 
+/* ---- jump probes (the OkMC loop of App. A; biased jumps of Sec. 4) ---------- */
+
+/* For every defect i and each of its njump (1..64) candidate whole-voxel jumps
+ * jumps[(i*njump + j)*3 + {0,1,2}] (x, y, z offsets in voxels, |component| <= 8
+ * and below half the cell; host array), the change of the defect's
+ * interaction energy with all the other defects if it alone were translated
+ * by that jump (eV):
+ *   dE_ij = E_i(X_i + lambda_ij) - E_i(X_i),
+ * from the resident stress and the defect's own field (a window of the
+ * periodic kernel, grown to cover the jumps); nothing is moved.
+ * dE_out: ndef*njump doubles, host or device (out_on_device), or NULL; the
+ * values stay with the state for ec_jump_select until the next solve or
+ * update.  Refreshes the energies as ec_interaction_energies does. */
+EC_API ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t njump, void* hip_stream,
+                                  double* dE_out, int32_t out_on_device);
+
+/* Biased jump frequencies of the last ec_jump_energies call,
+ *   nu_ij = 1/2 nu0 exp(-(Em_i + dE_ij / 2) / kT)   (barrier raised by half
+ * the energy change), and for each defect the jump on its frequency line
+ * R_k = sum_{j <= k} nu_ij whose interval holds xi_i in (0, 1]: the first j
+ * with xi_i <= R_j / R_tot.  Em, xi: ndef doubles (host; eV and the random
+ * numbers drawn by the caller); nu0 in 1/s, kT in eV.  nu_out (ndef*njump
+ * doubles) and choice_out (ndef int32) host or device (out_on_device), either
+ * may be NULL (xi may be NULL when choice_out is).  EC_ERR_STATE when the
+ * defect list changed since the jump energies were computed. */
+EC_API ec_status ec_jump_select(ec_state* st, const double* Em, double nu0, double kT, const double* xi,
+                                void* hip_stream, double* nu_out, int32_t* choice_out, int32_t out_on_device);
+
 /* ---- inspection (tests, benchmarks) ---------------------------------------- */
 
 /* Footprints of the current defect list: counts[ndef] and, if ids != NULL, the

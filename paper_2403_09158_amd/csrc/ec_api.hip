@@ -244,9 +244,23 @@ struct ec_state {
   int64_t upd_cap = 0;
   double* updE = nullptr;     // 6 doubles
   uint32_t* tilectr = nullptr;  // NTILECTR tile counters of the persistent passes
+  // jump probes: energy changes of the last ec_jump_energies call (jn per
+  // defect) and their scratch
+  int jn = 0;
+  bool jdE_ok = false;
+  int32_t* jjumps = nullptr;
+  size_t jjumps_cap = 0;
+  double *jdE = nullptr, *jt1 = nullptr, *jpartial = nullptr, *jsel = nullptr, *jnu = nullptr;
+  size_t jdE_cap = 0, jt1_cap = 0, jpartial_cap = 0, jsel_cap = 0, jnu_cap = 0;
+  SelfWork* jwork = nullptr;
+  size_t jwork_cap = 0;
+  int64_t* jwbeg = nullptr;
+  size_t jwbeg_cap = 0;
+  int32_t* jchoice = nullptr;
+  size_t jchoice_cap = 0;
   int64_t* updfix = nullptr;  // 6 int64
   // pinned staging: defect table, per-update records, moved footprint
-  Pinned pin_tab, pin_upd, pin_ids, pin_tags;
+  Pinned pin_tab, pin_upd, pin_ids, pin_tags, pin_jump;
   // profiling
   bool prof = false;
   std::vector<ProfRec> recs;
@@ -732,7 +746,9 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
   for (auto it = c->wins.begin(); it != c->wins.end(); ++it)
     if (it->n == st->n && it->C11 == st->C.C11 && it->C12 == st->C.C12 && it->C44 == st->C.C44 &&
         it->bc == st->prob.bc) {
-      // states still pointing at the old window refresh through ensure_window
+      // states still pointing at the old window refresh through ensure_window;
+      // no kernel of any stream may still read it
+      (void)hipDeviceSynchronize();
       raw_free(c, it->K);
       c->used -= std::min(c->used, it->bytes);
       c->wins.erase(it);
@@ -787,11 +803,11 @@ ec_status ensure_classes(ec_state* st, hipStream_t s) {
   return EC_OK;
 }
 
-ec_status compute_self_terms(ec_state* st, hipStream_t s) {
-  ec_status r = ensure_classes(st, s);
-  if (r != EC_OK) return r;
-  const int need = window_need(st);
-  r = ensure_window(st, need, s);
+// Kernel window covering every footprint's pair offsets plus `reach` voxels
+// (the largest jump of a jump probe; 0 for the self terms), and the class
+// windows on it.  Classes must be current.
+ec_status ensure_windows(ec_state* st, int reach, hipStream_t s) {
+  ec_status r = ensure_window(st, window_need(st) + reach, s);
   if (r != EC_OK) return r;
   const WinCache* w = st->win;
   const int D = w->D;
@@ -803,6 +819,7 @@ ec_status compute_self_terms(ec_state* st, hipStream_t s) {
     if (need_b > st->gcls_bytes) {
       void* q = nullptr;
       if ((r = ledger_alloc(st->ctx, need_b, &q)) != EC_OK) return r;
+      if (st->gcls) HIPCHK(hipDeviceSynchronize());  // self-term kernels may still read the old windows
       ledger_free(st->ctx, st->gcls, st->gcls_bytes);
       st->held += need_b;
       st->held -= std::min(st->held, st->gcls_bytes);
@@ -818,14 +835,21 @@ ec_status compute_self_terms(ec_state* st, hipStream_t s) {
     st->gcls_D = D;
     st->gcls_ncls = ncls;
   }
+  return EC_OK;
+}
+
+ec_status compute_self_terms(ec_state* st, hipStream_t s) {
+  ec_status r = ensure_classes(st, s);
+  if (r != EC_OK) return r;
+  if ((r = ensure_windows(st, 0, s)) != EC_OK) return r;
+  const WinCache* w = st->win;
+  const int D = w->D;
   // Work-list capacity: at most 64 items per defect, fewer for small boxes.
   int64_t cap = 0;
-  double pairs_bound = 0;
   for (const auto& d : st->hdefs) {
     const double m = (double)box_volume(d);
     const double k = std::ceil(m * (m + 1) / 2 / 32768.0);
     cap += (int64_t)std::min(64.0, std::max(1.0, k));
-    pairs_bound += m;
   }
   cap = std::max<int64_t>(cap, 1);
   if ((r = st_grow(st, &st->work, &st->work_cap, (size_t)cap)) != EC_OK) return r;
@@ -1113,6 +1137,16 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->work, st->work_cap * sizeof(SelfWork));
   ledger_free(c, st->partial, st->partial_cap * 8);
   ledger_free(c, st->wbeg, st->wbeg_cap * 8);
+  ledger_free(c, st->jjumps, st->jjumps_cap * 4);
+  ledger_free(c, st->jdE, st->jdE_cap * 8);
+  ledger_free(c, st->jt1, st->jt1_cap * 8);
+  ledger_free(c, st->jpartial, st->jpartial_cap * 8);
+  ledger_free(c, st->jsel, st->jsel_cap * 8);
+  ledger_free(c, st->jnu, st->jnu_cap * 8);
+  ledger_free(c, st->jwork, st->jwork_cap * sizeof(SelfWork));
+  ledger_free(c, st->jwbeg, st->jwbeg_cap * 8);
+  ledger_free(c, st->jchoice, st->jchoice_cap * 4);
+  pin_free(st->pin_jump);
   pin_free(st->pin_tab);
   pin_free(st->pin_upd);
   pin_free(st->pin_ids);
@@ -1196,6 +1230,7 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   st->ids_used = total;
   st->B_valid = false;
   st->classes_ok = false;
+  st->jdE_ok = false;
   LAUNCH(st, s, PF_OTHER, 0,
          launch_mean_stress(nb.tab, nb.cnt, ndef, st->n3, st->C, st->prob.bc, st->add6, s));
   // 4. Fourier solve
@@ -1249,6 +1284,7 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
     if (rc == EC_OK) rc = ensure_classes(st, s);
     if (rc != EC_OK) return rc;
   }
+  st->jdE_ok = false;
   const DevDefect od = st->hdefs[idx];
   const int n = st->n;
   // whole-voxel move of the same shape: the footprint translates and B_i is unchanged
@@ -1461,6 +1497,103 @@ ec_status ec_profile_read(ec_state* st, int64_t* launches, double* ms, double* b
     if (ms) ms[f] = tms[f];
     if (bytes) bytes[f] = cnt[f] ? tb[f] / cnt[f] : 0.0;
   }
+  return EC_OK;
+}
+
+// ---------------------------------------------------------------- jump probes
+
+constexpr int JUMP_MAX = 8;  // largest jump component, in voxels
+
+ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t njump, void* stream, double* dE_out,
+                           int32_t on_device) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
+  if (njump < 1 || njump > 64) return fail(EC_ERR_ARG, "njump %d outside [1, 64]", njump);
+  const int nd = st->ndef;
+  const size_t nu = (size_t)nd * njump;
+  if (nd > 0 && !jumps) return fail(EC_ERR_ARG, "jumps is NULL");
+  int reach = 0;
+  for (size_t k = 0; k < 3 * nu; ++k) {
+    const int v = std::abs(jumps[k]);
+    if (v > JUMP_MAX || 2 * v >= st->n)
+      return fail(EC_ERR_ARG, "jump %zu of defect %zu: component %d beyond %d voxels or half the cell", (k / 3) % njump,
+                  k / 3 / njump, jumps[k], JUMP_MAX);
+    reach = std::max(reach, v);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  st->jdE_ok = false;
+  if (nd == 0) {
+    st->jn = njump;
+    st->jdE_ok = true;
+    return EC_OK;
+  }
+  ec_status r;
+  if ((r = join_self(st, s)) != EC_OK) return r;
+  if ((r = ensure_classes(st, s)) != EC_OK) return r;
+  if ((r = ensure_windows(st, reach, s)) != EC_OK) return r;
+  if (!st->B_valid && (r = compute_self_terms(st, s)) != EC_OK) return r;
+  // work items: per (defect, jump) all ordered pairs of the footprint
+  int64_t cap = 0;
+  for (const auto& d : st->hdefs) {
+    const double m = (double)box_volume(d);
+    cap += (int64_t)njump * (int64_t)std::min(64.0, std::max(1.0, std::ceil(m * m / 32768.0)));
+  }
+  if ((r = st_grow(st, &st->jjumps, &st->jjumps_cap, 3 * nu)) != EC_OK ||
+      (r = st_grow(st, &st->jdE, &st->jdE_cap, nu)) != EC_OK || (r = st_grow(st, &st->jt1, &st->jt1_cap, nu)) != EC_OK ||
+      (r = st_grow(st, &st->jwbeg, &st->jwbeg_cap, nu + 1)) != EC_OK ||
+      (r = st_grow(st, &st->jwork, &st->jwork_cap, (size_t)cap)) != EC_OK ||
+      (r = st_grow(st, &st->jpartial, &st->jpartial_cap, (size_t)cap)) != EC_OK)
+    return r;
+  char* hp = nullptr;
+  if ((r = pin_begin(st->pin_jump, 3 * nu * 4, &hp)) != EC_OK) return r;
+  std::memcpy(hp, jumps, 3 * nu * 4);
+  HIPCHK(hipMemcpyAsync(st->jjumps, hp, 3 * nu * 4, hipMemcpyHostToDevice, s));
+  if ((r = pin_end(st->pin_jump, s)) != EC_OK) return r;
+  const DefBuf& b = st->db[st->cur];
+  // S(0): the footprint sums of the energies reduction (which also refreshes E)
+  LAUNCH(st, s, PF_REDUCE, 0,
+         launch_reduce(b.tab, nd, b.cnt, b.ids, st->sig, st->B, st->h3c, st->S6, st->E, s));
+  LAUNCH(st, s, PF_SELF, 0,
+         launch_jump_energies(b.tab, nd, b.cnt, b.ids, st->sig, st->n, st->jjumps, njump, st->S6, st->win->K,
+                              st->gcls, st->win->D, st->jwork, (int64_t)st->jwork_cap, st->jwbeg, st->jpartial,
+                              st->jt1, st->B, st->h3c, st->jdE, s));
+  st->jn = njump;
+  st->jdE_ok = true;
+  if (dE_out) return copy_out(dE_out, st->jdE, nu * 8, on_device != 0, s);
+  return EC_OK;
+}
+
+ec_status ec_jump_select(ec_state* st, const double* Em, double nu0, double kT, const double* xi, void* stream,
+                         double* nu_out, int32_t* choice_out, int32_t on_device) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  if (!st->jdE_ok) return fail(EC_ERR_STATE, "no jump energies for the current defect list");
+  if (!(nu0 > 0.0) || !std::isfinite(nu0) || !(kT > 0.0) || !std::isfinite(kT))
+    return fail(EC_ERR_ARG, "nu0 and kT must be positive and finite");
+  const int nd = st->ndef, nj = st->jn;
+  if (nd == 0) return EC_OK;
+  if (!Em) return fail(EC_ERR_ARG, "Em is NULL");
+  if (choice_out && !xi) return fail(EC_ERR_ARG, "xi is NULL");
+  for (int i = 0; i < nd; ++i) {
+    if (!std::isfinite(Em[i])) return fail(EC_ERR_ARG, "Em of defect %d not finite", i);
+    if (xi && !(xi[i] > 0.0 && xi[i] <= 1.0)) return fail(EC_ERR_ARG, "xi of defect %d outside (0, 1]", i);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  ec_status r;
+  const size_t nu = (size_t)nd * nj;
+  if ((r = st_grow(st, &st->jsel, &st->jsel_cap, 2 * (size_t)nd)) != EC_OK) return r;
+  if (nu_out && (r = st_grow(st, &st->jnu, &st->jnu_cap, nu)) != EC_OK) return r;
+  if (choice_out && (r = st_grow(st, &st->jchoice, &st->jchoice_cap, (size_t)nd)) != EC_OK) return r;
+  char* hp = nullptr;
+  if ((r = pin_begin(st->pin_jump, 2 * (size_t)nd * 8, &hp)) != EC_OK) return r;
+  std::memcpy(hp, Em, (size_t)nd * 8);
+  if (xi) std::memcpy(hp + (size_t)nd * 8, xi, (size_t)nd * 8);
+  HIPCHK(hipMemcpyAsync(st->jsel, hp, 2 * (size_t)nd * 8, hipMemcpyHostToDevice, s));
+  if ((r = pin_end(st->pin_jump, s)) != EC_OK) return r;
+  LAUNCH(st, s, PF_OTHER, 0,
+         launch_jump_select(st->jdE, nd, nj, st->jsel, nu0, kT, xi ? st->jsel + nd : nullptr,
+                            nu_out ? st->jnu : nullptr, choice_out ? st->jchoice : nullptr, s));
+  if (nu_out && (r = copy_out(nu_out, st->jnu, nu * 8, on_device != 0, s)) != EC_OK) return r;
+  if (choice_out) return copy_out(choice_out, st->jchoice, (size_t)nd * 4, on_device != 0, s);
   return EC_OK;
 }
 

@@ -274,6 +274,17 @@ struct SelfWork {
 hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int n,
                              const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
                              int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s);
+// Jump probes: dE[i nj + j] for jump jumps[3 (i nj + j) ..] of defect i (see
+// k_energy.hip); S0 = the footprint sums of the last reduction, B the self
+// terms; scratch as for the self terms, t1[ndef nj], wbeg[ndef nj + 1].
+hipError_t launch_jump_energies(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids,
+                                const double* sig, int n, const int32_t* jumps, int nj, const double* S0,
+                                const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
+                                int64_t* wbeg, double* partial, double* t1, const double* B, double h3c, double* dE,
+                                hipStream_t s);
+// Biased jump frequencies and the frequency-line choice (nu, choice may be null).
+hipError_t launch_jump_select(const double* dE, int ndef, int nj, const double* Em, double nu0, double kT,
+                              const double* xi, double* nu, int32_t* choice, hipStream_t s);
 // Eigenstrain direction class of a defect (index into the class windows, -1
 // for the generic path) and its scale s (E = s e).
 struct ClassTag {

@@ -370,6 +370,258 @@ __global__ void k_self_finish(const int64_t* __restrict__ wbeg, const double* __
   B[i] = -h3c * scale * (s + c);
 }
 
+// ---- jump probes (the OkMC loop of App. A, biased jumps of Sec. 4) -----------
+//
+// Defect i translated by a whole-voxel jump lambda, everything else fixed:
+//   E_i(X + lambda) = -h^3 c E_i : sum_{x in Omega_i + lambda} (sigma - sigma_i)(x),
+//   sigma_i(x) = sum_{y in Omega_i} G(x - y) : E_i,
+// so with S(lambda) the sum of the resident stress over the translated
+// footprint and X(lambda) = sum over x in Omega_i + lambda, y in Omega_i of
+// E_i:G(x - y):E_i (all ordered pairs; X(0) gives the self term, B_i = -h^3 c X(0)),
+//   dE = -h^3 c E_i:(S(lambda) - S(0)) + h^3 c X(lambda) + B_i.
+
+__device__ __forceinline__ int wrap_axis(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// One workgroup per (defect, jump): S(lambda) with the footprint ids shifted,
+// t1 = -h^3 c E:(S(lambda) - S(0)); S(0) from the energies reduction.
+__global__ __launch_bounds__(RDT) void k_jump_sums(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
+                                                   const int32_t* __restrict__ ids, const double* __restrict__ sig,
+                                                   int n, const int32_t* __restrict__ jumps, int nj,
+                                                   const double* __restrict__ S0, double h3c, double* __restrict__ t1) {
+  const int i = blockIdx.x / nj;
+  const int u = blockIdx.x;
+  const int lx = jumps[3 * u], ly = jumps[3 * u + 1], lz = jumps[3 * u + 2];
+  const int64_t o = defs[i].slot;
+  const int m = cnt[i];
+  double s[6], c[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) s[a] = c[a] = 0.0;
+  for (int k = threadIdx.x; k < m; k += RDT) {
+    const int id = ids[o + k];
+    const int x = wrap_axis(id % n + lx, n), y = wrap_axis((id / n) % n + ly, n), z = wrap_axis(id / (n * n) + lz, n);
+    double v[6];
+    ld_voxel(sig, ((int64_t)z * n + y) * n + x, v);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) neumaier(s[a], c[a], v[a]);
+  }
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      const double s2 = __shfl_down(s[a], off), c2 = __shfl_down(c[a], off);
+      neumaier_merge(s[a], c[a], s2, c2);
+    }
+  __shared__ double ws[RDT / 64][6], wc[RDT / 64][6];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      ws[wave][a] = s[a];
+      wc[wave][a] = c[a];
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const DevDefect d = defs[i];
+    double dot = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      double ss = ws[0][a], cc = wc[0][a];
+      for (int w = 1; w < RDT / 64; ++w) neumaier_merge(ss, cc, ws[w][a], wc[w][a]);
+      dot += ddot_w(a) * d.E[a] * ((ss + cc) - S0[6 * i + a]);
+    }
+    t1[u] = -h3c * dot;
+  }
+}
+
+// Work items of the cross sums: per (defect, jump) ceil(m^2 / target) items
+// (at most SELF_KMAX), each a range of rows p with all m columns q.
+__device__ __forceinline__ int cross_items_of(int m) {
+  const double md = m;
+  const int k = (int)ceil(md * md / SELF_TARGET);
+  return k < 1 ? 1 : (k > SELF_KMAX ? SELF_KMAX : k);
+}
+
+__global__ __launch_bounds__(PT) void k_cross_plan(const int32_t* __restrict__ cnt, int ndef, int nj,
+                                                   int64_t* __restrict__ wbeg, SelfWork* __restrict__ work,
+                                                   int64_t cap) {
+  __shared__ int64_t part[2 * (PT / 64)];
+  const int nu = ndef * nj;
+  const int per = (nu + PT - 1) / PT;
+  const int b = threadIdx.x * per, e = min(nu, b + per);
+  int64_t s = 0;
+  for (int u = b; u < e; ++u) s += cross_items_of(cnt[u / nj]);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int64_t x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) part[wv] = x;
+  __syncthreads();
+  if (wv == 0) {
+    int64_t w = lane < PT / 64 ? part[lane] : 0;
+    for (int o = 1; o < PT / 64; o <<= 1) {
+      const int64_t y = __shfl_up(w, o);
+      if (lane >= o) w += y;
+    }
+    if (lane < PT / 64) part[PT / 64 + lane] = w;
+  }
+  __syncthreads();
+  int64_t at = x - s + (wv > 0 ? part[PT / 64 + wv - 1] : 0);
+  if (threadIdx.x == PT - 1) wbeg[nu] = part[2 * (PT / 64) - 1];
+  for (int u = b; u < e; ++u) {
+    const int m = cnt[u / nj];
+    const int k = cross_items_of(m);
+    wbeg[u] = at;
+    for (int j = 0; j < k; ++j) {
+      const int p0 = (int)((int64_t)m * j / k), p1 = (int)((int64_t)m * (j + 1) / k);
+      if (at + j < cap) work[at + j] = SelfWork{u / nj, p0, p1, u % nj};
+    }
+    at += k;
+  }
+}
+
+// Each item: rows [p0, p1) of defect def against all of its m footprint voxels,
+// for jump `pad` of that defect.  Box-relative linear coordinates when every
+// pair offset plus the jump stays within the window, packed coordinates with
+// the minimum image otherwise; the class window, or the full tensor window
+// for a defect without a class.
+__global__ __launch_bounds__(ST) void k_cross(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
+                                              const int32_t* __restrict__ ids, int n, const double* __restrict__ K,
+                                              const double* __restrict__ gcls, int D,
+                                              const int32_t* __restrict__ jumps, int nj,
+                                              const SelfWork* __restrict__ work, const int64_t* __restrict__ nwork_p,
+                                              int64_t cap, double* __restrict__ partial) {
+  __shared__ int32_t pk[SMAX];
+  __shared__ double wsum[ST / 64];
+  const int64_t nwork = *nwork_p < cap ? *nwork_p : cap;
+  const int W = 2 * D + 1;
+  const int h = n / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t wi = blockIdx.x; wi < nwork; wi += gridDim.x) {
+    const SelfWork wk = work[wi];
+    const int i = wk.def;
+    const int m = cnt[i];
+    const int64_t o = defs[i].slot;
+    const int cls = defs[i].cls;
+    const int* lam = jumps + 3 * (i * nj + wk.pad);
+    const int lx = lam[0], ly = lam[1], lz = lam[2];
+    const bool staged = m <= SMAX;
+    const int bx = defs[i].lo[0], by = defs[i].lo[1], bz = defs[i].lo[2];
+    const bool lin = defs[i].w[0] + abs(lx) <= D + 1 && defs[i].w[1] + abs(ly) <= D + 1 &&
+                     defs[i].w[2] + abs(lz) <= D + 1;
+    auto linear = [&](int id) -> int32_t {
+      int x = id % n - bx, y = (id / n) % n - by, z = id / (n * n) - bz;
+      x += x < 0 ? n : 0;
+      y += y < 0 ? n : 0;
+      z += z < 0 ? n : 0;
+      return (z * W + y) * W + x;
+    };
+    auto enc = [&](int id) -> int32_t { return lin ? linear(id) : pack_xyz(id, n); };
+    if (staged)
+      for (int k = threadIdx.x; k < m; k += ST) pk[k] = enc(ids[o + k]);
+    __syncthreads();
+    auto coord = [&](int k) -> int32_t { return staged ? pk[k] : enc(ids[o + k]); };
+    const int C0 = (D * W + D) * W + D;
+    const int L0 = (lz * W + ly) * W + lx;  // the jump in window-linear units
+    auto widx = [&](int32_t P, int32_t Q) -> int {
+      if (lin) return P - Q + L0 + C0;
+      int rx = (P & 1023) - (Q & 1023) + lx, ry = ((P >> 10) & 1023) - ((Q >> 10) & 1023) + ly,
+          rz = (P >> 20) - (Q >> 20) + lz;
+      rx += rx < -h ? n : (rx >= h ? -n : 0);
+      ry += ry < -h ? n : (ry >= h ? -n : 0);
+      rz += rz < -h ? n : (rz >= h ? -n : 0);
+      return ((rz + D) * W + (ry + D)) * W + (rx + D);
+    };
+    double acc = 0.0;
+    if (cls >= 0 && staged && lin) {
+      const double* g = gcls + (size_t)cls * W * W * W;
+      for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
+        const double* gp = g + (pk[p] + L0 + C0);
+        for (int q = lane; q < m; q += 256) {
+          double v[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int qq = q + 64 * k;
+            const double x = gp[-pk[qq < m ? qq : m - 1]];
+            v[k] = qq < m ? x : 0.0;
+          }
+          acc += (v[0] + v[1]) + (v[2] + v[3]);
+        }
+      }
+    } else if (cls >= 0) {
+      const double* g = gcls + (size_t)cls * W * W * W;
+      for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
+        const int32_t P = coord(p);
+        for (int q = lane; q < m; q += 64) acc += g[widx(P, coord(q))];
+      }
+    } else {
+      double E[6];
+      for (int a = 0; a < 6; ++a) E[a] = defs[i].E[a];
+      for (int p = wk.p0 + wave; p < wk.p1; p += ST / 64) {
+        const int32_t P = coord(p);
+        for (int q = lane; q < m; q += 64) {
+          const double* k = K + (size_t)widx(P, coord(q)) * KWIN;
+          double v = 0.0;
+          for (int a = 0; a < 6; ++a) {
+            v += E[a] * E[a] * k[tri(a, a)];
+            for (int b = a + 1; b < 6; ++b) v += 2.0 * E[a] * E[b] * k[tri(a, b)];
+          }
+          acc += v;
+        }
+      }
+    }
+    for (int sh = 32; sh > 0; sh >>= 1) acc += __shfl_down(acc, sh);
+    if (lane == 0) wsum[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < ST / 64; ++w) t += wsum[w];
+      partial[wi] = t;
+    }
+    __syncthreads();  // pk and wsum are rewritten by the next item
+  }
+}
+
+// dE per (defect, jump): X = the item partials added in a fixed order.
+__global__ void k_cross_finish(const int64_t* __restrict__ wbeg, const double* __restrict__ partial,
+                               const DevDefect* __restrict__ defs, int ndef, int nj, const double* __restrict__ t1,
+                               const double* __restrict__ B, double h3c, double* __restrict__ dE) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= ndef * nj) return;
+  const int i = u / nj;
+  double s = 0.0, c = 0.0;
+  for (int64_t w = wbeg[u]; w < wbeg[u + 1]; ++w) neumaier(s, c, partial[w]);
+  const double scale = defs[i].cls >= 0 ? defs[i].s * defs[i].s : 1.0;
+  dE[u] = t1[u] + h3c * scale * (s + c) + B[i];
+}
+
+// Biased frequencies nu = 1/2 nu0 exp(-(Em + dE / 2) / kT) of every jump of a
+// defect, and the jump whose frequency-line interval holds xi: the first j
+// with xi <= R_j / R_tot (R the running sum in jump order).
+__global__ void k_jump_select(const double* __restrict__ dE, int ndef, int nj, const double* __restrict__ Em,
+                              double nu0, double kT, const double* __restrict__ xi, double* __restrict__ nu,
+                              int32_t* __restrict__ choice) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndef) return;
+  double tot = 0.0;
+  for (int j = 0; j < nj; ++j) {
+    const double v = 0.5 * nu0 * exp(-(Em[i] + 0.5 * dE[i * nj + j]) / kT);
+    if (nu) nu[i * nj + j] = v;
+    tot += v;
+  }
+  if (!choice) return;
+  double R = 0.0;
+  int pick = nj - 1;
+  for (int j = 0; j < nj; ++j) {
+    R += 0.5 * nu0 * exp(-(Em[i] + 0.5 * dE[i * nj + j]) / kT);
+    if (xi[i] <= R / tot) {
+      pick = j;
+      break;
+    }
+  }
+  choice[i] = pick;
+}
+
 // Dense component-major outputs [6][n^3] from the voxel-major sigma: which
 // 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic compliance), 2 -> eps*
 // (owner-list gather).
@@ -457,6 +709,31 @@ hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts
   hipLaunchKernelGGL(k_self, dim3(grid), dim3(ST), 0, s, d, counts, ids, n, K, gcls, D, work, wbeg + ndef, work_cap,
                      partial);
   hipLaunchKernelGGL(k_self_finish, dim3(g1), dim3(256), 0, s, wbeg, partial, d, ndef, h3c, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_jump_energies(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids,
+                                const double* sig, int n, const int32_t* jumps, int nj, const double* S0,
+                                const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
+                                int64_t* wbeg, double* partial, double* t1, const double* B, double h3c, double* dE,
+                                hipStream_t s) {
+  if (ndef == 0 || nj == 0) return hipSuccess;
+  const int nu = ndef * nj;
+  hipLaunchKernelGGL(k_jump_sums, dim3(nu), dim3(RDT), 0, s, d, counts, ids, sig, n, jumps, nj, S0, h3c, t1);
+  hipLaunchKernelGGL(k_cross_plan, dim3(1), dim3(PT), 0, s, counts, ndef, nj, wbeg, work, work_cap);
+  const int grid = (int)std::min<int64_t>(work_cap, 4096);
+  hipLaunchKernelGGL(k_cross, dim3(grid), dim3(ST), 0, s, d, counts, ids, n, K, gcls, D, jumps, nj, work, wbeg + nu,
+                     work_cap, partial);
+  hipLaunchKernelGGL(k_cross_finish, dim3((nu + 255) / 256), dim3(256), 0, s, wbeg, partial, d, ndef, nj, t1, B, h3c,
+                     dE);
+  return hipGetLastError();
+}
+
+hipError_t launch_jump_select(const double* dE, int ndef, int nj, const double* Em, double nu0, double kT,
+                              const double* xi, double* nu, int32_t* choice, hipStream_t s) {
+  if (ndef == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_jump_select, dim3((ndef + 255) / 256), dim3(256), 0, s, dE, ndef, nj, Em, nu0, kT, xi, nu,
+                     choice);
   return hipGetLastError();
 }
 

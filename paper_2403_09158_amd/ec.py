@@ -37,6 +37,8 @@ EXPORTS = (
     "ec_solve_fields",
     "ec_interaction_energies",
     "ec_update_defect",
+    "ec_jump_energies",
+    "ec_jump_select",
     "ec_state_footprints",
     "ec_state_field",
     "ec_state_self_terms",
@@ -99,6 +101,8 @@ def load() -> ctypes.CDLL:
         "ec_solve_fields": (c_int, [vp, vp, c_int32, vp, vp, vp, c_int32]),
         "ec_interaction_energies": (c_int, [vp, vp, vp, c_int32]),
         "ec_update_defect": (c_int, [vp, c_int32, vp, vp, vp, c_int32]),
+        "ec_jump_energies": (c_int, [vp, vp, c_int32, vp, vp, c_int32]),
+        "ec_jump_select": (c_int, [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, c_int32]),
         "ec_state_footprints": (c_int, [vp, i32p, i32p, c_int64, i64p]),
         "ec_state_field": (c_int, [vp, c_int32, dp]),
         "ec_state_self_terms": (c_int, [vp, dp]),
@@ -208,6 +212,7 @@ class State:
         _check(load().ec_state_create(ctx.h, ctypes.byref(p), ctypes.byref(h)))
         self.h = h
         self.ndef = 0
+        self._jn = 0  # jumps per defect of the last jump_energies call
 
     @property
     def n(self):
@@ -269,6 +274,45 @@ class State:
             return E
         _check(load().ec_update_defect(self.h, idx, d.ctypes.data, h, None, 0))
         return None
+
+    def jump_energies(self, jumps, stream=None, out=None) -> np.ndarray:
+        """Energy change (eV) of every defect for each of its candidate
+        whole-voxel jumps, ``jumps`` of shape (ndef, njump, 3) (integer voxel
+        offsets); a host array (ndef, njump), or written to a device tensor
+        ``out`` without synchronising."""
+        j = np.ascontiguousarray(jumps, dtype=np.int32)
+        if j.ndim != 3 or j.shape[0] != self.ndef or j.shape[2] != 3:
+            raise ValueError(f"jumps must have shape (ndef={self.ndef}, njump, 3), got {j.shape}")
+        nj = j.shape[1]
+        h = _stream_handle(stream)
+        if out is not None and not isinstance(out, np.ndarray):
+            _check(load().ec_jump_energies(self.h, j.ctypes.data, nj, h, out.data_ptr(), 1))
+            self._jn = nj
+            return out
+        dE = np.zeros((self.ndef, nj)) if out is None else out
+        _check(load().ec_jump_energies(self.h, j.ctypes.data, nj, h, dE.ctypes.data, 0))
+        self._jn = nj
+        return dE
+
+    def jump_select(self, Em, nu0: float, kT: float, xi=None, stream=None):
+        """Biased frequencies (ndef, njump) of the last jump energies and, given
+        random numbers ``xi`` in (0, 1] (one per defect), the chosen jump per
+        defect (int32 array; None without ``xi``)."""
+        nd = self.ndef
+        Em = np.ascontiguousarray(np.broadcast_to(np.asarray(Em, dtype=np.float64), (nd,)))
+        x = None if xi is None else np.ascontiguousarray(xi, dtype=np.float64)
+        if x is not None and x.shape != (nd,):
+            raise ValueError(f"xi must have shape ({nd},)")
+        nj = self._jn
+        nu = np.zeros((nd, nj))
+        choice = np.zeros(nd, dtype=np.int32) if x is not None else None
+        _check(
+            load().ec_jump_select(
+                self.h, Em.ctypes.data, float(nu0), float(kT), None if x is None else x.ctypes.data,
+                _stream_handle(stream), nu.ctypes.data, None if choice is None else choice.ctypes.data, 0,
+            )
+        )
+        return nu, choice
 
     def footprints(self):
         """List of ascending voxel-id arrays, one per defect."""
