@@ -222,6 +222,75 @@ def mixed_512_block(steps=3):
     return out
 
 
+def jump_probe_block(steps=10):
+    """Jump probes on mixed_256 (2000 defects, two glide jumps each): energy
+    changes of all candidate jumps, biased frequencies and the frequency-line
+    choice per defect; FP32 against FP64 and, for a few defects, against the
+    energy change of actually making the move."""
+    import numpy as np
+    import torch
+
+    from paper_2403_09158_amd import ec, inputs
+
+    prob, defs = inputs.mixed_256(prec=1)
+    J = inputs.glide_jumps(defs)
+    rng = np.random.default_rng(inputs.SEED_BASE + 50)
+    Em = np.full(len(defs), 0.1)  # eV
+    kT, nu0 = 0.0258, 1.0e13  # eV (300 K), 1/s
+    ctx = ec.Context(0)
+    out = {
+        "workload": "mixed_256 jump probes: 2000 defects, 2 glide jumps each (one voxel forward and back along b), "
+        "biased frequencies (Em 0.1 eV, kT 0.0258 eV, nu0 1e13/s) and the frequency-line choice",
+        "jumps_per_defect": int(J.shape[1]),
+    }
+    dE, E = {}, {}
+    for prec, name in ((1, "fp32"), (0, "fp64")):
+        st = ec.State(ctx, prob.with_(prec=prec))
+        st.solve(defs)
+        E[prec] = st.energies().copy()
+        for _ in range(2):
+            st.jump_energies(J)
+            st.jump_select(Em, nu0, kT, 1.0 - rng.uniform(size=len(defs)))
+        torch.cuda.synchronize()
+        st.profile(True)
+        st.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dE[prec] = st.jump_energies(J)
+            nu, choice = st.jump_select(Em, nu0, kT, 1.0 - rng.uniform(size=len(defs)))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        # pair sums actually formed: one per jump up to sign (X(-l) = X(l)), none for l = 0
+        m = np.array([len(f) for f in st.footprints()], dtype=np.float64)
+        distinct = np.array([len({min(tuple(v), tuple(-v)) for v in J[i] if v.any()}) for i in range(len(defs))])
+        pairs = float((m * m * distinct).sum())
+        out[name] = {
+            "ms_per_probe": round(dt * 1e3, 3),
+            "pairs_per_probe": pairs,
+            "per_family": family_table(st.profile_read()),
+        }
+        if prec == 0:
+            # a few defects: the energy change of making the move
+            diffs = []
+            for i in range(0, len(defs), 400):
+                moved = defs[i].copy()
+                moved["c"] = moved["c"] + J[i, 0].astype(np.float64) * prob.h
+                E1 = st.update(i, moved)
+                diffs.append(abs((E1[i] - E[0][i]) - dE[0][i, 0]))
+                st.update(i, defs[i])
+            out["fp64_vs_move_max_abs_eV"] = float(max(diffs))
+        st.close()
+    tol = 2.0 * np.maximum(1e-4 * np.abs(E[0]), 1e-5)[:, None]
+    err = np.abs(dE[1] - dE[0])
+    out["fp32_vs_fp64"] = {
+        "max_abs_eV": float(err.max()),
+        "pass_fraction": float(np.mean(err <= tol)),
+        "max_err_over_tol": float((err / tol).max()),
+    }
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -233,6 +302,8 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true", help="time the FP32 path only (profiling runs)")
     ap.add_argument("--no-serving", action="store_true", help="skip the many-replica serving workload")
     ap.add_argument("--no-512", action="store_true", help="skip the 512^3 / 20000-defect workload")
+    ap.add_argument("--no-jumps", action="store_true", help="skip the jump-probe workload")
+    ap.add_argument("--jumps-only", action="store_true", help="run the jump-probe workload alone (profiling runs)")
     ap.add_argument(
         "--calibrate-copy",
         action="store_true",
@@ -259,6 +330,9 @@ def main():
         b.copy_(a)  # reads and writes exactly 2^30 bytes each
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 1 << 30}), flush=True)
+        return
+    if args.jumps_only:
+        print(json.dumps({"jump_probe": jump_probe_block()}), flush=True)
         return
     prob32, defs = inputs.mixed_256(prec=1)
     prob64 = prob32.with_(prec=0)
@@ -351,6 +425,8 @@ def main():
         line["serving"] = serving_block()
     if not args.no_512:
         line["mixed_512"] = mixed_512_block()
+    if not args.no_jumps:
+        line["jump_probe"] = jump_probe_block()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob64, defs)
     print(json.dumps(line), flush=True)

@@ -432,6 +432,20 @@ __global__ __launch_bounds__(RDT) void k_jump_sums(const DevDefect* __restrict__
   }
 }
 
+// X(-lambda) = X(lambda) (G(r) = G(-r): swap the two voxels of every pair),
+// so a jump whose opposite comes earlier in the defect's list reuses that
+// jump's sum, and the zero jump needs none (X(0) is the self-term sum).
+// Returns the jump whose cross sum serves jump j of defect i, or -1 for zero.
+__device__ __forceinline__ int cross_source(const int32_t* __restrict__ jumps, int i, int j, int nj) {
+  const int32_t* l = jumps + 3 * (i * nj + j);
+  if (l[0] == 0 && l[1] == 0 && l[2] == 0) return -1;
+  for (int k = 0; k < j; ++k) {
+    const int32_t* q = jumps + 3 * (i * nj + k);
+    if (q[0] == -l[0] && q[1] == -l[1] && q[2] == -l[2]) return k;
+  }
+  return j;
+}
+
 // Work items of the cross sums: per (defect, jump) ceil(m^2 / target) items
 // (at most SELF_KMAX), each a range of rows p with all m columns q.
 __device__ __forceinline__ int cross_items_of(int m) {
@@ -441,14 +455,15 @@ __device__ __forceinline__ int cross_items_of(int m) {
 }
 
 __global__ __launch_bounds__(PT) void k_cross_plan(const int32_t* __restrict__ cnt, int ndef, int nj,
-                                                   int64_t* __restrict__ wbeg, SelfWork* __restrict__ work,
-                                                   int64_t cap) {
+                                                   const int32_t* __restrict__ jumps, int64_t* __restrict__ wbeg,
+                                                   SelfWork* __restrict__ work, int64_t cap) {
   __shared__ int64_t part[2 * (PT / 64)];
   const int nu = ndef * nj;
   const int per = (nu + PT - 1) / PT;
   const int b = threadIdx.x * per, e = min(nu, b + per);
   int64_t s = 0;
-  for (int u = b; u < e; ++u) s += cross_items_of(cnt[u / nj]);
+  auto items = [&](int u) { return cross_source(jumps, u / nj, u % nj, nj) == u % nj ? cross_items_of(cnt[u / nj]) : 0; };
+  for (int u = b; u < e; ++u) s += items(u);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int64_t x = s;
   for (int o = 1; o < 64; o <<= 1) {
@@ -470,7 +485,7 @@ __global__ __launch_bounds__(PT) void k_cross_plan(const int32_t* __restrict__ c
   if (threadIdx.x == PT - 1) wbeg[nu] = part[2 * (PT / 64) - 1];
   for (int u = b; u < e; ++u) {
     const int m = cnt[u / nj];
-    const int k = cross_items_of(m);
+    const int k = items(u);
     wbeg[u] = at;
     for (int j = 0; j < k; ++j) {
       const int p0 = (int)((int64_t)m * j / k), p1 = (int)((int64_t)m * (j + 1) / k);
@@ -582,15 +597,23 @@ __global__ __launch_bounds__(ST) void k_cross(const DevDefect* __restrict__ defs
   }
 }
 
-// dE per (defect, jump): X = the item partials added in a fixed order.
+// dE per (defect, jump): X = the item partials (of the jump itself or of its
+// opposite) added in a fixed order; the zero jump keeps only the S term.
 __global__ void k_cross_finish(const int64_t* __restrict__ wbeg, const double* __restrict__ partial,
-                               const DevDefect* __restrict__ defs, int ndef, int nj, const double* __restrict__ t1,
-                               const double* __restrict__ B, double h3c, double* __restrict__ dE) {
+                               const DevDefect* __restrict__ defs, int ndef, int nj, const int32_t* __restrict__ jumps,
+                               const double* __restrict__ t1, const double* __restrict__ B, double h3c,
+                               double* __restrict__ dE) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= ndef * nj) return;
   const int i = u / nj;
+  const int src = cross_source(jumps, i, u % nj, nj);
+  if (src < 0) {
+    dE[u] = t1[u];
+    return;
+  }
+  const int us = i * nj + src;
   double s = 0.0, c = 0.0;
-  for (int64_t w = wbeg[u]; w < wbeg[u + 1]; ++w) neumaier(s, c, partial[w]);
+  for (int64_t w = wbeg[us]; w < wbeg[us + 1]; ++w) neumaier(s, c, partial[w]);
   const double scale = defs[i].cls >= 0 ? defs[i].s * defs[i].s : 1.0;
   dE[u] = t1[u] + h3c * scale * (s + c) + B[i];
 }
@@ -720,12 +743,12 @@ hipError_t launch_jump_energies(const DevDefect* d, int ndef, const int32_t* cou
   if (ndef == 0 || nj == 0) return hipSuccess;
   const int nu = ndef * nj;
   hipLaunchKernelGGL(k_jump_sums, dim3(nu), dim3(RDT), 0, s, d, counts, ids, sig, n, jumps, nj, S0, h3c, t1);
-  hipLaunchKernelGGL(k_cross_plan, dim3(1), dim3(PT), 0, s, counts, ndef, nj, wbeg, work, work_cap);
+  hipLaunchKernelGGL(k_cross_plan, dim3(1), dim3(PT), 0, s, counts, ndef, nj, jumps, wbeg, work, work_cap);
   const int grid = (int)std::min<int64_t>(work_cap, 4096);
   hipLaunchKernelGGL(k_cross, dim3(grid), dim3(ST), 0, s, d, counts, ids, n, K, gcls, D, jumps, nj, work, wbeg + nu,
                      work_cap, partial);
-  hipLaunchKernelGGL(k_cross_finish, dim3((nu + 255) / 256), dim3(256), 0, s, wbeg, partial, d, ndef, nj, t1, B, h3c,
-                     dE);
+  hipLaunchKernelGGL(k_cross_finish, dim3((nu + 255) / 256), dim3(256), 0, s, wbeg, partial, d, ndef, nj, jumps, t1, B,
+                     h3c, dE);
   return hipGetLastError();
 }
 

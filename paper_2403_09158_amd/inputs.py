@@ -21,6 +21,8 @@ Workload recipes (defect populations in a cubic-iron-like crystal):
   h = 0.3125 nm, 50-1500 defects drawn as in mixed_256.
 * ``mixed_512``: 512^3, 160 nm; 20000 defects as mixed_256 but 1/2<111> R
   log-uniform in [0.5, 8] nm and <100> R ~ U[1, 8] nm.
+* ``glide_jumps``: the candidate jumps of the jump-probe workload, one voxel
+  forward and back along each defect's Burgers-vector sign pattern.
 
 Seeds: ``numpy.random.default_rng(240309158 + k)`` with k = 1, 2, 3, 5 for the
 four fixed workloads above (pair_32 to mixed_512), 40 + r for serving replica r
@@ -210,7 +212,7 @@ def mixed_512(prec: int = 1):
 
 
 def scaled_mixed(n: int, prec: int = 1, seed: int = 0):
-    """Config-3 defect density and size mix in an n^3 cell with h = 0.3125 nm."""
+    """The mixed_256 defect density and size mix in an n^3 cell with h = 0.3125 nm."""
     rng = np.random.default_rng(SEED_BASE + 300 + seed)
     L = n * H_VOXEL
     ndef = max(2, int(round(2000 * (n / 256.0) ** 3)))
@@ -251,3 +253,18 @@ def serving_trace(nrep: int, nreq: int, rate_per_s: float = 2000.0, update_frac:
     draw = rng.random(nreq)
     hop = rng.integers(0, 8, size=nreq)
     return t, rep, is_update, draw, hop
+
+
+def glide_jumps(defects) -> np.ndarray:
+    """Candidate jumps of the jump-probe workload: per defect one voxel forward
+    and back along the sign pattern of its Burgers vector (the glide direction
+    of a loop: (+-1, +-1, +-1) for 1/2<111>, (+-1, 0, 0) and the like for
+    <100>), along x for a sphere.  Shape (ndef, 2, 3), int32 voxel offsets."""
+    d = np.asarray(defects)
+    out = np.zeros((len(d), 2, 3), dtype=np.int32)
+    for i, rec in enumerate(d):
+        v = np.sign(np.round(rec["b"], 12)).astype(np.int32)
+        if not v.any():
+            v = np.array([1, 0, 0], dtype=np.int32)
+        out[i, 0], out[i, 1] = v, -v
+    return out

@@ -93,6 +93,36 @@ def test_mixed256_translation_invariance(ctx):
     st.close()
 
 
+def test_mixed256_jump_probes(ctx):
+    """Jump energies of the 2000 defects (two glide jumps each) at full size:
+    FP32 within twice the per-defect energy tolerance of FP64, and FP64 equal to
+    the energy change of actually making the move for sampled defects."""
+    from paper_2403_09158_amd import ec
+
+    J = None
+    dE, E = {}, {}
+    for prec in (0, 1):
+        prob, defs = inputs.mixed_256(prec=prec)
+        J = inputs.glide_jumps(defs)
+        st = ec.State(ctx, prob)
+        st.solve(defs)
+        E[prec] = st.energies().copy()
+        dE[prec] = st.jump_energies(J)
+        if prec == 0:
+            scale = np.abs(E[0]).max()
+            for i in range(3, len(defs), 333):
+                for j in range(2):
+                    moved = defs[i].copy()
+                    moved["c"] = moved["c"] + J[i, j].astype(np.float64) * prob.h
+                    E1 = st.update(i, moved)
+                    assert abs((E1[i] - E[0][i]) - dE[0][i, j]) <= 1e-10 * scale, (i, j)
+                    st.update(i, defs[i])
+        st.close()
+    tol = 2.0 * np.maximum(1e-4 * np.abs(E[0]), 1e-5)[:, None]
+    assert np.all(np.abs(dE[1] - dE[0]) <= tol)
+    assert np.abs(dE[0]).max() > 1e-4  # the probes see the interactions
+
+
 def test_mixed512_fp32_against_fp64_and_sampled_footprints(ctx):
     """512^3 / 20000 defects: too large for the oracle's solve, so the FP64
     path (oracle-matched at smaller sizes) is the reference for the FP32 one,
