@@ -291,6 +291,43 @@ def jump_probe_block(steps=10):
     return out
 
 
+def dipole_block(steps=10):
+    """Dipole-tensor energies on mixed_256 (FP64 state) against the exact ones:
+    the paper's comparison of the two, as error statistics."""
+    import numpy as np
+    import torch
+
+    from paper_2403_09158_amd import ec, inputs
+
+    prob, defs = inputs.mixed_256(prec=0)
+    ctx = ec.Context(0)
+    st = ec.State(ctx, prob)
+    st.solve(defs)
+    E = st.energies().copy()
+    Ed = st.dipole_energies()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        Ed = st.dipole_energies()
+    dt = (time.perf_counter() - t0) / steps
+    st.close()
+    ctx.close()
+    err = np.abs(Ed - E)
+    big = np.abs(E) > 1e-3
+    rel = err[big] / np.abs(E[big])
+    return {
+        "workload": "mixed_256 (FP64 state): dipole-tensor energies -P:eps_others(x_c) against the exact energies",
+        "ms_per_call": round(dt * 1e3, 3),
+        "abs_err_eV": {"p50": float(np.median(err)), "p99": float(np.quantile(err, 0.99)), "max": float(err.max())},
+        "rel_err_where_abs_E_above_1meV": {
+            "count": int(big.sum()),
+            "p50": float(np.median(rel)),
+            "p90": float(np.quantile(rel, 0.9)),
+            "max": float(rel.max()),
+        },
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,7 +369,7 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": 1 << 30}), flush=True)
         return
     if args.jumps_only:
-        print(json.dumps({"jump_probe": jump_probe_block()}), flush=True)
+        print(json.dumps({"jump_probe": jump_probe_block(), "dipole": dipole_block()}), flush=True)
         return
     prob32, defs = inputs.mixed_256(prec=1)
     prob64 = prob32.with_(prec=0)
@@ -427,6 +464,7 @@ def main():
         line["mixed_512"] = mixed_512_block()
     if not args.no_jumps:
         line["jump_probe"] = jump_probe_block()
+        line["dipole"] = dipole_block()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob64, defs)
     print(json.dumps(line), flush=True)

@@ -187,6 +187,18 @@ EC_API ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t nj
 EC_API ec_status ec_jump_select(ec_state* st, const double* Em, double nu0, double kT, const double* xi,
                                 void* hip_stream, double* nu_out, int32_t* choice_out, int32_t out_on_device);
 
+/* ---- dipole-tensor approximation (Sec. 2.1) --------------------------------- */
+
+/* Interaction energy of every defect in the dipole approximation (eV): the
+ * field of the other defects taken as constant over the defect, at the voxel
+ * that holds its centre x_c,
+ *   E_i^dip = -P_i : eps_others(x_c) = -h^3 c m_i E_i : sigma_others(x_c),
+ * with P_i = m_i h^3 C:E_i its dipole tensor (m_i footprint voxels) and
+ * sigma_others = the resident stress minus the defect's own (from the kernel
+ * window), for comparison with the exact energies of ec_interaction_energies.
+ * E_out: ndef doubles, host or device (out_on_device). */
+EC_API ec_status ec_dipole_energies(ec_state* st, void* hip_stream, double* E_out, int32_t out_on_device);
+
 /* ---- inspection (tests, benchmarks) ---------------------------------------- */
 
 /* Footprints of the current defect list: counts[ndef] and, if ids != NULL, the

@@ -258,6 +258,8 @@ struct ec_state {
   size_t jwbeg_cap = 0;
   int32_t* jchoice = nullptr;
   size_t jchoice_cap = 0;
+  double* dip = nullptr;  // dipole-tensor energies
+  size_t dip_cap = 0;
   int64_t* updfix = nullptr;  // 6 int64
   // pinned staging: defect table, per-update records, moved footprint
   Pinned pin_tab, pin_upd, pin_ids, pin_tags, pin_jump;
@@ -1146,6 +1148,7 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->jwork, st->jwork_cap * sizeof(SelfWork));
   ledger_free(c, st->jwbeg, st->jwbeg_cap * 8);
   ledger_free(c, st->jchoice, st->jchoice_cap * 4);
+  ledger_free(c, st->dip, st->dip_cap * 8);
   pin_free(st->pin_jump);
   pin_free(st->pin_tab);
   pin_free(st->pin_upd);
@@ -1594,6 +1597,27 @@ ec_status ec_jump_select(ec_state* st, const double* Em, double nu0, double kT, 
                             nu_out ? st->jnu : nullptr, choice_out ? st->jchoice : nullptr, s));
   if (nu_out && (r = copy_out(nu_out, st->jnu, nu * 8, on_device != 0, s)) != EC_OK) return r;
   if (choice_out) return copy_out(choice_out, st->jchoice, (size_t)nd * 4, on_device != 0, s);
+  return EC_OK;
+}
+
+// ---------------------------------------------------------------- dipole energies
+
+ec_status ec_dipole_energies(ec_state* st, void* stream, double* E_out, int32_t on_device) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
+  const int nd = st->ndef;
+  if (nd == 0) return EC_OK;
+  hipStream_t s = (hipStream_t)stream;
+  ec_status r;
+  if ((r = join_self(st, s)) != EC_OK) return r;
+  if ((r = ensure_classes(st, s)) != EC_OK) return r;
+  if ((r = ensure_windows(st, 0, s)) != EC_OK) return r;
+  if ((r = st_grow(st, &st->dip, &st->dip_cap, (size_t)nd)) != EC_OK) return r;
+  const DefBuf& b = st->db[st->cur];
+  LAUNCH(st, s, PF_REDUCE, 0,
+         launch_dipole(b.tab, nd, b.cnt, b.ids, st->sig, st->n, st->win->K, st->gcls, st->win->D, st->h3c, st->dip,
+                       s));
+  if (E_out) return copy_out(E_out, st->dip, (size_t)nd * 8, on_device != 0, s);
   return EC_OK;
 }
 

@@ -645,6 +645,62 @@ __global__ void k_jump_select(const double* __restrict__ dE, int ndef, int nj, c
   choice[i] = pick;
 }
 
+// ---- dipole-tensor energies (Sec. 2.1) ------------------------------------------
+//
+// E_i^dip = -h^3 c m_i E_i : (sigma(x_c) - sigma_i(x_c)), x_c the voxel holding
+// the defect centre and sigma_i(x_c) = sum_{y in Omega_i} G(x_c - y) : E_i (the
+// window); one workgroup per defect.
+__global__ __launch_bounds__(RDT) void k_dipole(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
+                                                const int32_t* __restrict__ ids, const double* __restrict__ sig,
+                                                int n, const double* __restrict__ K,
+                                                const double* __restrict__ gcls, int D, double h3c,
+                                                double* __restrict__ Edip) {
+  const int i = blockIdx.x;
+  const DevDefect d = defs[i];
+  const int64_t o = d.slot;
+  const int m = cnt[i];
+  const int W = 2 * D + 1;
+  const int hn = n / 2;
+  int c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) c[k] = (d.cq[k] / QSUB) % n;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < m; k += RDT) {
+    const int id = ids[o + k];
+    int r[3] = {c[0] - id % n, c[1] - (id / n) % n, c[2] - id / (n * n)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r[a] += r[a] < -hn ? n : (r[a] >= hn ? -n : 0);
+    const int w = ((r[2] + D) * W + (r[1] + D)) * W + (r[0] + D);
+    if (d.cls >= 0) {
+      acc += gcls[(size_t)d.cls * W * W * W + w];
+    } else {
+      const double* kk = K + (size_t)w * KWIN;
+      double v = 0.0;
+      for (int a = 0; a < 6; ++a) {
+        v += d.E[a] * d.E[a] * kk[tri(a, a)];
+        for (int b = a + 1; b < 6; ++b) v += 2.0 * d.E[a] * d.E[b] * kk[tri(a, b)];
+      }
+      acc += v;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
+  __shared__ double ws[RDT / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) ws[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double own = 0.0;
+    for (int w = 0; w < RDT / 64; ++w) own += ws[w];
+    if (d.cls >= 0) own *= d.s * d.s;
+    double s6[6];
+    ld_voxel(sig, ((int64_t)c[2] * n + c[1]) * n + c[0], s6);
+    double dot = 0.0;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) dot += ddot_w(a) * d.E[a] * s6[a];
+    Edip[i] = -h3c * m * (dot - own);
+  }
+}
+
 // Dense component-major outputs [6][n^3] from the voxel-major sigma: which
 // 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic compliance), 2 -> eps*
 // (owner-list gather).
@@ -757,6 +813,13 @@ hipError_t launch_jump_select(const double* dE, int ndef, int nj, const double* 
   if (ndef == 0) return hipSuccess;
   hipLaunchKernelGGL(k_jump_select, dim3((ndef + 255) / 256), dim3(256), 0, s, dE, ndef, nj, Em, nu0, kT, xi, nu,
                      choice);
+  return hipGetLastError();
+}
+
+hipError_t launch_dipole(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, const double* sig,
+                         int n, const double* K, const double* gcls, int D, double h3c, double* Edip, hipStream_t s) {
+  if (ndef == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dipole, dim3(ndef), dim3(RDT), 0, s, d, counts, ids, sig, n, K, gcls, D, h3c, Edip);
   return hipGetLastError();
 }
 

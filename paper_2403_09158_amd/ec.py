@@ -39,6 +39,7 @@ EXPORTS = (
     "ec_update_defect",
     "ec_jump_energies",
     "ec_jump_select",
+    "ec_dipole_energies",
     "ec_state_footprints",
     "ec_state_field",
     "ec_state_self_terms",
@@ -103,6 +104,7 @@ def load() -> ctypes.CDLL:
         "ec_update_defect": (c_int, [vp, c_int32, vp, vp, vp, c_int32]),
         "ec_jump_energies": (c_int, [vp, vp, c_int32, vp, vp, c_int32]),
         "ec_jump_select": (c_int, [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, c_int32]),
+        "ec_dipole_energies": (c_int, [vp, vp, vp, c_int32]),
         "ec_state_footprints": (c_int, [vp, i32p, i32p, c_int64, i64p]),
         "ec_state_field": (c_int, [vp, c_int32, dp]),
         "ec_state_self_terms": (c_int, [vp, dp]),
@@ -313,6 +315,16 @@ class State:
             )
         )
         return nu, choice
+
+    def dipole_energies(self, stream=None, out=None) -> np.ndarray:
+        """Dipole-tensor interaction energies (eV) of the current defects; host
+        array unless a device tensor is passed as ``out``."""
+        if out is not None and not isinstance(out, np.ndarray):
+            _check(load().ec_dipole_energies(self.h, _stream_handle(stream), out.data_ptr(), 1))
+            return out
+        E = np.zeros(self.ndef) if out is None else out
+        _check(load().ec_dipole_energies(self.h, _stream_handle(stream), E.ctypes.data, 0))
+        return E
 
     def footprints(self):
         """List of ascending voxel-id arrays, one per defect."""

@@ -1,6 +1,7 @@
 """Jump probes on the GPU: energy changes of candidate whole-voxel jumps against
 the oracle and against actually moving the defect, the biased frequencies and
-the frequency-line choice against the oracle, and the argument checks.
+the frequency-line choice against the oracle, and the argument checks; the
+dipole-tensor energies against the oracle.
 
 Tolerances: FP64 states to 1e-10 of the largest interaction energy (the
 normwise energy tolerance; a jump energy is a difference of two energies);
@@ -78,7 +79,7 @@ def test_jump_energies_match_oracle(ctx, prec):
 def test_jump_energy_is_the_energy_change_of_the_move(ctx):
     """dE_ij equals E_i after actually moving defect i by the jump (an
     incremental update) minus E_i before, for defects across a 64^3 mix."""
-    from paper_2403_09158_amd import ec, serve
+    from paper_2403_09158_amd import ec
 
     rng = np.random.default_rng(inputs.SEED_BASE + 730)
     n = 64
@@ -156,4 +157,46 @@ def test_jump_probe_argument_checks(ctx):
         with pytest.raises(ec.EcError) as ei:
             st.jump_select(Em, nu0, kT, xi)
         assert ei.value.status == ec.EC_ERR_ARG
+    st.close()
+
+
+# ------------------------------------------------------------------ dipole mode
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dipole_energies_match_oracle(ctx, prec):
+    from oracle import dipole as odipole
+    from paper_2403_09158_amd import ec
+
+    prob, d = _cell(prec)
+    st = ec.State(ctx, prob)
+    st.solve(d)
+    got = st.dipole_energies()
+    fps, Es = raster.rasterise(prob, d)
+    want = odipole.dipole_energies_brute(prob, fps, Es, odipole.centre_voxels(prob, d))
+    if prec == 0:
+        assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+    else:
+        assert np.all(np.abs(got - want) <= np.maximum(1e-4 * np.abs(want), 1e-5))
+    st.close()
+
+
+def test_dipole_energies_mixed_cell_against_oracle(ctx):
+    from oracle import dipole as odipole
+    from paper_2403_09158_amd import ec
+
+    rng = np.random.default_rng(inputs.SEED_BASE + 750)
+    n = 48
+    L = n * inputs.H_VOXEL
+    prob = inputs.Problem(n, L, *inputs.CUBIC_FE, prec=0)
+    d = inputs.mixed_population(rng, 25, L, inputs.H_VOXEL, r111=(0.4, 1.2), r100=(0.5, 1.2))
+    st = ec.State(ctx, prob)
+    st.solve(d)
+    got = st.dipole_energies()
+    exact = st.energies()
+    fps, Es = raster.rasterise(prob, d)
+    want = odipole.dipole_energies_fast(prob, fps, Es, odipole.centre_voxels(prob, d))
+    assert np.abs(got - want).max() <= 1e-10 * np.abs(want).max()
+    # the approximation differs from the exact energies (it is reported, not hidden)
+    assert np.abs(got - exact).max() > 1e-6
     st.close()
