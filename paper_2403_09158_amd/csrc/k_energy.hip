@@ -669,7 +669,7 @@ __global__ __launch_bounds__(RDT) void k_dipole(const DevDefect* __restrict__ de
     const int id = ids[o + k];
     int r[3] = {c[0] - id % n, c[1] - (id / n) % n, c[2] - id / (n * n)};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) r[a] += r[a] < -hn ? n : (r[a] >= hn ? -n : 0);
+    for (int a = 0; a < 3; ++a) r[a] += r[a] < -hn ? n : (r[a] >= hn ? -n : 0);  // [-n/2, n/2): n is even
     const int w = ((r[2] + D) * W + (r[1] + D)) * W + (r[0] + D);
     if (d.cls >= 0) {
       acc += gcls[(size_t)d.cls * W * W * W + w];
