@@ -21,6 +21,11 @@ elastic interactions in OkMC" (arXiv 2403.09158):
 * ``jumps``    - energy changes of candidate whole-voxel jumps, the biased jump
                  frequencies and the frequency-line selection (Sec. 4 and the
                  OkMC loop of App. A).
+* ``okmc``     - one step of the parallel OkMC loop (Sec. 4, App. A): fixed time
+                 step, Poisson event counts, one chosen jump per acting defect,
+                 energies of the moved list.
+* ``dipole``   - the dipole-tensor approximation of the interaction energy
+                 (Sec. 2.1).
 
 Everything is float64 / complex128 and uses full 3x3 and 3x3x3x3 tensors (no
 Voigt shortcuts).  Readings of garbled or silent passages are stated in each
