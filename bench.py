@@ -254,20 +254,34 @@ def jump_probe_block(steps=10):
         torch.cuda.synchronize()
         st.profile(True)
         st.profile_read()
+        # a probe of a new configuration: the jump order alternates, so the
+        # stored cross parts (kept while footprints only translate) are not reused
+        Jr = np.ascontiguousarray(J[:, ::-1])
+        t0 = time.perf_counter()
+        for k in range(steps):
+            st.jump_energies(Jr if k % 2 else J)
+            nu, choice = st.jump_select(Em, nu0, kT, 1.0 - rng.uniform(size=len(defs)))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        fam = family_table(st.profile_read())
+        # the same jumps again (as after an OkMC step): cross parts reused
+        dE[prec] = st.jump_energies(J)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             dE[prec] = st.jump_energies(J)
             nu, choice = st.jump_select(Em, nu0, kT, 1.0 - rng.uniform(size=len(defs)))
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
+        dt_warm = (time.perf_counter() - t0) / steps
         # pair sums actually formed: one per jump up to sign (X(-l) = X(l)), none for l = 0
         m = np.array([len(f) for f in st.footprints()], dtype=np.float64)
         distinct = np.array([len({min(tuple(v), tuple(-v)) for v in J[i] if v.any()}) for i in range(len(defs))])
         pairs = float((m * m * distinct).sum())
         out[name] = {
             "ms_per_probe": round(dt * 1e3, 3),
+            "ms_per_probe_cross_parts_reused": round(dt_warm * 1e3, 3),
             "pairs_per_probe": pairs,
-            "per_family": family_table(st.profile_read()),
+            "per_family": fam,
         }
         if prec == 0:
             # a few defects: the energy change of making the move
@@ -287,6 +301,54 @@ def jump_probe_block(steps=10):
         "pass_fraction": float(np.mean(err <= tol)),
         "max_err_over_tol": float((err / tol).max()),
     }
+    ctx.close()
+    return out
+
+
+def okmc_block(steps=20, warmup=3):
+    """OkMC time steps on mixed_256 (Sec. 4, App. A): Poisson gate over the
+    fixed step, jump probes and choice for every defect, the chosen jumps made
+    and the field solved again; the 1/2<111> loop migration barrier of the
+    paper's loop runs (0.1 eV at 300 K) for every defect, two glide jumps each."""
+    import numpy as np
+    import torch
+
+    from paper_2403_09158_amd import ec, inputs
+
+    prob, defs = inputs.mixed_256(prec=1)
+    J = inputs.glide_jumps(defs)
+    nd = len(defs)
+    Em = np.full(nd, 0.1)  # eV
+    kT, nu0 = 8.617333262e-5 * 300.0, 1.0e13
+    dt_s = 1.0 / (nu0 * np.exp(-0.1 / kT))
+    ctx = ec.Context(0)
+    out = {
+        "workload": "mixed_256 OkMC steps: 2000 defects, 2 glide jumps each, Em 0.1 eV, 300 K, nu0 1e13/s, "
+        "fixed step 1/nu_max; per step: Poisson gate, jump probes of all defects, frequency-line choice, "
+        "chosen jumps made and the field solved again",
+        "dt_ps": round(dt_s * 1e12, 4),
+    }
+    for prec, name in ((1, "fp32"), (0, "fp64")):
+        rng = np.random.default_rng(inputs.SEED_BASE + 60)
+        st = ec.State(ctx, prob.with_(prec=prec))
+        st.solve(defs)
+        for _ in range(warmup):
+            st.okmc_step(J, Em, nu0, kT, 1.0 - rng.uniform(size=nd), 1.0 - rng.uniform(size=nd))
+        torch.cuda.synchronize()
+        moved = 0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ch = st.okmc_step(J, Em, nu0, kT, 1.0 - rng.uniform(size=nd), 1.0 - rng.uniform(size=nd))
+            moved += int((ch >= 0).sum())
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        st.close()
+        out[name] = {
+            "ms_per_step": round(t * 1e3, 3),
+            "steps_per_s": round(1.0 / t, 1),
+            "moved_fraction": round(moved / (steps * nd), 4),
+            "simulated_ns_per_wall_s": round(dt_s / t * 1e9, 3),
+        }
     ctx.close()
     return out
 
@@ -375,6 +437,7 @@ def main():
     ap.add_argument("--no-512", action="store_true", help="skip the 512^3 / 20000-defect workload")
     ap.add_argument("--no-jumps", action="store_true", help="skip the jump-probe workload")
     ap.add_argument("--jumps-only", action="store_true", help="run the jump-probe workload alone (profiling runs)")
+    ap.add_argument("--okmc-only", action="store_true", help="run the OkMC-step workload alone (profiling runs)")
     ap.add_argument(
         "--calibrate-copy",
         action="store_true",
@@ -402,8 +465,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 1 << 30}), flush=True)
         return
+    if args.okmc_only:
+        print(json.dumps({"okmc": okmc_block()}), flush=True)
+        return
     if args.jumps_only:
-        print(json.dumps({"jump_probe": jump_probe_block(), "dipole": dipole_block()}), flush=True)
+        print(json.dumps({"jump_probe": jump_probe_block(), "dipole": dipole_block(), "okmc": okmc_block()}), flush=True)
         return
     prob32, defs = inputs.mixed_256(prec=1)
     prob64 = prob32.with_(prec=0)
@@ -499,6 +565,7 @@ def main():
     if not args.no_jumps:
         line["jump_probe"] = jump_probe_block()
         line["dipole"] = dipole_block()
+        line["okmc"] = okmc_block()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob64, defs)
     print(json.dumps(line), flush=True)

@@ -187,6 +187,26 @@ EC_API ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t nj
 EC_API ec_status ec_jump_select(ec_state* st, const double* Em, double nu0, double kT, const double* xi,
                                 void* hip_stream, double* nu_out, int32_t* choice_out, int32_t out_on_device);
 
+/* One time step of the parallel OkMC loop (Sec. 4 and App. A) on the solved
+ * state.  Every defect draws its event count N_i over dt from the Poisson law
+ * with its nominal frequency nu_i = nu0 exp(-Em_i / kT): N_i = 0 when
+ * u_i <= exp(-nu_i dt).  Each defect with N_i > 0 takes one jump, chosen as in
+ * ec_jump_select from its biased frequencies against the field at the start of
+ * the step (all defects probed against the same field); the chosen jumps are
+ * then made together and the field of the new positions solved.
+ *   jumps: host int32 [ndef][njump][3] as in ec_jump_energies;
+ *   Em, u, xi: host, ndef doubles each (u, xi in (0, 1]: the caller's random
+ *   numbers for the gate and the selection);
+ *   dt > 0 in s, or <= 0 for the paper's fixed step 1 / max_i nu_i;
+ *   choice_out: host, ndef int32 (the jump index taken, -1 for none), or NULL;
+ *   E_out: host, ndef doubles (energies after the step), or NULL.
+ * The state's centres move by whole voxels in its quantised units, exactly;
+ * the caller's record of defect i moves by h * jumps[i][choice_i].  Errors in
+ * the arguments leave the state unchanged. */
+EC_API ec_status ec_okmc_step(ec_state* st, const int32_t* jumps, int32_t njump, const double* Em, double nu0,
+                              double kT, double dt, const double* u, const double* xi, void* hip_stream,
+                              int32_t* choice_out, double* E_out);
+
 /* ---- dipole-tensor approximation (Sec. 2.1) --------------------------------- */
 
 /* Interaction energy of every defect in the dipole approximation (eV): the

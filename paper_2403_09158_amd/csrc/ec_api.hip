@@ -254,6 +254,12 @@ struct ec_state {
   size_t jdE_cap = 0, jt1_cap = 0, jpartial_cap = 0, jsel_cap = 0, jnu_cap = 0;
   SelfWork* jwork = nullptr;
   size_t jwork_cap = 0;
+  // cross parts h^3 c X(lambda) + B_i of the jumps jx_jumps, valid while the
+  // list changes by whole-voxel translations only
+  double* jxc = nullptr;
+  size_t jxc_cap = 0;
+  bool jx_ok = false;
+  std::vector<int32_t> jx_jumps;
   int64_t* jwbeg = nullptr;
   size_t jwbeg_cap = 0;
   int32_t* jchoice = nullptr;
@@ -996,6 +1002,99 @@ void cyclic_cover(int lo1, int w1, int lo2, int w2, int n, int& lo, int& len) {
   len = n - best;
 }
 
+// Commits the quantised list h (ndef entries in the pinned staging buffer of
+// the device table, pin_begin already called on it) and solves: footprint
+// slots from the box volumes, the old eigenstrain out and the new one in, the
+// Fourier passes, the self terms beside them.  keep_self: h is the current list
+// with whole-voxel translations only (same order, shapes and classes, the
+// classes already in h), so the self terms, classes and windows stay valid.
+ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, bool keep_self = false) {
+  ec_status r;
+  const char* hp = (const char*)h;
+  int64_t total = 0;
+  for (int i = 0; i < ndef; ++i) {
+    h[i].slot = total;
+    total += box_volume(h[i]);
+  }
+  // buffers of the new list (the spare set)
+  DefBuf& nb = st->db[1 - st->cur];
+  size_t idcap = (size_t)nb.ids_cap, lkcap = (size_t)nb.ids_cap;
+  const size_t need = (size_t)std::max<int64_t>(total, 1);
+  if ((r = ensure_defbuf(st, nb, ndef)) != EC_OK || (r = ensure_per_defect(st, ndef)) != EC_OK ||
+      (r = st_grow(st, &nb.ids, &idcap, need)) != EC_OK || (r = st_grow(st, &nb.lnk, &lkcap, need)) != EC_OK)
+    return r;
+  nb.ids_cap = (int64_t)std::min(idcap, lkcap);
+  if (ndef > 0) {
+    HIPCHK(hipMemcpyAsync(nb.tab, hp, ndef * sizeof(DevDefect), hipMemcpyHostToDevice, s));
+    if ((r = pin_end(st->pin_tab, s)) != EC_OK) return r;
+  }
+  // commit: remove the old eigenstrain, add the new one
+  if ((r = join_self(st, s)) != EC_OK) return r;
+  const DefBuf& ob = st->db[st->cur];
+  if (st->ndef > 0)
+    LAUNCH(st, s, PF_RASTER, 0, launch_unraster(ob.tab, st->ndef, ob.cnt, ob.ids, st->own, s));
+  LAUNCH(st, s, PF_RASTER, 0, launch_raster_fill(nb.tab, ndef, st->n, nb.ids, nb.lnk, nb.cnt, st->own, s));
+  if (!st->ev_fill) HIPCHK(hipEventCreateWithFlags(&st->ev_fill, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(st->ev_fill, s));
+  st->cur = 1 - st->cur;
+  st->hcnt_ok = false;
+  st->ndef = ndef;
+  st->ids_used = total;
+  if (!keep_self) {
+    st->B_valid = false;
+    st->classes_ok = false;
+    st->jx_ok = false;
+  }
+  st->jdE_ok = false;
+  LAUNCH(st, s, PF_OTHER, 0,
+         launch_mean_stress(nb.tab, nb.cnt, ndef, st->n3, st->C, st->prob.bc, st->add6, s));
+  // Fourier solve.  The self terms run on the side stream beside the forward x and y passes
+  // (after the rasterisation), and the z pass waits for them: its workgroups
+  // each take most of a CU's LDS, so self-term blocks still resident would
+  // hold some of them back and stretch the pass.
+  auto beside = [&]() -> ec_status {
+    // host copies of the list while the device works (the staging buffer is
+    // only read by the pending upload); the self-term set-up reads them
+    st->hdefs.assign(h, h + ndef);
+    st->hcap.resize(ndef);
+    for (int i = 0; i < ndef; ++i) st->hcap[i] = box_volume(h[i]);
+    if (ndef == 0 || keep_self) return EC_OK;
+    ec_status q = self_terms_beside(st);
+    return q == EC_OK ? join_self(st, s) : q;
+  };
+  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6, st->tilectr, beside);
+  if (r != EC_OK) return r;
+  st->solved = true;
+  return EC_OK;
+}
+
+// Biased frequencies and the frequency-line choice from the jump energies of
+// the current list; with u, the Poisson gate of the time step dt first (-1: no
+// event).  Arguments already validated.
+ec_status run_select(ec_state* st, const double* Em, double nu0, double kT, const double* xi, const double* u,
+                     double dt, hipStream_t s, double* nu_out, int32_t* choice_out, bool on_device) {
+  const int nd = st->ndef, nj = st->jn;
+  const size_t nu = (size_t)nd * nj;
+  ec_status r;
+  if ((r = st_grow(st, &st->jsel, &st->jsel_cap, 3 * (size_t)nd)) != EC_OK) return r;
+  if (nu_out && (r = st_grow(st, &st->jnu, &st->jnu_cap, nu)) != EC_OK) return r;
+  if (choice_out && (r = st_grow(st, &st->jchoice, &st->jchoice_cap, (size_t)nd)) != EC_OK) return r;
+  char* hp = nullptr;
+  if ((r = pin_begin(st->pin_jump, 3 * (size_t)nd * 8, &hp)) != EC_OK) return r;
+  std::memcpy(hp, Em, (size_t)nd * 8);
+  if (xi) std::memcpy(hp + (size_t)nd * 8, xi, (size_t)nd * 8);
+  if (u) std::memcpy(hp + 2 * (size_t)nd * 8, u, (size_t)nd * 8);
+  HIPCHK(hipMemcpyAsync(st->jsel, hp, 3 * (size_t)nd * 8, hipMemcpyHostToDevice, s));
+  if ((r = pin_end(st->pin_jump, s)) != EC_OK) return r;
+  LAUNCH(st, s, PF_OTHER, 0,
+         launch_jump_select(st->jdE, nd, nj, st->jsel, nu0, kT, xi ? st->jsel + nd : nullptr,
+                            u ? st->jsel + 2 * nd : nullptr, dt, nu_out ? st->jnu : nullptr,
+                            choice_out ? st->jchoice : nullptr, s));
+  if (nu_out && (r = copy_out(nu_out, st->jnu, nu * 8, on_device, s)) != EC_OK) return r;
+  if (choice_out) return copy_out(choice_out, st->jchoice, (size_t)nd * 4, on_device, s);
+  return EC_OK;
+}
+
 }  // namespace
 
 // =============================================================================== ABI
@@ -1142,6 +1241,7 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->jjumps, st->jjumps_cap * 4);
   ledger_free(c, st->jdE, st->jdE_cap * 8);
   ledger_free(c, st->jt1, st->jt1_cap * 8);
+  ledger_free(c, st->jxc, st->jxc_cap * 8);
   ledger_free(c, st->jpartial, st->jpartial_cap * 8);
   ledger_free(c, st->jsel, st->jsel_cap * 8);
   ledger_free(c, st->jnu, st->jnu_cap * 8);
@@ -1177,9 +1277,8 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   if (!st) return fail(EC_ERR_ARG, "state is NULL");
   if (ndef < 0 || (ndef > 0 && !defs)) return fail(EC_ERR_ARG, "bad defect array");
   hipStream_t s = (hipStream_t)stream;
-  // 1. validate and quantise everything before touching the state, straight
-  // into the pinned staging buffer of the device table; footprint slots from
-  // the box volumes
+  // validate and quantise everything before touching the state, straight into
+  // the pinned staging buffer of the device table
   ec_status r;
   char* hp = nullptr;
   if ((r = pin_begin(st->pin_tab, std::max<size_t>(ndef, 1) * sizeof(DevDefect), &hp)) != EC_OK) return r;
@@ -1202,58 +1301,7 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
     for (int c = 0; c < nch; ++c)
       if (bad[c] != INT_MAX) return fail(EC_ERR_ARG, "defect %d: %s", bad[c], why[c].c_str());
   }
-  int64_t total = 0;
-  for (int i = 0; i < ndef; ++i) {
-    h[i].slot = total;
-    total += box_volume(h[i]);
-  }
-  // 2. buffers of the new list (the spare set)
-  DefBuf& nb = st->db[1 - st->cur];
-  size_t idcap = (size_t)nb.ids_cap, lkcap = (size_t)nb.ids_cap;
-  const size_t need = (size_t)std::max<int64_t>(total, 1);
-  if ((r = ensure_defbuf(st, nb, ndef)) != EC_OK || (r = ensure_per_defect(st, ndef)) != EC_OK ||
-      (r = st_grow(st, &nb.ids, &idcap, need)) != EC_OK || (r = st_grow(st, &nb.lnk, &lkcap, need)) != EC_OK)
-    return r;
-  nb.ids_cap = (int64_t)std::min(idcap, lkcap);
-  if (ndef > 0) {
-    HIPCHK(hipMemcpyAsync(nb.tab, hp, ndef * sizeof(DevDefect), hipMemcpyHostToDevice, s));
-    if ((r = pin_end(st->pin_tab, s)) != EC_OK) return r;
-  }
-  // 3. commit: remove the old eigenstrain, add the new one
-  if ((r = join_self(st, s)) != EC_OK) return r;
-  const DefBuf& ob = st->db[st->cur];
-  if (st->ndef > 0)
-    LAUNCH(st, s, PF_RASTER, 0, launch_unraster(ob.tab, st->ndef, ob.cnt, ob.ids, st->own, s));
-  LAUNCH(st, s, PF_RASTER, 0, launch_raster_fill(nb.tab, ndef, st->n, nb.ids, nb.lnk, nb.cnt, st->own, s));
-  if (!st->ev_fill) HIPCHK(hipEventCreateWithFlags(&st->ev_fill, hipEventDisableTiming));
-  HIPCHK(hipEventRecord(st->ev_fill, s));
-  st->cur = 1 - st->cur;
-  st->hcnt_ok = false;
-  st->ndef = ndef;
-  st->ids_used = total;
-  st->B_valid = false;
-  st->classes_ok = false;
-  st->jdE_ok = false;
-  LAUNCH(st, s, PF_OTHER, 0,
-         launch_mean_stress(nb.tab, nb.cnt, ndef, st->n3, st->C, st->prob.bc, st->add6, s));
-  // 4. Fourier solve
-  // The self terms run on the side stream beside the forward x and y passes
-  // (after the rasterisation), and the z pass waits for them: its workgroups
-  // each take most of a CU's LDS, so self-term blocks still resident would
-  // hold some of them back and stretch the pass.
-  auto beside = [&]() -> ec_status {
-    // host copies of the list while the device works (the staging buffer is
-    // only read by the pending upload); the self-term set-up reads them
-    st->hdefs.assign(h, h + ndef);
-    st->hcap.resize(ndef);
-    for (int i = 0; i < ndef; ++i) st->hcap[i] = box_volume(h[i]);
-    if (ndef == 0) return EC_OK;
-    ec_status q = self_terms_beside(st);
-    return q == EC_OK ? join_self(st, s) : q;
-  };
-  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6, st->tilectr, beside);
-  if (r != EC_OK) return r;
-  st->solved = true;
+  if ((r = solve_table(st, h, ndef, s)) != EC_OK) return r;
   if (eps_out && (r = write_field(st, 1, eps_out, on_device != 0, s)) != EC_OK) return r;
   if (sig_out && (r = write_field(st, 0, sig_out, on_device != 0, s)) != EC_OK) return r;
   return EC_OK;
@@ -1288,6 +1336,7 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
     if (rc != EC_OK) return rc;
   }
   st->jdE_ok = false;
+  st->jx_ok = false;
   const DevDefect od = st->hdefs[idx];
   const int n = st->n;
   // whole-voxel move of the same shape: the footprint translates and B_i is unchanged
@@ -1541,7 +1590,9 @@ ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t njump, vo
     const double m = (double)box_volume(d);
     cap += (int64_t)njump * (int64_t)std::min(64.0, std::max(1.0, std::ceil(m * m / 32768.0)));
   }
+  if (st->jxc_cap < nu) st->jx_ok = false;
   if ((r = st_grow(st, &st->jjumps, &st->jjumps_cap, 3 * nu)) != EC_OK ||
+      (r = st_grow(st, &st->jxc, &st->jxc_cap, nu)) != EC_OK ||
       (r = st_grow(st, &st->jdE, &st->jdE_cap, nu)) != EC_OK || (r = st_grow(st, &st->jt1, &st->jt1_cap, nu)) != EC_OK ||
       (r = st_grow(st, &st->jwbeg, &st->jwbeg_cap, nu + 1)) != EC_OK ||
       (r = st_grow(st, &st->jwork, &st->jwork_cap, (size_t)cap)) != EC_OK ||
@@ -1553,15 +1604,21 @@ ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t njump, vo
   HIPCHK(hipMemcpyAsync(st->jjumps, hp, 3 * nu * 4, hipMemcpyHostToDevice, s));
   if ((r = pin_end(st->pin_jump, s)) != EC_OK) return r;
   const DefBuf& b = st->db[st->cur];
+  const bool xc_valid = st->jx_ok && st->jx_jumps.size() == 3 * nu &&
+                        std::memcmp(st->jx_jumps.data(), jumps, 3 * nu * 4) == 0;
   // S(0): the footprint sums of the energies reduction (which also refreshes E)
   LAUNCH(st, s, PF_REDUCE, 0,
          launch_reduce(b.tab, nd, b.cnt, b.ids, st->sig, st->B, st->h3c, st->S6, st->E, s));
   LAUNCH(st, s, PF_SELF, 0,
          launch_jump_energies(b.tab, nd, b.cnt, b.ids, st->sig, st->n, st->jjumps, njump, st->S6, st->win->K,
                               st->gcls, st->win->D, st->jwork, (int64_t)st->jwork_cap, st->jwbeg, st->jpartial,
-                              st->jt1, st->B, st->h3c, st->jdE, s));
+                              st->jt1, st->B, st->h3c, st->jxc, xc_valid, st->jdE, s));
   st->jn = njump;
   st->jdE_ok = true;
+  if (!xc_valid) {
+    st->jx_jumps.assign(jumps, jumps + 3 * nu);
+    st->jx_ok = true;
+  }
   if (dE_out) return copy_out(dE_out, st->jdE, nu * 8, on_device != 0, s);
   return EC_OK;
 }
@@ -1580,23 +1637,58 @@ ec_status ec_jump_select(ec_state* st, const double* Em, double nu0, double kT, 
     if (!std::isfinite(Em[i])) return fail(EC_ERR_ARG, "Em of defect %d not finite", i);
     if (xi && !(xi[i] > 0.0 && xi[i] <= 1.0)) return fail(EC_ERR_ARG, "xi of defect %d outside (0, 1]", i);
   }
+  return run_select(st, Em, nu0, kT, xi, nullptr, 0.0, (hipStream_t)stream, nu_out, choice_out, on_device != 0);
+}
+
+ec_status ec_okmc_step(ec_state* st, const int32_t* jumps, int32_t njump, const double* Em, double nu0, double kT,
+                       double dt, const double* u, const double* xi, void* stream, int32_t* choice_out,
+                       double* E_out) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
+  if (!(nu0 > 0.0) || !std::isfinite(nu0) || !(kT > 0.0) || !std::isfinite(kT))
+    return fail(EC_ERR_ARG, "nu0 and kT must be positive and finite");
+  if (!std::isfinite(dt)) return fail(EC_ERR_ARG, "dt is not finite");
+  const int nd = st->ndef;
+  if (nd > 0 && (!Em || !u || !xi)) return fail(EC_ERR_ARG, "Em, u or xi is NULL");
+  double numax = 0.0;
+  for (int i = 0; i < nd; ++i) {
+    if (!std::isfinite(Em[i])) return fail(EC_ERR_ARG, "Em of defect %d not finite", i);
+    if (!(u[i] > 0.0 && u[i] <= 1.0)) return fail(EC_ERR_ARG, "u of defect %d outside (0, 1]", i);
+    if (!(xi[i] > 0.0 && xi[i] <= 1.0)) return fail(EC_ERR_ARG, "xi of defect %d outside (0, 1]", i);
+    numax = std::max(numax, nu0 * std::exp(-Em[i] / kT));
+  }
+  // the paper's fixed step: one event on average for the fastest defect
+  if (dt <= 0.0 && nd > 0) {
+    if (!(numax > 0.0) || !std::isfinite(numax)) return fail(EC_ERR_ARG, "no finite positive frequency for dt");
+    dt = 1.0 / numax;
+  }
   hipStream_t s = (hipStream_t)stream;
   ec_status r;
-  const size_t nu = (size_t)nd * nj;
-  if ((r = st_grow(st, &st->jsel, &st->jsel_cap, 2 * (size_t)nd)) != EC_OK) return r;
-  if (nu_out && (r = st_grow(st, &st->jnu, &st->jnu_cap, nu)) != EC_OK) return r;
-  if (choice_out && (r = st_grow(st, &st->jchoice, &st->jchoice_cap, (size_t)nd)) != EC_OK) return r;
+  if ((r = ec_jump_energies(st, jumps, njump, stream, nullptr, 0)) != EC_OK) return r;
+  if (nd == 0) return EC_OK;
+  std::vector<int32_t> ch(nd);
+  if ((r = run_select(st, Em, nu0, kT, xi, u, dt, s, nullptr, ch.data(), false)) != EC_OK) return r;
+  // the chosen jumps: whole-voxel translations of the quantised centres (box,
+  // offsets and eigenstrain are unchanged), then the field of the new positions
   char* hp = nullptr;
-  if ((r = pin_begin(st->pin_jump, 2 * (size_t)nd * 8, &hp)) != EC_OK) return r;
-  std::memcpy(hp, Em, (size_t)nd * 8);
-  if (xi) std::memcpy(hp + (size_t)nd * 8, xi, (size_t)nd * 8);
-  HIPCHK(hipMemcpyAsync(st->jsel, hp, 2 * (size_t)nd * 8, hipMemcpyHostToDevice, s));
-  if ((r = pin_end(st->pin_jump, s)) != EC_OK) return r;
-  LAUNCH(st, s, PF_OTHER, 0,
-         launch_jump_select(st->jdE, nd, nj, st->jsel, nu0, kT, xi ? st->jsel + nd : nullptr,
-                            nu_out ? st->jnu : nullptr, choice_out ? st->jchoice : nullptr, s));
-  if (nu_out && (r = copy_out(nu_out, st->jnu, nu * 8, on_device != 0, s)) != EC_OK) return r;
-  if (choice_out) return copy_out(choice_out, st->jchoice, (size_t)nd * 4, on_device != 0, s);
+  if ((r = pin_begin(st->pin_tab, (size_t)nd * sizeof(DevDefect), &hp)) != EC_OK) return r;
+  DevDefect* h = (DevDefect*)hp;
+  const int n = st->n;
+  const int32_t Lq = QSUB * n;
+  for (int i = 0; i < nd; ++i) {
+    h[i] = st->hdefs[i];
+    if (ch[i] < 0) continue;
+    const int32_t* lam = jumps + ((size_t)i * njump + ch[i]) * 3;
+    for (int k = 0; k < 3; ++k) {
+      h[i].cq[k] = (int32_t)((((int64_t)h[i].cq[k] + (int64_t)lam[k] * QSUB) % Lq + Lq) % Lq);
+      h[i].lo[k] = ((h[i].lo[k] + lam[k]) % n + n) % n;
+    }
+  }
+  // the probe left the self terms and classes current, and a translation by
+  // whole voxels keeps every footprint's shape
+  if ((r = solve_table(st, h, nd, s, st->B_valid && st->classes_ok)) != EC_OK) return r;
+  if (choice_out) std::memcpy(choice_out, ch.data(), (size_t)nd * 4);
+  if (E_out) return ec_interaction_energies(st, stream, E_out, 0);
   return EC_OK;
 }
 

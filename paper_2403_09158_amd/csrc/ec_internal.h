@@ -280,15 +280,16 @@ hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts
 hipError_t launch_jump_energies(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids,
                                 const double* sig, int n, const int32_t* jumps, int nj, const double* S0,
                                 const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
-                                int64_t* wbeg, double* partial, double* t1, const double* B, double h3c, double* dE,
-                                hipStream_t s);
+                                int64_t* wbeg, double* partial, double* t1, const double* B, double h3c, double* xc,
+                                bool xc_valid, double* dE, hipStream_t s);
 // Dipole-tensor energies: Edip[i] = -h^3 c m_i E_i : (sigma - sigma_i) at the
 // voxel holding the defect centre (sig voxel-major; window as for the self terms).
 hipError_t launch_dipole(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, const double* sig,
                          int n, const double* K, const double* gcls, int D, double h3c, double* Edip, hipStream_t s);
 // Biased jump frequencies and the frequency-line choice (nu, choice may be null).
 hipError_t launch_jump_select(const double* dE, int ndef, int nj, const double* Em, double nu0, double kT,
-                              const double* xi, double* nu, int32_t* choice, hipStream_t s);
+                              const double* xi, const double* u, double dt, double* nu, int32_t* choice,
+                              hipStream_t s);
 // Eigenstrain direction class of a defect (index into the class windows, -1
 // for the generic path) and its scale s (E = s e).
 struct ClassTag {

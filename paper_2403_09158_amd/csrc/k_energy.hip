@@ -383,11 +383,14 @@ __global__ void k_self_finish(const int64_t* __restrict__ wbeg, const double* __
 __device__ __forceinline__ int wrap_axis(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
 // One workgroup per (defect, jump): S(lambda) with the footprint ids shifted,
-// t1 = -h^3 c E:(S(lambda) - S(0)); S(0) from the energies reduction.
+// t1 = -h^3 c E:(S(lambda) - S(0)); S(0) from the energies reduction.  With xc
+// (the stored cross part of each jump, h^3 c X(lambda) + B_i, unchanged while
+// the footprints only translate) also dE = t1 + xc.
 __global__ __launch_bounds__(RDT) void k_jump_sums(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
                                                    const int32_t* __restrict__ ids, const double* __restrict__ sig,
                                                    int n, const int32_t* __restrict__ jumps, int nj,
-                                                   const double* __restrict__ S0, double h3c, double* __restrict__ t1) {
+                                                   const double* __restrict__ S0, double h3c, double* __restrict__ t1,
+                                                   const double* __restrict__ xc, double* __restrict__ dE) {
   const int i = blockIdx.x / nj;
   const int u = blockIdx.x;
   const int lx = jumps[3 * u], ly = jumps[3 * u + 1], lz = jumps[3 * u + 2];
@@ -428,7 +431,9 @@ __global__ __launch_bounds__(RDT) void k_jump_sums(const DevDefect* __restrict__
       for (int w = 1; w < RDT / 64; ++w) neumaier_merge(ss, cc, ws[w][a], wc[w][a]);
       dot += ddot_w(a) * d.E[a] * ((ss + cc) - S0[6 * i + a]);
     }
-    t1[u] = -h3c * dot;
+    const double v = -h3c * dot;
+    t1[u] = v;
+    if (xc) dE[u] = v + xc[u];
   }
 }
 
@@ -598,32 +603,35 @@ __global__ __launch_bounds__(ST) void k_cross(const DevDefect* __restrict__ defs
 }
 
 // dE per (defect, jump): X = the item partials (of the jump itself or of its
-// opposite) added in a fixed order; the zero jump keeps only the S term.
+// opposite) added in a fixed order; the zero jump keeps only the S term.  The
+// cross part xc = h^3 c X + B_i is stored, so that dE = t1 + xc comes out the
+// same whether xc is fresh or reused.
 __global__ void k_cross_finish(const int64_t* __restrict__ wbeg, const double* __restrict__ partial,
                                const DevDefect* __restrict__ defs, int ndef, int nj, const int32_t* __restrict__ jumps,
                                const double* __restrict__ t1, const double* __restrict__ B, double h3c,
-                               double* __restrict__ dE) {
+                               double* __restrict__ xc, double* __restrict__ dE) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= ndef * nj) return;
   const int i = u / nj;
   const int src = cross_source(jumps, i, u % nj, nj);
-  if (src < 0) {
-    dE[u] = t1[u];
-    return;
+  double x = 0.0;
+  if (src >= 0) {
+    const int us = i * nj + src;
+    double s = 0.0, c = 0.0;
+    for (int64_t w = wbeg[us]; w < wbeg[us + 1]; ++w) neumaier(s, c, partial[w]);
+    const double scale = defs[i].cls >= 0 ? defs[i].s * defs[i].s : 1.0;
+    x = h3c * scale * (s + c) + B[i];
   }
-  const int us = i * nj + src;
-  double s = 0.0, c = 0.0;
-  for (int64_t w = wbeg[us]; w < wbeg[us + 1]; ++w) neumaier(s, c, partial[w]);
-  const double scale = defs[i].cls >= 0 ? defs[i].s * defs[i].s : 1.0;
-  dE[u] = t1[u] + h3c * scale * (s + c) + B[i];
+  xc[u] = x;
+  dE[u] = t1[u] + x;
 }
 
 // Biased frequencies nu = 1/2 nu0 exp(-(Em + dE / 2) / kT) of every jump of a
 // defect, and the jump whose frequency-line interval holds xi: the first j
 // with xi <= R_j / R_tot (R the running sum in jump order).
 __global__ void k_jump_select(const double* __restrict__ dE, int ndef, int nj, const double* __restrict__ Em,
-                              double nu0, double kT, const double* __restrict__ xi, double* __restrict__ nu,
-                              int32_t* __restrict__ choice) {
+                              double nu0, double kT, const double* __restrict__ xi, const double* __restrict__ u,
+                              double dt, double* __restrict__ nu, int32_t* __restrict__ choice) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ndef) return;
   double tot = 0.0;
@@ -633,6 +641,12 @@ __global__ void k_jump_select(const double* __restrict__ dE, int ndef, int nj, c
     tot += v;
   }
   if (!choice) return;
+  // Poisson gate of the time step: no event when u <= P(N = 0) = exp(-nu_i dt),
+  // nu_i the defect's nominal frequency
+  if (u && u[i] <= exp(-nu0 * exp(-Em[i] / kT) * dt)) {
+    choice[i] = -1;
+    return;
+  }
   double R = 0.0;
   int pick = nj - 1;
   for (int j = 0; j < nj; ++j) {
@@ -794,25 +808,32 @@ hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts
 hipError_t launch_jump_energies(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids,
                                 const double* sig, int n, const int32_t* jumps, int nj, const double* S0,
                                 const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
-                                int64_t* wbeg, double* partial, double* t1, const double* B, double h3c, double* dE,
-                                hipStream_t s) {
+                                int64_t* wbeg, double* partial, double* t1, const double* B, double h3c, double* xc,
+                                bool xc_valid, double* dE, hipStream_t s) {
   if (ndef == 0 || nj == 0) return hipSuccess;
   const int nu = ndef * nj;
-  hipLaunchKernelGGL(k_jump_sums, dim3(nu), dim3(RDT), 0, s, d, counts, ids, sig, n, jumps, nj, S0, h3c, t1);
+  if (xc_valid) {
+    hipLaunchKernelGGL(k_jump_sums, dim3(nu), dim3(RDT), 0, s, d, counts, ids, sig, n, jumps, nj, S0, h3c, t1,
+                       (const double*)xc, dE);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_jump_sums, dim3(nu), dim3(RDT), 0, s, d, counts, ids, sig, n, jumps, nj, S0, h3c, t1,
+                     (const double*)nullptr, (double*)nullptr);
   hipLaunchKernelGGL(k_cross_plan, dim3(1), dim3(PT), 0, s, counts, ndef, nj, jumps, wbeg, work, work_cap);
   const int grid = (int)std::min<int64_t>(work_cap, 4096);
   hipLaunchKernelGGL(k_cross, dim3(grid), dim3(ST), 0, s, d, counts, ids, n, K, gcls, D, jumps, nj, work, wbeg + nu,
                      work_cap, partial);
   hipLaunchKernelGGL(k_cross_finish, dim3((nu + 255) / 256), dim3(256), 0, s, wbeg, partial, d, ndef, nj, jumps, t1, B,
-                     h3c, dE);
+                     h3c, xc, dE);
   return hipGetLastError();
 }
 
 hipError_t launch_jump_select(const double* dE, int ndef, int nj, const double* Em, double nu0, double kT,
-                              const double* xi, double* nu, int32_t* choice, hipStream_t s) {
+                              const double* xi, const double* u, double dt, double* nu, int32_t* choice,
+                              hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_jump_select, dim3((ndef + 255) / 256), dim3(256), 0, s, dE, ndef, nj, Em, nu0, kT, xi, nu,
-                     choice);
+  hipLaunchKernelGGL(k_jump_select, dim3((ndef + 255) / 256), dim3(256), 0, s, dE, ndef, nj, Em, nu0, kT, xi, u, dt,
+                     nu, choice);
   return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ EXPORTS = (
     "ec_update_defect",
     "ec_jump_energies",
     "ec_jump_select",
+    "ec_okmc_step",
     "ec_dipole_energies",
     "ec_state_footprints",
     "ec_state_field",
@@ -104,6 +105,10 @@ def load() -> ctypes.CDLL:
         "ec_update_defect": (c_int, [vp, c_int32, vp, vp, vp, c_int32]),
         "ec_jump_energies": (c_int, [vp, vp, c_int32, vp, vp, c_int32]),
         "ec_jump_select": (c_int, [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, c_int32]),
+        "ec_okmc_step": (
+            c_int,
+            [vp, vp, c_int32, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp],
+        ),
         "ec_dipole_energies": (c_int, [vp, vp, vp, c_int32]),
         "ec_state_footprints": (c_int, [vp, i32p, i32p, c_int64, i64p]),
         "ec_state_field": (c_int, [vp, c_int32, dp]),
@@ -315,6 +320,32 @@ class State:
             )
         )
         return nu, choice
+
+    def okmc_step(self, jumps, Em, nu0: float, kT: float, u, xi, dt: float = 0.0, stream=None, energies=False):
+        """One OkMC time step: Poisson gate with ``u``, frequency-line choice
+        with ``xi`` (both (ndef,) in (0, 1]) among ``jumps`` (ndef, njump, 3),
+        the chosen jumps made and the field solved again; ``dt`` <= 0 takes
+        1 / max nominal frequency.  Returns the jump index per defect (-1: none)
+        and, with ``energies``, the energies after the step."""
+        nd = self.ndef
+        j = np.ascontiguousarray(jumps, dtype=np.int32)
+        if j.ndim != 3 or j.shape[0] != nd or j.shape[2] != 3:
+            raise ValueError(f"jumps must have shape (ndef={nd}, njump, 3), got {j.shape}")
+        Em = np.ascontiguousarray(np.broadcast_to(np.asarray(Em, dtype=np.float64), (nd,)))
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        x = np.ascontiguousarray(xi, dtype=np.float64)
+        if u.shape != (nd,) or x.shape != (nd,):
+            raise ValueError(f"u and xi must have shape ({nd},)")
+        choice = np.zeros(nd, dtype=np.int32)
+        E = np.zeros(nd) if energies else None
+        _check(
+            load().ec_okmc_step(
+                self.h, j.ctypes.data, j.shape[1], Em.ctypes.data, float(nu0), float(kT), float(dt), u.ctypes.data,
+                x.ctypes.data, _stream_handle(stream), choice.ctypes.data, None if E is None else E.ctypes.data,
+            )
+        )
+        self._jn = j.shape[1]
+        return (choice, E) if energies else choice
 
     def dipole_energies(self, stream=None, out=None) -> np.ndarray:
         """Dipole-tensor interaction energies (eV) of the current defects; host
