@@ -436,8 +436,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the many-replica serving workload")
     ap.add_argument("--no-512", action="store_true", help="skip the 512^3 / 20000-defect workload")
     ap.add_argument("--no-jumps", action="store_true", help="skip the jump-probe workload")
-    ap.add_argument("--jumps-only", action="store_true", help="run the jump-probe workload alone (profiling runs)")
+    ap.add_argument("--jumps-only", action="store_true", help="run the jump-probe, dipole and OkMC workloads alone")
     ap.add_argument("--okmc-only", action="store_true", help="run the OkMC-step workload alone (profiling runs)")
+    ap.add_argument("--probe-only", action="store_true", help="run the jump-probe workload alone (profiling runs)")
     ap.add_argument(
         "--calibrate-copy",
         action="store_true",
@@ -464,6 +465,9 @@ def main():
         b.copy_(a)  # reads and writes exactly 2^30 bytes each
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 1 << 30}), flush=True)
+        return
+    if args.probe_only:
+        print(json.dumps({"jump_probe": jump_probe_block()}), flush=True)
         return
     if args.okmc_only:
         print(json.dumps({"okmc": okmc_block()}), flush=True)
