@@ -43,8 +43,21 @@ def isotropic_stiffness(lam: float, mu: float) -> np.ndarray:
     return C
 
 
+def rotate_stiffness(C: np.ndarray, A) -> np.ndarray:
+    """C in the cell frame of a rotated crystal, C'_ijkl = A_ip A_jq A_kr A_ls C_pqrs,
+    where the rows of A are the cell axes as unit vectors in cube coordinates
+    (Sec. 5 places x, y, z along [111], [-1-12] and [1-10])."""
+    A = np.asarray(A, dtype=np.float64).reshape(3, 3)
+    return np.einsum("ip,jq,kr,ls,pqrs->ijkl", A, A, A, A, C)
+
+
 def stiffness_of(problem) -> np.ndarray:
-    return cubic_stiffness(problem.C11, problem.C12, problem.C44)
+    """The problem's stiffness in cell coordinates (rotated when it gives a frame)."""
+    C = cubic_stiffness(problem.C11, problem.C12, problem.C44)
+    frame = tuple(getattr(problem, "frame", ()) or ())
+    if frame and any(v != 0.0 for v in frame):
+        C = rotate_stiffness(C, frame)
+    return C
 
 
 def acoustic_tensor(C: np.ndarray, xi: np.ndarray) -> np.ndarray:

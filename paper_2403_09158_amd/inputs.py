@@ -74,6 +74,7 @@ class Problem:
     prec: int = 0  # 0 = FP64, 1 = FP32 storage
     bc: int = 0  # 0 = mean stress zero, 1 = mean strain zero
     nyq: int = 0  # 0 = paper-literal even-N Nyquist rule
+    frame: tuple = ()  # 9 numbers, rows = cell axes in cube coordinates; () = cube axes
 
     @property
     def h(self) -> float:
@@ -236,6 +237,19 @@ def serving_replicas(nrep: int = 64, prec: int = 1):
         prob = Problem(n, L, *CUBIC_FE, prec=prec)
         out.append((prob, mixed_population(rng, ndef, L, H_VOXEL)))
     return out
+
+
+# Crystal orientation of the paper's simulations (Sec. 5): cell x, y, z along
+# [111], [-1-12], [1-10] (rows: unit vectors in cube coordinates).
+FRAME_111 = tuple(
+    np.concatenate(
+        [
+            np.array([1.0, 1.0, 1.0]) / np.sqrt(3.0),
+            np.array([-1.0, -1.0, 2.0]) / np.sqrt(6.0),
+            np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0),
+        ]
+    ).tolist()
+)
 
 
 HOPS111 = np.array(
