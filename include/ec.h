@@ -75,10 +75,14 @@ typedef enum {
                       the all -n/2 and all +n/2 representatives of a Nyquist bin */
 } ec_nyquist;
 
-/* Periodic cubic cell of n^3 voxels and side L, cubic stiffness C11, C12, C44
- * with cube axes along x, y, z.  n must be one of
- * 8 16 24 32 48 64 96 128 160 240 256 512 (even, 2/3/5-smooth);
- * anything else gives EC_ERR_SIZE. */
+/* Periodic cubic cell of n^3 voxels and side L, cubic stiffness C11, C12, C44.
+ * frame: the crystal orientation, row-major 3x3 whose rows are the cell's x, y
+ * and z axes as unit vectors in cube coordinates (the simulations of Sec. 5
+ * take x = [111]/sqrt3, y = [-1-12]/sqrt6, z = [1-10]/sqrt2); all zeros for
+ * cube axes along x, y, z.  Rows must be orthonormal to 1e-9 with determinant
+ * +1 (EC_ERR_ARG otherwise).  Defects are given in cell coordinates either way.
+ * n must be one of 8 16 24 32 48 64 96 128 160 240 256 512 (even,
+ * 2/3/5-smooth); anything else gives EC_ERR_SIZE. */
 typedef struct {
   int32_t n;
   int32_t prec; /* ec_precision */
@@ -86,6 +90,7 @@ typedef struct {
   int32_t nyq;  /* ec_nyquist */
   double L;
   double C11, C12, C44;
+  double frame[9];
 } ec_problem;
 
 typedef enum { EC_LOOP = 0, EC_SPHERE = 1 } ec_kind;

@@ -10,6 +10,7 @@
 #include <atomic>
 #include <chrono>
 #include <climits>
+#include <cstddef>
 #include <cmath>
 #include <condition_variable>
 #include <cstdarg>
@@ -50,6 +51,7 @@ ec_status fail(ec_status s, const char* fmt, ...) {
 struct WinCache {
   int n = 0;
   double C11 = 0, C12 = 0, C44 = 0;
+  std::array<double, 9> frame{};  // all zeros: cube axes
   int bc = 0;
   int D = 0;
   double* K = nullptr;
@@ -232,6 +234,9 @@ struct ec_state {
   size_t gcls_bytes = 0;
   int gcls_D = -1, gcls_ncls = -1;
   const WinCache* win = nullptr;
+  std::array<double, 9> frame{};  // the problem's frame, all zeros for cube axes
+  std::array<double, FRAME_LEN> frmh{};  // host copy of its maps
+  double* frm = nullptr;          // its device form (FRAME_LEN doubles), null for cube axes
   // self-term work list (built on the device)
   SelfWork* work = nullptr;
   size_t work_cap = 0;
@@ -672,13 +677,32 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
 }
 
 // Window of the discrete kernel G for this problem: six FP64 impulse solves.
+// out = -C:m for the state's crystal (the cubic stiffness applied in the cube
+// frame when the crystal is rotated).
+void neg_C_dot(const ec_state* st, const double* m, double* out) {
+  double mc[6], t[6];
+  if (st->frm)
+    rot6(st->frmh.data(), m, mc);
+  else
+    std::copy(m, m + 6, mc);
+  const Cubic& C = st->C;
+  t[0] = -(C.C11 * mc[0] + C.C12 * (mc[1] + mc[2]));
+  t[1] = -(C.C11 * mc[1] + C.C12 * (mc[0] + mc[2]));
+  t[2] = -(C.C11 * mc[2] + C.C12 * (mc[0] + mc[1]));
+  for (int a = 3; a < 6; ++a) t[a] = -2.0 * C.C44 * mc[a];
+  if (st->frm)
+    rot6(st->frmh.data() + 36, t, out);
+  else
+    std::copy(t, t + 6, out);
+}
+
 ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
   ec_ctx* c = st->ctx;
   {
     std::lock_guard<std::mutex> lk(c->mu);
     for (auto& w : c->wins)
       if (w.n == st->n && w.C11 == st->C.C11 && w.C12 == st->C.C12 && w.C44 == st->C.C44 && w.bc == st->prob.bc &&
-          w.D >= Dneed) {
+          w.frame == st->frame && w.D >= Dneed) {
         st->win = &w;
         return EC_OK;
       }
@@ -717,10 +741,7 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
       for (int b = 0; b < 6; ++b) {
         double m[6] = {0, 0, 0, 0, 0, 0};
         m[b] = 1.0 / (double)st->n3;
-        add[b][0] = -(st->C.C11 * m[0] + st->C.C12 * (m[1] + m[2]));
-        add[b][1] = -(st->C.C11 * m[1] + st->C.C12 * (m[0] + m[2]));
-        add[b][2] = -(st->C.C11 * m[2] + st->C.C12 * (m[0] + m[1]));
-        for (int a = 3; a < 6; ++a) add[b][a] = -2.0 * st->C.C44 * m[a];
+        neg_C_dot(st, m, add[b]);
       }
     // six one-voxel "defects" with unit eigenstrain component b at voxel 0
     DevDefect unit[6];
@@ -753,7 +774,7 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
   std::lock_guard<std::mutex> lk(c->mu);
   for (auto it = c->wins.begin(); it != c->wins.end(); ++it)
     if (it->n == st->n && it->C11 == st->C.C11 && it->C12 == st->C.C12 && it->C44 == st->C.C44 &&
-        it->bc == st->prob.bc) {
+        it->bc == st->prob.bc && it->frame == st->frame) {
       // states still pointing at the old window refresh through ensure_window;
       // no kernel of any stream may still read it
       (void)hipDeviceSynchronize();
@@ -768,6 +789,7 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
   w.C12 = st->C.C12;
   w.C44 = st->C.C44;
   w.bc = st->prob.bc;
+  w.frame = st->frame;
   w.D = D;
   w.K = (double*)K;
   w.bytes = Kbytes;
@@ -1002,6 +1024,24 @@ void cyclic_cover(int lo1, int w1, int lo2, int w2, int n, int& lo, int& len) {
   len = n - best;
 }
 
+// Device form of a crystal frame (rows of A: the cell axes in cube
+// coordinates): the maps of the six tensor components cell -> cube
+// (T_c = A^T T A) and cube -> cell (T = A T_c A^T), then A itself.
+static_assert(sizeof(ec_problem) == 120 && offsetof(ec_problem, frame) == 48, "ec_problem layout of include/ec.h");
+
+void frame_maps(const double* A, double* out) {
+  static const int P[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+  auto a = [&](int i, int p) { return A[3 * i + p]; };
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) {
+      const int p = P[r][0], q = P[r][1], i = P[c][0], j = P[c][1];
+      out[6 * r + c] = a(i, p) * a(j, q) + (i != j ? a(j, p) * a(i, q) : 0.0);
+      const int ii = P[r][0], jj = P[r][1], pp = P[c][0], qq = P[c][1];
+      out[36 + 6 * r + c] = a(ii, pp) * a(jj, qq) + (pp != qq ? a(ii, qq) * a(jj, pp) : 0.0);
+    }
+  for (int k = 0; k < 9; ++k) out[72 + k] = A[k];
+}
+
 // Commits the quantised list h (ndef entries in the pinned staging buffer of
 // the device table, pin_begin already called on it) and solves: footprint
 // slots from the box volumes, the old eigenstrain out and the new one in, the
@@ -1149,7 +1189,32 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
   if (p->nyq != EC_NYQ_PAPER) return fail(EC_ERR_ARG, "unknown Nyquist rule");
   if (!(p->C11 - p->C12 > 0.0) || !(p->C11 + 2.0 * p->C12 > 0.0) || !(p->C44 > 0.0))
     return fail(EC_ERR_ARG, "stiffness is not positive definite");
+  std::array<double, FRAME_LEN> fr{};
+  bool rotated = false;
+  for (int k = 0; k < 9; ++k) {
+    if (!std::isfinite(p->frame[k])) return fail(EC_ERR_ARG, "frame is not finite");
+    rotated |= p->frame[k] != (k % 4 == 0 ? 1.0 : 0.0);
+  }
+  bool zero = true;
+  for (int k = 0; k < 9; ++k) zero &= p->frame[k] == 0.0;
+  if (zero) rotated = false;
+  if (rotated) {
+    const double* A = p->frame;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double d = A[3 * i] * A[3 * j] + A[3 * i + 1] * A[3 * j + 1] + A[3 * i + 2] * A[3 * j + 2];
+        if (std::fabs(d - (i == j ? 1.0 : 0.0)) > 1e-9) return fail(EC_ERR_ARG, "frame rows are not orthonormal");
+      }
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(det > 0.0)) return fail(EC_ERR_ARG, "frame is not a rotation (determinant %g)", det);
+    frame_maps(A, fr.data());
+  }
   ec_state* st = new ec_state;
+  if (rotated) {
+    std::copy(p->frame, p->frame + 9, st->frame.begin());
+    st->frmh = fr;
+  }
   st->ctx = c;
   st->prob = *p;
   st->n = p->n;
@@ -1157,7 +1222,7 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
   st->fp64 = p->prec == EC_FP64;
   st->g.n = p->n;
   st->g.P = spec_pitch(p->n, st->fp64);
-  st->C = Cubic{p->C11, p->C12, p->C44};
+  st->C = Cubic{p->C11, p->C12, p->C44, nullptr};
   const double h = p->L / p->n;
   st->h3c = h * h * h * GPA_NM3_EV;
   st->spec_bytes = (size_t)6 * p->n * p->n * st->g.P * (st->fp64 ? 16 : 8);
@@ -1169,6 +1234,7 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
   }
   void *sp = nullptr, *own = nullptr, *sg = nullptr, *ad = nullptr, *dirs = nullptr, *ue = nullptr, *uf = nullptr;
   void* tc = nullptr;
+  void* fm = nullptr;
   const size_t ob = (size_t)st->n3 * 4;
   ec_status r;
   auto undo = [&]() {
@@ -1180,11 +1246,13 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
     ledger_free(c, ue, 64);
     ledger_free(c, uf, 64);
     ledger_free(c, tc, 128);
+    ledger_free(c, fm, FRAME_LEN * 8);
   };
   if ((r = ledger_alloc(c, st->spec_bytes, &sp)) != EC_OK || (r = ledger_alloc(c, ob, &own)) != EC_OK ||
       (r = ledger_alloc(c, fb, &sg)) != EC_OK || (r = ledger_alloc(c, 256, &ad)) != EC_OK ||
       (r = ledger_alloc(c, MAXCLS * 48, &dirs)) != EC_OK || (r = ledger_alloc(c, 64, &ue)) != EC_OK ||
-      (r = ledger_alloc(c, 64, &uf)) != EC_OK || (r = ledger_alloc(c, 128, &tc)) != EC_OK) {
+      (r = ledger_alloc(c, 64, &uf)) != EC_OK || (r = ledger_alloc(c, 128, &tc)) != EC_OK ||
+      (rotated && (r = ledger_alloc(c, FRAME_LEN * 8, &fm)) != EC_OK)) {
     undo();
     delete st;
     return r;
@@ -1197,10 +1265,13 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
   st->updE = (double*)ue;
   st->updfix = (int64_t*)uf;
   st->tilectr = (uint32_t*)tc;
-  st->held = st->spec_bytes + fb + ob + 256 + MAXCLS * 48 + 128 + 128;
+  st->frm = (double*)fm;
+  st->C.frm = st->frm;
+  st->held = st->spec_bytes + fb + ob + 256 + MAXCLS * 48 + 128 + 128 + (rotated ? FRAME_LEN * 8 : 0);
   hipError_t e = launch_fill_i32(st->own, st->n3, -1, nullptr);
   if (e == hipSuccess) e = hipMemset(st->sig, 0, fb);
   if (e == hipSuccess) e = hipMemset(st->add6, 0, 256);
+  if (e == hipSuccess && rotated) e = hipMemcpy(st->frm, fr.data(), FRAME_LEN * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     undo();
@@ -1241,6 +1312,7 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->jjumps, st->jjumps_cap * 4);
   ledger_free(c, st->jdE, st->jdE_cap * 8);
   ledger_free(c, st->jt1, st->jt1_cap * 8);
+  ledger_free(c, st->frm, st->frm ? FRAME_LEN * 8 : 0);
   ledger_free(c, st->jxc, st->jxc_cap * 8);
   ledger_free(c, st->jpartial, st->jpartial_cap * 8);
   ledger_free(c, st->jsel, st->jsel_cap * 8);
@@ -1405,10 +1477,7 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
     double m[6];
     for (int a = 0; a < 6; ++a)
       m[a] = ((double)cnt_new * nd.E[a] - (double)st->hcnt[idx] * od.E[a]) / (double)st->n3;
-    dadd[0] = -(st->C.C11 * m[0] + st->C.C12 * (m[1] + m[2]));
-    dadd[1] = -(st->C.C11 * m[1] + st->C.C12 * (m[0] + m[2]));
-    dadd[2] = -(st->C.C11 * m[2] + st->C.C12 * (m[0] + m[1]));
-    for (int a = 3; a < 6; ++a) dadd[a] = -2.0 * st->C.C44 * m[a];
+    neg_C_dot(st, m, dadd);
   }
   // --- commit
   char* up = nullptr;  // [E 48][efix 48][dadd 48][count 8][record]

@@ -177,10 +177,39 @@ struct Cplx<double> {
   using T = double2;
 };
 
-// Cubic stiffness passed to kernels.
+// Cubic stiffness passed to kernels.  frm, when not null, points to the
+// frame of a rotated crystal in device memory (FRAME_LEN doubles): [0, 36) the
+// map of the six tensor components (xx yy zz yz xz xy) from the cell axes to
+// the cube axes, [36, 72) the map back, [72, 81) the matrix A whose rows are
+// the cell axes in cube coordinates (a cell vector v has cube components A^T v).
+constexpr int FRAME_LEN = 81;
 struct Cubic {
   double C11, C12, C44;
+  const double* frm = nullptr;
 };
+
+// out = M in for a 6x6 row-major M (tensor components); in and out distinct.
+template <typename V>
+__host__ __device__ inline void rot6(const double* M, const V* in, V* out);
+template <>
+__host__ __device__ inline void rot6<double>(const double* M, const double* in, double* out) {
+  for (int r = 0; r < 6; ++r) {
+    double v = 0.0;
+    for (int c = 0; c < 6; ++c) v += M[6 * r + c] * in[c];
+    out[r] = v;
+  }
+}
+template <>
+__host__ __device__ inline void rot6<double2>(const double* M, const double2* in, double2* out) {
+  for (int r = 0; r < 6; ++r) {
+    double2 v = make_double2(0.0, 0.0);
+    for (int c = 0; c < 6; ++c) {
+      v.x += M[6 * r + c] * in[c].x;
+      v.y += M[6 * r + c] * in[c].y;
+    }
+    out[r] = v;
+  }
+}
 
 // Profiling families (see ec_profile_read).
 enum ProfFam { PF_RASTER = 0, PF_XF = 1, PF_Y = 2, PF_Z = 3, PF_XI = 4, PF_REDUCE = 5, PF_SELF = 6, PF_OTHER = 7 };

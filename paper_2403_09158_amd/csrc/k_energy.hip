@@ -716,7 +716,8 @@ __global__ __launch_bounds__(RDT) void k_dipole(const DevDefect* __restrict__ de
 }
 
 // Dense component-major outputs [6][n^3] from the voxel-major sigma: which
-// 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic compliance), 2 -> eps*
+// 0 -> sigma, 1 -> eps = C^-1:sigma + eps* (cubic compliance, in the cube
+// frame for a rotated crystal), 2 -> eps*
 // (owner-list gather).
 template <typename OT>
 __global__ void k_sig_to_out(const double* __restrict__ sig, const int32_t* __restrict__ own,
@@ -743,11 +744,19 @@ __global__ void k_sig_to_out(const double* __restrict__ sig, const int32_t* __re
   }
   const double den = (C.C11 - C.C12) * (C.C11 + 2.0 * C.C12);
   const double S11 = (C.C11 + C.C12) / den, S12 = -C.C12 / den, S44h = 0.5 / C.C44;
-  double e[6];
-  e[0] = S11 * s[0] + S12 * (s[1] + s[2]);
-  e[1] = S11 * s[1] + S12 * (s[0] + s[2]);
-  e[2] = S11 * s[2] + S12 * (s[0] + s[1]);
-  for (int a = 3; a < 6; ++a) e[a] = S44h * s[a];
+  double sc[6], ec[6], e[6];
+  if (C.frm)
+    rot6(C.frm, s, sc);  // the compliance applied in the cube frame
+  else
+    for (int a = 0; a < 6; ++a) sc[a] = s[a];
+  ec[0] = S11 * sc[0] + S12 * (sc[1] + sc[2]);
+  ec[1] = S11 * sc[1] + S12 * (sc[0] + sc[2]);
+  ec[2] = S11 * sc[2] + S12 * (sc[0] + sc[1]);
+  for (int a = 3; a < 6; ++a) ec[a] = S44h * sc[a];
+  if (C.frm)
+    rot6(C.frm + 36, ec, e);
+  else
+    for (int a = 0; a < 6; ++a) e[a] = ec[a];
 #pragma unroll
   for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)(e[a] + es[a]);
 }

@@ -126,6 +126,58 @@ __device__ __forceinline__ void green_bin(double2* e, int kx, int ky, int kz, in
   for (int c = 3; c < 6; ++c) e[c] = make_double2(c44x2 * eps[c].x - tau[c].x, c44x2 * eps[c].y - tau[c].y);
 }
 
+// Rotated crystal (C.frm set): the cubic operator applied in the cube frame,
+// eps*_hat and the frequency labels rotated in and sigma_hat rotated back, so
+// that the cell-frame operator is built from C' = A^T-rotated C without
+// forming its 21 constants.
+__device__ __forceinline__ void green_bin_rot(double2* e, int kx, int ky, int kz, int n, const Cubic& C) {
+  if (kx == 0 && ky == 0 && kz == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double* F = C.frm;
+  const double* A = F + 72;
+  double2 ec[6];
+  rot6(F, e, ec);
+  double2 tau[6];
+  const double c44x2 = 2.0 * C.C44;
+  tau[0].x = C.C11 * ec[0].x + C.C12 * (ec[1].x + ec[2].x);
+  tau[0].y = C.C11 * ec[0].y + C.C12 * (ec[1].y + ec[2].y);
+  tau[1].x = C.C11 * ec[1].x + C.C12 * (ec[0].x + ec[2].x);
+  tau[1].y = C.C11 * ec[1].y + C.C12 * (ec[0].y + ec[2].y);
+  tau[2].x = C.C11 * ec[2].x + C.C12 * (ec[0].x + ec[1].x);
+  tau[2].y = C.C11 * ec[2].y + C.C12 * (ec[0].y + ec[1].y);
+#pragma unroll
+  for (int c = 3; c < 6; ++c) tau[c] = make_double2(c44x2 * ec[c].x, c44x2 * ec[c].y);
+  double2 eps[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) eps[c] = make_double2(0.0, 0.0);
+  const int h = n / 2;
+  const bool nx = kx == h, ny = ky == h, nz = kz == h;
+  const double lx = kx, ly = ky < h ? ky : ky - n, lz = kz < h ? kz : kz - n;
+  auto acc = [&](double x, double y, double z, double wgt) {
+    acc_eps(A[0] * x + A[3] * y + A[6] * z, A[1] * x + A[4] * y + A[7] * z, A[2] * x + A[5] * y + A[8] * z, C, tau,
+            eps, wgt);
+  };
+  if (!(nx || ny || nz)) {
+    acc(lx, ly, lz, 1.0);
+  } else {
+    acc(nx ? -h : lx, ny ? -h : ly, nz ? -h : lz, 0.5);
+    acc(nx ? h : lx, ny ? h : ly, nz ? h : lz, 0.5);
+  }
+  double2 sc[6];
+  sc[0].x = C.C11 * eps[0].x + C.C12 * (eps[1].x + eps[2].x) - tau[0].x;
+  sc[0].y = C.C11 * eps[0].y + C.C12 * (eps[1].y + eps[2].y) - tau[0].y;
+  sc[1].x = C.C11 * eps[1].x + C.C12 * (eps[0].x + eps[2].x) - tau[1].x;
+  sc[1].y = C.C11 * eps[1].y + C.C12 * (eps[0].y + eps[2].y) - tau[1].y;
+  sc[2].x = C.C11 * eps[2].x + C.C12 * (eps[0].x + eps[1].x) - tau[2].x;
+  sc[2].y = C.C11 * eps[2].y + C.C12 * (eps[0].y + eps[1].y) - tau[2].y;
+#pragma unroll
+  for (int c = 3; c < 6; ++c) sc[c] = make_double2(c44x2 * eps[c].x - tau[c].x, c44x2 * eps[c].y - tau[c].y);
+  rot6(F + 36, sc, e);
+}
+
 // ----------------------------------------------------------------- x forward (R2C)
 
 // x forward pass with a two-stage plan of equal radices: each thread reads
@@ -545,7 +597,7 @@ constexpr int zg_threads() {
 // three, so stride-R stores of the first stages spread over all banks.
 __device__ __forceinline__ int zg_swz(int i) { return (i & ~7) | ((i ^ (i >> 3)) & 7); }
 
-template <int N, typename S, bool PRUNE>
+template <int N, typename S, bool PRUNE, bool ROT>
 __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S>::T* __restrict__ spec, Cubic C,
                                                                 Prune pr, const double2* __restrict__ twg,
                                                                 uint32_t* __restrict__ ctr) {
@@ -649,7 +701,10 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
       double2 e[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) e[c] = from_lds(bw * 6 + c, kz);
-      green_bin(e, bkx, ky, kz, N, C);
+      if constexpr (ROT)
+        green_bin_rot(e, bkx, ky, kz, N, C);
+      else
+        green_bin(e, bkx, ky, kz, N, C);
 #pragma unroll
       for (int c = 0; c < 6; ++c) to_lds(bw * 6 + c, kz, e[c]);
     }
@@ -678,7 +733,10 @@ __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__
   double2 e[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) e[c] = ld2(bin + c);
-  green_bin(e, kx, ky, kz, n, C);
+  if (C.frm)
+    green_bin_rot(e, kx, ky, kz, n, C);
+  else
+    green_bin(e, kx, ky, kz, n, C);
 #pragma unroll
   for (int c = 0; c < 6; ++c) st2(bin + c, e[c]);
 }
@@ -899,7 +957,8 @@ hipError_t go_zgreen(void* spec, SpecGeom g, Cubic C, Prune pr, const double2* t
   using C2 = typename Cplx<S>::T;
   const bool prune = pr.in_len < N;
   if (g.P != spec_pitch(N, sizeof(S) == 8)) return hipErrorInvalidValue;
-  auto* k = prune ? k_zgreen<N, S, true> : k_zgreen<N, S, false>;
+  auto* k = C.frm ? (prune ? k_zgreen<N, S, true, true> : k_zgreen<N, S, false, true>)
+                  : (prune ? k_zgreen<N, S, true, false> : k_zgreen<N, S, false, false>);
   const int grid = tile_grid(k, T, NT, sizeof(S) == 4);
   if (grid < 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, C, pr, tw, ctr);

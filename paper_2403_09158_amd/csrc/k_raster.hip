@@ -259,10 +259,19 @@ __global__ __launch_bounds__(MT) void k_mean_stress(const DevDefect* __restrict_
     }
     m[a] = (ss + cc) * inv_n3;
   }
-  add6[0] = -(C.C11 * m[0] + C.C12 * (m[1] + m[2]));
-  add6[1] = -(C.C11 * m[1] + C.C12 * (m[0] + m[2]));
-  add6[2] = -(C.C11 * m[2] + C.C12 * (m[0] + m[1]));
-  for (int a = 3; a < 6; ++a) add6[a] = -2.0 * C.C44 * m[a];
+  double mc[6], t[6];
+  if (C.frm)
+    rot6(C.frm, m, mc);  // the mean eigenstrain in the cube frame
+  else
+    for (int a = 0; a < 6; ++a) mc[a] = m[a];
+  t[0] = -(C.C11 * mc[0] + C.C12 * (mc[1] + mc[2]));
+  t[1] = -(C.C11 * mc[1] + C.C12 * (mc[0] + mc[2]));
+  t[2] = -(C.C11 * mc[2] + C.C12 * (mc[0] + mc[1]));
+  for (int a = 3; a < 6; ++a) t[a] = -2.0 * C.C44 * mc[a];
+  if (C.frm)
+    rot6(C.frm + 36, t, add6);
+  else
+    for (int a = 0; a < 6; ++a) add6[a] = t[a];
 }
 
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {

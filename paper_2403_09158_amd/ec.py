@@ -68,6 +68,7 @@ class CProblem(ctypes.Structure):
         ("C11", c_double),
         ("C12", c_double),
         ("C44", c_double),
+        ("frame", c_double * 9),
     ]
 
 
@@ -214,7 +215,13 @@ class State:
     def __init__(self, ctx: Context, problem: Problem):
         self.ctx = ctx
         self.problem = problem
-        p = CProblem(problem.n, problem.prec, problem.bc, problem.nyq, problem.L, problem.C11, problem.C12, problem.C44)
+        fr = tuple(getattr(problem, "frame", ()) or ())
+        if fr and len(fr) != 9:
+            raise ValueError("frame must hold 9 numbers")
+        p = CProblem(
+            problem.n, problem.prec, problem.bc, problem.nyq, problem.L, problem.C11, problem.C12, problem.C44,
+            (c_double * 9)(*(fr or (0.0,) * 9)),
+        )
         h = c_void_p()
         _check(load().ec_state_create(ctx.h, ctypes.byref(p), ctypes.byref(h)))
         self.h = h

@@ -34,4 +34,5 @@ def test_defect_record_layout():
     assert DEFECT_DTYPE.itemsize == 104
     assert DEFECT_DTYPE.fields["c"][1] == 8
     assert DEFECT_DTYPE.fields["eig_v"][1] == 96
-    assert ctypes.sizeof(ec.CProblem) == 48
+    assert ctypes.sizeof(ec.CProblem) == 120
+    assert ec.CProblem.frame.offset == 48

@@ -1,0 +1,122 @@
+"""Rotated crystal on the GPU (ec_problem.frame; the cell axes of Sec. 5 along
+[111], [-1-12], [1-10]): fields, strains and energies against the oracle for
+both mean conditions and precisions, whole-voxel hops through the incremental
+update, the explicit identity frame, states of different frames sharing one
+context, and the frame checks.
+
+Tolerances: fields rel L2 1e-12 (FP64) / 1e-5 (FP32); energies 1e-10 of the
+largest (FP64) / max(1e-4 |E_i|, 1e-5 eV) per defect (FP32)."""
+import numpy as np
+import pytest
+
+from helpers import energy_ok_fp32, energy_ok_fp64, rel_l2, to6
+from oracle import elastic, energy, raster, solve
+from paper_2403_09158_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2403_09158_amd import ec
+
+    return ec.Context()
+
+
+def _cell(n=32, prec=0, bc=0, frame=inputs.FRAME_111):
+    h = inputs.H_VOXEL
+    prob = inputs.Problem(n, n * h, *inputs.CUBIC_FE, prec=prec, bc=bc, frame=frame)
+    bx = 0.5 * inputs.A_FE * np.sqrt(3.0) * np.array([1.0, 0.0, 0.0])
+    bz = 0.5 * inputs.A_FE * np.array([0.0, 0.0, 1.0])
+    d = np.concatenate(
+        [
+            inputs.loop(np.array([8.5, 10.5, 12.5]) * h, 3.2 * h, bx, bx),
+            inputs.loop(np.array([21.2, 19.7, 18.4]) * h, 2.8 * h, bz, np.array([0.0, 0.0, 1.0])),
+            inputs.loop(np.array([30.6, 4.1, 25.0]) * h, 2.1 * h, -bx, bx),
+            inputs.sphere(np.array([24.5, 3.5, 8.5]) * h, 1.9 * h, 0.012),
+        ]
+    )
+    return prob, d
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rotated_fields_and_energies(ctx, prec, bc):
+    from paper_2403_09158_amd import ec
+
+    prob, d = _cell(prec=prec, bc=bc)
+    fps, Es = raster.rasterise(prob, d)
+    es = raster.eigenstrain_field(prob.n, fps, Es)
+    eps_o, sig_o, _ = solve.solve_field(elastic.stiffness_of(prob), prob.L, es, prob.bc)
+    Eo = energy.energies_fast(prob, d)
+    st = ec.State(ctx, prob)
+    st.solve(d)
+    E = st.energies()
+    sig, eps = st.field("sigma"), st.field("eps")
+    if prec == 0:
+        assert rel_l2(sig, to6(sig_o)) < 1e-12
+        assert rel_l2(eps, to6(eps_o)) < 1e-12
+        assert energy_ok_fp64(E, Eo)
+    else:
+        assert rel_l2(sig, to6(sig_o)) < 1e-5
+        assert rel_l2(eps, to6(eps_o)) < 1e-5
+        assert np.all(energy_ok_fp32(E, Eo))
+    st.close()
+
+
+def test_rotated_hops_through_the_update(ctx):
+    from paper_2403_09158_amd import ec
+
+    prob, d = _cell()
+    st = ec.State(ctx, prob)
+    st.solve(d)
+    cur = d.copy()
+    for i, lam in ((0, (1, 0, 0)), (1, (0, -1, 1)), (3, (-1, 1, 0))):
+        cur[i]["c"] = cur[i]["c"] + np.asarray(lam, dtype=np.float64) * prob.h
+        E = st.update(i, cur[i])
+    assert energy_ok_fp64(E, energy.energies_fast(prob, cur))
+    st.close()
+
+
+def test_identity_frame_equals_cube_axes(ctx):
+    from paper_2403_09158_amd import ec
+
+    p0, d = _cell(frame=())
+    p1, _ = _cell(frame=(1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0))
+    a, b = ec.State(ctx, p0), ec.State(ctx, p1)
+    a.solve(d)
+    b.solve(d)
+    assert np.array_equal(a.energies(), b.energies())
+    a.close()
+    b.close()
+
+
+def test_frames_share_a_context(ctx):
+    """Two states of the same n, C and mean condition but different frames
+    keep separate kernel windows."""
+    from paper_2403_09158_amd import ec
+
+    p0, d = _cell(frame=())
+    p1, _ = _cell()
+    a, b = ec.State(ctx, p0), ec.State(ctx, p1)
+    a.solve(d)
+    b.solve(d)
+    assert energy_ok_fp64(a.energies(), energy.energies_fast(p0, d))
+    assert energy_ok_fp64(b.energies(), energy.energies_fast(p1, d))
+    a.close()
+    b.close()
+
+
+def test_frame_checks(ctx):
+    from paper_2403_09158_amd import ec
+
+    bad = [
+        (1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, -1.0),  # a reflection
+        (1.0, 0.1, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0),  # not orthonormal
+        (np.nan, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0),
+    ]
+    for fr in bad:
+        prob, _ = _cell(frame=fr)
+        with pytest.raises(ec.EcError) as ei:
+            ec.State(ctx, prob)
+        assert ei.value.status == ec.EC_ERR_ARG
