@@ -222,6 +222,30 @@ def mixed_512_block(steps=3):
     return out
 
 
+def frame_block(steps=10, warmup=3):
+    """mixed_256 with the crystal in the orientation of the paper's simulations
+    (cell x, y, z along [111], [-1-12], [1-10]): solve + energies per step in
+    FP32 and FP64, per-pass times, and the FP32 energy error against FP64."""
+    from paper_2403_09158_amd import ec, inputs
+
+    prob, defs = inputs.mixed_256(prec=1)
+    prob = prob.with_(frame=inputs.FRAME_111)
+    ctx = ec.Context(0)
+    out = {
+        "workload": "mixed_256 (256^3, 2000 defects) in a crystal rotated to cell axes [111], [-1-12], [1-10]: "
+        "the Green step applied in the cube frame"
+    }
+    E = {}
+    for prec, name in ((1, "fp32"), (0, "fp64")):
+        st = ec.State(ctx, prob.with_(prec=prec))
+        dt, E[prec], prof = timed_steps(st, defs, steps, warmup, True)
+        out[name] = {"ms_per_step": round(dt / steps * 1e3, 4), "per_family": family_table(prof)}
+        st.close()
+    out["fp32_vs_fp64"] = energy_errors(E[1], E[0])
+    ctx.close()
+    return out
+
+
 def jump_probe_block(steps=10):
     """Jump probes on mixed_256 (2000 defects, two glide jumps each): energy
     changes of all candidate jumps, biased frequencies and the frequency-line
@@ -439,6 +463,8 @@ def main():
     ap.add_argument("--jumps-only", action="store_true", help="run the jump-probe, dipole and OkMC workloads alone")
     ap.add_argument("--okmc-only", action="store_true", help="run the OkMC-step workload alone (profiling runs)")
     ap.add_argument("--probe-only", action="store_true", help="run the jump-probe workload alone (profiling runs)")
+    ap.add_argument("--no-frame", action="store_true", help="skip the rotated-crystal workload")
+    ap.add_argument("--frame-only", action="store_true", help="run the rotated-crystal workload alone")
     ap.add_argument(
         "--calibrate-copy",
         action="store_true",
@@ -465,6 +491,9 @@ def main():
         b.copy_(a)  # reads and writes exactly 2^30 bytes each
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 1 << 30}), flush=True)
+        return
+    if args.frame_only:
+        print(json.dumps({"frame_111": frame_block()}), flush=True)
         return
     if args.probe_only:
         print(json.dumps({"jump_probe": jump_probe_block()}), flush=True)
@@ -570,6 +599,8 @@ def main():
         line["jump_probe"] = jump_probe_block()
         line["dipole"] = dipole_block()
         line["okmc"] = okmc_block()
+    if not args.no_frame:
+        line["frame_111"] = frame_block()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob64, defs)
     print(json.dumps(line), flush=True)
