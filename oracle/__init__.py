@@ -26,6 +26,9 @@ elastic interactions in OkMC" (arXiv 2403.09158):
                  energies of the moved list.
 * ``dipole``   - the dipole-tensor approximation of the interaction energy
                  (Sec. 2.1).
+* ``dislocation`` - straight dislocation lines by field dislocation mechanics
+                 (Sec. 3.1): Nye tensor, incompatible plastic distortion, the
+                 Green solve of its symmetric part.
 
 Everything is float64 / complex128 and uses full 3x3 and 3x3x3x3 tensors (no
 Voigt shortcuts).  Readings of garbled or silent passages are stated in each
