@@ -212,6 +212,31 @@ EC_API ec_status ec_okmc_step(ec_state* st, const int32_t* jumps, int32_t njump,
                               double kT, double dt, const double* u, const double* xi, void* hip_stream,
                               int32_t* choice_out, double* E_out);
 
+/* ---- dislocation lines (Sec. 3.1, field dislocation mechanics) -------------- */
+
+/* An infinite straight dislocation line along a cell axis (56 bytes): a point
+ * p on it (nm, cell coordinates), the axis (0 = x, 1 = y, 2 = z), its sense
+ * (+1 or -1 along the axis) and its Burgers vector b (nm, cell coordinates). */
+typedef struct {
+  double p[3];
+  int32_t axis;
+  int32_t sense;
+  double b[3];
+} ec_line;
+
+/* Set the state's dislocation lines (nlines in [0, 64]; 0 removes them).  The
+ * Burgers vector density of each one-voxel subsegment is spread to the four
+ * grid points around the line (the eight around the subsegment midpoint, which
+ * lies on a voxel-centre level); the Nye tensor alpha = b (x) t rho gives the
+ * incompatible plastic distortion U_hat_ij = -i xi_k / xi^2 e_jkl alpha_hat_il
+ * (xi != 0; straight lines have no compatible part), and sym(U) is solved as an
+ * eigenstrain with the state's stiffness and frame.  The lines' stress is kept
+ * as a background added to the resident stress of this and every later solve,
+ * so energies, jump probes, dipole energies and OkMC steps include each
+ * defect's interaction with the lines.  Lines must have |b| > 0, finite values,
+ * axis in {0, 1, 2} and sense +-1 (EC_ERR_ARG otherwise). */
+EC_API ec_status ec_set_dislocations(ec_state* st, const ec_line* lines, int32_t nlines, void* hip_stream);
+
 /* ---- dipole-tensor approximation (Sec. 2.1) --------------------------------- */
 
 /* Interaction energy of every defect in the dipole approximation (eV): the

@@ -236,6 +236,15 @@ struct ec_state {
   const WinCache* win = nullptr;
   std::array<double, 9> frame{};  // the problem's frame, all zeros for cube axes
   std::array<double, FRAME_LEN> frmh{};  // host copy of its maps
+  // dislocation lines: stress planes per axis ([3][n^2][6]) added to every
+  // solve's stress, the axes present, and the scratch of their computation
+  double* bg = nullptr;
+  size_t bg_cap = 0;
+  int bg_mask = 0;
+  double2* bgspec = nullptr;
+  size_t bgspec_cap = 0;
+  DevLine* dlines = nullptr;
+  size_t dlines_cap = 0;
   double* frm = nullptr;          // its device form (FRAME_LEN doubles), null for cube axes
   // self-term work list (built on the device)
   SelfWork* work = nullptr;
@@ -1028,6 +1037,8 @@ void cyclic_cover(int lo1, int w1, int lo2, int w2, int n, int& lo, int& len) {
 // coordinates): the maps of the six tensor components cell -> cube
 // (T_c = A^T T A) and cube -> cell (T = A T_c A^T), then A itself.
 static_assert(sizeof(ec_problem) == 120 && offsetof(ec_problem, frame) == 48, "ec_problem layout of include/ec.h");
+static_assert(sizeof(ec_line) == 56 && offsetof(ec_line, axis) == 24 && offsetof(ec_line, b) == 32,
+              "ec_line layout of include/ec.h");
 
 void frame_maps(const double* A, double* out) {
   static const int P[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
@@ -1104,6 +1115,7 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
   };
   r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6, st->tilectr, beside);
   if (r != EC_OK) return r;
+  if (st->bg_mask) LAUNCH(st, s, PF_OTHER, 0, launch_bg_add(st->sig, st->bg, st->bg_mask, st->n, 1.0, s));
   st->solved = true;
   return EC_OK;
 }
@@ -1314,6 +1326,9 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->jt1, st->jt1_cap * 8);
   ledger_free(c, st->frm, st->frm ? FRAME_LEN * 8 : 0);
   ledger_free(c, st->jxc, st->jxc_cap * 8);
+  ledger_free(c, st->bg, st->bg_cap * 8);
+  ledger_free(c, st->bgspec, st->bgspec_cap * 16);
+  ledger_free(c, st->dlines, st->dlines_cap * sizeof(DevLine));
   ledger_free(c, st->jpartial, st->jpartial_cap * 8);
   ledger_free(c, st->jsel, st->jsel_cap * 8);
   ledger_free(c, st->jnu, st->jnu_cap * 8);
@@ -1762,6 +1777,60 @@ ec_status ec_okmc_step(ec_state* st, const int32_t* jumps, int32_t njump, const 
 }
 
 // ---------------------------------------------------------------- dipole energies
+
+ec_status ec_set_dislocations(ec_state* st, const ec_line* lines, int32_t nlines, void* stream) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  if (nlines < 0 || nlines > 64) return fail(EC_ERR_ARG, "nlines %d outside [0, 64]", nlines);
+  if (nlines > 0 && !lines) return fail(EC_ERR_ARG, "lines is NULL");
+  const int n = st->n;
+  const double h = st->prob.L / n;
+  std::vector<DevLine> by[3];
+  for (int i = 0; i < nlines; ++i) {
+    const ec_line& l = lines[i];
+    bool fin = true;
+    for (int k = 0; k < 3; ++k) fin &= std::isfinite(l.p[k]) && std::isfinite(l.b[k]);
+    if (!fin) return fail(EC_ERR_ARG, "line %d: non-finite value", i);
+    if (l.axis < 0 || l.axis > 2) return fail(EC_ERR_ARG, "line %d: axis %d not in {0, 1, 2}", i, l.axis);
+    if (l.sense != 1 && l.sense != -1) return fail(EC_ERR_ARG, "line %d: sense %d not +-1", i, l.sense);
+    if (!(l.b[0] * l.b[0] + l.b[1] * l.b[1] + l.b[2] * l.b[2] > 0.0))
+      return fail(EC_ERR_ARG, "line %d: zero Burgers vector", i);
+    const int a1 = l.axis == 0 ? 1 : 0, a2 = l.axis == 2 ? 1 : 2;
+    DevLine d{};
+    d.u1 = l.p[a1] / h - 0.5;
+    d.u2 = l.p[a2] / h - 0.5;
+    if (!(std::fabs(d.u1) < 1e9 && std::fabs(d.u2) < 1e9)) return fail(EC_ERR_ARG, "line %d: position too far", i);
+    for (int k = 0; k < 3; ++k) {
+      d.b[k] = l.b[k];
+      d.t[k] = k == l.axis ? (double)l.sense : 0.0;
+    }
+    by[l.axis].push_back(d);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  ec_status r;
+  const size_t nn = (size_t)n * n;
+  if ((r = st_grow(st, &st->bg, &st->bg_cap, 3 * nn * 6, true, s)) != EC_OK ||
+      (r = st_grow(st, &st->bgspec, &st->bgspec_cap, 12 * nn)) != EC_OK ||
+      (r = st_grow(st, &st->dlines, &st->dlines_cap, 64)) != EC_OK)
+    return r;
+  if ((r = join_self(st, s)) != EC_OK) return r;
+  // take the old lines' stress out of the resident field, put the new one in
+  if (st->solved && st->bg_mask)
+    LAUNCH(st, s, PF_OTHER, 0, launch_bg_add(st->sig, st->bg, st->bg_mask, n, -1.0, s));
+  int mask = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (by[a].empty()) continue;
+    HIPCHK(hipMemcpyAsync(st->dlines, by[a].data(), by[a].size() * sizeof(DevLine), hipMemcpyHostToDevice, s));
+    LAUNCH(st, s, PF_OTHER, 0,
+           launch_disl_plane(st->dlines, (int)by[a].size(), a, n, st->prob.L, st->C, st->bgspec,
+                             st->bgspec + 6 * nn, st->bg + (size_t)a * nn * 6, s));
+    HIPCHK(hipStreamSynchronize(s));  // the line table is pageable host memory reused per axis
+    mask |= 1 << a;
+  }
+  st->bg_mask = mask;
+  if (st->solved && mask) LAUNCH(st, s, PF_OTHER, 0, launch_bg_add(st->sig, st->bg, mask, n, 1.0, s));
+  st->jdE_ok = false;
+  return EC_OK;
+}
 
 ec_status ec_dipole_energies(ec_state* st, void* stream, double* E_out, int32_t on_device) {
   if (!st) return fail(EC_ERR_ARG, "state is NULL");

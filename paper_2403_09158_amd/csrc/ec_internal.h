@@ -211,6 +211,15 @@ __host__ __device__ inline void rot6<double2>(const double* M, const double2* in
   }
 }
 
+// A straight dislocation line along a cell axis: (u1, u2) its position in grid
+// index units (voxel centres at integers) along the other two axes in
+// increasing order, b its Burgers vector (nm), t its unit direction.
+struct DevLine {
+  double u1, u2;
+  double b[3];
+  double t[3];
+};
+
 // Profiling families (see ec_profile_read).
 enum ProfFam { PF_RASTER = 0, PF_XF = 1, PF_Y = 2, PF_Z = 3, PF_XI = 4, PF_REDUCE = 5, PF_SELF = 6, PF_OTHER = 7 };
 
@@ -265,6 +274,16 @@ hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, const int3
 // ctr: eight zeroed tile counters for this launch, or nullptr
 hipError_t launch_pencil(bool fp64, bool inv, int axis, void* spec, SpecGeom g, Prune pr, const double2* tw,
                          uint32_t* ctr, hipStream_t s);
+// Stress of straight dislocation lines along cell axis `axis` (Sec. 3.1, field
+// dislocation mechanics): the spectrum on the plane k_axis = 0 (Nye tensor of
+// the spread lines, incompatible plastic distortion, Green step; spec and tmp
+// hold 6 n^2 complex values), then its inverse 2-D transform into plane
+// ([n^2][6] FP64, index i2 * n + i1 over the other two axes).
+hipError_t launch_disl_plane(const DevLine* lines, int nl, int axis, int n, double L, Cubic C, double2* spec,
+                             double2* tmp, double* plane, hipStream_t s);
+// sig (voxel-major [n^3][6]) += sgn * the planes of the axes in mask
+// (planes: three [n^2][6] blocks).
+hipError_t launch_bg_add(double* sig, const double* planes, int mask, int n, double sgn, hipStream_t s);
 hipError_t launch_green(bool fp64, void* spec, SpecGeom g, Cubic C, hipStream_t s);
 hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, uint32_t* ctr,
                           hipStream_t s);

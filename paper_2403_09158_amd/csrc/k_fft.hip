@@ -991,4 +991,162 @@ hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig
   return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------ dislocation lines (Sec. 3.1)
+//
+// A straight line along cell axis a is uniform along a, so its Nye tensor,
+// plastic distortion and stress live on the plane k_a = 0 of the spectrum.
+// Per bin (k1, k2) over the other two axes (a1 < a2): rho_hat of each spread
+// line (bilinear weights over the four grid points around it, density 1/h^2),
+// the distortion U_hat_ij = -i xi_k / xi^2 e_jkl b_i t_l rho_hat (Nyquist bins:
+// the mean over the all -n/2 and all +n/2 representatives, the real part of the
+// centred solution), eps*_hat = sym(U_hat) summed over the lines, then the Green
+// step of the bin (the operator is even in xi, so a bin past n/2 along x uses its
+// mirror in the half-spectrum indexing of green_bin).
+__global__ __launch_bounds__(256) void k_disl_spectrum(const DevLine* __restrict__ lines, int nl, int axis, int n,
+                                                       double L, Cubic C, double2* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nn = n * n;
+  if (t >= nn) return;
+  const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+  const int k1 = t % n, k2 = t / n;
+  int kb[3];
+  kb[axis] = 0;
+  kb[a1] = k1;
+  kb[a2] = k2;
+  const int hn = n / 2;
+  const double s2pi = 2.0 * M_PI / L;
+  double2 e[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) e[c] = make_double2(0.0, 0.0);
+  if (k1 != 0 || k2 != 0) {
+    // the representatives of the bin: one, or two for a Nyquist bin
+    double lab[2][3];
+    bool nyq = false;
+    for (int d = 0; d < 3; ++d) {
+      const int k = kb[d];
+      nyq |= k == hn;
+      lab[0][d] = k == hn ? -hn : (k < hn ? k : k - n);
+      lab[1][d] = k == hn ? hn : lab[0][d];
+    }
+    const int nrep = nyq ? 2 : 1;
+    const double h = L / n;
+    for (int li = 0; li < nl; ++li) {
+      const DevLine ln = lines[li];
+      // rho_hat = sum_c w_c exp(-2 pi i (k1 i1 + k2 i2) / n) / h^2
+      const double f1 = floor(ln.u1), f2 = floor(ln.u2);
+      double2 rho = make_double2(0.0, 0.0);
+      for (int c1 = 0; c1 < 2; ++c1)
+        for (int c2 = 0; c2 < 2; ++c2) {
+          const double w = (1.0 - fabs(ln.u1 - (f1 + c1))) * (1.0 - fabs(ln.u2 - (f2 + c2)));
+          if (w == 0.0) continue;
+          const int64_t i1 = (((int64_t)f1 + c1) % n + n) % n, i2 = (((int64_t)f2 + c2) % n + n) % n;
+          const int64_t m = ((int64_t)k1 * i1 + (int64_t)k2 * i2) % n;
+          double sn, cs;
+          sincospi(-2.0 * (double)m / n, &sn, &cs);
+          rho.x += w * cs;
+          rho.y += w * sn;
+        }
+      rho.x /= h * h;
+      rho.y /= h * h;
+      // F = mean over the representatives of (xi x t) / xi^2
+      double F[3] = {0.0, 0.0, 0.0};
+      for (int r = 0; r < nrep; ++r) {
+        const double x0 = s2pi * lab[r][0], x1 = s2pi * lab[r][1], x2 = s2pi * lab[r][2];
+        const double q = 1.0 / ((x0 * x0 + x1 * x1 + x2 * x2) * nrep);
+        F[0] += (x1 * ln.t[2] - x2 * ln.t[1]) * q;
+        F[1] += (x2 * ln.t[0] - x0 * ln.t[2]) * q;
+        F[2] += (x0 * ln.t[1] - x1 * ln.t[0]) * q;
+      }
+      // w = -i F rho
+      double2 w[3];
+      for (int j = 0; j < 3; ++j) w[j] = make_double2(F[j] * rho.y, -F[j] * rho.x);
+      const double* b = ln.b;
+      e[0].x += b[0] * w[0].x;
+      e[0].y += b[0] * w[0].y;
+      e[1].x += b[1] * w[1].x;
+      e[1].y += b[1] * w[1].y;
+      e[2].x += b[2] * w[2].x;
+      e[2].y += b[2] * w[2].y;
+      e[3].x += 0.5 * (b[1] * w[2].x + b[2] * w[1].x);
+      e[3].y += 0.5 * (b[1] * w[2].y + b[2] * w[1].y);
+      e[4].x += 0.5 * (b[0] * w[2].x + b[2] * w[0].x);
+      e[4].y += 0.5 * (b[0] * w[2].y + b[2] * w[0].y);
+      e[5].x += 0.5 * (b[0] * w[1].x + b[1] * w[0].x);
+      e[5].y += 0.5 * (b[0] * w[1].y + b[1] * w[0].y);
+    }
+    int gx = kb[0], gy = kb[1], gz = kb[2];
+    if (gx > hn) {
+      gx = n - gx;
+      gy = (n - gy) % n;
+      gz = (n - gz) % n;
+    }
+    if (C.frm)
+      green_bin_rot(e, gx, gy, gz, n, C);
+    else
+      green_bin(e, gx, gy, gz, n, C);
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) out[(size_t)c * nn + t] = e[c];
+}
+
+// One direction of the inverse 2-D transform by direct sums (exact phase
+// reduction, m = k i mod n): DIM 0 over k1 (in [c][k2][k1] -> out [c][k2][i1]),
+// DIM 1 over k2 with the 1/n^2 scale and the real part into plane [i2 * n + i1][c].
+template <int DIM>
+__global__ __launch_bounds__(256) void k_disl_idft(const double2* __restrict__ in, int n, double2* __restrict__ out,
+                                                   double* __restrict__ plane) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nn = n * n;
+  if (t >= 6 * nn) return;
+  const int c = t / nn, r = t % nn;
+  const int i = r % n, o = r / n;  // output index along the transformed axis, the other axis
+  double2 acc = make_double2(0.0, 0.0);
+  for (int k = 0; k < n; ++k) {
+    const double2 v = DIM == 0 ? in[(size_t)c * nn + (size_t)o * n + k] : in[(size_t)c * nn + (size_t)k * n + o];
+    const int64_t m = ((int64_t)k * i) % n;
+    double sn, cs;
+    sincospi(2.0 * (double)m / n, &sn, &cs);
+    acc.x += v.x * cs - v.y * sn;
+    acc.y += v.x * sn + v.y * cs;
+  }
+  if (DIM == 0)
+    out[(size_t)c * nn + (size_t)o * n + i] = acc;
+  else
+    plane[((size_t)i * n + o) * 6 + c] = acc.x / ((double)n * n);
+}
+
+__global__ __launch_bounds__(256) void k_bg_add(double* __restrict__ sig, const double* __restrict__ planes, int mask,
+                                                int n, double sgn) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (v >= nn * n) return;
+  const int x[3] = {(int)(v % n), (int)((v / n) % n), (int)(v / nn)};
+  double add[6] = {0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < 3; ++a) {
+    if (!(mask & (1 << a))) continue;
+    const int a1 = a == 0 ? 1 : 0, a2 = a == 2 ? 1 : 2;
+    const double* p = planes + ((size_t)a * nn + (size_t)x[a2] * n + x[a1]) * 6;
+    for (int c = 0; c < 6; ++c) add[c] += p[c];
+  }
+  double* q = sig + 6 * v;
+  for (int c = 0; c < 6; ++c) q[c] += sgn * add[c];
+}
+
+hipError_t launch_disl_plane(const DevLine* lines, int nl, int axis, int n, double L, Cubic C, double2* spec,
+                             double2* tmp, double* plane, hipStream_t s) {
+  const int nn = n * n;
+  hipLaunchKernelGGL(k_disl_spectrum, dim3((nn + 255) / 256), dim3(256), 0, s, lines, nl, axis, n, L, C, spec);
+  hipLaunchKernelGGL(k_disl_idft<0>, dim3((6 * nn + 255) / 256), dim3(256), 0, s, (const double2*)spec, n, tmp,
+                     (double*)nullptr);
+  hipLaunchKernelGGL(k_disl_idft<1>, dim3((6 * nn + 255) / 256), dim3(256), 0, s, (const double2*)tmp, n,
+                     (double2*)nullptr, plane);
+  return hipGetLastError();
+}
+
+hipError_t launch_bg_add(double* sig, const double* planes, int mask, int n, double sgn, hipStream_t s) {
+  const int64_t n3 = (int64_t)n * n * n;
+  hipLaunchKernelGGL(k_bg_add, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, s, sig, planes, mask, n, sgn);
+  return hipGetLastError();
+}
+
 }  // namespace ec

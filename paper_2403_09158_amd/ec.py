@@ -40,6 +40,7 @@ EXPORTS = (
     "ec_jump_energies",
     "ec_jump_select",
     "ec_okmc_step",
+    "ec_set_dislocations",
     "ec_dipole_energies",
     "ec_state_footprints",
     "ec_state_field",
@@ -111,6 +112,7 @@ def load() -> ctypes.CDLL:
             [vp, vp, c_int32, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp],
         ),
         "ec_dipole_energies": (c_int, [vp, vp, vp, c_int32]),
+        "ec_set_dislocations": (c_int, [vp, vp, c_int32, vp]),
         "ec_state_footprints": (c_int, [vp, i32p, i32p, c_int64, i64p]),
         "ec_state_field": (c_int, [vp, c_int32, dp]),
         "ec_state_self_terms": (c_int, [vp, dp]),
@@ -353,6 +355,14 @@ class State:
         )
         self._jn = j.shape[1]
         return (choice, E) if energies else choice
+
+    def set_dislocations(self, lines, stream=None):
+        """Straight dislocation lines (records of ``inputs.LINE_DTYPE``) whose
+        stress is added to every solve of this state; an empty array removes them."""
+        from .inputs import LINE_DTYPE
+
+        a = np.ascontiguousarray(np.asarray(lines, dtype=LINE_DTYPE).reshape(-1))
+        _check(load().ec_set_dislocations(self.h, a.ctypes.data if len(a) else None, len(a), _stream_handle(stream)))
 
     def dipole_energies(self, stream=None, out=None) -> np.ndarray:
         """Dipole-tensor interaction energies (eV) of the current defects; host

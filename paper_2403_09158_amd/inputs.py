@@ -56,6 +56,24 @@ DEFECT_DTYPE = np.dtype(
 )
 assert DEFECT_DTYPE.itemsize == 104
 
+# Layout-compatible with ``ec_line`` in include/ec.h (56 bytes): an infinite
+# straight dislocation line along a cell axis.
+LINE_DTYPE = np.dtype(
+    [("p", "<f8", (3,)), ("axis", "<i4"), ("sense", "<i4"), ("b", "<f8", (3,))],
+    align=True,
+)
+assert LINE_DTYPE.itemsize == 56
+
+
+def line(p, axis, sense, b):
+    rec = np.zeros(1, dtype=LINE_DTYPE)
+    rec["p"] = p
+    rec["axis"] = axis
+    rec["sense"] = sense
+    rec["b"] = b
+    return rec
+
+
 CUBIC_FE = (243.0, 145.0, 116.0)
 
 # The four 1/2<111> Burgers-vector variants (b and -b describe the same loop).

@@ -36,3 +36,7 @@ def test_defect_record_layout():
     assert DEFECT_DTYPE.fields["eig_v"][1] == 96
     assert ctypes.sizeof(ec.CProblem) == 120
     assert ec.CProblem.frame.offset == 48
+    from paper_2403_09158_amd.inputs import LINE_DTYPE
+
+    assert LINE_DTYPE.itemsize == 56
+    assert LINE_DTYPE.fields["axis"][1] == 24 and LINE_DTYPE.fields["b"][1] == 32
