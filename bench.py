@@ -246,6 +246,60 @@ def frame_block(steps=10, warmup=3):
     return out
 
 
+def dislocation_block(steps=10, warmup=3):
+    """An edge dislocation in the paper's rotated frame (line along the cell z
+    axis [1-10], Burgers vector 1/2[111] along x): the cost of setting the line
+    and of solve + energies of mixed_256 with it present (FP32), and the
+    interaction energy of a 1/2[111] loop (R = 1 nm) hopping along its glide
+    direction x, 5 nm above the dislocation's glide plane (128^3, FP64)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_09158_amd import ec, inputs
+
+    h = inputs.H_VOXEL
+    bx = 0.5 * inputs.A_FE * np.sqrt(3.0) * np.array([1.0, 0.0, 0.0])
+    ctx = ec.Context(0)
+    prob, defs = inputs.mixed_256(prec=1)
+    prob = prob.with_(frame=inputs.FRAME_111)
+    line = inputs.line(np.array([128.0, 128.0, 0.0]) * h, 2, 1, bx)
+    st = ec.State(ctx, prob)
+    st.solve(defs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.set_dislocations(line)
+    torch.cuda.synchronize()
+    t_set = time.perf_counter() - t0
+    dt, _, prof = timed_steps(st, defs, steps, warmup, True)
+    st.close()
+    out = {
+        "workload": "edge dislocation (line [1-10], b 1/2[111]) in the rotated frame: mixed_256 solve + energies with the "
+        "line present (FP32), and a 1/2[111] loop (R 1 nm) hopping along x 5 nm above the glide plane (128^3, FP64)",
+        "set_line_ms": round(t_set * 1e3, 3),
+        "fp32_ms_per_step_with_line": round(dt / steps * 1e3, 4),
+        "per_family": family_table(prof),
+    }
+    n = 128
+    pp = inputs.Problem(n, n * h, *inputs.CUBIC_FE, prec=0, frame=inputs.FRAME_111)
+    st = ec.State(ctx, pp)
+    st.set_dislocations(inputs.line(np.array([64.0, 64.0, 0.0]) * h, 2, 1, bx))
+    loop = inputs.loop(np.array([64.0 - 32.0 + 0.5, 64.0 + 16.0 + 0.5, 64.5]) * h, 1.0, bx, bx)
+    st.solve(loop)
+    xs, Es = [], []
+    for k in range(17):
+        if k:
+            loop["c"][0] = loop["c"][0] + np.array([4.0 * h, 0.0, 0.0])
+            E = st.update(0, loop[0])
+        else:
+            E = st.energies()
+        xs.append(round(float(loop["c"][0][0] - 64.0 * h), 4))
+        Es.append(float(E[0]))
+    st.close()
+    ctx.close()
+    out["loop_profile"] = {"x_nm_from_line": xs, "E_eV": Es, "E_min_eV": min(Es), "E_max_eV": max(Es)}
+    return out
+
+
 def jump_probe_block(steps=10):
     """Jump probes on mixed_256 (2000 defects, two glide jumps each): energy
     changes of all candidate jumps, biased frequencies and the frequency-line
@@ -463,8 +517,8 @@ def main():
     ap.add_argument("--jumps-only", action="store_true", help="run the jump-probe, dipole and OkMC workloads alone")
     ap.add_argument("--okmc-only", action="store_true", help="run the OkMC-step workload alone (profiling runs)")
     ap.add_argument("--probe-only", action="store_true", help="run the jump-probe workload alone (profiling runs)")
-    ap.add_argument("--no-frame", action="store_true", help="skip the rotated-crystal workload")
-    ap.add_argument("--frame-only", action="store_true", help="run the rotated-crystal workload alone")
+    ap.add_argument("--no-frame", action="store_true", help="skip the rotated-crystal and dislocation workloads")
+    ap.add_argument("--frame-only", action="store_true", help="run the rotated-crystal and dislocation workloads alone")
     ap.add_argument(
         "--calibrate-copy",
         action="store_true",
@@ -493,7 +547,7 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": 1 << 30}), flush=True)
         return
     if args.frame_only:
-        print(json.dumps({"frame_111": frame_block()}), flush=True)
+        print(json.dumps({"frame_111": frame_block(), "dislocation": dislocation_block()}), flush=True)
         return
     if args.probe_only:
         print(json.dumps({"jump_probe": jump_probe_block()}), flush=True)
@@ -601,6 +655,7 @@ def main():
         line["okmc"] = okmc_block()
     if not args.no_frame:
         line["frame_111"] = frame_block()
+        line["dislocation"] = dislocation_block()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob64, defs)
     print(json.dumps(line), flush=True)
