@@ -130,16 +130,15 @@ __device__ __forceinline__ void green_bin(double2* e, int kx, int ky, int kz, in
 // eps*_hat and the frequency labels rotated in and sigma_hat rotated back, so
 // that the cell-frame operator is built from C' = A^T-rotated C without
 // forming its 21 constants.
-__device__ __forceinline__ void green_bin_rot(double2* e, int kx, int ky, int kz, int n, const Cubic& C) {
+// The cubic operator on a bin whose eps*_hat is already in the cube frame, with
+// the frequency label rotated there; sigma_hat stays in the cube frame.
+__device__ __forceinline__ void green_core_rot(double2* ec, int kx, int ky, int kz, int n, const Cubic& C) {
   if (kx == 0 && ky == 0 && kz == 0) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) e[c] = make_double2(0.0, 0.0);
+    for (int c = 0; c < 6; ++c) ec[c] = make_double2(0.0, 0.0);
     return;
   }
-  const double* F = C.frm;
-  const double* A = F + 72;
-  double2 ec[6];
-  rot6(F, e, ec);
+  const double* A = C.frm + 72;
   double2 tau[6];
   const double c44x2 = 2.0 * C.C44;
   tau[0].x = C.C11 * ec[0].x + C.C12 * (ec[1].x + ec[2].x);
@@ -166,16 +165,21 @@ __device__ __forceinline__ void green_bin_rot(double2* e, int kx, int ky, int kz
     acc(nx ? -h : lx, ny ? -h : ly, nz ? -h : lz, 0.5);
     acc(nx ? h : lx, ny ? h : ly, nz ? h : lz, 0.5);
   }
-  double2 sc[6];
-  sc[0].x = C.C11 * eps[0].x + C.C12 * (eps[1].x + eps[2].x) - tau[0].x;
-  sc[0].y = C.C11 * eps[0].y + C.C12 * (eps[1].y + eps[2].y) - tau[0].y;
-  sc[1].x = C.C11 * eps[1].x + C.C12 * (eps[0].x + eps[2].x) - tau[1].x;
-  sc[1].y = C.C11 * eps[1].y + C.C12 * (eps[0].y + eps[2].y) - tau[1].y;
-  sc[2].x = C.C11 * eps[2].x + C.C12 * (eps[0].x + eps[1].x) - tau[2].x;
-  sc[2].y = C.C11 * eps[2].y + C.C12 * (eps[0].y + eps[1].y) - tau[2].y;
+  ec[0].x = C.C11 * eps[0].x + C.C12 * (eps[1].x + eps[2].x) - tau[0].x;
+  ec[0].y = C.C11 * eps[0].y + C.C12 * (eps[1].y + eps[2].y) - tau[0].y;
+  ec[1].x = C.C11 * eps[1].x + C.C12 * (eps[0].x + eps[2].x) - tau[1].x;
+  ec[1].y = C.C11 * eps[1].y + C.C12 * (eps[0].y + eps[2].y) - tau[1].y;
+  ec[2].x = C.C11 * eps[2].x + C.C12 * (eps[0].x + eps[1].x) - tau[2].x;
+  ec[2].y = C.C11 * eps[2].y + C.C12 * (eps[0].y + eps[1].y) - tau[2].y;
 #pragma unroll
-  for (int c = 3; c < 6; ++c) sc[c] = make_double2(c44x2 * eps[c].x - tau[c].x, c44x2 * eps[c].y - tau[c].y);
-  rot6(F + 36, sc, e);
+  for (int c = 3; c < 6; ++c) ec[c] = make_double2(c44x2 * eps[c].x - tau[c].x, c44x2 * eps[c].y - tau[c].y);
+}
+
+__device__ __forceinline__ void green_bin_rot(double2* e, int kx, int ky, int kz, int n, const Cubic& C) {
+  double2 ec[6];
+  rot6(C.frm, e, ec);
+  green_core_rot(ec, kx, ky, kz, n, C);
+  rot6(C.frm + 36, ec, e);
 }
 
 // ----------------------------------------------------------------- x forward (R2C)
@@ -693,7 +697,23 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
       stage<N, R2, R0 * R1, false, Map::Pencil, NF, T>(tw, from_lds, to_lds, true, tid);
     }
     __syncthreads();
-    // Green step: one bin (all six components) per iteration, in place
+    // Green step: one bin (all six components) per iteration, in place.  A
+    // rotated crystal takes three loops (eps*_hat into the cube frame, the cubic
+    // operator with rotated labels, sigma_hat back), each thread on the same
+    // bins throughout, so that each loop's registers stay few.
+    if constexpr (ROT) {
+#pragma unroll 1
+      for (int b = tid; b < N * W; b += T) {
+        const int bw = b % W, kz = b / W;
+        if (kx - w + bw >= NH) continue;
+        double2 e[6], r[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) e[c] = from_lds(bw * 6 + c, kz);
+        rot6(C.frm, e, r);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) to_lds(bw * 6 + c, kz, r[c]);
+      }
+    }
 #pragma unroll 1
     for (int b = tid; b < N * W; b += T) {
       const int bw = b % W, kz = b / W, bkx = kx - w + bw;
@@ -702,11 +722,24 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
 #pragma unroll
       for (int c = 0; c < 6; ++c) e[c] = from_lds(bw * 6 + c, kz);
       if constexpr (ROT)
-        green_bin_rot(e, bkx, ky, kz, N, C);
+        green_core_rot(e, bkx, ky, kz, N, C);
       else
         green_bin(e, bkx, ky, kz, N, C);
 #pragma unroll
       for (int c = 0; c < 6; ++c) to_lds(bw * 6 + c, kz, e[c]);
+    }
+    if constexpr (ROT) {
+#pragma unroll 1
+      for (int b = tid; b < N * W; b += T) {
+        const int bw = b % W, kz = b / W;
+        if (kx - w + bw >= NH) continue;
+        double2 e[6], r[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) e[c] = from_lds(bw * 6 + c, kz);
+        rot6(C.frm + 36, e, r);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) to_lds(bw * 6 + c, kz, r[c]);
+      }
     }
     __syncthreads();
     auto store_last = [&](int, int i, double2 v) {
