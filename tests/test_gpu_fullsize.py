@@ -123,6 +123,55 @@ def test_mixed256_jump_probes(ctx):
     assert np.abs(dE[0]).max() > 1e-4  # the probes see the interactions
 
 
+def test_mixed256_rotated_frame_and_line(ctx):
+    """mixed_256 in the paper's rotated frame: FP32 energies within the
+    per-defect tolerance of FP64, and an edge dislocation line's stress added
+    and taken out again exactly (to rounding)."""
+    from paper_2403_09158_amd import ec
+
+    prob, d = inputs.mixed_256(prec=0)
+    prob = prob.with_(frame=inputs.FRAME_111)
+    E = {}
+    for prec in (0, 1):
+        st = ec.State(ctx, prob.with_(prec=prec))
+        st.solve(d)
+        E[prec] = st.energies().copy()
+        if prec == 0:
+            bx = 0.5 * inputs.A_FE * np.sqrt(3.0) * np.array([1.0, 0.0, 0.0])
+            st.set_dislocations(inputs.line(np.array([128.0, 128.0, 0.0]) * prob.h, 2, 1, bx))
+            E_line = st.energies().copy()
+            assert np.abs(E_line - E[0]).max() > 1e-3
+            st.set_dislocations(np.zeros(0, dtype=inputs.LINE_DTYPE))
+            assert energy_ok_fp64(st.energies(), E[0], rtol=1e-12)
+        st.close()
+    assert np.all(energy_ok_fp32(E[1], E[0]))
+
+
+def test_mixed256_okmc_step_equals_fresh_solve(ctx):
+    """An OkMC step on mixed_256 (FP64): the energies after the step equal a
+    fresh solve of the moved records, and the acting fraction is near 1 - 1/e."""
+    from paper_2403_09158_amd import ec
+
+    prob, d = inputs.mixed_256(prec=0)
+    J = inputs.glide_jumps(d)
+    rng = np.random.default_rng(inputs.SEED_BASE + 880)
+    nd = len(d)
+    kT = 8.617333262e-5 * 300.0
+    st = ec.State(ctx, prob)
+    st.solve(d)
+    choice, E = st.okmc_step(J, np.full(nd, 0.1), 1e13, kT, 1.0 - rng.uniform(size=nd), 1.0 - rng.uniform(size=nd), energies=True)
+    frac = float((choice >= 0).mean())
+    assert abs(frac - (1.0 - np.exp(-1.0))) < 5.0 * np.sqrt(0.25 / nd)
+    moved = d.copy()
+    sel = choice >= 0
+    moved["c"][sel] = moved["c"][sel] + J[np.nonzero(sel)[0], choice[sel]].astype(np.float64) * prob.h
+    fresh = ec.State(ctx, prob)
+    fresh.solve(moved)
+    assert energy_ok_fp64(E, fresh.energies())
+    st.close()
+    fresh.close()
+
+
 def test_mixed512_fp32_against_fp64_and_sampled_footprints(ctx):
     """512^3 / 20000 defects: too large for the oracle's solve, so the FP64
     path (oracle-matched at smaller sizes) is the reference for the FP32 one,
