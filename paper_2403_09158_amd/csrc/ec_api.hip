@@ -685,7 +685,6 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
   return EC_OK;
 }
 
-// Window of the discrete kernel G for this problem: six FP64 impulse solves.
 // out = -C:m for the state's crystal (the cubic stiffness applied in the cube
 // frame when the crystal is rotated).
 void neg_C_dot(const ec_state* st, const double* m, double* out) {
@@ -705,6 +704,7 @@ void neg_C_dot(const ec_state* st, const double* m, double* out) {
     std::copy(t, t + 6, out);
 }
 
+// Window of the discrete kernel G for this problem: six FP64 impulse solves.
 ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
   ec_ctx* c = st->ctx;
   {
