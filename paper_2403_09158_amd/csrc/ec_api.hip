@@ -282,7 +282,7 @@ struct ec_state {
   size_t dip_cap = 0;
   int64_t* updfix = nullptr;  // 6 int64
   // pinned staging: defect table, per-update records, moved footprint
-  Pinned pin_tab, pin_upd, pin_ids, pin_tags, pin_jump;
+  Pinned pin_tab, pin_upd, pin_ids, pin_tags, pin_jump, pin_choice;
   // profiling
   bool prof = false;
   std::vector<ProfRec> recs;
@@ -1059,13 +1059,21 @@ void frame_maps(const double* A, double* out) {
 // Fourier passes, the self terms beside them.  keep_self: h is the current list
 // with whole-voxel translations only (same order, shapes and classes, the
 // classes already in h), so the self terms, classes and windows stay valid.
-ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, bool keep_self = false) {
+// With h null, fill_dev writes the new table on the device instead: the list
+// is the current one with whole-voxel translations (keep_self must hold), so
+// the slots stay, and the caller brings the host copy of the list up to date.
+ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, bool keep_self = false,
+                      const std::function<ec_status(DevDefect*)>& fill_dev = {}) {
   ec_status r;
   const char* hp = (const char*)h;
   int64_t total = 0;
-  for (int i = 0; i < ndef; ++i) {
-    h[i].slot = total;
-    total += box_volume(h[i]);
+  if (h) {
+    for (int i = 0; i < ndef; ++i) {
+      h[i].slot = total;
+      total += box_volume(h[i]);
+    }
+  } else {
+    total = st->ids_used;
   }
   // buffers of the new list (the spare set)
   DefBuf& nb = st->db[1 - st->cur];
@@ -1075,9 +1083,11 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
       (r = st_grow(st, &nb.ids, &idcap, need)) != EC_OK || (r = st_grow(st, &nb.lnk, &lkcap, need)) != EC_OK)
     return r;
   nb.ids_cap = (int64_t)std::min(idcap, lkcap);
-  if (ndef > 0) {
+  if (ndef > 0 && h) {
     HIPCHK(hipMemcpyAsync(nb.tab, hp, ndef * sizeof(DevDefect), hipMemcpyHostToDevice, s));
     if ((r = pin_end(st->pin_tab, s)) != EC_OK) return r;
+  } else if (ndef > 0 && (r = fill_dev(nb.tab)) != EC_OK) {
+    return r;
   }
   // commit: remove the old eigenstrain, add the new one
   if ((r = join_self(st, s)) != EC_OK) return r;
@@ -1106,9 +1116,11 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
   auto beside = [&]() -> ec_status {
     // host copies of the list while the device works (the staging buffer is
     // only read by the pending upload); the self-term set-up reads them
-    st->hdefs.assign(h, h + ndef);
-    st->hcap.resize(ndef);
-    for (int i = 0; i < ndef; ++i) st->hcap[i] = box_volume(h[i]);
+    if (h) {
+      st->hdefs.assign(h, h + ndef);
+      st->hcap.resize(ndef);
+      for (int i = 0; i < ndef; ++i) st->hcap[i] = box_volume(h[i]);
+    }
     if (ndef == 0 || keep_self) return EC_OK;
     ec_status q = self_terms_beside(st);
     return q == EC_OK ? join_self(st, s) : q;
@@ -1124,13 +1136,15 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
 // the current list; with u, the Poisson gate of the time step dt first (-1: no
 // event).  Arguments already validated.
 ec_status run_select(ec_state* st, const double* Em, double nu0, double kT, const double* xi, const double* u,
-                     double dt, hipStream_t s, double* nu_out, int32_t* choice_out, bool on_device) {
+                     double dt, hipStream_t s, double* nu_out, int32_t* choice_out, bool on_device,
+                     bool choice_kept = false) {
   const int nd = st->ndef, nj = st->jn;
   const size_t nu = (size_t)nd * nj;
   ec_status r;
   if ((r = st_grow(st, &st->jsel, &st->jsel_cap, 3 * (size_t)nd)) != EC_OK) return r;
   if (nu_out && (r = st_grow(st, &st->jnu, &st->jnu_cap, nu)) != EC_OK) return r;
-  if (choice_out && (r = st_grow(st, &st->jchoice, &st->jchoice_cap, (size_t)nd)) != EC_OK) return r;
+  const bool want_choice = choice_out || choice_kept;
+  if (want_choice && (r = st_grow(st, &st->jchoice, &st->jchoice_cap, (size_t)nd)) != EC_OK) return r;
   char* hp = nullptr;
   if ((r = pin_begin(st->pin_jump, 3 * (size_t)nd * 8, &hp)) != EC_OK) return r;
   std::memcpy(hp, Em, (size_t)nd * 8);
@@ -1141,7 +1155,7 @@ ec_status run_select(ec_state* st, const double* Em, double nu0, double kT, cons
   LAUNCH(st, s, PF_OTHER, 0,
          launch_jump_select(st->jdE, nd, nj, st->jsel, nu0, kT, xi ? st->jsel + nd : nullptr,
                             u ? st->jsel + 2 * nd : nullptr, dt, nu_out ? st->jnu : nullptr,
-                            choice_out ? st->jchoice : nullptr, s));
+                            want_choice ? st->jchoice : nullptr, s));
   if (nu_out && (r = copy_out(nu_out, st->jnu, nu * 8, on_device, s)) != EC_OK) return r;
   if (choice_out) return copy_out(choice_out, st->jchoice, (size_t)nd * 4, on_device, s);
   return EC_OK;
@@ -1337,6 +1351,7 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->jchoice, st->jchoice_cap * 4);
   ledger_free(c, st->dip, st->dip_cap * 8);
   pin_free(st->pin_jump);
+  pin_free(st->pin_choice);
   pin_free(st->pin_tab);
   pin_free(st->pin_upd);
   pin_free(st->pin_ids);
@@ -1751,14 +1766,46 @@ ec_status ec_okmc_step(ec_state* st, const int32_t* jumps, int32_t njump, const 
   if ((r = ec_jump_energies(st, jumps, njump, stream, nullptr, 0)) != EC_OK) return r;
   if (nd == 0) return EC_OK;
   std::vector<int32_t> ch(nd);
+  const int n = st->n;
+  const int32_t Lq = QSUB * n;
+  if (st->B_valid && st->classes_ok) {
+    // the probe left the self terms and classes current, and a translation by
+    // whole voxels keeps every footprint's shape: the choices stay on the
+    // device, the moved table is written there, and the host waits only at
+    // the end (for its copy of the choices)
+    if ((r = run_select(st, Em, nu0, kT, xi, u, dt, s, nullptr, nullptr, false, true)) != EC_OK) return r;
+    char* hc = nullptr;
+    if ((r = pin_begin(st->pin_choice, (size_t)nd * 4, &hc)) != EC_OK) return r;
+    HIPCHK(hipMemcpyAsync(hc, st->jchoice, (size_t)nd * 4, hipMemcpyDeviceToHost, s));
+    if ((r = pin_end(st->pin_choice, s)) != EC_OK) return r;
+    const DevDefect* src = st->db[st->cur].tab;
+    r = solve_table(st, nullptr, nd, s, true, [&](DevDefect* dst) -> ec_status {
+      LAUNCH(st, s, PF_OTHER, 0, launch_apply_jumps(src, dst, nd, st->jchoice, st->jjumps, njump, n, s));
+      return EC_OK;
+    });
+    if (r != EC_OK) return r;
+    HIPCHK(hipEventSynchronize(st->pin_choice.ev));
+    st->pin_choice.pending = false;
+    std::memcpy(ch.data(), hc, (size_t)nd * 4);
+    for (int i = 0; i < nd; ++i) {
+      if (ch[i] < 0) continue;
+      const int32_t* lam = jumps + ((size_t)i * njump + ch[i]) * 3;
+      DevDefect& d = st->hdefs[i];
+      for (int k = 0; k < 3; ++k) {
+        d.cq[k] = (int32_t)((((int64_t)d.cq[k] + (int64_t)lam[k] * QSUB) % Lq + Lq) % Lq);
+        d.lo[k] = ((d.lo[k] + lam[k]) % n + n) % n;
+      }
+    }
+    if (choice_out) std::memcpy(choice_out, ch.data(), (size_t)nd * 4);
+    if (E_out) return ec_interaction_energies(st, stream, E_out, 0);
+    return EC_OK;
+  }
   if ((r = run_select(st, Em, nu0, kT, xi, u, dt, s, nullptr, ch.data(), false)) != EC_OK) return r;
   // the chosen jumps: whole-voxel translations of the quantised centres (box,
   // offsets and eigenstrain are unchanged), then the field of the new positions
   char* hp = nullptr;
   if ((r = pin_begin(st->pin_tab, (size_t)nd * sizeof(DevDefect), &hp)) != EC_OK) return r;
   DevDefect* h = (DevDefect*)hp;
-  const int n = st->n;
-  const int32_t Lq = QSUB * n;
   for (int i = 0; i < nd; ++i) {
     h[i] = st->hdefs[i];
     if (ch[i] < 0) continue;
@@ -1768,9 +1815,7 @@ ec_status ec_okmc_step(ec_state* st, const int32_t* jumps, int32_t njump, const 
       h[i].lo[k] = ((h[i].lo[k] + lam[k]) % n + n) % n;
     }
   }
-  // the probe left the self terms and classes current, and a translation by
-  // whole voxels keeps every footprint's shape
-  if ((r = solve_table(st, h, nd, s, st->B_valid && st->classes_ok)) != EC_OK) return r;
+  if ((r = solve_table(st, h, nd, s)) != EC_OK) return r;
   if (choice_out) std::memcpy(choice_out, ch.data(), (size_t)nd * 4);
   if (E_out) return ec_interaction_energies(st, stream, E_out, 0);
   return EC_OK;

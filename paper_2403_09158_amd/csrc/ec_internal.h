@@ -334,6 +334,10 @@ hipError_t launch_jump_energies(const DevDefect* d, int ndef, const int32_t* cou
 // voxel holding the defect centre (sig voxel-major; window as for the self terms).
 hipError_t launch_dipole(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, const double* sig,
                          int n, const double* K, const double* gcls, int D, double h3c, double* Edip, hipStream_t s);
+// The table of the chosen whole-voxel jumps: dst[i] = src[i] with its centre
+// and box moved by jumps[(i * nj + choice[i]) * 3 ..] voxels (choice < 0: as is).
+hipError_t launch_apply_jumps(const DevDefect* src, DevDefect* dst, int ndef, const int32_t* choice,
+                              const int32_t* jumps, int nj, int n, hipStream_t s);
 // Biased jump frequencies and the frequency-line choice (nu, choice may be null).
 hipError_t launch_jump_select(const double* dE, int ndef, int nj, const double* Em, double nu0, double kT,
                               const double* xi, const double* u, double dt, double* nu, int32_t* choice,

@@ -837,6 +837,31 @@ hipError_t launch_jump_energies(const DevDefect* d, int ndef, const int32_t* cou
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_apply_jumps(const DevDefect* __restrict__ src, DevDefect* __restrict__ dst,
+                                                     int ndef, const int32_t* __restrict__ choice,
+                                                     const int32_t* __restrict__ jumps, int nj, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ndef) return;
+  DevDefect d = src[i];
+  const int c = choice[i];
+  if (c >= 0) {
+    const int32_t* l = jumps + ((size_t)i * nj + c) * 3;
+    const int64_t Lq = (int64_t)QSUB * n;
+    for (int k = 0; k < 3; ++k) {
+      d.cq[k] = (int32_t)((((int64_t)d.cq[k] + (int64_t)l[k] * QSUB) % Lq + Lq) % Lq);
+      d.lo[k] = ((d.lo[k] + l[k]) % n + n) % n;
+    }
+  }
+  dst[i] = d;
+}
+
+hipError_t launch_apply_jumps(const DevDefect* src, DevDefect* dst, int ndef, const int32_t* choice,
+                              const int32_t* jumps, int nj, int n, hipStream_t s) {
+  if (ndef == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_apply_jumps, dim3((ndef + 255) / 256), dim3(256), 0, s, src, dst, ndef, choice, jumps, nj, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_jump_select(const double* dE, int ndef, int nj, const double* Em, double nu0, double kT,
                               const double* xi, const double* u, double dt, double* nu, int32_t* choice,
                               hipStream_t s) {
