@@ -667,7 +667,7 @@ ec_status join_self(ec_state* st, hipStream_t s);
 // are enqueued and before the z pass is.
 ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs,
                    void* spec, double* sig, const double* add6, uint32_t* ctr,
-                   const std::function<ec_status()>& between = {}) {
+                   const std::function<ec_status()>& between = {}, const double* bg = nullptr, int bg_mask = 0) {
   const Prune full{0, st->n, 0, st->n};
   const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
   SpecGeom g{st->n, 0};
@@ -681,7 +681,7 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
   }
   LAUNCH(st, s, PF_Z, 2 * sb, launch_z_green(fp64, spec, g, st->C, full, st->tw, ctr ? ctr + 8 : nullptr, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, spec, g, full, st->tw, ctr ? ctr + 16 : nullptr, s));
-  LAUNCH(st, s, PF_XI, sb + fb, launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s));
+  LAUNCH(st, s, PF_XI, sb + fb, launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s, bg, bg_mask));
   return EC_OK;
 }
 
@@ -1125,9 +1125,10 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
     ec_status q = self_terms_beside(st);
     return q == EC_OK ? join_self(st, s) : q;
   };
-  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6, st->tilectr, beside);
+  // the stress of dislocation lines, if any, is added by the x inverse pass
+  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6, st->tilectr, beside, st->bg,
+               st->bg_mask);
   if (r != EC_OK) return r;
-  if (st->bg_mask) LAUNCH(st, s, PF_OTHER, 0, launch_bg_add(st->sig, st->bg, st->bg_mask, st->n, 1.0, s));
   st->solved = true;
   return EC_OK;
 }

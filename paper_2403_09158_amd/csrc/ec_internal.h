@@ -287,8 +287,9 @@ hipError_t launch_bg_add(double* sig, const double* planes, int mask, int n, dou
 hipError_t launch_green(bool fp64, void* spec, SpecGeom g, Cubic C, hipStream_t s);
 hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, uint32_t* ctr,
                           hipStream_t s);
+// bg / bg_mask: stress planes of dislocation lines added to sigma (not with accum).
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
-                            const double2* tw, hipStream_t s);
+                            const double2* tw, hipStream_t s, const double* bg = nullptr, int bg_mask = 0);
 
 // ---- k_raster.hip / k_energy.hip -----------------------------------------------
 

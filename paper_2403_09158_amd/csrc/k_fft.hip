@@ -776,10 +776,12 @@ __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__
 
 // --------------------------------------------------------- x inverse (C2R) + stress
 
-template <int N, typename S, bool ACC>
+// BG: the stress planes of dislocation lines along the axes in bg_mask
+// ([3][n^2][6], FP64) are added as well.
+template <int N, typename S, bool ACC, bool BG>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
     const typename Cplx<S>::T* __restrict__ spec, double* __restrict__ sig, const double* __restrict__ mean6,
-    const double2* __restrict__ twg) {
+    const double2* __restrict__ twg, const double* __restrict__ bg, int bg_mask) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;
   constexpr int T = pick_T(max_nb(N, NF));
@@ -823,6 +825,16 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
       const double2 o = *s01;
       r.x += o.x;
       r.y += o.y;
+    }
+    if constexpr (BG) {
+      const int v[3] = {x, y, z};
+      for (int a = 0; a < 3; ++a) {
+        if (!(bg_mask & (1 << a))) continue;
+        const int a1 = a == 0 ? 1 : 0, a2 = a == 2 ? 1 : 2;
+        const double2 o = *reinterpret_cast<const double2*>(bg + ((a * N + v[a2]) * N + v[a1]) * 6 + 2 * p);
+        r.x += o.x;
+        r.y += o.y;
+      }
     }
     *s01 = r;
   };
@@ -900,15 +912,20 @@ hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const
 
 template <int N, typename S>
 hipError_t go_xi(bool acc, const void* spec, double* sig, SpecGeom g, const double* mean6, const double2* tw,
-                 hipStream_t s) {
+                 const double* bg, int bg_mask, hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   const int grid = N * (N / x_rows(N));
   using C2 = typename Cplx<S>::T;
   if (g.P != spec_pitch(N, sizeof(S) == 8)) return hipErrorInvalidValue;
   if (acc)
-    hipLaunchKernelGGL((k_x_inverse<N, S, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw);
+    hipLaunchKernelGGL((k_x_inverse<N, S, true, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
+                       bg, 0);
+  else if (bg && bg_mask)
+    hipLaunchKernelGGL((k_x_inverse<N, S, false, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
+                       bg, bg_mask);
   else
-    hipLaunchKernelGGL((k_x_inverse<N, S, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw);
+    hipLaunchKernelGGL((k_x_inverse<N, S, false, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
+                       bg, 0);
   return hipGetLastError();
 }
 
@@ -1012,12 +1029,12 @@ hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, 
 }
 
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
-                            const double2* tw, hipStream_t s) {
+                            const double2* tw, hipStream_t s, const double* bg, int bg_mask) {
   switch (g.n) {
-#define EC_CASE(NN)                                                          \
-  case NN:                                                                   \
-    return fp64 ? go_xi<NN, double>(accum, spec, sig, g, mean6, tw, s) \
-                : go_xi<NN, float>(accum, spec, sig, g, mean6, tw, s);
+#define EC_CASE(NN)                                                                   \
+  case NN:                                                                            \
+    return fp64 ? go_xi<NN, double>(accum, spec, sig, g, mean6, tw, bg, bg_mask, s) \
+                : go_xi<NN, float>(accum, spec, sig, g, mean6, tw, bg, bg_mask, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }
