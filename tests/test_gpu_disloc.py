@@ -123,3 +123,17 @@ def test_dislocation_argument_checks(ctx):
         assert ei.value.status == ec.EC_ERR_ARG
     assert np.array_equal(st.energies(), E0)
     st.close()
+
+
+def test_lines_without_defects(ctx):
+    """An empty defect list: the resident stress is the lines' stress alone."""
+    from paper_2403_09158_amd import ec
+
+    prob, _, lines = _case()
+    st = ec.State(ctx, prob)
+    st.set_dislocations(lines)
+    st.solve(inputs.empty_defects(0))
+    assert len(st.energies()) == 0
+    sig_o = to6(odl.dislocation_stress(prob, _oracle_lines(lines)))
+    assert rel_l2(st.field("sigma"), sig_o) < 1e-12
+    st.close()

@@ -174,3 +174,15 @@ def test_probe_after_step_reuses_cross_parts(ctx, prec):
     assert np.abs(warm - cold).max() <= tol * np.abs(cold).max()
     a.close()
     b.close()
+
+
+def test_okmc_step_on_an_empty_list(ctx):
+    from paper_2403_09158_amd import ec
+
+    prob = inputs.Problem(32, 32 * inputs.H_VOXEL, *inputs.CUBIC_FE)
+    st = ec.State(ctx, prob)
+    st.solve(inputs.empty_defects(0))
+    z = np.zeros(0)
+    choice = st.okmc_step(np.zeros((0, 2, 3), dtype=np.int32), z, NU0, KT, z, z)
+    assert choice.shape == (0,)
+    st.close()
