@@ -31,10 +31,10 @@ __host__ __device__ constexpr Plan2 plan_of(int N) {
          : N == 32  ? Plan2{2, {8, 4, 1}}
          : N == 48  ? Plan2{2, {16, 3, 1}}
          : N == 64  ? Plan2{2, {8, 8, 1}}
-         : N == 96  ? Plan2{3, {8, 4, 3}}
+         : N == 96  ? Plan2{2, {16, 6, 1}}
          : N == 128 ? Plan2{2, {16, 8, 1}}
-         : N == 160 ? Plan2{3, {8, 4, 5}}
-         : N == 240 ? Plan2{3, {16, 5, 3}}
+         : N == 160 ? Plan2{2, {16, 10, 1}}
+         : N == 240 ? Plan2{2, {16, 15, 1}}
          : N == 256 ? Plan2{2, {16, 16, 1}}
          : N == 512 ? Plan2{3, {8, 8, 8}}
                     : Plan2{0, {1, 1, 1}};
@@ -186,6 +186,51 @@ struct Dft<8, INV> {
 template <bool INV>
 struct Dft<16, INV> {
   __device__ __forceinline__ static void run(double2* v) { dft_composite<4, 4, INV>(v); }
+};
+
+// R = R1 x R2 with R1, R2 coprime, by the prime-factor (Good-Thomas) mapping,
+// no inner twiddles: input n = (R2 n1 + R1 n2) mod R, output k = (E1 k1 + E2 k2)
+// mod R with E1 = 1 mod R1, 0 mod R2 and E2 = 0 mod R1, 1 mod R2, so the
+// exponent n k reduces to R2 n1 k1 + R1 n2 k2 mod R: an R1 x R2 two-dimensional
+// DFT.
+template <int R1, int R2, int E1, int E2, bool INV>
+__device__ __forceinline__ void dft_pfa(double2* v) {
+  constexpr int R = R1 * R2;
+  static_assert(E1 % R1 == 1 && E1 % R2 == 0 && E2 % R1 == 0 && E2 % R2 == 1, "CRT output map");
+  double2 y[R];
+#pragma unroll
+  for (int n1 = 0; n1 < R1; ++n1) {
+    double2 t[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) t[n2] = v[(R2 * n1 + R1 * n2) % R];
+    Dft<R2, INV>::run(t);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) y[n1 * R2 + k2] = t[k2];
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    double2 t[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) t[n1] = y[n1 * R2 + k2];
+    Dft<R1, INV>::run(t);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) v[(E1 * k1 + E2 * k2) % R] = t[k1];
+  }
+}
+
+template <bool INV>
+struct Dft<6, INV> {
+  __device__ __forceinline__ static void run(double2* v) { dft_pfa<2, 3, 3, 4, INV>(v); }
+};
+
+template <bool INV>
+struct Dft<10, INV> {
+  __device__ __forceinline__ static void run(double2* v) { dft_pfa<2, 5, 5, 6, INV>(v); }
+};
+
+template <bool INV>
+struct Dft<15, INV> {
+  __device__ __forceinline__ static void run(double2* v) { dft_pfa<3, 5, 10, 6, INV>(v); }
 };
 
 // Twiddle from the LDS table (forward W_N^e; conjugated for the inverse).
@@ -385,10 +430,10 @@ __host__ __device__ constexpr Plan2 plan_fused(int N) {
          : N == 32  ? Plan2{2, {8, 4, 1}}
          : N == 48  ? Plan2{2, {16, 3, 1}}
          : N == 64  ? Plan2{3, {8, 2, 4}}
-         : N == 96  ? Plan2{3, {8, 4, 3}}
+         : N == 96  ? Plan2{2, {16, 6, 1}}
          : N == 128 ? Plan2{3, {8, 4, 4}}
-         : N == 160 ? Plan2{3, {8, 4, 5}}
-         : N == 240 ? Plan2{3, {16, 5, 3}}
+         : N == 160 ? Plan2{2, {16, 10, 1}}
+         : N == 240 ? Plan2{2, {16, 15, 1}}
          : N == 256 ? Plan2{2, {16, 16, 1}}
          : N == 512 ? Plan2{3, {8, 16, 4}}
                     : Plan2{0, {1, 1, 1}};
