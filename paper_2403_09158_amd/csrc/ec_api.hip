@@ -282,7 +282,7 @@ struct ec_state {
   size_t dip_cap = 0;
   int64_t* updfix = nullptr;  // 6 int64
   // pinned staging: defect table, per-update records, moved footprint
-  Pinned pin_tab, pin_upd, pin_ids, pin_tags, pin_jump, pin_choice;
+  Pinned pin_tab, pin_upd, pin_ids, pin_tags, pin_jump, pin_choice, pin_out;
   // profiling
   bool prof = false;
   std::vector<ProfRec> recs;
@@ -931,6 +931,19 @@ ec_status copy_out(void* dst, const void* src, size_t bytes, bool on_device, hip
   return EC_OK;
 }
 
+// A per-defect output: to the host through the state's pinned bounce buffer (a
+// direct copy into pageable memory is staged by the runtime), synchronously.
+ec_status copy_small(ec_state* st, void* dst, const void* src, size_t bytes, bool on_device, hipStream_t s) {
+  if (on_device || bytes == 0) return copy_out(dst, src, bytes, on_device, s);
+  char* hp = nullptr;
+  ec_status r = pin_begin(st->pin_out, bytes, &hp);
+  if (r != EC_OK) return r;
+  HIPCHK(hipMemcpyAsync(hp, src, bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::memcpy(dst, hp, bytes);
+  return EC_OK;
+}
+
 ec_status write_field(ec_state* st, int which, void* out, bool on_device, hipStream_t s) {
   const bool f32 = !st->fp64;
   const size_t bytes = (size_t)6 * st->n3 * (f32 ? 4 : 8);
@@ -1157,8 +1170,8 @@ ec_status run_select(ec_state* st, const double* Em, double nu0, double kT, cons
          launch_jump_select(st->jdE, nd, nj, st->jsel, nu0, kT, xi ? st->jsel + nd : nullptr,
                             u ? st->jsel + 2 * nd : nullptr, dt, nu_out ? st->jnu : nullptr,
                             want_choice ? st->jchoice : nullptr, s));
-  if (nu_out && (r = copy_out(nu_out, st->jnu, nu * 8, on_device, s)) != EC_OK) return r;
-  if (choice_out) return copy_out(choice_out, st->jchoice, (size_t)nd * 4, on_device, s);
+  if (nu_out && (r = copy_small(st, nu_out, st->jnu, nu * 8, on_device, s)) != EC_OK) return r;
+  if (choice_out) return copy_small(st, choice_out, st->jchoice, (size_t)nd * 4, on_device, s);
   return EC_OK;
 }
 
@@ -1353,6 +1366,7 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->dip, st->dip_cap * 8);
   pin_free(st->pin_jump);
   pin_free(st->pin_choice);
+  pin_free(st->pin_out);
   pin_free(st->pin_tab);
   pin_free(st->pin_upd);
   pin_free(st->pin_ids);
@@ -1420,7 +1434,7 @@ ec_status ec_interaction_energies(ec_state* st, void* stream, double* E_out, int
   const DefBuf& b = st->db[st->cur];
   LAUNCH(st, s, PF_REDUCE, 0,
          launch_reduce(b.tab, st->ndef, b.cnt, b.ids, st->sig, st->B, st->h3c, st->S6, st->E, s));
-  if (E_out && st->ndef > 0) return copy_out(E_out, st->E, st->ndef * 8, on_device != 0, s);
+  if (E_out && st->ndef > 0) return copy_small(st, E_out, st->E, (size_t)st->ndef * 8, on_device != 0, s);
   return EC_OK;
 }
 
@@ -1719,7 +1733,7 @@ ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t njump, vo
     st->jx_jumps.assign(jumps, jumps + 3 * nu);
     st->jx_ok = true;
   }
-  if (dE_out) return copy_out(dE_out, st->jdE, nu * 8, on_device != 0, s);
+  if (dE_out) return copy_small(st, dE_out, st->jdE, nu * 8, on_device != 0, s);
   return EC_OK;
 }
 
@@ -1893,7 +1907,7 @@ ec_status ec_dipole_energies(ec_state* st, void* stream, double* E_out, int32_t 
   LAUNCH(st, s, PF_REDUCE, 0,
          launch_dipole(b.tab, nd, b.cnt, b.ids, st->sig, st->n, st->win->K, st->gcls, st->win->D, st->h3c, st->dip,
                        s));
-  if (E_out) return copy_out(E_out, st->dip, (size_t)nd * 8, on_device != 0, s);
+  if (E_out) return copy_small(st, E_out, st->dip, (size_t)nd * 8, on_device != 0, s);
   return EC_OK;
 }
 
