@@ -427,6 +427,25 @@ def okmc_block(steps=20, warmup=3):
             "moved_fraction": round(moved / (steps * nd), 4),
             "simulated_ns_per_wall_s": round(dt_s / t * 1e9, 3),
         }
+        if prec == 1:
+            # short steps (dt = 1e-3 / nu_max): about two defects act per step and
+            # are moved one by one with the incremental update
+            st = ec.State(ctx, prob.with_(prec=prec))
+            st.solve(defs)
+            dts = 1e-3 * dt_s
+            for _ in range(warmup):
+                st.okmc_step(J, Em, nu0, kT, 1.0 - rng.uniform(size=nd), 1.0 - rng.uniform(size=nd), dt=dts)
+            torch.cuda.synchronize()
+            acted = 0
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                ch = st.okmc_step(J, Em, nu0, kT, 1.0 - rng.uniform(size=nd), 1.0 - rng.uniform(size=nd), dt=dts)
+                acted += int((ch >= 0).sum())
+            torch.cuda.synchronize()
+            tf = (time.perf_counter() - t0) / steps
+            st.close()
+            out["fp32_short_steps"] = {"dt_ps": round(dts * 1e12, 6), "ms_per_step": round(tf * 1e3, 3),
+                                       "acting_per_step": round(acted / steps, 2)}
     ctx.close()
     return out
 

@@ -1175,6 +1175,146 @@ ec_status run_select(ec_state* st, const double* Em, double nu0, double kT, cons
   return EC_OK;
 }
 
+// Moves defect idx to the quantised record nd (validated): by linearity only
+// the eigenstrain difference is solved and the resident stress accumulated;
+// a whole-voxel move of the same shape translates the footprint.
+ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
+  {
+    ec_status rc = join_self(st, s);
+    if (rc == EC_OK) rc = ensure_classes(st, s);
+    if (rc != EC_OK) return rc;
+  }
+  st->jdE_ok = false;
+  const DevDefect od = st->hdefs[idx];
+  const int n = st->n;
+  // whole-voxel move of the same shape: the footprint translates and B_i is unchanged
+  bool hop = od.kind == nd.kind && od.R2q == nd.R2q && od.eq == nd.eq && od.mm == nd.mm;
+  for (int k = 0; k < 3 && hop; ++k) hop = od.m[k] == nd.m[k] && ((nd.cq[k] - od.cq[k]) % QSUB) == 0;
+  for (int a = 0; a < 6 && hop; ++a) hop = od.efix[a] == nd.efix[a];
+  if (!hop) st->jx_ok = false;  // a translation keeps the probe's cross parts
+  int sh[3] = {0, 0, 0};
+  if (hop)
+    for (int k = 0; k < 3; ++k) {
+      int d = ((nd.cq[k] - od.cq[k]) / QSUB) % n;
+      if (d < 0) d += n;
+      if (d >= n / 2) d -= n;
+      sh[k] = d;
+    }
+  const size_t ncls_before = st->classes.size();
+  if (hop) {
+    nd.cls = od.cls;
+    nd.s = od.s;
+  } else {
+    assign_class(st, nd);
+  }
+  DefBuf& b = st->db[st->cur];
+  std::vector<int32_t> new_ids;
+  int cnt_new = -1;  // hop: same count as the old footprint (read on the device)
+  int64_t cap_new = st->hcap[idx];
+  nd.slot = od.slot;
+  ec_status r;
+  if (!hop) {
+    // new footprint on the host, same enumeration and membership as the rasteriser
+    for (int iz = 0; iz < nd.w[2]; ++iz)
+      for (int iy = 0; iy < nd.w[1]; ++iy) {
+        const int y = box_axis(nd.lo[1], nd.w[1], n, iy), z = box_axis(nd.lo[2], nd.w[2], n, iz);
+        for (int ix = 0; ix < nd.w[0]; ++ix) {
+          const int x = box_axis(nd.lo[0], nd.w[0], n, ix);
+          if (member(nd, n, x, y, z)) new_ids.push_back((z * n + y) * n + x);
+        }
+      }
+    cnt_new = (int)new_ids.size();
+    size_t ucap = (size_t)st->upd_cap;
+    if ((r = st_grow(st, &st->upd_ids, &ucap, std::max<size_t>(cnt_new, 1))) != EC_OK) {
+      st->classes.resize(ncls_before);
+      return r;
+    }
+    st->upd_cap = (int64_t)ucap;
+    if (cnt_new > st->hcap[idx]) {  // does not fit the old slot: take a new one at the end
+      nd.slot = st->ids_used;
+      cap_new = box_volume(nd);
+      size_t icap = (size_t)b.ids_cap, lcap = (size_t)b.ids_cap;
+      const size_t need = (size_t)(st->ids_used + cap_new);
+      if ((r = st_grow(st, &b.ids, &icap, need, true, s)) != EC_OK ||
+          (r = st_grow(st, &b.lnk, &lcap, need, true, s)) != EC_OK) {
+        st->classes.resize(ncls_before);
+        return r;
+      }
+      b.ids_cap = (int64_t)std::min(icap, lcap);
+    }
+  }
+  // rows of the eigenstrain change
+  int ylo, ylen, zlo, zlen;
+  cyclic_cover(od.lo[1], od.w[1], nd.lo[1], nd.w[1], n, ylo, ylen);
+  cyclic_cover(od.lo[2], od.w[2], nd.lo[2], nd.w[2], n, zlo, zlen);
+  double dadd[6] = {0, 0, 0, 0, 0, 0};
+  if (!hop && st->prob.bc == EC_MEAN_STRAIN_ZERO) {
+    // mean strain zero: the mean stress moves with the eigenstrain volume
+    if ((r = fetch_counts(st)) != EC_OK) return r;
+    double m[6];
+    for (int a = 0; a < 6; ++a)
+      m[a] = ((double)cnt_new * nd.E[a] - (double)st->hcnt[idx] * od.E[a]) / (double)st->n3;
+    neg_C_dot(st, m, dadd);
+  }
+  // --- commit
+  char* up = nullptr;  // [E 48][efix 48][dadd 48][count 8][record]
+  if ((r = pin_begin(st->pin_upd, 152 + sizeof(DevDefect), &up)) != EC_OK) return r;
+  std::memcpy(up, nd.E, 48);
+  std::memcpy(up + 48, nd.efix, 48);
+  std::memcpy(up + 96, dadd, 48);
+  std::memcpy(up + 144, &cnt_new, 4);
+  std::memcpy(up + 152, &nd, sizeof nd);
+  if (!hop && cnt_new > 0) {
+    char* ip = nullptr;
+    if ((r = pin_begin(st->pin_ids, (size_t)cnt_new * 4, &ip)) != EC_OK) return r;
+    std::memcpy(ip, new_ids.data(), (size_t)cnt_new * 4);
+    HIPCHK(hipMemcpyAsync(st->upd_ids, ip, (size_t)cnt_new * 4, hipMemcpyHostToDevice, s));
+    if ((r = pin_end(st->pin_ids, s)) != EC_OK) return r;
+  }
+  HIPCHK(hipMemcpyAsync(st->updE, up, 48, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(st->updfix, up + 48, 48, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(st->add6 + 12, up + 96, 48, hipMemcpyHostToDevice, s));
+  const int32_t* oids = b.ids + od.slot;
+  const int32_t* ocnt = b.cnt + idx;
+  const int32_t* nids = hop ? nullptr : st->upd_ids;
+  {
+    const bool fp64 = st->fp64;
+    const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
+    const double frac_z = (double)zlen / n;
+    LAUNCH(st, s, PF_XF, frac_z * ylen / n * sb,
+           launch_x_forward_sparse(fp64, oids, ocnt, nids, cnt_new, sh[0], sh[1], sh[2], st->updE, st->spec, st->g,
+                                   ylo, ylen, zlo, zlen, st->tw, st->tilectr, s));
+    const Prune py{ylo, ylen, zlo, zlen};
+    LAUNCH(st, s, PF_Y, 2 * frac_z * sb, launch_pencil(fp64, false, 1, st->spec, st->g, py, st->tw, st->tilectr, s));
+    const Prune pz{zlo, zlen, 0, n};
+    const Prune full{0, n, 0, n};
+    LAUNCH(st, s, PF_Z, (1 + frac_z) * sb,
+           launch_z_green(fp64, st->spec, st->g, st->C, pz, st->tw, st->tilectr + 8, s));
+    LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, st->spec, st->g, full, st->tw, st->tilectr + 16, s));
+    LAUNCH(st, s, PF_XI, sb + 2 * fb,
+           launch_x_inverse(fp64, true, st->spec, st->sig, st->g, st->add6 + 12, st->tw, s));
+  }
+  // membership lists and footprint ids of the moved defect (after the sparse
+  // forward pass, which still reads the old footprint)
+  LAUNCH(st, s, PF_RASTER, 0,
+         launch_move_lists(idx, ocnt, od.slot, nids, cnt_new, nd.slot, sh[0], sh[1], sh[2], n, b.ids, b.lnk, st->own,
+                           s));
+  if (!hop) {
+    HIPCHK(hipMemcpyAsync(b.cnt + idx, up + 144, 4, hipMemcpyHostToDevice, s));
+    if (nd.slot != od.slot) {
+      st->ids_used += cap_new;
+      st->hcap[idx] = cap_new;
+    }
+    if (st->hcnt_ok) st->hcnt[idx] = cnt_new;
+    st->B_valid = false;
+    if (st->classes.size() != ncls_before) st->gcls_ncls = -1;
+  }
+  HIPCHK(hipMemcpyAsync(b.tab + idx, up + 152, sizeof nd, hipMemcpyHostToDevice, s));
+  if ((r = pin_end(st->pin_upd, s)) != EC_OK) return r;
+  st->hdefs[idx] = nd;
+  return EC_OK;
+}
+
 }  // namespace
 
 // =============================================================================== ABI
@@ -1447,139 +1587,8 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
   DevDefect nd;
   std::string err;
   if (!quantise(st->prob, *moved, nd, err)) return fail(EC_ERR_ARG, "moved defect: %s", err.c_str());
-  {
-    ec_status rc = join_self(st, s);
-    if (rc == EC_OK) rc = ensure_classes(st, s);
-    if (rc != EC_OK) return rc;
-  }
-  st->jdE_ok = false;
-  st->jx_ok = false;
-  const DevDefect od = st->hdefs[idx];
-  const int n = st->n;
-  // whole-voxel move of the same shape: the footprint translates and B_i is unchanged
-  bool hop = od.kind == nd.kind && od.R2q == nd.R2q && od.eq == nd.eq && od.mm == nd.mm;
-  for (int k = 0; k < 3 && hop; ++k) hop = od.m[k] == nd.m[k] && ((nd.cq[k] - od.cq[k]) % QSUB) == 0;
-  for (int a = 0; a < 6 && hop; ++a) hop = od.efix[a] == nd.efix[a];
-  int sh[3] = {0, 0, 0};
-  if (hop)
-    for (int k = 0; k < 3; ++k) {
-      int d = ((nd.cq[k] - od.cq[k]) / QSUB) % n;
-      if (d < 0) d += n;
-      if (d >= n / 2) d -= n;
-      sh[k] = d;
-    }
-  const size_t ncls_before = st->classes.size();
-  if (hop) {
-    nd.cls = od.cls;
-    nd.s = od.s;
-  } else {
-    assign_class(st, nd);
-  }
-  DefBuf& b = st->db[st->cur];
-  std::vector<int32_t> new_ids;
-  int cnt_new = -1;  // hop: same count as the old footprint (read on the device)
-  int64_t cap_new = st->hcap[idx];
-  nd.slot = od.slot;
-  ec_status r;
-  if (!hop) {
-    // new footprint on the host, same enumeration and membership as the rasteriser
-    for (int iz = 0; iz < nd.w[2]; ++iz)
-      for (int iy = 0; iy < nd.w[1]; ++iy) {
-        const int y = box_axis(nd.lo[1], nd.w[1], n, iy), z = box_axis(nd.lo[2], nd.w[2], n, iz);
-        for (int ix = 0; ix < nd.w[0]; ++ix) {
-          const int x = box_axis(nd.lo[0], nd.w[0], n, ix);
-          if (member(nd, n, x, y, z)) new_ids.push_back((z * n + y) * n + x);
-        }
-      }
-    cnt_new = (int)new_ids.size();
-    size_t ucap = (size_t)st->upd_cap;
-    if ((r = st_grow(st, &st->upd_ids, &ucap, std::max<size_t>(cnt_new, 1))) != EC_OK) {
-      st->classes.resize(ncls_before);
-      return r;
-    }
-    st->upd_cap = (int64_t)ucap;
-    if (cnt_new > st->hcap[idx]) {  // does not fit the old slot: take a new one at the end
-      nd.slot = st->ids_used;
-      cap_new = box_volume(nd);
-      size_t icap = (size_t)b.ids_cap, lcap = (size_t)b.ids_cap;
-      const size_t need = (size_t)(st->ids_used + cap_new);
-      if ((r = st_grow(st, &b.ids, &icap, need, true, s)) != EC_OK ||
-          (r = st_grow(st, &b.lnk, &lcap, need, true, s)) != EC_OK) {
-        st->classes.resize(ncls_before);
-        return r;
-      }
-      b.ids_cap = (int64_t)std::min(icap, lcap);
-    }
-  }
-  // rows of the eigenstrain change
-  int ylo, ylen, zlo, zlen;
-  cyclic_cover(od.lo[1], od.w[1], nd.lo[1], nd.w[1], n, ylo, ylen);
-  cyclic_cover(od.lo[2], od.w[2], nd.lo[2], nd.w[2], n, zlo, zlen);
-  double dadd[6] = {0, 0, 0, 0, 0, 0};
-  if (!hop && st->prob.bc == EC_MEAN_STRAIN_ZERO) {
-    // mean strain zero: the mean stress moves with the eigenstrain volume
-    if ((r = fetch_counts(st)) != EC_OK) return r;
-    double m[6];
-    for (int a = 0; a < 6; ++a)
-      m[a] = ((double)cnt_new * nd.E[a] - (double)st->hcnt[idx] * od.E[a]) / (double)st->n3;
-    neg_C_dot(st, m, dadd);
-  }
-  // --- commit
-  char* up = nullptr;  // [E 48][efix 48][dadd 48][count 8][record]
-  if ((r = pin_begin(st->pin_upd, 152 + sizeof(DevDefect), &up)) != EC_OK) return r;
-  std::memcpy(up, nd.E, 48);
-  std::memcpy(up + 48, nd.efix, 48);
-  std::memcpy(up + 96, dadd, 48);
-  std::memcpy(up + 144, &cnt_new, 4);
-  std::memcpy(up + 152, &nd, sizeof nd);
-  if (!hop && cnt_new > 0) {
-    char* ip = nullptr;
-    if ((r = pin_begin(st->pin_ids, (size_t)cnt_new * 4, &ip)) != EC_OK) return r;
-    std::memcpy(ip, new_ids.data(), (size_t)cnt_new * 4);
-    HIPCHK(hipMemcpyAsync(st->upd_ids, ip, (size_t)cnt_new * 4, hipMemcpyHostToDevice, s));
-    if ((r = pin_end(st->pin_ids, s)) != EC_OK) return r;
-  }
-  HIPCHK(hipMemcpyAsync(st->updE, up, 48, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(st->updfix, up + 48, 48, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(st->add6 + 12, up + 96, 48, hipMemcpyHostToDevice, s));
-  const int32_t* oids = b.ids + od.slot;
-  const int32_t* ocnt = b.cnt + idx;
-  const int32_t* nids = hop ? nullptr : st->upd_ids;
-  {
-    const bool fp64 = st->fp64;
-    const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
-    const double frac_z = (double)zlen / n;
-    LAUNCH(st, s, PF_XF, frac_z * ylen / n * sb,
-           launch_x_forward_sparse(fp64, oids, ocnt, nids, cnt_new, sh[0], sh[1], sh[2], st->updE, st->spec, st->g,
-                                   ylo, ylen, zlo, zlen, st->tw, st->tilectr, s));
-    const Prune py{ylo, ylen, zlo, zlen};
-    LAUNCH(st, s, PF_Y, 2 * frac_z * sb, launch_pencil(fp64, false, 1, st->spec, st->g, py, st->tw, st->tilectr, s));
-    const Prune pz{zlo, zlen, 0, n};
-    const Prune full{0, n, 0, n};
-    LAUNCH(st, s, PF_Z, (1 + frac_z) * sb,
-           launch_z_green(fp64, st->spec, st->g, st->C, pz, st->tw, st->tilectr + 8, s));
-    LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, st->spec, st->g, full, st->tw, st->tilectr + 16, s));
-    LAUNCH(st, s, PF_XI, sb + 2 * fb,
-           launch_x_inverse(fp64, true, st->spec, st->sig, st->g, st->add6 + 12, st->tw, s));
-  }
-  // membership lists and footprint ids of the moved defect (after the sparse
-  // forward pass, which still reads the old footprint)
-  LAUNCH(st, s, PF_RASTER, 0,
-         launch_move_lists(idx, ocnt, od.slot, nids, cnt_new, nd.slot, sh[0], sh[1], sh[2], n, b.ids, b.lnk, st->own,
-                           s));
-  if (!hop) {
-    HIPCHK(hipMemcpyAsync(b.cnt + idx, up + 144, 4, hipMemcpyHostToDevice, s));
-    if (nd.slot != od.slot) {
-      st->ids_used += cap_new;
-      st->hcap[idx] = cap_new;
-    }
-    if (st->hcnt_ok) st->hcnt[idx] = cnt_new;
-    st->B_valid = false;
-    if (st->classes.size() != ncls_before) st->gcls_ncls = -1;
-  }
-  HIPCHK(hipMemcpyAsync(b.tab + idx, up + 152, sizeof nd, hipMemcpyHostToDevice, s));
-  if ((r = pin_end(st->pin_upd, s)) != EC_OK) return r;
-  st->hdefs[idx] = nd;
+  ec_status r0 = update_q(st, idx, nd, s);
+  if (r0 != EC_OK) return r0;
   if (E_out) return ec_interaction_energies(st, stream, E_out, on_device);
   return EC_OK;
 }
@@ -1669,6 +1678,7 @@ ec_status ec_profile_read(ec_state* st, int64_t* launches, double* ms, double* b
 // ---------------------------------------------------------------- jump probes
 
 constexpr int JUMP_MAX = 8;  // largest jump component, in voxels
+constexpr int OKMC_FEW = 1;  // acting defects up to which a step moves them one by one
 
 ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t njump, void* stream, double* dE_out,
                            int32_t on_device) {
@@ -1783,6 +1793,28 @@ ec_status ec_okmc_step(ec_state* st, const int32_t* jumps, int32_t njump, const 
   std::vector<int32_t> ch(nd);
   const int n = st->n;
   const int32_t Lq = QSUB * n;
+  // the gate needs only the nominal frequencies, so the host knows how many
+  // defects act; a few are moved one by one with the incremental update (each
+  // a fraction of a re-solve), all choices still taken against the field at
+  // the start of the step
+  int acting = 0;
+  for (int i = 0; i < nd; ++i) acting += u[i] > std::exp(-nu0 * std::exp(-Em[i] / kT) * dt);
+  if (acting <= OKMC_FEW) {
+    if ((r = run_select(st, Em, nu0, kT, xi, u, dt, s, nullptr, ch.data(), false)) != EC_OK) return r;
+    for (int i = 0; i < nd; ++i) {
+      if (ch[i] < 0) continue;
+      DevDefect q = st->hdefs[i];
+      const int32_t* lam = jumps + ((size_t)i * njump + ch[i]) * 3;
+      for (int k = 0; k < 3; ++k) {
+        q.cq[k] = (int32_t)((((int64_t)q.cq[k] + (int64_t)lam[k] * QSUB) % Lq + Lq) % Lq);
+        q.lo[k] = ((q.lo[k] + lam[k]) % n + n) % n;
+      }
+      if ((r = update_q(st, i, q, s)) != EC_OK) return r;
+    }
+    if (choice_out) std::memcpy(choice_out, ch.data(), (size_t)nd * 4);
+    if (E_out) return ec_interaction_energies(st, stream, E_out, 0);
+    return EC_OK;
+  }
   if (st->B_valid && st->classes_ok) {
     // the probe left the self terms and classes current, and a translation by
     // whole voxels keeps every footprint's shape: the choices stay on the

@@ -9,6 +9,7 @@ are integers decided in FP64 on both sides and compared exactly."""
 import numpy as np
 import pytest
 
+from oracle import energy as oenergy
 from oracle import okmc as ookmc
 from paper_2403_09158_amd import inputs
 
@@ -186,3 +187,34 @@ def test_okmc_step_on_an_empty_list(ctx):
     choice = st.okmc_step(np.zeros((0, 2, 3), dtype=np.int32), z, NU0, KT, z, z)
     assert choice.shape == (0,)
     st.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_okmc_step_with_one_acting_defect(ctx, prec):
+    """A short step in which one defect acts (moved with the incremental
+    update) against the oracle's step and a fresh solve."""
+    from paper_2403_09158_amd import ec
+
+    rng, prob, d, J, Em = _population(892, 48, 20, prec)
+    u = 1.0 - rng.uniform(size=len(d))
+    xi = 1.0 - rng.uniform(size=len(d))
+    st = ec.State(ctx, prob)
+    st.solve(d)
+    choice, E = st.okmc_step(J, Em, NU0, KT, u, xi, dt=1.0e-12, energies=True)
+    N, want_choice, moved, want_E = ookmc.okmc_step(prob.with_(prec=0), d, J, Em, NU0, KT, 1.0e-12, u, xi)
+    assert (choice >= 0).sum() == 1
+    if prec == 0:
+        assert np.array_equal(choice, want_choice)
+        assert np.abs(E - want_E).max() <= 1e-10 * np.abs(want_E).max()
+    else:
+        assert np.array_equal(choice >= 0, N > 0)
+        want_E = oenergy.energies_fast(prob, ookmc.move(prob, d, J, choice))
+        assert np.all(np.abs(E - want_E) <= np.maximum(1e-4 * np.abs(want_E), 1e-5))
+    fresh = ec.State(ctx, prob)
+    fresh.solve(ookmc.move(prob, d, J, choice))
+    tol = 1e-10 if prec == 0 else 1e-6
+    assert np.abs(E - fresh.energies()).max() <= tol * np.abs(E).max()
+    # the probe after the step still reuses its cross parts (hops keep them)
+    assert np.allclose(st.jump_energies(J), fresh.jump_energies(J), rtol=0, atol=tol * np.abs(E).max())
+    st.close()
+    fresh.close()
