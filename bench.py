@@ -536,6 +536,7 @@ def main():
     ap.add_argument("--jumps-only", action="store_true", help="run the jump-probe, dipole and OkMC workloads alone")
     ap.add_argument("--okmc-only", action="store_true", help="run the OkMC-step workload alone (profiling runs)")
     ap.add_argument("--probe-only", action="store_true", help="run the jump-probe workload alone (profiling runs)")
+    ap.add_argument("--dipole-only", action="store_true", help="run the dipole-tensor workload alone (profiling runs)")
     ap.add_argument("--no-frame", action="store_true", help="skip the rotated-crystal and dislocation workloads")
     ap.add_argument("--frame-only", action="store_true", help="run the rotated-crystal and dislocation workloads alone")
     ap.add_argument(
@@ -567,6 +568,9 @@ def main():
         return
     if args.frame_only:
         print(json.dumps({"frame_111": frame_block(), "dislocation": dislocation_block()}), flush=True)
+        return
+    if args.dipole_only:
+        print(json.dumps({"dipole": dipole_block()}), flush=True)
         return
     if args.probe_only:
         print(json.dumps({"jump_probe": jump_probe_block()}), flush=True)
