@@ -137,3 +137,25 @@ def test_lines_without_defects(ctx):
     sig_o = to6(odl.dislocation_stress(prob, _oracle_lines(lines)))
     assert rel_l2(st.field("sigma"), sig_o) < 1e-12
     st.close()
+
+
+def test_lines_along_every_axis(ctx):
+    """One line along each cell axis (mixed Burgers vectors), with defects."""
+    from paper_2403_09158_amd import ec
+
+    prob, d, _ = _case()
+    h = prob.h
+    lines = np.concatenate(
+        [
+            inputs.line(np.array([0.0, 9.3, 20.8]) * h, 0, 1, np.array([0.12, 0.05, -0.07])),
+            inputs.line(np.array([27.1, 0.0, 5.6]) * h, 1, 1, np.array([-0.1, 0.15, 0.02])),
+            inputs.line(np.array([3.4, 29.9, 0.0]) * h, 2, -1, np.array([0.0, 0.08, 0.2])),
+        ]
+    )
+    sig_o, E_o = _oracle(prob, d, lines)
+    st = ec.State(ctx, prob)
+    st.set_dislocations(lines)
+    st.solve(d)
+    assert rel_l2(st.field("sigma"), sig_o) < 1e-12
+    assert energy_ok_fp64(st.energies(), E_o)
+    st.close()

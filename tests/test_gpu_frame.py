@@ -120,3 +120,29 @@ def test_frame_checks(ctx):
         with pytest.raises(ec.EcError) as ei:
             ec.State(ctx, prob)
         assert ei.value.status == ec.EC_ERR_ARG
+
+
+@pytest.mark.parametrize("n", [8, 16, 24, 48, 64])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rotated_every_small_size(ctx, n, prec):
+    """The rotated Green step of every small grid size against the oracle's
+    fields (one sphere and one 1/2[111] loop along the cell x axis)."""
+    from paper_2403_09158_amd import ec
+
+    h = inputs.H_VOXEL
+    prob = inputs.Problem(n, n * h, *inputs.CUBIC_FE, prec=prec, frame=inputs.FRAME_111)
+    bx = 0.5 * inputs.A_FE * np.sqrt(3.0) * np.array([1.0, 0.0, 0.0])
+    r = max(1.2, n / 10.0) * h
+    d = np.concatenate(
+        [
+            inputs.loop(np.array([0.3 * n, 0.4 * n, 0.55 * n]) * h, r, bx, bx),
+            inputs.sphere(np.array([0.7 * n + 0.5, 0.6 * n + 0.5, 0.2 * n + 0.5]) * h, r, 0.01),
+        ]
+    )
+    fps, Es = raster.rasterise(prob, d)
+    es = raster.eigenstrain_field(prob.n, fps, Es)
+    _, sig_o, _ = solve.solve_field(elastic.stiffness_of(prob), prob.L, es, prob.bc)
+    st = ec.State(ctx, prob)
+    st.solve(d)
+    assert rel_l2(st.field("sigma"), to6(sig_o)) < (1e-12 if prec == 0 else 1e-5)
+    st.close()
