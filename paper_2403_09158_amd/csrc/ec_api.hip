@@ -501,6 +501,32 @@ int64_t isqrt64(int64_t v) {
   return r;
 }
 
+// Whether a problem's frame rotates the crystal (all zeros and the identity do not).
+bool frame_rotates(const double* fr) {
+  bool any = false, id = true;
+  for (int k = 0; k < 9; ++k) {
+    any |= fr[k] != 0.0;
+    id &= fr[k] == (k % 4 == 0 ? 1.0 : 0.0);
+  }
+  return any && !id;
+}
+
+// Tensor components (xx yy zz yz xz xy) in the cube frame, T_c = A^T T A, for a
+// frame A whose rows are the cell axes in cube coordinates.
+void to_cube(const double* A, const double* t, double* out) {
+  const double T[3][3] = {{t[0], t[5], t[4]}, {t[5], t[1], t[3]}, {t[4], t[3], t[2]}};
+  double U[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int q = 0; q < 3; ++q) U[i][q] = T[i][0] * A[q] + T[i][1] * A[3 + q] + T[i][2] * A[6 + q];
+  auto tc = [&](int p, int q) { return A[p] * U[0][q] + A[3 + p] * U[1][q] + A[6 + p] * U[2][q]; };
+  out[0] = tc(0, 0);
+  out[1] = tc(1, 1);
+  out[2] = tc(2, 2);
+  out[3] = tc(1, 2);
+  out[4] = tc(0, 2);
+  out[5] = tc(0, 1);
+}
+
 bool quantise(const ec_problem& P, const ec_defect& rec, DevDefect& d, std::string& err) {
   std::memset(&d, 0, sizeof d);
   const int n = P.n;
@@ -559,9 +585,18 @@ bool quantise(const ec_problem& P, const ec_defect& rec, DevDefect& d, std::stri
   d.E[3] = E[1][2];
   d.E[4] = E[0][2];
   d.E[5] = E[0][1];
+  // the rasterised eigenstrain (fixed point) is kept in the cube frame of a
+  // rotated crystal, where the Green step applies the cubic operator; E stays
+  // in cell coordinates for the energies
+  double Ef[6];
+  if (frame_rotates(P.frame))
+    to_cube(P.frame, d.E, Ef);
+  else
+    std::copy(d.E, d.E + 6, Ef);
   for (int a = 0; a < 6; ++a) {
-    if (!(std::fabs(d.E[a]) < 64.0)) return err = "eigenstrain component too large", false;
-    d.efix[a] = (int64_t)std::llrint(d.E[a] * FIX_SCALE);
+    if (!(std::fabs(d.E[a]) < 64.0) || !(std::fabs(Ef[a]) < 64.0))
+      return err = "eigenstrain component too large", false;
+    d.efix[a] = (int64_t)std::llrint(Ef[a] * FIX_SCALE);
   }
   for (int k = 0; k < 3; ++k) {
     const int64_t lo = floordiv((int64_t)d.cq[k] - ext - 512 + (QSUB - 1), QSUB);
@@ -755,7 +790,15 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
     // six one-voxel "defects" with unit eigenstrain component b at voxel 0
     DevDefect unit[6];
     std::memset(unit, 0, sizeof unit);
-    for (int b = 0; b < 6; ++b) unit[b].efix[b] = (int64_t)FIX_SCALE;
+    for (int b = 0; b < 6; ++b) {
+      double e[6] = {0, 0, 0, 0, 0, 0}, ec[6];
+      e[b] = 1.0;
+      if (st->frm)
+        to_cube(st->frame.data(), e, ec);  // the unit component in the cube frame
+      else
+        std::copy(e, e + 6, ec);
+      for (int a = 0; a < 6; ++a) unit[b].efix[a] = (int64_t)std::llrint(ec[a] * FIX_SCALE);
+    }
     DevDefect* dunit = (DevDefect*)imp;
     int2* dlnk = (int2*)((char*)imp + 6 * sizeof(DevDefect));
     HIPCHK(hipStreamSynchronize(s));
@@ -1259,7 +1302,13 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
   // --- commit
   char* up = nullptr;  // [E 48][efix 48][dadd 48][count 8][record]
   if ((r = pin_begin(st->pin_upd, 152 + sizeof(DevDefect), &up)) != EC_OK) return r;
-  std::memcpy(up, nd.E, 48);
+  if (st->frm) {
+    double ec[6];
+    to_cube(st->frame.data(), nd.E, ec);  // the sparse transform works in the cube frame
+    std::memcpy(up, ec, 48);
+  } else {
+    std::memcpy(up, nd.E, 48);
+  }
   std::memcpy(up + 48, nd.efix, 48);
   std::memcpy(up + 96, dadd, 48);
   std::memcpy(up + 144, &cnt_new, 4);

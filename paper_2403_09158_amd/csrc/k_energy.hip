@@ -732,7 +732,12 @@ __global__ void k_sig_to_out(const double* __restrict__ sig, const int32_t* __re
     for (int c = 0; c < 6; ++c) es[c] = (double)acc[c] * FIX_INV;
   }
   if (which == 2) {
-    for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)es[a];
+    double el[6];
+    if (C.frm)
+      rot6(C.frm + 36, es, el);  // the rasterised eigenstrain is kept in the cube frame
+    else
+      for (int a = 0; a < 6; ++a) el[a] = es[a];
+    for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)el[a];
     return;
   }
   double s[6];
@@ -753,12 +758,15 @@ __global__ void k_sig_to_out(const double* __restrict__ sig, const int32_t* __re
   ec[1] = S11 * sc[1] + S12 * (sc[0] + sc[2]);
   ec[2] = S11 * sc[2] + S12 * (sc[0] + sc[1]);
   for (int a = 3; a < 6; ++a) ec[a] = S44h * sc[a];
-  if (C.frm)
+  if (C.frm) {
+    // eps = C^-1:sigma + eps*, both in the cube frame, then back to the cell
+    for (int a = 0; a < 6; ++a) ec[a] += es[a];
     rot6(C.frm + 36, ec, e);
-  else
-    for (int a = 0; a < 6; ++a) e[a] = ec[a];
+  } else {
+    for (int a = 0; a < 6; ++a) e[a] = ec[a] + es[a];
+  }
 #pragma unroll
-  for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)(e[a] + es[a]);
+  for (int a = 0; a < 6; ++a) out[a * n3 + t] = (OT)e[a];
 }
 
 __global__ __launch_bounds__(256) void k_set_class(DevDefect* __restrict__ defs, int ndef,

@@ -697,23 +697,11 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
       stage<N, R2, R0 * R1, false, Map::Pencil, NF, T>(tw, from_lds, to_lds, true, tid);
     }
     __syncthreads();
-    // Green step: one bin (all six components) per iteration, in place.  A
-    // rotated crystal takes three loops (eps*_hat into the cube frame, the cubic
-    // operator with rotated labels, sigma_hat back), each thread on the same
-    // bins throughout, so that each loop's registers stay few.
-    if constexpr (ROT) {
-#pragma unroll 1
-      for (int b = tid; b < N * W; b += T) {
-        const int bw = b % W, kz = b / W;
-        if (kx - w + bw >= NH) continue;
-        double2 e[6], r[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) e[c] = from_lds(bw * 6 + c, kz);
-        rot6(C.frm, e, r);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) to_lds(bw * 6 + c, kz, r[c]);
-      }
-    }
+    // Green step: one bin (all six components) per iteration, in place.  For
+    // a rotated crystal eps*_hat arrives in the cube frame (the rasterised
+    // eigenstrain is kept there), the cubic operator takes rotated labels, and
+    // a second loop over the same bins of each thread turns sigma_hat back to
+    // the cell frame (one loop for both pushed the FP32 tile past 256 VGPRs).
 #pragma unroll 1
     for (int b = tid; b < N * W; b += T) {
       const int bw = b % W, kz = b / W, bkx = kx - w + bw;
