@@ -448,3 +448,45 @@ def test_raster_rejects_invalid_defects():
     for d in bad:
         with pytest.raises(raster.DefectError):
             raster.rasterise(prob, d)
+
+
+# ------------------------------------------------ loop eigenstrain amplitude (Sec. 2.1, 3.1)
+
+
+@pytest.mark.parametrize(
+    "family,R_vox,e_vox,n",
+    [("100", 8.0, 1.0, 32), ("100", 12.5, 1.0, 32), ("100", 10.0, 2.0, 32), ("111", 8.0, math.sqrt(3.0), 32),
+     ("111", 12.0, math.sqrt(3.0), 40)],
+)
+def test_loop_dipole_tensor_matches_the_paper(family, R_vox, e_vox, n):
+    """The loop eigenstrain sym(b x n)/e of Sec. 3.1 has the dipole tensor the
+    paper prints for a loop (Sec. 4.2): P = 1/2 C:(b x A + A x b), A = pi R^2 n
+    its oriented area.  With <eps> = 0 (equal displacements on opposite cell
+    faces) the paper's appendix gives P = -(integral of sigma over the cell), so
+    the oracle's solve must return -h^3 sum_x sigma(x) = that P, up to the
+    count of voxel centres in the discrete slab against its continuum volume
+    (a few per cent here).  The <100> slabs hold one or two whole lattice
+    planes; the (111) slab of thickness sqrt(3) h holds three planes of density
+    1/(sqrt(3) h^2), i.e. sqrt(3) planes per h.  A dropped 1/2 of the symmetric
+    part, a division by h instead of e or a sign error is off by a factor of 2,
+    sqrt(3), 2 or -1 and fails."""
+    h = inputs.H_VOXEL
+    L = n * h
+    prob = inputs.Problem(n, L, *inputs.CUBIC_FE, bc=1)
+    if family == "100":
+        b = inputs.A_FE * np.array([1.0, 0.0, 0.0])
+        nrm = np.array([1.0, 0.0, 0.0])
+    else:
+        b = 0.5 * inputs.A_FE * np.array([1.0, 1.0, 1.0])
+        nrm = np.array([1.0, 1.0, 1.0])
+    c = (np.full(3, n // 2) + 0.5) * h  # a voxel centre: the slab planes sit symmetrically
+    d = inputs.loop(c, R_vox * h, b, nrm, thickness=e_vox * h)
+    fps, Es = raster.rasterise(prob, d)
+    es = raster.eigenstrain_field(n, fps, Es)
+    C = elastic.stiffness_of(prob)
+    _, sig, _ = solve.solve_field(C, L, es, bc=1)
+    P_num = -(h**3) * sig.sum(axis=(2, 3, 4))
+    A = math.pi * (R_vox * h) ** 2 * nrm / np.linalg.norm(nrm)
+    P_paper = 0.5 * np.einsum("ijkl,kl->ij", C, np.outer(b, A) + np.outer(A, b))
+    assert np.linalg.norm(P_num - P_paper) <= 0.03 * np.linalg.norm(P_paper)
+    assert np.allclose(P_num, P_num.T, rtol=0, atol=1e-12 * np.abs(P_num).max())
