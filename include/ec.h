@@ -125,6 +125,7 @@ typedef void (*ec_free_fn)(void* p, void* stream, void* user);
  * (n, C, bc). */
 EC_API ec_status ec_ctx_create(int device, size_t hbm_budget_bytes, ec_alloc_fn alloc_fn, ec_free_fn free_fn,
                         void* user, ec_ctx** out);
+/* Destroy every state of a context before the context itself. */
 EC_API void ec_ctx_destroy(ec_ctx* ctx);
 
 /* Bytes the context has admitted so far, and its budget. */

@@ -48,7 +48,16 @@ ec_status fail(ec_status s, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(EC_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+}  // namespace
+
+// A window of the discrete Green kernel, shared by the states of one problem.
+// States hold it by shared_ptr: when a wider window replaces it in the
+// context's cache, the old one stays alive (and its device memory allocated)
+// until the last state using it lets go; its destructor waits for the device
+// before freeing.  It must never be destroyed while the context's mutex is
+// held (the free takes that mutex for the ledger).
 struct WinCache {
+  ec_ctx* ctx = nullptr;
   int n = 0;
   double C11 = 0, C12 = 0, C44 = 0;
   std::array<double, 9> frame{};  // all zeros: cube axes
@@ -56,9 +65,8 @@ struct WinCache {
   int D = 0;
   double* K = nullptr;
   size_t bytes = 0;
+  ~WinCache();
 };
-
-}  // namespace
 
 // Host worker threads for per-defect preparation of large defect lists.
 // run(n, fn) calls fn(c) for every chunk c in [0, n) on the workers and the
@@ -155,7 +163,7 @@ struct ec_ctx {
   void* user = nullptr;
   std::mutex mu;
   std::map<int, double2*> tw;
-  std::vector<WinCache> wins;
+  std::vector<std::shared_ptr<WinCache>> wins;
   std::unique_ptr<WorkPool> pool;
 };
 
@@ -233,7 +241,7 @@ struct ec_state {
   double* gcls = nullptr;
   size_t gcls_bytes = 0;
   int gcls_D = -1, gcls_ncls = -1;
-  const WinCache* win = nullptr;
+  std::shared_ptr<const WinCache> win;
   std::array<double, 9> frame{};  // the problem's frame, all zeros for cube axes
   std::array<double, FRAME_LEN> frmh{};  // host copy of its maps
   // dislocation lines: stress planes per axis ([3][n^2][6]) added to every
@@ -256,7 +264,7 @@ struct ec_state {
   // update scratch
   int32_t* upd_ids = nullptr;
   int64_t upd_cap = 0;
-  double* updE = nullptr;     // 6 doubles
+  double* updE = nullptr;     // 12 doubles: the old and the new eigenstrain of a moved defect
   uint32_t* tilectr = nullptr;  // NTILECTR tile counters of the persistent passes
   // jump probes: energy changes of the last ec_jump_energies call (jn per
   // defect) and their scratch
@@ -280,7 +288,6 @@ struct ec_state {
   size_t jchoice_cap = 0;
   double* dip = nullptr;  // dipole-tensor energies
   size_t dip_cap = 0;
-  int64_t* updfix = nullptr;  // 6 int64
   // pinned staging: defect table, per-update records, moved footprint
   Pinned pin_tab, pin_upd, pin_ids, pin_tags, pin_jump, pin_choice, pin_out;
   // profiling
@@ -338,6 +345,16 @@ void ledger_free(ec_ctx* c, void* p, size_t bytes) {
   raw_free(c, p);
   release(c, bytes);
 }
+
+}  // namespace
+
+WinCache::~WinCache() {
+  if (!K) return;
+  (void)hipDeviceSynchronize();  // kernels of any stream may still read the window
+  ledger_free(ctx, K, bytes);
+}
+
+namespace {
 
 template <class T>
 ec_status st_grow(ec_state* st, T** p, size_t* cap_elems, size_t need, bool keep = false, hipStream_t s = nullptr) {
@@ -701,14 +718,14 @@ ec_status join_self(ec_state* st, hipStream_t s);
 // `between` (may be empty) runs on the host after the forward x and y passes
 // are enqueued and before the z pass is.
 ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs,
-                   void* spec, double* sig, const double* add6, uint32_t* ctr,
+                   int ndef, void* spec, double* sig, const double* add6, uint32_t* ctr,
                    const std::function<ec_status()>& between = {}, const double* bg = nullptr, int bg_mask = 0) {
   const Prune full{0, st->n, 0, st->n};
   const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
   SpecGeom g{st->n, 0};
   g.P = spec_pitch(st->n, fp64);
   LAUNCH(st, s, PF_XF, 4.0 * (double)st->n3 + sb,
-         launch_x_forward(fp64, own, lnk, defs, nullptr, spec, g, st->tw, ctr, s));
+         launch_x_forward(fp64, own, lnk, defs, ndef, nullptr, spec, g, st->tw, ctr, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, false, 1, spec, g, full, st->tw, ctr ? ctr : nullptr, s));
   if (between) {
     const ec_status r = between();
@@ -740,18 +757,33 @@ void neg_C_dot(const ec_state* st, const double* m, double* out) {
 }
 
 // Window of the discrete kernel G for this problem: six FP64 impulse solves.
+// The context caches one window per problem (n, C, mean condition, frame); a
+// wider one replaces it in the cache, and states still holding the narrower
+// one keep it alive until they move on (see WinCache).
 ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
   ec_ctx* c = st->ctx;
+  Dneed = std::max(1, std::min(Dneed, st->n / 2));
+  auto same_problem = [&](const WinCache& w) {
+    return w.n == st->n && w.C11 == st->C.C11 && w.C12 == st->C.C12 && w.C44 == st->C.C44 && w.bc == st->prob.bc &&
+           w.frame == st->frame;
+  };
   {
-    std::lock_guard<std::mutex> lk(c->mu);
-    for (auto& w : c->wins)
-      if (w.n == st->n && w.C11 == st->C.C11 && w.C12 == st->C.C12 && w.C44 == st->C.C44 && w.bc == st->prob.bc &&
-          w.frame == st->frame && w.D >= Dneed) {
-        st->win = &w;
-        return EC_OK;
-      }
+    std::shared_ptr<const WinCache> found;
+    {
+      std::lock_guard<std::mutex> lk(c->mu);
+      for (auto& w : c->wins)
+        if (same_problem(*w) && w->D >= Dneed) {
+          found = w;
+          break;
+        }
+    }
+    if (found) {
+      if (found != st->win) st->gcls_D = -1;
+      st->win = std::move(found);  // a window released here is freed outside the lock
+      return EC_OK;
+    }
   }
-  const int D = std::max(1, std::min(Dneed, st->n / 2));
+  const int D = Dneed;
   const int W = 2 * D + 1;
   const size_t Kbytes = (size_t)W * W * W * KWIN * sizeof(double);
   const int n = st->n;
@@ -809,7 +841,7 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
     for (int b = 0; b < 6; ++b) {
       HIPCHK(launch_fill_i32((int32_t*)own, 1, b, s));  // voxel 0 owned by unit defect b
       ec_status q =
-          pipeline(st, s, true, (const int32_t*)own, dlnk, dunit, sp, (double*)sg, (const double*)ad + 8 * b, nullptr);
+          pipeline(st, s, true, (const int32_t*)own, dlnk, dunit, 6, sp, (double*)sg, (const double*)ad + 8 * b, nullptr);
       if (q != EC_OK) return q;
       HIPCHK(launch_window_crop((const double*)sg, n, D, b, (double*)K, s));
     }
@@ -823,33 +855,31 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
     ledger_free(c, K, Kbytes);
     return r;
   }
-  std::lock_guard<std::mutex> lk(c->mu);
-  for (auto it = c->wins.begin(); it != c->wins.end(); ++it)
-    if (it->n == st->n && it->C11 == st->C.C11 && it->C12 == st->C.C12 && it->C44 == st->C.C44 &&
-        it->bc == st->prob.bc && it->frame == st->frame) {
-      // states still pointing at the old window refresh through ensure_window;
-      // no kernel of any stream may still read it
-      (void)hipDeviceSynchronize();
-      raw_free(c, it->K);
-      c->used -= std::min(c->used, it->bytes);
-      c->wins.erase(it);
-      break;
+  auto w = std::make_shared<WinCache>();
+  w->ctx = c;
+  w->n = st->n;
+  w->C11 = st->C.C11;
+  w->C12 = st->C.C12;
+  w->C44 = st->C.C44;
+  w->bc = st->prob.bc;
+  w->frame = st->frame;
+  w->D = D;
+  w->K = (double*)K;
+  w->bytes = Kbytes;
+  std::vector<std::shared_ptr<WinCache>> dropped;  // released after the lock
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    for (auto it = c->wins.begin(); it != c->wins.end();) {
+      if (same_problem(**it) && (*it)->D <= D) {
+        dropped.push_back(std::move(*it));
+        it = c->wins.erase(it);
+      } else {
+        ++it;
+      }
     }
-  WinCache w;
-  w.n = st->n;
-  w.C11 = st->C.C11;
-  w.C12 = st->C.C12;
-  w.C44 = st->C.C44;
-  w.bc = st->prob.bc;
-  w.frame = st->frame;
-  w.D = D;
-  w.K = (double*)K;
-  w.bytes = Kbytes;
-  c->wins.reserve(c->wins.size() + 1);
-  c->wins.push_back(w);
-  st->win = nullptr;
-  for (auto& x : c->wins)
-    if (x.K == (double*)K) st->win = &x;
+    c->wins.push_back(w);
+  }
+  st->win = w;
   st->gcls_D = -1;
   return EC_OK;
 }
@@ -891,7 +921,7 @@ ec_status ensure_classes(ec_state* st, hipStream_t s) {
 ec_status ensure_windows(ec_state* st, int reach, hipStream_t s) {
   ec_status r = ensure_window(st, window_need(st) + reach, s);
   if (r != EC_OK) return r;
-  const WinCache* w = st->win;
+  const WinCache* w = st->win.get();
   const int D = w->D;
   const int W = 2 * D + 1;
   const size_t W3 = (size_t)W * W * W;
@@ -924,7 +954,7 @@ ec_status compute_self_terms(ec_state* st, hipStream_t s) {
   ec_status r = ensure_classes(st, s);
   if (r != EC_OK) return r;
   if ((r = ensure_windows(st, 0, s)) != EC_OK) return r;
-  const WinCache* w = st->win;
+  const WinCache* w = st->win.get();
   const int D = w->D;
   // Work-list capacity: at most 64 items per defect, fewer for small boxes.
   int64_t cap = 0;
@@ -993,14 +1023,14 @@ ec_status write_field(ec_state* st, int which, void* out, bool on_device, hipStr
   if (on_device) {
     const DefBuf& b = st->db[st->cur];
     LAUNCH(st, s, PF_OTHER, 96.0 * st->n3,
-           launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, which, f32, out, s));
+           launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->ndef, st->n3, st->C, which, f32, out, s));
     return EC_OK;
   }
   void* tmp = nullptr;
   ec_status r = ledger_alloc(st->ctx, bytes, &tmp);
   if (r != EC_OK) return r;
   const DefBuf& b = st->db[st->cur];
-  hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, which, f32, tmp, s);
+  hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->ndef, st->n3, st->C, which, f32, tmp, s);
   if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   ledger_free(st->ctx, tmp, bytes);
@@ -1182,7 +1212,7 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
     return q == EC_OK ? join_self(st, s) : q;
   };
   // the stress of dislocation lines, if any, is added by the x inverse pass
-  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, st->spec, st->sig, st->add6, st->tilectr, beside, st->bg,
+  r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, ndef, st->spec, st->sig, st->add6, st->tilectr, beside, st->bg,
                st->bg_mask);
   if (r != EC_OK) return r;
   st->solved = true;
@@ -1300,16 +1330,21 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
     neg_C_dot(st, m, dadd);
   }
   // --- commit
-  char* up = nullptr;  // [E 48][efix 48][dadd 48][count 8][record]
+  // [old E 48][new E 48][dadd 48][count 8][record]: the eigenstrain change is
+  // -E_old on the old footprint and +E_new on the new one; both as the
+  // rasterised field holds them (the fixed-point components, in the cube
+  // frame of a rotated crystal, where the sparse transform works)
+  char* up = nullptr;
   if ((r = pin_begin(st->pin_upd, 152 + sizeof(DevDefect), &up)) != EC_OK) return r;
-  if (st->frm) {
-    double ec[6];
-    to_cube(st->frame.data(), nd.E, ec);  // the sparse transform works in the cube frame
-    std::memcpy(up, ec, 48);
-  } else {
-    std::memcpy(up, nd.E, 48);
+  {
+    double eo[6], en[6];
+    for (int a = 0; a < 6; ++a) {
+      eo[a] = (double)od.efix[a] * FIX_INV;
+      en[a] = (double)nd.efix[a] * FIX_INV;
+    }
+    std::memcpy(up, eo, 48);
+    std::memcpy(up + 48, en, 48);
   }
-  std::memcpy(up + 48, nd.efix, 48);
   std::memcpy(up + 96, dadd, 48);
   std::memcpy(up + 144, &cnt_new, 4);
   std::memcpy(up + 152, &nd, sizeof nd);
@@ -1320,8 +1355,7 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(st->upd_ids, ip, (size_t)cnt_new * 4, hipMemcpyHostToDevice, s));
     if ((r = pin_end(st->pin_ids, s)) != EC_OK) return r;
   }
-  HIPCHK(hipMemcpyAsync(st->updE, up, 48, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(st->updfix, up + 48, 48, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(st->updE, up, 96, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(st->add6 + 12, up + 96, 48, hipMemcpyHostToDevice, s));
   const int32_t* oids = b.ids + od.slot;
   const int32_t* ocnt = b.cnt + idx;
@@ -1346,8 +1380,8 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
   // membership lists and footprint ids of the moved defect (after the sparse
   // forward pass, which still reads the old footprint)
   LAUNCH(st, s, PF_RASTER, 0,
-         launch_move_lists(idx, ocnt, od.slot, nids, cnt_new, nd.slot, sh[0], sh[1], sh[2], n, b.ids, b.lnk, st->own,
-                           s));
+         launch_move_lists(idx, st->ndef, ocnt, od.slot, nids, cnt_new, nd.slot, sh[0], sh[1], sh[2], n, b.ids, b.lnk,
+                           st->own, s));
   if (!hop) {
     HIPCHK(hipMemcpyAsync(b.cnt + idx, up + 144, 4, hipMemcpyHostToDevice, s));
     if (nd.slot != od.slot) {
@@ -1396,7 +1430,7 @@ ec_status ec_ctx_create(int device, size_t budget, ec_alloc_fn af, ec_free_fn ff
 void ec_ctx_destroy(ec_ctx* c) {
   if (!c) return;
   for (auto& kv : c->tw) raw_free(c, kv.second);
-  for (auto& w : c->wins) raw_free(c, w.K);
+  c->wins.clear();  // windows no state holds any more are freed here
   delete c;
 }
 
@@ -1461,7 +1495,7 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
     delete st;
     return fail(EC_ERR_DEVICE, "twiddle table allocation failed");
   }
-  void *sp = nullptr, *own = nullptr, *sg = nullptr, *ad = nullptr, *dirs = nullptr, *ue = nullptr, *uf = nullptr;
+  void *sp = nullptr, *own = nullptr, *sg = nullptr, *ad = nullptr, *dirs = nullptr, *ue = nullptr;
   void* tc = nullptr;
   void* fm = nullptr;
   const size_t ob = (size_t)st->n3 * 4;
@@ -1472,15 +1506,14 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
     ledger_free(c, sg, fb);
     ledger_free(c, ad, 256);
     ledger_free(c, dirs, MAXCLS * 48);
-    ledger_free(c, ue, 64);
-    ledger_free(c, uf, 64);
+    ledger_free(c, ue, 128);
     ledger_free(c, tc, 128);
     ledger_free(c, fm, FRAME_LEN * 8);
   };
   if ((r = ledger_alloc(c, st->spec_bytes, &sp)) != EC_OK || (r = ledger_alloc(c, ob, &own)) != EC_OK ||
       (r = ledger_alloc(c, fb, &sg)) != EC_OK || (r = ledger_alloc(c, 256, &ad)) != EC_OK ||
-      (r = ledger_alloc(c, MAXCLS * 48, &dirs)) != EC_OK || (r = ledger_alloc(c, 64, &ue)) != EC_OK ||
-      (r = ledger_alloc(c, 64, &uf)) != EC_OK || (r = ledger_alloc(c, 128, &tc)) != EC_OK ||
+      (r = ledger_alloc(c, MAXCLS * 48, &dirs)) != EC_OK || (r = ledger_alloc(c, 128, &ue)) != EC_OK ||
+      (r = ledger_alloc(c, 128, &tc)) != EC_OK ||
       (rotated && (r = ledger_alloc(c, FRAME_LEN * 8, &fm)) != EC_OK)) {
     undo();
     delete st;
@@ -1492,7 +1525,6 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
   st->add6 = (double*)ad;
   st->dirs = (double*)dirs;
   st->updE = (double*)ue;
-  st->updfix = (int64_t*)uf;
   st->tilectr = (uint32_t*)tc;
   st->frm = (double*)fm;
   st->C.frm = st->frm;
@@ -1521,8 +1553,7 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->sig, fb);
   ledger_free(c, st->add6, 256);
   ledger_free(c, st->dirs, MAXCLS * 48);
-  ledger_free(c, st->updE, 64);
-  ledger_free(c, st->updfix, 64);
+  ledger_free(c, st->updE, 128);
   ledger_free(c, st->tilectr, 128);
   for (auto& b : st->db) {
     ledger_free(c, b.tab, b.cap * sizeof(DevDefect));
@@ -1675,7 +1706,7 @@ ec_status ec_state_field(ec_state* st, int32_t which, double* out) {
     ec_status r = ledger_alloc(st->ctx, cnt * 8, &tmp);
     if (r != EC_OK) return r;
     const DefBuf& b = st->db[st->cur];
-    hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->n3, st->C, which, false, tmp, nullptr);
+    hipError_t e = launch_sig_to_out(st->sig, st->own, b.lnk, b.tab, st->ndef, st->n3, st->C, which, false, tmp, nullptr);
     if (e == hipSuccess) e = hipMemcpy(out, tmp, cnt * 8, hipMemcpyDeviceToHost);
     ledger_free(st->ctx, tmp, cnt * 8);
     if (e != hipSuccess) return fail(EC_ERR_DEVICE, "field output %d: %s", which, hipGetErrorString(e));
@@ -2066,7 +2097,7 @@ ec_status ec_debug_forward(ec_state* st, const double* field, double* out) {
   if ((r = ledger_alloc(st->ctx, sp.b = st->spec_bytes, &sp.p)) != EC_OK) return r;
   HIPCHK(hipMemcpy(fd.p, field, cnt * 8, hipMemcpyHostToDevice));
   const Prune full{0, st->n, 0, st->n};
-  HIPCHK(launch_x_forward(st->fp64, nullptr, nullptr, nullptr, (const double*)fd.p, sp.p, st->g, st->tw, nullptr,
+  HIPCHK(launch_x_forward(st->fp64, nullptr, nullptr, nullptr, 0, (const double*)fd.p, sp.p, st->g, st->tw, nullptr,
                           nullptr));
   HIPCHK(launch_pencil(st->fp64, false, 1, sp.p, st->g, full, st->tw, nullptr, nullptr));
   HIPCHK(launch_pencil(st->fp64, false, 2, sp.p, st->g, full, st->tw, nullptr, nullptr));
@@ -2101,7 +2132,7 @@ ec_status ec_debug_inverse(ec_state* st, const double* in, double* out) {
   HIPCHK(launch_pencil(st->fp64, true, 1, sp.p, st->g, full, st->tw, nullptr, nullptr));
   HIPCHK(launch_x_inverse(st->fp64, false, sp.p, (double*)sg.p, st->g, (const double*)ad.p, st->tw, nullptr));
   // voxel-major result -> the component-major [6][n^3] of the entry point
-  HIPCHK(launch_sig_to_out((const double*)sg.p, nullptr, nullptr, nullptr, st->n3, st->C, 0, false, cm.p, nullptr));
+  HIPCHK(launch_sig_to_out((const double*)sg.p, nullptr, nullptr, nullptr, 0, st->n3, st->C, 0, false, cm.p, nullptr));
   HIPCHK(hipDeviceSynchronize());
   HIPCHK(hipMemcpy(out, cm.p, cnt * 8, hipMemcpyDeviceToHost));
   return EC_OK;

@@ -12,10 +12,10 @@ namespace ec {
 
 constexpr int QSUB = 1024;  // coordinate quantisation steps per voxel edge (q = h/1024)
 
-// Eigenstrain components are int64 fixed point with 56 fractional bits: the
-// contributions of overlapping defects add exactly and in any order, so the
-// field is deterministic and an incremental move restores untouched voxels bit
-// for bit.  |sum of overlapping components| must stay below 128.
+// Eigenstrain components are int64 fixed point with 56 fractional bits
+// (|component| < 64 per defect): the contributions of overlapping defects add
+// exactly and in any order, so the field is deterministic and an incremental
+// move restores untouched voxels bit for bit.
 //
 // The field itself is not stored densely.  Every voxel keeps a link own[v]:
 //   -1        no defect covers the voxel;
@@ -24,14 +24,31 @@ constexpr int QSUB = 1024;  // coordinate quantisation steps per voxel edge (q =
 //             whose record lnk[e] = {defect, link} continues with a link of the
 //             same three forms.
 // The first defect to reach a voxel stores itself with one compare-and-swap;
-// later ones push an entry with an exchange.  Decoding sums the owners'
-// fixed-point components, so the order of the chain does not matter.
+// later ones push an entry with an exchange.  A chain holds each defect at most
+// once, so it is never longer than the defect count.
 __host__ __device__ constexpr int32_t entry_link(int64_t e) { return (int32_t)(-2 - e); }
 
+constexpr double FIX_SCALE = 72057594037927936.0;  // 2^56
+constexpr double FIX_INV = 1.0 / 72057594037927936.0;
+
+// Eigenstrain of one voxel: the exact sum of its owners' fixed-point
+// components, rounded once to double.  Each component is split as
+// f = hi 2^32 + lo (hi = f >> 32, lo in [0, 2^32)) and the halves are summed
+// separately, so no number of owners can overflow (up to 2^21 owners the two
+// sums stay exact in double); the result is hi 2^-24 + lo 2^-56 with a single
+// rounding, the same value as (double)f * 2^-56 for a single owner.  The walk
+// stops after max_links links (the defect count) whatever the data.
 template <class Defs>
 __device__ __forceinline__ void decode_voxel(int32_t link, const int2* __restrict__ lnk, const Defs& defs,
-                                             int64_t* acc) {
-  for (int guard = 0; guard < 4096 && link != -1; ++guard) {
+                                             double* e, int max_links) {
+  if (link >= 0) {  // one owner (the common case)
+    const int64_t* f = defs[link].efix;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = (double)f[c] * FIX_INV;
+    return;
+  }
+  int64_t hi[6] = {0, 0, 0, 0, 0, 0}, lo[6] = {0, 0, 0, 0, 0, 0};
+  for (int guard = 0; guard < max_links && link != -1; ++guard) {
     int d;
     if (link >= 0) {
       d = link;
@@ -43,11 +60,14 @@ __device__ __forceinline__ void decode_voxel(int32_t link, const int2* __restric
     }
     const int64_t* f = defs[d].efix;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) acc[c] += f[c];
+    for (int c = 0; c < 6; ++c) {
+      hi[c] += f[c] >> 32;
+      lo[c] += (int64_t)(uint32_t)f[c];
+    }
   }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) e[c] = (double)hi[c] * 0x1p-24 + (double)lo[c] * 0x1p-56;
 }
-constexpr double FIX_SCALE = 72057594037927936.0;  // 2^56
-constexpr double FIX_INV = 1.0 / 72057594037927936.0;
 
 // 1 GPa nm^3 in eV (1e-18 J / elementary charge).
 constexpr double GPA_NM3_EV = 1.0e-18 / 1.602176634e-19;
@@ -264,8 +284,10 @@ constexpr int NTILECTR = 24;
 // Owner-list input (own/lnk/defs) or, when dense != nullptr, a dense FP64
 // [6][n^3] field (kernel-level tests).  zero_ctr: NTILECTR counters to zero,
 // or nullptr.
-hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs, const double* dense,
-                            void* spec, SpecGeom g, const double2* tw, uint32_t* zero_ctr, hipStream_t s);
+hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs, int ndef,
+                            const double* dense, void* spec, SpecGeom g, const double2* tw, uint32_t* zero_ctr,
+                            hipStream_t s);
+// E: 12 doubles, the old eigenstrain (on old_ids) then the new one (on the new ids).
 hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, const int32_t* old_cnt, const int32_t* new_ids,
                                    int new_cnt,
                                    int shift_x, int shift_y, int shift_z, const double* E, void* spec, SpecGeom g,
@@ -301,9 +323,9 @@ hipError_t launch_unraster(const DevDefect* d, int ndef, const int32_t* counts, 
 // One defect moved: unlink its old entries [slot, slot + *cnt_old), then link
 // the new ones (new voxel = old shifted by whole voxels when new_ids ==
 // nullptr, else new_ids[0 .. cnt_new) copied into [new_slot, ...)).
-hipError_t launch_move_lists(int def, const int32_t* cnt_old, int64_t old_slot, const int32_t* new_ids, int cnt_new,
-                             int64_t new_slot, int shift_x, int shift_y, int shift_z, int n, int32_t* ids, int2* lnk,
-                             int32_t* own, hipStream_t s);
+hipError_t launch_move_lists(int def, int ndef, const int32_t* cnt_old, int64_t old_slot, const int32_t* new_ids,
+                             int cnt_new, int64_t new_slot, int shift_x, int shift_y, int shift_z, int n, int32_t* ids,
+                             int2* lnk, int32_t* own, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 hipError_t launch_mean_stress(const DevDefect* d, const int32_t* counts, int ndef, int64_t n3, Cubic C, int bc,
                               double* add6, hipStream_t s);
@@ -352,8 +374,8 @@ struct ClassTag {
 // Writes tags[i] into defs[i].cls / defs[i].s.
 hipError_t launch_set_class(DevDefect* d, int ndef, const ClassTag* tags, hipStream_t s);
 // which 0: sigma, 1: eps = C^-1:sigma + eps*, 2: eps* alone; out is float or double.
-hipError_t launch_sig_to_out(const double* sig, const int32_t* own, const int2* lnk, const DevDefect* defs, int64_t n3,
-                             Cubic C, int which, bool fp32, void* out, hipStream_t s);
+hipError_t launch_sig_to_out(const double* sig, const int32_t* own, const int2* lnk, const DevDefect* defs, int ndef,
+                             int64_t n3, Cubic C, int which, bool fp32, void* out, hipStream_t s);
 
 constexpr int KWIN = 24;  // doubles per window point (21 used: the symmetric 6x6 kernel)
 

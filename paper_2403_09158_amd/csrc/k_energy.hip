@@ -721,15 +721,13 @@ __global__ __launch_bounds__(RDT) void k_dipole(const DevDefect* __restrict__ de
 // (owner-list gather).
 template <typename OT>
 __global__ void k_sig_to_out(const double* __restrict__ sig, const int32_t* __restrict__ own,
-                             const int2* __restrict__ lnk, const DevDefect* __restrict__ defs, int64_t n3, Cubic C,
-                             int which, OT* __restrict__ out) {
+                             const int2* __restrict__ lnk, const DevDefect* __restrict__ defs, int max_links,
+                             int64_t n3, Cubic C, int which, OT* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n3) return;
   double es[6] = {0, 0, 0, 0, 0, 0};
   if (which > 0) {
-    int64_t acc[6] = {0, 0, 0, 0, 0, 0};
-    decode_voxel(own[t], lnk, defs, acc);
-    for (int c = 0; c < 6; ++c) es[c] = (double)acc[c] * FIX_INV;
+    decode_voxel(own[t], lnk, defs, es, max_links);
   }
   if (which == 2) {
     double el[6];
@@ -886,14 +884,14 @@ hipError_t launch_dipole(const DevDefect* d, int ndef, const int32_t* counts, co
   return hipGetLastError();
 }
 
-hipError_t launch_sig_to_out(const double* sig, const int32_t* own, const int2* lnk, const DevDefect* defs, int64_t n3,
-                             Cubic C, int which, bool fp32, void* out, hipStream_t s) {
+hipError_t launch_sig_to_out(const double* sig, const int32_t* own, const int2* lnk, const DevDefect* defs, int ndef,
+                             int64_t n3, Cubic C, int which, bool fp32, void* out, hipStream_t s) {
   const unsigned grid = (unsigned)((n3 + 255) / 256);
   if (fp32)
-    hipLaunchKernelGGL(k_sig_to_out<float>, dim3(grid), dim3(256), 0, s, sig, own, lnk, defs, n3, C, which,
+    hipLaunchKernelGGL(k_sig_to_out<float>, dim3(grid), dim3(256), 0, s, sig, own, lnk, defs, ndef, n3, C, which,
                        (float*)out);
   else
-    hipLaunchKernelGGL(k_sig_to_out<double>, dim3(grid), dim3(256), 0, s, sig, own, lnk, defs, n3, C, which,
+    hipLaunchKernelGGL(k_sig_to_out<double>, dim3(grid), dim3(256), 0, s, sig, own, lnk, defs, ndef, n3, C, which,
                        (double*)out);
   return hipGetLastError();
 }

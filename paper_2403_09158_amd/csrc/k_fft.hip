@@ -209,7 +209,7 @@ template <int N, typename S, bool DENSE>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
     const int32_t* __restrict__ own, const int2* __restrict__ lnk, const DevDefect* __restrict__ defs,
     const double* __restrict__ dense, typename Cplx<S>::T* __restrict__ spec, int P, const double2* __restrict__ twg,
-    uint32_t* __restrict__ zero_ctr) {
+    uint32_t* __restrict__ zero_ctr, int max_links) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;  // (xx,yy), (zz,yz), (xz,xy) per row
   constexpr int T = pick_T(max_nb(N, NF));
@@ -249,10 +249,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
 #pragma unroll
         for (int c = 0; c < 6; ++c) e[c] = dense[c * n3 + v];
       } else {
-        int64_t acc[6] = {0, 0, 0, 0, 0, 0};
-        decode_voxel(link[k], lnk, defs, acc);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) e[c] = (double)acc[c] * FIX_INV;
+        decode_voxel(link[k], lnk, defs, e, max_links);
       }
 #pragma unroll
       for (int p = 0; p < 3; ++p) st2(lds(3 * r + p, x), make_double2(e[2 * p], e[2 * p + 1]));
@@ -304,7 +301,8 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   }
 }
 
-// Update variant: the rows of the eigenstrain change dE = E (chi_new - chi_old)
+// Update variant: the rows of the eigenstrain change
+// dE = E_new chi_new - E_old chi_old (E: E_old in [0, 6), E_new in [6, 12))
 // are built in LDS from the two footprint lists (new ids = old ids shifted by
 // (sx, sy, sz) voxels when new_ids == nullptr), for rows y in [y_lo, y_lo+y_len),
 // z in [z_lo, z_lo+z_len) (cyclic); other rows are zero and never touched.
@@ -332,8 +330,8 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
   if (z >= N) z -= N;
   __syncthreads();
   auto lds = [&](int f, int i) -> double2& { return buf[f * LDN + i + (i >> 4)]; };
-  // scatter +-E of the voxels that fall in this block's rows (one row per y)
-  auto scatter = [&](int id, double sgn) {
+  // scatter sgn * Ev of the voxels that fall in this block's rows (one row per y)
+  auto scatter = [&](int id, double sgn, const double* Ev) {
     const int x = id % N, y = (id / N) % N, zz = id / (N * N);
     if (zz != z) return;
     int yi = y - y_lo;
@@ -343,13 +341,13 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
       double2& slot = lds(3 * yi + p, x);
-      slot.x += sgn * E[2 * p];
-      slot.y += sgn * E[2 * p + 1];
+      slot.x += sgn * Ev[2 * p];
+      slot.y += sgn * Ev[2 * p + 1];
     }
   };
   // Each voxel is owned by one thread per list pass; a voxel can sit in both
   // lists, so the two passes are separated by a barrier.
-  for (int i = threadIdx.x; i < old_cnt; i += T) scatter(old_ids[i], -1.0);
+  for (int i = threadIdx.x; i < old_cnt; i += T) scatter(old_ids[i], -1.0, E);
   __syncthreads();
   for (int i = threadIdx.x; i < new_cnt; i += T) {
     int id;
@@ -363,7 +361,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
       zz = (zz % N + N) % N;
       id = (zz * N + y) * N + x;
     }
-    scatter(id, 1.0);
+    scatter(id, 1.0, E + 6);
   }
   __syncthreads();
   auto from_lds = [&](int f, int i) { return lds(f, i); };
@@ -832,18 +830,18 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
 // ------------------------------------------------------------------ launchers
 
 template <int N, typename S>
-hipError_t go_xf(const int32_t* own, const int2* lnk, const DevDefect* defs, const double* dense, void* spec,
-                 SpecGeom g, const double2* tw, uint32_t* zero_ctr, hipStream_t s) {
+hipError_t go_xf(const int32_t* own, const int2* lnk, const DevDefect* defs, int ndef, const double* dense,
+                 void* spec, SpecGeom g, const double2* tw, uint32_t* zero_ctr, hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   static_assert(T >= NTILECTR, "the first block zeroes the tile counters");
   const int grid = N * (N / x_rows(N));
   using C2 = typename Cplx<S>::T;
   if (dense)
     hipLaunchKernelGGL((k_x_forward<N, S, true>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P, tw,
-                       zero_ctr);
+                       zero_ctr, ndef);
   else
     hipLaunchKernelGGL((k_x_forward<N, S, false>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P,
-                       tw, zero_ctr);
+                       tw, zero_ctr, ndef);
   return hipGetLastError();
 }
 
@@ -934,13 +932,14 @@ bool fft_supported(int n) {
 
 int pencil_width(int n, bool) { return n >= 512 ? 8 : 16; }
 
-hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs, const double* dense,
-                            void* spec, SpecGeom g, const double2* tw, uint32_t* zero_ctr, hipStream_t s) {
+hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs, int ndef,
+                            const double* dense, void* spec, SpecGeom g, const double2* tw, uint32_t* zero_ctr,
+                            hipStream_t s) {
   switch (g.n) {
 #define EC_CASE(NN)                                                                     \
   case NN:                                                                              \
-    return fp64 ? go_xf<NN, double>(own, lnk, defs, dense, spec, g, tw, zero_ctr, s) \
-                : go_xf<NN, float>(own, lnk, defs, dense, spec, g, tw, zero_ctr, s);
+    return fp64 ? go_xf<NN, double>(own, lnk, defs, ndef, dense, spec, g, tw, zero_ctr, s) \
+                : go_xf<NN, float>(own, lnk, defs, ndef, dense, spec, g, tw, zero_ctr, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }

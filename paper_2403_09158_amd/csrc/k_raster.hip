@@ -182,13 +182,13 @@ __device__ __forceinline__ int shift_id(int id, int sx, int sy, int sz, int n) {
 // footprint is visited by exactly one thread, and no other chain changes
 // meanwhile.  The defect sits on the chain either as a terminal id or as an
 // entry; either way the link that points to it is redirected past it.
-__global__ __launch_bounds__(RT) void k_unlink(int def, const int32_t* __restrict__ cnt_p, int64_t slot,
-                                               const int32_t* __restrict__ ids, int2* __restrict__ lnk,
+__global__ __launch_bounds__(RT) void k_unlink(int def, int max_links, const int32_t* __restrict__ cnt_p,
+                                               int64_t slot, const int32_t* __restrict__ ids, int2* __restrict__ lnk,
                                                int32_t* __restrict__ own) {
   const int cnt = *cnt_p;
   for (int k = blockIdx.x * RT + threadIdx.x; k < cnt; k += gridDim.x * RT) {
     int32_t* p = &own[ids[slot + k]];
-    for (int guard = 0; guard < 4096; ++guard) {
+    for (int guard = 0; guard < max_links; ++guard) {  // a chain holds each defect once
       const int32_t link = *p;
       if (link == -1) break;  // not found (cannot happen for a consistent chain)
       if (link >= 0) {
@@ -305,10 +305,10 @@ hipError_t launch_unraster(const DevDefect* d, int ndef, const int32_t* counts, 
   return hipGetLastError();
 }
 
-hipError_t launch_move_lists(int def, const int32_t* cnt_old, int64_t old_slot, const int32_t* new_ids, int cnt_new,
-                             int64_t new_slot, int sx, int sy, int sz, int n, int32_t* ids, int2* lnk, int32_t* own,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_unlink, dim3(16), dim3(RT), 0, s, def, cnt_old, old_slot, ids, lnk, own);
+hipError_t launch_move_lists(int def, int ndef, const int32_t* cnt_old, int64_t old_slot, const int32_t* new_ids,
+                             int cnt_new, int64_t new_slot, int sx, int sy, int sz, int n, int32_t* ids, int2* lnk,
+                             int32_t* own, hipStream_t s) {
+  hipLaunchKernelGGL(k_unlink, dim3(16), dim3(RT), 0, s, def, ndef, cnt_old, old_slot, ids, lnk, own);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_link, dim3(16), dim3(RT), 0, s, def, cnt_old, old_slot, new_ids, cnt_new, new_slot, sx, sy, sz,

@@ -14,6 +14,12 @@ def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
+def rel_max(a, b):
+    """Largest pointwise difference over the largest reference magnitude (a
+    local error that a whole-field L2 norm would dilute)."""
+    return float(np.max(np.abs(a - b)) / max(float(np.max(np.abs(b))), 1e-300))
+
+
 def energy_ok_fp32(E, Eref):
     """Per-defect FP32 criterion: |E - Eref| <= max(1e-4 |Eref|, 1e-5 eV)."""
     return np.abs(E - Eref) <= np.maximum(1e-4 * np.abs(Eref), 1e-5)

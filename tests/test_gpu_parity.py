@@ -7,7 +7,7 @@ max(1e-4 |E|, 1e-5 eV) (FP32 storage).
 import numpy as np
 import pytest
 
-from helpers import energy_ok_fp32, energy_ok_fp64, rel_l2, to6
+from helpers import energy_ok_fp32, energy_ok_fp64, rel_l2, rel_max, to6
 from oracle import elastic, energy, raster, solve
 from paper_2403_09158_amd import inputs
 
@@ -107,7 +107,7 @@ def test_first_invalid_defect_of_a_long_list_is_reported(ctx):
 # --------------------------------------------------------------- single passes
 
 
-@pytest.mark.parametrize("n", [8, 16, 24, 32, 48, 64, 96, 128, 160, 240])
+@pytest.mark.parametrize("n", [8, 16, 24, 32, 48, 64, 96, 128, 160, 240, 256])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_forward_transform(ctx, n, prec):
     rng = np.random.default_rng(n)
@@ -118,9 +118,10 @@ def test_forward_transform(ctx, n, prec):
     want = solve.fft3(f)[..., : n // 2 + 1]
     tol = 1e-13 if prec == 0 else 2e-7
     assert rel_l2(got, want) < tol
+    assert rel_max(got, want) < 10 * tol
 
 
-@pytest.mark.parametrize("n", [8, 24, 48, 96, 160, 240])
+@pytest.mark.parametrize("n", [8, 24, 48, 96, 160, 240, 256])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_inverse_transform(ctx, n, prec):
     rng = np.random.default_rng(100 + n)
@@ -131,6 +132,7 @@ def test_inverse_transform(ctx, n, prec):
     got = st.debug_inverse(spec)
     tol = 1e-13 if prec == 0 else 2e-7
     assert rel_l2(got, f) < tol
+    assert rel_max(got, f) < 10 * tol
 
 
 @pytest.mark.parametrize("n", [8, 16, 32])
@@ -160,7 +162,9 @@ def test_solve_fields_every_size(ctx, n, prec):
     st = _state(ctx, prob)
     st.solve(d)
     tol = 1e-12 if prec == 0 else 1e-5
-    assert rel_l2(st.field("sigma"), sig6) < tol
+    sig = st.field("sigma")
+    assert rel_l2(sig, sig6) < tol
+    assert rel_max(sig, sig6) < 10 * tol
     st.close()
 
 
@@ -177,13 +181,12 @@ def test_pair32_fields_and_energies(ctx, prec, bc):
     E = st.energies()
     sig = st.field("sigma")
     eps = st.field("eps")
+    tol = 1e-12 if prec == 0 else 1e-5
+    assert rel_l2(sig, sig6) < tol and rel_max(sig, sig6) < 10 * tol
+    assert rel_l2(eps, eps6) < tol and rel_max(eps, eps6) < 10 * tol
     if prec == 0:
-        assert rel_l2(sig, sig6) < 1e-12
-        assert rel_l2(eps, eps6) < 1e-12
         assert energy_ok_fp64(E, Eo)
     else:
-        assert rel_l2(sig, sig6) < 1e-5
-        assert rel_l2(eps, eps6) < 1e-5
         assert np.all(energy_ok_fp32(E, Eo))
     # reciprocity of a pair: E_1 = E_12 = E_21 = E_2
     if prec == 0:
@@ -304,3 +307,57 @@ def test_general_move_matches_resolve(ctx):
     E = st.update(3, cur[3])
     Eo = energy.energies_fast(prob, cur)
     assert energy_ok_fp64(E, Eo)
+
+
+def _move_kinds(d, prob):
+    """Moves that change a defect's eigenstrain, not only its position: a
+    reversed Burgers vector with the habit normal kept (E -> -E), a new
+    sphere dilatation, a thicker slab, and a loop turned into a sphere."""
+    loops = np.flatnonzero(d["kind"] == 0)
+    spheres = np.flatnonzero(d["kind"] == 1)
+    i, j, k = int(loops[0]), int(spheres[0]), int(loops[1])
+    moves = []
+    m = d[i].copy()
+    m["b"] = -m["b"]
+    moves.append((i, m))
+    m = d[j].copy()
+    m["eig_v"] = 2.5 * m["eig_v"]
+    moves.append((j, m))
+    m = d[k].copy()
+    m["thickness"] = 2.0 * prob.h
+    moves.append((k, m))
+    m = d[i].copy()  # the reversed loop of the first move becomes a sphere
+    m["kind"] = 1
+    m["radius"] = 1.7 * prob.h
+    m["eig_v"] = 0.011
+    moves.append((i, m))
+    return moves
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_moves_that_change_the_eigenstrain(ctx, prec, bc):
+    """ec_update_defect with a new eigenstrain (App. B: the old field out, the
+    new one in): after every move the incremental state matches a fresh solve
+    of the moved list and the oracle."""
+    prob, d = _mixed(32, 16, 21, prec=prec, bc=bc)
+    st = _state(ctx, prob)
+    st.solve(d)
+    cur = d.copy()
+    for idx, rec in _move_kinds(d, prob):
+        cur[idx] = rec
+        E = st.update(idx, rec)
+        ref = _state(ctx, prob)
+        ref.solve(cur)
+        Er = ref.energies()
+        Eo = energy.energies_fast(prob, cur)
+        assert np.array_equal(st.field("eps_star"), ref.field("eps_star"))
+        if prec == 0:
+            assert energy_ok_fp64(E, Eo)
+            assert energy_ok_fp64(E, Er)
+            assert rel_l2(st.field("sigma"), ref.field("sigma")) < 1e-12
+        else:
+            assert np.all(energy_ok_fp32(E, Eo))
+            assert rel_l2(st.field("sigma"), ref.field("sigma")) < 1e-5
+        ref.close()
+    st.close()
