@@ -158,6 +158,20 @@ EC_API ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t nd
  * (c = 1 GPa nm^3 in eV).  E_out holds ndef doubles (device or host). */
 EC_API ec_status ec_interaction_energies(ec_state* st, void* hip_stream, double* E_out, int32_t out_on_device);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ec_interaction_energies
+ * that allocates nothing.  E_dev is a device buffer of ndef doubles, written
+ * on hip_stream without synchronising.  When the self terms must be computed
+ * again (after an update that changed a footprint's shape), their work list,
+ * per-defect offsets and partial sums live in a fixed scratch area of the
+ * library on each device (about 6.1 MB, held until the process ends) instead
+ * of state buffers; it serves at most 16384 defects and 262144 self-term work
+ * items (EC_ERR_SIZE beyond).  The kernel and class windows must already cover
+ * the list (EC_ERR_STATE otherwise: one ec_interaction_energies call builds
+ * them).  Every call on one device shares the scratch area, so calls that
+ * overlap on one device (other streams, other states or contexts) race. */
+EC_API ec_status ec_interaction_energies_noalloc(ec_state* st, void* hip_stream, double* E_dev);
+
 /* Move defect idx to the record *moved (Appendix B: subtract the old field,
  * add the new one).  By linearity only the eigenstrain difference is solved;
  * the resident FP64 stress is accumulated and, if E_out != NULL, all ndef

@@ -155,8 +155,53 @@ class WorkPool {
   std::atomic<bool> astop_{false};
 };
 
+// ------------------------------------------------ fixed device scratch area
+//
+// Scratch of ec_interaction_energies_noalloc: the self-term work list, the
+// per-defect item offsets and the per-item partial sums of the energies
+// (k_self_plan / k_self / k_self_finish), for up to NA_MAX_DEFECTS defects and
+// NA_MAX_ITEMS work items.  Every GPU the library runs on holds one copy until
+// the process ends; every call on a GPU shares it (calls that overlap on one
+// GPU race).  Nothing in it needs to start at zero: the plan writes every
+// offset and item it uses, and every item writes its partial.  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (noalloc_scratch()); the array's name in host code is a
+// host-side stand-in, not a device address.
+namespace {
+constexpr int64_t NA_MAX_DEFECTS = 16384;
+constexpr int64_t NA_MAX_ITEMS = 262144;
+constexpr size_t NA_WORK_OFF = 0;
+constexpr size_t NA_PART_OFF = NA_WORK_OFF + NA_MAX_ITEMS * sizeof(SelfWork);
+constexpr size_t NA_WBEG_OFF = NA_PART_OFF + NA_MAX_ITEMS * sizeof(double);
+constexpr size_t NA_BYTES = NA_WBEG_OFF + (NA_MAX_DEFECTS + 1) * sizeof(int64_t);
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NA_MAX_DEVICES] = {};
+
+// Device address of the scratch area on `device` (which must be current),
+// looked up once per device.
+hipError_t noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= NA_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+}  // namespace
+
 struct ec_ctx {
   int device = 0;
+  void* scratch = nullptr;  // this device's copy of the fixed scratch area
   size_t budget = 0, used = 0;
   ec_alloc_fn af = nullptr;
   ec_free_fn ff = nullptr;
@@ -950,20 +995,25 @@ ec_status ensure_windows(ec_state* st, int reach, hipStream_t s) {
   return EC_OK;
 }
 
-ec_status compute_self_terms(ec_state* st, hipStream_t s) {
-  ec_status r = ensure_classes(st, s);
-  if (r != EC_OK) return r;
-  if ((r = ensure_windows(st, 0, s)) != EC_OK) return r;
-  const WinCache* w = st->win.get();
-  const int D = w->D;
-  // Work-list capacity: at most 64 items per defect, fewer for small boxes.
+// Self-term work-list capacity: at most 64 items per defect, fewer for small
+// boxes (the device plan, from the footprint counts, never needs more).
+int64_t self_work_cap(const ec_state* st) {
   int64_t cap = 0;
   for (const auto& d : st->hdefs) {
     const double m = (double)box_volume(d);
     const double k = std::ceil(m * (m + 1) / 2 / 32768.0);
     cap += (int64_t)std::min(64.0, std::max(1.0, k));
   }
-  cap = std::max<int64_t>(cap, 1);
+  return std::max<int64_t>(cap, 1);
+}
+
+ec_status compute_self_terms(ec_state* st, hipStream_t s) {
+  ec_status r = ensure_classes(st, s);
+  if (r != EC_OK) return r;
+  if ((r = ensure_windows(st, 0, s)) != EC_OK) return r;
+  const WinCache* w = st->win.get();
+  const int D = w->D;
+  const int64_t cap = self_work_cap(st);
   if ((r = st_grow(st, &st->work, &st->work_cap, (size_t)cap)) != EC_OK) return r;
   if ((r = st_grow(st, &st->partial, &st->partial_cap, (size_t)cap)) != EC_OK) return r;
   if ((r = st_grow(st, &st->wbeg, &st->wbeg_cap, (size_t)st->ndef + 1)) != EC_OK) return r;
@@ -1415,8 +1465,11 @@ ec_status ec_ctx_create(int device, size_t budget, ec_alloc_fn af, ec_free_fn ff
   HIPCHK(hipSetDevice(device));
   size_t fr = 0, tot = 0;
   HIPCHK(hipMemGetInfo(&fr, &tot));
+  void* scr = nullptr;
+  HIPCHK(noalloc_scratch(device, &scr));
   ec_ctx* c = new ec_ctx;
   c->device = device;
+  c->scratch = scr;
   c->budget = budget ? budget : fr;
   c->af = af;
   c->ff = ff;
@@ -1655,6 +1708,44 @@ ec_status ec_interaction_energies(ec_state* st, void* stream, double* E_out, int
   LAUNCH(st, s, PF_REDUCE, 0,
          launch_reduce(b.tab, st->ndef, b.cnt, b.ids, st->sig, st->B, st->h3c, st->S6, st->E, s));
   if (E_out && st->ndef > 0) return copy_small(st, E_out, st->E, (size_t)st->ndef * 8, on_device != 0, s);
+  return EC_OK;
+}
+
+ec_status ec_interaction_energies_noalloc(ec_state* st, void* stream, double* E_dev) {
+  if (!st || !E_dev) return fail(EC_ERR_ARG, "NULL argument");
+  if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
+  if (st->ndef > NA_MAX_DEFECTS)
+    return fail(EC_ERR_SIZE, "%d defects: the no-allocation energies take at most %lld", st->ndef,
+                (long long)NA_MAX_DEFECTS);
+  if (!st->ctx->scratch) return fail(EC_ERR_DEVICE, "no scratch area on this device");
+  hipStream_t s = (hipStream_t)stream;
+  ec_status r;
+  if ((r = join_self(st, s)) != EC_OK) return r;
+  const DefBuf& b = st->db[st->cur];
+  if (!st->B_valid && st->ndef > 0) {
+    // the self terms again (a footprint changed shape): the kernel and class
+    // windows must already cover the list, since building them allocates
+    const WinCache* w = st->win.get();
+    if (!st->classes_ok || !w || window_need(st) > w->D || st->gcls_D != w->D ||
+        st->gcls_ncls != (int)st->classes.size())
+      return fail(EC_ERR_STATE,
+                  "the self terms need new kernel or class windows (a footprint outgrew the window or a new "
+                  "eigenstrain direction appeared): call ec_interaction_energies once");
+    const int64_t cap = self_work_cap(st);
+    if (cap > NA_MAX_ITEMS)
+      return fail(EC_ERR_SIZE, "the self terms need %lld work items: the no-allocation energies take at most %lld",
+                  (long long)cap, (long long)NA_MAX_ITEMS);
+    char* base = (char*)st->ctx->scratch;
+    LAUNCH(st, s, PF_SELF, 0,
+           launch_self_terms(b.tab, st->ndef, b.cnt, b.ids, st->n, w->K, st->gcls, w->D,
+                             (SelfWork*)(base + NA_WORK_OFF), cap, (int64_t*)(base + NA_WBEG_OFF),
+                             (double*)(base + NA_PART_OFF), st->h3c, st->B, s));
+    st->B_valid = true;
+  }
+  LAUNCH(st, s, PF_REDUCE, 0,
+         launch_reduce(b.tab, st->ndef, b.cnt, b.ids, st->sig, st->B, st->h3c, st->S6, st->E, s));
+  if (st->ndef > 0)
+    HIPCHK(hipMemcpyAsync(E_dev, st->E, (size_t)st->ndef * 8, hipMemcpyDeviceToDevice, s));
   return EC_OK;
 }
 

@@ -36,6 +36,7 @@ EXPORTS = (
     "ec_state_bytes",
     "ec_solve_fields",
     "ec_interaction_energies",
+    "ec_interaction_energies_noalloc",
     "ec_update_defect",
     "ec_jump_energies",
     "ec_jump_select",
@@ -104,6 +105,7 @@ def load() -> ctypes.CDLL:
         "ec_state_bytes": (c_int, [vp, POINTER(c_size_t)]),
         "ec_solve_fields": (c_int, [vp, vp, c_int32, vp, vp, vp, c_int32]),
         "ec_interaction_energies": (c_int, [vp, vp, vp, c_int32]),
+        "ec_interaction_energies_noalloc": (c_int, [vp, vp, vp]),
         "ec_update_defect": (c_int, [vp, c_int32, vp, vp, vp, c_int32]),
         "ec_jump_energies": (c_int, [vp, vp, c_int32, vp, vp, c_int32]),
         "ec_jump_select": (c_int, [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, c_int32]),
@@ -274,6 +276,12 @@ class State:
         E = np.zeros(self.ndef) if out is None else out
         _check(load().ec_interaction_energies(self.h, _stream_handle(stream), E.ctypes.data, 0))
         return E
+
+    def energies_noalloc(self, out, stream=None):
+        """Interaction energies written to the device tensor ``out`` (ndef
+        float64) by the entry point that allocates nothing; no synchronisation."""
+        _check(load().ec_interaction_energies_noalloc(self.h, _stream_handle(stream), out.data_ptr()))
+        return out
 
     def update(self, idx: int, defect, stream=None, energies: bool = True, out=None):
         """Move defect ``idx`` to ``defect``.  Energies of all defects after the
