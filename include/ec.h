@@ -164,7 +164,7 @@ EC_API ec_status ec_interaction_energies(ec_state* st, void* hip_stream, double*
  * on hip_stream without synchronising.  When the self terms must be computed
  * again (after an update that changed a footprint's shape), their work list,
  * per-defect offsets and partial sums live in a fixed scratch area of the
- * library on each device (about 6.1 MB, held until the process ends) instead
+ * library on each device (about 6.3 MB, held until the process ends) instead
  * of state buffers; it serves at most 16384 defects and 262144 self-term work
  * items (EC_ERR_SIZE beyond).  The kernel and class windows must already cover
  * the list (EC_ERR_STATE otherwise: one ec_interaction_energies call builds

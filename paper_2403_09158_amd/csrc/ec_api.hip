@@ -158,12 +158,14 @@ class WorkPool {
 // ------------------------------------------------ fixed device scratch area
 //
 // Scratch of ec_interaction_energies_noalloc: the self-term work list, the
-// per-defect item offsets and the per-item partial sums of the energies
-// (k_self_plan / k_self / k_self_finish), for up to NA_MAX_DEFECTS defects and
+// per-defect item offsets, the per-item partial sums and the per-defect run
+// sums of the energies (k_self_plan / k_self / k_self_runs / k_self_finish),
+// for up to NA_MAX_DEFECTS defects and
 // NA_MAX_ITEMS work items.  Every GPU the library runs on holds one copy until
 // the process ends; every call on a GPU shares it (calls that overlap on one
 // GPU race).  Nothing in it needs to start at zero: the plan writes every
-// offset and item it uses, and every item writes its partial.  Host code
+// offset and item it uses, every item writes its partial, and every defect on
+// the run path writes its run sum (the others' entries are not read).  Host code
 // reaches it only through the address hipGetSymbolAddress returns for the
 // current device (noalloc_scratch()); the array's name in host code is a
 // host-side stand-in, not a device address.
@@ -173,7 +175,8 @@ constexpr int64_t NA_MAX_ITEMS = 262144;
 constexpr size_t NA_WORK_OFF = 0;
 constexpr size_t NA_PART_OFF = NA_WORK_OFF + NA_MAX_ITEMS * sizeof(SelfWork);
 constexpr size_t NA_WBEG_OFF = NA_PART_OFF + NA_MAX_ITEMS * sizeof(double);
-constexpr size_t NA_BYTES = NA_WBEG_OFF + (NA_MAX_DEFECTS + 1) * sizeof(int64_t);
+constexpr size_t NA_RUN_OFF = NA_WBEG_OFF + (NA_MAX_DEFECTS + 8) * sizeof(int64_t);
+constexpr size_t NA_BYTES = NA_RUN_OFF + NA_MAX_DEFECTS * sizeof(double);
 }  // namespace
 
 static __device__ __align__(256) unsigned char scratch[NA_BYTES];
@@ -268,6 +271,7 @@ struct ec_state {
   double* B = nullptr;
   double* E = nullptr;
   double* S6 = nullptr;
+  double* runsum = nullptr;  // self-term run sums (scratch of the self terms)
   size_t pd_cap = 0;
   bool B_valid = false;
   // self terms of a fresh solve run on a side stream beside the Fourier
@@ -280,6 +284,14 @@ struct ec_state {
   // new defect list are assigned when first needed (classes_ok false until then)
   bool classes_ok = true;
   std::vector<std::array<double, 6>> classes;
+  // run classes (class, run direction) and their self-term tables (double
+  // prefix sums of the class windows along the run direction)
+  std::vector<std::array<int, 4>> runcls;
+  int4* runinfo = nullptr;  // MAXRUN entries {class, tx, ty, tz}
+  double* gff = nullptr;
+  size_t gff_bytes = 0;
+  int gff_D = -1, gff_nrun = -1;
+  int max_runs = 0;  // largest run bound over the list (host, with the run classes)
   ClassTag* tags = nullptr;
   size_t tags_cap = 0;
   double* dirs = nullptr;
@@ -589,8 +601,28 @@ void to_cube(const double* A, const double* t, double* out) {
   out[5] = tc(0, 1);
 }
 
+// Run direction of a loop for the self terms: the shortest lattice vector t in
+// the habit plane (m . t = 0) with components in [-2, 2] (first nonzero one
+// positive, ties in a fixed order); none found leaves t = 0 (no run path).
+void run_direction(const int32_t m[3], int32_t t[3]) {
+  t[0] = t[1] = t[2] = 0;
+  for (int len2 = 1; len2 <= 12; ++len2)
+    for (int a = -2; a <= 2; ++a)
+      for (int b = -2; b <= 2; ++b)
+        for (int c = -2; c <= 2; ++c) {
+          if (a * a + b * b + c * c != len2) continue;
+          const int first = a != 0 ? a : (b != 0 ? b : c);
+          if (first < 0 || m[0] * a + m[1] * b + m[2] * c != 0) continue;
+          t[0] = a;
+          t[1] = b;
+          t[2] = c;
+          return;
+        }
+}
+
 bool quantise(const ec_problem& P, const ec_defect& rec, DevDefect& d, std::string& err) {
   std::memset(&d, 0, sizeof d);
+  d.rcls = -1;
   const int n = P.n;
   const double L = P.L;
   const double s = (1024.0 * n) / L;
@@ -628,6 +660,7 @@ bool quantise(const ec_problem& P, const ec_defect& rec, DevDefect& d, std::stri
     if (R + 0.5 * e_nm >= 0.5 * L) return err = "loop extent reaches half the cell", false;
     if (!lattice_normal(rec.normal, d.m)) return err = "habit normal is not a small-integer lattice direction", false;
     d.mm = d.m[0] * d.m[0] + d.m[1] * d.m[1] + d.m[2] * d.m[2];
+    run_direction(d.m, d.rt);
     const double nrm = std::sqrt((double)d.mm);
     double nh[3];
     for (int k = 0; k < 3; ++k) nh[k] = (double)d.m[k] / nrm;
@@ -636,6 +669,7 @@ bool quantise(const ec_problem& P, const ec_defect& rec, DevDefect& d, std::stri
     ext += (d.eq + 1) / 2;
   } else if (rec.kind == EC_SPHERE) {
     if (R >= 0.5 * L) return err = "sphere extent reaches half the cell", false;
+    d.rt[0] = 1;  // runs along x
     if (!std::isfinite(rec.eig_v)) return err = "eigenstrain not finite", false;
     for (int a = 0; a < 3; ++a) E[a][a] = rec.eig_v;
   } else {
@@ -683,6 +717,36 @@ void direction(const DevDefect& d, std::array<double, 6>& e, double& s) {
 }
 
 constexpr int MAXCLS = 32;
+constexpr int MAXRUN = 32;  // run classes (class, run direction) with self-term tables
+
+// Bound on the number of runs of a footprint along its run direction: the
+// lattice lines along t that meet its box.  Each such line has a first point p
+// in the box with p - t outside, so p lies within |t_k| layers of a face
+// normal to an axis k with t_k != 0: at most sum_k |t_k| prod_{j != k} w_j.
+int64_t run_bound(const DevDefect& d) {
+  int64_t lines = 0;
+  for (int k = 0; k < 3; ++k)
+    lines += (int64_t)std::abs(d.rt[k]) * d.w[(k + 1) % 3] * d.w[(k + 2) % 3];
+  return lines;
+}
+
+// Run class of a defect whose class is set: the pair (class, run direction),
+// added to the state's list on first appearance (-1: no class, no direction,
+// a run bound above SELF_RUN_MAX, or the list is full).
+void assign_run_class(ec_state* st, DevDefect& d) {
+  d.rcls = -1;
+  if (d.cls < 0 || (d.rt[0] == 0 && d.rt[1] == 0 && d.rt[2] == 0) || run_bound(d) > SELF_RUN_MAX) return;
+  const std::array<int, 4> key{d.cls, d.rt[0], d.rt[1], d.rt[2]};
+  for (size_t r = 0; r < st->runcls.size(); ++r)
+    if (st->runcls[r] == key) {
+      d.rcls = (int)r;
+      return;
+    }
+  if ((int)st->runcls.size() < MAXRUN) {
+    st->runcls.push_back(key);
+    d.rcls = (int)st->runcls.size() - 1;
+  }
+}
 
 void assign_class(ec_state* st, DevDefect& d) {
   std::array<double, 6> e;
@@ -690,16 +754,21 @@ void assign_class(ec_state* st, DevDefect& d) {
   direction(d, e, s);
   d.s = s;
   d.cls = -1;
+  d.rcls = -1;
   if (s == 0.0) return;
+  const size_t nrun_before = st->runcls.size();
   for (size_t c = 0; c < st->classes.size(); ++c)
     if (std::memcmp(st->classes[c].data(), e.data(), sizeof(double) * 6) == 0) {
       d.cls = (int)c;
-      return;
+      break;
     }
-  if ((int)st->classes.size() < MAXCLS) {
+  if (d.cls < 0 && (int)st->classes.size() < MAXCLS) {
     st->classes.push_back(e);
     d.cls = (int)st->classes.size() - 1;
   }
+  assign_run_class(st, d);
+  if (d.rcls >= 0) st->max_runs = std::max<int64_t>(st->max_runs, run_bound(d));
+  if (st->runcls.size() != nrun_before) st->gff_nrun = -1;
 }
 
 // Classes of a whole list, the same as assign_class on each defect in list
@@ -747,6 +816,11 @@ void assign_classes(ec_state* st, std::vector<DevDefect>& defs) {
       }
     }
   }
+  for (size_t i = 0; i < nd; ++i) assign_run_class(st, defs[i]);
+  int64_t mr = 0;
+  for (size_t i = 0; i < nd; ++i)
+    if (defs[i].rcls >= 0) mr = std::max(mr, run_bound(defs[i]));
+  st->max_runs = (int)mr;
 }
 
 // ------------------------------------------------------------------ solve pipeline
@@ -944,14 +1018,17 @@ ec_status ensure_classes(ec_state* st, hipStream_t s) {
   ec_status r;
   if (nd > 0 && (r = st_grow(st, &st->tags, &st->tags_cap, nd)) != EC_OK) return r;
   const std::vector<std::array<double, 6>> old = st->classes;
+  const std::vector<std::array<int, 4>> oldrun = st->runcls;
   st->classes.clear();
+  st->runcls.clear();
   assign_classes(st, st->hdefs);
   if (old != st->classes) st->gcls_ncls = -1;
+  if (oldrun != st->runcls) st->gff_nrun = -1;
   if (nd > 0) {
     char* hp = nullptr;
     if ((r = pin_begin(st->pin_tags, nd * sizeof(ClassTag), &hp)) != EC_OK) return r;
     ClassTag* t = (ClassTag*)hp;
-    for (size_t i = 0; i < nd; ++i) t[i] = ClassTag{st->hdefs[i].s, st->hdefs[i].cls, 0};
+    for (size_t i = 0; i < nd; ++i) t[i] = ClassTag{st->hdefs[i].s, st->hdefs[i].cls, st->hdefs[i].rcls};
     HIPCHK(hipMemcpyAsync(st->tags, hp, nd * sizeof(ClassTag), hipMemcpyHostToDevice, s));
     if ((r = pin_end(st->pin_tags, s)) != EC_OK) return r;
     LAUNCH(st, s, PF_OTHER, 0, launch_set_class(st->db[st->cur].tab, (int)nd, st->tags, s));
@@ -991,20 +1068,62 @@ ec_status ensure_windows(ec_state* st, int reach, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));  // dirs staging buffer is pageable
     st->gcls_D = D;
     st->gcls_ncls = ncls;
+    st->gff_D = -1;  // the run tables come from the class windows
+  }
+  // the run tables on the state's own window need (<= D), so that they do not
+  // depend on the width the shared window has for other states
+  const int nrun = (int)st->runcls.size();
+  const int Drun = std::min(D, window_need(st));
+  if (st->gff_D != Drun || st->gff_nrun != nrun) {
+    const size_t Wr = 2 * (size_t)Drun + 1;
+    const size_t need_b = std::max<size_t>(1, (size_t)nrun) * Wr * Wr * Wr * sizeof(double);
+    if (need_b > st->gff_bytes) {
+      void* q = nullptr;
+      if ((r = ledger_alloc(st->ctx, need_b, &q)) != EC_OK) return r;
+      if (st->gff) HIPCHK(hipDeviceSynchronize());  // self-term kernels may still read the old tables
+      ledger_free(st->ctx, st->gff, st->gff_bytes);
+      st->held += need_b;
+      st->held -= std::min(st->held, st->gff_bytes);
+      st->gff = (double*)q;
+      st->gff_bytes = need_b;
+    }
+    std::vector<int4> info(std::max(nrun, 1));
+    for (int k = 0; k < nrun; ++k)
+      info[k] = make_int4(st->runcls[k][0], st->runcls[k][1], st->runcls[k][2], st->runcls[k][3]);
+    HIPCHK(hipMemcpyAsync(st->runinfo, info.data(), info.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+    LAUNCH(st, s, PF_OTHER, Wr * Wr * Wr * nrun * 16.0,
+           launch_run_tables(st->gcls, D, Drun, st->runinfo, nrun, st->gff, s));
+    HIPCHK(hipStreamSynchronize(s));  // info staging buffer is pageable
+    st->gff_D = Drun;
+    st->gff_nrun = nrun;
   }
   return EC_OK;
 }
 
-// Self-term work-list capacity: at most 64 items per defect, fewer for small
-// boxes (the device plan, from the footprint counts, never needs more).
+RunTables run_tables(const ec_state* st) {
+  RunTables t;
+  t.ff = st->gff;
+  t.info = st->runinfo;
+  t.nrun = st->gff_nrun > 0 && st->gff_D > 0 ? st->gff_nrun : 0;
+  t.D = std::max(st->gff_D, 0);
+  t.max_runs = st->max_runs;
+  return t;
+}
+
+// Self-term work-list capacity of the pair path: at most 64 items per defect
+// off the run path, fewer for small boxes (the device plan, from the footprint
+// counts, never needs more); 0 when every defect takes the run path.  The run
+// tables must be current (after ensure_windows).
 int64_t self_work_cap(const ec_state* st) {
+  const int nrun = st->gff_D > 0 ? st->gff_nrun : 0, Dr = st->gff_D;
   int64_t cap = 0;
   for (const auto& d : st->hdefs) {
+    if (d.rcls >= 0 && d.rcls < nrun && d.w[0] <= Dr + 1 && d.w[1] <= Dr + 1 && d.w[2] <= Dr + 1) continue;
     const double m = (double)box_volume(d);
     const double k = std::ceil(m * (m + 1) / 2 / 32768.0);
     cap += (int64_t)std::min(64.0, std::max(1.0, k));
   }
-  return std::max<int64_t>(cap, 1);
+  return cap;
 }
 
 ec_status compute_self_terms(ec_state* st, hipStream_t s) {
@@ -1014,13 +1133,13 @@ ec_status compute_self_terms(ec_state* st, hipStream_t s) {
   const WinCache* w = st->win.get();
   const int D = w->D;
   const int64_t cap = self_work_cap(st);
-  if ((r = st_grow(st, &st->work, &st->work_cap, (size_t)cap)) != EC_OK) return r;
-  if ((r = st_grow(st, &st->partial, &st->partial_cap, (size_t)cap)) != EC_OK) return r;
+  if ((r = st_grow(st, &st->work, &st->work_cap, (size_t)std::max<int64_t>(cap, 1))) != EC_OK) return r;
+  if ((r = st_grow(st, &st->partial, &st->partial_cap, (size_t)std::max<int64_t>(cap, 1))) != EC_OK) return r;
   if ((r = st_grow(st, &st->wbeg, &st->wbeg_cap, (size_t)st->ndef + 1)) != EC_OK) return r;
   const DefBuf& b = st->db[st->cur];
   LAUNCH(st, s, PF_SELF, 0,
-         launch_self_terms(b.tab, st->ndef, b.cnt, b.ids, st->n, w->K, st->gcls, D, st->work, (int64_t)st->work_cap,
-                           st->wbeg, st->partial, st->h3c, st->B, s));
+         launch_self_terms(b.tab, st->ndef, b.cnt, b.ids, st->n, w->K, st->gcls, D, run_tables(st), st->work, cap,
+                           st->wbeg, st->partial, st->runsum, st->h3c, st->B, s));
   st->B_valid = true;
   return EC_OK;
 }
@@ -1091,7 +1210,7 @@ ec_status write_field(ec_state* st, int which, void* out, bool on_device, hipStr
 ec_status ensure_per_defect(ec_state* st, size_t ndef) {
   if (ndef <= st->pd_cap && st->B) return EC_OK;
   size_t cap = std::max<size_t>(ndef, 16);
-  void *b = nullptr, *e = nullptr, *s6 = nullptr;
+  void *b = nullptr, *e = nullptr, *s6 = nullptr, *rs = nullptr;
   ec_status r;
   if ((r = ledger_alloc(st->ctx, cap * 8, &b)) != EC_OK) return r;
   if ((r = ledger_alloc(st->ctx, cap * 8, &e)) != EC_OK) {
@@ -1103,14 +1222,22 @@ ec_status ensure_per_defect(ec_state* st, size_t ndef) {
     ledger_free(st->ctx, e, cap * 8);
     return r;
   }
+  if ((r = ledger_alloc(st->ctx, cap * 8, &rs)) != EC_OK) {
+    ledger_free(st->ctx, b, cap * 8);
+    ledger_free(st->ctx, e, cap * 8);
+    ledger_free(st->ctx, s6, cap * 48);
+    return r;
+  }
   ledger_free(st->ctx, st->B, st->pd_cap * 8);
   ledger_free(st->ctx, st->E, st->pd_cap * 8);
   ledger_free(st->ctx, st->S6, st->pd_cap * 48);
-  st->held += cap * 64;
-  st->held -= std::min(st->held, st->pd_cap * 64);
+  ledger_free(st->ctx, st->runsum, st->pd_cap * 8);
+  st->held += cap * 72;
+  st->held -= std::min(st->held, st->pd_cap * 72);
   st->B = (double*)b;
   st->E = (double*)e;
   st->S6 = (double*)s6;
+  st->runsum = (double*)rs;
   st->pd_cap = cap;
   return EC_OK;
 }
@@ -1323,10 +1450,11 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
       if (d >= n / 2) d -= n;
       sh[k] = d;
     }
-  const size_t ncls_before = st->classes.size();
+  const size_t ncls_before = st->classes.size(), nrun_before = st->runcls.size();
   if (hop) {
     nd.cls = od.cls;
     nd.s = od.s;
+    nd.rcls = od.rcls;
   } else {
     assign_class(st, nd);
   }
@@ -1350,6 +1478,7 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
     size_t ucap = (size_t)st->upd_cap;
     if ((r = st_grow(st, &st->upd_ids, &ucap, std::max<size_t>(cnt_new, 1))) != EC_OK) {
       st->classes.resize(ncls_before);
+      st->runcls.resize(nrun_before);
       return r;
     }
     st->upd_cap = (int64_t)ucap;
@@ -1361,6 +1490,7 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
       if ((r = st_grow(st, &b.ids, &icap, need, true, s)) != EC_OK ||
           (r = st_grow(st, &b.lnk, &lcap, need, true, s)) != EC_OK) {
         st->classes.resize(ncls_before);
+        st->runcls.resize(nrun_before);
         return r;
       }
       b.ids_cap = (int64_t)std::min(icap, lcap);
@@ -1548,7 +1678,7 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
     delete st;
     return fail(EC_ERR_DEVICE, "twiddle table allocation failed");
   }
-  void *sp = nullptr, *own = nullptr, *sg = nullptr, *ad = nullptr, *dirs = nullptr, *ue = nullptr;
+  void *sp = nullptr, *own = nullptr, *sg = nullptr, *ad = nullptr, *dirs = nullptr, *ue = nullptr, *ri = nullptr;
   void* tc = nullptr;
   void* fm = nullptr;
   const size_t ob = (size_t)st->n3 * 4;
@@ -1560,13 +1690,14 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
     ledger_free(c, ad, 256);
     ledger_free(c, dirs, MAXCLS * 48);
     ledger_free(c, ue, 128);
+    ledger_free(c, ri, MAXRUN * sizeof(int4));
     ledger_free(c, tc, 128);
     ledger_free(c, fm, FRAME_LEN * 8);
   };
   if ((r = ledger_alloc(c, st->spec_bytes, &sp)) != EC_OK || (r = ledger_alloc(c, ob, &own)) != EC_OK ||
       (r = ledger_alloc(c, fb, &sg)) != EC_OK || (r = ledger_alloc(c, 256, &ad)) != EC_OK ||
       (r = ledger_alloc(c, MAXCLS * 48, &dirs)) != EC_OK || (r = ledger_alloc(c, 128, &ue)) != EC_OK ||
-      (r = ledger_alloc(c, 128, &tc)) != EC_OK ||
+      (r = ledger_alloc(c, 128, &tc)) != EC_OK || (r = ledger_alloc(c, MAXRUN * sizeof(int4), &ri)) != EC_OK ||
       (rotated && (r = ledger_alloc(c, FRAME_LEN * 8, &fm)) != EC_OK)) {
     undo();
     delete st;
@@ -1578,10 +1709,12 @@ ec_status ec_state_create(ec_ctx* c, const ec_problem* p, ec_state** out) {
   st->add6 = (double*)ad;
   st->dirs = (double*)dirs;
   st->updE = (double*)ue;
+  st->runinfo = (int4*)ri;
   st->tilectr = (uint32_t*)tc;
   st->frm = (double*)fm;
   st->C.frm = st->frm;
-  st->held = st->spec_bytes + fb + ob + 256 + MAXCLS * 48 + 128 + 128 + (rotated ? FRAME_LEN * 8 : 0);
+  st->held = st->spec_bytes + fb + ob + 256 + MAXCLS * 48 + 128 + 128 + MAXRUN * sizeof(int4) +
+             (rotated ? FRAME_LEN * 8 : 0);
   hipError_t e = launch_fill_i32(st->own, st->n3, -1, nullptr);
   if (e == hipSuccess) e = hipMemset(st->sig, 0, fb);
   if (e == hipSuccess) e = hipMemset(st->add6, 0, 256);
@@ -1617,7 +1750,10 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->B, st->pd_cap * 8);
   ledger_free(c, st->E, st->pd_cap * 8);
   ledger_free(c, st->S6, st->pd_cap * 48);
+  ledger_free(c, st->runsum, st->pd_cap * 8);
   ledger_free(c, st->gcls, st->gcls_bytes);
+  ledger_free(c, st->gff, st->gff_bytes);
+  ledger_free(c, st->runinfo, MAXRUN * sizeof(int4));
   ledger_free(c, st->upd_ids, st->upd_cap * 4);
   ledger_free(c, st->work, st->work_cap * sizeof(SelfWork));
   ledger_free(c, st->partial, st->partial_cap * 8);
@@ -1727,19 +1863,31 @@ ec_status ec_interaction_energies_noalloc(ec_state* st, void* stream, double* E_
     // windows must already cover the list, since building them allocates
     const WinCache* w = st->win.get();
     if (!st->classes_ok || !w || window_need(st) > w->D || st->gcls_D != w->D ||
-        st->gcls_ncls != (int)st->classes.size())
+        st->gcls_ncls != (int)st->classes.size() || st->gff_nrun != (int)st->runcls.size())
       return fail(EC_ERR_STATE,
                   "the self terms need new kernel or class windows (a footprint outgrew the window or a new "
                   "eigenstrain direction appeared): call ec_interaction_energies once");
+    // run tables on a new window need are rebuilt in place when they fit the
+    // state's buffer (their run classes are already on the device)
+    const int Drun = std::min(w->D, window_need(st));
+    if (st->gff_D != Drun) {
+      const size_t Wr = 2 * (size_t)Drun + 1;
+      if (std::max<size_t>(1, st->runcls.size()) * Wr * Wr * Wr * sizeof(double) > st->gff_bytes)
+        return fail(EC_ERR_STATE,
+                    "the self-term run tables must grow (a footprint grew): call ec_interaction_energies once");
+      LAUNCH(st, s, PF_OTHER, 0,
+             launch_run_tables(st->gcls, w->D, Drun, st->runinfo, (int)st->runcls.size(), st->gff, s));
+      st->gff_D = Drun;
+    }
     const int64_t cap = self_work_cap(st);
     if (cap > NA_MAX_ITEMS)
       return fail(EC_ERR_SIZE, "the self terms need %lld work items: the no-allocation energies take at most %lld",
                   (long long)cap, (long long)NA_MAX_ITEMS);
     char* base = (char*)st->ctx->scratch;
     LAUNCH(st, s, PF_SELF, 0,
-           launch_self_terms(b.tab, st->ndef, b.cnt, b.ids, st->n, w->K, st->gcls, w->D,
+           launch_self_terms(b.tab, st->ndef, b.cnt, b.ids, st->n, w->K, st->gcls, w->D, run_tables(st),
                              (SelfWork*)(base + NA_WORK_OFF), cap, (int64_t*)(base + NA_WBEG_OFF),
-                             (double*)(base + NA_PART_OFF), st->h3c, st->B, s));
+                             (double*)(base + NA_PART_OFF), (double*)(base + NA_RUN_OFF), st->h3c, st->B, s));
     st->B_valid = true;
   }
   LAUNCH(st, s, PF_REDUCE, 0,

@@ -92,6 +92,8 @@ struct DevDefect {
   int64_t efix[6];
   double E[6];    // eigenstrain, tensor components xx yy zz yz xz xy
   double s;       // E = s * class direction (when cls >= 0)
+  int32_t rt[3];  // run direction: a small lattice vector in the habit plane (loops) or x (spheres)
+  int32_t rcls;   // run class (class and run direction) of the self-term tables, -1: none
 };
 
 // Voxel-centre membership, exact integer arithmetic (loops: half-open slab
@@ -340,11 +342,35 @@ hipError_t launch_class_windows(const double* K, int D, const double* dirs, int 
 struct SelfWork {
   int32_t def, p0, p1, pad;
 };
+// Runs of one footprint held in LDS by the self-term run path at most; the host
+// gives a defect a run class only when a bound on its run count stays below.
+constexpr int SELF_RUN_MAX = 8192;
+
+// Run tables of the self terms: for run class r (class c, run direction t),
+// ff[r W^3 + point] holds the double prefix sum of the class window g_c along
+// t over the window of half-width D (W = 2 D + 1; see k_run_tables);
+// info[r] = {c, tx, ty, tz}.  D is the state's own window need, so the tables
+// (and the self terms) do not depend on how wide the shared kernel window has
+// grown for other states.
+struct RunTables {
+  const double* ff = nullptr;
+  const int4* info = nullptr;
+  int nrun = 0;
+  int D = 0;
+  int max_runs = 0;  // largest run bound of a defect on the run path (LDS of the run kernel)
+};
 // Builds the work list on the device in one workgroup (scratch: wbeg[ndef + 1])
-// and runs it on a fixed grid; no host synchronisation.
+// and runs it on a fixed grid; no host synchronisation.  Defects with a run
+// class whose box fits the window take the run path instead (scratch:
+// runsum[ndef]).
 hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int n,
-                             const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
-                             int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s);
+                             const double* K, const double* gcls, int D, RunTables rt, SelfWork* work,
+                             int64_t work_cap, int64_t* wbeg, double* partial, double* runsum, double h3c, double* B,
+                             hipStream_t s);
+// The run tables of nrun run classes on the half-width Drun <= Dg from the
+// class windows g ((2 Dg + 1)^3 per class).
+hipError_t launch_run_tables(const double* g, int Dg, int Drun, const int4* info, int nrun, double* ff,
+                             hipStream_t s);
 // Jump probes: dE[i nj + j] for jump jumps[3 (i nj + j) ..] of defect i (see
 // k_energy.hip); S0 = the footprint sums of the last reduction, B the self
 // terms; scratch as for the self terms, t1[ndef nj], wbeg[ndef nj + 1].
@@ -369,9 +395,9 @@ hipError_t launch_jump_select(const double* dE, int ndef, int nj, const double* 
 // for the generic path) and its scale s (E = s e).
 struct ClassTag {
   double s;
-  int32_t cls, pad;
+  int32_t cls, rcls;
 };
-// Writes tags[i] into defs[i].cls / defs[i].s.
+// Writes tags[i] into defs[i].cls / defs[i].s / defs[i].rcls.
 hipError_t launch_set_class(DevDefect* d, int ndef, const ClassTag* tags, hipStream_t s);
 // which 0: sigma, 1: eps = C^-1:sigma + eps*, 2: eps* alone; out is float or double.
 hipError_t launch_sig_to_out(const double* sig, const int32_t* own, const int2* lnk, const DevDefect* defs, int ndef,

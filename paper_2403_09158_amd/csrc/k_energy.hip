@@ -161,14 +161,33 @@ constexpr int PT = 1024;  // threads of the planning workgroup
 // [p0, p1) of a defect's pair triangle with about equal pair counts (rows
 // [0, p) hold p m - p (p - 1) / 2 pairs).  Each thread takes a contiguous run
 // of defects.
-__global__ __launch_bounds__(PT) void k_self_plan(const int32_t* __restrict__ cnt, int ndef,
-                                                  int64_t* __restrict__ wbeg, SelfWork* __restrict__ work,
-                                                  int64_t cap) {
+// Self terms by runs: a footprint is a union of runs along its run direction
+// t (maximal segments of voxels p, p + t, p + 2t, ...; a convex footprint meets
+// each lattice line along t in one run).  For runs A = {P_A + a t, a < L_A} and
+// B = {P_B + b t, b < L_B} the pair sum of the class window g is
+//   sum_{a, b} g(d + (a - b) t),  d = P_A - P_B,
+// and with F, FF the single and double prefix sums of g along the lines of the
+// window in direction t (zero before a line enters the window),
+//   = FF(d + (L_A - 1) t) - FF(d - t) - FF(d + (L_A - 1 - L_B) t) + FF(d - (L_B + 1) t),
+// four lookups per run pair instead of L_A L_B.  g is even, so the ordered
+// pairs (A, B) and (B, A) give the same sum.  A defect takes this path when it
+// has a run class with a table (the host gives one only when at most
+// SELF_RUN_MAX runs can occur, so they fit LDS) and its box fits the tables'
+// window (every pair offset within +-rt.D); the host applies the same test to
+// size the pair path's work list.
+__device__ __forceinline__ bool self_by_runs(const DevDefect& d, int, const RunTables& rt) {
+  return d.rcls >= 0 && d.rcls < rt.nrun && d.w[0] <= rt.D + 1 && d.w[1] <= rt.D + 1 && d.w[2] <= rt.D + 1;
+}
+
+__global__ __launch_bounds__(PT) void k_self_plan(const int32_t* __restrict__ cnt, const DevDefect* __restrict__ defs,
+                                                  int ndef, RunTables rt, int64_t* __restrict__ wbeg,
+                                                  SelfWork* __restrict__ work, int64_t cap) {
+  auto items = [&](int i) { return self_by_runs(defs[i], cnt[i], rt) ? 0 : self_items_of(cnt[i]); };
   __shared__ int64_t part[2 * (PT / 64)];
   const int per = (ndef + PT - 1) / PT;
   const int b = threadIdx.x * per, e = min(ndef, b + per);
   int64_t s = 0;
-  for (int i = b; i < e; ++i) s += self_items_of(cnt[i]);
+  for (int i = b; i < e; ++i) s += items(i);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int64_t x = s;
   for (int o = 1; o < 64; o <<= 1) {
@@ -190,7 +209,7 @@ __global__ __launch_bounds__(PT) void k_self_plan(const int32_t* __restrict__ cn
   if (threadIdx.x == PT - 1) wbeg[ndef] = part[2 * (PT / 64) - 1];
   for (int i = b; i < e; ++i) {
     const int m = cnt[i];
-    const int k = self_items_of(m);
+    const int k = items(i);
     const double tot = (double)m * (m + 1.0) * 0.5, a = m + 0.5;
     wbeg[i] = at;
     int p0 = 0;
@@ -358,14 +377,178 @@ __global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs,
   }
 }
 
+// One workgroup per defect on the run path: the runs of the footprint (a run
+// starts at a member p whose p - t is not a member; exact integer membership),
+// compacted in footprint order into dynamic LDS (rcap runs), then the run
+// pairs A <= B over the threads, summed with Neumaier compensation and
+// combined in a fixed tree, so the result does not depend on timing.  Defects
+// off the run path return at once.
+//
+// A run's length comes from walking p + k t until the first non-member, with
+// the membership quantities updated by additions: for the offset d_k = d + k T
+// (T = 1024 t, q units) |d_k|^2 and m.d_k grow by 2 d_k.T + |T|^2 and m.T.  A
+// footprint spans less than half the cell, so its runs never reach the
+// minimum-image wrap; past it the unwrapped offset is far outside, as the
+// wrapped one would be.
+__device__ __forceinline__ int wrap_n(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__global__ __launch_bounds__(ST) void k_self_runs(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
+                                                  const int32_t* __restrict__ ids, int n, RunTables rtab, int rcap,
+                                                  double* __restrict__ runsum) {
+  extern __shared__ int32_t rstart[];  // rcap entries: box-relative x | y << 10 | z << 20 of each run's first voxel
+  int16_t* rlen = reinterpret_cast<int16_t*>(rstart + rcap);
+  __shared__ int wcnt[ST / 64];
+  __shared__ double wsum[ST / 64], wcmp[ST / 64];
+  const int i = blockIdx.x;
+  const DevDefect d = defs[i];
+  const int m = cnt[i];
+  if (!self_by_runs(d, m, rtab)) return;
+  const int D = rtab.D;
+  const int tx = d.rt[0], ty = d.rt[1], tz = d.rt[2];
+  const int lx = d.lo[0], ly = d.lo[1], lz = d.lo[2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t Lq = QSUB * n, hq = Lq / 2;
+  const int64_t T0 = (int64_t)QSUB * tx, T1 = (int64_t)QSUB * ty, T2 = (int64_t)QSUB * tz;
+  const int64_t TT = T0 * T0 + T1 * T1 + T2 * T2;
+  const int64_t mT = (int64_t)d.m[0] * T0 + (int64_t)d.m[1] * T1 + (int64_t)d.m[2] * T2;
+  const int64_t lim = (int64_t)d.eq * d.eq * d.mm, rr = (int64_t)d.mm * d.R2q;
+  int nrun = 0;
+  for (int k0 = 0; k0 < m; k0 += ST) {
+    const int k = k0 + threadIdx.x;
+    bool start = false;
+    int32_t pk = 0;
+    int len = 0;
+    if (k < m) {
+      const int id = ids[d.slot + k];
+      const int x = id % n, y = (id / n) % n, z = id / (n * n);
+      start = !member(d, n, wrap_n(x - tx, n), wrap_n(y - ty, n), wrap_n(z - tz, n));
+      if (start) {
+        const int v[3] = {x, y, z};
+        int64_t dd[3];
+        for (int a = 0; a < 3; ++a) {
+          int32_t q = QSUB * v[a] + QSUB / 2 - d.cq[a];
+          q += (q < -hq) ? Lq : 0;
+          q -= (q >= hq) ? Lq : 0;
+          dd[a] = q;
+        }
+        int64_t d2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+        int64_t dT = dd[0] * T0 + dd[1] * T1 + dd[2] * T2;
+        int64_t tm = (int64_t)d.m[0] * dd[0] + (int64_t)d.m[1] * dd[1] + (int64_t)d.m[2] * dd[2];
+        len = 1;
+        for (; len < n; ++len) {  // offset of p + len t from that of p + (len - 1) t
+          d2 += 2 * dT + TT;
+          dT += TT;
+          tm += mT;
+          bool in;
+          if (d.kind == 1) {
+            in = d2 <= d.R2q;
+          } else {
+            const bool slab = (tm >= 0) ? (4 * tm * tm < lim) : (4 * tm * tm <= lim);
+            in = slab && ((int64_t)d.mm * d2 - tm * tm <= rr);
+          }
+          if (!in) break;
+        }
+        const int bx = wrap_n(x - lx, n), by = wrap_n(y - ly, n), bz = wrap_n(z - lz, n);
+        pk = bx | (by << 10) | (bz << 20);
+      }
+    }
+    const uint64_t bal = __ballot(start);
+    if (lane == 0) wcnt[wave] = __popcll(bal);
+    __syncthreads();
+    int before = __popcll(bal & ((1ull << lane) - 1)), tot = 0;
+    for (int w = 0; w < ST / 64; ++w) {
+      if (w < wave) before += wcnt[w];
+      tot += wcnt[w];
+    }
+    if (start && nrun + before < rcap) {  // always true under the host's run bound
+      rstart[nrun + before] = pk;
+      rlen[nrun + before] = (int16_t)len;
+    }
+    nrun += tot;
+    __syncthreads();  // wcnt is rewritten by the next chunk; the runs are read below
+  }
+  nrun = nrun < rcap ? nrun : rcap;
+  const int W = 2 * D + 1;
+  const double* ff = rtab.ff + (size_t)d.rcls * W * W * W;
+  double s = 0.0, c = 0.0;
+  const int64_t npair = (int64_t)nrun * (nrun + 1) / 2;
+  for (int64_t u = threadIdx.x; u < npair; u += ST) {
+    // (A, B), A <= B, from the triangular index u = B (B + 1) / 2 + A
+    int Bi = (int)((sqrt(8.0 * (double)u + 1.0) - 1.0) * 0.5);
+    while ((int64_t)Bi * (Bi + 1) / 2 > u) --Bi;
+    while ((int64_t)(Bi + 1) * (Bi + 2) / 2 <= u) ++Bi;
+    const int Ai = (int)(u - (int64_t)Bi * (Bi + 1) / 2);
+    const int32_t PA = rstart[Ai], PB = rstart[Bi];
+    const int La = rlen[Ai], Lb = rlen[Bi];
+    const int dx = (PA & 1023) - (PB & 1023), dy = ((PA >> 10) & 1023) - ((PB >> 10) & 1023),
+              dz = (PA >> 20) - (PB >> 20);
+    auto ffat = [&](int kk) -> double {
+      const int px = dx + kk * tx, py = dy + kk * ty, pz = dz + kk * tz;
+      if (px < -D || px > D || py < -D || py > D || pz < -D || pz > D) return 0.0;  // before the line enters
+      return ff[((pz + D) * W + (py + D)) * W + (px + D)];
+    };
+    const double v = (ffat(La - 1) - ffat(-1)) - (ffat(La - 1 - Lb) - ffat(-Lb - 1));
+    neumaier(s, c, Ai == Bi ? v : 2.0 * v);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double s2 = __shfl_down(s, off), c2 = __shfl_down(c, off);
+    neumaier_merge(s, c, s2, c2);
+  }
+  if (lane == 0) {
+    wsum[wave] = s;
+    wcmp[wave] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ss = wsum[0], cc = wcmp[0];
+    for (int w = 1; w < ST / 64; ++w) neumaier_merge(ss, cc, wsum[w], wcmp[w]);
+    runsum[i] = ss + cc;
+  }
+}
+
+// Double prefix sums of the class windows along each run class's direction:
+// one thread per (run class, window point); a point whose predecessor along t
+// lies outside the window starts a line, and its thread walks the line,
+// storing FF = sum of F, F = sum of g (both compensated) at every point.
+__global__ void k_run_tables(const double* __restrict__ g, int Dg, int D, const int4* __restrict__ info, int nrun,
+                             double* __restrict__ ff) {
+  const int W = 2 * D + 1, Wg = 2 * Dg + 1;
+  const int64_t W3 = (int64_t)W * W * W, Wg3 = (int64_t)Wg * Wg * Wg;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W3 * nrun) return;
+  const int r = (int)(t / W3);
+  const int64_t p = t % W3;
+  const int4 q = info[r];
+  int x = (int)(p % W) - D, y = (int)((p / W) % W) - D, z = (int)(p / ((int64_t)W * W)) - D;
+  auto inside = [&](int a, int b, int c) { return a >= -D && a <= D && b >= -D && b <= D && c >= -D && c <= D; };
+  if (inside(x - q.y, y - q.z, z - q.w)) return;  // not the first point of its line
+  const double* gc = g + (size_t)q.x * Wg3;
+  double* out = ff + (size_t)r * W3;
+  double fs = 0.0, fc = 0.0, Fs = 0.0, Fc = 0.0;
+  while (inside(x, y, z)) {
+    const int64_t idx = ((int64_t)(z + D) * W + (y + D)) * W + (x + D);
+    neumaier(fs, fc, gc[((int64_t)(z + Dg) * Wg + (y + Dg)) * Wg + (x + Dg)]);
+    neumaier(Fs, Fc, fs + fc);
+    out[idx] = Fs + Fc;
+    x += q.y;
+    y += q.z;
+    z += q.w;
+  }
+}
+
 // B_i = -h^3 c s_i^2 sum(partials) (class windows hold the unit direction) or
 // -h^3 c sum(partials) (full-tensor path); partials added in a fixed order.
-__global__ void k_self_finish(const int64_t* __restrict__ wbeg, const double* __restrict__ partial,
+__global__ void k_self_finish(const int64_t* __restrict__ wbeg, int64_t cap, const double* __restrict__ partial,
+                              const double* __restrict__ runsum, const int32_t* __restrict__ cnt, RunTables rt,
                               const DevDefect* __restrict__ defs, int ndef, double h3c, double* __restrict__ B) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ndef) return;
   double s = 0.0, c = 0.0;
-  for (int64_t w = wbeg[i]; w < wbeg[i + 1]; ++w) neumaier(s, c, partial[w]);
+  if (self_by_runs(defs[i], cnt[i], rt)) s = runsum[i];
+  if (cap > 0) {  // no plan ran without pair-path items
+    const int64_t we = wbeg[i + 1] < cap ? wbeg[i + 1] : cap;  // the plan stores items below cap only
+    for (int64_t w = wbeg[i]; w < we; ++w) neumaier(s, c, partial[w]);
+  }
   const double scale = defs[i].cls >= 0 ? defs[i].s * defs[i].s : 1.0;
   B[i] = -h3c * scale * (s + c);
 }
@@ -773,6 +956,7 @@ __global__ __launch_bounds__(256) void k_set_class(DevDefect* __restrict__ defs,
   if (i < ndef) {
     defs[i].cls = tags[i].cls;
     defs[i].s = tags[i].s;
+    defs[i].rcls = tags[i].rcls;
   }
 }
 
@@ -808,15 +992,37 @@ hipError_t launch_class_windows(const double* K, int D, const double* dirs, int 
 }
 
 hipError_t launch_self_terms(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, int n,
-                             const double* K, const double* gcls, int D, SelfWork* work, int64_t work_cap,
-                             int64_t* wbeg, double* partial, double h3c, double* B, hipStream_t s) {
+                             const double* K, const double* gcls, int D, RunTables rt, SelfWork* work,
+                             int64_t work_cap, int64_t* wbeg, double* partial, double* runsum, double h3c, double* B,
+                             hipStream_t s) {
   if (ndef == 0) return hipSuccess;
   const int g1 = (ndef + 255) / 256;
-  hipLaunchKernelGGL(k_self_plan, dim3(1), dim3(PT), 0, s, counts, ndef, wbeg, work, work_cap);
-  const int grid = (int)std::min<int64_t>(work_cap, 4096);
-  hipLaunchKernelGGL(k_self, dim3(grid), dim3(ST), 0, s, d, counts, ids, n, K, gcls, D, work, wbeg + ndef, work_cap,
-                     partial);
-  hipLaunchKernelGGL(k_self_finish, dim3(g1), dim3(256), 0, s, wbeg, partial, d, ndef, h3c, B);
+  if (rt.nrun > 0) {
+    const int rcap = std::max(1, std::min(rt.max_runs, SELF_RUN_MAX));
+    const size_t lds = (size_t)rcap * (sizeof(int32_t) + sizeof(int16_t));
+    hipLaunchKernelGGL(k_self_runs, dim3(ndef), dim3(ST), lds, s, d, counts, ids, n, rt, rcap, runsum);
+  }
+  // the pair path only for the defects off the run path (work_cap bounds their
+  // items; none: neither the plan nor the pair kernel runs)
+  if (work_cap > 0) {
+    hipLaunchKernelGGL(k_self_plan, dim3(1), dim3(PT), 0, s, counts, d, ndef, rt, wbeg, work, work_cap);
+    const int grid = (int)std::min<int64_t>(work_cap, 4096);
+    hipLaunchKernelGGL(k_self, dim3(grid), dim3(ST), 0, s, d, counts, ids, n, K, gcls, D, work, wbeg + ndef,
+                       work_cap, partial);
+  }
+  hipLaunchKernelGGL(k_self_finish, dim3(g1), dim3(256), 0, s, wbeg, work_cap, partial, runsum, counts, rt, d, ndef,
+                     h3c, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_run_tables(const double* g, int Dg, int Drun, const int4* info, int nrun, double* ff,
+                             hipStream_t s) {
+  if (nrun == 0) return hipSuccess;
+  if (Drun > Dg) return hipErrorInvalidValue;
+  const int W = 2 * Drun + 1;
+  const int64_t tot = (int64_t)W * W * W * nrun;
+  hipLaunchKernelGGL(k_run_tables, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, g, Dg, Drun, info, nrun,
+                     ff);
   return hipGetLastError();
 }
 
