@@ -694,6 +694,7 @@ bool quantise(const ec_problem& P, const ec_defect& rec, DevDefect& d, std::stri
       return err = "eigenstrain component too large", false;
     d.efix[a] = (int64_t)std::llrint(Ef[a] * FIX_SCALE);
   }
+  set_efd(d);
   for (int k = 0; k < 3; ++k) {
     const int64_t lo = floordiv((int64_t)d.cq[k] - ext - 512 + (QSUB - 1), QSUB);
     const int64_t hi = floordiv((int64_t)d.cq[k] + ext - 512, QSUB);
@@ -949,6 +950,7 @@ ec_status ensure_window(ec_state* st, int Dneed, hipStream_t s) {
       else
         std::copy(e, e + 6, ec);
       for (int a = 0; a < 6; ++a) unit[b].efix[a] = (int64_t)std::llrint(ec[a] * FIX_SCALE);
+      set_efd(unit[b]);
     }
     DevDefect* dunit = (DevDefect*)imp;
     int2* dlnk = (int2*)((char*)imp + 6 * sizeof(DevDefect));

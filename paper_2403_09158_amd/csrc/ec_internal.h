@@ -41,10 +41,14 @@ constexpr double FIX_INV = 1.0 / 72057594037927936.0;
 template <class Defs>
 __device__ __forceinline__ void decode_voxel(int32_t link, const int2* __restrict__ lnk, const Defs& defs,
                                              double* e, int max_links) {
-  if (link >= 0) {  // one owner (the common case)
-    const int64_t* f = defs[link].efix;
+  if (link >= 0) {  // one owner (the common case): its converted value, three 16-byte loads
+    const double2* f = reinterpret_cast<const double2*>(defs[link].efd);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) e[c] = (double)f[c] * FIX_INV;
+    for (int c = 0; c < 3; ++c) {
+      const double2 v = f[c];
+      e[2 * c] = v.x;
+      e[2 * c + 1] = v.y;
+    }
     return;
   }
   int64_t hi[6] = {0, 0, 0, 0, 0, 0}, lo[6] = {0, 0, 0, 0, 0, 0};
@@ -94,7 +98,13 @@ struct DevDefect {
   double s;       // E = s * class direction (when cls >= 0)
   int32_t rt[3];  // run direction: a small lattice vector in the habit plane (loops) or x (spheres)
   int32_t rcls;   // run class (class and run direction) of the self-term tables, -1: none
+  alignas(16) double efd[6];  // (double)efix * 2^-56: the eigenstrain of a voxel this defect alone covers
 };
+
+// The double form of a record's fixed-point eigenstrain (set with efix).
+__host__ __device__ inline void set_efd(DevDefect& d) {
+  for (int c = 0; c < 6; ++c) d.efd[c] = (double)d.efix[c] * 1.3877787807814457e-17;  // 2^-56
+}
 
 // Voxel-centre membership, exact integer arithmetic (loops: half-open slab
 // along the lattice normal m, closed disk; spheres: closed ball).  d is the

@@ -182,6 +182,42 @@ __device__ __forceinline__ void green_bin_rot(double2* e, int kx, int ky, int kz
   rot6(C.frm + 36, ec, e);
 }
 
+// Tile order of a persistent pass.  The tiles are split into eight
+// contiguous ranges, one per XCD (dispatch puts workgroup b on XCD b % 8), so
+// that neighbouring tiles share an L2.  With a counter per XCD (zero at
+// launch) the workgroups of an XCD claim its tiles one at a time, so that one
+// starting late behind other work on its CU takes fewer tiles instead of
+// holding up the pass; without counters each takes every (grid / 8)-th tile
+// of the range.  The tile after the current one is known an iteration ahead
+// (for the prefetch): next() at the top of an iteration gives it, the claim
+// for the one after it is issued then and stored before the iteration's last
+// barrier.
+struct TileWalk {
+  int lo, hi, g8, xcd;
+  uint32_t* ctr;  // nullptr: static order
+  int* slot;      // two LDS entries
+  __device__ TileWalk(int ntiles, uint32_t* c, int* sl) : ctr(c), slot(sl) {
+    g8 = (int)gridDim.x / 8;
+    const int per = (ntiles + 7) / 8;
+    xcd = (int)(blockIdx.x % 8);
+    lo = xcd * per;
+    hi = min(ntiles, lo + per);
+  }
+  // the first two tiles (a barrier must follow before first())
+  __device__ void claim_first() {
+    if (ctr && threadIdx.x == 0) {
+      slot[0] = lo + (int)atomicAdd(&ctr[xcd], 1u);
+      slot[1] = lo + (int)atomicAdd(&ctr[xcd], 1u);
+    }
+  }
+  __device__ int first() const { return ctr ? slot[0] : lo + (int)(blockIdx.x / 8); }
+  __device__ int next(int t, int it) const { return ctr ? slot[(it + 1) & 1] : t + g8; }
+  __device__ uint32_t claim_issue() { return (ctr && threadIdx.x == 0) ? atomicAdd(&ctr[xcd], 1u) : 0u; }
+  __device__ void claim_store(int it, uint32_t v) {
+    if (ctr && threadIdx.x == 0) slot[it & 1] = lo + (int)v;
+  }
+};
+
 // ----------------------------------------------------------------- x forward (R2C)
 
 // x forward pass with a two-stage plan of equal radices: each thread reads
@@ -205,6 +241,10 @@ __device__ __forceinline__ auto x_twiddles(const double2* tw_lds, const double2*
   }
 }
 
+// Persistent: each workgroup walks row groups (ROWS rows of one z plane) in a
+// fixed order within its XCD's contiguous range, and loads the next group's
+// owner links into registers while it decodes and transforms the current one,
+// so the HBM latency of the owner map overlaps the work of the group before.
 template <int N, typename S, bool DENSE>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
     const int32_t* __restrict__ own, const int2* __restrict__ lnk, const DevDefect* __restrict__ defs,
@@ -215,89 +255,107 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   constexpr int T = pick_T(max_nb(N, NF));
   constexpr int LDN = N + N / 16 + 1;
   constexpr int NH = N / 2 + 1;
+  constexpr int bpp = N / ROWS;
+  constexpr int NG = N * bpp;  // row groups
   __shared__ double2 buf[NF * LDN];
   __shared__ double2 tw[x_twreg<N>() ? 1 : N];
+  __shared__ int tslot[2];
   if constexpr (!x_twreg<N>())
     for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
   if (zero_ctr && blockIdx.x == 0 && threadIdx.x < NTILECTR) zero_ctr[threadIdx.x] = 0u;
-  const int bpp = N / ROWS;
-  const int z = blockIdx.x / bpp;
-  const int y0 = (blockIdx.x % bpp) * ROWS;
   const size_t n3 = (size_t)N * N * N;
   auto lds = [&](int f, int i) -> double2* { return &buf[f * LDN + i + (i >> 4)]; };
-  // gather the rows' six components into the transform inputs (xx + i yy, ...);
-  // all of a thread's voxel links are loaded first, then the owners' records
   constexpr int KV = (ROWS * N + T - 1) / T;
-  int32_t link[KV];
+  // a group's voxels: ROWS consecutive rows, so ROWS * N consecutive ids
+  auto load_links = [&](int grp, int32_t* lk) {
 #pragma unroll
-  for (int k = 0; k < KV; ++k) {
-    const int i = threadIdx.x + k * T;
-    link[k] = -1;
-    if (!DENSE && i < ROWS * N) {
-      const int r = i / N, x = i - r * N;
-      link[k] = own[((size_t)z * N + y0 + r) * N + x];
+    for (int k = 0; k < KV; ++k) {
+      const int i = threadIdx.x + k * T;
+      lk[k] = -1;
+      if (!DENSE && i < ROWS * N) lk[k] = own[(size_t)grp * (ROWS * N) + i];
     }
-  }
+  };
+  TileWalk walk(NG, nullptr, tslot);
+  int grp = walk.first();
+  const int hi = walk.hi;
+  int32_t link[KV], nlink[KV];
+  if (grp < hi) load_links(grp, link);
+  const auto twp = x_twiddles<N, NF, T>(tw, twg);
+  __syncthreads();
+  for (int it = 0; grp < hi; ++it) {
+    const int gn = walk.next(grp, it);
+    if (gn < hi) load_links(gn, nlink);
+    const int z = grp / bpp;
+    const int y0 = (grp % bpp) * ROWS;
+    // gather the rows' six components into the transform inputs (xx + i yy, ...)
 #pragma unroll
-  for (int k = 0; k < KV; ++k) {
-    const int i = threadIdx.x + k * T;
-    if (i < ROWS * N) {
-      const int r = i / N, x = i - r * N;
-      double e[6];
-      if (DENSE) {
-        const size_t v = ((size_t)z * N + y0 + r) * N + x;
+    for (int k = 0; k < KV; ++k) {
+      const int i = threadIdx.x + k * T;
+      if (i < ROWS * N) {
+        const int r = i / N, x = i - r * N;
+        double e[6];
+        if (DENSE) {
+          const size_t v = ((size_t)z * N + y0 + r) * N + x;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) e[c] = dense[c * n3 + v];
-      } else {
-        decode_voxel(link[k], lnk, defs, e, max_links);
+          for (int c = 0; c < 6; ++c) e[c] = dense[c * n3 + v];
+        } else if (link[k] == -1) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) e[c] = 0.0;
+        } else {
+          decode_voxel(link[k], lnk, defs, e, max_links);
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) st2(lds(3 * r + p, x), make_double2(e[2 * p], e[2 * p + 1]));
       }
-#pragma unroll
-      for (int p = 0; p < 3; ++p) st2(lds(3 * r + p, x), make_double2(e[2 * p], e[2 * p + 1]));
     }
-  }
-  __syncthreads();
-  auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
-  auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
-  transform<N, false, Map::Row, NF, T, true, true>(x_twiddles<N, NF, T>(tw, twg), from_lds, from_lds, to_lds, to_lds);
-  __syncthreads();
-  // Hermitian split of the three pair transforms of a row into the six
-  // interleaved half-spectrum components.  FP64 storage: one output value per
-  // thread, so consecutive threads write consecutive 16-byte values of the
-  // row; FP32 storage: one bin (six values, 48 bytes) per thread, which
-  // halves the LDS reads and index work where the narrower writes matter less.
-  // The loops run over bins k < n/2; the thread of bin 0 of a row also does
-  // its bin n/2 (k = n/2 is its own mirror), so no loop pass is left with two
-  // busy threads.
-  if constexpr (sizeof(S) == 8) {
-    auto value = [&](int r, int k, int c) {
-      const int p = c >> 1;
-      const double2 zk = ld2(lds(3 * r + p, k));
-      const double2 zc = conjd(ld2(lds(3 * r + p, k == 0 ? 0 : N - k)));
-      const double2 v = (c & 1) ? make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x))
-                                : make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
-      st2(spec + spec_at(z, y0 + r, k, c, N, P), v);
-    };
-    for (int e = threadIdx.x; e < ROWS * (N / 2) * 6; e += T) {
-      const int r = e / ((N / 2) * 6), q = e % ((N / 2) * 6), k = q / 6, c = q % 6;
-      value(r, k, c);
-      if (k == 0) value(r, N / 2, c);
-    }
-  } else {
-    auto bin = [&](int r, int k) {
-      typename Cplx<S>::T* const out = spec + spec_at(z, y0 + r, k, 0, N, P);
-#pragma unroll
-      for (int p = 0; p < 3; ++p) {
+    __syncthreads();
+    auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
+    auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
+    transform<N, false, Map::Row, NF, T, true, true>(twp, from_lds, from_lds, to_lds, to_lds);
+    __syncthreads();
+    // Hermitian split of the three pair transforms of a row into the six
+    // interleaved half-spectrum components.  FP64 storage: one output value per
+    // thread, so consecutive threads write consecutive 16-byte values of the
+    // row; FP32 storage: one bin (six values, 48 bytes) per thread, which
+    // halves the LDS reads and index work where the narrower writes matter less.
+    // The loops run over bins k < n/2; the thread of bin 0 of a row also does
+    // its bin n/2 (k = n/2 is its own mirror), so no loop pass is left with two
+    // busy threads.
+    if constexpr (sizeof(S) == 8) {
+      auto value = [&](int r, int k, int c) {
+        const int p = c >> 1;
         const double2 zk = ld2(lds(3 * r + p, k));
         const double2 zc = conjd(ld2(lds(3 * r + p, k == 0 ? 0 : N - k)));
-        st2(out + 2 * p, make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y)));
-        st2(out + 2 * p + 1, make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x)));
+        const double2 v = (c & 1) ? make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x))
+                                  : make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+        st2(spec + spec_at(z, y0 + r, k, c, N, P), v);
+      };
+      for (int e = threadIdx.x; e < ROWS * (N / 2) * 6; e += T) {
+        const int r = e / ((N / 2) * 6), q = e % ((N / 2) * 6), k = q / 6, c = q % 6;
+        value(r, k, c);
+        if (k == 0) value(r, N / 2, c);
       }
-    };
-    for (int e = threadIdx.x; e < ROWS * (N / 2); e += T) {
-      const int r = e / (N / 2), k = e % (N / 2);
-      bin(r, k);
-      if (k == 0) bin(r, N / 2);
+    } else {
+      auto bin = [&](int r, int k) {
+        typename Cplx<S>::T* const out = spec + spec_at(z, y0 + r, k, 0, N, P);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+          const double2 zk = ld2(lds(3 * r + p, k));
+          const double2 zc = conjd(ld2(lds(3 * r + p, k == 0 ? 0 : N - k)));
+          st2(out + 2 * p, make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y)));
+          st2(out + 2 * p + 1, make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x)));
+        }
+      };
+      for (int e = threadIdx.x; e < ROWS * (N / 2); e += T) {
+        const int r = e / (N / 2), k = e % (N / 2);
+        bin(r, k);
+        if (k == 0) bin(r, N / 2);
+      }
     }
+    __syncthreads();  // the next group rewrites the LDS rows
+#pragma unroll
+    for (int k = 0; k < KV; ++k) link[k] = nlink[k];
+    grp = gn;
   }
 }
 
@@ -389,42 +447,6 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
 // run of 6 WX values; thread lane f = 6 w + c keeps its (column, component)
 // across butterflies (the workgroup size is a multiple of 6 WX).  The last kx
 // tile holds the n/2 column and idle lanes.
-
-// Tile order of a persistent pass.  The tiles are split into eight
-// contiguous ranges, one per XCD (dispatch puts workgroup b on XCD b % 8), so
-// that neighbouring tiles share an L2.  With a counter per XCD (zero at
-// launch) the workgroups of an XCD claim its tiles one at a time, so that one
-// starting late behind other work on its CU takes fewer tiles instead of
-// holding up the pass; without counters each takes every (grid / 8)-th tile
-// of the range.  The tile after the current one is known an iteration ahead
-// (for the prefetch): next() at the top of an iteration gives it, the claim
-// for the one after it is issued then and stored before the iteration's last
-// barrier.
-struct TileWalk {
-  int lo, hi, g8, xcd;
-  uint32_t* ctr;  // nullptr: static order
-  int* slot;      // two LDS entries
-  __device__ TileWalk(int ntiles, uint32_t* c, int* sl) : ctr(c), slot(sl) {
-    g8 = (int)gridDim.x / 8;
-    const int per = (ntiles + 7) / 8;
-    xcd = (int)(blockIdx.x % 8);
-    lo = xcd * per;
-    hi = min(ntiles, lo + per);
-  }
-  // the first two tiles (a barrier must follow before first())
-  __device__ void claim_first() {
-    if (ctr && threadIdx.x == 0) {
-      slot[0] = lo + (int)atomicAdd(&ctr[xcd], 1u);
-      slot[1] = lo + (int)atomicAdd(&ctr[xcd], 1u);
-    }
-  }
-  __device__ int first() const { return ctr ? slot[0] : lo + (int)(blockIdx.x / 8); }
-  __device__ int next(int t, int it) const { return ctr ? slot[(it + 1) & 1] : t + g8; }
-  __device__ uint32_t claim_issue() { return (ctr && threadIdx.x == 0) ? atomicAdd(&ctr[xcd], 1u) : 0u; }
-  __device__ void claim_store(int it, uint32_t v) {
-    if (ctr && threadIdx.x == 0) slot[it & 1] = lo + (int)v;
-  }
-};
 
 // largest radix of the pencil factorisation
 template <int N>
@@ -829,13 +851,32 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
 
 // ------------------------------------------------------------------ launchers
 
+// Grid of a tile-loop kernel, a multiple of eight.  Kernels that prefetch the
+// next tile (FP32 storage) get as many workgroups as stay resident; the others
+// get one tile per workgroup, so tiles overlap through the hardware scheduler.
+template <class K>
+int tile_grid(K kernel, int threads, int ntiles, bool prefetch) {
+  if (!prefetch) return ((ntiles + 7) / 8) * 8;
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+    return -1;
+  const int g = std::min(ncu * std::max(per_cu, 1), ntiles);
+  return std::max(8, (g / 8) * 8);
+}
+
 template <int N, typename S>
 hipError_t go_xf(const int32_t* own, const int2* lnk, const DevDefect* defs, int ndef, const double* dense,
                  void* spec, SpecGeom g, const double2* tw, uint32_t* zero_ctr, hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   static_assert(T >= NTILECTR, "the first block zeroes the tile counters");
-  const int grid = N * (N / x_rows(N));
+  const int ngroups = N * (N / x_rows(N));
   using C2 = typename Cplx<S>::T;
+  // as many workgroups as stay resident (a multiple of eight), at most one
+  // per row group
+  const int grid = tile_grid(k_x_forward<N, S, false>, T, ngroups, true);
+  if (grid < 0) return hipErrorInvalidValue;
   if (dense)
     hipLaunchKernelGGL((k_x_forward<N, S, true>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P, tw,
                        zero_ctr, ndef);
@@ -856,21 +897,6 @@ hipError_t go_xfs(const int32_t* oi, const int32_t* oc, const int32_t* ni, int n
   hipLaunchKernelGGL((k_x_forward_sparse<N, S>), dim3(grid), dim3(T), 0, s, oi, oc, ni, nc, sx, sy, sz, E,
                      (typename Cplx<S>::T*)spec, g.P, ylo, ylen, zlo, tw, zero_ctr);
   return hipGetLastError();
-}
-
-// Grid of a tile-loop kernel, a multiple of eight.  Kernels that prefetch the
-// next tile (FP32 storage) get as many workgroups as stay resident; the others
-// get one tile per workgroup, so tiles overlap through the hardware scheduler.
-template <class K>
-int tile_grid(K kernel, int threads, int ntiles, bool prefetch) {
-  if (!prefetch) return ((ntiles + 7) / 8) * 8;
-  int dev = 0, ncu = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
-    return -1;
-  const int g = std::min(ncu * std::max(per_cu, 1), ntiles);
-  return std::max(8, (g / 8) * 8);
 }
 
 // FP32 storage stages the inter-stage exchange in FP32 (half the LDS, so
