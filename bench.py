@@ -156,9 +156,11 @@ def energy_errors(E32, E64):
     }
 
 
-def serving_block(nreq=4000, rate=2000.0, slots=4, plain_req=1000):
+def serving_block(nreq=4000, rate=2000.0, slots=4, plain_req=1000, budget_gb=200.0):
     """Serving workload: 64 replicas (grids 64-240, 50-1500 defects), Poisson
-    arrivals, 90 % one-defect hops, 10 % re-solves."""
+    arrivals, 90 % one-defect hops, 10 % re-solves, admitted against a 200 GB
+    HBM budget; ready hops of one grid shape are batched and replayed from HIP
+    graphs."""
     import numpy as np
 
     from paper_2403_09158_amd import ec, inputs, serve
@@ -169,15 +171,19 @@ def serving_block(nreq=4000, rate=2000.0, slots=4, plain_req=1000):
         f"Poisson {rate:.0f} req/s, 90% (+-1,+-1,+-1) hops of a random defect, 10% re-solves",
         "slots": slots,
     }
-    ctx = ec.Context(0)
+    out["hbm_budget_gb"] = budget_gb
+    ctx = ec.Context(0, budget_bytes=int(budget_gb * 1e9))
     srv = serve.Server(ctx, reps, slots=slots)
     srv.warm()
     st = srv.run(serve.serving_requests(reps, nreq, rate), realtime=True)
     out["fp32_served"] = {"requests": nreq, "throughput_req_s": round(st.throughput, 1), "p50_ms": round(st.p50_ms, 4),
-                          "p99_ms": round(st.p99_ms, 4), "mean_ms": round(st.mean_ms, 4)}
+                          "p99_ms": round(st.p99_ms, 4), "mean_ms": round(st.mean_ms, 4), "batches": st.batches}
     st = srv.run(serve.serving_requests(reps, 3000, 1e9), realtime=False)
     out["fp32_saturated"] = {"requests": 3000, "throughput_req_s": round(st.throughput, 1),
-                             "p99_ms_queued_at_t0": round(st.p99_ms, 2)}
+                             "p99_ms_queued_at_t0": round(st.p99_ms, 2), "batches": st.batches}
+    out["hip_graphs"] = ctx.graphs()
+    used, budget = ctx.ledger()
+    out["ledger_gb"] = {"used": round(used / 1e9, 3), "budget": round(budget / 1e9, 1)}
     srv.close()
     ctx.close()
     ctx = ec.Context(0)

@@ -131,6 +131,10 @@ EC_API void ec_ctx_destroy(ec_ctx* ctx);
 /* Bytes the context has admitted so far, and its budget. */
 EC_API ec_status ec_ctx_ledger(const ec_ctx* ctx, size_t* used, size_t* budget);
 
+/* Number of executable HIP graphs the context holds for batched hops
+ * (ec_update_batch with use_graph on a non-null stream). */
+EC_API ec_status ec_ctx_graphs(const ec_ctx* ctx, int32_t* count);
+
 /* Thread-local text of the last error raised on this thread (never NULL). */
 EC_API const char* ec_last_error(void);
 
@@ -178,6 +182,22 @@ EC_API ec_status ec_interaction_energies_noalloc(ec_state* st, void* hip_stream,
  * energies are returned as in ec_interaction_energies. */
 EC_API ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, void* hip_stream, double* E_out,
                            int32_t out_on_device);
+
+/* Several whole-voxel hops at once, one per state (Appendix B's move, as
+ * ec_update_defect): states[k] are distinct solved states of one shape (the
+ * same n, precision, stiffness and frame), idx[k] the moved defect of each and
+ * moved[k] its record after the hop, a translation of its current record by
+ * whole voxels (same shape and eigenstrain; any other move is EC_ERR_ARG: use
+ * ec_update_defect).  The k hops run as one launch per pass over all k
+ * replicas' data (batched persistent passes); with use_graph != 0 and a
+ * non-null stream the launch sequence is captured once per (shape, k, stream)
+ * in a HIP graph and replayed with the new hops (direct launches otherwise).  E_dev: NULL or k device buffers (NULL entries allowed) of
+ * each state's ndef doubles, the energies after its hop; the states' own
+ * energies are refreshed as ec_interaction_energies does.  Nothing is
+ * synchronised; k in [1, 16].  Results are the same, bit for bit, as k calls
+ * of ec_update_defect. */
+EC_API ec_status ec_update_batch(ec_state* const* states, const int32_t* idx, const ec_defect* moved, int32_t k,
+                                 void* hip_stream, double* const* E_dev, int32_t use_graph);
 
 /* ---- jump probes (the OkMC loop of App. A; biased jumps of Sec. 4) ---------- */
 

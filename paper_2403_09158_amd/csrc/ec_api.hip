@@ -202,9 +202,37 @@ hipError_t noalloc_scratch(int device, void** out) {
 }
 }  // namespace
 
+// Buffers (and, once captured, the executable graph) of batched hops of one
+// shape, batch size and stream: the pinned job table the host fills, its device
+// copy, the tile counters, a zero mean-stress change and the frame maps.  The
+// graph reads the pinned table at a fixed address, so a new batch waits for the
+// previous launch from the same entry before rewriting it.
+struct BatchEntry {
+  HopJob* pin = nullptr;
+  HopJob* dev = nullptr;
+  uint32_t* ctr = nullptr;
+  double* zero6 = nullptr;
+  double* frm = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool graph_failed = false;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+struct BatchKey {
+  int n, prec, k;
+  double C11, C12, C44;
+  std::array<double, 9> frame;
+  void* stream;
+  bool operator<(const BatchKey& o) const {
+    return std::tie(n, prec, k, C11, C12, C44, frame, stream) <
+           std::tie(o.n, o.prec, o.k, o.C11, o.C12, o.C44, o.frame, o.stream);
+  }
+};
+
 struct ec_ctx {
   int device = 0;
   void* scratch = nullptr;  // this device's copy of the fixed scratch area
+  std::map<BatchKey, BatchEntry> batches;
   size_t budget = 0, used = 0;
   ec_alloc_fn af = nullptr;
   ec_free_fn ff = nullptr;
@@ -1580,6 +1608,111 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
   return EC_OK;
 }
 
+// The hop job of moving defect idx of st to the quantised record nd, if that
+// move is a whole-voxel translation of the same shape and eigenstrain (false
+// otherwise).  The record takes the defect's class, run class and slot.
+bool hop_job(ec_state* st, int32_t idx, DevDefect& nd, HopJob& job) {
+  const DevDefect& od = st->hdefs[idx];
+  const int n = st->n;
+  bool hop = od.kind == nd.kind && od.R2q == nd.R2q && od.eq == nd.eq && od.mm == nd.mm;
+  for (int k = 0; k < 3 && hop; ++k) hop = od.m[k] == nd.m[k] && ((nd.cq[k] - od.cq[k]) % QSUB) == 0;
+  for (int a = 0; a < 6 && hop; ++a) hop = od.efix[a] == nd.efix[a];
+  if (!hop) return false;
+  int sh[3];
+  for (int k = 0; k < 3; ++k) {
+    int d = ((nd.cq[k] - od.cq[k]) / QSUB) % n;
+    if (d < 0) d += n;
+    if (d >= n / 2) d -= n;
+    sh[k] = d;
+  }
+  nd.cls = od.cls;
+  nd.s = od.s;
+  nd.rcls = od.rcls;
+  nd.slot = od.slot;
+  std::memset(&job, 0, sizeof job);
+  const DefBuf& b = st->db[st->cur];
+  job.spec = st->spec;
+  job.sig = st->sig;
+  job.own = st->own;
+  job.ids = b.ids;
+  job.lnk = b.lnk;
+  job.cnt = b.cnt;
+  job.tab = b.tab;
+  job.B = st->B;
+  job.S6 = st->S6;
+  job.E = st->E;
+  job.slot = od.slot;
+  job.idx = idx;
+  job.ndef = st->ndef;
+  job.sx = sh[0];
+  job.sy = sh[1];
+  job.sz = sh[2];
+  cyclic_cover(od.lo[1], od.w[1], nd.lo[1], nd.w[1], n, job.ylo, job.ylen);
+  cyclic_cover(od.lo[2], od.w[2], nd.lo[2], nd.w[2], n, job.zlo, job.zlen);
+  job.xitems = job.zlen * ((job.ylen + x_rows(n) - 1) / x_rows(n));
+  job.h3c = st->h3c;
+  for (int a = 0; a < 6; ++a) job.E12[a] = job.E12[6 + a] = od.efd[a];
+  job.rec = nd;
+  return true;
+}
+
+ec_status batch_entry(ec_ctx* c, const BatchKey& key, const ec_state* st0, BatchEntry** out) {
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->batches.find(key);
+    if (it != c->batches.end()) {
+      *out = &it->second;
+      return EC_OK;
+    }
+  }
+  BatchEntry e;
+  auto undo = [&]() {
+    if (e.pin) (void)hipHostFree(e.pin);
+    if (e.done) (void)hipEventDestroy(e.done);
+    raw_free(c, e.dev);
+    raw_free(c, e.ctr);
+    raw_free(c, e.zero6);
+    raw_free(c, e.frm);
+  };
+  if (hipHostMalloc((void**)&e.pin, MAXBATCH * sizeof(HopJob), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&e.done, hipEventDisableTiming) != hipSuccess) {
+    undo();
+    return fail(EC_ERR_DEVICE, "batch staging allocation failed");
+  }
+  e.dev = (HopJob*)raw_alloc(c, MAXBATCH * sizeof(HopJob));
+  e.ctr = (uint32_t*)raw_alloc(c, NTILECTR * sizeof(uint32_t));
+  e.zero6 = (double*)raw_alloc(c, 64);
+  if (st0->frm) e.frm = (double*)raw_alloc(c, FRAME_LEN * sizeof(double));
+  if (!e.dev || !e.ctr || !e.zero6 || (st0->frm && !e.frm)) {
+    undo();
+    return fail(EC_ERR_DEVICE, "batch buffer allocation failed");
+  }
+  hipError_t r = hipMemset(e.zero6, 0, 64);
+  if (r == hipSuccess && e.frm)
+    r = hipMemcpy(e.frm, st0->frmh.data(), FRAME_LEN * sizeof(double), hipMemcpyHostToDevice);
+  if (r != hipSuccess) {
+    undo();
+    return fail(EC_ERR_DEVICE, "batch buffer set-up: %s", hipGetErrorString(r));
+  }
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto ins = c->batches.emplace(key, e);
+  if (!ins.second) undo();  // another thread made the same entry meanwhile
+  *out = &ins.first->second;
+  return EC_OK;
+}
+
+// The launches of one batch: the job table to the device, the Fourier passes,
+// the lists and records, the energies.
+ec_status batch_launches(const ec_state* st0, BatchEntry& e, int k, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(e.dev, e.pin, (size_t)k * sizeof(HopJob), hipMemcpyHostToDevice, s));
+  Cubic C = st0->C;
+  C.frm = e.frm;
+  HIPCHK(launch_hop_batch_fft(st0->fp64, e.dev, k, st0->g, C, st0->tw, e.ctr, e.zero6, s));
+  HIPCHK(launch_hop_batch_lists(e.dev, k, st0->n, s));
+  HIPCHK(launch_hop_batch_energies(e.dev, k, s));
+  return EC_OK;
+}
+
 }  // namespace
 
 // =============================================================================== ABI
@@ -1616,7 +1749,28 @@ void ec_ctx_destroy(ec_ctx* c) {
   if (!c) return;
   for (auto& kv : c->tw) raw_free(c, kv.second);
   c->wins.clear();  // windows no state holds any more are freed here
+  for (auto& kv : c->batches) {
+    BatchEntry& b = kv.second;
+    if (b.pending) (void)hipEventSynchronize(b.done);
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.pin) (void)hipHostFree(b.pin);
+    raw_free(c, b.dev);
+    raw_free(c, b.ctr);
+    raw_free(c, b.zero6);
+    raw_free(c, b.frm);
+  }
   delete c;
+}
+
+ec_status ec_ctx_graphs(const ec_ctx* c, int32_t* count) {
+  if (!c || !count) return fail(EC_ERR_ARG, "NULL argument");
+  ec_ctx* m = const_cast<ec_ctx*>(c);
+  std::lock_guard<std::mutex> lk(m->mu);
+  int32_t k = 0;
+  for (const auto& kv : c->batches) k += kv.second.exec != nullptr;
+  *count = k;
+  return EC_OK;
 }
 
 ec_status ec_ctx_ledger(const ec_ctx* c, size_t* used, size_t* budget) {
@@ -1911,6 +2065,74 @@ ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, vo
   ec_status r0 = update_q(st, idx, nd, s);
   if (r0 != EC_OK) return r0;
   if (E_out) return ec_interaction_energies(st, stream, E_out, on_device);
+  return EC_OK;
+}
+
+ec_status ec_update_batch(ec_state* const* states, const int32_t* idx, const ec_defect* moved, int32_t k,
+                          void* stream, double* const* E_dev, int32_t use_graph) {
+  if (!states || !idx || !moved) return fail(EC_ERR_ARG, "NULL argument");
+  if (k < 1 || k > MAXBATCH) return fail(EC_ERR_ARG, "batch size %d outside [1, %d]", k, MAXBATCH);
+  hipStream_t s = (hipStream_t)stream;
+  const ec_state* st0 = states[0];
+  if (!st0) return fail(EC_ERR_ARG, "NULL state");
+  // validate every hop before touching any state
+  HopJob jobs[MAXBATCH];
+  DevDefect recs[MAXBATCH];
+  for (int j = 0; j < k; ++j) {
+    ec_state* st = states[j];
+    if (!st) return fail(EC_ERR_ARG, "NULL state %d", j);
+    for (int i = 0; i < j; ++i)
+      if (states[i] == st) return fail(EC_ERR_ARG, "state %d appears twice in the batch", j);
+    if (st->ctx != st0->ctx || st->n != st0->n || st->fp64 != st0->fp64 || st->C.C11 != st0->C.C11 ||
+        st->C.C12 != st0->C.C12 || st->C.C44 != st0->C.C44 || st->frame != st0->frame)
+      return fail(EC_ERR_ARG, "state %d does not have the shape of state 0", j);
+    if (!st->solved) return fail(EC_ERR_STATE, "state %d has no solve yet", j);
+    if (idx[j] < 0 || idx[j] >= st->ndef) return fail(EC_ERR_ARG, "defect index %d of state %d out of range", idx[j], j);
+    std::string err;
+    if (!quantise(st->prob, moved[j], recs[j], err)) return fail(EC_ERR_ARG, "moved defect %d: %s", j, err.c_str());
+    if (!hop_job(st, idx[j], recs[j], jobs[j]))
+      return fail(EC_ERR_ARG, "move %d is not a whole-voxel hop of the same defect (use ec_update_defect)", j);
+    jobs[j].Eout = E_dev ? E_dev[j] : nullptr;
+  }
+  // self terms of every state current and joined on this stream
+  ec_status r;
+  for (int j = 0; j < k; ++j) {
+    ec_state* st = states[j];
+    if ((r = join_self(st, s)) != EC_OK) return r;
+    if (!st->B_valid && (r = compute_self_terms(st, s)) != EC_OK) return r;
+  }
+  BatchKey key{st0->n, st0->fp64 ? 0 : 1, k, st0->C.C11, st0->C.C12, st0->C.C44, st0->frame, stream};
+  BatchEntry* e = nullptr;
+  if ((r = batch_entry(st0->ctx, key, st0, &e)) != EC_OK) return r;
+  if (e->pending) HIPCHK(hipEventSynchronize(e->done));  // the previous batch read the table
+  e->pending = false;
+  std::memcpy(e->pin, jobs, (size_t)k * sizeof(HopJob));
+  if (!s) use_graph = 0;  // the null stream cannot be captured: direct launches
+  if (use_graph && !e->exec && !e->graph_failed) {
+    // capture the launch sequence once; it reads the pinned table at replay
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const ec_status rc = batch_launches(st0, *e, k, s);
+    const hipError_t ec2 = hipStreamEndCapture(s, &g);
+    if (rc != EC_OK || ec2 != hipSuccess || hipGraphInstantiate(&e->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      e->exec = nullptr;
+      e->graph_failed = true;  // direct launches from now on
+    }
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+  }
+  if (use_graph && e->exec) {
+    HIPCHK(hipGraphLaunch(e->exec, s));
+  } else if ((r = batch_launches(st0, *e, k, s)) != EC_OK) {
+    return r;
+  }
+  HIPCHK(hipEventRecord(e->done, s));
+  e->pending = true;
+  for (int j = 0; j < k; ++j) {
+    ec_state* st = states[j];
+    st->hdefs[idx[j]] = recs[j];
+    st->jdE_ok = false;
+  }
   return EC_OK;
 }
 

@@ -255,6 +255,36 @@ struct DevLine {
 // Profiling families (see ec_profile_read).
 enum ProfFam { PF_RASTER = 0, PF_XF = 1, PF_Y = 2, PF_Z = 3, PF_XI = 4, PF_REDUCE = 5, PF_SELF = 6, PF_OTHER = 7 };
 
+// One whole-voxel hop of a batch (device-resident table): every kernel of a
+// batched hop update reads its replica's buffers and pruning from it, so one
+// launch per pass serves the whole batch and the launch sequence does not
+// depend on which replicas are in it (it can be captured in a graph once and
+// replayed with new tables).  All replicas of a batch share one shape (n,
+// precision, stiffness, frame).
+constexpr int MAXBATCH = 16;
+struct HopJob {
+  void* spec;       // half spectrum
+  double* sig;      // resident stress (voxel-major)
+  int32_t* own;     // owner links
+  int32_t* ids;     // footprint ids
+  int2* lnk;        // membership entries
+  int32_t* cnt;     // footprint counts
+  DevDefect* tab;   // defect table
+  const double* B;  // self terms
+  double* S6;       // footprint stress sums
+  double* E;        // the state's energies
+  double* Eout;     // the caller's device output, or nullptr
+  int64_t slot;     // first footprint entry of the moved defect
+  int32_t idx, ndef;
+  int32_t sx, sy, sz;
+  int32_t ylo, ylen, zlo, zlen;
+  int32_t xitems;   // row blocks of its sparse x-forward pass
+  int32_t pad_;
+  double h3c;
+  double E12[12];   // eigenstrain removed from the old footprint, added on the new one
+  DevDefect rec;    // the moved record
+};
+
 // ---- launch interfaces implemented in k_fft.hip ------------------------------
 
 // Half spectrum layout: [kz][ky][kx][component], kx < n/2 + 1 padded to a
@@ -269,6 +299,15 @@ __host__ __device__ inline size_t spec_at(int kz, int ky, int kx, int c, int n, 
 // storage (128-byte rows of float2) or to 8 with FP64 storage.
 __host__ __device__ constexpr int spec_pitch(int n, bool fp64) {
   return fp64 ? ((n / 2 + 1 + 7) / 8) * 8 : ((n / 2 + 1 + 15) / 16) * 16;
+}
+
+// Rows per workgroup of the x passes: the most (a divisor of n) whose three
+// pair transforms per row fit 1536 points.
+__host__ __device__ constexpr int x_rows(int N) {
+  int best = 1;
+  for (int r = 1; r <= N; ++r)
+    if (N % r == 0 && 3 * r * N <= 1536) best = r;
+  return best;
 }
 
 struct SpecGeom {
@@ -324,6 +363,15 @@ hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, 
 // bg / bg_mask: stress planes of dislocation lines added to sigma (not with accum).
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
                             const double2* tw, hipStream_t s, const double* bg = nullptr, int bg_mask = 0);
+// The Fourier passes of a batch of hops (jobs: njob device records, see
+// HopJob; ctr: NTILECTR tile counters, zeroed by the first pass): sparse x
+// forward, pruned y forward, fused z pass, y inverse, accumulating x inverse
+// (the hop's mean-stress change is zero).
+hipError_t launch_hop_batch_fft(bool fp64, const HopJob* jobs, int njob, SpecGeom g, Cubic C, const double2* tw,
+                                uint32_t* ctr, const double* zero6, hipStream_t s);
+// The lists, records and energies of a batch of hops (after the passes).
+hipError_t launch_hop_batch_lists(const HopJob* jobs, int njob, int n, hipStream_t s);
+hipError_t launch_hop_batch_energies(const HopJob* jobs, int njob, hipStream_t s);
 
 // ---- k_raster.hip / k_energy.hip -----------------------------------------------
 

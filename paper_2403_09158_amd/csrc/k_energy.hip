@@ -48,11 +48,10 @@ __device__ __forceinline__ void neumaier_merge(double& s, double& c, double s2, 
 // Neumaier sums; four members in flight per thread), combined in a fixed
 // tree (lane shuffles, then the four wavefronts in order), then
 // E_i = -h^3 c E_i:S_i - B_i.
-__global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
-                                                const int32_t* __restrict__ ids, const double* __restrict__ sig,
-                                                const double* __restrict__ B, double h3c,
-                                                double* __restrict__ S6, double* __restrict__ E) {
-  const int i = blockIdx.x;
+__device__ __forceinline__ void reduce_defect(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
+                                              const int32_t* __restrict__ ids, const double* __restrict__ sig,
+                                              const double* __restrict__ B, double h3c, double* __restrict__ S6,
+                                              double* __restrict__ E, double* __restrict__ E2, int i) {
   const int64_t o = defs[i].slot;
   const int m = cnt[i];
   double s[6], c[6];
@@ -103,7 +102,30 @@ __global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ de
       dot += ddot_w(a) * d.E[a] * S;
       if (S6) S6[6 * i + a] = S;
     }
-    E[i] = -h3c * dot - B[i];
+    const double e = -h3c * dot - B[i];
+    E[i] = e;
+    if (E2) E2[i] = e;
+  }
+  __syncthreads();  // ws and wc are rewritten by the caller's next defect
+}
+
+__global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
+                                                const int32_t* __restrict__ ids, const double* __restrict__ sig,
+                                                const double* __restrict__ B, double h3c,
+                                                double* __restrict__ S6, double* __restrict__ E) {
+  reduce_defect(defs, cnt, ids, sig, B, h3c, S6, E, nullptr, blockIdx.x);
+}
+
+// Batched hops: the energies of every defect of every job (a fixed grid walks
+// them, job after job), also into the job's output buffer when it has one.
+__global__ __launch_bounds__(RDT) void k_reduce_batch(const HopJob* __restrict__ jobs, int njob) {
+  int total = 0;
+  for (int j = 0; j < njob; ++j) total += jobs[j].ndef;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int j = 0, first = 0;
+    while (item >= first + jobs[j].ndef) first += jobs[j++].ndef;
+    const HopJob& J = jobs[j];
+    reduce_defect(J.tab, J.cnt, J.ids, J.sig, J.B, J.h3c, J.S6, J.E, J.Eout, item - first);
   }
 }
 
@@ -972,6 +994,11 @@ hipError_t launch_reduce(const DevDefect* d, int ndef, const int32_t* counts, co
                          const double* B, double h3c, double* S6, double* E, hipStream_t s) {
   if (ndef == 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce, dim3(ndef), dim3(RDT), 0, s, d, counts, ids, sig, B, h3c, S6, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_hop_batch_energies(const HopJob* jobs, int njob, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_batch, dim3(1024), dim3(RDT), 0, s, jobs, njob);
   return hipGetLastError();
 }
 

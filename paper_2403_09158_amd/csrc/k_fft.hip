@@ -25,12 +25,7 @@ constexpr int max_nb(int N, int F) {
   return m;
 }
 constexpr int pick_T(int nb) { return nb >= 256 ? 256 : ((nb + 63) / 64) * 64; }
-constexpr int x_rows(int N) {
-  int best = 1;
-  for (int r = 1; r <= N; ++r)
-    if (N % r == 0 && 3 * r * N <= 1536) best = r;
-  return best;
-}
+
 
 // ----------------------------------------------------------------- Green operator
 //
@@ -364,26 +359,23 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
 // are built in LDS from the two footprint lists (new ids = old ids shifted by
 // (sx, sy, sz) voxels when new_ids == nullptr), for rows y in [y_lo, y_lo+y_len),
 // z in [z_lo, z_lo+z_len) (cyclic); other rows are zero and never touched.
+// One row block (ROWS rows of one z plane) of one move; buf and tw are the
+// caller's LDS (tw filled).
 template <int N, typename S>
-__global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_sparse(
-    const int32_t* __restrict__ old_ids, const int32_t* __restrict__ old_cnt_p, const int32_t* __restrict__ new_ids,
-    int new_cnt, int sx, int sy, int sz, const double* __restrict__ E, typename Cplx<S>::T* __restrict__ spec, int P,
-    int y_lo, int y_len, int z_lo, const double2* __restrict__ twg, uint32_t* __restrict__ zero_ctr) {
-  if (zero_ctr && blockIdx.x == 0 && threadIdx.x < NTILECTR) zero_ctr[threadIdx.x] = 0u;
-  const int old_cnt = *old_cnt_p;
-  if (!new_ids) new_cnt = old_cnt;
+__device__ __forceinline__ void xfs_block(double2* buf, const double2* tw, const int32_t* __restrict__ old_ids,
+                                          int old_cnt, const int32_t* __restrict__ new_ids, int new_cnt, int sx, int sy,
+                                          int sz, const double* __restrict__ E, typename Cplx<S>::T* __restrict__ spec,
+                                          int P, int y_lo, int y_len, int z_lo, int blk) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;
   constexpr int T = pick_T(max_nb(N, NF));
   constexpr int LDN = N + N / 16 + 1;
   constexpr int NH = N / 2 + 1;
-  __shared__ double2 buf[NF * LDN];
-  __shared__ double2 tw[N];
-  for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  if (!new_ids) new_cnt = old_cnt;
   for (int i = threadIdx.x; i < NF * LDN; i += T) buf[i] = make_double2(0.0, 0.0);
   const int rb = (y_len + ROWS - 1) / ROWS;
-  const int zi = blockIdx.x / rb;
-  const int y0i = (blockIdx.x % rb) * ROWS;
+  const int zi = blk / rb;
+  const int y0i = (blk % rb) * ROWS;
   int z = z_lo + zi;
   if (z >= N) z -= N;
   __syncthreads();
@@ -437,6 +429,46 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_
                               : make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
     st2(spec + spec_at(z, y, k, c, N, P), v);
   }
+  __syncthreads();  // the caller's next block rewrites LDS
+}
+
+template <int N, typename S>
+__global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_sparse(
+    const int32_t* __restrict__ old_ids, const int32_t* __restrict__ old_cnt_p, const int32_t* __restrict__ new_ids,
+    int new_cnt, int sx, int sy, int sz, const double* __restrict__ E, typename Cplx<S>::T* __restrict__ spec, int P,
+    int y_lo, int y_len, int z_lo, const double2* __restrict__ twg, uint32_t* __restrict__ zero_ctr) {
+  constexpr int NF = 3 * x_rows(N);
+  constexpr int T = pick_T(max_nb(N, NF));
+  constexpr int LDN = N + N / 16 + 1;
+  __shared__ double2 buf[NF * LDN];
+  __shared__ double2 tw[N];
+  if (zero_ctr && blockIdx.x == 0 && threadIdx.x < NTILECTR) zero_ctr[threadIdx.x] = 0u;
+  for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  xfs_block<N, S>(buf, tw, old_ids, *old_cnt_p, new_ids, new_cnt, sx, sy, sz, E, spec, P, y_lo, y_len, z_lo,
+                  blockIdx.x);
+}
+
+// Batched hops: the row blocks of every job, job after job, over a fixed grid
+// (a block takes every gridDim-th one).
+template <int N, typename S>
+__global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward_sparse_batch(
+    const HopJob* __restrict__ jobs, int njob, int P, const double2* __restrict__ twg, uint32_t* __restrict__ zero_ctr) {
+  constexpr int NF = 3 * x_rows(N);
+  constexpr int T = pick_T(max_nb(N, NF));
+  constexpr int LDN = N + N / 16 + 1;
+  __shared__ double2 buf[NF * LDN];
+  __shared__ double2 tw[N];
+  if (zero_ctr && blockIdx.x == 0 && threadIdx.x < NTILECTR) zero_ctr[threadIdx.x] = 0u;
+  for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
+  int total = 0;
+  for (int j = 0; j < njob; ++j) total += jobs[j].xitems;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int j = 0, first = 0;
+    while (item >= first + jobs[j].xitems) first += jobs[j++].xitems;
+    const HopJob& J = jobs[j];
+    xfs_block<N, S>(buf, tw, J.ids + J.slot, J.cnt[J.idx], nullptr, 0, J.sx, J.sy, J.sz, J.E12,
+                    (typename Cplx<S>::T*)J.spec, P, J.ylo, J.ylen, J.zlo, item - first);
+  }
 }
 
 // --------------------------------------------------------------- y / z pencils
@@ -468,10 +500,25 @@ constexpr int pencil_threads() {
   return 6 * pencil_wx<N, LT>() * (N / pencil_rmax<N>());
 }
 
-template <int N, typename S, bool INV, typename LT, bool PRUNE, int AXIS>
+// Tiles of a batch of hops: job j holds cnt(j) consecutive tiles; (job, local
+// tile) of tile t by a walk over the (at most MAXBATCH) jobs.
+template <class Count>
+__device__ __forceinline__ int job_of_tile(int t, int njob, Count&& cnt, int& local) {
+  int j = 0, first = 0;
+  while (j + 1 < njob && t >= first + cnt(j)) first += cnt(j++);
+  local = t - first;
+  return j;
+}
+
+// BATCH: the tiles of njob hops of a batch (jobs), job after job: a job's
+// spectrum and (y pass, PRUNE) its planes and input rows come from its record;
+// spec, pr and ntiles are then unused.
+template <int N, typename S, bool INV, typename LT, bool PRUNE, int AXIS, bool BATCH = false>
 __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename Cplx<S>::T* __restrict__ spec,
                                                                      Prune pr, const double2* __restrict__ twg,
-                                                                     int ntiles, uint32_t* __restrict__ ctr) {
+                                                                     int ntiles, uint32_t* __restrict__ ctr,
+                                                                     const HopJob* __restrict__ jobs = nullptr,
+                                                                     int njob = 0) {
   constexpr int WX = pencil_wx<N, LT>();
   constexpr int NF = 6 * WX;
   constexpr int T = pencil_threads<N, LT>();
@@ -489,23 +536,46 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
   __shared__ LT buf[N * NF];
   __shared__ double2 tw[N];
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
-  auto in_range = [&](int i) {
+  // tiles per job in a batch: the planes of its pruned range (y pass, PRUNE)
+  // or all of them
+  auto job_tiles = [&](int j) { return (PRUNE && AXIS == 1 ? jobs[j].zlen : N) * KB; };
+  if constexpr (BATCH) {
+    ntiles = 0;
+    for (int j = 0; j < njob; ++j) ntiles += job_tiles(j);
+  }
+  // the spectrum, pruning and local tile index of tile t
+  auto tile_of = [&](int t, C2*& base, Prune& p) -> int {
+    if constexpr (BATCH) {
+      int lt;
+      const int j = job_of_tile(t, njob, job_tiles, lt);
+      base = (C2*)jobs[j].spec;
+      p = Prune{jobs[j].ylo, jobs[j].ylen, jobs[j].zlo, jobs[j].zlen};
+      return lt;
+    } else {
+      base = spec;
+      p = pr;
+      return t;
+    }
+  };
+  auto in_range_of = [&](const Prune& p, int i) {
     if (!PRUNE) return true;
-    int d = i - pr.in_lo;
+    int d = i - p.in_lo;
     if (d < 0) d += N;
-    return d < pr.in_len;
+    return d < p.in_len;
   };
   // lane f's column in tile t (the base of the spectrum if the lane is idle)
-  auto column = [&](int t, int f, bool& valid) -> C2* {
-    const int o = t / KB, kx = (t % KB) * WX + f / 6;
+  auto column = [&](int t, int f, bool& valid, Prune& p) -> C2* {
+    C2* base;
+    const int lt = tile_of(t, base, p);
+    const int o = lt / KB, kx = (lt % KB) * WX + f / 6;
     valid = kx < NH;
-    if (!valid) return spec;
+    if (!valid) return base;
     if (AXIS == 1) {
-      int z = pr.z_lo + o;
+      int z = p.z_lo + o;
       if (z >= N) z -= N;
-      return spec + (z * N * P + kx) * 6 + f % 6;
+      return base + (z * N * P + kx) * 6 + f % 6;
     }
-    return spec + (o * P + kx) * 6 + f % 6;
+    return base + (o * P + kx) * 6 + f % 6;
   };
   // FP32 storage: raw first-stage operands of the next tile are loaded while
   // the current one is transformed (rows outside the input range read row
@@ -516,9 +586,10 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
   auto fetch = [&](int t, int tid) {
     if constexpr (!PIPE) return;
     bool v;
-    const C2* colp = column(t, tid % NF, v);
+    Prune p;
+    const C2* colp = column(t, tid % NF, v, p);
     for_operands<N, R0, Map::Pencil, NF, T>(
-        [&](int, int i, int slot) { nxt[slot] = colp[(in_range(i) ? i : pr.in_lo) * SI]; }, tid);
+        [&](int, int i, int slot) { nxt[slot] = colp[(in_range_of(p, i) ? i : p.in_lo) * SI]; }, tid);
   };
   auto from_lds = [&](int f, int i) { return ld2(&buf[i * NF + f]); };
   auto to_lds = [&](int f, int i, double2 v) { st2(&buf[i * NF + f], v); };
@@ -548,11 +619,12 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     bool valid;
-    C2* const colp = column(t, tid % NF, valid);
+    Prune pt;
+    C2* const colp = column(t, tid % NF, valid, pt);
     // a lane past the last column transforms whatever its loads returned
     // (finite spectrum values) and stores nothing
     auto load0 = [&](int, int i, int slot) -> double2 {
-      if (PRUNE && !(valid && in_range(i))) return make_double2(0.0, 0.0);
+      if (PRUNE && !(valid && in_range_of(pt, i))) return make_double2(0.0, 0.0);
       return PIPE ? ld2(&nxt[slot]) : ld2(colp + i * SI);
     };
     auto store_last = [&](int, int i, double2 v) {
@@ -621,10 +693,14 @@ constexpr int zg_threads() {
 // three, so stride-R stores of the first stages spread over all banks.
 __device__ __forceinline__ int zg_swz(int i) { return (i & ~7) | ((i ^ (i >> 3)) & 7); }
 
-template <int N, typename S, bool PRUNE, bool ROT>
+// BATCH: the tiles of njob hops of a batch, job after job (NT each), a job's
+// spectrum and input planes from its record (spec and pr unused).
+template <int N, typename S, bool PRUNE, bool ROT, bool BATCH = false>
 __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S>::T* __restrict__ spec, Cubic C,
                                                                 Prune pr, const double2* __restrict__ twg,
-                                                                uint32_t* __restrict__ ctr) {
+                                                                uint32_t* __restrict__ ctr,
+                                                                const HopJob* __restrict__ jobs = nullptr,
+                                                                int njob = 0) {
   using FP = FusedPlan<N>;
   constexpr int W = zg_width<N, S>();
   constexpr int T = zg_threads<N, S>();
@@ -649,11 +725,24 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   auto lds = [&](int f, int i) -> double2* { return &buf[__umul24(zg_swz(i), NF) + f]; };
   auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
   auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
-  auto in_z = [&](int i) {
+  // the spectrum and input planes of tile t, and its index within its job
+  auto tile_of = [&](int t, C2*& base, Prune& p) -> int {
+    if constexpr (BATCH) {
+      const int j = t / NT;
+      base = (C2*)jobs[j].spec;
+      p = Prune{jobs[j].zlo, jobs[j].zlen, 0, N};
+      return t - j * NT;
+    } else {
+      base = spec;
+      p = pr;
+      return t;
+    }
+  };
+  auto in_z_of = [&](const Prune& p, int i) {
     if (!PRUNE) return true;
-    int d = i - pr.in_lo;
+    int d = i - p.in_lo;
     if (d < 0) d += N;
-    return d < pr.in_len;
+    return d < p.in_len;
   };
   // FP32 storage: raw first-stage operands of the next tile, loaded while the
   // current one is transformed (rows outside the input range read row in_lo
@@ -663,13 +752,16 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   C2 nxt[NOP];
   auto fetch = [&](int t, int tid) {
     if constexpr (!PIPE) return;
-    const int f0 = tid % NF, kx = (t % KB) * W + f0 / 6;
-    const C2* col0 = spec + (kx < NH ? ((t / KB) * P + kx) * 6 + f0 % 6 : 0);
+    C2* base;
+    Prune p;
+    const int lt = tile_of(t, base, p);
+    const int f0 = tid % NF, kx = (lt % KB) * W + f0 / 6;
+    const C2* col0 = base + (kx < NH ? ((lt / KB) * P + kx) * 6 + f0 % 6 : 0);
     for_operands<N, R0, Map::Pencil, NF, T>(
-        [&](int, int i, int slot) { nxt[slot] = col0[(in_z(i) ? i : pr.in_lo) * SI]; }, tid);
+        [&](int, int i, int slot) { nxt[slot] = col0[(in_z_of(p, i) ? i : p.in_lo) * SI]; }, tid);
   };
   __shared__ int tslot[2];
-  TileWalk walk(NT, PIPE ? ctr : nullptr, tslot);
+  TileWalk walk(BATCH ? NT * njob : NT, PIPE ? ctr : nullptr, tslot);
   walk.claim_first();
   __syncthreads();
   int t = walk.first();
@@ -694,16 +786,19 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
     // across the loop
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const int ky = t / KB;
+    C2* tbase;
+    Prune pt;
+    const int lt = tile_of(t, tbase, pt);
+    const int ky = lt / KB;
     const int f0 = tid % NF, w = f0 / 6;  // lane f = 6 w + c keeps its column
-    const int kx = (t % KB) * W + w;
+    const int kx = (lt % KB) * W + w;
     const bool valid = kx < NH;
-    C2* const col0 = spec + (valid ? (ky * P + kx) * 6 + f0 % 6 : 0);
+    C2* const col0 = tbase + (valid ? (ky * P + kx) * 6 + f0 % 6 : 0);
     // a lane past the last column transforms whatever its loads returned
     // (finite spectrum values), takes no part in the Green step and stores
     // nothing
     auto load0 = [&](int, int i, int slot) -> double2 {
-      if (PRUNE && !(valid && in_z(i))) return make_double2(0.0, 0.0);
+      if (PRUNE && !(valid && in_z_of(pt, i))) return make_double2(0.0, 0.0);
       return PIPE ? ld2(&nxt[slot]) : ld2(col0 + i * SI);
     };
     stage<N, R0, 1, false, Map::Pencil, NF, T>(tw, load0, to_lds, false, tid);
@@ -786,10 +881,13 @@ __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__
 
 // BG: the stress planes of dislocation lines along the axes in bg_mask
 // ([3][n^2][6], FP64) are added as well.
-template <int N, typename S, bool ACC, bool BG>
+// BATCH: njob hops of a batch, N N / ROWS blocks each, a job's spectrum and
+// stress from its record (spec and sig unused).
+template <int N, typename S, bool ACC, bool BG, bool BATCH = false>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
     const typename Cplx<S>::T* __restrict__ spec, double* __restrict__ sig, const double* __restrict__ mean6,
-    const double2* __restrict__ twg, const double* __restrict__ bg, int bg_mask) {
+    const double2* __restrict__ twg, const double* __restrict__ bg, int bg_mask,
+    const HopJob* __restrict__ jobs = nullptr) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;
   constexpr int T = pick_T(max_nb(N, NF));
@@ -803,8 +901,15 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   for (int i = threadIdx.x; i < N; i += T) tw[i] = twg[i];
   if (threadIdx.x < 6) mean_s[threadIdx.x] = mean6[threadIdx.x];
   const int bpp = N / ROWS;
-  const int z = blockIdx.x / bpp;
-  const int y0 = (blockIdx.x % bpp) * ROWS;
+  int blk = blockIdx.x;
+  if constexpr (BATCH) {
+    const int j = blk / (N * bpp);
+    blk -= j * (N * bpp);
+    spec = (const typename Cplx<S>::T*)jobs[j].spec;
+    sig = jobs[j].sig;
+  }
+  const int z = blk / bpp;
+  const int y0 = (blk % bpp) * ROWS;
   const double scale = 1.0 / (double)N3;
   __syncthreads();
   auto load0 = [&](int f, int k) -> double2 {
@@ -918,7 +1023,7 @@ hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const
                       : (inv ? k_pencil<N, S, true, LT, false, 2> : k_pencil<N, S, false, LT, false, 2>);
   const int grid = tile_grid(k, T, ntiles, sizeof(S) == 4);
   if (grid < 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, pr, tw, ntiles, ctr);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, pr, tw, ntiles, ctr, (const HopJob*)nullptr, 0);
   return hipGetLastError();
 }
 
@@ -931,13 +1036,55 @@ hipError_t go_xi(bool acc, const void* spec, double* sig, SpecGeom g, const doub
   if (g.P != spec_pitch(N, sizeof(S) == 8)) return hipErrorInvalidValue;
   if (acc)
     hipLaunchKernelGGL((k_x_inverse<N, S, true, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
-                       bg, 0);
+                       bg, 0, (const HopJob*)nullptr);
   else if (bg && bg_mask)
     hipLaunchKernelGGL((k_x_inverse<N, S, false, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
-                       bg, bg_mask);
+                       bg, bg_mask, (const HopJob*)nullptr);
   else
     hipLaunchKernelGGL((k_x_inverse<N, S, false, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
-                       bg, 0);
+                       bg, 0, (const HopJob*)nullptr);
+  return hipGetLastError();
+}
+
+template <int N, typename S>
+hipError_t go_hop_batch(const HopJob* jobs, int njob, SpecGeom g, Cubic C, const double2* tw, uint32_t* ctr,
+                        const double* zero6, hipStream_t s) {
+  using C2 = typename Cplx<S>::T;
+  using LT = typename Cplx<S>::T;
+  if (g.P != spec_pitch(N, sizeof(S) == 8) || njob < 1 || njob > MAXBATCH) return hipErrorInvalidValue;
+  constexpr bool pipe = sizeof(S) == 4;
+  constexpr int TX = pick_T(max_nb(N, 3 * x_rows(N)));
+  // sparse x forward: a fixed grid walks the row blocks of every job
+  hipLaunchKernelGGL((k_x_forward_sparse_batch<N, S>), dim3(256), dim3(TX), 0, s, jobs, njob, g.P, tw, ctr);
+  // y forward (pruned planes and rows), fused z pass, y inverse: persistent
+  // grids over the jobs' tiles
+  constexpr int TP = pencil_threads<N, LT>();
+  constexpr int KB = (N / 2 + 1 + pencil_wx<N, LT>() - 1) / pencil_wx<N, LT>();
+  const Prune none{0, N, 0, N};
+  {
+    auto* k = k_pencil<N, S, false, LT, true, 1, true>;
+    const int grid = pipe ? tile_grid(k, TP, njob * N * KB, true) : ((njob * N * KB + 7) / 8) * 8;
+    if (grid < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(TP), 0, s, (C2*)nullptr, none, tw, 0, ctr, jobs, njob);
+  }
+  {
+    constexpr int W = zg_width<N, S>();
+    constexpr int T = zg_threads<N, S>();
+    constexpr int NT = N * ((N / 2 + 1 + W - 1) / W);
+    auto* k = C.frm ? k_zgreen<N, S, true, true, true> : k_zgreen<N, S, true, false, true>;
+    const int grid = tile_grid(k, T, njob * NT, pipe);
+    if (grid < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)nullptr, C, none, tw, ctr + 8, jobs, njob);
+  }
+  {
+    auto* k = k_pencil<N, S, true, LT, false, 1, true>;
+    const int grid = tile_grid(k, TP, njob * N * KB, pipe);
+    if (grid < 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(TP), 0, s, (C2*)nullptr, none, tw, 0, ctr + 16, jobs, njob);
+  }
+  // accumulating x inverse (a hop's mean-stress change is zero)
+  hipLaunchKernelGGL((k_x_inverse<N, S, true, false, true>), dim3(njob * N * (N / x_rows(N))), dim3(TX), 0, s,
+                     (const C2*)nullptr, (double*)nullptr, zero6, tw, (const double*)nullptr, 0, jobs);
   return hipGetLastError();
 }
 
@@ -1024,7 +1171,7 @@ hipError_t go_zgreen(void* spec, SpecGeom g, Cubic C, Prune pr, const double2* t
                   : (prune ? k_zgreen<N, S, true, false> : k_zgreen<N, S, false, false>);
   const int grid = tile_grid(k, T, NT, sizeof(S) == 4);
   if (grid < 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, C, pr, tw, ctr);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, C, pr, tw, ctr, (const HopJob*)nullptr, 0);
   return hipGetLastError();
 }
 
@@ -1035,6 +1182,19 @@ hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, 
   case NN:                                                               \
     return fp64 ? go_zgreen<NN, double>(spec, g, C, pr, tw, ctr, s)      \
                 : go_zgreen<NN, float>(spec, g, C, pr, tw, ctr, s);
+    EC_FOR_SIZES(EC_CASE)
+#undef EC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop_batch_fft(bool fp64, const HopJob* jobs, int njob, SpecGeom g, Cubic C, const double2* tw,
+                                uint32_t* ctr, const double* zero6, hipStream_t s) {
+  switch (g.n) {
+#define EC_CASE(NN)                                                                  \
+  case NN:                                                                           \
+    return fp64 ? go_hop_batch<NN, double>(jobs, njob, g, C, tw, ctr, zero6, s)     \
+                : go_hop_batch<NN, float>(jobs, njob, g, C, tw, ctr, zero6, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }

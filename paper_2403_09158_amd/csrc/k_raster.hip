@@ -221,6 +221,53 @@ __global__ __launch_bounds__(RT) void k_link(int def, const int32_t* __restrict_
   }
 }
 
+// Batched hops: unlink every job's moved defect from its old voxels, then (a
+// second launch) link it at its voxels shifted by the hop, then copy every
+// job's moved record into its table.  Sixteen blocks per job.
+__global__ __launch_bounds__(RT) void k_unlink_batch(const HopJob* __restrict__ jobs) {
+  const HopJob& J = jobs[blockIdx.x / 16];
+  const int lb = blockIdx.x % 16;
+  const int cnt = J.cnt[J.idx];
+  for (int k = lb * RT + threadIdx.x; k < cnt; k += 16 * RT) {
+    int32_t* p = &J.own[J.ids[J.slot + k]];
+    for (int guard = 0; guard < J.ndef; ++guard) {  // a chain holds each defect once
+      const int32_t link = *p;
+      if (link == -1) break;
+      if (link >= 0) {
+        if (link == J.idx) *p = -1;
+        break;
+      }
+      int2* L = &J.lnk[-2 - link];
+      if (L->x == J.idx) {
+        *p = L->y;
+        break;
+      }
+      p = &L->y;
+    }
+  }
+}
+
+__global__ __launch_bounds__(RT) void k_link_batch(const HopJob* __restrict__ jobs, int n) {
+  const HopJob& J = jobs[blockIdx.x / 16];
+  const int lb = blockIdx.x % 16;
+  const int cnt = J.cnt[J.idx];
+  for (int k = lb * RT + threadIdx.x; k < cnt; k += 16 * RT) {
+    const int64_t e = J.slot + k;
+    const int id = shift_id(J.ids[e], J.sx, J.sy, J.sz, n);
+    J.ids[e] = id;
+    int32_t next = -1;
+    if (atomicCAS(&J.own[id], -1, J.idx) != -1) next = atomicExch(&J.own[id], entry_link(e));
+    J.lnk[e] = make_int2(J.idx, next);
+  }
+}
+
+__global__ __launch_bounds__(64) void k_set_records(const HopJob* __restrict__ jobs) {
+  const HopJob& J = jobs[blockIdx.x];
+  const int32_t* src = reinterpret_cast<const int32_t*>(&J.rec);
+  int32_t* dst = reinterpret_cast<int32_t*>(J.tab + J.idx);
+  for (int w = threadIdx.x; w < (int)(sizeof(DevDefect) / 4); w += 64) dst[w] = src[w];
+}
+
 // Additive constant of the stress for the xi = 0 condition.  Mean strain zero:
 // sigma gets -C:<eps*>, <eps*> = (1/n^3) sum_i |Omega_i| E_i, compensated FP64
 // sums over a fixed partition of the defects (deterministic).  Mean stress
@@ -313,6 +360,13 @@ hipError_t launch_move_lists(int def, int ndef, const int32_t* cnt_old, int64_t 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_link, dim3(16), dim3(RT), 0, s, def, cnt_old, old_slot, new_ids, cnt_new, new_slot, sx, sy, sz,
                      n, ids, lnk, own);
+  return hipGetLastError();
+}
+
+hipError_t launch_hop_batch_lists(const HopJob* jobs, int njob, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_unlink_batch, dim3(16 * njob), dim3(RT), 0, s, jobs);
+  hipLaunchKernelGGL(k_link_batch, dim3(16 * njob), dim3(RT), 0, s, jobs, n);
+  hipLaunchKernelGGL(k_set_records, dim3(njob), dim3(64), 0, s, jobs);
   return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ EXPORTS = (
     "ec_ctx_create",
     "ec_ctx_destroy",
     "ec_ctx_ledger",
+    "ec_ctx_graphs",
     "ec_last_error",
     "ec_state_create",
     "ec_state_destroy",
@@ -38,6 +39,7 @@ EXPORTS = (
     "ec_interaction_energies",
     "ec_interaction_energies_noalloc",
     "ec_update_defect",
+    "ec_update_batch",
     "ec_jump_energies",
     "ec_jump_select",
     "ec_okmc_step",
@@ -99,6 +101,7 @@ def load() -> ctypes.CDLL:
         "ec_ctx_create": (c_int, [c_int, c_size_t, ALLOC_FN, FREE_FN, vp, POINTER(vp)]),
         "ec_ctx_destroy": (None, [vp]),
         "ec_ctx_ledger": (c_int, [vp, POINTER(c_size_t), POINTER(c_size_t)]),
+        "ec_ctx_graphs": (c_int, [vp, POINTER(c_int32)]),
         "ec_last_error": (ctypes.c_char_p, []),
         "ec_state_create": (c_int, [vp, POINTER(CProblem), POINTER(vp)]),
         "ec_state_destroy": (None, [vp]),
@@ -107,6 +110,7 @@ def load() -> ctypes.CDLL:
         "ec_interaction_energies": (c_int, [vp, vp, vp, c_int32]),
         "ec_interaction_energies_noalloc": (c_int, [vp, vp, vp]),
         "ec_update_defect": (c_int, [vp, c_int32, vp, vp, vp, c_int32]),
+        "ec_update_batch": (c_int, [vp, vp, vp, c_int32, vp, vp, c_int32]),
         "ec_jump_energies": (c_int, [vp, vp, c_int32, vp, vp, c_int32]),
         "ec_jump_select": (c_int, [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, c_int32]),
         "ec_okmc_step": (
@@ -194,6 +198,12 @@ class Context:
         _check(load().ec_ctx_ledger(self.h, ctypes.byref(used), ctypes.byref(budget)))
         return used.value, budget.value
 
+    def graphs(self) -> int:
+        """Executable HIP graphs held for batched hops."""
+        k = c_int32()
+        _check(load().ec_ctx_graphs(self.h, ctypes.byref(k)))
+        return k.value
+
     def close(self):
         if getattr(self, "h", None):
             load().ec_ctx_destroy(self.h)
@@ -211,6 +221,24 @@ def as_defects(defects) -> np.ndarray:
     if d.ndim == 0:
         d = d.reshape(1)
     return d
+
+
+def update_batch(states, idx, moved, stream=None, outs=None, use_graph=True):
+    """Whole-voxel hops of several states of one shape in one batch
+    (``ec_update_batch``): ``states`` (k), ``idx`` (k defect indices),
+    ``moved`` (k defect records after their hops), ``outs`` (None or k device
+    tensors / None for each state's energies).  Nothing is synchronised."""
+    k = len(states)
+    hs = (c_void_p * k)(*[st.h.value for st in states])
+    ix = np.ascontiguousarray(idx, dtype=np.int32)
+    mv = as_defects(moved)
+    if ix.shape != (k,) or len(mv) != k:
+        raise ValueError("states, idx and moved must have the same length")
+    eo = None
+    if outs is not None:
+        eo = (c_void_p * k)(*[None if o is None else o.data_ptr() for o in outs])
+    _check(load().ec_update_batch(hs, ix.ctypes.data, mv.ctypes.data, k, _stream_handle(stream), eo,
+                                  1 if use_graph else 0))
 
 
 class State:

@@ -14,10 +14,15 @@ The loop
   * admits a replica's state against the context's HBM budget; when the budget
     is full it evicts the least recently used idle replica, whose state is
     rebuilt by a solve of its current defect list when it runs again;
-  * runs up to ``slots`` requests of different replicas at the same time, each
-    on a stream of its own, so their kernels overlap on the device, and hands a
-    slot to the next ready request as soon as its request completes (a slot is
-    refilled immediately; requests are not drained in rounds);
+  * runs up to ``slots`` requests (or batches) of different replicas at the
+    same time, each on a stream of its own, so their kernels overlap on the
+    device, and hands a slot to the next ready work as soon as its work
+    completes (a slot is refilled immediately; requests are not drained in
+    rounds);
+  * merges ready whole-voxel hops of replicas of one shape (grid size and
+    precision) into one batch, up to ``batch`` of them and ``batch_voxels``
+    grid voxels in all, which ``ec_update_batch`` runs as one launch per pass,
+    replayed from a HIP graph captured once per (shape, batch size, slot);
   * times every request from its arrival to the completion of the copy of its
     energies to host memory, using device events.
 
@@ -68,7 +73,7 @@ def moved_defect(defs: np.ndarray, req: Request, h: float) -> np.ndarray:
 
 
 class _Replica:
-    def __init__(self, k: int, problem, defects):
+    def __init__(self, torch, k: int, problem, defects):
         self.k = k
         self.problem = problem
         self.defs = ec.as_defects(defects).copy()
@@ -79,14 +84,18 @@ class _Replica:
         self.last_used = -1.0
         self.E_dev = None
         self.energies_ok = False
+        self.E_host = torch.empty(max(1, len(self.defs)), dtype=torch.float64, pin_memory=True)
+
+    @property
+    def shape(self):
+        return (self.problem.n, self.problem.prec)
 
 
 class _Slot:
-    def __init__(self, torch, max_ndef: int):
+    def __init__(self, torch):
         self.stream = torch.cuda.Stream()
         self.done = torch.cuda.Event(enable_timing=True)
-        self.E_host = torch.empty(max(1, max_ndef), dtype=torch.float64, pin_memory=True)
-        self.req = None
+        self.reqs = []
 
 
 @dataclasses.dataclass
@@ -101,22 +110,27 @@ class ServeStats:
     evictions: int
     latency_ms: np.ndarray
     results: dict  # rid -> energies (when kept)
+    batches: int = 0  # launches that carried two or more hops
 
 
 class Server:
     """Continuous-batching request loop over replicas sharing one context."""
 
-    def __init__(self, ctx: ec.Context, replicas, slots: int = 4, keep_results: bool = False):
+    def __init__(self, ctx: ec.Context, replicas, slots: int = 4, keep_results: bool = False, batch: int = 8,
+                 batch_voxels: int = 8_000_000, graphs: bool = True):
         import torch
 
         self.torch = torch
         self.ctx = ctx
-        self.reps = [_Replica(k, p, d) for k, (p, d) in enumerate(replicas)]
+        self.reps = [_Replica(torch, k, p, d) for k, (p, d) in enumerate(replicas)]
         self.keep = keep_results
-        max_ndef = max(len(r.defs) for r in self.reps)
-        self.slots = [_Slot(torch, max_ndef) for _ in range(max(1, slots))]
+        self.slots = [_Slot(torch) for _ in range(max(1, slots))]
+        self.batch = max(1, min(batch, 16))
+        self.batch_voxels = batch_voxels
+        self.graphs = graphs
         self.admissions = 0
         self.evictions = 0
+        self.batches = 0  # batched launches (two or more hops)
 
     # -------------------------------------------------------------- admission
     def _evict_one(self, keep: _Replica) -> bool:
@@ -193,11 +207,39 @@ class Server:
                 if not self._evict_one(rep):
                     return False
         with torch.cuda.stream(s):
-            slot.E_host[: len(rep.defs)].copy_(rep.E_dev, non_blocking=True)
+            rep.E_host[: len(rep.defs)].copy_(rep.E_dev, non_blocking=True)
         slot.done.record(s)
-        slot.req = req
+        slot.reqs = [req]
         rep.busy = True
         return True
+
+    def _hop_ready(self, rep: _Replica) -> bool:
+        """Whether ``rep``'s head request can join a batch of hops."""
+        return (rep.queue and rep.queue[0].op == "update" and rep.state is not None and rep.solved
+                and rep.energies_ok and not rep.busy)
+
+    def _dispatch_batch(self, slot: _Slot, group) -> None:
+        """Enqueue the head hops of the replicas in ``group`` (one shape) as one
+        batch on ``slot`` (ec_update_batch: one launch per pass, from a HIP
+        graph)."""
+        torch = self.torch
+        s = slot.stream
+        reqs = [rep.queue[0] for rep in group]
+        moved = [moved_defect(rep.defs, rq, rep.problem.h) for rep, rq in zip(group, reqs)]
+        ec.update_batch([rep.state for rep in group], [rq.idx for rq in reqs],
+                        np.concatenate([m.reshape(1) for m in moved]), stream=s,
+                        outs=[rep.E_dev for rep in group], use_graph=self.graphs)
+        with torch.cuda.stream(s):
+            for rep, rq, m in zip(group, reqs, moved):
+                rep.defs[rq.idx] = m
+                rep.E_host[: len(rep.defs)].copy_(rep.E_dev, non_blocking=True)
+        slot.done.record(s)
+        slot.reqs = reqs
+        for rep in group:
+            rep.queue.popleft()
+            rep.busy = True
+        if len(group) > 1:
+            self.batches += 1
 
     @staticmethod
     def _stalled(busy, rep: _Replica):
@@ -227,6 +269,7 @@ class Server:
         free = list(self.slots)
         busy = []
         waiting = collections.deque()  # replicas with queued work, in order of their head request
+        batches0 = self.batches
         while completed < n:
             now = time.perf_counter() - t0
             while ptr < n and arrive[ptr] <= now:
@@ -236,13 +279,31 @@ class Server:
                     waiting.append(rep)
                 rep.queue.append(rq)
                 ptr += 1
-            # fill free slots with the oldest ready requests
+            # fill free slots with the oldest ready requests; a ready hop takes
+            # the ready hops of other replicas of its shape along in one batch
             if free and waiting:
                 for _ in range(len(waiting)):
-                    if not free:
+                    if not free or not waiting:  # a batch may take several waiting replicas
                         break
                     rep = waiting.popleft()
                     if rep.busy or not rep.queue:
+                        continue
+                    if self.batch > 1 and self._hop_ready(rep):
+                        group, vox = [rep], rep.problem.n ** 3
+                        for other in list(waiting):
+                            if len(group) >= self.batch:
+                                break
+                            if (other is not rep and other.shape == rep.shape and self._hop_ready(other)
+                                    and vox + other.problem.n ** 3 <= self.batch_voxels):
+                                group.append(other)
+                                vox += other.problem.n ** 3
+                        for other in group[1:]:
+                            waiting.remove(other)
+                        slot = free.pop()
+                        for g in group:
+                            g.last_used = now
+                        self._dispatch_batch(slot, group)
+                        busy.append(slot)
                         continue
                     if rep.state is None and not self._admit(rep, now):
                         self._stalled(busy, rep)
@@ -261,19 +322,19 @@ class Server:
             still = []
             for slot in busy:
                 if slot.done.query():
-                    rq = slot.req
-                    rep = self.reps[rq.replica]
-                    i = order[rq.rid]
-                    done_t[i] = ref.elapsed_time(slot.done) * 1e-3
-                    if self.keep:
-                        results[rq.rid] = slot.E_host[: len(rep.defs)].numpy().copy()
-                    rep.busy = False
-                    rep.last_used = now
-                    if rep.queue:
-                        waiting.append(rep)
-                    slot.req = None
+                    t_done = ref.elapsed_time(slot.done) * 1e-3
+                    for rq in slot.reqs:
+                        rep = self.reps[rq.replica]
+                        done_t[order[rq.rid]] = t_done
+                        if self.keep:
+                            results[rq.rid] = rep.E_host[: len(rep.defs)].numpy().copy()
+                        rep.busy = False
+                        rep.last_used = now
+                        if rep.queue:
+                            waiting.append(rep)
+                        completed += 1
+                    slot.reqs = []
                     free.append(slot)
-                    completed += 1
                 else:
                     still.append(slot)
             busy = still
@@ -290,6 +351,7 @@ class Server:
             evictions=self.evictions,
             latency_ms=lat,
             results=results,
+            batches=self.batches - batches0,
         )
 
     def close(self):

@@ -185,3 +185,24 @@ def test_states_driven_from_two_host_threads():
     for st in states:
         st.close()
     ctx.close()
+
+
+def test_batched_graph_launches_same_as_alone():
+    """Replicas of one shape: the loop merges their ready hops into batches
+    (ec_update_batch, launched from HIP graphs); every result is still the
+    plain path's, bit for bit."""
+    from paper_2403_09158_amd import ec, serve
+
+    reps = _replicas(8, seed=5, sizes=(48,))
+    reqs = [r for r in serve.serving_requests(reps, 80, rate_per_s=1e6)]
+    ctx = ec.Context()
+    srv = serve.Server(ctx, reps, slots=2, keep_results=True, batch=8)
+    srv.warm()
+    stats = srv.run(reqs, realtime=False)
+    srv.close()
+    assert stats.completed == len(reqs)
+    assert stats.batches > 0
+    assert ctx.graphs() > 0
+    _, _, alone = serve.run_plain(ctx, reps, reqs, keep_results=True)
+    assert all(np.array_equal(stats.results[r], alone[r]) for r in alone)
+    ctx.close()
