@@ -330,7 +330,14 @@ __device__ __forceinline__ void stage(const TW& tw, Load&& load, Store&& store, 
       Dft<R, INV>::run(v[q]);
       const int base = (j / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) store(f, base + r * NS, v[q][r]);
+      for (int r = 0; r < R; ++r) {
+        // a 4-argument rule also receives the output's slot q R + r (see
+        // for_outputs), a compile-time index into register-held values
+        if constexpr (std::is_invocable_v<Store, int, int, double2, int>)
+          store(f, base + r * NS, v[q][r], q * R + r);
+        else
+          store(f, base + r * NS, v[q][r]);
+      }
     }
   }
 }
@@ -349,6 +356,27 @@ __device__ __forceinline__ void for_operands(F&& fn, int tid = threadIdx.x) {
       bfly_index<M, N, R, NFFT, GW>(b, f, j);
 #pragma unroll
       for (int r = 0; r < R; ++r) fn(f, j + r * (N / R), q * R + r);
+    }
+  }
+}
+
+// Visit the outputs a thread writes in a radix-R stage after NS, in the order
+// stage() writes them: fn(f, i, slot) with slot = q R + r for its q-th
+// butterfly.
+template <int N, int R, int NS, Map M, int NFFT, int T, int GW = NFFT, class F>
+__device__ __forceinline__ void for_outputs(F&& fn, int tid = threadIdx.x) {
+  constexpr int NB = NFFT * (N / R);
+  constexpr int BPT = (NB + T - 1) / T;
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int b = tid + q * T;
+    if (NB % T == 0 || b < NB) {
+      int f, j;
+      bfly_index<M, N, R, NFFT, GW>(b, f, j);
+      const int k = j % NS;
+      const int base = (j / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) fn(f, base + r * NS, q * R + r);
     }
   }
 }

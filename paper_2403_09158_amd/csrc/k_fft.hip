@@ -930,12 +930,25 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   auto to_lds = [&](int f, int i, double2 v) { buf[f * LDN + i + (i >> 4)] = v; };
   // sigma is voxel-major, [n^3][6]: components 2p and 2p+1 of a voxel are one
   // aligned 16-byte pair, and the lanes of a store cover whole voxel records
-  auto store_last = [&](int f, int x, double2 v) {
+  auto sig_at = [&](int f, int x) -> double2* {
     const int p = f % 3, y = y0 + f / 3;
-    double2* s01 = reinterpret_cast<double2*>(sig + (6 * ((z * N + y) * N + x) + 2 * p));
+    return reinterpret_cast<double2*>(sig + (6 * ((z * N + y) * N + x) + 2 * p));
+  };
+  // accumulate: the thread's old values of the last stage's outputs are read
+  // before the transform, so their latency overlaps it
+  constexpr Plan2 PLX = plan_of(N);
+  constexpr int RL = PLX.r[PLX.nstage - 1];
+  constexpr int NSL = PLX.nstage == 1 ? 1 : (PLX.nstage == 2 ? PLX.r[0] : PLX.r[0] * PLX.r[1]);
+  constexpr int NOUT = ((NF * (N / RL) + T - 1) / T) * RL;
+  double2 old[ACC ? NOUT : 1];
+  if constexpr (ACC)
+    for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) { old[slot] = *sig_at(f, x); });
+  auto store_last = [&](int f, int x, double2 v, int slot) {
+    const int p = f % 3, y = y0 + f / 3;
+    double2* s01 = sig_at(f, x);
     double2 r = make_double2(v.x * scale + mean_s[2 * p], v.y * scale + mean_s[2 * p + 1]);
-    if (ACC) {
-      const double2 o = *s01;
+    if constexpr (ACC) {
+      const double2 o = old[slot];
       r.x += o.x;
       r.y += o.y;
     }
