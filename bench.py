@@ -390,7 +390,7 @@ def jump_probe_block(steps=10):
 
 
 def okmc_block(steps=20, warmup=3):
-    """OkMC time steps on mixed_256 (Sec. 4, App. A): Poisson gate over the
+    """OkMC time steps on mixed_256 (Sec. 5, App. B): Poisson gate over the
     fixed step, jump probes and choice for every defect, the chosen jumps made
     and the field solved again; the 1/2<111> loop migration barrier of the
     paper's loop runs (0.1 eV at 300 K) for every defect, two glide jumps each."""

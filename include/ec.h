@@ -77,12 +77,14 @@ typedef enum {
 
 /* Periodic cubic cell of n^3 voxels and side L, cubic stiffness C11, C12, C44.
  * frame: the crystal orientation, row-major 3x3 whose rows are the cell's x, y
- * and z axes as unit vectors in cube coordinates (the simulations of Sec. 5
+ * and z axes as unit vectors in cube coordinates (the simulations of Secs. 4 and 6
  * take x = [111]/sqrt3, y = [-1-12]/sqrt6, z = [1-10]/sqrt2); all zeros for
  * cube axes along x, y, z.  Rows must be orthonormal to 1e-9 with determinant
  * +1 (EC_ERR_ARG otherwise).  Defects are given in cell coordinates either way.
- * n must be one of 8 16 24 32 48 64 96 128 160 240 256 512 (even,
- * 2/3/5-smooth); anything else gives EC_ERR_SIZE. */
+ * n must be one of 8 16 24 32 45 48 64 96 128 129 160 240 256 512; anything
+ * else gives EC_ERR_SIZE.  The odd sizes (45, and 129 = 3 x 43, the grid of the
+ * simulations of Secs. 4 and 6) have no Nyquist bin: every centred label of Sec. 3.4
+ * lies in -(n-1)/2 .. (n-1)/2, and minimum images lie in the same range. */
 typedef struct {
   int32_t n;
   int32_t prec; /* ec_precision */
@@ -199,7 +201,7 @@ EC_API ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* mo
 EC_API ec_status ec_update_batch(ec_state* const* states, const int32_t* idx, const ec_defect* moved, int32_t k,
                                  void* hip_stream, double* const* E_dev, int32_t use_graph);
 
-/* ---- jump probes (the OkMC loop of App. A; biased jumps of Sec. 4) ---------- */
+/* ---- jump probes (the OkMC loop of App. B; biased jumps of Sec. 5) ---------- */
 
 /* For every defect i and each of its njump (1..64) candidate whole-voxel jumps
  * jumps[(i*njump + j)*3 + {0,1,2}] (x, y, z offsets in voxels, |component| <= 8
@@ -227,7 +229,7 @@ EC_API ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t nj
 EC_API ec_status ec_jump_select(ec_state* st, const double* Em, double nu0, double kT, const double* xi,
                                 void* hip_stream, double* nu_out, int32_t* choice_out, int32_t out_on_device);
 
-/* One time step of the parallel OkMC loop (Sec. 4 and App. A) on the solved
+/* One time step of the parallel OkMC loop (Sec. 5 and App. B) on the solved
  * state.  Every defect draws its event count N_i over dt from the Poisson law
  * with its nominal frequency nu_i = nu0 exp(-Em_i / kT): N_i = 0 when
  * u_i <= exp(-nu_i dt).  Each defect with N_i > 0 takes one jump, chosen as in

@@ -19,9 +19,9 @@ elastic interactions in OkMC" (arXiv 2403.09158):
 * ``energy``   - interaction energies from the Betti-reciprocity form (Sec. 2),
                  both brute-force pairwise and the fast exact form.
 * ``jumps``    - energy changes of candidate whole-voxel jumps, the biased jump
-                 frequencies and the frequency-line selection (Sec. 4 and the
-                 OkMC loop of App. A).
-* ``okmc``     - one step of the parallel OkMC loop (Sec. 4, App. A): fixed time
+                 frequencies and the frequency-line selection (Sec. 5 and the
+                 OkMC loop of App. B).
+* ``okmc``     - one step of the parallel OkMC loop (Sec. 5, App. B): fixed time
                  step, Poisson event counts, one chosen jump per acting defect,
                  energies of the moved list.
 * ``dipole``   - the dipole-tensor approximation of the interaction energy

@@ -46,7 +46,7 @@ def isotropic_stiffness(lam: float, mu: float) -> np.ndarray:
 def rotate_stiffness(C: np.ndarray, A) -> np.ndarray:
     """C in the cell frame of a rotated crystal, C'_ijkl = A_ip A_jq A_kr A_ls C_pqrs,
     where the rows of A are the cell axes as unit vectors in cube coordinates
-    (Sec. 5 places x, y, z along [111], [-1-12] and [1-10])."""
+    (Sec. 4 places x, y, z along [111], [-1-12] and [1-10])."""
     A = np.asarray(A, dtype=np.float64).reshape(3, 3)
     return np.einsum("ip,jq,kr,ls,pqrs->ijkl", A, A, A, A, C)
 

@@ -1,6 +1,6 @@
 """Jump-probe energies and biased jump selection (oracle; test infrastructure only).
 
-The OkMC loop of App. A: for every candidate jump lambda_j of a moving defect
+The OkMC loop of App. B: for every candidate jump lambda_j of a moving defect
 d_i, the defect's field is taken out of the total field and put back at
 X_i + lambda_j, and the elastic energy of that configuration is compared with
 the current one.  For a rigid whole-voxel translation the defect's own energy
@@ -12,7 +12,7 @@ all the other defects (which stay where they are):
 
 (the pair energy of Sec. 2 in the eigenstrain form used by ``energy``).
 
-Sec. 4 (biased jumps): the barrier of a jump is raised by half the energy
+Sec. 5 (biased jumps): the barrier of a jump is raised by half the energy
 change (the saddle point halfway between the two positions), so
 
     nu_i^j = 1/2 nu_0 exp(-(E_m,i + dE_ij / 2) / (k_B T)),
@@ -117,7 +117,7 @@ def jump_energies_fast(problem, fps, Es, jumps, bc=None, G=None, D=None):
 
 
 def jump_frequencies(dE, Em, kT, nu0):
-    """nu[i, j] = 1/2 nu0 exp(-(Em_i + dE_ij / 2) / kT) (Sec. 4, biased forward
+    """nu[i, j] = 1/2 nu0 exp(-(Em_i + dE_ij / 2) / kT) (Sec. 5, biased forward
     frequency with the barrier raised halfway)."""
     dE = np.asarray(dE, dtype=np.float64)
     Em = np.broadcast_to(np.asarray(Em, dtype=np.float64).reshape(-1, 1), dE.shape)

@@ -1,6 +1,6 @@
 """One time step of the parallel OkMC loop (oracle; test infrastructure only).
 
-Sec. 4 and App. A.  Every defect can act in every step.  The step is fixed
+Sec. 5 and App. B.  Every defect can act in every step.  The step is fixed
 once, from the nominal frequencies nu_i = nu_0 exp(-E_m,i / (k_B T)) (the jump
 frequency without elastic bias), as the inverse of the largest one, so that the
 fastest defect makes one event per step on average.  In a step each defect
@@ -29,17 +29,17 @@ from . import energy, jumps, raster
 
 
 def nominal_frequencies(Em, kT, nu0) -> np.ndarray:
-    """nu_i = nu_0 exp(-E_m,i / kT) (Sec. 4, the unbiased jump frequency)."""
+    """nu_i = nu_0 exp(-E_m,i / kT) (Sec. 5, the unbiased jump frequency)."""
     return nu0 * np.exp(-np.asarray(Em, dtype=np.float64) / kT)
 
 
 def time_step(Em, kT, nu0) -> float:
-    """dt = 1 / max_i nu_i (Sec. 4, the fixed time step)."""
+    """dt = 1 / max_i nu_i (Sec. 5, the fixed time step)."""
     return 1.0 / float(nominal_frequencies(Em, kT, nu0).max())
 
 
 def event_counts(nu, dt, u) -> np.ndarray:
-    """N_i from the Poisson law P(N) = (nu dt)^N exp(-nu dt) / N! (Sec. 4) by
+    """N_i from the Poisson law P(N) = (nu dt)^N exp(-nu dt) / N! (Sec. 5) by
     inversion: the smallest N whose cumulative probability reaches u_i."""
     out = np.zeros(len(nu), dtype=np.int64)
     for i, (rate, ui) in enumerate(zip(np.asarray(nu, dtype=np.float64), u)):

@@ -1,4 +1,4 @@
-// fft_core.h - mixed-radix (2/3/4/5/8/16) Stockham FFT building blocks for gfx950.
+// fft_core.h - mixed-radix (2/3/4/5/8/16, and the prime 43) Stockham FFT building blocks for gfx950.
 //
 // Every transform here is a 1-D DFT of compile-time length N computed by a
 // workgroup in FP64 registers.  The first stage reads its operands straight from
@@ -37,7 +37,17 @@ __host__ __device__ constexpr Plan2 plan_of(int N) {
          : N == 240 ? Plan2{2, {16, 15, 1}}
          : N == 256 ? Plan2{2, {16, 16, 1}}
          : N == 512 ? Plan2{3, {8, 8, 8}}
+         : N == 45  ? Plan2{2, {15, 3, 1}}
+         : N == 129 ? Plan2{2, {43, 3, 1}}
                     : Plan2{0, {1, 1, 1}};
+}
+
+// Radices whose butterfly is evaluated output by output (dft_direct) rather
+// than all at once in registers: the large prime of an odd length.  A plan
+// puts it first, where it needs no twiddles.
+__host__ __device__ constexpr bool direct_radix(int R) { return R == 43; }
+__host__ __device__ constexpr bool has_direct(Plan2 p) {
+  return direct_radix(p.r[0]) || direct_radix(p.r[1]) || direct_radix(p.r[2]);
 }
 
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -233,6 +243,48 @@ struct Dft<15, INV> {
   __device__ __forceinline__ static void run(double2* v) { dft_pfa<3, 5, 10, 6, INV>(v); }
 };
 
+// Length-R DFT of v[0..R) for an odd prime R, each output handed to put(r,
+// X_r) as soon as it is formed, so the butterfly never holds R outputs beside
+// its R inputs.  The inputs are first folded into symmetric pairs,
+// a_j = x_j + x_{R-j} and b_j = x_j - x_{R-j} (j = 1 .. (R-1)/2), in place; then
+//   X_0 = x_0 + sum a_j,  X_k, X_{R-k} = C_k -+ i S_k  (forward; +- inverse),
+//   C_k = x_0 + sum_j a_j cos(2 pi j k / R),  S_k = sum_j b_j sin(2 pi j k / R),
+// with the cosines and sines read from the length-N twiddle table
+// (W_N^{m N / R} = cos - i sin of 2 pi m / R).
+template <int N, int R, bool INV, class Put>
+__device__ __forceinline__ void dft_direct(double2* v, const double2* tw, Put&& put) {
+  static_assert(R % 2 == 1 && N % R == 0, "odd radix dividing N");
+  constexpr int H = (R - 1) / 2;
+  double2 x0 = v[0], sum = v[0];
+#pragma unroll
+  for (int j = 1; j <= H; ++j) {
+    const double2 a = cadd(v[j], v[R - j]), b = csub(v[j], v[R - j]);
+    v[j] = a;
+    v[R - j] = b;
+    sum = cadd(sum, a);
+  }
+  put(0, sum);
+#pragma unroll 1
+  for (int k = 1; k <= H; ++k) {
+    double2 C = x0, S = make_double2(0.0, 0.0);
+    int m = 0;
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      m += k;
+      if (m >= R) m -= R;
+      const double2 w = tw[m * (N / R)];  // (cos, -sin) of 2 pi m / R
+      C.x += v[j].x * w.x;
+      C.y += v[j].y * w.x;
+      S.x -= v[R - j].x * w.y;
+      S.y -= v[R - j].y * w.y;
+    }
+    // forward: X_k = C - i S, X_{R-k} = C + i S; the inverse swaps them
+    const double2 mi = make_double2(C.x + S.y, C.y - S.x), pi = make_double2(C.x - S.y, C.y + S.x);
+    put(k, INV ? pi : mi);
+    put(R - k, INV ? mi : pi);
+  }
+}
+
 // Twiddle from the LDS table (forward W_N^e; conjugated for the inverse).
 template <bool INV>
 __device__ __forceinline__ double2 tw_at(const double2* tw, int e) {
@@ -327,16 +379,24 @@ __device__ __forceinline__ void stage(const TW& tw, Load&& load, Store&& store, 
 #pragma unroll
         for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], twiddle<INV>(tw, r, k * r * (N / (NS * R))));
       }
-      Dft<R, INV>::run(v[q]);
       const int base = (j / NS) * NS * R + k;
+      if constexpr (direct_radix(R)) {
+        // outputs leave one by one in a loop, so a store rule that needs a
+        // compile-time slot cannot follow a direct radix
+        static_assert(!is_twreg<TW>::value, "a direct radix reads the twiddle table");
+        static_assert(!std::is_invocable_v<Store, int, int, double2, int>, "no slot-indexed store after a direct radix");
+        dft_direct<N, R, INV>(v[q], tw, [&](int r, double2 x) { store(f, base + r * NS, x); });
+      } else {
+        Dft<R, INV>::run(v[q]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        // a 4-argument rule also receives the output's slot q R + r (see
-        // for_outputs), a compile-time index into register-held values
-        if constexpr (std::is_invocable_v<Store, int, int, double2, int>)
-          store(f, base + r * NS, v[q][r], q * R + r);
-        else
-          store(f, base + r * NS, v[q][r]);
+        for (int r = 0; r < R; ++r) {
+          // a 4-argument rule also receives the output's slot q R + r (see
+          // for_outputs), a compile-time index into register-held values
+          if constexpr (std::is_invocable_v<Store, int, int, double2, int>)
+            store(f, base + r * NS, v[q][r], q * R + r);
+          else
+            store(f, base + r * NS, v[q][r]);
+        }
       }
     }
   }
@@ -464,6 +524,8 @@ __host__ __device__ constexpr Plan2 plan_fused(int N) {
          : N == 240 ? Plan2{2, {16, 15, 1}}
          : N == 256 ? Plan2{2, {16, 16, 1}}
          : N == 512 ? Plan2{3, {8, 16, 4}}
+         : N == 45  ? Plan2{2, {15, 3, 1}}
+         : N == 129 ? Plan2{2, {43, 3, 1}}
                     : Plan2{0, {1, 1, 1}};
 }
 

@@ -295,9 +295,9 @@ __global__ __launch_bounds__(ST) void k_self(const DevDefect* __restrict__ defs,
     auto widx = [&](int32_t P, int32_t Q) -> int {
       if (lin) return P - Q + C0;
       int rx = (P & 1023) - (Q & 1023), ry = ((P >> 10) & 1023) - ((Q >> 10) & 1023), rz = (P >> 20) - (Q >> 20);
-      rx += rx < -h ? n : (rx >= h ? -n : 0);
-      ry += ry < -h ? n : (ry >= h ? -n : 0);
-      rz += rz < -h ? n : (rz >= h ? -n : 0);
+      rx += rx < -h ? n : (rx >= n - h ? -n : 0);
+      ry += ry < -h ? n : (ry >= n - h ? -n : 0);
+      rz += rz < -h ? n : (rz >= n - h ? -n : 0);
       return ((rz + D) * W + (ry + D)) * W + (rx + D);
     };
     double acc = 0.0;
@@ -575,7 +575,7 @@ __global__ void k_self_finish(const int64_t* __restrict__ wbeg, int64_t cap, con
   B[i] = -h3c * scale * (s + c);
 }
 
-// ---- jump probes (the OkMC loop of App. A, biased jumps of Sec. 4) -----------
+// ---- jump probes (the OkMC loop of App. B, biased jumps of Sec. 5) -----------
 //
 // Defect i translated by a whole-voxel jump lambda, everything else fixed:
 //   E_i(X + lambda) = -h^3 c E_i : sum_{x in Omega_i + lambda} (sigma - sigma_i)(x),
@@ -752,9 +752,9 @@ __global__ __launch_bounds__(ST) void k_cross(const DevDefect* __restrict__ defs
       if (lin) return P - Q + L0 + C0;
       int rx = (P & 1023) - (Q & 1023) + lx, ry = ((P >> 10) & 1023) - ((Q >> 10) & 1023) + ly,
           rz = (P >> 20) - (Q >> 20) + lz;
-      rx += rx < -h ? n : (rx >= h ? -n : 0);
-      ry += ry < -h ? n : (ry >= h ? -n : 0);
-      rz += rz < -h ? n : (rz >= h ? -n : 0);
+      rx += rx < -h ? n : (rx >= n - h ? -n : 0);
+      ry += ry < -h ? n : (ry >= n - h ? -n : 0);
+      rz += rz < -h ? n : (rz >= n - h ? -n : 0);
       return ((rz + D) * W + (ry + D)) * W + (rx + D);
     };
     double acc = 0.0;
@@ -888,7 +888,8 @@ __global__ __launch_bounds__(RDT) void k_dipole(const DevDefect* __restrict__ de
     const int id = ids[o + k];
     int r[3] = {c[0] - id % n, c[1] - (id / n) % n, c[2] - id / (n * n)};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) r[a] += r[a] < -hn ? n : (r[a] >= hn ? -n : 0);  // [-n/2, n/2): n is even
+    // minimum image: [-n/2, n/2) for even n, [-(n-1)/2, (n-1)/2] for odd n
+    for (int a = 0; a < 3; ++a) r[a] += r[a] < -hn ? n : (r[a] >= n - hn ? -n : 0);
     const int w = ((r[2] + D) * W + (r[1] + D)) * W + (r[0] + D);
     if (d.cls >= 0) {
       acc += gcls[(size_t)d.cls * W * W * W + w];

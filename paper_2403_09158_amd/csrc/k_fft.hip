@@ -79,6 +79,12 @@ __device__ __forceinline__ void acc_eps(double ax, double ay, double az, const C
   eps[5].y += 0.5 * (ax * w1.y + ay * w0.y);
 }
 
+// Centred integer label of DFT bin k in [0, n) (Sec. 3.4): k up to (n - 1) / 2,
+// k - n above.  Only an even n has a Nyquist bin (k = n / 2), whose label the
+// callers choose.
+__device__ __forceinline__ int centred(int k, int n) { return k <= (n - 1) / 2 ? k : k - n; }
+__device__ __forceinline__ bool nyquist(int k, int n) { return (n & 1) == 0 && k == n / 2; }
+
 // sigma_hat at bin (kx in [0, n/2], ky, kz in [0, n)) from eps*_hat (in place).
 // Even-n Nyquist rule: a bin with any index at n/2 gets the mean of the
 // operators at the all -n/2 and all +n/2 labels (real part of the centred
@@ -103,8 +109,8 @@ __device__ __forceinline__ void green_bin(double2* e, int kx, int ky, int kz, in
 #pragma unroll
   for (int c = 0; c < 6; ++c) eps[c] = make_double2(0.0, 0.0);
   const int h = n / 2;
-  const bool nx = kx == h, ny = ky == h, nz = kz == h;
-  const double lx = kx, ly = ky < h ? ky : ky - n, lz = kz < h ? kz : kz - n;
+  const bool nx = nyquist(kx, n), ny = nyquist(ky, n), nz = nyquist(kz, n);
+  const double lx = kx, ly = centred(ky, n), lz = centred(kz, n);
   if (!(nx || ny || nz)) {
     acc_eps(lx, ly, lz, C, tau, eps, 1.0);
   } else {
@@ -148,8 +154,8 @@ __device__ __forceinline__ void green_core_rot(double2* ec, int kx, int ky, int 
 #pragma unroll
   for (int c = 0; c < 6; ++c) eps[c] = make_double2(0.0, 0.0);
   const int h = n / 2;
-  const bool nx = kx == h, ny = ky == h, nz = kz == h;
-  const double lx = kx, ly = ky < h ? ky : ky - n, lz = kz < h ? kz : kz - n;
+  const bool nx = nyquist(kx, n), ny = nyquist(ky, n), nz = nyquist(kz, n);
+  const double lx = kx, ly = centred(ky, n), lz = centred(kz, n);
   auto acc = [&](double x, double y, double z, double wgt) {
     acc_eps(A[0] * x + A[3] * y + A[6] * z, A[1] * x + A[4] * y + A[7] * z, A[2] * x + A[5] * y + A[8] * z, C, tau,
             eps, wgt);
@@ -494,10 +500,28 @@ constexpr int pencil_wx() {
   return N >= 512 ? w / 2 : w;
 }
 
-// one butterfly per thread in the widest-radix stage
+// Threads of a tile pass over NF transforms: one butterfly per thread in the
+// widest-radix stage.  With a direct radix that stage has few butterflies, so
+// the size is set by the other stages instead: the least multiple of NF that
+// fills whole wavefronts.
+template <int N>
+constexpr int tile_threads(int NF, int rmax) {
+  if (!has_direct(plan_of(N)) && !has_direct(plan_fused(N))) return NF * (N / rmax);
+  int t = NF;
+  while (t % 64) t += NF;
+  return t;
+}
+
 template <int N, typename LT>
 constexpr int pencil_threads() {
-  return 6 * pencil_wx<N, LT>() * (N / pencil_rmax<N>());
+  return tile_threads<N>(6 * pencil_wx<N, LT>(), pencil_rmax<N>());
+}
+
+// the pencil pass prefetches the next tile's operands (FP32 storage, plans
+// without a direct radix)
+template <int N, typename S>
+constexpr bool pencil_pipe() {
+  return sizeof(S) == 4 && !has_direct(plan_of(N));
 }
 
 // Tiles of a batch of hops: job j holds cnt(j) consecutive tiles; (job, local
@@ -580,8 +604,9 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
   // FP32 storage: raw first-stage operands of the next tile are loaded while
   // the current one is transformed (rows outside the input range read row
   // in_lo, a cache hit, and are zeroed when consumed).  FP64 storage would
-  // need twice the registers for them and loads each tile's operands in turn.
-  constexpr bool PIPE = sizeof(S) == 4;
+  // need twice the registers for them and loads each tile's operands in turn,
+  // and so does a plan with a direct radix.
+  constexpr bool PIPE = pencil_pipe<N, S>();
   C2 nxt[NOP];
   auto fetch = [&](int t, int tid) {
     if constexpr (!PIPE) return;
@@ -686,7 +711,12 @@ template <int N, typename S>
 constexpr int zg_threads() {
   using FP = FusedPlan<N>;
   constexpr int rmax = FP::R0 > FP::R1 ? (FP::R0 > FP::R2 ? FP::R0 : FP::R2) : (FP::R1 > FP::R2 ? FP::R1 : FP::R2);
-  return 6 * zg_width<N, S>() * (N / rmax);
+  return tile_threads<N>(6 * zg_width<N, S>(), rmax);
+}
+
+template <int N, typename S>
+constexpr bool zg_pipe() {
+  return sizeof(S) == 4 && !has_direct(plan_fused(N));
 }
 
 // LDS row swizzle: the low three bits of the z index are XORed with the next
@@ -710,7 +740,6 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   constexpr int NF = 6 * W;   // transforms per tile
   constexpr int R0 = FP::R0, R1 = FP::R1, R2 = FP::R2;
   constexpr int NOP = ((NF * (N / R0) + T - 1) / T) * R0;  // first-stage operands per thread
-  static_assert(N % 8 == 0, "row swizzle needs whole groups of eight");
   static_assert(FP::NSTG >= 2, "the first stage must not be the last");
   using C2 = typename Cplx<S>::T;
   // FP64 tile in both storage precisions: rounding the whole spectrum to FP32
@@ -722,7 +751,8 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   constexpr int P = spec_pitch(N, sizeof(S) == 8);
   constexpr int SI = 6 * N * P;  // kz stride; all offsets fit 32 bits
   static_assert(6LL * N * N * P < (1LL << 31), "32-bit element offsets");
-  auto lds = [&](int f, int i) -> double2* { return &buf[__umul24(zg_swz(i), NF) + f]; };
+  // the row swizzle permutes whole groups of eight rows
+  auto lds = [&](int f, int i) -> double2* { return &buf[__umul24(N % 8 == 0 ? zg_swz(i) : i, NF) + f]; };
   auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
   auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
   // the spectrum and input planes of tile t, and its index within its job
@@ -746,9 +776,10 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   };
   // FP32 storage: raw first-stage operands of the next tile, loaded while the
   // current one is transformed (rows outside the input range read row in_lo
-  // instead, a cache hit, and are zeroed when consumed).  FP64 storage loads
-  // each tile's operands in turn.
-  constexpr bool PIPE = sizeof(S) == 4;
+  // instead, a cache hit, and are zeroed when consumed).  FP64 storage, and
+  // a plan with a direct radix (whose operands already fill the registers),
+  // load each tile's operands in turn.
+  constexpr bool PIPE = zg_pipe<N, S>();
   C2 nxt[NOP];
   auto fetch = [&](int t, int tid) {
     if constexpr (!PIPE) return;
@@ -920,7 +951,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
     if (k > N / 2) {
       A = conjd(A);
       B = conjd(B);
-    } else if (k == 0 || k == N / 2) {
+    } else if (k == 0 || (N % 2 == 0 && k == N / 2)) {  // bins that are their own mirror
       A.y = 0.0;
       B.y = 0.0;
     }
@@ -1034,7 +1065,7 @@ hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const
   auto* k = axis == 1 ? (inv ? (prune ? k_pencil<N, S, true, LT, true, 1> : k_pencil<N, S, true, LT, false, 1>)
                              : (prune ? k_pencil<N, S, false, LT, true, 1> : k_pencil<N, S, false, LT, false, 1>))
                       : (inv ? k_pencil<N, S, true, LT, false, 2> : k_pencil<N, S, false, LT, false, 2>);
-  const int grid = tile_grid(k, T, ntiles, sizeof(S) == 4);
+  const int grid = tile_grid(k, T, ntiles, pencil_pipe<N, S>());
   if (grid < 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, pr, tw, ntiles, ctr, (const HopJob*)nullptr, 0);
   return hipGetLastError();
@@ -1065,7 +1096,7 @@ hipError_t go_hop_batch(const HopJob* jobs, int njob, SpecGeom g, Cubic C, const
   using C2 = typename Cplx<S>::T;
   using LT = typename Cplx<S>::T;
   if (g.P != spec_pitch(N, sizeof(S) == 8) || njob < 1 || njob > MAXBATCH) return hipErrorInvalidValue;
-  constexpr bool pipe = sizeof(S) == 4;
+  constexpr bool pipe = pencil_pipe<N, S>(), zpipe = zg_pipe<N, S>();
   constexpr int TX = pick_T(max_nb(N, 3 * x_rows(N)));
   // sparse x forward: a fixed grid walks the row blocks of every job
   hipLaunchKernelGGL((k_x_forward_sparse_batch<N, S>), dim3(256), dim3(TX), 0, s, jobs, njob, g.P, tw, ctr);
@@ -1085,7 +1116,7 @@ hipError_t go_hop_batch(const HopJob* jobs, int njob, SpecGeom g, Cubic C, const
     constexpr int T = zg_threads<N, S>();
     constexpr int NT = N * ((N / 2 + 1 + W - 1) / W);
     auto* k = C.frm ? k_zgreen<N, S, true, true, true> : k_zgreen<N, S, true, false, true>;
-    const int grid = tile_grid(k, T, njob * NT, pipe);
+    const int grid = tile_grid(k, T, njob * NT, zpipe);
     if (grid < 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)nullptr, C, none, tw, ctr + 8, jobs, njob);
   }
@@ -1103,7 +1134,7 @@ hipError_t go_hop_batch(const HopJob* jobs, int njob, SpecGeom g, Cubic C, const
 
 }  // namespace
 
-#define EC_FOR_SIZES(X) X(8) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(160) X(240) X(256) X(512)
+#define EC_FOR_SIZES(X) X(8) X(16) X(24) X(32) X(45) X(48) X(64) X(96) X(128) X(129) X(160) X(240) X(256) X(512)
 
 bool fft_supported(int n) {
   switch (n) {
@@ -1182,7 +1213,7 @@ hipError_t go_zgreen(void* spec, SpecGeom g, Cubic C, Prune pr, const double2* t
   if (g.P != spec_pitch(N, sizeof(S) == 8)) return hipErrorInvalidValue;
   auto* k = C.frm ? (prune ? k_zgreen<N, S, true, true> : k_zgreen<N, S, false, true>)
                   : (prune ? k_zgreen<N, S, true, false> : k_zgreen<N, S, false, false>);
-  const int grid = tile_grid(k, T, NT, sizeof(S) == 4);
+  const int grid = tile_grid(k, T, NT, zg_pipe<N, S>());
   if (grid < 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(grid), dim3(T), 0, s, (C2*)spec, C, pr, tw, ctr, (const HopJob*)nullptr, 0);
   return hipGetLastError();
@@ -1260,9 +1291,10 @@ __global__ __launch_bounds__(256) void k_disl_spectrum(const DevLine* __restrict
     bool nyq = false;
     for (int d = 0; d < 3; ++d) {
       const int k = kb[d];
-      nyq |= k == hn;
-      lab[0][d] = k == hn ? -hn : (k < hn ? k : k - n);
-      lab[1][d] = k == hn ? hn : lab[0][d];
+      const bool ny = nyquist(k, n);
+      nyq |= ny;
+      lab[0][d] = ny ? -hn : centred(k, n);
+      lab[1][d] = ny ? hn : lab[0][d];
     }
     const int nrep = nyq ? 2 : 1;
     const double h = L / n;

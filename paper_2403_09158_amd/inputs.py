@@ -216,6 +216,17 @@ def loops_128(prec: int = 0):
     return prob, _loops111(rng, 200, L, 1.0, 4.0, log_uniform=False)
 
 
+def paper_129(prec: int = 1):
+    """The odd grid of the paper's simulations (Sec. 4: 129^3 voxels in a cube
+    of 500 a0, cube axes here), with 300 defects mixed as in mixed_256 and
+    loop radii of 1.5-6 nm (1.4-5.4 voxels)."""
+    rng = _rng(129)
+    n = 129
+    L = 500.0 * A_FE
+    prob = Problem(n, L, *CUBIC_FE, prec=prec)
+    return prob, mixed_population(rng, 300, L, L / n, r111=(1.5, 6.0), r100=(2.0, 6.0))
+
+
 def mixed_256(prec: int = 1):
     rng = _rng(3)
     n, L = 256, 80.0
@@ -257,7 +268,7 @@ def serving_replicas(nrep: int = 64, prec: int = 1):
     return out
 
 
-# Crystal orientation of the paper's simulations (Sec. 5): cell x, y, z along
+# Crystal orientation of the paper's simulations (Sec. 4): cell x, y, z along
 # [111], [-1-12], [1-10] (rows: unit vectors in cube coordinates).
 FRAME_111 = tuple(
     np.concatenate(

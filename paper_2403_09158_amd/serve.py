@@ -4,7 +4,7 @@ A replica is one defect population on its own periodic grid (its own size and
 defect count) with a resident state on the device: owner map, footprints,
 half spectrum, FP64 stress and energies.  Requests arrive over time and either
 move one defect of a replica by a whole-voxel hop (the incremental update of
-App. A, most requests) or re-solve the replica's current defect list.  Every
+App. B, most requests) or re-solve the replica's current defect list.  Every
 request ends with the replica's interaction energies in host memory.
 
 The loop

@@ -6,7 +6,7 @@ integer fingerprint of every footprint (count, sum of voxel ids, sum of squared
 voxel ids), so the GPU rasteriser can be checked bit for bit without storing
 the lists themselves.
 
-Usage: python tests/golden/make_oracle_golden.py loops_128 mixed_256
+Usage: python tests/golden/make_oracle_golden.py loops_128 mixed_256 paper_129
 """
 import os
 import sys
@@ -32,7 +32,11 @@ def fingerprint(fps):
 
 def run(name):
     t = time.time()
-    prob, defs = {"loops_128": lambda: inputs.loops_128(prec=0), "mixed_256": lambda: inputs.mixed_256(prec=0)}[name]()
+    prob, defs = {
+        "loops_128": lambda: inputs.loops_128(prec=0),
+        "mixed_256": lambda: inputs.mixed_256(prec=0),
+        "paper_129": lambda: inputs.paper_129(prec=0),
+    }[name]()
     E, parts = energy.energies_fast(prob, defs, return_parts=True)
     cnt, s1, s2 = fingerprint(parts["fps"])
     out = os.path.join(HERE, f"oracle_{name}.npz")
@@ -41,5 +45,5 @@ def run(name):
 
 
 if __name__ == "__main__":
-    for name in sys.argv[1:] or ["loops_128", "mixed_256"]:
+    for name in sys.argv[1:] or ["loops_128", "mixed_256", "paper_129"]:
         run(name)

@@ -1,4 +1,4 @@
-"""Rotated crystal on the GPU (ec_problem.frame; the cell axes of Sec. 5 along
+"""Rotated crystal on the GPU (ec_problem.frame; the cell axes of Sec. 4 along
 [111], [-1-12], [1-10]): fields, strains and energies against the oracle for
 both mean conditions and precisions, whole-voxel hops through the incremental
 update, the explicit identity frame, states of different frames sharing one

@@ -1,4 +1,5 @@
-"""Full-size parity: the 128^3 / 200-loop and 256^3 / 2000-defect workloads.
+"""Full-size parity: the 128^3 / 200-loop and 256^3 / 2000-defect workloads, and
+the paper's odd 129^3 grid with 300 defects.
 
 Energies are compared with FP64 oracle values stored in tests/golden (written
 by tests/golden/make_oracle_golden.py, which calls only the oracle); the
@@ -35,12 +36,14 @@ def _fingerprint(fps):
     return cnt, s1, s2
 
 
-@pytest.mark.parametrize("name", ["loops_128", "mixed_256"])
+@pytest.mark.parametrize("name", ["loops_128", "mixed_256", "paper_129"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_energies_match_stored_oracle(ctx, name, prec):
     from paper_2403_09158_amd import ec
 
-    prob, defs = {"loops_128": inputs.loops_128, "mixed_256": inputs.mixed_256}[name](prec=prec)
+    prob, defs = {"loops_128": inputs.loops_128, "mixed_256": inputs.mixed_256, "paper_129": inputs.paper_129}[name](
+        prec=prec
+    )
     g = _golden(name)
     st = ec.State(ctx, prob)
     st.solve(defs)

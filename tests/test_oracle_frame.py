@@ -1,4 +1,4 @@
-"""Pins of the rotated-crystal stiffness (the cell axes of Sec. 5 along
+"""Pins of the rotated-crystal stiffness (the cell axes of Sec. 4 along
 [111], [-1-12], [1-10]): the textbook longitudinal modulus of a cubic crystal
 along any direction, the rotation invariants, cubic symmetry operations and an
 isotropic crystal leave C unchanged, and the solve with a rotated C keeps

@@ -39,7 +39,7 @@ def test_event_counts_are_the_poisson_inversion():
 
 def test_event_count_statistics_of_the_fixed_step():
     """With dt = 1 / nu_max the fastest defect makes one event per step on
-    average (Sec. 4); mean and variance 1, P(N = 0) = 1/e."""
+    average (Sec. 5); mean and variance 1, P(N = 0) = 1/e."""
     rng = np.random.default_rng(inputs.SEED_BASE + 801)
     k = 200000
     kT, nu0 = 0.025852, 1e13

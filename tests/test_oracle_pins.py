@@ -295,9 +295,12 @@ def _mixed_small(n=24, seed=0):
     return prob, d
 
 
+@pytest.mark.parametrize("n", [24, 21])
 @pytest.mark.parametrize("bc", [0, 1])
-def test_brute_energies_equal_fast_exact(bc):
-    prob, d = _mixed_small()
+def test_brute_energies_equal_fast_exact(bc, n):
+    """The windowed energies equal one solve per defect (the definition), also
+    for an odd grid, whose minimum images and labels have no Nyquist case."""
+    prob, d = _mixed_small(n=n)
     prob = prob.with_(bc=bc)
     Eb, Eij = energy.energies_brute(prob, d)
     Ef = energy.energies_fast(prob, d)
