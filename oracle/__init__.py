@@ -26,6 +26,9 @@ elastic interactions in OkMC" (arXiv 2403.09158):
                  energies of the moved list.
 * ``dipole``   - the dipole-tensor approximation of the interaction energy
                  (Sec. 2.1).
+* ``shift``    - stored defect-type fields translated by the shift theorem
+                 (Sec. 3.3, eq. ``shift``) and the energy of the translated
+                 defect with a stress field.
 * ``dislocation`` - straight dislocation lines by field dislocation mechanics
                  (Sec. 3.1): Nye tensor, incompatible plastic distortion, the
                  Green solve of its symmetric part.
