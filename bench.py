@@ -228,6 +228,62 @@ def mixed_512_block(steps=3):
     return out
 
 
+def paper_129_block(steps=10, warmup=3):
+    """The paper's odd grid (129^3 voxels in a cube of 500 a0, 300 defects):
+    FP32 and FP64 solve + energies, and both against the stored oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2403_09158_amd import ec, inputs
+
+    prob, defs = inputs.paper_129(prec=1)
+    ctx = ec.Context(0)
+    out = {"workload": "paper_129: 129^3 cell of 500 a0 (143.3 nm), cubic C 243/145/116 GPa, 300 defects"}
+    g = np.load(os.path.join(ROOT, "tests", "golden", "oracle_paper_129.npz"))
+    for prec, name in ((1, "fp32"), (0, "fp64")):
+        st = ec.State(ctx, prob.with_(prec=prec))
+        dt, E, _ = timed_steps(st, defs, steps, warmup, profile=False)
+        out[name] = {"solves_per_s": round(steps / dt, 2), "ms_per_step": round(1e3 * dt / steps, 4),
+                     "vs_oracle": energy_errors(E, g["E"])}
+        st.close()
+    ctx.close()
+    return out
+
+
+def stored_type_block(reps=10):
+    """Stored defect types translated by the shift theorem on mixed_256 (FP32
+    storage): storing a type, and the energies of one type at 16 and at 64
+    sub-voxel positions with the resident stress (the mover excluded)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_09158_amd import ec, inputs
+
+    prob, defs = inputs.mixed_256(prec=1)
+    ctx = ec.Context(0)
+    st = ec.State(ctx, prob)
+    st.solve(defs)
+    torch.cuda.synchronize()
+    i = 5
+    t0 = time.perf_counter()
+    t = st.type_store(defs[i : i + 1])
+    store_ms = (time.perf_counter() - t0) * 1e3
+    rng = np.random.default_rng(0)
+    out = {"workload": "mixed_256 FP32, type = defect 5 (a 1/2<111> loop), positions within 2 voxels",
+           "store_ms": round(store_ms, 3)}
+    for k in (16, 64):
+        X = defs[i]["c"] + rng.uniform(-2, 2, (k, 3)) * prob.h
+        st.type_energies(t, X, X_excl=defs[i]["c"])
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st.type_energies(t, X, X_excl=defs[i]["c"])
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        out[f"positions_{k}"] = {"ms_per_call": round(ms, 3), "us_per_position": round(1e3 * ms / k, 2)}
+    st.close()
+    ctx.close()
+    return out
+
+
 def frame_block(steps=10, warmup=3):
     """mixed_256 with the crystal in the orientation of the paper's simulations
     (cell x, y, z along [111], [-1-12], [1-10]): solve + energies per step in
@@ -545,6 +601,8 @@ def main():
     ap.add_argument("--dipole-only", action="store_true", help="run the dipole-tensor workload alone (profiling runs)")
     ap.add_argument("--no-frame", action="store_true", help="skip the rotated-crystal and dislocation workloads")
     ap.add_argument("--frame-only", action="store_true", help="run the rotated-crystal and dislocation workloads alone")
+    ap.add_argument("--no-f4", action="store_true", help="skip the odd-grid and stored-type workloads")
+    ap.add_argument("--f4-only", action="store_true", help="run the odd-grid and stored-type workloads alone")
     ap.add_argument(
         "--calibrate-copy",
         action="store_true",
@@ -571,6 +629,9 @@ def main():
         b.copy_(a)  # reads and writes exactly 2^30 bytes each
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 1 << 30}), flush=True)
+        return
+    if args.f4_only:
+        print(json.dumps({"paper_129": paper_129_block(), "stored_type": stored_type_block()}), flush=True)
         return
     if args.frame_only:
         print(json.dumps({"frame_111": frame_block(), "dislocation": dislocation_block()}), flush=True)
@@ -685,6 +746,9 @@ def main():
     if not args.no_frame:
         line["frame_111"] = frame_block()
         line["dislocation"] = dislocation_block()
+    if not args.no_f4:
+        line["paper_129"] = paper_129_block()
+        line["stored_type"] = stored_type_block()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob64, defs)
     print(json.dumps(line), flush=True)

@@ -201,6 +201,35 @@ EC_API ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* mo
 EC_API ec_status ec_update_batch(ec_state* const* states, const int32_t* idx, const ec_defect* moved, int32_t k,
                                  void* hip_stream, double* const* E_dev, int32_t use_graph);
 
+/* ---- stored defect types and the shift theorem (Sec. 3.3, eq. shift) ------ */
+
+/* Store a defect type: the prototype *proto is rasterised at its own centre X0
+ * (the reference position), and its eigenstrain spectrum eps*_hat_0(xi) and
+ * stress spectrum sigma_hat_0(xi) (the Green step of the solve; at xi = 0 the
+ * mean stress of the problem's mean condition) are kept on the device with the
+ * state: two half spectra in the state's storage precision, charged to the
+ * ledger (EC_ERR_ADMIT if they do not fit).  *type receives the type's index
+ * (0, 1, ... in storing order, at most 64 per state).  Synchronises the stream. */
+EC_API ec_status ec_type_store(ec_state* st, const ec_defect* proto, void* hip_stream, int32_t* type);
+
+/* Interaction energies (eV, host array E_out of k doubles) of a defect of a
+ * stored type translated to each of k positions X[3 p .. 3 p + 2] (nm, any real
+ * values: whole-voxel offsets from X0 translate the voxel field exactly, others
+ * give its trigonometric interpolation), with the state's resident stress
+ * (its last solve or update):
+ *   E_p = -h^3 c sum_x eps*_0(x - (X_p - X0)) : sigma_others(x),
+ * the translated eigenstrain being the real part of the inverse transform of
+ * exp(-i xi . (X_p - X0)) eps*_hat_0(xi) (centred labels of Sec. 3.4; at an even
+ * n's Nyquist bins the phase is averaged over the -n/2 and +n/2 representatives).
+ * sigma_others is the resident stress, minus, when X_excl is not NULL, the
+ * type's own stress translated to X_excl (the moving defect itself, when the
+ * state's list holds it there).  EC_ERR_STATE before the first solve.  The
+ * resident stress is transformed once per call and the positions are taken
+ * 16 per pass over the spectra; the state's work spectrum is overwritten.
+ * Synchronises the stream. */
+EC_API ec_status ec_type_energies(ec_state* st, int32_t type, const double* X, int32_t k, const double* X_excl,
+                                  void* hip_stream, double* E_out);
+
 /* ---- jump probes (the OkMC loop of App. B; biased jumps of Sec. 5) ---------- */
 
 /* For every defect i and each of its njump (1..64) candidate whole-voxel jumps

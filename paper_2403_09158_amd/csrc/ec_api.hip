@@ -373,6 +373,17 @@ struct ec_state {
   size_t jchoice_cap = 0;
   double* dip = nullptr;  // dipole-tensor energies
   size_t dip_cap = 0;
+  // stored defect types (Sec. 3.3): the eigenstrain and stress half spectra of
+  // each prototype at its reference centre X0, and the phase tables, partial
+  // sums and energies of ec_type_energies
+  struct TypeSpec {
+    void* eps = nullptr;
+    void* sig = nullptr;
+    double X0[3] = {0, 0, 0};
+  };
+  std::vector<TypeSpec> types;
+  double* tbuf = nullptr;
+  size_t tbuf_cap = 0;
   // pinned staging: defect table, per-update records, moved footprint
   Pinned pin_tab, pin_upd, pin_ids, pin_tags, pin_jump, pin_choice, pin_out;
   // profiling
@@ -1455,6 +1466,20 @@ ec_status run_select(ec_state* st, const double* Em, double nu0, double kT, cons
   return EC_OK;
 }
 
+// Footprint of a quantised defect on the host, ascending voxel ids: the same
+// box enumeration and membership test as the rasteriser.
+void footprint_ids(const DevDefect& d, int n, std::vector<int32_t>& ids) {
+  ids.clear();
+  for (int iz = 0; iz < d.w[2]; ++iz)
+    for (int iy = 0; iy < d.w[1]; ++iy) {
+      const int y = box_axis(d.lo[1], d.w[1], n, iy), z = box_axis(d.lo[2], d.w[2], n, iz);
+      for (int ix = 0; ix < d.w[0]; ++ix) {
+        const int x = box_axis(d.lo[0], d.w[0], n, ix);
+        if (member(d, n, x, y, z)) ids.push_back((z * n + y) * n + x);
+      }
+    }
+}
+
 // Moves defect idx to the quantised record nd (validated): by linearity only
 // the eigenstrain difference is solved and the resident stress accumulated;
 // a whole-voxel move of the same shape translates the footprint.
@@ -1495,15 +1520,7 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
   nd.slot = od.slot;
   ec_status r;
   if (!hop) {
-    // new footprint on the host, same enumeration and membership as the rasteriser
-    for (int iz = 0; iz < nd.w[2]; ++iz)
-      for (int iy = 0; iy < nd.w[1]; ++iy) {
-        const int y = box_axis(nd.lo[1], nd.w[1], n, iy), z = box_axis(nd.lo[2], nd.w[2], n, iz);
-        for (int ix = 0; ix < nd.w[0]; ++ix) {
-          const int x = box_axis(nd.lo[0], nd.w[0], n, ix);
-          if (member(nd, n, x, y, z)) new_ids.push_back((z * n + y) * n + x);
-        }
-      }
+    footprint_ids(nd, n, new_ids);
     cnt_new = (int)new_ids.size();
     size_t ucap = (size_t)st->upd_cap;
     if ((r = st_grow(st, &st->upd_ids, &ucap, std::max<size_t>(cnt_new, 1))) != EC_OK) {
@@ -1926,6 +1943,11 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->jsel, st->jsel_cap * 8);
   ledger_free(c, st->jnu, st->jnu_cap * 8);
   ledger_free(c, st->jwork, st->jwork_cap * sizeof(SelfWork));
+  for (const auto& t : st->types) {
+    ledger_free(c, t.eps, st->spec_bytes);
+    ledger_free(c, t.sig, st->spec_bytes);
+  }
+  ledger_free(c, st->tbuf, st->tbuf_cap * 8);
   ledger_free(c, st->jwbeg, st->jwbeg_cap * 8);
   ledger_free(c, st->jchoice, st->jchoice_cap * 4);
   ledger_free(c, st->dip, st->dip_cap * 8);
@@ -2550,6 +2572,154 @@ struct Tmp {
 }  // namespace
 
 extern "C" {
+
+ec_status ec_type_store(ec_state* st, const ec_defect* proto, void* stream, int32_t* type) {
+  if (!st || !proto || !type) return fail(EC_ERR_ARG, "NULL argument");
+  if (st->types.size() >= 64) return fail(EC_ERR_ARG, "at most 64 stored types per state");
+  hipStream_t s = (hipStream_t)stream;
+  DevDefect d;
+  std::string err;
+  if (!quantise(st->prob, *proto, d, err)) return fail(EC_ERR_ARG, "prototype: %s", err.c_str());
+  std::vector<int32_t> ids;
+  footprint_ids(d, st->n, ids);
+  const int m = (int)ids.size();
+  ec_ctx* c = st->ctx;
+  Tmp ti{c}, te{c};
+  ec_status r;
+  // [ids][zero count]; E: no old eigenstrain, the prototype's (cell frame) as the new one
+  if ((r = ledger_alloc(c, ti.b = (size_t)m * 4 + 64, &ti.p)) != EC_OK) return r;
+  if ((r = ledger_alloc(c, te.b = 96, &te.p)) != EC_OK) return r;
+  ec_state::TypeSpec t;
+  if ((r = ledger_alloc(c, st->spec_bytes, &t.eps)) != EC_OK) return r;
+  if ((r = ledger_alloc(c, st->spec_bytes, &t.sig)) != EC_OK) {
+    ledger_free(c, t.eps, st->spec_bytes);
+    return r;
+  }
+  auto undo = [&](ec_status rc) {
+    (void)hipStreamSynchronize(s);
+    ledger_free(c, t.eps, st->spec_bytes);
+    ledger_free(c, t.sig, st->spec_bytes);
+    return rc;
+  };
+  for (int k = 0; k < 3; ++k) t.X0[k] = proto->c[k];
+  double E12[12] = {0, 0, 0, 0, 0, 0};
+  std::copy(d.E, d.E + 6, E12 + 6);
+  const int32_t zero = 0;
+  int32_t* dids = (int32_t*)ti.p;
+  int32_t* dzero = (int32_t*)((char*)ti.p + (size_t)m * 4);
+  if (hipMemcpy(dzero, &zero, 4, hipMemcpyHostToDevice) != hipSuccess ||
+      (m > 0 && hipMemcpy(dids, ids.data(), (size_t)m * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(te.p, E12, 96, hipMemcpyHostToDevice) != hipSuccess)
+    return undo(fail(EC_ERR_DEVICE, "upload of the prototype failed"));
+  const bool fp64 = st->fp64;
+  const int n = st->n;
+  const Prune rows{d.lo[1], d.w[1], d.lo[2], d.w[2]}, full{0, n, 0, n};
+  // eps*_hat_0: the rasterised prototype's rows, then the y pass over its
+  // planes and the z pass over the cleared spectrum
+  hipError_t e = launch_fill_i32((int32_t*)t.eps, (int64_t)(st->spec_bytes / 4), 0, s);
+  if (e == hipSuccess)
+    e = launch_x_forward_sparse(fp64, dids, dzero, dids, m, 0, 0, 0, (const double*)te.p, t.eps, st->g, d.lo[1],
+                                d.w[1], d.lo[2], d.w[2], st->tw, nullptr, s);
+  if (e == hipSuccess) e = launch_pencil(fp64, false, 1, t.eps, st->g, rows, st->tw, nullptr, s);
+  if (e == hipSuccess) e = launch_pencil(fp64, false, 2, t.eps, st->g, full, st->tw, nullptr, s);
+  // sigma_hat_0 = S(xi):eps*_hat_0, the mean stress at xi = 0
+  if (e == hipSuccess) e = hipMemcpyAsync(t.sig, t.eps, st->spec_bytes, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = launch_green(fp64, t.sig, st->g, st->C, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && st->prob.bc == EC_MEAN_STRAIN_ZERO) {
+    double m6[6], s6[6];
+    for (int a = 0; a < 6; ++a) m6[a] = (double)m * d.E[a];
+    neg_C_dot(st, m6, s6);  // N <sigma> = -C : (m E)
+    if (fp64) {
+      double2 v[6];
+      for (int a = 0; a < 6; ++a) v[a] = make_double2(s6[a], 0.0);
+      e = hipMemcpy(t.sig, v, sizeof v, hipMemcpyHostToDevice);
+    } else {
+      float2 v[6];
+      for (int a = 0; a < 6; ++a) v[a] = make_float2((float)s6[a], 0.0f);
+      e = hipMemcpy(t.sig, v, sizeof v, hipMemcpyHostToDevice);
+    }
+  }
+  if (e != hipSuccess) return undo(fail(EC_ERR_DEVICE, "HIP error %s", hipGetErrorString(e)));
+  st->types.push_back(t);
+  st->held += 2 * st->spec_bytes;
+  *type = (int32_t)st->types.size() - 1;
+  return EC_OK;
+}
+
+ec_status ec_type_energies(ec_state* st, int32_t type, const double* X, int32_t k, const double* X_excl,
+                           void* stream, double* E_out) {
+  if (!st) return fail(EC_ERR_ARG, "NULL argument");
+  if (k < 0) return fail(EC_ERR_ARG, "negative position count");
+  if (k > 0 && (!X || !E_out)) return fail(EC_ERR_ARG, "NULL argument");
+  if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
+  if (type < 0 || type >= (int32_t)st->types.size()) return fail(EC_ERR_ARG, "type %d is not stored", type);
+  for (int64_t i = 0; i < 3 * (int64_t)k; ++i)
+    if (!std::isfinite(X[i])) return fail(EC_ERR_ARG, "position %lld is not finite", (long long)(i / 3));
+  if (X_excl)
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(X_excl[a])) return fail(EC_ERR_ARG, "excluded position is not finite");
+  if (k == 0) return EC_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int n = st->n;
+  const double L = st->prob.L;
+  const int grid = type_energy_grid(n);
+  const size_t ntab = (size_t)(TYPE_NP + 1) * 3 * n, nnyq = (size_t)(TYPE_NP + 1) * 3;
+  const size_t need = 2 * (ntab + nnyq) + (size_t)grid * TYPE_NP + (size_t)k;
+  ec_status r;
+  size_t cap = st->tbuf_cap;
+  if ((r = st_grow(st, &st->tbuf, &cap, need)) != EC_OK) return r;
+  st->tbuf_cap = cap;
+  double2* dtab = (double2*)st->tbuf;
+  double2* dnyq = dtab + ntab;
+  double* partial = (double*)(dnyq + nnyq);
+  double* dE = partial + (size_t)grid * TYPE_NP;
+  const ec_state::TypeSpec& T = st->types[type];
+  const bool fp64 = st->fp64;
+  const Prune full{0, n, 0, n};
+  // sigma_hat of the resident stress in the work spectrum
+  hipError_t e = launch_x_forward_vm(fp64, st->sig, st->spec, st->g, st->tw, s);
+  if (e == hipSuccess) e = launch_pencil(fp64, false, 1, st->spec, st->g, full, st->tw, nullptr, s);
+  if (e == hipSuccess) e = launch_pencil(fp64, false, 2, st->spec, st->g, full, st->tw, nullptr, s);
+  if (e != hipSuccess) return fail(EC_ERR_DEVICE, "HIP error %s", hipGetErrorString(e));
+  // phase factors exp(-2 pi i l d / L) per axis and label l (the centred label
+  // of each bin, -n/2 at an even n's Nyquist bin; +n/2 in the second table)
+  std::vector<double2> htab(ntab), hnyq(nnyq);
+  auto factor = [&](int l, double u) {
+    double t = (double)l * u;
+    t -= std::floor(t);
+    return make_double2(std::cos(2.0 * M_PI * t), -std::sin(2.0 * M_PI * t));
+  };
+  auto fill = [&](int p, const double* Xp) {
+    for (int a = 0; a < 3; ++a) {
+      const double u = (Xp[a] - T.X0[a]) / L;
+      double2* row = htab.data() + ((size_t)p * 3 + a) * n;
+      for (int q = 0; q < n; ++q) row[q] = factor(q <= (n - 1) / 2 ? q : q - n, u);
+      hnyq[(size_t)p * 3 + a] = factor(n / 2, u);
+    }
+  };
+  const double scale = -st->h3c / (double)st->n3;
+  for (int p0 = 0; p0 < k; p0 += TYPE_NP) {
+    const int np = std::min(TYPE_NP, k - p0);
+    if (p0 > 0 && (e = hipStreamSynchronize(s)) != hipSuccess) break;  // the host tables are refilled
+    for (int p = 0; p < np; ++p) fill(p, X + 3 * (size_t)(p0 + p));
+    if (X_excl) fill(np, X_excl);
+    const size_t rows = (size_t)(np + (X_excl ? 1 : 0));
+    if ((e = hipMemcpyAsync(dtab, htab.data(), rows * 3 * n * sizeof(double2), hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(dnyq, hnyq.data(), rows * 3 * sizeof(double2), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+      break;
+    // the excluded mover's factors sit in entry np of the tables
+    if ((e = launch_type_energies(fp64, st->spec, T.eps, T.sig, st->g, dtab, dnyq, np, X_excl != nullptr, partial,
+                                  scale, dE + p0, s)) != hipSuccess)
+      break;
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(E_out, dE, (size_t)k * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(EC_ERR_DEVICE, "HIP error %s", hipGetErrorString(e));
+  return EC_OK;
+}
 
 ec_status ec_debug_forward(ec_state* st, const double* field, double* out) {
   if (!st || !field || !out) return fail(EC_ERR_ARG, "NULL argument");

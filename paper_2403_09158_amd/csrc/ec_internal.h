@@ -338,6 +338,18 @@ constexpr int NTILECTR = 24;
 hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs, int ndef,
                             const double* dense, void* spec, SpecGeom g, const double2* tw, uint32_t* zero_ctr,
                             hipStream_t s);
+// Energies of a stored defect type at up to TYPE_NP translated positions per
+// launch (Sec. 3.3): sig, te, ts are the half spectra of the field, of the
+// type's eigenstrain and of its stress; tab/nyq the phase tables of the np
+// positions and, in entry np, of the excluded mover; partial holds
+// type_energy_grid(n) x TYPE_NP doubles; E[p] = scale * sum.
+constexpr int TYPE_NP = 16;
+int type_energy_grid(int n);
+hipError_t launch_type_energies(bool fp64, const void* sig, const void* te, const void* ts, SpecGeom g,
+                                const double2* tab, const double2* nyq, int np, bool excl, double* partial,
+                                double scale, double* E, hipStream_t s);
+// Dense voxel-major FP64 input [n^3][6] (the resident stress).
+hipError_t launch_x_forward_vm(bool fp64, const double* vm, void* spec, SpecGeom g, const double2* tw, hipStream_t s);
 // E: 12 doubles, the old eigenstrain (on old_ids) then the new one (on the new ids).
 hipError_t launch_x_forward_sparse(bool fp64, const int32_t* old_ids, const int32_t* old_cnt, const int32_t* new_ids,
                                    int new_cnt,

@@ -246,7 +246,9 @@ __device__ __forceinline__ auto x_twiddles(const double2* tw_lds, const double2*
 // fixed order within its XCD's contiguous range, and loads the next group's
 // owner links into registers while it decodes and transforms the current one,
 // so the HBM latency of the owner map overlaps the work of the group before.
-template <int N, typename S, bool DENSE>
+// DM: the input, 0 = owner lists, 1 = a dense field [6][n^3], 2 = a dense
+// voxel-major field [n^3][6] (the resident stress).
+template <int N, typename S, int DM>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
     const int32_t* __restrict__ own, const int2* __restrict__ lnk, const DevDefect* __restrict__ defs,
     const double* __restrict__ dense, typename Cplx<S>::T* __restrict__ spec, int P, const double2* __restrict__ twg,
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
     for (int k = 0; k < KV; ++k) {
       const int i = threadIdx.x + k * T;
       lk[k] = -1;
-      if (!DENSE && i < ROWS * N) lk[k] = own[(size_t)grp * (ROWS * N) + i];
+      if (DM == 0 && i < ROWS * N) lk[k] = own[(size_t)grp * (ROWS * N) + i];
     }
   };
   TileWalk walk(NG, nullptr, tslot);
@@ -295,10 +297,18 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
       if (i < ROWS * N) {
         const int r = i / N, x = i - r * N;
         double e[6];
-        if (DENSE) {
+        if (DM == 1) {
           const size_t v = ((size_t)z * N + y0 + r) * N + x;
 #pragma unroll
           for (int c = 0; c < 6; ++c) e[c] = dense[c * n3 + v];
+        } else if (DM == 2) {
+          const double2* vp = reinterpret_cast<const double2*>(dense + 6 * (((size_t)z * N + y0 + r) * N + x));
+#pragma unroll
+          for (int p = 0; p < 3; ++p) {
+            const double2 t = vp[p];
+            e[2 * p] = t.x;
+            e[2 * p + 1] = t.y;
+          }
         } else if (link[k] == -1) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) e[c] = 0.0;
@@ -1024,14 +1034,25 @@ hipError_t go_xf(const int32_t* own, const int2* lnk, const DevDefect* defs, int
   using C2 = typename Cplx<S>::T;
   // as many workgroups as stay resident (a multiple of eight), at most one
   // per row group
-  const int grid = tile_grid(k_x_forward<N, S, false>, T, ngroups, true);
+  const int grid = tile_grid(k_x_forward<N, S, 0>, T, ngroups, true);
   if (grid < 0) return hipErrorInvalidValue;
   if (dense)
-    hipLaunchKernelGGL((k_x_forward<N, S, true>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P, tw,
+    hipLaunchKernelGGL((k_x_forward<N, S, 1>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P, tw,
                        zero_ctr, ndef);
   else
-    hipLaunchKernelGGL((k_x_forward<N, S, false>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P,
+    hipLaunchKernelGGL((k_x_forward<N, S, 0>), dim3(grid), dim3(T), 0, s, own, lnk, defs, dense, (C2*)spec, g.P,
                        tw, zero_ctr, ndef);
+  return hipGetLastError();
+}
+
+template <int N, typename S>
+hipError_t go_xf_vm(const double* vm, void* spec, SpecGeom g, const double2* tw, hipStream_t s) {
+  constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
+  const int grid = tile_grid(k_x_forward<N, S, 2>, T, N * (N / x_rows(N)), true);
+  if (grid < 0 || g.P != spec_pitch(N, sizeof(S) == 8)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_x_forward<N, S, 2>), dim3(grid), dim3(T), 0, s, (const int32_t*)nullptr,
+                     (const int2*)nullptr, (const DevDefect*)nullptr, vm, (typename Cplx<S>::T*)spec, g.P, tw,
+                     (uint32_t*)nullptr, 0);
   return hipGetLastError();
 }
 
@@ -1157,6 +1178,17 @@ hipError_t launch_x_forward(bool fp64, const int32_t* own, const int2* lnk, cons
   case NN:                                                                              \
     return fp64 ? go_xf<NN, double>(own, lnk, defs, ndef, dense, spec, g, tw, zero_ctr, s) \
                 : go_xf<NN, float>(own, lnk, defs, ndef, dense, spec, g, tw, zero_ctr, s);
+    EC_FOR_SIZES(EC_CASE)
+#undef EC_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_x_forward_vm(bool fp64, const double* vm, void* spec, SpecGeom g, const double2* tw, hipStream_t s) {
+  switch (g.n) {
+#define EC_CASE(NN) \
+  case NN:          \
+    return fp64 ? go_xf_vm<NN, double>(vm, spec, g, tw, s) : go_xf_vm<NN, float>(vm, spec, g, tw, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }

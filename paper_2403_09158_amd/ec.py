@@ -45,6 +45,8 @@ EXPORTS = (
     "ec_okmc_step",
     "ec_set_dislocations",
     "ec_dipole_energies",
+    "ec_type_store",
+    "ec_type_energies",
     "ec_state_footprints",
     "ec_state_field",
     "ec_state_self_terms",
@@ -118,6 +120,8 @@ def load() -> ctypes.CDLL:
             [vp, vp, c_int32, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp],
         ),
         "ec_dipole_energies": (c_int, [vp, vp, vp, c_int32]),
+        "ec_type_store": (c_int, [vp, vp, vp, i32p]),
+        "ec_type_energies": (c_int, [vp, c_int32, vp, c_int32, vp, vp, vp]),
         "ec_set_dislocations": (c_int, [vp, vp, c_int32, vp]),
         "ec_state_footprints": (c_int, [vp, i32p, i32p, c_int64, i64p]),
         "ec_state_field": (c_int, [vp, c_int32, dp]),
@@ -326,6 +330,33 @@ class State:
             return E
         _check(load().ec_update_defect(self.h, idx, d.ctypes.data, h, None, 0))
         return None
+
+    def type_store(self, proto, stream=None) -> int:
+        """Store the spectra of the defect type of the one-record array
+        ``proto`` at its own centre; returns the type's index."""
+        d = as_defects(proto)
+        if len(d) != 1:
+            raise ValueError("a prototype is one defect record")
+        t = c_int32(-1)
+        _check(load().ec_type_store(self.h, d.ctypes.data, _stream_handle(stream), ctypes.byref(t)))
+        return t.value
+
+    def type_energies(self, type_id: int, X, X_excl=None, stream=None) -> np.ndarray:
+        """Energies (eV) of the stored type translated to the positions ``X``
+        (k, 3) (nm), with the resident stress (minus the type's own stress at
+        ``X_excl`` if given)."""
+        x = np.ascontiguousarray(np.atleast_2d(X), dtype=np.float64)
+        if x.shape[1] != 3:
+            raise ValueError(f"positions must have shape (k, 3), got {x.shape}")
+        xe = None if X_excl is None else np.ascontiguousarray(X_excl, dtype=np.float64).reshape(3)
+        E = np.zeros(len(x))
+        _check(
+            load().ec_type_energies(
+                self.h, type_id, x.ctypes.data, len(x), None if xe is None else xe.ctypes.data,
+                _stream_handle(stream), E.ctypes.data,
+            )
+        )
+        return E
 
     def jump_energies(self, jumps, stream=None, out=None) -> np.ndarray:
         """Energy change (eV) of every defect for each of its candidate

@@ -203,3 +203,32 @@ def test_mixed512_fp32_against_fp64_and_sampled_footprints(ctx):
     st.close()
     ok = energy_ok_fp32(E32, E64)
     assert np.all(ok), (np.flatnonzero(~ok)[:10], np.abs(E32 - E64)[~ok][:10])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mixed256_stored_types_against_state_energies(ctx, prec):
+    """Stored-type energies at full size (Sec. 3.3): a defect of the 2000 stored
+    as a type and excluded at its own position has, there, the state's
+    energy of that defect, and after a whole-voxel glide jump the state's
+    energy plus the jump probe's energy change (FP64 1e-10 of the largest |E|;
+    FP32 the per-defect bound)."""
+    from paper_2403_09158_amd import ec
+
+    prob, defs = inputs.mixed_256(prec=prec)
+    st = ec.State(ctx, prob)
+    st.solve(defs)
+    E = st.energies().copy()
+    J = inputs.glide_jumps(defs)
+    dE = st.jump_energies(J)
+    for i in (5, 711, 1999):
+        t = st.type_store(defs[i : i + 1])
+        Xi = defs[i]["c"]
+        X = np.array([Xi, Xi + J[i, 0] * prob.h, Xi + J[i, 1] * prob.h])
+        Et = st.type_energies(t, X, X_excl=Xi)
+        want = np.array([E[i], E[i] + dE[i, 0], E[i] + dE[i, 1]])
+        if prec == 0:
+            assert np.max(np.abs(Et - want)) <= 1e-10 * np.abs(E).max(), (i, Et, want)
+        else:
+            ok = energy_ok_fp32(Et, want)
+            assert np.all(ok), (i, Et, want)
+    st.close()
