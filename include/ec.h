@@ -23,7 +23,12 @@
  *
  * Error behaviour: every entry point returns an ec_status; nothing throws across
  * the boundary.  On error the state is left unchanged (strong guarantee) and a
- * message is available from ec_last_error().  Ownership: the caller owns every
+ * message is available from ec_last_error().  The calls that also return
+ * energies after changing the state (ec_update_defect with E_out, ec_okmc_step)
+ * are a change followed by an energies call: if the change succeeded and the
+ * energies fail, the state holds the change and the error is returned.  The
+ * self terms of a new list whose set-up cannot allocate are left to the next
+ * energies call, which reports the failure.  Ownership: the caller owns every
  * pointer it passes in (defect records are copied during the call; output
  * buffers are written, never retained); the library owns every ec_ctx/ec_state
  * and the device memory behind them until the matching destroy call.
@@ -181,7 +186,8 @@ EC_API ec_status ec_interaction_energies_noalloc(ec_state* st, void* hip_stream,
 /* Move defect idx to the record *moved (Appendix B: subtract the old field,
  * add the new one).  By linearity only the eigenstrain difference is solved;
  * the resident FP64 stress is accumulated and, if E_out != NULL, all ndef
- * energies are returned as in ec_interaction_energies. */
+ * energies are returned as in ec_interaction_energies (an error there leaves
+ * the move made). */
 EC_API ec_status ec_update_defect(ec_state* st, int32_t idx, const ec_defect* moved, void* hip_stream, double* E_out,
                            int32_t out_on_device);
 

@@ -1216,13 +1216,21 @@ ec_status copy_out(void* dst, const void* src, size_t bytes, bool on_device, hip
 
 // A per-defect output: to the host through the state's pinned bounce buffer (a
 // direct copy into pageable memory is staged by the runtime), synchronously.
+// Small results returned to a waiting host caller: copied into pinned memory
+// behind an event that the calling thread polls, since a thread blocked in
+// the driver's stream synchronisation resumes tens of microseconds after the
+// copy has landed.
 ec_status copy_small(ec_state* st, void* dst, const void* src, size_t bytes, bool on_device, hipStream_t s) {
   if (on_device || bytes == 0) return copy_out(dst, src, bytes, on_device, s);
   char* hp = nullptr;
   ec_status r = pin_begin(st->pin_out, bytes, &hp);
   if (r != EC_OK) return r;
   HIPCHK(hipMemcpyAsync(hp, src, bytes, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipEventRecord(st->pin_out.ev, s));
+  hipError_t q;
+  while ((q = hipEventQuery(st->pin_out.ev)) == hipErrorNotReady) {
+  }
+  HIPCHK(q);
   std::memcpy(dst, hp, bytes);
   return EC_OK;
 }
@@ -1268,6 +1276,21 @@ ec_status ensure_per_defect(ec_state* st, size_t ndef) {
     ledger_free(st->ctx, e, cap * 8);
     ledger_free(st->ctx, s6, cap * 48);
     return r;
+  }
+  // the current list's values move along: a call that fails after growing
+  // these leaves the state's self terms and energies as they were
+  if (st->B && st->pd_cap > 0) {
+    const size_t k = st->pd_cap;
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(b, st->B, k * 8, hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipMemcpy(e, st->E, k * 8, hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipMemcpy(s6, st->S6, k * 48, hipMemcpyDeviceToDevice) != hipSuccess ||
+        hipMemcpy(rs, st->runsum, k * 8, hipMemcpyDeviceToDevice) != hipSuccess) {
+      ledger_free(st->ctx, b, cap * 8);
+      ledger_free(st->ctx, e, cap * 8);
+      ledger_free(st->ctx, s6, cap * 48);
+      ledger_free(st->ctx, rs, cap * 8);
+      return fail(EC_ERR_DEVICE, "device copy failed while growing the per-defect buffers");
+    }
   }
   ledger_free(st->ctx, st->B, st->pd_cap * 8);
   ledger_free(st->ctx, st->E, st->pd_cap * 8);
@@ -1426,8 +1449,14 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
       for (int i = 0; i < ndef; ++i) st->hcap[i] = box_volume(h[i]);
     }
     if (ndef == 0 || keep_self) return EC_OK;
-    ec_status q = self_terms_beside(st);
-    return q == EC_OK ? join_self(st, s) : q;
+    // self terms that cannot be set up now (an allocation of their windows or
+    // work lists failed) are left to the next energies call, which reports
+    // the failure if it recurs; the solve itself has all it needs
+    if (self_terms_beside(st) != EC_OK) {
+      st->B_valid = false;
+      return EC_OK;
+    }
+    return join_self(st, s);
   };
   // the stress of dislocation lines, if any, is added by the x inverse pass
   r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, ndef, st->spec, st->sig, st->add6, st->tilectr, beside, st->bg,
@@ -2282,7 +2311,8 @@ ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t njump, vo
   if (st->jxc_cap < nu) st->jx_ok = false;
   if ((r = st_grow(st, &st->jjumps, &st->jjumps_cap, 3 * nu)) != EC_OK ||
       (r = st_grow(st, &st->jxc, &st->jxc_cap, nu)) != EC_OK ||
-      (r = st_grow(st, &st->jdE, &st->jdE_cap, nu)) != EC_OK || (r = st_grow(st, &st->jt1, &st->jt1_cap, nu)) != EC_OK ||
+      (r = st_grow(st, &st->jdE, &st->jdE_cap, nu, st->jdE_ok, s)) != EC_OK ||  // the last energies stay if this fails
+      (r = st_grow(st, &st->jt1, &st->jt1_cap, nu)) != EC_OK ||
       (r = st_grow(st, &st->jwbeg, &st->jwbeg_cap, nu + 1)) != EC_OK ||
       (r = st_grow(st, &st->jwork, &st->jwork_cap, (size_t)cap)) != EC_OK ||
       (r = st_grow(st, &st->jpartial, &st->jpartial_cap, (size_t)cap)) != EC_OK)

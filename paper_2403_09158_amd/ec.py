@@ -167,26 +167,55 @@ def _stream_handle(stream):
 def _torch_hooks():
     import torch
 
+    # bound now: at interpreter exit the torch module's attributes may be gone
+    # before the last library buffers are freed
+    _alloc, _delete = torch.cuda.caching_allocator_alloc, torch.cuda.caching_allocator_delete
+
     def alloc(nbytes, stream, user):
         try:
-            return torch.cuda.caching_allocator_alloc(int(nbytes))
+            return _alloc(int(nbytes))
         except Exception:  # reported to the library as an allocation failure
             return None
 
     def free(ptr, stream, user):
-        torch.cuda.caching_allocator_delete(ptr)
+        try:
+            _delete(ptr)
+        except Exception:
+            pass
 
     return ALLOC_FN(alloc), FREE_FN(free)
+
+
+def _user_hooks(alloc, free):
+    """ctypes hooks around Python callables alloc(nbytes) -> int or None and
+    free(ptr)."""
+
+    def a(nbytes, stream, user):
+        try:
+            return alloc(int(nbytes))
+        except Exception:
+            return None
+
+    def f(ptr, stream, user):
+        free(ptr)
+
+    return ALLOC_FN(a), FREE_FN(f)
 
 
 class Context:
     """One device: allocator hooks, HBM admission ledger, cached Green windows."""
 
-    def __init__(self, device: int = 0, budget_bytes: int = 0, allocator: str = "torch"):
+    def __init__(self, device: int = 0, budget_bytes: int = 0, allocator: str = "torch", hooks=None):
+        """allocator: "torch" (its caching allocator), or "hip" (the
+        library's own hipMalloc); hooks: a pair of Python callables
+        (alloc(nbytes) -> device pointer or None, free(ptr)) used instead."""
         L = load()
         self._hooks = None
         af, ff = ALLOC_FN(), FREE_FN()
-        if allocator == "torch":
+        if hooks is not None:
+            self._hooks = _user_hooks(*hooks)
+            af, ff = self._hooks
+        elif allocator == "torch":
             import torch
 
             if not torch.cuda.is_available():
