@@ -643,7 +643,7 @@ void to_cube(const double* A, const double* t, double* out) {
 // Run direction of a loop for the self terms: the shortest lattice vector t in
 // the habit plane (m . t = 0) with components in [-2, 2] (first nonzero one
 // positive, ties in a fixed order); none found leaves t = 0 (no run path).
-void run_direction(const int32_t m[3], int32_t t[3]) {
+void run_direction_search(const int32_t m[3], int32_t t[3]) {
   t[0] = t[1] = t[2] = 0;
   for (int len2 = 1; len2 <= 12; ++len2)
     for (int a = -2; a <= 2; ++a)
@@ -657,6 +657,27 @@ void run_direction(const int32_t m[3], int32_t t[3]) {
           t[2] = c;
           return;
         }
+}
+
+// The search above, remembered per thread for the last few normals (a defect
+// list uses a handful of habit planes).
+void run_direction(const int32_t m[3], int32_t t[3]) {
+  struct Entry {
+    int32_t m[3], t[3];
+  };
+  thread_local Entry memo[8];
+  thread_local int used = 0, next = 0;
+  for (int i = 0; i < used; ++i)
+    if (memo[i].m[0] == m[0] && memo[i].m[1] == m[1] && memo[i].m[2] == m[2]) {
+      std::copy(memo[i].t, memo[i].t + 3, t);
+      return;
+    }
+  run_direction_search(m, t);
+  Entry& e = memo[next];
+  std::copy(m, m + 3, e.m);
+  std::copy(t, t + 3, e.t);
+  next = (next + 1) % 8;
+  used = std::max(used, next == 0 ? 8 : next);
 }
 
 bool quantise(const ec_problem& P, const ec_defect& rec, DevDefect& d, std::string& err) {
@@ -2017,14 +2038,14 @@ ec_status ec_solve_fields(ec_state* st, const ec_defect* defs, int32_t ndef, voi
   if ((r = pin_begin(st->pin_tab, std::max<size_t>(ndef, 1) * sizeof(DevDefect), &hp)) != EC_OK) return r;
   DevDefect* h = (DevDefect*)hp;
   {
-    // chunks of 128 defects on the context's workers; the first invalid
+    // chunks of 64 defects on the context's workers; the first invalid
     // defect in list order is reported
-    const int nch = (ndef + 127) / 128;
+    const int nch = (ndef + 63) / 64;
     std::vector<int> bad(nch, INT_MAX);
     std::vector<std::string> why(nch);
     st->ctx->pool->run(nch, [&](int c) {
       std::string e;
-      for (int i = c * 128; i < std::min(ndef, (c + 1) * 128); ++i)
+      for (int i = c * 64; i < std::min(ndef, (c + 1) * 64); ++i)
         if (!quantise(st->prob, defs[i], h[i], e)) {
           bad[c] = i;
           why[c] = e;
