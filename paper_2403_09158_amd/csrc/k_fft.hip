@@ -707,12 +707,14 @@ struct FusedPlan {
   static constexpr int I2 = NSTG == 3 ? R0 : 1;
 };
 
-// columns per tile: four, or two at N = 512 (where a four-column tile would
-// not fit) and with FP64 storage from N = 256 on (no prefetch there, so three
-// resident two-column workgroups per CU hide more latency than one wider one)
+// columns per tile: four, or two at N = 256 and 512 (at 512 a four-column
+// tile would not fit; at 256 three resident two-column workgroups per CU,
+// without the prefetch and register twiddles that would take their
+// registers, hide more latency than one four-column one: 0.28 against 0.33 ms
+// for the FP32 pass at 256^3) and with FP64 storage from N = 256 on
 template <int N, typename S>
 constexpr int zg_width() {
-  return (N >= 512 || (sizeof(S) == 8 && N >= 256)) ? 2 : 4;
+  return (N >= 512 || N == 256 || (sizeof(S) == 8 && N >= 256)) ? 2 : 4;
 }
 
 // one butterfly per thread in the widest-radix stage; a multiple of the 6 W
@@ -726,7 +728,7 @@ constexpr int zg_threads() {
 
 template <int N, typename S>
 constexpr bool zg_pipe() {
-  return sizeof(S) == 4 && !has_direct(plan_fused(N));
+  return sizeof(S) == 4 && N != 256 && !has_direct(plan_fused(N));
 }
 
 // LDS row swizzle: the low three bits of the z index are XORed with the next
@@ -810,9 +812,10 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   if (t < hi) fetch(t, threadIdx.x);
   __syncthreads();
   // two equal radices: the twiddled stage of either direction gives a thread
-  // the same butterfly in every tile, so its twiddles stay in registers (FP32
-  // storage; with FP64 storage the extra registers would cost occupancy)
-  constexpr bool TWREG = FP::NSTG == 2 && R0 == R1 && sizeof(S) == 4;
+  // the same butterfly in every tile, so its twiddles stay in registers (with
+  // the prefetch, FP32 storage; otherwise the extra registers would cost
+  // occupancy)
+  constexpr bool TWREG = FP::NSTG == 2 && R0 == R1 && PIPE;
   const auto twz = [&] {
     if constexpr (TWREG)
       return make_twreg<N, R1, R0, Map::Pencil, NF, T>(tw, threadIdx.x);
