@@ -763,8 +763,11 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
   constexpr int P = spec_pitch(N, sizeof(S) == 8);
   constexpr int SI = 6 * N * P;  // kz stride; all offsets fit 32 bits
   static_assert(6LL * N * N * P < (1LL << 31), "32-bit element offsets");
-  // the row swizzle permutes whole groups of eight rows
-  auto lds = [&](int f, int i) -> double2* { return &buf[__umul24(N % 8 == 0 ? zg_swz(i) : i, NF) + f]; };
+  // the row swizzle permutes whole groups of eight rows; it pays for
+  // four-column tiles, while with two columns its index arithmetic costs more
+  // than the bank conflicts it removes (0.27 against 0.28 ms at 256^3)
+  constexpr bool SWZ = N % 8 == 0 && W == 4;
+  auto lds = [&](int f, int i) -> double2* { return &buf[__umul24(SWZ ? zg_swz(i) : i, NF) + f]; };
   auto from_lds = [&](int f, int i) { return ld2(lds(f, i)); };
   auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
   // the spectrum and input planes of tile t, and its index within its job
