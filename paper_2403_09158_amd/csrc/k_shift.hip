@@ -16,8 +16,8 @@
 // conj(sigma_hat - phi_d' sigma_hat_0).
 //
 // One pass over the three spectra serves up to TYPE_NP positions; each block
-// leaves one FP64 partial sum per position and a single thread per position
-// adds the partials in block order, so results do not depend on scheduling.
+// leaves one FP64 partial sum per position and the partials are added in a
+// fixed order, so results do not depend on scheduling.
 #include "ec_internal.h"
 
 namespace ec {
@@ -39,7 +39,9 @@ __device__ __forceinline__ double2 phase(const double2* __restrict__ tab, const 
   const double2 a = t[kx], b = t[n + ky], c = t[2 * n + kz];
   double2 m = cmul2(cmul2(a, b), c);
   if (nx || ny || nz) {
-    const double2 ap = nx ? nyq[3 * p] : a, bp = ny ? nyq[3 * p + 1] : b, cp = nz ? nyq[3 * p + 2] : c;
+    // values loaded first and then chosen, so that no local needs an address
+    const double2 na = nyq[3 * p], nb = nyq[3 * p + 1], nc = nyq[3 * p + 2];
+    const double2 ap = nx ? na : a, bp = ny ? nb : b, cp = nz ? nc : c;
     const double2 mp = cmul2(cmul2(ap, bp), cp);
     m = make_double2(0.5 * (m.x + mp.x), 0.5 * (m.y + mp.y));
   }
@@ -87,17 +89,17 @@ __global__ __launch_bounds__(TT) void k_type_energy(const typename Cplx<S>::T* _
     const double wx = (kx == 0 || nx) ? 1.0 : 2.0;
 #pragma unroll
     for (int p = 0; p < TYPE_NP; ++p) {
-      if (p >= np) break;
-      const double2 f = phase(tab, nyq, p, n, kx, ky, kz, nx, ny, nz);
-      acc[p] += wx * (f.x * A.x - f.y * A.y);
+      if (p < np) {
+        const double2 f = phase(tab, nyq, p, n, kx, ky, kz, nx, ny, nz);
+        acc[p] += wx * (f.x * A.x - f.y * A.y);
+      }
     }
   }
-  // block sums by a fixed tree
-#pragma unroll 1
-  for (int p = 0; p < np; ++p) {
-    red[threadIdx.x] = acc[0];
+  // block sums by a fixed tree (np is the same for every thread)
 #pragma unroll
-    for (int q = 0; q + 1 < TYPE_NP; ++q) acc[q] = acc[q + 1];
+  for (int p = 0; p < TYPE_NP; ++p) {
+    if (p >= np) break;
+    red[threadIdx.x] = acc[p];
     __syncthreads();
     for (int w = TT / 2; w > 0; w >>= 1) {
       if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -108,19 +110,30 @@ __global__ __launch_bounds__(TT) void k_type_energy(const typename Cplx<S>::T* _
   }
 }
 
-// E_p = scale * sum of the grid partials of position p, added in block order
-// (Neumaier).
-__global__ void k_type_finish(const double* __restrict__ partial, int grid, int np, double scale,
-                              double* __restrict__ E) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
+// E_p = scale * sum of the grid partials of position p: one workgroup per
+// position, strided Neumaier sums per thread, then a fixed tree.
+__global__ __launch_bounds__(256) void k_type_finish(const double* __restrict__ partial, int grid, double scale,
+                                                     double* __restrict__ E) {
+  __shared__ double rs[256], rc[256];
+  const int p = blockIdx.x;
   double s = 0.0, c = 0.0;
-  for (int b = 0; b < grid; ++b) {
+  for (int b = threadIdx.x; b < grid; b += 256) {
     const double v = partial[(size_t)p * grid + b], t = s + v;
     c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
     s = t;
   }
-  E[p] = scale * (s + c);
+  rs[threadIdx.x] = s;
+  rc[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double a = rs[threadIdx.x], v = rs[threadIdx.x + w], t = a + v;
+      rc[threadIdx.x] += rc[threadIdx.x + w] + (fabs(a) >= fabs(v) ? (a - t) + v : (v - t) + a);
+      rs[threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) E[p] = scale * (rs[0] + rc[0]);
 }
 
 }  // namespace
@@ -141,7 +154,7 @@ hipError_t launch_type_energies(bool fp64, const void* sig, const void* te, cons
   else
     hipLaunchKernelGGL(k_type_energy<float>, dim3(grid), dim3(TT), 0, s, (const float2*)sig, (const float2*)te,
                        (const float2*)ts, g.n, g.P, tab, nyq, np, excl ? 1 : 0, partial);
-  hipLaunchKernelGGL(k_type_finish, dim3(1), dim3(64), 0, s, partial, grid, np, scale, E);
+  hipLaunchKernelGGL(k_type_finish, dim3(np), dim3(256), 0, s, partial, grid, scale, E);
   return hipGetLastError();
 }
 
