@@ -94,17 +94,29 @@ def cpu_baseline(prob, defs, green_planes=16, self_sample=100):
     T["raster"] = time.perf_counter() - t
     t = time.perf_counter()
     tau = np.einsum("ijkl,kl...->ij...", C, es)
+    t_f = time.perf_counter()
     th = solve.fft3(tau)
-    del tau
+    fft_many = time.perf_counter() - t_f
     T["forward"] = time.perf_counter() - t
+    # the transforms are the only multi-threaded stages: timed again on one worker
+    T1 = {}
+    t = time.perf_counter()
+    solve.fft3(tau, workers=1)
+    T1["forward_fft"] = time.perf_counter() - t
+    del tau
     planes = list(range(0, n, n // green_planes))[:green_planes]
     t = time.perf_counter()
     eh = solve.apply_green(C, prob.L, th, es.sum(axis=(-3, -2, -1)), prob.bc, planes=planes)
     T["green"] = (time.perf_counter() - t) * n / len(planes)
     del th
     t = time.perf_counter()
-    eps = solve.fft3(eh, inverse=True).real
-    del eh
+    solve.fft3(eh, inverse=True, workers=1)
+    T1["inverse_fft"] = time.perf_counter() - t
+    t = time.perf_counter()
+    eps_c = solve.fft3(eh, inverse=True)
+    fft_many += time.perf_counter() - t
+    eps = eps_c.real
+    del eh, eps_c
     sig = np.einsum("ijkl,kl...->ij...", C, eps - es)
     T["inverse_stress"] = time.perf_counter() - t
     del eps
@@ -123,10 +135,26 @@ def cpu_baseline(prob, defs, green_planes=16, self_sample=100):
     T["self_terms"] = (time.perf_counter() - t) * len(fps) / len(idx)
     del sig, S
     total = sum(T.values())
+    # one worker: the transform time of the forward and inverse stages replaced
+    # by their single-worker time (the rest of the oracle runs on one thread)
+    t_fft_many = T1["forward_fft"] + T1["inverse_fft"]
+    total_1 = total - fft_many + t_fft_many
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": 1.0 / total,
         "unit": "solves/s",
         "cores": int(os.environ.get("ORACLE_FFT_WORKERS", "0")) or (os.cpu_count() or 1),
+        "cpu_model": cpu,
+        "one_worker": {"value": 1.0 / total_1, "fft_s": {k: round(v, 2) for k, v in T1.items()},
+                       "fft_s_all_workers": round(fft_many, 2)},
         "kind": "oracle",
         "sample": (
             f"mixed_256 workload at 256^3: full rasterisation, FFTs and footprint sums; Green step on "
