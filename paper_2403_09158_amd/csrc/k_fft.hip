@@ -707,14 +707,23 @@ struct FusedPlan {
   static constexpr int I2 = NSTG == 3 ? R0 : 1;
 };
 
-// columns per tile: four, or two at N = 256 and 512 (at 512 a four-column
-// tile would not fit; at 256 three resident two-column workgroups per CU,
-// without the prefetch and register twiddles that would take their
-// registers, hide more latency than one four-column one: 0.28 against 0.33 ms
-// for the FP32 pass at 256^3) and with FP64 storage from N = 256 on
+// Two-column tiles without the operand prefetch and register twiddles (which
+// would take their registers) for the even lengths 64 .. 256: three or more
+// resident workgroups per CU hide more latency than one four-column one with
+// the prefetch (FP32 pass at 256^3 0.33 -> 0.27 ms, 240^3 0.33 -> 0.27, 160^3
+// 0.098 -> 0.077, 128^3 0.070 -> 0.042, 64^3 0.030 -> 0.013).  At 512 the
+// two-column tile keeps the prefetch (without it 3.6 -> 4.2 ms), and the odd
+// 129 keeps four columns (two: 0.83 -> 1.03 ms per solve).
+template <int N>
+constexpr bool zg_narrow() {
+  return N >= 64 && N <= 256 && !has_direct(plan_fused(N));
+}
+
+// columns per tile: four, or two for the lengths above, at N = 512 (where a
+// four-column tile would not fit) and with FP64 storage from N = 256 on
 template <int N, typename S>
 constexpr int zg_width() {
-  return (N >= 512 || N == 256 || (sizeof(S) == 8 && N >= 256)) ? 2 : 4;
+  return (N >= 512 || zg_narrow<N>() || (sizeof(S) == 8 && N >= 256)) ? 2 : 4;
 }
 
 // one butterfly per thread in the widest-radix stage; a multiple of the 6 W
@@ -728,7 +737,7 @@ constexpr int zg_threads() {
 
 template <int N, typename S>
 constexpr bool zg_pipe() {
-  return sizeof(S) == 4 && N != 256 && !has_direct(plan_fused(N));
+  return sizeof(S) == 4 && !zg_narrow<N>() && !has_direct(plan_fused(N));
 }
 
 // LDS row swizzle: the low three bits of the z index are XORed with the next
