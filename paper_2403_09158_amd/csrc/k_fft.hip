@@ -658,9 +658,14 @@ __global__ __launch_bounds__((pencil_threads<N, LT>())) void k_pencil(typename C
     C2* const colp = column(t, tid % NF, valid, pt);
     // a lane past the last column transforms whatever its loads returned
     // (finite spectrum values) and stores nothing
+    // without the prefetch every operand is loaded (a row outside the input
+    // range reads row in_lo, a cache hit) and zeroed afterwards, so that the
+    // loads are issued together rather than one branch at a time
     auto load0 = [&](int, int i, int slot) -> double2 {
-      if (PRUNE && !(valid && in_range_of(pt, i))) return make_double2(0.0, 0.0);
-      return PIPE ? ld2(&nxt[slot]) : ld2(colp + i * SI);
+      const bool in = !PRUNE || (valid && in_range_of(pt, i));
+      if constexpr (PIPE) return in ? ld2(&nxt[slot]) : make_double2(0.0, 0.0);
+      const double2 v = ld2(colp + (in ? i : pt.in_lo) * SI);
+      return in ? v : make_double2(0.0, 0.0);
     };
     auto store_last = [&](int, int i, double2 v) {
       if (valid) st2(colp + i * SI, v);
@@ -853,9 +858,14 @@ __global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S
     // a lane past the last column transforms whatever its loads returned
     // (finite spectrum values), takes no part in the Green step and stores
     // nothing
+    // without the prefetch every operand is loaded (a plane outside the input
+    // range reads plane in_lo, a cache hit) and zeroed afterwards, so that the
+    // loads are issued together rather than one branch at a time
     auto load0 = [&](int, int i, int slot) -> double2 {
-      if (PRUNE && !(valid && in_z_of(pt, i))) return make_double2(0.0, 0.0);
-      return PIPE ? ld2(&nxt[slot]) : ld2(col0 + i * SI);
+      const bool in = !PRUNE || (valid && in_z_of(pt, i));
+      if constexpr (PIPE) return in ? ld2(&nxt[slot]) : make_double2(0.0, 0.0);
+      const double2 v = ld2(col0 + (in ? i : pt.in_lo) * SI);
+      return in ? v : make_double2(0.0, 0.0);
     };
     stage<N, R0, 1, false, Map::Pencil, NF, T>(tw, load0, to_lds, false, tid);
     if (tn < hi) fetch(tn, tid);
