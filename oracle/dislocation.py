@@ -1,4 +1,4 @@
-"""Straight dislocation lines by field dislocation mechanics (oracle; test
+"""Dislocation lines and loops by field dislocation mechanics (oracle; test
 infrastructure only).
 
 Sec. 3.1, for dislocations that do not close into loops: the plastic
@@ -103,3 +103,85 @@ def background_energies(problem, fps, Es, sig_d) -> np.ndarray:
     h3c = (problem.L / problem.n) ** 3 * GPA_NM3_EV
     sf = sig_d.reshape(3, 3, -1)
     return np.array([-h3c * float(np.einsum("ij,ijx->", E, sf[:, :, ids])) for ids, E in zip(fps, Es)])
+
+
+# --------------------------------------------------------------- closed paths
+#
+# Sec. 3.1 for dislocations in any direction: a path is a closed polyline, a
+# loop (the last vertex joined to the first) or a line through the periodic
+# cell (the last vertex joined to the first shifted by a lattice vector of the
+# cell).  Readings: (i) every segment is cut into the fewest equal pieces no
+# longer than h, and each piece's Burgers vector density b (x) dl / h^3 is
+# spread to the eight grid points around its midpoint with trilinear weights
+# (the paper spreads every subsegment to the eight surrounding grid points);
+# for a line along a cell axis this is the straight-line rule above.  (ii) With
+# alpha = b (x) t, t along the vertex order, and curl U^p = -alpha, a loop's
+# slipped area carries U^p = -b (x) n with n the right-hand normal of the vertex
+# order (a loop running counterclockwise about n has the field of the slab
+# eigenstrain -sym(b (x) n) of the defect records); the compatible part is the
+# mean plastic distortion of the slipped areas, -b (x) A / V with
+# A = 1/2 sum_j v_j x v_{j+1} the vector area of a loop (lines through the cell
+# have none): it adds to U_hat at xi = 0 and only changes the mean stress under
+# the zero-mean-strain condition.
+
+
+def path_segments(path):
+    """(start, vector) of every segment of a path (verts (k, 3), shift (3,))."""
+    verts, shift = np.asarray(path[0], dtype=np.float64), np.asarray(path[1], dtype=np.float64)
+    k = len(verts)
+    out = []
+    for j in range(k):
+        a = verts[j]
+        b = verts[j + 1] if j + 1 < k else verts[0] + shift
+        out.append((a, b - a))
+    return out
+
+
+def path_nye_field(problem, paths) -> np.ndarray:
+    """alpha_ij(x) (3, 3, n, n, n) [z, y, x] of closed paths (verts, shift, b)."""
+    n, h = problem.n, problem.L / problem.n
+    alpha = np.zeros((3, 3, n, n, n))
+    for verts, shift, b in paths:
+        b = np.asarray(b, dtype=np.float64)
+        for a, d in path_segments((verts, shift)):
+            m = max(1, int(np.ceil(np.linalg.norm(d) / h - 1e-12)))
+            dl = d / m
+            for q in range(m):
+                mid = a + (q + 0.5) * dl
+                u = mid / h - 0.5  # grid-index coordinates
+                f = np.floor(u).astype(np.int64)
+                for cz in (0, 1):
+                    for cy in (0, 1):
+                        for cx in (0, 1):
+                            g = f + np.array([cx, cy, cz])
+                            w = np.prod(1.0 - np.abs(u - g))
+                            if w == 0.0:
+                                continue
+                            gx, gy, gz = (int(v) % n for v in g)
+                            alpha[:, :, gz, gy, gx] += np.outer(b, dl) * (w / h**3)
+    return alpha
+
+
+def path_mean_distortion(problem, paths) -> np.ndarray:
+    """<U^p> = -sum over loops of b (x) A / V (lines through the cell: none)."""
+    V = problem.L**3
+    U = np.zeros((3, 3))
+    for verts, shift, b in paths:
+        if np.any(np.asarray(shift) != 0.0):
+            continue
+        v = np.asarray(verts, dtype=np.float64)
+        A = 0.5 * sum(np.cross(v[j], v[(j + 1) % len(v)]) for j in range(len(v)))
+        U -= np.outer(b, A) / V
+    return U
+
+
+def path_stress(problem, paths, bc=None) -> np.ndarray:
+    """sigma (3, 3, n, n, n) of the paths alone: sym(U^p) solved as an
+    eigenstrain, U^p from the Nye tensor at xi != 0 and the mean distortion at
+    xi = 0."""
+    bc = problem.bc if bc is None else bc
+    U = plastic_distortion(problem, path_nye_field(problem, paths))
+    U = U + path_mean_distortion(problem, paths)[:, :, None, None, None]
+    es = 0.5 * (U + U.transpose(1, 0, 2, 3, 4))
+    _, sig, _ = solve_field(stiffness_of(problem), problem.L, es, bc)
+    return sig
