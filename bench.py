@@ -387,6 +387,38 @@ def dislocation_block(steps=10, warmup=3):
     st.close()
     ctx.close()
     out["loop_profile"] = {"x_nm_from_line": xs, "E_eV": Es, "E_min_eV": min(Es), "E_max_eV": max(Es)}
+    # dislocation loops and a line in a general direction by field dislocation
+    # mechanics (ec_set_dislocation_paths): 16 hexagonal 1/2<111> loops of
+    # radius 2 nm in their (111) planes and one mixed line along [1 1 0] through
+    # the cell, on mixed_256 (FP32)
+    prob, defs = inputs.mixed_256(prec=1)
+    rng = np.random.default_rng(7)
+    L = prob.L
+    paths = []
+    for k in range(16):
+        s = np.array([1.0, 1.0, 1.0]) * rng.choice([-1.0, 1.0], 3)
+        nrm = s / np.sqrt(3.0)
+        e1 = np.cross(nrm, [1.0, 0.0, 0.0] if abs(nrm[0]) < 0.9 else [0.0, 1.0, 0.0])
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(nrm, e1)
+        ang = np.arange(6) * np.pi / 3.0
+        c = rng.uniform(0.0, L, 3)
+        paths.append((c + 2.0 * (np.cos(ang)[:, None] * e1 + np.sin(ang)[:, None] * e2), np.zeros(3),
+                      0.5 * inputs.A_FE * s))
+    paths.append((np.array([[1.3, 7.9, 40.6]]), np.array([L, L, 0.0]), np.array([0.12, 0.0, 0.21])))
+    ctx = ec.Context(0)
+    st = ec.State(ctx, prob)
+    st.solve(defs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.set_dislocation_paths(paths)
+    torch.cuda.synchronize()
+    t_paths = time.perf_counter() - t0
+    dt, _, _ = timed_steps(st, defs, steps, warmup, False)
+    st.close()
+    ctx.close()
+    out["paths"] = {"workload": "16 hexagonal 1/2<111> loops (R 2 nm) and a mixed line along [1 1 0], mixed_256 FP32",
+                    "set_paths_ms": round(t_paths * 1e3, 3), "fp32_ms_per_step_with_paths": round(dt / steps * 1e3, 4)}
     return out
 
 

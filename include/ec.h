@@ -309,6 +309,36 @@ typedef struct {
  * axis in {0, 1, 2} and sense +-1 (EC_ERR_ARG otherwise). */
 EC_API ec_status ec_set_dislocations(ec_state* st, const ec_line* lines, int32_t nlines, void* hip_stream);
 
+/* A dislocation path (56 bytes): a closed polyline through vertices
+ * verts[first .. first + count) (3 doubles each, nm, cell coordinates), the last
+ * joined to the first shifted by `shift` (nm): zero for a loop (count >= 3), a
+ * nonzero lattice vector of the cell (integer multiples of L per axis, |m| <= 64)
+ * for a line through the periodic cell in any direction (count >= 1).  b is the
+ * Burgers vector (nm); the line sense t runs along the vertex order. */
+typedef struct {
+  int32_t first;
+  int32_t count;
+  double shift[3];
+  double b[3];
+} ec_path;
+
+/* Set the state's dislocation paths (npaths in [0, 256]; 0 removes them):
+ * field dislocation mechanics in any direction (Sec. 3.1).  Every segment is
+ * cut into the fewest equal pieces no longer than h, and each piece's Nye
+ * tensor b (x) dl / h^3 is spread to the eight grid points around its midpoint
+ * with trilinear weights; U_hat_ij = -i xi_k / xi^2 e_jkl alpha_hat_il at
+ * xi != 0 (curl U^p = -alpha), and at xi = 0 the loops' compatible part, the
+ * mean plastic distortion -b (x) A / V with A = 1/2 sum_j v_j x v_{j+1} the
+ * vector area of a loop (a loop counterclockwise about n has the slipped-area
+ * distortion -b (x) n; it changes the mean stress only under
+ * EC_MEAN_STRAIN_ZERO).  sym(U^p) is solved as an eigenstrain with the state's
+ * stiffness and frame, and the stress is kept as a background added to the
+ * resident stress of this and every later solve, as for ec_set_dislocations
+ * (both kinds may be present).  At most 2^20 pieces in all; finite values,
+ * |b| > 0 (EC_ERR_ARG otherwise).  Synchronises the stream. */
+EC_API ec_status ec_set_dislocation_paths(ec_state* st, const ec_path* paths, int32_t npaths, const double* verts,
+                                          int32_t nverts, void* hip_stream);
+
 /* ---- dipole-tensor approximation (Sec. 2.1) --------------------------------- */
 
 /* Interaction energy of every defect in the dipole approximation (eV): the

@@ -338,6 +338,11 @@ struct ec_state {
   size_t bgspec_cap = 0;
   DevLine* dlines = nullptr;
   size_t dlines_cap = 0;
+  // dislocation paths in any direction: their stress ([n^3][6] FP64), added to
+  // the resident stress of every solve while bg3_on
+  double* bg3 = nullptr;
+  size_t bg3_cap = 0;
+  bool bg3_on = false;
   double* frm = nullptr;          // its device form (FRAME_LEN doubles), null for cube axes
   // self-term work list (built on the device)
   SelfWork* work = nullptr;
@@ -441,6 +446,15 @@ void ledger_free(ec_ctx* c, void* p, size_t bytes) {
   raw_free(c, p);
   release(c, bytes);
 }
+
+// A temporary device buffer charged to the ledger, freed when it goes out of
+// scope (callers synchronise before that when kernels may still use it).
+struct Tmp {
+  ec_ctx* c;
+  void* p = nullptr;
+  size_t b = 0;
+  ~Tmp() { ledger_free(c, p, b); }
+};
 
 }  // namespace
 
@@ -899,7 +913,8 @@ ec_status join_self(ec_state* st, hipStream_t s);
 // are enqueued and before the z pass is.
 ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs,
                    int ndef, void* spec, double* sig, const double* add6, uint32_t* ctr,
-                   const std::function<ec_status()>& between = {}, const double* bg = nullptr, int bg_mask = 0) {
+                   const std::function<ec_status()>& between = {}, const double* bg = nullptr, int bg_mask = 0,
+                   const double* bg3 = nullptr) {
   const Prune full{0, st->n, 0, st->n};
   const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
   SpecGeom g{st->n, 0};
@@ -914,6 +929,7 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
   LAUNCH(st, s, PF_Z, 2 * sb, launch_z_green(fp64, spec, g, st->C, full, st->tw, ctr ? ctr + 8 : nullptr, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, spec, g, full, st->tw, ctr ? ctr + 16 : nullptr, s));
   LAUNCH(st, s, PF_XI, sb + fb, launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s, bg, bg_mask));
+  if (bg3) LAUNCH(st, s, PF_OTHER, 2 * fb, launch_bg3_add(sig, bg3, st->n3, 1.0, s));
   return EC_OK;
 }
 
@@ -1481,7 +1497,7 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
   };
   // the stress of dislocation lines, if any, is added by the x inverse pass
   r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, ndef, st->spec, st->sig, st->add6, st->tilectr, beside, st->bg,
-               st->bg_mask);
+               st->bg_mask, st->bg3_on ? st->bg3 : nullptr);
   if (r != EC_OK) return r;
   st->solved = true;
   return EC_OK;
@@ -1989,6 +2005,7 @@ void ec_state_destroy(ec_state* st) {
   ledger_free(c, st->bg, st->bg_cap * 8);
   ledger_free(c, st->bgspec, st->bgspec_cap * 16);
   ledger_free(c, st->dlines, st->dlines_cap * sizeof(DevLine));
+  ledger_free(c, st->bg3, st->bg3_cap * 8);
   ledger_free(c, st->jpartial, st->jpartial_cap * 8);
   ledger_free(c, st->jsel, st->jsel_cap * 8);
   ledger_free(c, st->jnu, st->jnu_cap * 8);
@@ -2540,6 +2557,116 @@ ec_status ec_set_dislocations(ec_state* st, const ec_line* lines, int32_t nlines
   return EC_OK;
 }
 
+ec_status ec_set_dislocation_paths(ec_state* st, const ec_path* paths, int32_t npaths, const double* verts,
+                                   int32_t nverts, void* stream) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  if (npaths < 0 || npaths > 256) return fail(EC_ERR_ARG, "npaths %d outside [0, 256]", npaths);
+  if (npaths > 0 && (!paths || !verts || nverts <= 0)) return fail(EC_ERR_ARG, "NULL argument");
+  const int n = st->n;
+  const double L = st->prob.L, h = L / n, h3 = h * h * h;
+  std::vector<DevPiece> pieces;
+  double Ubar[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // mean plastic distortion of the loops
+  const size_t max_pieces = (size_t)1 << 20;
+  for (int k = 0; k < npaths; ++k) {
+    const ec_path& P = paths[k];
+    if (P.count < 1 || P.first < 0 || (int64_t)P.first + P.count > nverts)
+      return fail(EC_ERR_ARG, "path %d: vertices [%d, %d) outside the %d given", k, P.first, P.first + P.count, nverts);
+    bool fin = true, loop = true;
+    double bb = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      fin &= std::isfinite(P.b[a]) && std::isfinite(P.shift[a]);
+      bb += P.b[a] * P.b[a];
+      const double m = P.shift[a] / L;
+      if (!(std::fabs(m - std::nearbyint(m)) < 1e-9) || std::fabs(m) > 64.0)
+        return fail(EC_ERR_ARG, "path %d: shift is not a lattice vector of the cell", k);
+      loop &= P.shift[a] == 0.0 || std::nearbyint(m) == 0.0;
+    }
+    if (!fin) return fail(EC_ERR_ARG, "path %d: non-finite value", k);
+    if (!(bb > 0.0)) return fail(EC_ERR_ARG, "path %d: zero Burgers vector", k);
+    if (loop && P.count < 3) return fail(EC_ERR_ARG, "path %d: a loop needs at least three vertices", k);
+    const double* v = verts + 3 * (size_t)P.first;
+    for (int j = 0; j < 3 * P.count; ++j)
+      if (!std::isfinite(v[j]) || std::fabs(v[j]) > 1e6 * L) return fail(EC_ERR_ARG, "path %d: vertex out of range", k);
+    double A[3] = {0, 0, 0};
+    for (int j = 0; j < P.count; ++j) {
+      double a[3], d[3];
+      for (int c = 0; c < 3; ++c) {
+        a[c] = v[3 * j + c];
+        const double e = j + 1 < P.count ? v[3 * (j + 1) + c] : v[c] + (loop ? 0.0 : P.shift[c]);
+        d[c] = e - a[c];
+      }
+      if (loop) {  // vector area 1/2 sum v_j x v_{j+1}
+        const double* w = j + 1 < P.count ? v + 3 * (j + 1) : v;
+        A[0] += 0.5 * (a[1] * w[2] - a[2] * w[1]);
+        A[1] += 0.5 * (a[2] * w[0] - a[0] * w[2]);
+        A[2] += 0.5 * (a[0] * w[1] - a[1] * w[0]);
+      }
+      const double len = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      const int m = std::max(1, (int)std::ceil(len / h - 1e-12));
+      if (pieces.size() + (size_t)m > max_pieces) return fail(EC_ERR_ARG, "paths cut into more than 2^20 pieces");
+      for (int q = 0; q < m; ++q) {
+        DevPiece pc{};
+        for (int c = 0; c < 3; ++c) {
+          const double mid = a[c] + (q + 0.5) * d[c] / m;
+          const double u = mid / h - 0.5;
+          const double f = std::floor(u);
+          pc.fr[c] = u - f;
+          pc.f[c] = (int32_t)(((int64_t)f % n + n) % n);
+        }
+        for (int i = 0; i < 3; ++i)
+          for (int l = 0; l < 3; ++l) pc.M[3 * i + l] = P.b[i] * (d[l] / m) / h3;
+        pieces.push_back(pc);
+      }
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int l = 0; l < 3; ++l) Ubar[3 * i + l] -= P.b[i] * A[l] / (L * L * L);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  ec_status r;
+  if (pieces.empty()) {  // remove the paths
+    if (st->bg3_on) {
+      if ((r = join_self(st, s)) != EC_OK) return r;
+      if (st->solved) LAUNCH(st, s, PF_OTHER, 0, launch_bg3_add(st->sig, st->bg3, st->n3, -1.0, s));
+      st->bg3_on = false;
+      st->jdE_ok = false;
+    }
+    return EC_OK;
+  }
+  const size_t need = (size_t)st->n3 * 6;
+  size_t cap = st->bg3_cap;
+  if ((r = st_grow(st, &st->bg3, &cap, need, st->bg3_on, s)) != EC_OK) return r;
+  st->bg3_cap = cap;
+  Tmp tp{st->ctx}, tm{st->ctx};
+  if ((r = ledger_alloc(st->ctx, tp.b = pieces.size() * sizeof(DevPiece), &tp.p)) != EC_OK) return r;
+  if ((r = ledger_alloc(st->ctx, tm.b = 64, &tm.p)) != EC_OK) return r;
+  // mean stress of the compatible part (zero-mean-strain condition only)
+  double mean6[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (st->prob.bc == EC_MEAN_STRAIN_ZERO) {
+    const double e6[6] = {Ubar[0], Ubar[4], Ubar[8], 0.5 * (Ubar[5] + Ubar[7]), 0.5 * (Ubar[2] + Ubar[6]),
+                          0.5 * (Ubar[1] + Ubar[3])};
+    neg_C_dot(st, e6, mean6);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(tp.p, pieces.data(), tp.b, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(tm.p, mean6, 64, hipMemcpyHostToDevice));
+  if ((r = join_self(st, s)) != EC_OK) return r;
+  // take the old paths' stress out of the resident field, put the new one in
+  if (st->solved && st->bg3_on) LAUNCH(st, s, PF_OTHER, 0, launch_bg3_add(st->sig, st->bg3, st->n3, -1.0, s));
+  st->bg3_on = false;
+  const bool fp64 = st->fp64;
+  const Prune full{0, n, 0, n};
+  LAUNCH(st, s, PF_OTHER, 0,
+         launch_path_spectrum(fp64, (const DevPiece*)tp.p, (int)pieces.size(), st->g, L, st->C, st->tw, st->spec, s));
+  LAUNCH(st, s, PF_Z, 0, launch_pencil(fp64, true, 2, st->spec, st->g, full, st->tw, nullptr, s));
+  LAUNCH(st, s, PF_Y, 0, launch_pencil(fp64, true, 1, st->spec, st->g, full, st->tw, nullptr, s));
+  LAUNCH(st, s, PF_XI, 0, launch_x_inverse(fp64, false, st->spec, st->bg3, st->g, (const double*)tm.p, st->tw, s));
+  st->bg3_on = true;
+  if (st->solved) LAUNCH(st, s, PF_OTHER, 0, launch_bg3_add(st->sig, st->bg3, st->n3, 1.0, s));
+  st->jdE_ok = false;
+  HIPCHK(hipStreamSynchronize(s));  // the piece table is freed on return
+  return EC_OK;
+}
+
 ec_status ec_dipole_energies(ec_state* st, void* stream, double* E_out, int32_t on_device) {
   if (!st) return fail(EC_ERR_ARG, "state is NULL");
   if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
@@ -2612,13 +2739,6 @@ ec_status download_spec(ec_state* st, const void* dev, double* host) {
         }
   return EC_OK;
 }
-
-struct Tmp {
-  ec_ctx* c;
-  void* p = nullptr;
-  size_t b = 0;
-  ~Tmp() { ledger_free(c, p, b); }
-};
 
 }  // namespace
 

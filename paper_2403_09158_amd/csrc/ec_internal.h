@@ -252,6 +252,17 @@ struct DevLine {
   double t[3];
 };
 
+// One piece of a dislocation path (a segment cut into pieces no longer than h):
+// the grid cell holding its midpoint (f, integer grid indices reduced mod n),
+// the midpoint's offset in that cell (fr in [0, 1) per axis) and the Nye
+// tensor it carries, M_il = b_i dl_l / h^3.
+struct DevPiece {
+  int32_t f[3];
+  int32_t pad_;
+  double fr[3];
+  double M[9];
+};
+
 // Profiling families (see ec_profile_read).
 enum ProfFam { PF_RASTER = 0, PF_XF = 1, PF_Y = 2, PF_Z = 3, PF_XI = 4, PF_REDUCE = 5, PF_SELF = 6, PF_OTHER = 7 };
 
@@ -369,6 +380,12 @@ hipError_t launch_disl_plane(const DevLine* lines, int nl, int axis, int n, doub
 // sig (voxel-major [n^3][6]) += sgn * the planes of the axes in mask
 // (planes: three [n^2][6] blocks).
 hipError_t launch_bg_add(double* sig, const double* planes, int mask, int n, double sgn, hipStream_t s);
+// sigma_hat of dislocation pieces (Sec. 3.1) over the whole half spectrum
+// (xi = 0 left at zero), written into spec in the state's storage precision.
+hipError_t launch_path_spectrum(bool fp64, const DevPiece* pieces, int np, SpecGeom g, double L, Cubic C,
+                                const double2* tw, void* spec, hipStream_t s);
+// sig[v][c] += sgn * bg3[v][c] over n^3 voxels (a 3-D background stress).
+hipError_t launch_bg3_add(double* sig, const double* bg3, int64_t n3, double sgn, hipStream_t s);
 hipError_t launch_green(bool fp64, void* spec, SpecGeom g, Cubic C, hipStream_t s);
 hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, uint32_t* ctr,
                           hipStream_t s);

@@ -1457,6 +1457,138 @@ __global__ __launch_bounds__(256) void k_bg_add(double* __restrict__ sig, const 
   for (int c = 0; c < 6; ++c) q[c] += sgn * add[c];
 }
 
+// Dislocation paths in any direction (Sec. 3.1): per bin of the half spectrum
+// the Nye tensor alpha_hat_il = sum over pieces of M_il rho_hat, with the
+// trilinear spread of a piece separable per axis,
+//   rho_hat = prod_a e^{-2 pi i k_a f_a / n} ((1 - fr_a) + fr_a e^{-2 pi i k_a / n}),
+// the exponents reduced exactly (k_a f_a mod n) and read from the twiddle
+// table; then U_hat_ij = -i e_jkl xi_k alpha_hat_il / |xi|^2 (at an even n's
+// Nyquist bins the mean over the all -n/2 and all +n/2 representatives),
+// eps*_hat = sym(U_hat) and the Green step.  Pieces are staged in LDS in
+// chunks; one thread per bin.
+constexpr int PATH_CHUNK = 128;
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_path_spectrum(const DevPiece* __restrict__ pieces, int np, int n, int P,
+                                                       double L, Cubic C, const double2* __restrict__ tw,
+                                                       typename Cplx<S>::T* __restrict__ spec) {
+  __shared__ DevPiece sp[PATH_CHUNK];
+  const int NH = n / 2 + 1;
+  const int64_t bins = (int64_t)n * n * NH;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = b < bins;
+  const int kx = live ? (int)(b % NH) : 0;
+  const int64_t r = live ? b / NH : 0;
+  const int ky = (int)(r % n), kz = (int)(r / n);
+  const int k[3] = {kx, ky, kz};
+  double2 e1[3];  // e^{-2 pi i k_a / n}
+#pragma unroll
+  for (int a = 0; a < 3; ++a) e1[a] = tw[k[a]];
+  double2 al[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) al[c] = make_double2(0.0, 0.0);
+  for (int p0 = 0; p0 < np; p0 += PATH_CHUNK) {
+    const int m = min(PATH_CHUNK, np - p0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += blockDim.x) sp[i] = pieces[p0 + i];
+    __syncthreads();
+    if (!live) continue;
+    for (int i = 0; i < m; ++i) {
+      const DevPiece& q = sp[i];
+      double2 rho = make_double2(1.0, 0.0);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double2 ph = tw[(k[a] * q.f[a]) % n];
+        const double w = q.fr[a];
+        const double2 f = make_double2((1.0 - w) + w * e1[a].x, w * e1[a].y);
+        const double2 t = make_double2(ph.x * f.x - ph.y * f.y, ph.x * f.y + ph.y * f.x);
+        rho = make_double2(rho.x * t.x - rho.y * t.y, rho.x * t.y + rho.y * t.x);
+      }
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        al[c].x += q.M[c] * rho.x;
+        al[c].y += q.M[c] * rho.y;
+      }
+    }
+  }
+  if (!live) return;
+  double2 e[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) e[c] = make_double2(0.0, 0.0);
+  if (kx != 0 || ky != 0 || kz != 0) {
+    const bool nyq = nyquist(kx, n) || nyquist(ky, n) || nyquist(kz, n);
+    const int nrep = nyq ? 2 : 1;
+    const double s2pi = 2.0 * M_PI / L;
+    double2 U[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) U[i][j] = make_double2(0.0, 0.0);
+    for (int rep = 0; rep < nrep; ++rep) {
+      double x[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const int h = n / 2;
+        x[a] = s2pi * (nyquist(k[a], n) ? (rep == 0 ? -h : h) : centred(k[a], n));
+      }
+      const double q = 1.0 / ((x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) * nrep);
+      // U_ij += -i (xi x alpha_i.)_j / |xi|^2, alpha_i. the row i of alpha_hat
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const double2 a0 = al[3 * i], a1 = al[3 * i + 1], a2 = al[3 * i + 2];
+        const double2 c0 = make_double2(x[1] * a2.x - x[2] * a1.x, x[1] * a2.y - x[2] * a1.y);
+        const double2 c1 = make_double2(x[2] * a0.x - x[0] * a2.x, x[2] * a0.y - x[0] * a2.y);
+        const double2 c2 = make_double2(x[0] * a1.x - x[1] * a0.x, x[0] * a1.y - x[1] * a0.y);
+        // -i c = (c.y, -c.x)
+        U[i][0].x += q * c0.y;
+        U[i][0].y -= q * c0.x;
+        U[i][1].x += q * c1.y;
+        U[i][1].y -= q * c1.x;
+        U[i][2].x += q * c2.y;
+        U[i][2].y -= q * c2.x;
+      }
+    }
+    e[0] = U[0][0];
+    e[1] = U[1][1];
+    e[2] = U[2][2];
+    e[3] = make_double2(0.5 * (U[1][2].x + U[2][1].x), 0.5 * (U[1][2].y + U[2][1].y));
+    e[4] = make_double2(0.5 * (U[0][2].x + U[2][0].x), 0.5 * (U[0][2].y + U[2][0].y));
+    e[5] = make_double2(0.5 * (U[0][1].x + U[1][0].x), 0.5 * (U[0][1].y + U[1][0].y));
+    if (C.frm)
+      green_bin_rot(e, kx, ky, kz, n, C);
+    else
+      green_bin(e, kx, ky, kz, n, C);
+  }
+  typename Cplx<S>::T* const out = spec + spec_at(kz, ky, kx, 0, n, P);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) st2(out + c, e[c]);
+}
+
+__global__ __launch_bounds__(256) void k_bg3_add(double* __restrict__ sig, const double* __restrict__ bg3,
+                                                 int64_t count, double sgn) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) sig[i] += sgn * bg3[i];
+}
+
+hipError_t launch_path_spectrum(bool fp64, const DevPiece* pieces, int np, SpecGeom g, double L, Cubic C,
+                                const double2* tw, void* spec, hipStream_t s) {
+  const int64_t bins = (int64_t)g.n * g.n * (g.n / 2 + 1);
+  const int grid = (int)((bins + 255) / 256);
+  if (fp64)
+    hipLaunchKernelGGL(k_path_spectrum<double>, dim3(grid), dim3(256), 0, s, pieces, np, g.n, g.P, L, C, tw,
+                       (double2*)spec);
+  else
+    hipLaunchKernelGGL(k_path_spectrum<float>, dim3(grid), dim3(256), 0, s, pieces, np, g.n, g.P, L, C, tw,
+                       (float2*)spec);
+  return hipGetLastError();
+}
+
+hipError_t launch_bg3_add(double* sig, const double* bg3, int64_t n3, double sgn, hipStream_t s) {
+  const int64_t count = 6 * n3;
+  hipLaunchKernelGGL(k_bg3_add, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, sig, bg3, count, sgn);
+  return hipGetLastError();
+}
+
 hipError_t launch_disl_plane(const DevLine* lines, int nl, int axis, int n, double L, Cubic C, double2* spec,
                              double2* tmp, double* plane, hipStream_t s) {
   const int nn = n * n;

@@ -44,6 +44,7 @@ EXPORTS = (
     "ec_jump_select",
     "ec_okmc_step",
     "ec_set_dislocations",
+    "ec_set_dislocation_paths",
     "ec_dipole_energies",
     "ec_type_store",
     "ec_type_energies",
@@ -56,6 +57,11 @@ EXPORTS = (
     "ec_debug_green",
     "ec_debug_inverse",
 )
+
+
+# ec_path of include/ec.h
+PATH_DTYPE = np.dtype([("first", np.int32), ("count", np.int32), ("shift", np.float64, 3), ("b", np.float64, 3)])
+assert PATH_DTYPE.itemsize == 56
 
 
 class EcError(RuntimeError):
@@ -123,6 +129,7 @@ def load() -> ctypes.CDLL:
         "ec_type_store": (c_int, [vp, vp, vp, i32p]),
         "ec_type_energies": (c_int, [vp, c_int32, vp, c_int32, vp, vp, vp]),
         "ec_set_dislocations": (c_int, [vp, vp, c_int32, vp]),
+        "ec_set_dislocation_paths": (c_int, [vp, vp, c_int32, vp, c_int32, vp]),
         "ec_state_footprints": (c_int, [vp, i32p, i32p, c_int64, i64p]),
         "ec_state_field": (c_int, [vp, c_int32, dp]),
         "ec_state_self_terms": (c_int, [vp, dp]),
@@ -459,6 +466,28 @@ class State:
 
         a = np.ascontiguousarray(np.asarray(lines, dtype=LINE_DTYPE).reshape(-1))
         _check(load().ec_set_dislocations(self.h, a.ctypes.data if len(a) else None, len(a), _stream_handle(stream)))
+
+    def set_dislocation_paths(self, paths, stream=None):
+        """Dislocation loops and lines in any direction whose stress is added to
+        every solve of this state: ``paths`` is a list of (verts (k, 3) nm,
+        shift (3,) nm, b (3,) nm), a loop when shift is zero, a line through the
+        periodic cell when shift is a lattice vector of it; [] removes them."""
+        recs = np.zeros(len(paths), dtype=PATH_DTYPE)
+        vs = []
+        first = 0
+        for k, (verts, shift, b) in enumerate(paths):
+            v = np.asarray(verts, dtype=np.float64).reshape(-1, 3)
+            recs[k]["first"], recs[k]["count"] = first, len(v)
+            recs[k]["shift"], recs[k]["b"] = shift, b
+            vs.append(v)
+            first += len(v)
+        verts = np.ascontiguousarray(np.concatenate(vs) if vs else np.zeros((0, 3)))
+        _check(
+            load().ec_set_dislocation_paths(
+                self.h, recs.ctypes.data if len(recs) else None, len(recs),
+                verts.ctypes.data if len(verts) else None, len(verts), _stream_handle(stream),
+            )
+        )
 
     def dipole_energies(self, stream=None, out=None) -> np.ndarray:
         """Dipole-tensor interaction energies (eV) of the current defects; host
