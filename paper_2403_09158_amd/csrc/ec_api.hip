@@ -928,8 +928,8 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
   }
   LAUNCH(st, s, PF_Z, 2 * sb, launch_z_green(fp64, spec, g, st->C, full, st->tw, ctr ? ctr + 8 : nullptr, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, spec, g, full, st->tw, ctr ? ctr + 16 : nullptr, s));
-  LAUNCH(st, s, PF_XI, sb + fb, launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s, bg, bg_mask));
-  if (bg3) LAUNCH(st, s, PF_OTHER, 2 * fb, launch_bg3_add(sig, bg3, st->n3, 1.0, s));
+  LAUNCH(st, s, PF_XI, sb + (bg3 ? 2 : 1) * fb,
+         launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s, bg, bg_mask, bg3));
   return EC_OK;
 }
 

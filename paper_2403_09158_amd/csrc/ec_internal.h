@@ -390,8 +390,10 @@ hipError_t launch_green(bool fp64, void* spec, SpecGeom g, Cubic C, hipStream_t 
 hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, const double2* tw, uint32_t* ctr,
                           hipStream_t s);
 // bg / bg_mask: stress planes of dislocation lines added to sigma (not with accum).
+// add3: a stress field [n^3][6] (FP64) added to sigma (not with accum).
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
-                            const double2* tw, hipStream_t s, const double* bg = nullptr, int bg_mask = 0);
+                            const double2* tw, hipStream_t s, const double* bg = nullptr, int bg_mask = 0,
+                            const double* add3 = nullptr);
 // The Fourier passes of a batch of hops (jobs: njob device records, see
 // HopJob; ctr: NTILECTR tile counters, zeroed by the first pass): sparse x
 // forward, pruned y forward, fused z pass, y inverse, accumulating x inverse

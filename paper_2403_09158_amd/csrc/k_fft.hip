@@ -945,6 +945,9 @@ __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__
 
 // --------------------------------------------------------- x inverse (C2R) + stress
 
+// ACC: the result is added to a field of the stress's layout: add3 (a stress
+// held beside the solve, such as that of dislocation loops), or sig itself when
+// add3 is null.
 // BG: the stress planes of dislocation lines along the axes in bg_mask
 // ([3][n^2][6], FP64) are added as well.
 // BATCH: njob hops of a batch, N N / ROWS blocks each, a job's spectrum and
@@ -953,7 +956,7 @@ template <int N, typename S, bool ACC, bool BG, bool BATCH = false>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
     const typename Cplx<S>::T* __restrict__ spec, double* __restrict__ sig, const double* __restrict__ mean6,
     const double2* __restrict__ twg, const double* __restrict__ bg, int bg_mask,
-    const HopJob* __restrict__ jobs = nullptr) {
+    const HopJob* __restrict__ jobs = nullptr, const double* add3 = nullptr) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;
   constexpr int T = pick_T(max_nb(N, NF));
@@ -1000,6 +1003,10 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
     const int p = f % 3, y = y0 + f / 3;
     return reinterpret_cast<double2*>(sig + (6 * ((z * N + y) * N + x) + 2 * p));
   };
+  auto add_at = [&](int f, int x) -> double2 {
+    const int p = f % 3, y = y0 + f / 3;
+    return *reinterpret_cast<const double2*>((add3 ? add3 : sig) + (6 * ((z * N + y) * N + x) + 2 * p));
+  };
   // accumulate: the thread's old values of the last stage's outputs are read
   // before the transform, so their latency overlaps it
   constexpr Plan2 PLX = plan_of(N);
@@ -1008,7 +1015,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   constexpr int NOUT = ((NF * (N / RL) + T - 1) / T) * RL;
   double2 old[ACC ? NOUT : 1];
   if constexpr (ACC)
-    for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) { old[slot] = *sig_at(f, x); });
+    for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) { old[slot] = add_at(f, x); });
   auto store_last = [&](int f, int x, double2 v, int slot) {
     const int p = f % 3, y = y0 + f / 3;
     double2* s01 = sig_at(f, x);
@@ -1119,14 +1126,17 @@ hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const
 
 template <int N, typename S>
 hipError_t go_xi(bool acc, const void* spec, double* sig, SpecGeom g, const double* mean6, const double2* tw,
-                 const double* bg, int bg_mask, hipStream_t s) {
+                 const double* bg, int bg_mask, const double* add3, hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   const int grid = N * (N / x_rows(N));
   using C2 = typename Cplx<S>::T;
-  if (g.P != spec_pitch(N, sizeof(S) == 8)) return hipErrorInvalidValue;
-  if (acc)
+  if (g.P != spec_pitch(N, sizeof(S) == 8) || (acc && add3)) return hipErrorInvalidValue;
+  if (add3 && bg && bg_mask)
+    hipLaunchKernelGGL((k_x_inverse<N, S, true, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
+                       bg, bg_mask, (const HopJob*)nullptr, add3);
+  else if (acc || add3)
     hipLaunchKernelGGL((k_x_inverse<N, S, true, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
-                       bg, 0, (const HopJob*)nullptr);
+                       bg, 0, (const HopJob*)nullptr, add3);
   else if (bg && bg_mask)
     hipLaunchKernelGGL((k_x_inverse<N, S, false, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
                        bg, bg_mask, (const HopJob*)nullptr);
@@ -1303,12 +1313,12 @@ hipError_t launch_hop_batch_fft(bool fp64, const HopJob* jobs, int njob, SpecGeo
 }
 
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
-                            const double2* tw, hipStream_t s, const double* bg, int bg_mask) {
+                            const double2* tw, hipStream_t s, const double* bg, int bg_mask, const double* add3) {
   switch (g.n) {
-#define EC_CASE(NN)                                                                   \
-  case NN:                                                                            \
-    return fp64 ? go_xi<NN, double>(accum, spec, sig, g, mean6, tw, bg, bg_mask, s) \
-                : go_xi<NN, float>(accum, spec, sig, g, mean6, tw, bg, bg_mask, s);
+#define EC_CASE(NN)                                                                         \
+  case NN:                                                                                  \
+    return fp64 ? go_xi<NN, double>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, s) \
+                : go_xi<NN, float>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }
