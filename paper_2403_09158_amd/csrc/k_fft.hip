@@ -35,14 +35,27 @@ constexpr int pick_T(int nb) { return nb >= 256 ? 256 : ((nb + 63) / 64) * 64; }
 // inverse transform yields sigma directly).  Gamma is homogeneous of degree 0 in
 // xi, so the integer labels stand in for xi = 2 pi k / L.
 
-__device__ __forceinline__ void acc_eps(double ax, double ay, double az, const Cubic& C, const double2* tau,
-                                        double2* eps, double wgt) {
+// tau = C:e for cubic C (components xx yy zz yz xz xy; the shear entries of
+// e are tensor components, so they take 2 C44).
+__device__ __forceinline__ void cubic_stress(const double2* e, const Cubic& C, double2* tau) {
+  const double d = C.C11 - C.C12, c44x2 = 2.0 * C.C44;
+  const double trx = e[0].x + e[1].x + e[2].x, try_ = e[0].y + e[1].y + e[2].y;
+  const double ctx = C.C12 * trx, cty = C.C12 * try_;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) tau[c] = make_double2(fma(d, e[c].x, ctx), fma(d, e[c].y, cty));
+#pragma unroll
+  for (int c = 3; c < 6; ++c) tau[c] = make_double2(c44x2 * e[c].x, c44x2 * e[c].y);
+}
+
+// w = wgt N(xi) (tau xi), N = K^-1 by the adjugate, K_ik = C_ijkl xi_j xi_l.
+__device__ __forceinline__ void green_w(double ax, double ay, double az, const Cubic& C, const double2* tau,
+                                        double wgt, double2* w) {
   const double x2 = ax * ax, y2 = ay * ay, z2 = az * az, r2 = x2 + y2 + z2;
-  const double K00 = C.C11 * x2 + C.C44 * (r2 - x2);
-  const double K11 = C.C11 * y2 + C.C44 * (r2 - y2);
-  const double K22 = C.C11 * z2 + C.C44 * (r2 - z2);
+  const double c44r2 = C.C44 * r2, dd = C.C11 - C.C44;
+  const double K00 = fma(dd, x2, c44r2), K11 = fma(dd, y2, c44r2), K22 = fma(dd, z2, c44r2);
   const double cc = C.C12 + C.C44;
-  const double K01 = cc * ax * ay, K02 = cc * ax * az, K12 = cc * ay * az;
+  const double ccx = cc * ax;
+  const double K01 = ccx * ay, K02 = ccx * az, K12 = cc * ay * az;
   const double A00 = K11 * K22 - K12 * K12;
   const double A11 = K00 * K22 - K02 * K02;
   const double A22 = K00 * K11 - K01 * K01;
@@ -58,25 +71,39 @@ __device__ __forceinline__ void acc_eps(double ax, double ay, double az, const C
   v1.y = tau[5].y * ax + tau[1].y * ay + tau[3].y * az;
   v2.x = tau[4].x * ax + tau[3].x * ay + tau[2].x * az;
   v2.y = tau[4].y * ax + tau[3].y * ay + tau[2].y * az;
-  double2 w0, w1, w2;  // w = N v (scaled by wgt)
-  w0.x = (A00 * v0.x + A01 * v1.x + A02 * v2.x) * inv;
-  w0.y = (A00 * v0.y + A01 * v1.y + A02 * v2.y) * inv;
-  w1.x = (A01 * v0.x + A11 * v1.x + A12 * v2.x) * inv;
-  w1.y = (A01 * v0.y + A11 * v1.y + A12 * v2.y) * inv;
-  w2.x = (A02 * v0.x + A12 * v1.x + A22 * v2.x) * inv;
-  w2.y = (A02 * v0.y + A12 * v1.y + A22 * v2.y) * inv;
-  eps[0].x += ax * w0.x;
-  eps[0].y += ax * w0.y;
-  eps[1].x += ay * w1.x;
-  eps[1].y += ay * w1.y;
-  eps[2].x += az * w2.x;
-  eps[2].y += az * w2.y;
-  eps[3].x += 0.5 * (ay * w2.x + az * w1.x);
-  eps[3].y += 0.5 * (ay * w2.y + az * w1.y);
-  eps[4].x += 0.5 * (ax * w2.x + az * w0.x);
-  eps[4].y += 0.5 * (ax * w2.y + az * w0.y);
-  eps[5].x += 0.5 * (ax * w1.x + ay * w0.x);
-  eps[5].y += 0.5 * (ax * w1.y + ay * w0.y);
+  w[0].x = (A00 * v0.x + A01 * v1.x + A02 * v2.x) * inv;
+  w[0].y = (A00 * v0.y + A01 * v1.y + A02 * v2.y) * inv;
+  w[1].x = (A01 * v0.x + A11 * v1.x + A12 * v2.x) * inv;
+  w[1].y = (A01 * v0.y + A11 * v1.y + A12 * v2.y) * inv;
+  w[2].x = (A02 * v0.x + A12 * v1.x + A22 * v2.x) * inv;
+  w[2].y = (A02 * v0.y + A12 * v1.y + A22 * v2.y) * inv;
+}
+
+// s = C:sym(xi (x) w) - tau (FIRST) or s += C:sym(xi (x) w), cubic C: normal
+// entries C12 (xi . w) + (C11 - C12) xi_i w_i, shear entries
+// C44 (xi_i w_j + xi_j w_i).
+template <bool FIRST>
+__device__ __forceinline__ void add_cubic_sym(double ax, double ay, double az, const Cubic& C, const double2* w,
+                                              const double2* tau, double2* s) {
+  const double d = C.C11 - C.C12;
+  const double a[3] = {ax, ay, az};
+  const double dx = ax * w[0].x + ay * w[1].x + az * w[2].x;
+  const double dy = ax * w[0].y + ay * w[1].y + az * w[2].y;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double bx = FIRST ? fma(C.C12, dx, -tau[c].x) : fma(C.C12, dx, s[c].x);
+    const double by = FIRST ? fma(C.C12, dy, -tau[c].y) : fma(C.C12, dy, s[c].y);
+    s[c] = make_double2(fma(d, a[c] * w[c].x, bx), fma(d, a[c] * w[c].y, by));
+  }
+  // shear (yz, xz, xy) = pairs (1, 2), (0, 2), (0, 1)
+  constexpr int P[3][2] = {{1, 2}, {0, 2}, {0, 1}};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int i = P[q][0], j = P[q][1];
+    const double mx = fma(a[i], w[j].x, a[j] * w[i].x), my = fma(a[i], w[j].y, a[j] * w[i].y);
+    const double bx = FIRST ? -tau[3 + q].x : s[3 + q].x, by = FIRST ? -tau[3 + q].y : s[3 + q].y;
+    s[3 + q] = make_double2(fma(C.C44, mx, bx), fma(C.C44, my, by));
+  }
 }
 
 // Centred integer label of DFT bin k in [0, n) (Sec. 3.4): k up to (n - 1) / 2,
@@ -95,36 +122,20 @@ __device__ __forceinline__ void green_bin(double2* e, int kx, int ky, int kz, in
     for (int c = 0; c < 6; ++c) e[c] = make_double2(0.0, 0.0);
     return;
   }
-  double2 tau[6];
-  const double c44x2 = 2.0 * C.C44;
-  tau[0].x = C.C11 * e[0].x + C.C12 * (e[1].x + e[2].x);
-  tau[0].y = C.C11 * e[0].y + C.C12 * (e[1].y + e[2].y);
-  tau[1].x = C.C11 * e[1].x + C.C12 * (e[0].x + e[2].x);
-  tau[1].y = C.C11 * e[1].y + C.C12 * (e[0].y + e[2].y);
-  tau[2].x = C.C11 * e[2].x + C.C12 * (e[0].x + e[1].x);
-  tau[2].y = C.C11 * e[2].y + C.C12 * (e[0].y + e[1].y);
-#pragma unroll
-  for (int c = 3; c < 6; ++c) tau[c] = make_double2(c44x2 * e[c].x, c44x2 * e[c].y);
-  double2 eps[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) eps[c] = make_double2(0.0, 0.0);
+  double2 tau[6], w[3];
+  cubic_stress(e, C, tau);
   const int h = n / 2;
-  const bool nx = nyquist(kx, n), ny = nyquist(ky, n), nz = nyquist(kz, n);
-  const double lx = kx, ly = centred(ky, n), lz = centred(kz, n);
-  if (!(nx || ny || nz)) {
-    acc_eps(lx, ly, lz, C, tau, eps, 1.0);
-  } else {
-    acc_eps(nx ? -h : lx, ny ? -h : ly, nz ? -h : lz, C, tau, eps, 0.5);
-    acc_eps(nx ? h : lx, ny ? h : ly, nz ? h : lz, C, tau, eps, 0.5);
+  const bool nx = nyquist(kx, n), ny = nyquist(ky, n), nz = nyquist(kz, n), nq = nx || ny || nz;
+  const double lx = nx ? -h : kx, ly = ny ? -h : centred(ky, n), lz = nz ? -h : centred(kz, n);
+  // every bin takes its (first) label; a Nyquist bin weighs it 1/2 and adds
+  // the all +n/2 label, so the lanes of a wavefront part for one label only
+  green_w(lx, ly, lz, C, tau, nq ? 0.5 : 1.0, w);
+  add_cubic_sym<true>(lx, ly, lz, C, w, tau, e);
+  if (nq) {
+    const double px = nx ? h : lx, py = ny ? h : ly, pz = nz ? h : lz;
+    green_w(px, py, pz, C, tau, 0.5, w);
+    add_cubic_sym<false>(px, py, pz, C, w, tau, e);
   }
-  e[0].x = C.C11 * eps[0].x + C.C12 * (eps[1].x + eps[2].x) - tau[0].x;
-  e[0].y = C.C11 * eps[0].y + C.C12 * (eps[1].y + eps[2].y) - tau[0].y;
-  e[1].x = C.C11 * eps[1].x + C.C12 * (eps[0].x + eps[2].x) - tau[1].x;
-  e[1].y = C.C11 * eps[1].y + C.C12 * (eps[0].y + eps[2].y) - tau[1].y;
-  e[2].x = C.C11 * eps[2].x + C.C12 * (eps[0].x + eps[1].x) - tau[2].x;
-  e[2].y = C.C11 * eps[2].y + C.C12 * (eps[0].y + eps[1].y) - tau[2].y;
-#pragma unroll
-  for (int c = 3; c < 6; ++c) e[c] = make_double2(c44x2 * eps[c].x - tau[c].x, c44x2 * eps[c].y - tau[c].y);
 }
 
 // Rotated crystal (C.frm set): the cubic operator applied in the cube frame,
@@ -140,40 +151,25 @@ __device__ __forceinline__ void green_core_rot(double2* ec, int kx, int ky, int 
     return;
   }
   const double* A = C.frm + 72;
-  double2 tau[6];
-  const double c44x2 = 2.0 * C.C44;
-  tau[0].x = C.C11 * ec[0].x + C.C12 * (ec[1].x + ec[2].x);
-  tau[0].y = C.C11 * ec[0].y + C.C12 * (ec[1].y + ec[2].y);
-  tau[1].x = C.C11 * ec[1].x + C.C12 * (ec[0].x + ec[2].x);
-  tau[1].y = C.C11 * ec[1].y + C.C12 * (ec[0].y + ec[2].y);
-  tau[2].x = C.C11 * ec[2].x + C.C12 * (ec[0].x + ec[1].x);
-  tau[2].y = C.C11 * ec[2].y + C.C12 * (ec[0].y + ec[1].y);
-#pragma unroll
-  for (int c = 3; c < 6; ++c) tau[c] = make_double2(c44x2 * ec[c].x, c44x2 * ec[c].y);
-  double2 eps[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) eps[c] = make_double2(0.0, 0.0);
+  double2 tau[6], w[3];
+  cubic_stress(ec, C, tau);
   const int h = n / 2;
-  const bool nx = nyquist(kx, n), ny = nyquist(ky, n), nz = nyquist(kz, n);
-  const double lx = kx, ly = centred(ky, n), lz = centred(kz, n);
-  auto acc = [&](double x, double y, double z, double wgt) {
-    acc_eps(A[0] * x + A[3] * y + A[6] * z, A[1] * x + A[4] * y + A[7] * z, A[2] * x + A[5] * y + A[8] * z, C, tau,
-            eps, wgt);
+  const bool nx = nyquist(kx, n), ny = nyquist(ky, n), nz = nyquist(kz, n), nq = nx || ny || nz;
+  const double lx = nx ? -h : kx, ly = ny ? -h : centred(ky, n), lz = nz ? -h : centred(kz, n);
+  auto label = [&](double x, double y, double z, double* r) {
+    r[0] = A[0] * x + A[3] * y + A[6] * z;
+    r[1] = A[1] * x + A[4] * y + A[7] * z;
+    r[2] = A[2] * x + A[5] * y + A[8] * z;
   };
-  if (!(nx || ny || nz)) {
-    acc(lx, ly, lz, 1.0);
-  } else {
-    acc(nx ? -h : lx, ny ? -h : ly, nz ? -h : lz, 0.5);
-    acc(nx ? h : lx, ny ? h : ly, nz ? h : lz, 0.5);
+  double r[3];
+  label(lx, ly, lz, r);
+  green_w(r[0], r[1], r[2], C, tau, nq ? 0.5 : 1.0, w);
+  add_cubic_sym<true>(r[0], r[1], r[2], C, w, tau, ec);
+  if (nq) {
+    label(nx ? h : lx, ny ? h : ly, nz ? h : lz, r);
+    green_w(r[0], r[1], r[2], C, tau, 0.5, w);
+    add_cubic_sym<false>(r[0], r[1], r[2], C, w, tau, ec);
   }
-  ec[0].x = C.C11 * eps[0].x + C.C12 * (eps[1].x + eps[2].x) - tau[0].x;
-  ec[0].y = C.C11 * eps[0].y + C.C12 * (eps[1].y + eps[2].y) - tau[0].y;
-  ec[1].x = C.C11 * eps[1].x + C.C12 * (eps[0].x + eps[2].x) - tau[1].x;
-  ec[1].y = C.C11 * eps[1].y + C.C12 * (eps[0].y + eps[2].y) - tau[1].y;
-  ec[2].x = C.C11 * eps[2].x + C.C12 * (eps[0].x + eps[1].x) - tau[2].x;
-  ec[2].y = C.C11 * eps[2].y + C.C12 * (eps[0].y + eps[1].y) - tau[2].y;
-#pragma unroll
-  for (int c = 3; c < 6; ++c) ec[c] = make_double2(c44x2 * eps[c].x - tau[c].x, c44x2 * eps[c].y - tau[c].y);
 }
 
 __device__ __forceinline__ void green_bin_rot(double2* e, int kx, int ky, int kz, int n, const Cubic& C) {
@@ -246,6 +242,13 @@ __device__ __forceinline__ auto x_twiddles(const double2* tw_lds, const double2*
 // fixed order within its XCD's contiguous range, and loads the next group's
 // owner links into registers while it decodes and transforms the current one,
 // so the HBM latency of the owner map overlaps the work of the group before.
+// The eigenstrains of the next group's single-owner voxels are loaded after
+// the current group's transform and before its spectrum stores: vector memory
+// operations complete in issue order as far as a wave's wait counter is
+// concerned, so a load issued after the stores would wait for them to drain,
+// and loads issued one voxel at a time would each wait for the one before.
+// Voxels of several owners (a few per cent of the row groups) are decoded in
+// place.
 // DM: the input, 0 = owner lists, 1 = a dense field [6][n^3], 2 = a dense
 // voxel-major field [n^3][6] (the resident stress).
 template <int N, typename S, int DM>
@@ -270,24 +273,53 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
   auto lds = [&](int f, int i) -> double2* { return &buf[f * LDN + i + (i >> 4)]; };
   constexpr int KV = (ROWS * N + T - 1) / T;
   // a group's voxels: ROWS consecutive rows, so ROWS * N consecutive ids
+  // The loads below are issued without branches (a lane past the group reads
+  // its last voxel and is skipped by the gather, one without an owner reads
+  // the twiddle table and is masked), so that the compiler can count them and
+  // wait for exactly the ones a use needs.
   auto load_links = [&](int grp, int32_t* lk) {
 #pragma unroll
     for (int k = 0; k < KV; ++k) {
       const int i = threadIdx.x + k * T;
-      lk[k] = -1;
-      if (DM == 0 && i < ROWS * N) lk[k] = own[(size_t)grp * (ROWS * N) + i];
+      if constexpr (DM == 0) {
+        lk[k] = own[(size_t)grp * (ROWS * N) + min(i, ROWS * N - 1)];
+      } else {
+        lk[k] = -1;
+      }
+    }
+  };
+  // single-owner eigenstrains of a group's voxels (zero elsewhere)
+  double2 ev[KV][3];
+  auto load_vals = [&](const int32_t* lk) {
+#pragma unroll
+    for (int k = 0; k < KV; ++k) {
+      if constexpr (DM == 0) {
+        const double2* f = lk[k] >= 0 ? reinterpret_cast<const double2*>(defs[lk[k]].efd) : twg;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ev[k][c] = f[c];
+      }
     }
   };
   TileWalk walk(NG, nullptr, tslot);
   int grp = walk.first();
   const int hi = walk.hi;
   int32_t link[KV], nlink[KV];
-  if (grp < hi) load_links(grp, link);
+  if (grp < hi) {
+    load_links(grp, link);
+    load_vals(link);
+  }
   const auto twp = x_twiddles<N, NF, T>(tw, twg);
+  // Nothing loaded so far stays pending into the loop: the loop's waits are
+  // then counted from its own steady state alone (with loads of the set-up
+  // still in flight at entry, each wait would have to cover them, and in
+  // every later pass it would also wait for the stores of the group before).
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int it = 0; grp < hi; ++it) {
     const int gn = walk.next(grp, it);
-    if (gn < hi) load_links(gn, nlink);
+    // past the range the loads repeat the current group, unused (so that no
+    // branch makes their count uncertain)
+    load_links(gn < hi ? gn : grp, nlink);
     const int z = grp / bpp;
     const int y0 = (grp % bpp) * ROWS;
     // gather the rows' six components into the transform inputs (xx + i yy, ...)
@@ -309,14 +341,30 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
             e[2 * p] = t.x;
             e[2 * p + 1] = t.y;
           }
-        } else if (link[k] == -1) {
+        } else {  // one owner (loaded with the group before), or none; several: below
+          const bool one = link[k] >= 0;
 #pragma unroll
-          for (int c = 0; c < 6; ++c) e[c] = 0.0;
-        } else {
-          decode_voxel(link[k], lnk, defs, e, max_links);
+          for (int p = 0; p < 3; ++p) {
+            e[2 * p] = one ? ev[k][p].x : 0.0;
+            e[2 * p + 1] = one ? ev[k][p].y : 0.0;
+          }
         }
 #pragma unroll
         for (int p = 0; p < 3; ++p) st2(lds(3 * r + p, x), make_double2(e[2 * p], e[2 * p + 1]));
+      }
+    }
+    if constexpr (DM == 0) {
+      // voxels of several owners: the exact fixed-point sum over the chain
+#pragma unroll
+      for (int k = 0; k < KV; ++k) {
+        const int i = threadIdx.x + k * T;
+        if (i < ROWS * N && link[k] < -1) {
+          const int r = i / N, x = i - r * N;
+          double e[6];
+          decode_voxel(link[k], lnk, defs, e, max_links);
+#pragma unroll
+          for (int p = 0; p < 3; ++p) st2(lds(3 * r + p, x), make_double2(e[2 * p], e[2 * p + 1]));
+        }
       }
     }
     __syncthreads();
@@ -324,6 +372,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
     auto to_lds = [&](int f, int i, double2 v) { st2(lds(f, i), v); };
     transform<N, false, Map::Row, NF, T, true, true>(twp, from_lds, from_lds, to_lds, to_lds);
     __syncthreads();
+    load_vals(nlink);
     // Hermitian split of the three pair transforms of a row into the six
     // interleaved half-spectrum components.  FP64 storage: one output value per
     // thread, so consecutive threads write consecutive 16-byte values of the
@@ -357,10 +406,18 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_forward(
           st2(out + 2 * p + 1, make_double2(0.5 * (zk.y - zc.y), -0.5 * (zk.x - zc.x)));
         }
       };
-      for (int e = threadIdx.x; e < ROWS * (N / 2); e += T) {
-        const int r = e / (N / 2), k = e % (N / 2);
-        bin(r, k);
-        if (k == 0) bin(r, N / 2);
+      // a compile-time trip count, so that the compiler counts the stores
+      // (the next group's gather then waits for its loads and leaves these
+      // in flight)
+      constexpr int NB = ROWS * (N / 2);
+#pragma unroll
+      for (int q0 = 0; q0 < (NB + T - 1) / T; ++q0) {
+        const int e = threadIdx.x + q0 * T;
+        if (NB % T == 0 || e < NB) {
+          const int r = e / (N / 2), k = e % (N / 2);
+          bin(r, k);
+          if (k == 0) bin(r, N / 2);
+        }
       }
     }
     __syncthreads();  // the next group rewrites the LDS rows
@@ -734,15 +791,35 @@ constexpr int zg_width() {
 // one butterfly per thread in the widest-radix stage; a multiple of the 6 W
 // transforms, so every lane keeps its transform
 template <int N, typename S>
-constexpr int zg_threads() {
+constexpr int zg_fft_threads() {
   using FP = FusedPlan<N>;
   constexpr int rmax = FP::R0 > FP::R1 ? (FP::R0 > FP::R2 ? FP::R0 : FP::R2) : (FP::R1 > FP::R2 ? FP::R1 : FP::R2);
   return tile_threads<N>(6 * zg_width<N, S>(), rmax);
 }
 
+// Workgroup size: the butterfly threads, or for the two-column tile at 256
+// four whole wavefronts (the fourth idle in the transform stages, every one
+// busy in the Green step): three resident workgroups then put three
+// wavefronts on every SIMD, where three-wavefront groups would put three on
+// one SIMD and two on the others, and every workgroup has a wavefront on the
+// busiest one.
+template <int N, typename S>
+constexpr int zg_threads() {
+  constexpr int t = zg_fft_threads<N, S>();
+  return (N == 256 && zg_narrow<N>() && zg_width<N, S>() == 2) ? ((t + 255) / 256) * 256 : t;
+}
+
 template <int N, typename S>
 constexpr bool zg_pipe() {
   return sizeof(S) == 4 && !zg_narrow<N>() && !has_direct(plan_fused(N));
+}
+
+// Wavefronts per SIMD the compiler must leave registers for: three for the
+// two-column tiles of 64 .. 256 (three resident workgroups; at 256 twelve
+// wavefronts per CU), else one (no bound beyond the workgroup size).
+template <int N, typename S>
+constexpr int zg_waves_per_eu() {
+  return zg_narrow<N>() ? 3 : 1;
 }
 
 // LDS row swizzle: the low three bits of the z index are XORed with the next
@@ -752,7 +829,8 @@ __device__ __forceinline__ int zg_swz(int i) { return (i & ~7) | ((i ^ (i >> 3))
 // BATCH: the tiles of njob hops of a batch, job after job (NT each), a job's
 // spectrum and input planes from its record (spec and pr unused).
 template <int N, typename S, bool PRUNE, bool ROT, bool BATCH = false>
-__global__ __launch_bounds__((zg_threads<N, S>())) void k_zgreen(typename Cplx<S>::T* __restrict__ spec, Cubic C,
+__global__ __launch_bounds__((zg_threads<N, S>())) __attribute__((amdgpu_waves_per_eu(zg_waves_per_eu<N, S>())))
+void k_zgreen(typename Cplx<S>::T* __restrict__ spec, Cubic C,
                                                                 Prune pr, const double2* __restrict__ twg,
                                                                 uint32_t* __restrict__ ctr,
                                                                 const HopJob* __restrict__ jobs = nullptr,
