@@ -374,6 +374,10 @@ EC_API ec_status ec_state_self_terms(ec_state* st, double* host_out);
  * 4 x-inverse + stress, 5 energy reduction, 6 self term, 7 other. */
 #define EC_NPROF 8
 EC_API ec_status ec_profile_enable(ec_state* st, int32_t on);
+/* Families timed while profiling is enabled: bit f of family_mask for family
+ * f (every family by default), so that a caller can time one family without
+ * the events of the others in its stream; other bits: EC_ERR_ARG. */
+EC_API ec_status ec_profile_select(ec_state* st, int32_t family_mask);
 EC_API ec_status ec_profile_read(ec_state* st, int64_t* launches, double* ms, double* bytes_per_launch);
 
 /* ---- kernel-level entry points (parity tests of single passes) -------------- */

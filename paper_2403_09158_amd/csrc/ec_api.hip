@@ -393,6 +393,7 @@ struct ec_state {
   Pinned pin_tab, pin_upd, pin_ids, pin_tags, pin_jump, pin_choice, pin_out;
   // profiling
   bool prof = false;
+  int32_t prof_mask = (1 << EC_NPROF) - 1;  // families whose launches are timed
   std::vector<ProfRec> recs;
   std::vector<hipEvent_t> evpool;
 };
@@ -537,7 +538,7 @@ hipEvent_t take_event(ec_state* st) {
 
 template <class F>
 hipError_t run(ec_state* st, hipStream_t s, int fam, double bytes, F&& f) {
-  if (!st->prof) return f();
+  if (!st->prof || !((st->prof_mask >> fam) & 1)) return f();
   hipEvent_t a = take_event(st), b = take_event(st);
   (void)hipEventRecord(a, s);
   hipError_t e = f();
@@ -2281,6 +2282,13 @@ ec_status ec_state_self_terms(ec_state* st, double* out) {
 ec_status ec_profile_enable(ec_state* st, int32_t on) {
   if (!st) return fail(EC_ERR_ARG, "state is NULL");
   st->prof = on != 0;
+  return EC_OK;
+}
+
+ec_status ec_profile_select(ec_state* st, int32_t family_mask) {
+  if (!st) return fail(EC_ERR_ARG, "state is NULL");
+  if (family_mask & ~((1 << EC_NPROF) - 1)) return fail(EC_ERR_ARG, "family mask 0x%x names no family", family_mask);
+  st->prof_mask = family_mask;
   return EC_OK;
 }
 

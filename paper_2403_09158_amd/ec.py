@@ -52,6 +52,7 @@ EXPORTS = (
     "ec_state_field",
     "ec_state_self_terms",
     "ec_profile_enable",
+    "ec_profile_select",
     "ec_profile_read",
     "ec_debug_forward",
     "ec_debug_green",
@@ -134,6 +135,7 @@ def load() -> ctypes.CDLL:
         "ec_state_field": (c_int, [vp, c_int32, dp]),
         "ec_state_self_terms": (c_int, [vp, dp]),
         "ec_profile_enable": (c_int, [vp, c_int32]),
+        "ec_profile_select": (c_int, [vp, c_int32]),
         "ec_profile_read": (c_int, [vp, i64p, dp, dp]),
         "ec_debug_forward": (c_int, [vp, dp, dp]),
         "ec_debug_green": (c_int, [vp, dp, dp]),
@@ -529,7 +531,11 @@ class State:
         _check(load().ec_state_self_terms(self.h, _dptr(out)))
         return out[: self.ndef]
 
-    def profile(self, on: bool = True):
+    def profile(self, on: bool = True, families=None):
+        """Kernel timing on or off; ``families``: names from PROF_FAMILIES to
+        time (None: all)."""
+        mask = (1 << NPROF) - 1 if families is None else sum(1 << PROF_FAMILIES.index(f) for f in families)
+        _check(load().ec_profile_select(self.h, mask))
         _check(load().ec_profile_enable(self.h, 1 if on else 0))
 
     def profile_read(self) -> dict:
