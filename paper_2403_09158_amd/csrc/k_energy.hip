@@ -44,24 +44,28 @@ __device__ __forceinline__ void neumaier_merge(double& s, double& c, double s2, 
   c += c2;
 }
 
-// One workgroup per defect: S_i = sum of sigma over the footprint (six FP64
-// Neumaier sums; four members in flight per thread), combined in a fixed
-// tree (lane shuffles, then the four wavefronts in order), then
-// E_i = -h^3 c E_i:S_i - B_i.
+// One wavefront per defect: S_i = sum of sigma over the footprint (six FP64
+// Neumaier sums per lane, four members in flight per lane), combined in a
+// fixed tree of lane shuffles, then E_i = -h^3 c E_i:S_i - B_i.  A footprint
+// averages a few hundred members, so a wavefront keeps its lanes busy where a
+// workgroup per defect would leave most of them idle and add a cross-wavefront
+// combine.
+constexpr int RDW = 4;  // defects (wavefronts) per workgroup
+
 __device__ __forceinline__ void reduce_defect(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
                                               const int32_t* __restrict__ ids, const double* __restrict__ sig,
                                               const double* __restrict__ B, double h3c, double* __restrict__ S6,
-                                              double* __restrict__ E, double* __restrict__ E2, int i) {
+                                              double* __restrict__ E, double* __restrict__ E2, int i, int lane) {
   const int64_t o = defs[i].slot;
   const int m = cnt[i];
   double s[6], c[6];
 #pragma unroll
   for (int a = 0; a < 6; ++a) s[a] = c[a] = 0.0;
-  int k = threadIdx.x;
-  for (; k + 3 * RDT < m; k += 4 * RDT) {
+  int k = lane;
+  for (; k + 3 * 64 < m; k += 4 * 64) {
     int id[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) id[j] = ids[o + k + j * RDT];
+    for (int j = 0; j < 4; ++j) id[j] = ids[o + k + j * 64];
     double v[4][6];
 #pragma unroll
     for (int j = 0; j < 4; ++j) ld_voxel(sig, id[j], v[j]);
@@ -70,7 +74,7 @@ __device__ __forceinline__ void reduce_defect(const DevDefect* __restrict__ defs
 #pragma unroll
       for (int a = 0; a < 6; ++a) neumaier(s[a], c[a], v[j][a]);
   }
-  for (; k < m; k += RDT) {
+  for (; k < m; k += 64) {
     double v[6];
     ld_voxel(sig, ids[o + k], v);
 #pragma unroll
@@ -82,50 +86,39 @@ __device__ __forceinline__ void reduce_defect(const DevDefect* __restrict__ defs
       const double s2 = __shfl_down(s[a], off), c2 = __shfl_down(c[a], off);
       neumaier_merge(s[a], c[a], s2, c2);
     }
-  __shared__ double ws[RDT / 64][6], wc[RDT / 64][6];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0)
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      ws[wave][a] = s[a];
-      wc[wave][a] = c[a];
-    }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const DevDefect d = defs[i];
+  if (lane == 0) {
     double dot = 0.0;
 #pragma unroll
     for (int a = 0; a < 6; ++a) {
-      double ss = ws[0][a], cc = wc[0][a];
-      for (int w = 1; w < RDT / 64; ++w) neumaier_merge(ss, cc, ws[w][a], wc[w][a]);
-      const double S = ss + cc;
-      dot += ddot_w(a) * d.E[a] * S;
+      const double S = s[a] + c[a];
+      dot += ddot_w(a) * defs[i].E[a] * S;
       if (S6) S6[6 * i + a] = S;
     }
     const double e = -h3c * dot - B[i];
     E[i] = e;
     if (E2) E2[i] = e;
   }
-  __syncthreads();  // ws and wc are rewritten by the caller's next defect
 }
 
-__global__ __launch_bounds__(RDT) void k_reduce(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
-                                                const int32_t* __restrict__ ids, const double* __restrict__ sig,
-                                                const double* __restrict__ B, double h3c,
-                                                double* __restrict__ S6, double* __restrict__ E) {
-  reduce_defect(defs, cnt, ids, sig, B, h3c, S6, E, nullptr, blockIdx.x);
+__global__ __launch_bounds__(64 * RDW) void k_reduce(const DevDefect* __restrict__ defs, const int32_t* __restrict__ cnt,
+                                                     const int32_t* __restrict__ ids, const double* __restrict__ sig,
+                                                     const double* __restrict__ B, double h3c,
+                                                     double* __restrict__ S6, double* __restrict__ E, int ndef) {
+  const int i = blockIdx.x * RDW + (int)(threadIdx.x >> 6);
+  if (i < ndef) reduce_defect(defs, cnt, ids, sig, B, h3c, S6, E, nullptr, i, (int)(threadIdx.x & 63));
 }
 
-// Batched hops: the energies of every defect of every job (a fixed grid walks
-// them, job after job), also into the job's output buffer when it has one.
-__global__ __launch_bounds__(RDT) void k_reduce_batch(const HopJob* __restrict__ jobs, int njob) {
+// Batched hops: the energies of every defect of every job (a fixed grid of
+// wavefronts walks them, job after job), also into the job's output buffer
+// when it has one.
+__global__ __launch_bounds__(64 * RDW) void k_reduce_batch(const HopJob* __restrict__ jobs, int njob) {
   int total = 0;
   for (int j = 0; j < njob; ++j) total += jobs[j].ndef;
-  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+  for (int item = blockIdx.x * RDW + (int)(threadIdx.x >> 6); item < total; item += gridDim.x * RDW) {
     int j = 0, first = 0;
     while (item >= first + jobs[j].ndef) first += jobs[j++].ndef;
     const HopJob& J = jobs[j];
-    reduce_defect(J.tab, J.cnt, J.ids, J.sig, J.B, J.h3c, J.S6, J.E, J.Eout, item - first);
+    reduce_defect(J.tab, J.cnt, J.ids, J.sig, J.B, J.h3c, J.S6, J.E, J.Eout, item - first, (int)(threadIdx.x & 63));
   }
 }
 
@@ -994,12 +987,13 @@ hipError_t launch_set_class(DevDefect* d, int ndef, const ClassTag* tags, hipStr
 hipError_t launch_reduce(const DevDefect* d, int ndef, const int32_t* counts, const int32_t* ids, const double* sig,
                          const double* B, double h3c, double* S6, double* E, hipStream_t s) {
   if (ndef == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(ndef), dim3(RDT), 0, s, d, counts, ids, sig, B, h3c, S6, E);
+  hipLaunchKernelGGL(k_reduce, dim3((ndef + RDW - 1) / RDW), dim3(64 * RDW), 0, s, d, counts, ids, sig, B, h3c, S6, E,
+                     ndef);
   return hipGetLastError();
 }
 
 hipError_t launch_hop_batch_energies(const HopJob* jobs, int njob, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_batch, dim3(1024), dim3(RDT), 0, s, jobs, njob);
+  hipLaunchKernelGGL(k_reduce_batch, dim3(1024), dim3(64 * RDW), 0, s, jobs, njob);
   return hipGetLastError();
 }
 
