@@ -1824,7 +1824,7 @@ ec_status ec_ctx_create(int device, size_t budget, ec_alloc_fn af, ec_free_fn ff
   c->ff = ff;
   c->user = user;
   const unsigned hw = std::thread::hardware_concurrency();
-  c->pool.reset(new WorkPool(hw > 2 ? (int)std::min(4u, hw - 1) : 0));
+  c->pool.reset(new WorkPool(hw > 2 ? (int)std::min(8u, hw - 1) : 0));
   *out = c;
   return EC_OK;
 }
