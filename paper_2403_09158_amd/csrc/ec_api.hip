@@ -289,6 +289,11 @@ struct ec_state {
   // defect list
   int ndef = 0;
   bool solved = false;
+  // The stress of the last solve is stored only at the voxels its defects
+  // cover (all that the energy reductions read); the rest is formed from the
+  // resident spectrum (the y inverse pass's output) when something first needs
+  // the whole field (ensure_sigma).
+  bool sig_lazy = false;
   std::vector<DevDefect> hdefs;
   std::vector<int32_t> hcnt;  // host copy of the counts, valid when hcnt_ok
   bool hcnt_ok = false;
@@ -915,7 +920,7 @@ ec_status join_self(ec_state* st, hipStream_t s);
 ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, const int2* lnk, const DevDefect* defs,
                    int ndef, void* spec, double* sig, const double* add6, uint32_t* ctr,
                    const std::function<ec_status()>& between = {}, const double* bg = nullptr, int bg_mask = 0,
-                   const double* bg3 = nullptr) {
+                   const double* bg3 = nullptr, bool covered_only = false) {
   const Prune full{0, st->n, 0, st->n};
   const double sb = spec_valid_bytes(st, fp64), fb = 48.0 * (double)st->n3;
   SpecGeom g{st->n, 0};
@@ -929,8 +934,24 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
   }
   LAUNCH(st, s, PF_Z, 2 * sb, launch_z_green(fp64, spec, g, st->C, full, st->tw, ctr ? ctr + 8 : nullptr, s));
   LAUNCH(st, s, PF_Y, 2 * sb, launch_pencil(fp64, true, 1, spec, g, full, st->tw, ctr ? ctr + 16 : nullptr, s));
+  // covered_only: the spectrum and the owner map are read, and the stress is
+  // stored at the covered voxels only (their bytes not counted here)
+  LAUNCH(st, s, PF_XI, covered_only ? sb + 4.0 * (double)st->n3 : sb + (bg3 ? 2 : 1) * fb,
+         launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s, bg, bg_mask, bg3, covered_only ? own : nullptr));
+  return EC_OK;
+}
+
+// The whole stress field of the last solve, where it was stored only at the
+// covered voxels: the x inverse pass again over the resident spectrum, with the
+// mean term and the dislocation stresses the solve added.  Called by every
+// entry point that reads the stress at other voxels or overwrites the spectrum.
+ec_status ensure_sigma(ec_state* st, hipStream_t s) {
+  if (!st->sig_lazy) return EC_OK;
+  const double sb = spec_valid_bytes(st, st->fp64), fb = 48.0 * (double)st->n3;
+  const double* bg3 = st->bg3_on ? st->bg3 : nullptr;
   LAUNCH(st, s, PF_XI, sb + (bg3 ? 2 : 1) * fb,
-         launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s, bg, bg_mask, bg3));
+         launch_x_inverse(st->fp64, false, st->spec, st->sig, st->g, st->add6, st->tw, s, st->bg, st->bg_mask, bg3));
+  st->sig_lazy = false;
   return EC_OK;
 }
 
@@ -1274,6 +1295,10 @@ ec_status copy_small(ec_state* st, void* dst, const void* src, size_t bytes, boo
 }
 
 ec_status write_field(ec_state* st, int which, void* out, bool on_device, hipStream_t s) {
+  {
+    const ec_status r0 = ensure_sigma(st, s);
+    if (r0 != EC_OK) return r0;
+  }
   const bool f32 = !st->fp64;
   const size_t bytes = (size_t)6 * st->n3 * (f32 ? 4 : 8);
   if (on_device) {
@@ -1498,9 +1523,10 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
   };
   // the stress of dislocation lines, if any, is added by the x inverse pass
   r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, ndef, st->spec, st->sig, st->add6, st->tilectr, beside, st->bg,
-               st->bg_mask, st->bg3_on ? st->bg3 : nullptr);
+               st->bg_mask, st->bg3_on ? st->bg3 : nullptr, true);
   if (r != EC_OK) return r;
   st->solved = true;
+  st->sig_lazy = true;
   return EC_OK;
 }
 
@@ -1554,6 +1580,7 @@ ec_status update_q(ec_state* st, int32_t idx, DevDefect nd, hipStream_t s) {
   {
     ec_status rc = join_self(st, s);
     if (rc == EC_OK) rc = ensure_classes(st, s);
+    if (rc == EC_OK) rc = ensure_sigma(st, s);  // the update adds to the whole field
     if (rc != EC_OK) return rc;
   }
   st->jdE_ok = false;
@@ -2190,6 +2217,7 @@ ec_status ec_update_batch(ec_state* const* states, const int32_t* idx, const ec_
     ec_state* st = states[j];
     if ((r = join_self(st, s)) != EC_OK) return r;
     if (!st->B_valid && (r = compute_self_terms(st, s)) != EC_OK) return r;
+    if ((r = ensure_sigma(st, s)) != EC_OK) return r;  // the hops add to the whole field
   }
   BatchKey key{st0->n, st0->fp64 ? 0 : 1, k, st0->C.C11, st0->C.C12, st0->C.C44, st0->frame, stream};
   BatchEntry* e = nullptr;
@@ -2250,6 +2278,10 @@ ec_status ec_state_footprints(ec_state* st, int32_t* counts, int32_t* ids, int64
 
 ec_status ec_state_field(ec_state* st, int32_t which, double* out) {
   if (!st || !out) return fail(EC_ERR_ARG, "NULL argument");
+  {
+    const ec_status r0 = ensure_sigma(st, nullptr);
+    if (r0 != EC_OK) return r0;
+  }
   HIPCHK(hipDeviceSynchronize());
   const size_t cnt = (size_t)6 * st->n3;
   if (which >= 0 && which <= 2) {
@@ -2345,6 +2377,7 @@ ec_status ec_jump_energies(ec_state* st, const int32_t* jumps, int32_t njump, vo
   }
   ec_status r;
   if ((r = join_self(st, s)) != EC_OK) return r;
+  if ((r = ensure_sigma(st, s)) != EC_OK) return r;  // the jumped footprints leave the covered voxels
   if ((r = ensure_classes(st, s)) != EC_OK) return r;
   if ((r = ensure_windows(st, reach, s)) != EC_OK) return r;
   if (!st->B_valid && (r = compute_self_terms(st, s)) != EC_OK) return r;
@@ -2540,6 +2573,8 @@ ec_status ec_set_dislocations(ec_state* st, const ec_line* lines, int32_t nlines
   }
   hipStream_t s = (hipStream_t)stream;
   ec_status r;
+  // the whole field with the old lines' stress, before it is exchanged
+  if ((r = ensure_sigma(st, s)) != EC_OK) return r;
   const size_t nn = (size_t)n * n;
   if ((r = st_grow(st, &st->bg, &st->bg_cap, 3 * nn * 6, true, s)) != EC_OK ||
       (r = st_grow(st, &st->bgspec, &st->bgspec_cap, 12 * nn)) != EC_OK ||
@@ -2631,6 +2666,9 @@ ec_status ec_set_dislocation_paths(ec_state* st, const ec_path* paths, int32_t n
   }
   hipStream_t s = (hipStream_t)stream;
   ec_status r;
+  // the whole field with the old loops' stress, before the spectrum is reused
+  // for the new ones and their stress exchanged
+  if ((r = ensure_sigma(st, s)) != EC_OK) return r;
   if (pieces.empty()) {  // remove the paths
     if (st->bg3_on) {
       if ((r = join_self(st, s)) != EC_OK) return r;
@@ -2683,6 +2721,7 @@ ec_status ec_dipole_energies(ec_state* st, void* stream, double* E_out, int32_t 
   hipStream_t s = (hipStream_t)stream;
   ec_status r;
   if ((r = join_self(st, s)) != EC_OK) return r;
+  if ((r = ensure_sigma(st, s)) != EC_OK) return r;  // the stress at the centres
   if ((r = ensure_classes(st, s)) != EC_OK) return r;
   if ((r = ensure_windows(st, 0, s)) != EC_OK) return r;
   if ((r = st_grow(st, &st->dip, &st->dip_cap, (size_t)nd)) != EC_OK) return r;
@@ -2840,6 +2879,10 @@ ec_status ec_type_energies(ec_state* st, int32_t type, const double* X, int32_t 
       if (!std::isfinite(X_excl[a])) return fail(EC_ERR_ARG, "excluded position is not finite");
   if (k == 0) return EC_OK;
   hipStream_t s = (hipStream_t)stream;
+  {
+    const ec_status r0 = ensure_sigma(st, s);  // the whole resident field is transformed
+    if (r0 != EC_OK) return r0;
+  }
   const int n = st->n;
   const double L = st->prob.L;
   const int grid = type_energy_grid(n);

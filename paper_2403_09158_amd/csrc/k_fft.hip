@@ -1030,11 +1030,14 @@ __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__
 // ([3][n^2][6], FP64) are added as well.
 // BATCH: njob hops of a batch, N N / ROWS blocks each, a job's spectrum and
 // stress from its record (spec and sig unused).
-template <int N, typename S, bool ACC, bool BG, bool BATCH = false>
+// MASK: the stress is stored only at voxels some defect covers (own[v] != -1),
+// the voxels an energy reduction reads; the others keep what they held.
+template <int N, typename S, bool ACC, bool BG, bool BATCH = false, bool MASK = false>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
     const typename Cplx<S>::T* __restrict__ spec, double* __restrict__ sig, const double* __restrict__ mean6,
     const double2* __restrict__ twg, const double* __restrict__ bg, int bg_mask,
-    const HopJob* __restrict__ jobs = nullptr, const double* add3 = nullptr) {
+    const HopJob* __restrict__ jobs = nullptr, const double* add3 = nullptr,
+    const int32_t* __restrict__ own = nullptr) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;
   constexpr int T = pick_T(max_nb(N, NF));
@@ -1092,9 +1095,20 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   constexpr int NSL = PLX.nstage == 1 ? 1 : (PLX.nstage == 2 ? PLX.r[0] : PLX.r[0] * PLX.r[1]);
   constexpr int NOUT = ((NF * (N / RL) + T - 1) / T) * RL;
   double2 old[ACC ? NOUT : 1];
+  int32_t ow[MASK ? NOUT : 1];
+  if constexpr (MASK)
+    for_outputs<N, RL, NSL, Map::Row, NF, T>(
+        [&](int f, int x, int slot) { ow[slot] = own[(z * N + y0 + f / 3) * N + x]; });
   if constexpr (ACC)
-    for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) { old[slot] = add_at(f, x); });
+    for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) {
+      if (!MASK || ow[slot] != -1)
+        old[slot] = add_at(f, x);
+      else
+        old[slot] = make_double2(0.0, 0.0);
+    });
   auto store_last = [&](int f, int x, double2 v, int slot) {
+    if constexpr (MASK)
+      if (ow[slot] == -1) return;
     const int p = f % 3, y = y0 + f / 3;
     double2* s01 = sig_at(f, x);
     double2 r = make_double2(v.x * scale + mean_s[2 * p], v.y * scale + mean_s[2 * p + 1]);
@@ -1202,25 +1216,32 @@ hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const
   return hipGetLastError();
 }
 
-template <int N, typename S>
-hipError_t go_xi(bool acc, const void* spec, double* sig, SpecGeom g, const double* mean6, const double2* tw,
-                 const double* bg, int bg_mask, const double* add3, hipStream_t s) {
+template <int N, typename S, bool ACC, bool BG>
+void go_xi_k(const void* spec, double* sig, const double* mean6, const double2* tw, const double* bg, int bg_mask,
+             const double* add3, const int32_t* own, hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   const int grid = N * (N / x_rows(N));
   using C2 = typename Cplx<S>::T;
-  if (g.P != spec_pitch(N, sizeof(S) == 8) || (acc && add3)) return hipErrorInvalidValue;
-  if (add3 && bg && bg_mask)
-    hipLaunchKernelGGL((k_x_inverse<N, S, true, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
-                       bg, bg_mask, (const HopJob*)nullptr, add3);
-  else if (acc || add3)
-    hipLaunchKernelGGL((k_x_inverse<N, S, true, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
-                       bg, 0, (const HopJob*)nullptr, add3);
-  else if (bg && bg_mask)
-    hipLaunchKernelGGL((k_x_inverse<N, S, false, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
-                       bg, bg_mask, (const HopJob*)nullptr);
+  if (own)
+    hipLaunchKernelGGL((k_x_inverse<N, S, ACC, BG, false, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig,
+                       mean6, tw, bg, BG ? bg_mask : 0, (const HopJob*)nullptr, add3, own);
   else
-    hipLaunchKernelGGL((k_x_inverse<N, S, false, false>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw,
-                       bg, 0, (const HopJob*)nullptr);
+    hipLaunchKernelGGL((k_x_inverse<N, S, ACC, BG>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw, bg,
+                       BG ? bg_mask : 0, (const HopJob*)nullptr, add3);
+}
+
+template <int N, typename S>
+hipError_t go_xi(bool acc, const void* spec, double* sig, SpecGeom g, const double* mean6, const double2* tw,
+                 const double* bg, int bg_mask, const double* add3, const int32_t* own, hipStream_t s) {
+  if (g.P != spec_pitch(N, sizeof(S) == 8) || (acc && add3) || (acc && own)) return hipErrorInvalidValue;
+  if (add3 && bg && bg_mask)
+    go_xi_k<N, S, true, true>(spec, sig, mean6, tw, bg, bg_mask, add3, own, s);
+  else if (acc || add3)
+    go_xi_k<N, S, true, false>(spec, sig, mean6, tw, bg, 0, add3, own, s);
+  else if (bg && bg_mask)
+    go_xi_k<N, S, false, true>(spec, sig, mean6, tw, bg, bg_mask, nullptr, own, s);
+  else
+    go_xi_k<N, S, false, false>(spec, sig, mean6, tw, bg, 0, nullptr, own, s);
   return hipGetLastError();
 }
 
@@ -1391,12 +1412,13 @@ hipError_t launch_hop_batch_fft(bool fp64, const HopJob* jobs, int njob, SpecGeo
 }
 
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
-                            const double2* tw, hipStream_t s, const double* bg, int bg_mask, const double* add3) {
+                            const double2* tw, hipStream_t s, const double* bg, int bg_mask, const double* add3,
+                            const int32_t* own) {
   switch (g.n) {
-#define EC_CASE(NN)                                                                         \
-  case NN:                                                                                  \
-    return fp64 ? go_xi<NN, double>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, s) \
-                : go_xi<NN, float>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, s);
+#define EC_CASE(NN)                                                                              \
+  case NN:                                                                                       \
+    return fp64 ? go_xi<NN, double>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, own, s) \
+                : go_xi<NN, float>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, own, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }
