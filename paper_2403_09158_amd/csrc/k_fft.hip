@@ -1096,9 +1096,15 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   constexpr int NOUT = ((NF * (N / RL) + T - 1) / T) * RL;
   double2 old[ACC ? NOUT : 1];
   int32_t ow[MASK ? NOUT : 1];
-  if constexpr (MASK)
-    for_outputs<N, RL, NSL, Map::Row, NF, T>(
-        [&](int f, int x, int slot) { ow[slot] = own[(z * N + y0 + f / 3) * N + x]; });
+  if constexpr (MASK) {
+    bool any = false;
+    for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) {
+      ow[slot] = own[(z * N + y0 + f / 3) * N + x];
+      any |= ow[slot] != -1;
+    });
+    // rows that no defect covers store nothing: their transform is skipped
+    if (!__syncthreads_or(any)) return;
+  }
   if constexpr (ACC)
     for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) {
       if (!MASK || ow[slot] != -1)
