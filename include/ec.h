@@ -155,10 +155,11 @@ EC_API ec_status ec_state_bytes(const ec_state* st, size_t* bytes);
 
 /* Full solve (Sec. 3.2, 3.4): rasterise defs[0..ndef) (host array, copied),
  * Fourier-space Green solve, sigma = C:(eps - eps*) kept resident in FP64.
- * The solve stores sigma at the voxels the defects cover (all that the
- * energies read) and keeps the stress spectrum; the rest of the field is
- * formed, bit for bit as the solve would have, by the first call that needs
- * it (field outputs, updates, jump probes, dipole energies, dislocations,
+ * When nothing read the whole stress field since the state's previous solve,
+ * the solve stores sigma only at the voxels the defects cover (all that the
+ * energies read) and keeps the stress spectrum; the rest of the field is then
+ * formed, bit for bit as a whole-field solve would have, by the first call that
+ * needs it (field outputs, updates, jump probes, dipole energies, dislocations,
  * stored-type energies), on that call's stream.
  * Optional outputs eps_out / sig_out ([6][n^3], float for EC_FP32 states,
  * double for EC_FP64 states) on the device (out_on_device != 0) or on the host;

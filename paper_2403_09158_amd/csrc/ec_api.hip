@@ -292,8 +292,12 @@ struct ec_state {
   // The stress of the last solve is stored only at the voxels its defects
   // cover (all that the energy reductions read); the rest is formed from the
   // resident spectrum (the y inverse pass's output) when something first needs
-  // the whole field (ensure_sigma).
+  // the whole field (ensure_sigma).  A solve stores only the covered voxels
+  // when nothing read the whole field since the solve before it (a caller
+  // that reads it after every solve, an OkMC loop or a serving replica
+  // between hops, gets it stored at once instead of formed twice).
   bool sig_lazy = false;
+  bool whole_read = false;  // the whole field was needed since the last solve
   std::vector<DevDefect> hdefs;
   std::vector<int32_t> hcnt;  // host copy of the counts, valid when hcnt_ok
   bool hcnt_ok = false;
@@ -561,9 +565,14 @@ hipError_t run(ec_state* st, hipStream_t s, int fam, double bytes, F&& f) {
 // ------------------------------------------------------------------ twiddles
 
 double2* ctx_twiddles(ec_ctx* c, int n) {
-  std::lock_guard<std::mutex> lk(c->mu);
-  auto it = c->tw.find(n);
-  if (it != c->tw.end()) return it->second;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->tw.find(n);
+    if (it != c->tw.end()) return it->second;
+  }
+  // built and allocated without the lock: an allocator the caller supplies may
+  // run code that re-enters the library (a garbage collector destroying
+  // another state, say), which takes the lock
   std::vector<double2> h(n);
   const long double pi = acosl(-1.0L);
   for (int e = 0; e < n; ++e) {
@@ -576,8 +585,16 @@ double2* ctx_twiddles(ec_ctx* c, int n) {
     raw_free(c, p);
     return nullptr;
   }
-  c->tw[n] = (double2*)p;
-  return (double2*)p;
+  void* drop = nullptr;
+  double2* out = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto ins = c->tw.emplace(n, (double2*)p);
+    if (!ins.second) drop = p;  // another thread made the table meanwhile
+    out = ins.first->second;
+  }
+  raw_free(c, drop);
+  return out;
 }
 
 // ------------------------------------------------------------------ quantisation
@@ -946,6 +963,7 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
 // mean term and the dislocation stresses the solve added.  Called by every
 // entry point that reads the stress at other voxels or overwrites the spectrum.
 ec_status ensure_sigma(ec_state* st, hipStream_t s) {
+  st->whole_read = true;
   if (!st->sig_lazy) return EC_OK;
   const double sb = spec_valid_bytes(st, st->fp64), fb = 48.0 * (double)st->n3;
   const double* bg3 = st->bg3_on ? st->bg3 : nullptr;
@@ -1522,11 +1540,13 @@ ec_status solve_table(ec_state* st, DevDefect* h, int32_t ndef, hipStream_t s, b
     return join_self(st, s);
   };
   // the stress of dislocation lines, if any, is added by the x inverse pass
+  const bool covered = !st->whole_read;
   r = pipeline(st, s, st->fp64, st->own, nb.lnk, nb.tab, ndef, st->spec, st->sig, st->add6, st->tilectr, beside, st->bg,
-               st->bg_mask, st->bg3_on ? st->bg3 : nullptr, true);
+               st->bg_mask, st->bg3_on ? st->bg3 : nullptr, covered);
   if (r != EC_OK) return r;
   st->solved = true;
-  st->sig_lazy = true;
+  st->sig_lazy = covered;
+  st->whole_read = false;
   return EC_OK;
 }
 
@@ -1805,10 +1825,14 @@ ec_status batch_entry(ec_ctx* c, const BatchKey& key, const ec_state* st0, Batch
     undo();
     return fail(EC_ERR_DEVICE, "batch buffer set-up: %s", hipGetErrorString(r));
   }
-  std::lock_guard<std::mutex> lk(c->mu);
-  auto ins = c->batches.emplace(key, e);
-  if (!ins.second) undo();  // another thread made the same entry meanwhile
-  *out = &ins.first->second;
+  bool dup = false;
+  {
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto ins = c->batches.emplace(key, e);
+    dup = !ins.second;  // another thread made the same entry meanwhile
+    *out = &ins.first->second;
+  }
+  if (dup) undo();  // outside the lock (the caller's free may re-enter the library)
   return EC_OK;
 }
 

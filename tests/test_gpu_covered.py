@@ -1,0 +1,109 @@
+"""The solve's stress stored at the covered voxels only (ec_solve_fields, as
+include/ec.h describes it): the whole field formed later is bitwise the one a
+solve storing the whole field leaves, the energies are bitwise the same either
+way, and the choice follows the caller (a solve stores only the covered voxels
+when nothing read the whole field since the solve before it).  Exercised with
+plain defects, with straight dislocation lines (their stress is added where the
+x inverse pass stores) and with dislocation loops (their stress field is read
+where it stores), in both precisions."""
+import numpy as np
+import pytest
+
+from paper_2403_09158_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2403_09158_amd import ec
+
+    return ec.Context()
+
+
+def _case(prec, n=32):
+    h = inputs.H_VOXEL
+    prob = inputs.Problem(n, n * h, *inputs.CUBIC_FE, prec=prec)
+    rng = np.random.default_rng(2403)
+    d = inputs.mixed_population(rng, 12, n * h, h, r111=(0.4, 1.2), r100=(0.5, 1.2))
+    return prob, d
+
+
+def _cycle(st, defs):
+    """solve + energies (nothing reads the whole field), then the whole field."""
+    st.solve(defs)
+    E = st.energies()
+    return E, st.field("sigma")
+
+
+def _lines(n):
+    h = inputs.H_VOXEL
+    bx = 0.5 * inputs.A_FE * np.sqrt(3.0) * np.array([1.0, 0.0, 0.0])
+    return np.concatenate([inputs.line(np.array([15.3, 16.8, 0.0]) * h, 2, 1, bx)])
+
+
+def _loop_paths(n):
+    h = inputs.H_VOXEL
+    c = np.array([9.3, 11.2, 12.7]) * h
+    n111 = np.array([1.0, 1.0, 1.0]) / np.sqrt(3.0)
+    e1 = np.array([1.0, -1.0, 0.0]) / np.sqrt(2.0)
+    e2 = np.cross(n111, e1)
+    ang = np.arange(6) * np.pi / 3.0
+    hexv = c + 3.1 * h * (np.cos(ang)[:, None] * e1 + np.sin(ang)[:, None] * e2)
+    return [(hexv, np.zeros(3), 0.5 * inputs.A_FE * np.array([1.0, 1.0, 1.0]))]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("extra", ["none", "lines", "loops"])
+def test_covered_voxels_then_whole_field_equals_whole_field_solve(ctx, prec, extra):
+    from paper_2403_09158_amd import ec
+
+    prob, defs = _case(prec)
+    st = ec.State(ctx, prob)
+    if extra == "lines":
+        st.set_dislocations(_lines(prob.n))
+    elif extra == "loops":
+        st.set_dislocation_paths(_loop_paths(prob.n))
+    # the first solve after the set-up reads nothing of the whole field before
+    # it: covered voxels only, the field formed on request
+    st.solve(defs)
+    st.solve(defs)
+    E_cov = st.energies()
+    F_formed = st.field("sigma")
+    # the field was read since that solve: the next one stores all of it
+    st.solve(defs)
+    E_whole = st.energies()
+    F_whole = st.field("sigma")
+    assert np.array_equal(E_cov, E_whole)
+    assert np.array_equal(F_formed, F_whole)
+    # and a solve after solves that nobody read the field of stores the covered
+    # voxels again, with the same energies
+    st.solve(defs)
+    st.solve(defs)
+    assert np.array_equal(st.energies(), E_whole)
+    st.close()
+
+
+def test_update_after_covered_solve_equals_update_after_whole_solve(ctx):
+    """A hop after a solve that stored only the covered voxels first forms the
+    whole field; the result equals the hop after a solve that stored it."""
+    from paper_2403_09158_amd import ec
+
+    prob, defs = _case(1)
+    h = prob.L / prob.n
+    moved = defs[3:4].copy()
+    moved["c"] += np.array([1.0, -1.0, 1.0]) * h
+    a = ec.State(ctx, prob)
+    a.solve(defs)  # covered voxels only (fresh state)
+    Ea = a.update(3, moved)
+    Fa = a.field("sigma")
+    b = ec.State(ctx, prob)
+    b.solve(defs)
+    b.field("sigma")  # reads the whole field: the next solve stores it
+    b.solve(defs)
+    Eb = b.update(3, moved)
+    Fb = b.field("sigma")
+    assert np.array_equal(Ea, Eb)
+    assert np.array_equal(Fa, Fb)
+    a.close()
+    b.close()
