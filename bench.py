@@ -209,7 +209,8 @@ def serving_block(nreq=4000, rate=2000.0, slots=4, plain_req=1000, budget_gb=200
     srv.warm()
     st = srv.run(serve.serving_requests(reps, nreq, rate), realtime=True)
     out["fp32_served"] = {"requests": nreq, "throughput_req_s": round(st.throughput, 1), "p50_ms": round(st.p50_ms, 4),
-                          "p99_ms": round(st.p99_ms, 4), "mean_ms": round(st.mean_ms, 4), "batches": st.batches}
+                          "p99_ms": round(st.p99_ms, 4), "mean_ms": round(st.mean_ms, 4), "batches": st.batches,
+                          "by_grid": st.by_grid()}
     st = srv.run(serve.serving_requests(reps, 3000, 1e9), realtime=False)
     out["fp32_saturated"] = {"requests": 3000, "throughput_req_s": round(st.throughput, 1),
                              "p99_ms_queued_at_t0": round(st.p99_ms, 2), "batches": st.batches}

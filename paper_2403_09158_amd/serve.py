@@ -24,7 +24,9 @@ The loop
     grid voxels in all, which ``ec_update_batch`` runs as one launch per pass,
     replayed from a HIP graph captured once per (shape, batch size, slot);
   * times every request from its arrival to the completion of the copy of its
-    energies to host memory, using device events.
+    energies to host memory, using device events, and splits that latency at
+    the request's dispatch (the wait for a slot or for its replica's previous
+    request, then the service on the device).
 
 All device work goes through the C ABI in ``libec.so``; this module only
 schedules it.  ``run_plain`` is the reference it is compared with: the same
@@ -111,6 +113,21 @@ class ServeStats:
     latency_ms: np.ndarray
     results: dict  # rid -> energies (when kept)
     batches: int = 0  # launches that carried two or more hops
+    wait_ms: np.ndarray = None  # arrival -> dispatch on the host, per request (arrival order)
+    grid: np.ndarray = None  # grid size of each request's replica (arrival order)
+
+    def by_grid(self):
+        """Latency percentiles per replica grid size: {n: {requests, p50_ms,
+        p99_ms, wait_p99_ms, service_p50_ms}} (service = latency - wait)."""
+        out = {}
+        for n in sorted(set(self.grid.tolist())):
+            m = self.grid == n
+            lat, wait = self.latency_ms[m], self.wait_ms[m]
+            out[int(n)] = {"requests": int(m.sum()), "p50_ms": round(float(np.median(lat)), 4),
+                           "p99_ms": round(float(np.quantile(lat, 0.99)), 4),
+                           "wait_p99_ms": round(float(np.quantile(wait, 0.99)), 4),
+                           "service_p50_ms": round(float(np.median(lat - wait)), 4)}
+        return out
 
 
 class Server:
@@ -262,6 +279,7 @@ class Server:
         t0 = time.perf_counter()
         arrive = np.array([r.t if realtime else 0.0 for r in reqs])
         done_t = np.zeros(n)
+        disp_t = np.zeros(n)
         results = {}
         order = {r.rid: i for i, r in enumerate(reqs)}
         ptr = 0
@@ -302,6 +320,7 @@ class Server:
                         slot = free.pop()
                         for g in group:
                             g.last_used = now
+                            disp_t[order[g.queue[0].rid]] = now
                         self._dispatch_batch(slot, group)
                         busy.append(slot)
                         continue
@@ -312,6 +331,7 @@ class Server:
                     slot = free.pop()
                     rep.last_used = now
                     if self._dispatch(slot, rep, rep.queue[0]):
+                        disp_t[order[rep.queue[0].rid]] = now
                         rep.queue.popleft()
                         busy.append(slot)
                     else:  # over budget until running requests finish
@@ -352,6 +372,8 @@ class Server:
             latency_ms=lat,
             results=results,
             batches=self.batches - batches0,
+            wait_ms=np.maximum(disp_t - arrive, 0.0) * 1e3,
+            grid=np.array([self.reps[r.replica].problem.n for r in reqs]),
         )
 
     def close(self):

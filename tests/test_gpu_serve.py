@@ -131,6 +131,12 @@ def test_realtime_latency_bookkeeping():
     assert stats.completed == len(reqs)
     assert np.all(stats.latency_ms > 0)
     assert stats.p50_ms <= stats.p99_ms
+    # every request waits a non-negative time before its dispatch, which comes
+    # before its completion (host and device clocks agree to well under 0.1 ms)
+    assert np.all(stats.wait_ms >= 0) and np.all(stats.wait_ms <= stats.latency_ms + 0.1)
+    g = stats.by_grid()
+    assert sum(v["requests"] for v in g.values()) == len(reqs)
+    assert set(g) == {p.n for p, _ in reps}
     # the trace spans about 80 / 4000 s; the loop cannot finish before the last arrival
     assert stats.wall_s >= max(r.t for r in reqs)
 

@@ -46,3 +46,18 @@ def test_moved_defect_is_a_whole_voxel_hop():
     for f in ("kind", "radius", "b", "normal", "thickness", "eig_v"):
         assert np.array_equal(d[f], defs[3][f])
     assert not np.shares_memory(d, defs)
+
+
+def test_latency_split_by_grid():
+    # four requests on two grid sizes; service = latency - wait per request
+    lat = np.array([1.0, 3.0, 2.0, 6.0])
+    wait = np.array([0.0, 1.0, 0.5, 4.0])
+    st = serve.ServeStats(completed=4, wall_s=1.0, throughput=4.0, p50_ms=2.5, p99_ms=6.0, mean_ms=3.0, admissions=0,
+                          evictions=0, latency_ms=lat, results={}, wait_ms=wait, grid=np.array([64, 240, 64, 240]))
+    g = st.by_grid()
+    assert sorted(g) == [64, 240]
+    assert g[64]["requests"] == 2 and g[240]["requests"] == 2
+    assert g[64]["p50_ms"] == 1.5 and g[240]["p50_ms"] == 4.5
+    assert g[64]["service_p50_ms"] == 1.25 and g[240]["service_p50_ms"] == 2.0
+    assert abs(g[240]["wait_p99_ms"] - (1.0 + 0.99 * 3.0)) < 1e-9
+    assert abs(g[240]["p99_ms"] - (3.0 + 0.99 * 3.0)) < 1e-9
