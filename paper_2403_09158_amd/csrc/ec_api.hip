@@ -2302,6 +2302,9 @@ ec_status ec_state_footprints(ec_state* st, int32_t* counts, int32_t* ids, int64
 
 ec_status ec_state_field(ec_state* st, int32_t which, double* out) {
   if (!st || !out) return fail(EC_ERR_ARG, "NULL argument");
+  // the state's earlier work may still run on another stream (which the null
+  // stream need not wait for): it ends before the whole stress is formed
+  HIPCHK(hipDeviceSynchronize());
   {
     const ec_status r0 = ensure_sigma(st, nullptr);
     if (r0 != EC_OK) return r0;
@@ -2329,6 +2332,7 @@ ec_status ec_state_self_terms(ec_state* st, double* out) {
   if (!st || !out) return fail(EC_ERR_ARG, "NULL argument");
   if (!st->solved) return fail(EC_ERR_STATE, "no solve on this state yet");
   ec_status r;
+  HIPCHK(hipDeviceSynchronize());  // earlier work of the state on other streams
   if (!st->B_valid && (r = compute_self_terms(st, nullptr)) != EC_OK) return r;
   HIPCHK(hipDeviceSynchronize());
   if (st->ndef > 0) HIPCHK(hipMemcpy(out, st->B, st->ndef * 8, hipMemcpyDeviceToHost));

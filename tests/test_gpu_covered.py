@@ -107,3 +107,29 @@ def test_update_after_covered_solve_equals_update_after_whole_solve(ctx):
     assert np.array_equal(Fa, Fb)
     a.close()
     b.close()
+
+
+def test_whole_field_waits_for_a_solve_on_another_stream(ctx):
+    """ec_state_field forms the whole field on the null stream after a covered
+    solve enqueued on a non-blocking stream (which the null stream does not wait
+    for): the call first waits for the solve, so the field is the one the same
+    solve gives when it runs on the null stream."""
+    import torch
+
+    from paper_2403_09158_amd import ec
+
+    prob, defs = inputs.mixed_256(prec=1)
+    s = torch.cuda.Stream()
+    a = ec.State(ctx, prob)
+    a.solve(defs)
+    a.energies()
+    torch.cuda.synchronize()
+    a.solve(defs, stream=s)  # covered voxels; about a millisecond of kernels
+    Fa = a.field("sigma")  # no synchronisation between the two calls
+    torch.cuda.synchronize()
+    a.close()
+    b = ec.State(ctx, prob)
+    b.solve(defs)
+    Fb = b.field("sigma")
+    b.close()
+    assert np.array_equal(Fa, Fb)
