@@ -21,11 +21,11 @@ def ctx():
     return ec.Context()
 
 
-def _case(prec, n=32):
+def _case(prec, n=32, ndef=12):
     h = inputs.H_VOXEL
     prob = inputs.Problem(n, n * h, *inputs.CUBIC_FE, prec=prec)
     rng = np.random.default_rng(2403)
-    d = inputs.mixed_population(rng, 12, n * h, h, r111=(0.4, 1.2), r100=(0.5, 1.2))
+    d = inputs.mixed_population(rng, ndef, n * h, h, r111=(0.4, 1.2), r100=(0.5, 1.2))
     return prob, d
 
 
@@ -54,11 +54,13 @@ def _loop_paths(n):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("extra", ["none", "lines", "loops"])
+@pytest.mark.parametrize("extra", ["none", "lines", "loops", "dense"])
 def test_covered_voxels_then_whole_field_equals_whole_field_solve(ctx, prec, extra):
+    """dense: 600 defects on 64^3, whose boxes span more x rows than the grid
+    has (nearly every row group of the covered-voxel pass stores)."""
     from paper_2403_09158_amd import ec
 
-    prob, defs = _case(prec)
+    prob, defs = _case(prec, 64, 600) if extra == "dense" else _case(prec)
     st = ec.State(ctx, prob)
     if extra == "lines":
         st.set_dislocations(_lines(prob.n))
