@@ -1031,7 +1031,10 @@ __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__
 // BATCH: njob hops of a batch, N N / ROWS blocks each, a job's spectrum and
 // stress from its record (spec and sig unused).
 // MASK: the stress is stored only at voxels some defect covers (own[v] != -1),
-// the voxels an energy reduction reads; the others keep what they held.
+// the voxels an energy reduction reads; the others keep what they held.  With
+// own null every voxel is stored: the pass that forms the whole field runs
+// this same code, so a covered voxel gets the same bits either way (separate
+// code for the two could fuse multiplies and adds differently).
 template <int N, typename S, bool ACC, bool BG, bool BATCH = false, bool MASK = false>
 __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
     const typename Cplx<S>::T* __restrict__ spec, double* __restrict__ sig, const double* __restrict__ mean6,
@@ -1099,7 +1102,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   if constexpr (MASK) {
     bool any = false;
     for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) {
-      ow[slot] = own[(z * N + y0 + f / 3) * N + x];
+      ow[slot] = own ? own[(z * N + y0 + f / 3) * N + x] : 0;
       any |= ow[slot] != -1;
     });
     // rows that no defect covers store nothing: their transform is skipped
@@ -1228,7 +1231,9 @@ void go_xi_k(const void* spec, double* sig, const double* mean6, const double2* 
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   const int grid = N * (N / x_rows(N));
   using C2 = typename Cplx<S>::T;
-  if (own)
+  // every pass but the accumulating one of an update (sig += the inverse):
+  // covered voxels (own) or all of them (own null) by the same code
+  if (own || !ACC || add3)
     hipLaunchKernelGGL((k_x_inverse<N, S, ACC, BG, false, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig,
                        mean6, tw, bg, BG ? bg_mask : 0, (const HopJob*)nullptr, add3, own);
   else

@@ -54,13 +54,24 @@ def _loop_paths(n):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("extra", ["none", "lines", "loops", "dense"])
+@pytest.mark.parametrize("extra", ["none", "lines", "loops", "dense", "frame", "odd", "paper129"])
 def test_covered_voxels_then_whole_field_equals_whole_field_solve(ctx, prec, extra):
     """dense: 600 defects on 64^3, whose boxes span more x rows than the grid
-    has (nearly every row group of the covered-voxel pass stores)."""
+    has (nearly every row group of the covered-voxel pass stores); frame: the
+    crystal rotated to the paper's cell axes; odd: a 45^3 grid; paper129: the
+    paper's 129^3 grid (length-43 stages)."""
     from paper_2403_09158_amd import ec
 
-    prob, defs = _case(prec, 64, 600) if extra == "dense" else _case(prec)
+    if extra == "dense":
+        prob, defs = _case(prec, 64, 600)
+    elif extra == "odd":
+        prob, defs = _case(prec, 45, 20)
+    elif extra == "paper129":
+        prob, defs = _case(prec, 129, 200)
+    else:
+        prob, defs = _case(prec)
+    if extra == "frame":
+        prob = prob.with_(frame=inputs.FRAME_111)
     st = ec.State(ctx, prob)
     if extra == "lines":
         st.set_dislocations(_lines(prob.n))
