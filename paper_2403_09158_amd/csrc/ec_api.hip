@@ -954,7 +954,7 @@ ec_status pipeline(ec_state* st, hipStream_t s, bool fp64, const int32_t* own, c
   // covered_only: the spectrum and the owner map are read, and the stress is
   // stored at the covered voxels only (their bytes not counted here)
   LAUNCH(st, s, PF_XI, covered_only ? sb + 4.0 * (double)st->n3 : sb + (bg3 ? 2 : 1) * fb,
-         launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s, bg, bg_mask, bg3, covered_only ? own : nullptr));
+         launch_x_inverse(fp64, false, spec, sig, g, add6, st->tw, s, bg, bg_mask, bg3, own, !covered_only));
   return EC_OK;
 }
 
@@ -968,7 +968,8 @@ ec_status ensure_sigma(ec_state* st, hipStream_t s) {
   const double sb = spec_valid_bytes(st, st->fp64), fb = 48.0 * (double)st->n3;
   const double* bg3 = st->bg3_on ? st->bg3 : nullptr;
   LAUNCH(st, s, PF_XI, sb + (bg3 ? 2 : 1) * fb,
-         launch_x_inverse(st->fp64, false, st->spec, st->sig, st->g, st->add6, st->tw, s, st->bg, st->bg_mask, bg3));
+         launch_x_inverse(st->fp64, false, st->spec, st->sig, st->g, st->add6, st->tw, s, st->bg, st->bg_mask, bg3,
+                          st->own, true));
   st->sig_lazy = false;
   return EC_OK;
 }

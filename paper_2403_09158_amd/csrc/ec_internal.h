@@ -392,10 +392,11 @@ hipError_t launch_z_green(bool fp64, void* spec, SpecGeom g, Cubic C, Prune pr, 
 // bg / bg_mask: stress planes of dislocation lines added to sigma (not with accum).
 // add3: a stress field [n^3][6] (FP64) added to sigma (not with accum).
 // own: the owner map; when given, sigma is stored only at voxels some defect
-// covers (not with accum).
+// covers (not with accum), or with all at every voxel by the same code, so
+// that both give a covered voxel the same bits.
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
                             const double2* tw, hipStream_t s, const double* bg = nullptr, int bg_mask = 0,
-                            const double* add3 = nullptr, const int32_t* own = nullptr);
+                            const double* add3 = nullptr, const int32_t* own = nullptr, bool all = false);
 // The Fourier passes of a batch of hops (jobs: njob device records, see
 // HopJob; ctr: NTILECTR tile counters, zeroed by the first pass): sparse x
 // forward, pruned y forward, fused z pass, y inverse, accumulating x inverse

@@ -1030,9 +1030,9 @@ __global__ __launch_bounds__(256) void k_green(typename Cplx<S>::T* __restrict__
 // ([3][n^2][6], FP64) are added as well.
 // BATCH: njob hops of a batch, N N / ROWS blocks each, a job's spectrum and
 // stress from its record (spec and sig unused).
-// MASK: the stress is stored only at voxels some defect covers (own[v] != -1),
-// the voxels an energy reduction reads; the others keep what they held.  With
-// own null every voxel is stored: the pass that forms the whole field runs
+// MASK: the stress is stored only at voxels some defect covers (own[v] & keep
+// != -1), the voxels an energy reduction reads; the others keep what they
+// held.  keep = 0 stores every voxel: the pass that forms the whole field runs
 // this same code, so a covered voxel gets the same bits either way (separate
 // code for the two could fuse multiplies and adds differently).
 template <int N, typename S, bool ACC, bool BG, bool BATCH = false, bool MASK = false>
@@ -1040,7 +1040,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
     const typename Cplx<S>::T* __restrict__ spec, double* __restrict__ sig, const double* __restrict__ mean6,
     const double2* __restrict__ twg, const double* __restrict__ bg, int bg_mask,
     const HopJob* __restrict__ jobs = nullptr, const double* add3 = nullptr,
-    const int32_t* __restrict__ own = nullptr) {
+    const int32_t* __restrict__ own = nullptr, int32_t keep = -1) {
   constexpr int ROWS = x_rows(N);
   constexpr int NF = 3 * ROWS;
   constexpr int T = pick_T(max_nb(N, NF));
@@ -1102,7 +1102,7 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   if constexpr (MASK) {
     bool any = false;
     for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) {
-      ow[slot] = own ? own[(z * N + y0 + f / 3) * N + x] : 0;
+      ow[slot] = own[(z * N + y0 + f / 3) * N + x] & keep;
       any |= ow[slot] != -1;
     });
     // rows that no defect covers store nothing: their transform is skipped
@@ -1227,15 +1227,14 @@ hipError_t go_pencil(bool inv, int axis, void* spec, SpecGeom g, Prune pr, const
 
 template <int N, typename S, bool ACC, bool BG>
 void go_xi_k(const void* spec, double* sig, const double* mean6, const double2* tw, const double* bg, int bg_mask,
-             const double* add3, const int32_t* own, hipStream_t s) {
+             const double* add3, const int32_t* own, bool all, hipStream_t s) {
   constexpr int T = pick_T(max_nb(N, 3 * x_rows(N)));
   const int grid = N * (N / x_rows(N));
   using C2 = typename Cplx<S>::T;
-  // every pass but the accumulating one of an update (sig += the inverse):
-  // covered voxels (own) or all of them (own null) by the same code
-  if (own || !ACC || add3)
+  // with an owner map: the covered voxels, or all of them (all) by the same code
+  if (own)
     hipLaunchKernelGGL((k_x_inverse<N, S, ACC, BG, false, true>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig,
-                       mean6, tw, bg, BG ? bg_mask : 0, (const HopJob*)nullptr, add3, own);
+                       mean6, tw, bg, BG ? bg_mask : 0, (const HopJob*)nullptr, add3, own, all ? 0 : -1);
   else
     hipLaunchKernelGGL((k_x_inverse<N, S, ACC, BG>), dim3(grid), dim3(T), 0, s, (const C2*)spec, sig, mean6, tw, bg,
                        BG ? bg_mask : 0, (const HopJob*)nullptr, add3);
@@ -1243,16 +1242,16 @@ void go_xi_k(const void* spec, double* sig, const double* mean6, const double2* 
 
 template <int N, typename S>
 hipError_t go_xi(bool acc, const void* spec, double* sig, SpecGeom g, const double* mean6, const double2* tw,
-                 const double* bg, int bg_mask, const double* add3, const int32_t* own, hipStream_t s) {
+                 const double* bg, int bg_mask, const double* add3, const int32_t* own, bool all, hipStream_t s) {
   if (g.P != spec_pitch(N, sizeof(S) == 8) || (acc && add3) || (acc && own)) return hipErrorInvalidValue;
   if (add3 && bg && bg_mask)
-    go_xi_k<N, S, true, true>(spec, sig, mean6, tw, bg, bg_mask, add3, own, s);
+    go_xi_k<N, S, true, true>(spec, sig, mean6, tw, bg, bg_mask, add3, own, all, s);
   else if (acc || add3)
-    go_xi_k<N, S, true, false>(spec, sig, mean6, tw, bg, 0, add3, own, s);
+    go_xi_k<N, S, true, false>(spec, sig, mean6, tw, bg, 0, add3, own, all, s);
   else if (bg && bg_mask)
-    go_xi_k<N, S, false, true>(spec, sig, mean6, tw, bg, bg_mask, nullptr, own, s);
+    go_xi_k<N, S, false, true>(spec, sig, mean6, tw, bg, bg_mask, nullptr, own, all, s);
   else
-    go_xi_k<N, S, false, false>(spec, sig, mean6, tw, bg, 0, nullptr, own, s);
+    go_xi_k<N, S, false, false>(spec, sig, mean6, tw, bg, 0, nullptr, own, all, s);
   return hipGetLastError();
 }
 
@@ -1424,12 +1423,12 @@ hipError_t launch_hop_batch_fft(bool fp64, const HopJob* jobs, int njob, SpecGeo
 
 hipError_t launch_x_inverse(bool fp64, bool accum, const void* spec, double* sig, SpecGeom g, const double* mean6,
                             const double2* tw, hipStream_t s, const double* bg, int bg_mask, const double* add3,
-                            const int32_t* own) {
+                            const int32_t* own, bool all) {
   switch (g.n) {
 #define EC_CASE(NN)                                                                              \
   case NN:                                                                                       \
-    return fp64 ? go_xi<NN, double>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, own, s) \
-                : go_xi<NN, float>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, own, s);
+    return fp64 ? go_xi<NN, double>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, own, all, s) \
+                : go_xi<NN, float>(accum, spec, sig, g, mean6, tw, bg, bg_mask, add3, own, all, s);
     EC_FOR_SIZES(EC_CASE)
 #undef EC_CASE
   }
