@@ -1102,7 +1102,9 @@ __global__ __launch_bounds__(pick_T(max_nb(N, 3 * x_rows(N)))) void k_x_inverse(
   if constexpr (MASK) {
     bool any = false;
     for_outputs<N, RL, NSL, Map::Row, NF, T>([&](int f, int x, int slot) {
-      ow[slot] = own[(z * N + y0 + f / 3) * N + x] & keep;
+      // keep = 0 (every voxel): the loads all read the map's first entry, one
+      // cached line, instead of the whole map
+      ow[slot] = own[((z * N + y0 + f / 3) * N + x) & keep] & keep;
       any |= ow[slot] != -1;
     });
     // rows that no defect covers store nothing: their transform is skipped
